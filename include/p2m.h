@@ -1,0 +1,224 @@
+/*
+ * p2m.h -- particle <-> fixed-mesh projection on MI355X (gfx950).
+ *
+ * C ABI of libp2m.so.  Implements the projection step of Duque & Espanol,
+ * "Rapid convergence for simulations that project from particles onto a fixed
+ * mesh": particle -> mesh (P2M) with the quadratically consistent particle
+ * shape functions of App. B, mesh -> particle (M2P) with the fixed mesh's
+ * linear FE shape functions, and the adjoints of both.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Every array argument is a DEVICE pointer (memory of the current HIP
+ *    device) owned by the caller, unless stated otherwise.  Positions are
+ *    FP64, interleaved [N][2] (x, y), 16-byte aligned.  Field values are
+ *    channels-last [N][C] (particles) or [(nx+1)*(ny+1)][C] (mesh, node
+ *    k = j*(nx+1) + i, x fastest), element type given by a p2m_dtype.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default
+ *    stream).  All calls are asynchronous on that stream unless they say they
+ *    synchronise; argument errors are reported synchronously by the return
+ *    code, data-dependent errors (a particle outside the mesh, a non-finite
+ *    coordinate, a cap overflow) are recorded on the device and reported by
+ *    p2m_weights_diag(), which synchronises the stream.
+ *  - Return value: P2M_OK (0) or a negative p2m_status; p2m_last_error()
+ *    returns a thread-local message describing the last failure.
+ *  - The library never reads field values from host memory and never falls
+ *    back to a CPU computation.
+ */
+#ifndef P2M_H
+#define P2M_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Fixed uniform mesh: (nx+1)*(ny+1) nodes at (x0 + i*H, y0 + j*H),
+ * 0 <= i <= nx, 0 <= j <= ny.  H is the mesh spacing of the paper (Sec. 1,
+ * Fig. idea).  The domain is bounded (the paper's periodic boxes are not
+ * formed); particles must lie in [x0, x0+nx*H] x [y0, y0+ny*H]. */
+typedef struct p2m_mesh {
+    int32_t nx, ny;
+    double H;
+    double x0, y0;
+} p2m_mesh;
+
+typedef enum p2m_status {
+    P2M_OK = 0,
+    P2M_EINVAL = -1,   /* bad argument: null/misaligned pointer, N <= 0,
+                          H <= 0, h <= 0, C not in [1, 16], unknown dtype   */
+    P2M_EDOMAIN = -2,  /* particle outside the mesh or non-finite (diag)    */
+    P2M_ECAP = -3,     /* a node's support exceeded P2M_MAX_SUPPORT (diag)  */
+    P2M_EGEOM = -4,    /* coincident particles, a node left without weights,
+                          or a rank-deficient system with P2M_STRICT (diag) */
+    P2M_EHIP = -5,     /* a HIP runtime call failed                         */
+    P2M_ENOMEM = -6    /* device allocation failed                          */
+} p2m_status;
+
+/* Element type of field arrays (values, mesh values and their gradients). */
+typedef enum p2m_dtype {
+    P2M_F64 = 0,       /* FP64 storage, FP64 sums                           */
+    P2M_F32 = 1,       /* FP32 storage, FP32 sums                           */
+    P2M_BF16 = 2       /* BF16 storage of PARTICLE arrays, FP32 sums; mesh
+                          arrays and mesh outputs are FP32                  */
+} p2m_dtype;
+
+/* Flags of p2m_build_weights. */
+#define P2M_WEIGHTS_F32 0x1  /* also keep FP32 copies of the weights (mixed path) */
+#define P2M_STRICT      0x2  /* rank-deficient systems make diag report EGEOM   */
+
+/* Largest number of particles one node's weights may involve (ELL width). */
+#define P2M_MAX_SUPPORT 32
+/* Nearest particles used by a closure node (boundary ring / outside hull). */
+#define P2M_CLOSURE_K 12
+
+/* Device-side diagnostics of the last build (all counts are per build). */
+typedef struct p2m_diag {
+    int64_t interior_nodes;     /* nodes with a Delaunay triangle              */
+    int64_t closure_nodes;      /* boundary-ring + outside-hull nodes          */
+    int64_t outside_hull_nodes; /* subset of closure_nodes                     */
+    int64_t rank_deficient;     /* moment systems solved by the pseudo-inverse */
+    int64_t cap_overflow;       /* nodes whose support exceeded the ELL width  */
+    int64_t escalated_nodes;    /* nodes that needed a larger search region    */
+    int64_t global_nodes;       /* nodes that needed a scan of every particle  */
+    int64_t near_degenerate;    /* predicate decisions inside the error bound  */
+    int64_t bad_particles;      /* outside the mesh or non-finite (excluded)   */
+    int64_t failed_nodes;       /* nodes left without weights (zero row)       */
+    int64_t duplicate_pairs;    /* pairs of coincident particles (EGEOM)       */
+    int32_t status;             /* P2M_OK, P2M_EDOMAIN, P2M_ECAP or P2M_EGEOM  */
+    int32_t support_max;        /* largest support of any node                 */
+} p2m_diag;
+
+/* Opaque weights handle: the P2M operator of one particle set on one mesh.
+ * Owned by the library; holds device memory until p2m_weights_destroy(). */
+typedef struct p2m_weights p2m_weights;
+
+/*
+ * p2m_build_weights -- psi_mu(r_i) for every mesh node i (App. B, eq. phiquad).
+ *
+ * For each interior node: the Delaunay triangle T = (a, b, c) of the particles
+ * that contains the node, the Delaunay rings of a, b, c, and for each edge
+ * e = (nu, sigma) of T the minimum-norm coefficients A_{mu e} over
+ * S_e = ring(nu) U ring(sigma) solving eqs. (A0), (A1), (A2_2); the weight of
+ * particle mu is phi_mu + 2 sum_e phi_nu phi_sigma A_{mu e}.  Nodes on the
+ * mesh's outer ring and nodes outside the particles' convex hull use the
+ * minimum-norm quadratic-moment weights of their P2M_CLOSURE_K nearest
+ * particles (a closure the paper's periodic runs never needed).
+ *
+ *  mesh   host pointer to the mesh description.
+ *  h      mean particle spacing (the paper's h).  A performance hint only:
+ *         it sizes the binning grid; results do not depend on it.
+ *  pos    device [N][2] FP64 particle positions (user order).
+ *  N      number of particles, 3 <= N < 2^28.
+ *  flags  P2M_WEIGHTS_F32 | P2M_STRICT.
+ *  w      in/out: *w == NULL allocates a new handle; a handle from an earlier
+ *         call is reused (its buffers grow if needed; previous contents are
+ *         overwritten, so no work may still be pending on them on another
+ *         stream).
+ *  stream hipStream_t.
+ * Errors: EINVAL (arguments), ENOMEM, EHIP.  Data errors -> p2m_weights_diag.
+ */
+int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t N,
+                      int flags, p2m_weights** w, void* stream);
+
+/* Copy the diagnostics of the last build on this handle to host memory.
+ * Synchronises `stream`.  Returns diag->status (P2M_OK if the build had no
+ * data error). */
+int p2m_weights_diag(const p2m_weights* w, p2m_diag* diag, void* stream);
+
+/* Copy the ELL weights to caller device buffers (for inspection and tests).
+ * idx  int32 [P2M_MAX_SUPPORT][n_nodes] user particle ids (unused slots -1),
+ * wts  FP64 [P2M_MAX_SUPPORT][n_nodes], cnt int32 [n_nodes],
+ * tri  int32 [n_nodes][3] user ids of the node's Delaunay triangle (-1 for
+ *      closure nodes).  Any pointer may be NULL. */
+int p2m_weights_export(const p2m_weights* w, int32_t* idx, double* wts, int32_t* cnt,
+                       int32_t* tri, void* stream);
+
+/* Number of mesh nodes and particles of a handle (host values). */
+int p2m_weights_shape(const p2m_weights* w, int64_t* n_nodes, int64_t* n_particles);
+
+/*
+ * p2m_project -- eq. (p2m): mesh_vals[i][c] = sum_mu psi_mu(r_i) vals[mu][c].
+ *  vals      device [N][C] particle values of type dtype (user order).
+ *  mesh_vals device [(nx+1)(ny+1)][C] output; type dtype, FP32 for P2M_BF16.
+ *  P2M_F64 uses the FP64 weights; P2M_F32/P2M_BF16 use FP32 weights and
+ *  FP32 sums (the handle must have been built with P2M_WEIGHTS_F32).
+ */
+int p2m_project(const p2m_weights* w, const void* vals, int C, int dtype,
+                void* mesh_vals, void* stream);
+
+/*
+ * m2p_interpolate -- eq. (m2p) with linear FE mesh functions:
+ * vals[mu][c] = sum_i phi^m_i(r_mu) mesh_vals[i][c].  Each cell
+ * [i, i+1] x [j, j+1] is split by the diagonal (i,j)-(i+1,j+1); a particle
+ * takes cell i = min(floor((x-x0)/H), nx-1) (same in y).
+ *  mesh_vals device [(nx+1)(ny+1)][C], type dtype (FP32 for P2M_BF16).
+ *  pos       device [N][2] FP64.
+ *  vals      device [N][C] output, type dtype (BF16 for P2M_BF16).
+ * Particles outside the mesh get NaN and are counted nowhere: validate
+ * positions with p2m_build_weights / p2m_weights_diag.
+ */
+int m2p_interpolate(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtype,
+                    const double* pos, int64_t N, void* vals, void* stream);
+
+/*
+ * m2p_interpolate_backward -- adjoint of m2p_interpolate.
+ *  grad_vals  device [N][C] upstream gradient (type dtype; FP32 for BF16).
+ *  grad_mesh  device [(nx+1)(ny+1)][C] output, OVERWRITTEN with
+ *             sum_mu phi^m_i(r_mu) grad_vals[mu][c]; may be NULL.
+ *  grad_pos   device [N][2] FP64, ACCUMULATED (+=) with
+ *             sum_c grad_vals[mu][c] * grad_r (sum_i phi^m_i mesh_vals[i][c])
+ *             (the interpolant's gradient on the particle's triangle);
+ *             may be NULL.  mesh_vals is needed only when grad_pos != NULL.
+ * grad_mesh uses atomic adds: its bits may differ between runs.
+ */
+int m2p_interpolate_backward(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtype,
+                             const double* pos, int64_t N, const void* grad_vals,
+                             void* grad_mesh, double* grad_pos, void* stream);
+
+/*
+ * p2m_project_backward -- adjoint of p2m_project for fixed weights.
+ *  grad_mesh  device [(nx+1)(ny+1)][C] upstream gradient (dtype; FP32 for BF16).
+ *  grad_vals  device [N][C] output (dtype; FP32 for BF16), OVERWRITTEN with
+ *             sum_i psi_mu(r_i) grad_mesh[i][c]; may be NULL (atomic adds).
+ *  vals       device [N][C] forward particle values; needed iff grad_w.
+ *  grad_w     device FP64 [P2M_MAX_SUPPORT][n_nodes] output, OVERWRITTEN with
+ *             d L / d psi = sum_c grad_mesh[i][c] vals[idx][c]; may be NULL.
+ */
+int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int dtype,
+                         const void* vals, void* grad_vals, double* grad_w, void* stream);
+
+/*
+ * p2m_build_weights_backward -- d L / d r through the weights: given grad_w
+ * (layout of p2m_project_backward), grad_pos[mu] += sum_{i,k} grad_w[k][i]
+ * d psi_k(r_i) / d r_mu for the particle positions pos (the same array the
+ * handle was built from; geometry is recomputed, not stored).  The
+ * combinatorial structure (triangles, rings, nearest sets) is held fixed.
+ *  grad_pos  device [N][2] FP64, ACCUMULATED with atomic adds.
+ */
+int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const double* grad_w,
+                               double* grad_pos, void* stream);
+
+void p2m_weights_destroy(p2m_weights* w);
+
+/* Process-wide tuning knobs for the weight build (performance only; results
+ * do not depend on them).  Not thread-safe with concurrent builds.
+ *   "bin_scale"  bin width ~ bin_scale * h        (0.25 .. 8,  default 1)
+ *   "region_h"   first search half-width / h      (1 .. 64,    default 4)
+ *   "levels"     region doublings before a scan
+ *                of every particle                (0 .. 8,     default 3)
+ * Returns P2M_EINVAL for an unknown name or a value out of range. */
+int p2m_set_option(const char* name, double value);
+
+/* Thread-local description of the last error (never NULL). */
+const char* p2m_last_error(void);
+
+/* Library version string. */
+const char* p2m_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* P2M_H */

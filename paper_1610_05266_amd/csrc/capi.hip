@@ -1,0 +1,423 @@
+// C ABI of libp2m: argument validation, handle and workspace management,
+// diagnostics and error reporting.  All device work is in the other files.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "kernels.h"
+
+namespace p2m {
+
+namespace {
+thread_local std::string g_err = "no error";
+
+// Process-wide tuning knobs (set with p2m_set_option).
+struct Tuning {
+    double bin_scale = 1.0;       // bin width ~ bin_scale * h
+    double region_h = 4.0;        // first search half-width, in units of h
+    int levels = 3;               // doublings before the global scan
+} g_tune;
+}  // namespace
+
+void set_error(const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+}
+
+int hip_check(hipError_t e, const char* what) {
+    set_error("%s failed: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? P2M_ENOMEM : P2M_EHIP;
+}
+
+}  // namespace p2m
+
+using namespace p2m;
+
+struct p2m_weights {
+    int device = -1;
+    MeshD mesh{};
+    double h = 0.0;
+    Grid grid{};
+    int64_t N = 0;
+    int64_t n_nodes = 0;
+    int flags = 0;
+    // capacities of the device buffers
+    int64_t capN = 0, capBins = 0, capNodes = 0, capTiles = 0;
+    bool capW32 = false;
+    BinBuffers bins{};
+    uint32_t* meta = nullptr;
+    int32_t* idx = nullptr;
+    double* w64 = nullptr;
+    float* w32 = nullptr;
+    uint8_t* mem = nullptr;
+    unsigned long long* diag = nullptr;
+};
+
+namespace {
+
+template <typename T>
+int grow(T** p, int64_t count, int64_t have) {
+    if (*p && have >= count) return P2M_OK;
+    if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (count <= 0) count = 1;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * static_cast<size_t>(count));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_check(e, "hipMalloc");
+    }
+    return P2M_OK;
+}
+
+void release(p2m_weights* w) {
+    void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.count, w->bins.start, w->bins.tsum, w->bins.pos_s,
+                    w->bins.perm, w->meta, w->idx, w->w64, w->w32, w->mem, w->diag};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+int check_mesh(const p2m_mesh* m) {
+    if (!m) {
+        set_error("mesh is NULL");
+        return P2M_EINVAL;
+    }
+    if (m->nx < 1 || m->ny < 1 || !(m->H > 0.0) || !is_fin(m->H) || !is_fin(m->x0) || !is_fin(m->y0)) {
+        set_error("invalid mesh (nx=%d ny=%d H=%g)", m->nx, m->ny, m->H);
+        return P2M_EINVAL;
+    }
+    const int64_t nn = static_cast<int64_t>(m->nx + 1) * (m->ny + 1);
+    if (nn * KMAX >= (int64_t(1) << 40)) {
+        set_error("mesh too large");
+        return P2M_EINVAL;
+    }
+    return P2M_OK;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+size_t dsize(int dtype) { return dtype == P2M_F64 ? 8 : dtype == P2M_F32 ? 4 : 2; }
+
+int check_vals(const void* p, int C, int dtype, const char* what, bool mesh_side) {
+    if (C < 1 || C > 16) {
+        set_error("C=%d out of range [1, 16]", C);
+        return P2M_EINVAL;
+    }
+    if (dtype != P2M_F64 && dtype != P2M_F32 && dtype != P2M_BF16) {
+        set_error("unknown dtype %d", dtype);
+        return P2M_EINVAL;
+    }
+    if (!p) {
+        set_error("%s is NULL", what);
+        return P2M_EINVAL;
+    }
+    const size_t a = mesh_side && dtype == P2M_BF16 ? 4 : dsize(dtype);
+    if (!aligned(p, a)) {
+        set_error("%s is misaligned", what);
+        return P2M_EINVAL;
+    }
+    return P2M_OK;
+}
+
+MeshD to_meshd(const p2m_mesh* m) { return MeshD{m->nx, m->ny, m->H, m->x0, m->y0}; }
+
+WeightsView view(const p2m_weights* w) {
+    WeightsView v;
+    v.mesh = w->mesh;
+    v.grid = w->grid;
+    v.n_nodes = w->n_nodes;
+    v.N = w->N;
+    v.meta = w->meta;
+    v.idx = w->idx;
+    v.w64 = w->w64;
+    v.w32 = (w->flags & P2M_WEIGHTS_F32) ? w->w32 : nullptr;
+    v.mem = w->mem;
+    return v;
+}
+
+int check_handle(const p2m_weights* w) {
+    if (!w || w->n_nodes <= 0) {
+        set_error("weights handle is NULL or was never built");
+        return P2M_EINVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != w->device) {
+        set_error("weights handle belongs to device %d, current device is %d", w->device, dev);
+        return P2M_EINVAL;
+    }
+    return P2M_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* p2m_last_error(void) { return g_err.c_str(); }
+
+const char* p2m_version(void) { return "libp2m 0.1 (gfx950)"; }
+
+int p2m_set_option(const char* name, double value) {
+    if (!name) {
+        set_error("option name is NULL");
+        return P2M_EINVAL;
+    }
+    if (!std::strcmp(name, "bin_scale") && value >= 0.25 && value <= 8.0) {
+        g_tune.bin_scale = value;
+    } else if (!std::strcmp(name, "region_h") && value >= 1.0 && value <= 64.0) {
+        g_tune.region_h = value;
+    } else if (!std::strcmp(name, "levels") && value >= 0.0 && value <= 8.0) {
+        g_tune.levels = static_cast<int>(value);
+    } else {
+        set_error("unknown option or value out of range: %s=%g", name, value);
+        return P2M_EINVAL;
+    }
+    return P2M_OK;
+}
+
+int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t N, int flags,
+                      p2m_weights** wout, void* stream) {
+    int rc = check_mesh(mesh);
+    if (rc) return rc;
+    if (!(h > 0.0) || !is_fin(h)) {
+        set_error("h must be positive and finite (got %g)", h);
+        return P2M_EINVAL;
+    }
+    if (!pos || !aligned(pos, 16)) {
+        set_error("pos is NULL or not 16-byte aligned");
+        return P2M_EINVAL;
+    }
+    if (N < 3 || N >= (int64_t(1) << 28)) {
+        set_error("N=%lld out of range [3, 2^28)", static_cast<long long>(N));
+        return P2M_EINVAL;
+    }
+    if (!wout) {
+        set_error("output handle pointer is NULL");
+        return P2M_EINVAL;
+    }
+    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT)) {
+        set_error("unknown flags 0x%x", flags);
+        return P2M_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int dev = 0;
+    P2M_HIP(hipGetDevice(&dev));
+
+    // binning grid: kb x kb bins per cell, bin width close to bin_scale * h
+    const double want = g_tune.bin_scale * h;
+    int64_t kb = std::max<int64_t>(1, std::llround(mesh->H / want));
+    while (kb > 1 && static_cast<double>(mesh->nx) * kb * static_cast<double>(mesh->ny) * kb > 1.0e9) --kb;
+    const int64_t nbins = static_cast<int64_t>(mesh->nx) * kb * mesh->ny * kb;
+    if (nbins > (int64_t(1) << 30)) {
+        set_error("binning grid too large (%lld bins)", static_cast<long long>(nbins));
+        return P2M_EINVAL;
+    }
+    Grid g;
+    g.kb = static_cast<int>(kb);
+    g.nbx = static_cast<int>(mesh->nx * kb);
+    g.nby = static_cast<int>(mesh->ny * kb);
+    g.bw = mesh->H / static_cast<double>(kb);
+    g.x0 = mesh->x0;
+    g.y0 = mesh->y0;
+
+    p2m_weights* w = *wout;
+    bool fresh = false;
+    if (!w) {
+        w = new (std::nothrow) p2m_weights();
+        if (!w) {
+            set_error("host allocation failed");
+            return P2M_ENOMEM;
+        }
+        w->device = dev;
+        fresh = true;
+    } else if (w->device != dev) {
+        set_error("handle belongs to device %d, current device is %d", w->device, dev);
+        return P2M_EINVAL;
+    }
+    const int64_t n_nodes = static_cast<int64_t>(mesh->nx + 1) * (mesh->ny + 1);
+    const int64_t ntiles = scan_tile_count(nbins + 1) + 1;
+    const bool want32 = (flags & P2M_WEIGHTS_F32) != 0;
+    rc = P2M_OK;
+    if (!rc) rc = grow(&w->bins.key, N, w->capN);
+    if (!rc) rc = grow(&w->bins.rank, N, w->capN);
+    if (!rc) rc = grow(&w->bins.perm, N, w->capN);
+    if (!rc) rc = grow(&w->bins.pos_s, 2 * N, 2 * w->capN);
+    if (!rc) w->capN = std::max(w->capN, N);
+    if (!rc) rc = grow(&w->bins.count, nbins + 1, w->capBins + 1);
+    if (!rc) rc = grow(&w->bins.start, nbins + 2, w->capBins + 2);
+    if (!rc) w->capBins = std::max(w->capBins, nbins);
+    if (!rc) rc = grow(&w->bins.tsum, ntiles + 1, w->capTiles + 1);
+    if (!rc) w->capTiles = std::max(w->capTiles, ntiles);
+    if (!rc) rc = grow(&w->meta, n_nodes, w->capNodes);
+    if (!rc) rc = grow(&w->idx, n_nodes * KMAX, w->capNodes * KMAX);
+    if (!rc) rc = grow(&w->w64, n_nodes * KMAX, w->capNodes * KMAX);
+    if (!rc) rc = grow(&w->mem, n_nodes * KMAX, w->capNodes * KMAX);
+    if (!rc && want32) rc = grow(&w->w32, n_nodes * KMAX, w->capW32 ? w->capNodes * KMAX : 0);
+    if (!rc && !w->diag) rc = grow(&w->diag, D_COUNT, 0);
+    if (rc) {
+        if (fresh) {
+            release(w);
+            delete w;
+        }
+        return rc;
+    }
+    if (want32 && !w->capW32) w->capW32 = true;
+    w->capNodes = std::max(w->capNodes, n_nodes);
+    w->mesh = to_meshd(mesh);
+    w->h = h;
+    w->grid = g;
+    w->N = N;
+    w->n_nodes = n_nodes;
+    w->flags = flags;
+    *wout = w;
+
+    rc = fill_u64(w->diag, 0ull, D_COUNT, st);
+    if (!rc) rc = bin_particles(w->bins, pos, N, w->mesh, g, w->diag, st);
+    if (rc) return rc;
+    BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem};
+    BuildParams prm;
+    prm.hw0 = std::max(2, static_cast<int>(std::ceil(g_tune.region_h * h / g.bw)));
+    prm.levels = g_tune.levels;
+    return build_weights(w->bins, w->mesh, g, N, out, prm, w->diag, st);
+}
+
+int p2m_weights_diag(const p2m_weights* w, p2m_diag* d, void* stream) {
+    int rc = check_handle(w);
+    if (rc) return rc;
+    if (!d) {
+        set_error("diag is NULL");
+        return P2M_EINVAL;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    unsigned long long h[D_COUNT];
+    P2M_HIP(hipMemcpyAsync(h, w->diag, sizeof h, hipMemcpyDeviceToHost, st));
+    P2M_HIP(hipStreamSynchronize(st));
+    d->interior_nodes = static_cast<int64_t>(h[D_INTERIOR]);
+    d->closure_nodes = static_cast<int64_t>(h[D_CLOSURE]);
+    d->outside_hull_nodes = static_cast<int64_t>(h[D_OUTSIDE]);
+    d->rank_deficient = static_cast<int64_t>(h[D_RANKDEF]);
+    d->cap_overflow = static_cast<int64_t>(h[D_CAP]);
+    d->escalated_nodes = static_cast<int64_t>(h[D_ESCALATED]);
+    d->global_nodes = static_cast<int64_t>(h[D_GLOBAL]);
+    d->near_degenerate = static_cast<int64_t>(h[D_NEARDEG]);
+    d->bad_particles = static_cast<int64_t>(h[D_BAD]);
+    d->failed_nodes = static_cast<int64_t>(h[D_FAILED]);
+    d->support_max = static_cast<int32_t>(h[D_SUPMAX]);
+    d->duplicate_pairs = static_cast<int64_t>(h[D_DUP]);
+    int status = P2M_OK;
+    if (d->bad_particles) {
+        status = P2M_EDOMAIN;
+        set_error("%lld particle(s) outside the mesh or non-finite", static_cast<long long>(d->bad_particles));
+    } else if (d->duplicate_pairs) {
+        status = P2M_EGEOM;
+        set_error("%lld pair(s) of coincident particles", static_cast<long long>(d->duplicate_pairs));
+    } else if (d->cap_overflow) {
+        status = P2M_ECAP;
+        set_error("%lld node(s) exceeded the support cap %d", static_cast<long long>(d->cap_overflow), KMAX);
+    } else if ((w->flags & P2M_STRICT) && d->rank_deficient) {
+        status = P2M_EGEOM;
+        set_error("%lld rank-deficient moment system(s)", static_cast<long long>(d->rank_deficient));
+    } else if (d->failed_nodes) {
+        status = P2M_EGEOM;
+        set_error("%lld node(s) without weights (degenerate geometry)", static_cast<long long>(d->failed_nodes));
+    }
+    d->status = status;
+    return status;
+}
+
+int p2m_weights_export(const p2m_weights* w, int32_t* idx, double* wts, int32_t* cnt, int32_t* tri, void* stream) {
+    int rc = check_handle(w);
+    if (rc) return rc;
+    return export_weights(view(w), idx, wts, cnt, tri, static_cast<hipStream_t>(stream));
+}
+
+int p2m_weights_shape(const p2m_weights* w, int64_t* n_nodes, int64_t* n_particles) {
+    if (!w) {
+        set_error("weights handle is NULL");
+        return P2M_EINVAL;
+    }
+    if (n_nodes) *n_nodes = w->n_nodes;
+    if (n_particles) *n_particles = w->N;
+    return P2M_OK;
+}
+
+int p2m_project(const p2m_weights* w, const void* vals, int C, int dtype, void* mesh_vals, void* stream) {
+    int rc = check_handle(w);
+    if (!rc) rc = check_vals(vals, C, dtype, "vals", false);
+    if (!rc) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (rc) return rc;
+    return project(view(w), vals, C, dtype, mesh_vals, static_cast<hipStream_t>(stream));
+}
+
+int m2p_interpolate(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N,
+                    void* vals, void* stream) {
+    int rc = check_mesh(mesh);
+    if (!rc) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (!rc) rc = check_vals(vals, C, dtype, "vals", false);
+    if (rc) return rc;
+    if (!pos || !aligned(pos, 16) || N < 1 || N >= (int64_t(1) << 31)) {
+        set_error("pos is NULL/misaligned or N=%lld out of range", static_cast<long long>(N));
+        return P2M_EINVAL;
+    }
+    return m2p(to_meshd(mesh), mesh_vals, C, dtype, pos, N, vals, static_cast<hipStream_t>(stream));
+}
+
+int m2p_interpolate_backward(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtype, const double* pos,
+                             int64_t N, const void* grad_vals, void* grad_mesh, double* grad_pos, void* stream) {
+    int rc = check_mesh(mesh);
+    if (!rc) rc = check_vals(grad_vals, C, dtype == P2M_BF16 ? P2M_F32 : dtype, "grad_vals", true);
+    if (!rc && grad_mesh) rc = check_vals(grad_mesh, C, dtype, "grad_mesh", true);
+    if (!rc && grad_pos) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (rc) return rc;
+    if (!pos || !aligned(pos, 16) || N < 1 || N >= (int64_t(1) << 31)) {
+        set_error("pos is NULL/misaligned or N=%lld out of range", static_cast<long long>(N));
+        return P2M_EINVAL;
+    }
+    if (grad_pos && !aligned(grad_pos, 16)) {
+        set_error("grad_pos is misaligned");
+        return P2M_EINVAL;
+    }
+    return m2p_backward(to_meshd(mesh), mesh_vals, C, dtype, pos, N, grad_vals, grad_mesh, grad_pos,
+                        static_cast<hipStream_t>(stream));
+}
+
+int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int dtype, const void* vals,
+                         void* grad_vals, double* grad_w, void* stream) {
+    int rc = check_handle(w);
+    if (!rc) rc = check_vals(grad_mesh, C, dtype, "grad_mesh", true);
+    if (!rc && grad_vals) rc = check_vals(grad_vals, C, dtype == P2M_BF16 ? P2M_F32 : dtype, "grad_vals", false);
+    if (!rc && grad_w) rc = check_vals(vals, C, dtype, "vals", false);
+    if (rc) return rc;
+    if (grad_w && !aligned(grad_w, 8)) {
+        set_error("grad_w is misaligned");
+        return P2M_EINVAL;
+    }
+    return project_backward(view(w), grad_mesh, C, dtype, vals, grad_vals, grad_w, static_cast<hipStream_t>(stream));
+}
+
+int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const double* grad_w, double* grad_pos,
+                               void* stream) {
+    int rc = check_handle(w);
+    if (rc) return rc;
+    if (!pos || !aligned(pos, 16) || !grad_w || !aligned(grad_w, 8) || !grad_pos || !aligned(grad_pos, 16)) {
+        set_error("pos / grad_w / grad_pos NULL or misaligned");
+        return P2M_EINVAL;
+    }
+    return build_backward(view(w), pos, grad_w, grad_pos, static_cast<hipStream_t>(stream));
+}
+
+void p2m_weights_destroy(p2m_weights* w) {
+    if (!w) return;
+    release(w);
+    delete w;
+}
+
+}  // extern "C"

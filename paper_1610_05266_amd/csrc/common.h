@@ -1,0 +1,103 @@
+// Internal definitions shared by the HIP translation units of libp2m.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "p2m.h"
+
+namespace p2m {
+
+// Uniform mesh as the kernels see it.
+struct MeshD {
+    int nx, ny;
+    double H, x0, y0;
+};
+
+// Binning grid: kb x kb square bins per mesh cell, bins cover the mesh
+// rectangle exactly; bin (bx, by) has key by*nbx + bx.  Key nbins collects
+// particles that are outside the mesh or non-finite (excluded everywhere).
+struct Grid {
+    int nbx, nby, kb;
+    double bw, x0, y0;
+};
+
+// Diagnostics counters (device int64 array, one build).
+enum DiagIdx : int {
+    D_INTERIOR = 0,
+    D_CLOSURE,
+    D_OUTSIDE,
+    D_RANKDEF,
+    D_CAP,
+    D_ESCALATED,
+    D_GLOBAL,
+    D_NEARDEG,
+    D_BAD,
+    D_FAILED,
+    D_SUPMAX,
+    D_DUP,
+    D_COUNT
+};
+
+constexpr int KMAX = P2M_MAX_SUPPORT;  // ELL width
+constexpr int KNN = P2M_CLOSURE_K;
+
+// Per-node metadata word of the ELL weights.
+enum NodeType : uint32_t { NT_INTERIOR = 0, NT_RING = 1, NT_OUTSIDE = 2, NT_FAILED = 3 };
+__host__ __device__ inline uint32_t meta_pack(uint32_t type, uint32_t cnt, uint32_t ta, uint32_t tb,
+                                              uint32_t tc, uint32_t flags) {
+    return type | (cnt << 2) | (ta << 8) | (tb << 13) | (tc << 18) | (flags << 23);
+}
+__host__ __device__ inline uint32_t meta_type(uint32_t m) { return m & 3u; }
+__host__ __device__ inline uint32_t meta_cnt(uint32_t m) { return (m >> 2) & 63u; }
+__host__ __device__ inline uint32_t meta_t(uint32_t m, int k) { return (m >> (8 + 5 * k)) & 31u; }
+constexpr uint32_t MF_NEARDEG = 1u, MF_RANKDEF = 2u, MF_ESCALATED = 4u, MF_GLOBAL = 8u;
+__host__ __device__ inline uint32_t meta_flags(uint32_t m) { return m >> 23; }
+
+// Membership bits stored per ELL entry: bit k set when the particle belongs to
+// the Delaunay ring of the k-th vertex of the node's triangle.
+constexpr uint8_t MB_RING_A = 1, MB_RING_B = 2, MB_RING_C = 4;
+
+// Everything the kernels need to know about one weights handle.
+struct WeightsView {
+    MeshD mesh;
+    Grid grid;
+    int64_t n_nodes;
+    int64_t N;
+    const uint32_t* meta;   // [n_nodes]
+    const int32_t* idx;     // [KMAX][n_nodes] user particle ids
+    const double* w64;      // [KMAX][n_nodes]
+    const float* w32;       // [KMAX][n_nodes] or null
+    const uint8_t* mem;     // [KMAX][n_nodes]
+};
+
+// Exact-rounding helpers: products/sums that must not be contracted into
+// FMAs (node coordinates are defined as x0 + i*H with two roundings).
+__device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+
+// Field element loads/stores with widening to the accumulation type.
+__device__ __forceinline__ float bf16_to_f32(uint16_t v) {
+    return __uint_as_float(static_cast<uint32_t>(v) << 16);
+}
+// Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
+__device__ __forceinline__ uint16_t f32_to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u && (u & 0x007fffffu)) return static_cast<uint16_t>((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return static_cast<uint16_t>(u >> 16);
+}
+
+}  // namespace p2m
+
+// Host-side launch helpers (defined in capi.hip).
+namespace p2m {
+void set_error(const char* fmt, ...);
+int hip_check(hipError_t e, const char* what);
+}  // namespace p2m
+
+#define P2M_HIP(call)                                              \
+    do {                                                           \
+        hipError_t _e = (call);                                    \
+        if (_e != hipSuccess) return ::p2m::hip_check(_e, #call);  \
+    } while (0)

@@ -1,0 +1,58 @@
+// Host-side launchers of the HIP kernels (internal to libp2m).
+#pragma once
+
+#include "common.h"
+
+namespace p2m {
+
+// ---- utilities (util.hip) ----
+int fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
+int fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t st);
+int fill_bytes_zero(void* p, int64_t nbytes, hipStream_t st);
+
+// ---- binning (binning.hip) ----
+struct BinBuffers {
+    uint32_t* key;   // [N]
+    int32_t* rank;   // [N]
+    int32_t* count;  // [nbins + 1]
+    int32_t* start;  // [nbins + 2]
+    int32_t* tsum;   // [scan tiles + 1]
+    double* pos_s;   // [N][2] sorted positions
+    int32_t* perm;   // [N] sorted -> user id
+};
+int64_t scan_tile_count(int64_t n);
+int exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum, hipStream_t st);
+int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const MeshD& m, const Grid& g,
+                  unsigned long long* diag, hipStream_t st);
+
+// ---- weight build (build.hip) ----
+struct BuildOut {
+    uint32_t* meta;  // [n_nodes]
+    int32_t* idx;    // [KMAX][n_nodes]
+    double* w64;     // [KMAX][n_nodes]
+    float* w32;      // [KMAX][n_nodes] or null
+    uint8_t* mem;    // [KMAX][n_nodes]
+};
+struct BuildParams {
+    int hw0;         // half-width (bins) of the first search region
+    int levels;      // region doublings before the global scan
+};
+int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N, const BuildOut& out,
+                  const BuildParams& prm, unsigned long long* diag, hipStream_t st);
+
+// ---- projection and interpolation (project.hip, m2p.hip) ----
+int project(const WeightsView& w, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st);
+int project_backward(const WeightsView& w, const void* grad_mesh, int C, int dtype, const void* vals,
+                     void* grad_vals, double* grad_w, hipStream_t st);
+int m2p(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N, void* vals,
+        hipStream_t st);
+int m2p_backward(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N,
+                 const void* grad_vals, void* grad_mesh, double* grad_pos, hipStream_t st);
+
+// ---- adjoint of the weights (adjoint.hip) ----
+int build_backward(const WeightsView& w, const double* pos, const double* grad_w, double* grad_pos,
+                   hipStream_t st);
+int export_weights(const WeightsView& w, int32_t* idx, double* wts, int32_t* cnt, int32_t* tri,
+                   hipStream_t st);
+
+}  // namespace p2m

@@ -1,0 +1,176 @@
+// M2P, eq. (m2p), with the fixed mesh's linear FE shape functions, and its
+// adjoint.
+//
+// The mesh is uniform, so locating a particle is arithmetic: cell
+// i = min(floor((x - x0)/H), nx - 1) (same in y), local coordinates
+// xi = (x - x0)/H - i, eta likewise; the cell's diagonal (i,j)-(i+1,j+1)
+// splits it into the triangle with xi >= eta (nodes (i,j), (i+1,j), (i+1,j+1),
+// weights 1-xi, xi-eta, eta) and the one with xi < eta (nodes (i,j),
+// (i+1,j+1), (i,j+1), weights 1-eta, xi, eta-xi).  One thread per particle:
+// 16 bytes of position in, C values out, three gathers from the mesh array
+// (small enough to stay in the last-level cache).
+#include "kernels.h"
+
+namespace p2m {
+
+namespace {
+
+constexpr int CMAX = 16;
+
+struct Loc {
+    int64_t n0, n1, n2;
+    double w0, w1, w2;
+    bool lower, ok;
+};
+
+__device__ __forceinline__ Loc locate_cell(const MeshD& m, double2 p) {
+    Loc L;
+    const double x1 = add_rn(m.x0, mul_rn(static_cast<double>(m.nx), m.H));
+    const double y1 = add_rn(m.y0, mul_rn(static_cast<double>(m.ny), m.H));
+    L.ok = p.x >= m.x0 && p.x <= x1 && p.y >= m.y0 && p.y <= y1;
+    const double tx = (p.x - m.x0) / m.H;
+    const double ty = (p.y - m.y0) / m.H;
+    // clamp in floating point first (NaN and huge values included)
+    const int i = static_cast<int>(fmax(fmin(floor(tx), static_cast<double>(m.nx - 1)), 0.0));
+    const int j = static_cast<int>(fmax(fmin(floor(ty), static_cast<double>(m.ny - 1)), 0.0));
+    const double xi = tx - i, eta = ty - j;
+    const int64_t s = m.nx + 1;
+    const int64_t n00 = static_cast<int64_t>(j) * s + i;
+    L.lower = xi >= eta;
+    if (L.lower) {
+        L.n0 = n00;
+        L.n1 = n00 + 1;
+        L.n2 = n00 + s + 1;
+        L.w0 = 1.0 - xi;
+        L.w1 = xi - eta;
+        L.w2 = eta;
+    } else {
+        L.n0 = n00;
+        L.n1 = n00 + s + 1;
+        L.n2 = n00 + s;
+        L.w0 = 1.0 - eta;
+        L.w1 = xi;
+        L.w2 = eta - xi;
+    }
+    return L;
+}
+
+__device__ __forceinline__ double ldm(const double* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ldm(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ void st(double* p, int64_t i, double v) { p[i] = v; }
+__device__ __forceinline__ void st(float* p, int64_t i, float v) { p[i] = v; }
+__device__ __forceinline__ void st(uint16_t* p, int64_t i, float v) { p[i] = f32_to_bf16(v); }
+__device__ __forceinline__ double ldv(const double* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
+
+// TM mesh value type (accumulation type), TO particle output type
+template <typename TM, typename TO, int CC>
+__global__ void __launch_bounds__(256) k_m2p(MeshD m, const TM* __restrict__ mv, int Crt,
+                                             const double2* __restrict__ pos, int64_t N, TO* __restrict__ out) {
+    const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (mu >= N) return;
+    const int C = CC > 0 ? CC : Crt;
+    const Loc L = locate_cell(m, pos[mu]);
+    const TM w0 = static_cast<TM>(L.w0), w1 = static_cast<TM>(L.w1), w2 = static_cast<TM>(L.w2);
+#pragma unroll
+    for (int c = 0; c < (CC > 0 ? CC : CMAX); ++c) {
+        if (c >= C) break;
+        TM v = w0 * ldm(mv, L.n0 * C + c) + w1 * ldm(mv, L.n1 * C + c) + w2 * ldm(mv, L.n2 * C + c);
+        if (!L.ok) v = static_cast<TM>(NAN);
+        st(out, mu * C + c, v);
+    }
+}
+
+template <typename TM, typename TO>
+void launch_m2p(const MeshD& m, const void* mv, int C, const double* pos, int64_t N, void* out, hipStream_t s) {
+    const int blocks = static_cast<int>((N + 255) / 256);
+    const TM* M = static_cast<const TM*>(mv);
+    const double2* P = reinterpret_cast<const double2*>(pos);
+    TO* O = static_cast<TO*>(out);
+    switch (C) {
+        case 1: k_m2p<TM, TO, 1><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        case 2: k_m2p<TM, TO, 2><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        case 3: k_m2p<TM, TO, 3><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        case 4: k_m2p<TM, TO, 4><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        default: k_m2p<TM, TO, 0><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+    }
+}
+
+// grad_mesh += phi_i(r_mu) g_mu (atomics); grad_pos[mu] += sum_c g_mu,c grad u_c
+template <typename TM>
+__global__ void __launch_bounds__(256) k_m2p_bwd(MeshD m, const TM* __restrict__ mv, int C,
+                                                 const double2* __restrict__ pos, int64_t N,
+                                                 const TM* __restrict__ gv, TM* __restrict__ gmesh,
+                                                 double2* __restrict__ gpos) {
+    const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (mu >= N) return;
+    const Loc L = locate_cell(m, pos[mu]);
+    if (!L.ok) return;
+    // d(weights)/dxi and d/deta on the particle's triangle
+    const double dxi0 = L.lower ? -1.0 : 0.0, dxi1 = 1.0, dxi2 = L.lower ? 0.0 : -1.0;
+    const double det0 = L.lower ? 0.0 : -1.0, det1 = L.lower ? -1.0 : 0.0, det2 = 1.0;
+    double gx = 0.0, gy = 0.0;
+    for (int c = 0; c < C; ++c) {
+        const TM g = gv[mu * C + c];
+        if (gmesh) {
+            atomicAdd(&gmesh[L.n0 * C + c], static_cast<TM>(L.w0) * g);
+            atomicAdd(&gmesh[L.n1 * C + c], static_cast<TM>(L.w1) * g);
+            atomicAdd(&gmesh[L.n2 * C + c], static_cast<TM>(L.w2) * g);
+        }
+        if (gpos) {
+            const double v0 = ldm(mv, L.n0 * C + c), v1 = ldm(mv, L.n1 * C + c), v2 = ldm(mv, L.n2 * C + c);
+            const double gd = static_cast<double>(g);
+            gx += gd * (dxi0 * v0 + dxi1 * v1 + dxi2 * v2);
+            gy += gd * (det0 * v0 + det1 * v1 + det2 * v2);
+        }
+    }
+    if (gpos) {
+        double2 a = gpos[mu];
+        a.x += gx / m.H;
+        a.y += gy / m.H;
+        gpos[mu] = a;
+    }
+}
+
+}  // namespace
+
+int m2p(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N, void* vals,
+        hipStream_t st) {
+    if (dtype == P2M_F64)
+        launch_m2p<double, double>(m, mesh_vals, C, pos, N, vals, st);
+    else if (dtype == P2M_F32)
+        launch_m2p<float, float>(m, mesh_vals, C, pos, N, vals, st);
+    else
+        launch_m2p<float, uint16_t>(m, mesh_vals, C, pos, N, vals, st);
+    P2M_HIP(hipGetLastError());
+    return P2M_OK;
+}
+
+int m2p_backward(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N,
+                 const void* grad_vals, void* grad_mesh, double* grad_pos, hipStream_t st) {
+    const int blocks = static_cast<int>((N + 255) / 256);
+    const int64_t nn = static_cast<int64_t>(m.nx + 1) * (m.ny + 1);
+    const double2* P = reinterpret_cast<const double2*>(pos);
+    double2* GP = reinterpret_cast<double2*>(grad_pos);
+    if (dtype == P2M_F64) {
+        if (grad_mesh) {
+            int rc = fill_bytes_zero(grad_mesh, sizeof(double) * nn * C, st);
+            if (rc) return rc;
+        }
+        k_m2p_bwd<double><<<blocks, 256, 0, st>>>(m, static_cast<const double*>(mesh_vals), C, P, N,
+                                                  static_cast<const double*>(grad_vals),
+                                                  static_cast<double*>(grad_mesh), GP);
+    } else {
+        if (grad_mesh) {
+            int rc = fill_bytes_zero(grad_mesh, sizeof(float) * nn * C, st);
+            if (rc) return rc;
+        }
+        k_m2p_bwd<float><<<blocks, 256, 0, st>>>(m, static_cast<const float*>(mesh_vals), C, P, N,
+                                                 static_cast<const float*>(grad_vals),
+                                                 static_cast<float*>(grad_mesh), GP);
+    }
+    P2M_HIP(hipGetLastError());
+    return P2M_OK;
+}
+
+}  // namespace p2m

@@ -1,0 +1,266 @@
+"""Python binding of libp2m: the C-ABI calls under the same names, on torch
+device tensors.  Argument marshalling only -- every step runs in the HIP
+library; nothing here computes on the host.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import (P2M_BF16, P2M_F32, P2M_F64, P2M_STRICT, P2M_WEIGHTS_F32, MAX_SUPPORT, P2MDiag, P2MError,
+                   P2MMesh, check, load)
+
+__all__ = [
+    "Mesh",
+    "Weights",
+    "p2m_build_weights",
+    "p2m_project",
+    "m2p_interpolate",
+    "m2p_interpolate_backward",
+    "p2m_project_backward",
+    "p2m_build_weights_backward",
+    "p2m_set_option",
+    "P2MError",
+    "P2M_WEIGHTS_F32",
+    "P2M_STRICT",
+]
+
+
+@dataclass(frozen=True)
+class Mesh:
+    """Uniform fixed mesh: nodes (x0 + i*H, y0 + j*H), 0<=i<=nx, 0<=j<=ny."""
+
+    nx: int
+    ny: int
+    H: float
+    x0: float = 0.0
+    y0: float = 0.0
+
+    @property
+    def n_nodes(self) -> int:
+        return (self.nx + 1) * (self.ny + 1)
+
+    def c(self) -> P2MMesh:
+        return P2MMesh(int(self.nx), int(self.ny), float(self.H), float(self.x0), float(self.y0))
+
+    @classmethod
+    def of(cls, m) -> "Mesh":
+        return m if isinstance(m, Mesh) else cls(int(m.nx), int(m.ny), float(m.H), float(m.x0), float(m.y0))
+
+
+def _stream(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _need(t: torch.Tensor, name: str, dtype=None, shape=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+
+
+def _dtype_code(particle_dtype: torch.dtype) -> int:
+    if particle_dtype == torch.float64:
+        return P2M_F64
+    if particle_dtype == torch.float32:
+        return P2M_F32
+    if particle_dtype == torch.bfloat16:
+        return P2M_BF16
+    raise ValueError(f"unsupported value dtype {particle_dtype}")
+
+
+def _mesh_dtype(code: int) -> torch.dtype:
+    return torch.float64 if code == P2M_F64 else torch.float32
+
+
+class Weights:
+    """Owner of a p2m_weights handle (the P2M operator of one particle set)."""
+
+    def __init__(self):
+        self._h = ctypes.c_void_p(0)
+        self.mesh: Optional[Mesh] = None
+        self.N = 0
+        self.flags = 0
+        self.device = None
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h.value:
+            raise ValueError("weights were never built")
+        return self._h
+
+    @property
+    def n_nodes(self) -> int:
+        return self.mesh.n_nodes
+
+    def diag(self, check_status: bool = True) -> dict:
+        d = P2MDiag()
+        st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+        rc = load().p2m_weights_diag(self.handle, ctypes.byref(d), st)
+        if check_status:
+            check(rc)
+        return d.as_dict()
+
+    def export(self):
+        """ELL weights as CPU tensors: idx [K, n_nodes], w [K, n_nodes], cnt, tri [n_nodes, 3]."""
+        dev = self.device
+        nn = self.n_nodes
+        idx = torch.empty((MAX_SUPPORT, nn), dtype=torch.int32, device=dev)
+        w = torch.empty((MAX_SUPPORT, nn), dtype=torch.float64, device=dev)
+        cnt = torch.empty((nn,), dtype=torch.int32, device=dev)
+        tri = torch.empty((nn, 3), dtype=torch.int32, device=dev)
+        check(load().p2m_weights_export(self.handle, _ptr(idx), _ptr(w), _ptr(cnt), _ptr(tri), _stream(idx)))
+        torch.cuda.synchronize(dev)
+        return idx.cpu(), w.cpu(), cnt.cpu(), tri.cpu()
+
+    def close(self):
+        if self._h.value:
+            load().p2m_weights_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def p2m_set_option(name: str, value: float):
+    check(load().p2m_set_option(name.encode(), float(value)))
+
+
+def p2m_build_weights(mesh, h: float, pos: torch.Tensor, flags: int = 0,
+                      weights: Optional[Weights] = None, check_diag: bool = True) -> Weights:
+    """Build psi_mu(r_i) for all mesh nodes (C call of the same name).
+
+    ``weights`` reuses an existing handle (no allocation when it is large
+    enough).  ``check_diag`` synchronises and raises on data errors.
+    """
+    mesh = Mesh.of(mesh)
+    _need(pos, "pos", torch.float64)
+    if pos.dim() != 2 or pos.shape[1] != 2:
+        raise ValueError("pos must have shape [N, 2]")
+    w = weights if weights is not None else Weights()
+    lib = load()
+    cm = mesh.c()
+    with torch.cuda.device(pos.device):
+        rc = lib.p2m_build_weights(ctypes.byref(cm), float(h), _ptr(pos), pos.shape[0], int(flags),
+                                   ctypes.byref(w._h), _stream(pos))
+    check(rc)
+    w.mesh, w.N, w.flags, w.device = mesh, pos.shape[0], int(flags), pos.device
+    if check_diag:
+        w.diag(check_status=True)
+    return w
+
+
+def p2m_project(w: Weights, vals: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Eq. (p2m): mesh values [n_nodes, C] from particle values [N, C]."""
+    _need(vals, "vals")
+    if vals.dim() != 2 or vals.shape[0] != w.N:
+        raise ValueError(f"vals must have shape [{w.N}, C]")
+    code = _dtype_code(vals.dtype)
+    C = vals.shape[1]
+    if out is None:
+        out = torch.empty((w.n_nodes, C), dtype=_mesh_dtype(code), device=vals.device)
+    _need(out, "out", _mesh_dtype(code), (w.n_nodes, C))
+    with torch.cuda.device(vals.device):
+        check(load().p2m_project(w.handle, _ptr(vals), C, code, _ptr(out), _stream(vals)))
+    return out
+
+
+def m2p_interpolate(mesh, mesh_vals: torch.Tensor, pos: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    bf16_out: bool = False) -> torch.Tensor:
+    """Eq. (m2p) with linear FE mesh functions: particle values [N, C]."""
+    mesh = Mesh.of(mesh)
+    _need(mesh_vals, "mesh_vals")
+    _need(pos, "pos", torch.float64)
+    if mesh_vals.dim() != 2 or mesh_vals.shape[0] != mesh.n_nodes:
+        raise ValueError(f"mesh_vals must have shape [{mesh.n_nodes}, C]")
+    C = mesh_vals.shape[1]
+    if mesh_vals.dtype == torch.float64:
+        code, odt = P2M_F64, torch.float64
+    elif mesh_vals.dtype == torch.float32:
+        code, odt = (P2M_BF16, torch.bfloat16) if bf16_out else (P2M_F32, torch.float32)
+    else:
+        raise ValueError("mesh_vals must be float64 or float32")
+    N = pos.shape[0]
+    if out is None:
+        out = torch.empty((N, C), dtype=odt, device=pos.device)
+    _need(out, "out", odt, (N, C))
+    cm = mesh.c()
+    with torch.cuda.device(pos.device):
+        check(load().m2p_interpolate(ctypes.byref(cm), _ptr(mesh_vals), C, code, _ptr(pos), N, _ptr(out),
+                                     _stream(pos)))
+    return out
+
+
+def m2p_interpolate_backward(mesh, mesh_vals: Optional[torch.Tensor], pos: torch.Tensor, grad_vals: torch.Tensor,
+                             want_mesh: bool = True, grad_pos: Optional[torch.Tensor] = None):
+    """Adjoint of m2p_interpolate: (grad_mesh or None, grad_pos or None).
+
+    grad_pos, when given, is accumulated into (+=)."""
+    mesh = Mesh.of(mesh)
+    _need(pos, "pos", torch.float64)
+    _need(grad_vals, "grad_vals")
+    C = grad_vals.shape[1]
+    code = P2M_F64 if grad_vals.dtype == torch.float64 else P2M_F32
+    mdt = _mesh_dtype(code)
+    gm = torch.empty((mesh.n_nodes, C), dtype=mdt, device=pos.device) if want_mesh else None
+    if grad_pos is not None:
+        _need(grad_pos, "grad_pos", torch.float64, tuple(pos.shape))
+        _need(mesh_vals, "mesh_vals", mdt, (mesh.n_nodes, C))
+    cm = mesh.c()
+    with torch.cuda.device(pos.device):
+        check(load().m2p_interpolate_backward(ctypes.byref(cm), _ptr(mesh_vals), C, code, _ptr(pos), pos.shape[0],
+                                              _ptr(grad_vals), _ptr(gm), _ptr(grad_pos), _stream(pos)))
+    return gm, grad_pos
+
+
+def p2m_project_backward(w: Weights, grad_mesh: torch.Tensor, vals: Optional[torch.Tensor] = None,
+                         want_vals: bool = True, want_w: bool = False):
+    """Adjoint of p2m_project for fixed weights: (grad_vals or None, grad_w or None).
+
+    grad_w has the ELL layout [MAX_SUPPORT, n_nodes] (FP64)."""
+    _need(grad_mesh, "grad_mesh")
+    C = grad_mesh.shape[1]
+    if vals is not None:
+        code = _dtype_code(vals.dtype)
+    else:
+        code = P2M_F64 if grad_mesh.dtype == torch.float64 else P2M_F32
+    gdt = _mesh_dtype(code)
+    _need(grad_mesh, "grad_mesh", gdt, (w.n_nodes, C))
+    gv = torch.empty((w.N, C), dtype=gdt, device=grad_mesh.device) if want_vals else None
+    gw = torch.empty((MAX_SUPPORT, w.n_nodes), dtype=torch.float64, device=grad_mesh.device) if want_w else None
+    if want_w:
+        if vals is None:
+            raise ValueError("vals are needed for grad_w")
+        _need(vals, "vals", None, (w.N, C))
+    with torch.cuda.device(grad_mesh.device):
+        check(load().p2m_project_backward(w.handle, _ptr(grad_mesh), C, code, _ptr(vals), _ptr(gv), _ptr(gw),
+                                          _stream(grad_mesh)))
+    return gv, gw
+
+
+def p2m_build_weights_backward(w: Weights, pos: torch.Tensor, grad_w: torch.Tensor,
+                               grad_pos: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """d L / d pos through the weights (accumulates into grad_pos)."""
+    _need(pos, "pos", torch.float64, (w.N, 2))
+    _need(grad_w, "grad_w", torch.float64, (MAX_SUPPORT, w.n_nodes))
+    if grad_pos is None:
+        grad_pos = torch.zeros_like(pos)
+    _need(grad_pos, "grad_pos", torch.float64, (w.N, 2))
+    with torch.cuda.device(pos.device):
+        check(load().p2m_build_weights_backward(w.handle, _ptr(pos), _ptr(grad_w), _ptr(grad_pos), _stream(pos)))
+    return grad_pos

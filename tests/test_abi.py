@@ -1,0 +1,60 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/p2m.h declares, and rejects bad arguments before touching a device."""
+import ctypes
+
+import pytest
+
+import paper_1610_05266_amd as pkg
+from paper_1610_05266_amd import _lib
+
+
+def test_library_exports_every_declared_symbol():
+    lib = pkg.load()
+    names = pkg.header_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(names) == set(_lib._SIGS), "binding signatures out of sync with include/p2m.h"
+
+
+def test_version_and_error_strings():
+    lib = pkg.load()
+    assert b"gfx950" in lib.p2m_version()
+    assert isinstance(lib.p2m_last_error(), bytes)
+
+
+def test_argument_validation_without_device():
+    lib = pkg.load()
+    h = ctypes.c_void_p(0)
+    # NULL mesh
+    assert lib.p2m_build_weights(None, 0.01, ctypes.c_void_p(16), 10, 0, ctypes.byref(h), None) == _lib.P2M_EINVAL
+    m = _lib.P2MMesh(0, 4, 0.25, 0.0, 0.0)
+    assert lib.p2m_build_weights(ctypes.byref(m), 0.01, ctypes.c_void_p(16), 10, 0, ctypes.byref(h), None) == -1
+    m = _lib.P2MMesh(4, 4, 0.25, 0.0, 0.0)
+    # h <= 0, misaligned pos, N out of range, unknown flags
+    assert lib.p2m_build_weights(ctypes.byref(m), 0.0, ctypes.c_void_p(16), 10, 0, ctypes.byref(h), None) == -1
+    assert lib.p2m_build_weights(ctypes.byref(m), 0.1, ctypes.c_void_p(8), 10, 0, ctypes.byref(h), None) == -1
+    assert lib.p2m_build_weights(ctypes.byref(m), 0.1, ctypes.c_void_p(16), 2, 0, ctypes.byref(h), None) == -1
+    assert lib.p2m_build_weights(ctypes.byref(m), 0.1, ctypes.c_void_p(16), 10, 0x80, ctypes.byref(h), None) == -1
+    assert b"flags" in lib.p2m_last_error()
+    # M2P: C out of range, unknown dtype, NULL pointers
+    assert lib.m2p_interpolate(ctypes.byref(m), ctypes.c_void_p(16), 0, 0, ctypes.c_void_p(16), 5,
+                               ctypes.c_void_p(16), None) == -1
+    assert lib.m2p_interpolate(ctypes.byref(m), ctypes.c_void_p(16), 3, 7, ctypes.c_void_p(16), 5,
+                               ctypes.c_void_p(16), None) == -1
+    assert lib.m2p_interpolate(ctypes.byref(m), None, 3, 0, ctypes.c_void_p(16), 5,
+                               ctypes.c_void_p(16), None) == -1
+    # handle-based calls with a NULL handle
+    assert lib.p2m_project(None, ctypes.c_void_p(16), 1, 0, ctypes.c_void_p(16), None) == -1
+    d = _lib.P2MDiag()
+    assert lib.p2m_weights_diag(None, ctypes.byref(d), None) == -1
+    lib.p2m_weights_destroy(None)
+
+
+def test_options():
+    lib = pkg.load()
+    assert lib.p2m_set_option(b"region_h", 4.0) == 0
+    assert lib.p2m_set_option(b"levels", 3) == 0
+    assert lib.p2m_set_option(b"bin_scale", 1.0) == 0
+    assert lib.p2m_set_option(b"nonsense", 1.0) == -1
+    assert lib.p2m_set_option(b"region_h", 1000.0) == -1
