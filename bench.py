@@ -1,0 +1,240 @@
+#!/usr/bin/env python3
+"""Benchmark of the particle <-> mesh projection round trip on one MI355X.
+
+One step = the whole forward hot path over one synthetic particle set, with
+the particle shape functions rebuilt every step (the method recomputes them
+whenever particles move): binning, weight build (Delaunay + moment solves),
+P2M (eq. p2m) and M2P (eq. m2p) of the P2M result.  Workload: 256x256 mesh,
+1024x1024 jittered lattice (h = H/4, jitter 0.3h), 3 channels (Taylor-Green
+u, v, p), randomly permuted particle order, inputs resident in HBM.
+
+Prints one JSON line.  ``value`` is the round-trip rate of the mixed form
+(FP32 values, weights and sums; FP64 geometry and solves); the plain FP64
+form is timed in the same run and reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+METRIC = "P2M+M2P round-trip Mparticles/s + % HBM roofline; FP32-mixed vs FP64 at ≤1e-5"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_VECTOR_PEAK_TFS = 78.6    # MI355X FP64 vector
+# algorithmic FP64 work of the weight build per node (moment assembly of the
+# three edge systems, Gram/Cholesky/solve with one refinement, weights)
+BUILD_FLOP_INTERIOR = 2100.0
+BUILD_FLOP_CLOSURE = 700.0
+
+
+def parse(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
+    ap.add_argument("--no-oracle-check", action="store_true", help="skip the sampled oracle comparison")
+    ap.add_argument("--cpu-side", type=float, default=1.0,
+                    help="side of the sub-square of the workload the CPU oracle is timed on")
+    return ap.parse_args(argv)
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def rel_errs(got, ref):
+    import numpy as np
+
+    d = np.asarray(got, np.float64) - np.asarray(ref, np.float64)
+    return (float(np.linalg.norm(d) / np.linalg.norm(ref)), float(np.abs(d).max() / np.abs(ref).max()))
+
+
+def cpu_baseline(cloud, side):
+    """Time the CPU oracle (as it stands) on the sub-square [0, side]^2 of the
+    same workload: P2M weights + P2M + M2P of the result."""
+    import numpy as np
+
+    import oracle
+    from oracle import Mesh as OMesh, P2MOracle
+
+    m = cloud.mesh
+    n_sub = int(round(side / m.H))
+    side = n_sub * m.H
+    keep = (cloud.pos[:, 0] <= side) & (cloud.pos[:, 1] <= side)
+    pos = cloud.pos[keep]
+    vals = cloud.vals[keep]
+    om = OMesh(n_sub, n_sub, m.H)
+    try:
+        from threadpoolctl import threadpool_info
+
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    orc = P2MOracle(pos, om, cloud.h)
+    W, _ = orc.matrix()
+    mesh_vals = W @ vals
+    oracle.m2p(om, mesh_vals, pos)
+    t = time.perf_counter() - t0
+    return {
+        "value": round(pos.shape[0] / t / 1e6, 4),
+        "unit": "Mparticles/s",
+        "cores": int(threads),
+        "kind": "oracle",
+        "sample": (f"sub-square [0,{side:g}]^2 of the workload: {pos.shape[0]} particles, "
+                   f"{om.nx}x{om.ny} cells; FP64 Qhull (1 thread) + LAPACK SVD weights + P2M + M2P, "
+                   f"{t:.1f} s"),
+    }
+
+
+def main(argv=None):
+    a = parse(argv)
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU design is "
+              "described in DESIGN.md and is not built.", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1610_05266_amd import load, ops
+    from paper_1610_05266_amd._lib import P2M_WEIGHTS_F32
+
+    lib = load()
+    dev = torch.device("cuda:0")
+    log("generating workload")
+    cloud = wl.config2()
+    mesh = ops.Mesh.of(cloud.mesh)
+    N, C, nn = cloud.N, cloud.vals.shape[1], mesh.n_nodes
+    pos = torch.from_numpy(cloud.pos).to(dev)
+    v64 = torch.from_numpy(cloud.vals).to(dev)
+    v32 = v64.float().contiguous()
+    mesh64 = torch.empty((nn, C), dtype=torch.float64, device=dev)
+    mesh32 = torch.empty((nn, C), dtype=torch.float32, device=dev)
+    out64 = torch.empty((N, C), dtype=torch.float64, device=dev)
+    out32 = torch.empty((N, C), dtype=torch.float32, device=dev)
+    w = ops.Weights()
+    ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32, weights=w, check_diag=True)
+    diag = w.diag()
+    log(f"diag {diag}")
+
+    def step(mixed):
+        ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 if mixed else 0, weights=w, check_diag=False)
+        if mixed:
+            ops.p2m_project(w, v32, out=mesh32)
+            ops.m2p_interpolate(mesh, mesh32, pos, out=out32)
+        else:
+            ops.p2m_project(w, v64, out=mesh64)
+            ops.m2p_interpolate(mesh, mesh64, pos, out=out64)
+
+    def timed(mixed):
+        for _ in range(a.warmup):
+            step(mixed)
+        torch.cuda.synchronize()
+        lib.p2m_profile_enable(1)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(a.steps):
+            step(mixed)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        phases = {}
+        import ctypes
+
+        for ph in ("bin", "build", "project", "m2p"):
+            tot, cnt = ctypes.c_double(), ctypes.c_int64()
+            lib.p2m_profile_read(ph.encode(), ctypes.byref(tot), ctypes.byref(cnt))
+            phases[ph] = tot.value / max(cnt.value, 1)
+        lib.p2m_profile_enable(0)
+        return ms, phases
+
+    log("timing FP64 form")
+    ms64, ph64 = timed(False)
+    log(f"FP64 {ms64:.4f} ms/step phases {ph64}")
+    log("timing mixed form")
+    ms32, ph32 = timed(True)
+    log(f"mixed {ms32:.4f} ms/step phases {ph32}")
+    torch.cuda.synchronize()
+
+    # accuracy of the mixed form against the FP64 form (both full outputs)
+    e_mesh = rel_errs(mesh32.cpu().numpy(), mesh64.cpu().numpy())
+    e_part = rel_errs(out32.cpu().numpy(), out64.cpu().numpy())
+    result_err = {"mixed_vs_fp64_mesh": e_mesh, "mixed_vs_fp64_particles": e_part}
+
+    if not a.no_oracle_check:
+        log("sampled oracle check")
+        from oracle import Mesh as OMesh, P2MOracle
+
+        om = OMesh.from_spec(cloud.mesh)
+        rng = np.random.default_rng(0)
+        sample = np.unique(np.concatenate([rng.choice(nn, 256, replace=False), [0, mesh.nx, nn - 1]]))
+        orc = P2MOracle(cloud.pos, om, cloud.h, mode="local")
+        Ws, _ = orc.matrix(sample)
+        ref = Ws @ cloud.vals
+        result_err["fp64_vs_oracle_sampled_nodes"] = rel_errs(mesh64.cpu().numpy()[sample], ref)
+        result_err["mixed_vs_oracle_sampled_nodes"] = rel_errs(mesh32.cpu().numpy()[sample], ref)
+
+    # roofline of the dominant kernel group
+    dom = max(ph32, key=ph32.get)
+    flops = BUILD_FLOP_INTERIOR * diag["interior_nodes"] + BUILD_FLOP_CLOSURE * diag["closure_nodes"]
+    if dom == "build":
+        achieved = flops / (ph32["build"] * 1e-3) / 1e12
+        roof = {"kernel": "k_build (weight build)", "bound": "alu", "achieved": round(achieved, 4),
+                "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFS, 5),
+                "traffic": None, "algorithmic_per_launch": f"{flops:.4g} FP64 flop "
+                f"({BUILD_FLOP_INTERIOR:g}/interior node, {BUILD_FLOP_CLOSURE:g}/closure node)",
+                "avg_launch_ms": round(ph32["build"], 5)}
+    else:
+        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None, "avg_launch_ms": round(ph32[dom], 5)}
+    b32 = N * (2 * 16 + (4 + 4) * C) + nn * C * (4 + 4)
+    b64 = N * (2 * 16 + (8 + 8) * C) + nn * C * (8 + 8)
+    rt = {"algorithmic_bytes": b32, "achieved_GBs": round(b32 / (ms32 * 1e-3) / 1e9, 2),
+          "frac": round(b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
+    rt64 = {"algorithmic_bytes": b64, "achieved_GBs": round(b64 / (ms64 * 1e-3) / 1e9, 2),
+            "frac": round(b64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("timing the CPU oracle")
+        cpu = cpu_baseline(cloud, a.cpu_side)
+        log(f"cpu baseline {cpu}")
+
+    out = {
+        "metric": METRIC,
+        "value": round(N / (ms32 * 1e-3) / 1e6, 3),
+        "unit": "Mparticles/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ms32, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32 values/weights/sums + fp64 geometry/solves",
+        "data": "synthetic",
+        "config": {"workload": "Taylor-Green round trip, 256x256 mesh (H=1/256), 1024x1024 jittered lattice "
+                               "(h=H/4, jitter 0.3h, seed 2, permuted), 3 channels (u, v, p), weights rebuilt "
+                               "every step", "particles": N, "nodes": nn, "channels": C},
+        "roofline": roof,
+        "round_trip_hbm": rt,
+        "cpu_baseline": cpu,
+        "fp64": {"value": round(N / (ms64 * 1e-3) / 1e6, 3), "ms_per_step": round(ms64, 5),
+                 "round_trip_hbm": rt64, "phases_ms": {k: round(v, 5) for k, v in ph64.items()}},
+        "phases_ms": {k: round(v, 5) for k, v in ph32.items()},
+        "errors": result_err,
+        "diag": diag,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

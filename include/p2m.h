@@ -211,6 +211,15 @@ void p2m_weights_destroy(p2m_weights* w);
  * Returns P2M_EINVAL for an unknown name or a value out of range. */
 int p2m_set_option(const char* name, double value);
 
+/* Event timing of the library's kernel groups, for measurement.
+ * p2m_profile_enable(1) clears the totals and starts recording a pair of HIP
+ * events on the caller's stream around each group ("bin", "build",
+ * "project", "m2p", "m2p_bwd", "project_bwd", "build_bwd"); 0 stops.
+ * p2m_profile_read() waits for the recorded events and returns the summed
+ * GPU time in milliseconds and the number of launches of one group. */
+int p2m_profile_enable(int on);
+int p2m_profile_read(const char* phase, double* total_ms, int64_t* count);
+
 /* Thread-local description of the last error (never NULL). */
 const char* p2m_last_error(void);
 

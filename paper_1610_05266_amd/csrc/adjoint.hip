@@ -301,6 +301,7 @@ __global__ void __launch_bounds__(256) k_export(WeightsView w, int32_t* __restri
 
 int build_backward(const WeightsView& w, const double* pos, const double* grad_w, double* grad_pos,
                    hipStream_t st) {
+    PhaseTimer _timer(PH_BUILD_BWD, st);
     BArgs a;
     a.w = w;
     a.pos = reinterpret_cast<const double2*>(pos);

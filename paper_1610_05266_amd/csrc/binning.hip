@@ -175,6 +175,7 @@ int exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum, hi
 
 int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const MeshD& m, const Grid& g,
                   unsigned long long* diag, hipStream_t st) {
+    PhaseTimer _timer(PH_BIN, st);
     const int64_t nbins = static_cast<int64_t>(g.nbx) * g.nby;
     // count[0..nbins] (the last entry collects invalid particles)
     int rc = fill_i32(b.count, 0, nbins + 1, st);

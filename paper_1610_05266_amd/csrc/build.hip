@@ -783,6 +783,7 @@ __global__ void __launch_bounds__(WG) k_build(KArgs a) {
 
 int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N, const BuildOut& out,
                   const BuildParams& prm, unsigned long long* diag, hipStream_t st) {
+    PhaseTimer _timer(PH_BUILD, st);
     (void)N;
     KArgs a;
     a.pos_s = reinterpret_cast<const double2*>(b.pos_s);

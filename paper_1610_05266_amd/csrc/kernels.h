@@ -5,6 +5,21 @@
 
 namespace p2m {
 
+// ---- optional event timing of kernel groups (profile.hip) ----
+enum Phase : int { PH_BIN = 0, PH_BUILD, PH_PROJECT, PH_M2P, PH_M2P_BWD, PH_PROJECT_BWD, PH_BUILD_BWD, PH_COUNT };
+class PhaseTimer {
+  public:
+    PhaseTimer(int phase, hipStream_t st);
+    ~PhaseTimer();
+    PhaseTimer(const PhaseTimer&) = delete;
+    PhaseTimer& operator=(const PhaseTimer&) = delete;
+
+  private:
+    int phase_;
+    hipStream_t st_;
+    hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
 // ---- utilities (util.hip) ----
 int fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t st);
 int fill_u64(unsigned long long* p, unsigned long long v, int64_t n, hipStream_t st);

@@ -136,6 +136,7 @@ __global__ void __launch_bounds__(256) k_m2p_bwd(MeshD m, const TM* __restrict__
 
 int m2p(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N, void* vals,
         hipStream_t st) {
+    PhaseTimer _timer(PH_M2P, st);
     if (dtype == P2M_F64)
         launch_m2p<double, double>(m, mesh_vals, C, pos, N, vals, st);
     else if (dtype == P2M_F32)
@@ -148,6 +149,7 @@ int m2p(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* p
 
 int m2p_backward(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N,
                  const void* grad_vals, void* grad_mesh, double* grad_pos, hipStream_t st) {
+    PhaseTimer _timer(PH_M2P_BWD, st);
     const int blocks = static_cast<int>((N + 255) / 256);
     const int64_t nn = static_cast<int64_t>(m.nx + 1) * (m.ny + 1);
     const double2* P = reinterpret_cast<const double2*>(pos);

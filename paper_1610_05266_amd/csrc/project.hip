@@ -89,6 +89,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const uint32_t* __restrict_
 }  // namespace
 
 int project(const WeightsView& wv, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st) {
+    PhaseTimer _timer(PH_PROJECT, st);
     if (dtype == P2M_F64) {
         launch_project<double, double, double>(wv, wv.w64, vals, C, mesh_vals, st);
     } else {
@@ -107,6 +108,7 @@ int project(const WeightsView& wv, const void* vals, int C, int dtype, void* mes
 
 int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dtype, const void* vals,
                      void* grad_vals, double* grad_w, hipStream_t st) {
+    PhaseTimer _timer(PH_PROJECT_BWD, st);
     const int blocks = static_cast<int>((wv.n_nodes + 255) / 256);
     if (dtype == P2M_F64) {
         if (grad_vals) {
