@@ -205,7 +205,10 @@ void p2m_weights_destroy(p2m_weights* w);
 /* Process-wide tuning knobs for the weight build (performance only; results
  * do not depend on them).  Not thread-safe with concurrent builds.
  *   "bin_scale"  bin width ~ bin_scale * h        (0.25 .. 8,  default 1)
- *   "region_h"   first search half-width / h      (1 .. 64,    default 4)
+ *   "fast_radius" candidate radius / h of the
+ *                register-resident first pass     (1.5 .. 8,   default 2.8)
+ *   "region_h"   first search half-width / h of
+ *                the fallback pass                (1 .. 64,    default 4)
  *   "levels"     region doublings before a scan
  *                of every particle                (0 .. 8,     default 3)
  * Returns P2M_EINVAL for an unknown name or a value out of range. */
@@ -214,7 +217,8 @@ int p2m_set_option(const char* name, double value);
 /* Event timing of the library's kernel groups, for measurement.
  * p2m_profile_enable(1) clears the totals and starts recording a pair of HIP
  * events on the caller's stream around each group ("bin", "build",
- * "project", "m2p", "m2p_bwd", "project_bwd", "build_bwd"); 0 stops.
+ * "project", "m2p", "m2p_bwd", "project_bwd", "build_bwd", and the three
+ * parts of "build": "build_fast", "build_slow", "weights"); 0 stops.
  * p2m_profile_read() waits for the recorded events and returns the summed
  * GPU time in milliseconds and the number of launches of one group. */
 int p2m_profile_enable(int on);

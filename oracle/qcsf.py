@@ -117,6 +117,8 @@ def min_norm_svd(M, b, k_eff):
     c = np.einsum("...ji,...j->...i", U, b)
     c = np.where(keep, c / np.where(keep, sig, 1.0), 0.0)
     A = np.einsum("...ij,...i->...j", Vt, c)
+    if sig.shape[-1] < 6:  # fewer columns than conditions: report 6 values
+        sig = np.concatenate([sig, np.zeros(sig.shape[:-1] + (6 - sig.shape[-1],))], axis=-1)
     return A, keep.sum(-1), sig
 
 

@@ -1,6 +1,6 @@
 // Weight build: psi_mu(r_i) at every mesh node (App. B of the paper).
 //
-// One thread per mesh node.  For an interior node q:
+// For an interior node q:
 //   1. Delaunay triangle T = (a, b, c) of the particles containing q, found by
 //      local gift-wrapping: the apex of the Delaunay triangle on one side of a
 //      Delaunay edge (v, a) is the candidate that minimises the position of the
@@ -25,12 +25,24 @@
 // P2M_CLOSURE_K nearest particles.
 //
 // Every Delaunay decision is certified: a triangle is used only if its
-// circumdisk lies inside the searched bin region (sides of the region on the
-// mesh boundary count as walls: no particle lies beyond them).  Otherwise the
-// node is redone with a region of twice the half-width, and finally with all
-// particles (where every decision is certified).  Near-ties of the FP64
-// predicates (|det| within a forward error bound) are counted and broken by
-// the user particle id.
+// circumdisk lies inside a region all of whose particles were candidates.
+// Near-ties of the FP64 predicates (|det| within a forward error bound) are
+// counted and broken by the user particle id.
+//
+// Execution (three kernels): the FAST kernel gives each interior node a quad
+// of four lanes.
+// The lanes hold the particles within a radius Rf of the node in registers,
+// split round-robin, so each gift-wrapping step is a short register loop plus
+// a two-step quad reduction; a decision is certified when its disk lies in
+// the disk of radius Rf around the node.  A node whose decisions cannot all
+// be certified there (or any node on the mesh's outer ring) is appended to a
+// list for the SLOW kernel: one wave per node scanning square bin regions
+// that double in size up to all particles (closure nodes get their weights
+// there).  Both leave each interior node's support in its ELL row, and the
+// WEIGHTS kernel (again a quad per node) turns every such row into weights,
+// so the result of a node does not depend on the path that found its
+// triangle.
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 
@@ -40,11 +52,137 @@ namespace p2m {
 
 namespace {
 
-constexpr int WG = 64;
 constexpr double EPS = DBL_EPSILON;
+constexpr int WAVE = 64;
+constexpr int SWG = 256;       // slow kernel: four waves, one node per wave
+constexpr int QL = 4;          // lanes per node in the quad kernels
+constexpr int NS = 10;         // candidate slots per lane (fast kernel)
+constexpr int QWG = 256;       // quad kernels: 64 nodes per block
+constexpr int QPB = QWG / QL;
+constexpr int MS = KMAX / QL;  // support entries per lane
+constexpr uint32_t IDX_MASK = 0x0fffffffu;
 
 enum Result : int { R_OK = 0, R_MORE = 1, R_OUTSIDE = 2, R_FAIL = 3, R_CAP = 4 };
 
+__device__ __forceinline__ double orient(double2 p, double2 q, double2 r) {
+    return (q.x - p.x) * (r.y - p.y) - (q.y - p.y) * (r.x - p.x);
+}
+
+__device__ __forceinline__ double2 node_pos(const MeshD& m, int i, int j) {
+    return make_double2(add_rn(m.x0, mul_rn(static_cast<double>(i), m.H)),
+                        add_rn(m.y0, mul_rn(static_cast<double>(j), m.H)));
+}
+
+// ------------------------------------------------- candidate comparisons
+// Bisector key of candidate b for the edge v -> a on side sgn: the circumcentre
+// of (v, a, b) is v + A/2 + (num / 2cr) sgn perp(A), with A = a - v, B = b - v,
+// num = B.(B - A), cr = sgn cross(A, B) > 0.  Smaller key = touched first.
+struct Key {
+    int t;           // sorted index, -1 = none
+    double num, cr;  // key = num / cr
+    double Nm, Cm;   // magnitudes for the forward error bound
+    double bx, by;   // the candidate's position
+};
+
+__device__ __forceinline__ Key no_key() {
+    Key k;
+    k.t = -1;
+    k.num = k.cr = k.Nm = k.Cm = k.bx = k.by = 0.0;
+    return k;
+}
+
+__device__ __forceinline__ Key key_of(int t, double2 v, double2 a, double2 b, double sgn, int& neardeg) {
+    Key k;
+    const double Ax = a.x - v.x, Ay = a.y - v.y;
+    const double Bx = b.x - v.x, By = b.y - v.y;
+    k.cr = sgn * (Ax * By - Ay * Bx);
+    k.Cm = fabs(Ax) * fabs(By) + fabs(Ay) * fabs(Bx);
+    k.num = Bx * (Bx - Ax) + By * (By - Ay);
+    k.Nm = Bx * Bx + By * By + fabs(Bx * Ax) + fabs(By * Ay);
+    k.bx = b.x;
+    k.by = b.y;
+    k.t = t;
+    if (k.cr <= 4.0 * EPS * k.Cm) {
+        if (k.cr > -4.0 * EPS * k.Cm) ++neardeg;  // (nearly) on the line through v, a
+        k.t = -1;
+    }
+    return k;
+}
+
+// true if `o` is touched before `m` (ties within the error bound go to the
+// smaller user id; `uid` maps a sorted index to the user id).
+template <class Uid>
+__device__ __forceinline__ bool key_better(const Key& o, const Key& m, Uid uid, int& neardeg) {
+    if (o.t < 0) return false;
+    if (m.t < 0) return true;
+    if (o.t == m.t) return false;
+    const double lhs = o.num * m.cr, rhs = m.num * o.cr;
+    const double err = 16.0 * EPS * (o.Nm * m.Cm + m.Nm * o.Cm);
+    if (lhs < rhs - err) return true;
+    if (lhs > rhs + err) return false;
+    ++neardeg;
+    return uid(o.t) < uid(m.t);
+}
+
+__device__ __forceinline__ void circumcircle(const Key& k, double2 v, double2 a, double sgn, double& cx,
+                                             double& cy, double& rr) {
+    const double Ax = a.x - v.x, Ay = a.y - v.y;
+    const double tk = k.num / (2.0 * k.cr);
+    const double ox = 0.5 * Ax - sgn * tk * Ay;
+    const double oy = 0.5 * Ay + sgn * tk * Ax;
+    cx = v.x + ox;
+    cy = v.y + oy;
+    rr = sqrt(ox * ox + oy * oy);
+}
+
+// Butterfly reductions over groups of W lanes: every lane of a group ends
+// with the same answer.  Near-ties met during the reduction are counted once
+// per pair (by its lower lane).
+template <int W, class Uid>
+__device__ __forceinline__ void reduce_key(Key& best, Uid uid, int lane, int& nd) {
+#pragma unroll
+    for (int m = 1; m < W; m <<= 1) {
+        Key o;
+        o.t = __shfl_xor(best.t, m, W);
+        o.num = __shfl_xor(best.num, m, W);
+        o.cr = __shfl_xor(best.cr, m, W);
+        o.Nm = __shfl_xor(best.Nm, m, W);
+        o.Cm = __shfl_xor(best.Cm, m, W);
+        o.bx = __shfl_xor(best.bx, m, W);
+        o.by = __shfl_xor(best.by, m, W);
+        int dummy = 0;
+        if (key_better(o, best, uid, (lane & m) ? dummy : nd)) best = o;
+    }
+}
+
+template <int W>
+__device__ __forceinline__ void reduce_nearest(double& d2, int& t, double2& p, const int32_t* perm) {
+#pragma unroll
+    for (int m = 1; m < W; m <<= 1) {
+        const double od = __shfl_xor(d2, m, W);
+        const int ot = __shfl_xor(t, m, W);
+        const double ox = __shfl_xor(p.x, m, W), oy = __shfl_xor(p.y, m, W);
+        bool take = false;
+        if (ot >= 0 && ot != t) {
+            if (t < 0 || od < d2) take = true;
+            else if (od == d2) take = perm[ot] < perm[t];
+        }
+        if (take) {
+            d2 = od;
+            t = ot;
+            p = make_double2(ox, oy);
+        }
+    }
+}
+
+template <int W>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int m = 1; m < W; m <<= 1) v += __shfl_xor(v, m, W);
+    return v;
+}
+
+// ------------------------------------------------ slow candidate source
 struct Region {
     int bx0, bx1, by0, by1;
     double xlo, xhi, ylo, yhi;
@@ -66,269 +204,399 @@ __device__ Region make_region(const Grid& g, int cbx, int cby, int hw) {
     return R;
 }
 
-__device__ __forceinline__ bool disk_inside(const Region& R, double cx, double cy, double r) {
-    r *= 1.0 + 1e-9;
-    return cx - r >= R.xlo && cx + r <= R.xhi && cy - r >= R.ylo && cy + r <= R.yhi;
-}
-
-struct Ctx {
-    const double2* __restrict__ pos;  // sorted positions
+// A whole wave per node, scanning a square region of bins (sides on the
+// mesh boundary are walls: no particle lies beyond them); the candidates are
+// dealt round-robin over the 64 lanes.
+struct WaveSource {
+    const double2* __restrict__ pos;
     const int32_t* __restrict__ perm;
     const int32_t* __restrict__ start;
     Grid g;
     Region R;
     int neardeg;
-};
+    int lane;
 
-__device__ __forceinline__ double orient(double2 p, double2 q, double2 r) {
-    return (q.x - p.x) * (r.y - p.y) - (q.y - p.y) * (r.x - p.x);
-}
-
-// Nearest candidate to (qx, qy) other than `exclude`; ties -> smaller user id.
-__device__ int nearest(Ctx& c, double qx, double qy, int exclude, double& d2best) {
-    int best = -1;
-    int buid = -1;
-    d2best = INFINITY;
-    for (int by = c.R.by0; by < c.R.by1; ++by) {
-        const int row = by * c.g.nbx;
-        const int s = c.start[row + c.R.bx0], e = c.start[row + c.R.bx1];
-        for (int t = s; t < e; ++t) {
-            if (t == exclude) continue;
-            const double2 p = c.pos[t];
-            const double dx = p.x - qx, dy = p.y - qy;
+    __device__ bool global() const { return R.global; }
+    __device__ double2 P(int t) const { return pos[t]; }
+    __device__ bool certify(double cx, double cy, double r) const {
+        r *= 1.0 + 1e-9;
+        return cx - r >= R.xlo && cx + r <= R.xhi && cy - r >= R.ylo && cy + r <= R.yhi;
+    }
+    template <class F>
+    __device__ void scan(F&& f) const {
+        int flat = 0;
+        for (int by = R.by0; by < R.by1; ++by) {
+            const int row = by * g.nbx;
+            const int s = start[row + R.bx0], e = start[row + R.bx1];
+            for (int t = s + ((lane - flat) & (WAVE - 1)); t < e; t += WAVE) f(t, pos[t]);
+            flat += e - s;
+        }
+    }
+    __device__ int nearest(double2 c, int exclude, double& d2best, double2& pbest) {
+        int best = -1;
+        d2best = INFINITY;
+        pbest = make_double2(0.0, 0.0);
+        scan([&](int t, double2 p) {
+            if (t == exclude) return;
+            const double dx = p.x - c.x, dy = p.y - c.y;
             const double d2 = dx * dx + dy * dy;
-            if (d2 < d2best) {
+            if (d2 < d2best || (d2 == d2best && best >= 0 && perm[t] < perm[best])) {
                 best = t;
                 d2best = d2;
-                buid = -1;
-            } else if (d2 == d2best) {
-                if (buid < 0) buid = c.perm[best];
-                const int u = c.perm[t];
-                if (u < buid) {
-                    best = t;
-                    buid = u;
-                }
+                pbest = p;
+            }
+        });
+        reduce_nearest<WAVE>(d2best, best, pbest, perm);
+        return best;
+    }
+    __device__ Key wrap(int iv, double2 v, int ia, double2 a, double sgn) {
+        Key best = no_key();
+        auto uid = [&](int t) { return perm[t]; };
+        int nd = 0;
+        scan([&](int t, double2 b) {
+            if (t == iv || t == ia) return;
+            const Key k = key_of(t, v, a, b, sgn, nd);
+            if (key_better(k, best, uid, nd)) best = k;
+        });
+        reduce_key<WAVE>(best, uid, lane, nd);
+        neardeg += nd;
+        return best;
+    }
+};
+
+// -------------------------------------------------- fast candidate source
+// Four lanes of a quad hold the node's candidates (particles within Rf of
+// the node q) in registers; every query is a lane-local loop plus a
+// two-step reduction, after which all four lanes agree on the answer.
+struct QuadSource {
+    const double2* __restrict__ pos;
+    const int32_t* __restrict__ perm;
+    double2 q;
+    double Rf;
+    double cx_[NS], cy_[NS];
+    int ct_[NS];
+    int n;
+    int lane;  // 0..3
+
+    __device__ bool global() const { return false; }
+    __device__ bool certify(double cx, double cy, double r) const {
+        const double dx = cx - q.x, dy = cy - q.y;
+        return sqrt(dx * dx + dy * dy) + r * (1.0 + 1e-9) <= Rf * (1.0 - 1e-12);
+    }
+    __device__ int nearest(double2 c, int exclude, double& d2best, double2& pbest) {
+        int best = -1;
+        d2best = INFINITY;
+        pbest = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (s >= n) continue;
+            const int t = ct_[s];
+            if (t == exclude) continue;
+            const double dx = cx_[s] - c.x, dy = cy_[s] - c.y;
+            const double d2 = dx * dx + dy * dy;
+            if (d2 < d2best || (d2 == d2best && best >= 0 && perm[t] < perm[best])) {
+                best = t;
+                d2best = d2;
+                pbest = make_double2(cx_[s], cy_[s]);
             }
         }
+        reduce_nearest<QL>(d2best, best, pbest, perm);
+        return best;
     }
-    return best;
-}
-
-// Apex of the Delaunay triangle on side `sgn` (+1 left, -1 right) of the
-// directed edge v -> a, among the region's candidates: the candidate b with
-// sgn*cross(a-v, b-v) > 0 minimising t_b = |B|^2 - A.B over 2 sgn cross(A, B),
-// the bisector coordinate of the circumcentre of (v, a, b).  Returns -1 when
-// no candidate lies strictly on that side.  (cx, cy, rr): circumcircle.
-__device__ int wrap(Ctx& c, int iv, double2 v, int ia, double2 a, double sgn, double& cx, double& cy,
-                    double& rr) {
-    const double Ax = a.x - v.x, Ay = a.y - v.y;
-    const double aAx = fabs(Ax), aAy = fabs(Ay);
-    int best = -1, buid = -1;
-    double bn = 0.0, bc = 1.0, bN = 0.0, bC = 0.0;
-    for (int by = c.R.by0; by < c.R.by1; ++by) {
-        const int row = by * c.g.nbx;
-        const int s = c.start[row + c.R.bx0], e = c.start[row + c.R.bx1];
-        for (int t = s; t < e; ++t) {
-            if (t == iv || t == ia) continue;
-            const double2 b = c.pos[t];
-            const double Bx = b.x - v.x, By = b.y - v.y;
-            const double cr = sgn * (Ax * By - Ay * Bx);
-            const double Cm = aAx * fabs(By) + aAy * fabs(Bx);
-            if (cr <= 4.0 * EPS * Cm) {
-                if (cr > -4.0 * EPS * Cm) ++c.neardeg;  // (nearly) on the line through v, a
-                continue;
-            }
+    __device__ double2 P(int t) const { return pos[t]; }
+    // A branch-free loop that compares bisector keys against a static
+    // forward error bound valid for every candidate (all candidates, and v
+    // and a, lie within Rf of q, so |A|, |B| <= 2 Rf and both error
+    // magnitudes of key_of are <= 8 Rf^2).  Outside that bound its decisions
+    // are the exact ones.  When any comparison falls inside it -- a near
+    // tie, or a candidate nearly on the line through v and a -- the answer
+    // is t = -2 and the node is left to the wave path, which compares with
+    // per-candidate bounds and breaks ties by user id.
+    __device__ Key wrap(int iv, double2 v, int ia, double2 a, double sgn) {
+        const double Ax = a.x - v.x, Ay = a.y - v.y;
+        const double nx = -sgn * Ay, ny = sgn * Ax;  // sgn cross(A, B) = n . B
+        const double R2 = Rf * Rf;
+        const double crmin = 32.0 * EPS * R2;
+        const double errS = 2048.0 * EPS * R2 * R2;
+        int bt = -1;
+        double bn = 0.0, bc = 1.0, bx = 0.0, by = 0.0;
+        bool amb = false;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const double Bx = cx_[s] - v.x, By = cy_[s] - v.y;
+            const double cr = nx * Bx + ny * By;
             const double num = Bx * (Bx - Ax) + By * (By - Ay);
-            const double Nm = Bx * Bx + By * By + fabs(Bx * Ax) + fabs(By * Ay);
-            if (best < 0) {
-                best = t;
-                bn = num;
-                bc = cr;
-                bN = Nm;
-                bC = Cm;
-                buid = -1;
-                continue;
-            }
-            const double lhs = num * bc, rhs = bn * cr;
-            const double err = 16.0 * EPS * (Nm * bC + bN * Cm);
-            bool take = lhs < rhs - err;
-            if (!take && lhs <= rhs + err) {  // co-circular within rounding
-                ++c.neardeg;
-                if (buid < 0) buid = c.perm[best];
-                const int u = c.perm[t];
-                take = u < buid;
-                if (take) buid = u;
-            } else if (take) {
-                buid = -1;
-            }
-            if (take) {
-                best = t;
-                bn = num;
-                bc = cr;
-                bN = Nm;
-                bC = Cm;
-            }
+            const bool ok = s < n && ct_[s] != iv && ct_[s] != ia;
+            const bool left = ok && cr > crmin;
+            const double d = num * bc - bn * cr;
+            amb = amb || (ok && fabs(cr) <= crmin) || (left && bt >= 0 && fabs(d) <= errS);
+            const bool take = left && (bt < 0 || d < -errS);
+            bt = take ? ct_[s] : bt;
+            bn = take ? num : bn;
+            bc = take ? cr : bc;
+            bx = take ? cx_[s] : bx;
+            by = take ? cy_[s] : by;
         }
+#pragma unroll
+        for (int m = 1; m < QL; m <<= 1) {
+            const int ot = __shfl_xor(bt, m, QL);
+            const double on = __shfl_xor(bn, m, QL), oc = __shfl_xor(bc, m, QL);
+            const double ox = __shfl_xor(bx, m, QL), oy = __shfl_xor(by, m, QL);
+            const double d = on * bc - bn * oc;
+            const bool other = ot >= 0 && ot != bt;
+            amb = amb || (other && bt >= 0 && fabs(d) <= errS);
+            const bool take = other && (bt < 0 || d < -errS);
+            bt = take ? ot : bt;
+            bn = take ? on : bn;
+            bc = take ? oc : bc;
+            bx = take ? ox : bx;
+            by = take ? oy : by;
+        }
+        int am = amb ? 1 : 0;
+        am |= __shfl_xor(am, 1, QL);
+        am |= __shfl_xor(am, 2, QL);
+        Key k;
+        k.t = am ? -2 : bt;
+        k.num = bn;
+        k.cr = bc;
+        k.Nm = k.Cm = 0.0;
+        k.bx = bx;
+        k.by = by;
+        return k;
     }
-    if (best >= 0) {
-        const double tk = bn / (2.0 * bc);
-        const double ox = 0.5 * Ax - sgn * tk * Ay;
-        const double oy = 0.5 * Ay + sgn * tk * Ax;
-        cx = v.x + ox;
-        cy = v.y + oy;
-        rr = sqrt(ox * ox + oy * oy);
+};
+
+// ------------------------------------------------- the Delaunay routine
+// Support list U of one node: sorted particle index | membership << 28,
+// entry k at u[k].  The W lanes cooperating on a node search it together
+// (lane l checks entries l, l + W, ...) and perform identical updates.
+template <int W>
+struct Support {
+    int32_t* u;
+    int n;
+    int lane;
+    __device__ int find(int t) const {
+        int f = -1;
+        for (int k = lane; k < n; k += W)
+            if (static_cast<int>(static_cast<uint32_t>(u[k]) & IDX_MASK) == t) f = k;
+#pragma unroll
+        for (int m = 1; m < W; m <<= 1) f = max(f, __shfl_xor(f, m, W));
+        return f;
     }
-    return best;
+    __device__ bool add(int t, int bit) {
+        const int f = find(t);
+        if (f >= 0) {
+            const int e = u[f];
+            __builtin_amdgcn_wave_barrier();
+            u[f] = e | (bit << 28);
+        } else {
+            if (n >= KMAX) return false;
+            u[n] = t | (bit << 28);
+            ++n;
+        }
+        __builtin_amdgcn_wave_barrier();
+        return true;
+    }
+};
+
+template <class T>
+__device__ __forceinline__ T sel3(const T a[3], int i) {
+    return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
 }
 
-// Triangle containing q, as sorted indices (CCW).  R_OUTSIDE when q is
-// outside the convex hull (only concluded with the global region).
-__device__ int locate(Ctx& c, double2 q, int T[3]) {
+// Delaunay work of one node q: the triangle T (CCW, sorted indices) of the
+// particles' Delaunay triangulation that contains q, and the rings of its
+// three vertices (into S, bit k for the ring of T[k]).  Three phases, each a
+// loop around one gift-wrapping step:
+//   wedge   rotate about the nearest particle n0 (from its nearest
+//           neighbour a0, a Delaunay neighbour) to the wedge holding q;
+//           clockwise as well for a hull vertex (only a global source sees one);
+//   walk    visibility walk across the edge facing q;
+//   rings   rotate about T[k] from the known triangle T back to it (clockwise
+//           for the rest of an open fan of a hull vertex).
+// Work is reused: when q lies in a triangle at n0, the ring of n0 only
+// rotates until it meets the neighbours the wedge search visited (kept in
+// `vis`); the first step of rings 1 and 2 and the last step of ring 2 are
+// triangles across an edge of T that an earlier ring already found.
+// Returns R_OK, R_OUTSIDE (q outside the convex hull), R_MORE (not
+// certified by this source), R_FAIL or R_CAP.
+template <class G, class S_>
+__device__ int delaunay_node(G& g, double2 q, int T[3], S_& S, int32_t* vis) {
     double d2;
-    const int n0 = nearest(c, q.x, q.y, -1, d2);
+    double2 v;
+    const int n0 = g.nearest(q, -1, d2, v);
     if (n0 < 0) return R_MORE;
-    if (!disk_inside(c.R, q.x, q.y, sqrt(d2))) return R_MORE;
-    const double2 v = c.pos[n0];
+    if (!g.certify(q.x, q.y, sqrt(d2))) return R_MORE;
     double e2;
-    const int a0 = nearest(c, v.x, v.y, n0, e2);
-    if (a0 < 0) return c.R.global ? R_OUTSIDE : R_MORE;
+    double2 pa0;
+    const int a0 = g.nearest(v, n0, e2, pa0);
+    if (a0 < 0) return g.global() ? R_OUTSIDE : R_MORE;
     // the nearest neighbour of v is a Delaunay neighbour of v
-    if (!disk_inside(c.R, v.x, v.y, sqrt(e2))) return R_MORE;
+    if (!g.certify(v.x, v.y, sqrt(e2))) return R_MORE;
     double cx, cy, rr;
-    int ta = -1, tb = -1, tcc = -1;
-    bool found = false;
-    bool open = false;
+
+    // ---- wedge: T = (n0, cur, next) with q between cur and next
+    double2 PT[3] = {v, v, v};
     int cur = a0;
-    double2 pc = c.pos[a0];
+    double2 pcur = pa0;
+    int nvis = 1;
+    vis[0] = a0;
+    bool found = false, open = false;
     for (int step = 0; step < 2 * KMAX; ++step) {
-        const int nx = wrap(c, n0, v, cur, pc, 1.0, cx, cy, rr);
-        if (nx < 0) {
-            if (!c.R.global) return R_MORE;
+        const Key k = g.wrap(n0, v, cur, pcur, 1.0);
+        if (k.t == -2) return R_MORE;
+        if (k.t < 0) {
+            if (!g.global()) return R_MORE;
             open = true;
             break;
         }
-        if (!disk_inside(c.R, cx, cy, rr)) return R_MORE;
-        const double2 pn = c.pos[nx];
-        if (d2 == 0.0 || (orient(v, pc, q) >= 0.0 && orient(v, pn, q) < 0.0)) {
-            ta = n0;
-            tb = cur;
-            tcc = nx;
+        circumcircle(k, v, pcur, 1.0, cx, cy, rr);
+        if (!g.certify(cx, cy, rr)) return R_MORE;
+        const double2 pk = make_double2(k.bx, k.by);
+        if (d2 == 0.0 || (orient(v, pcur, q) >= 0.0 && orient(v, pk, q) < 0.0)) {
+            T[0] = n0; T[1] = cur; T[2] = k.t;
+            PT[0] = v; PT[1] = pcur; PT[2] = pk;
             found = true;
             break;
         }
-        cur = nx;
-        pc = pn;
-        if (cur == a0) return R_FAIL;
+        // a full turn (or a step past a0 through co-circular ties) without
+        // finding the wedge: numerically inconsistent
+        if (k.t == a0 || (orient(v, pcur, pa0) > 0.0 && orient(v, pa0, pk) > 0.0)) return R_FAIL;
+        if (nvis >= KMAX) return R_CAP;
+        vis[nvis++] = k.t;
+        cur = k.t;
+        pcur = pk;
     }
     if (!found && !open) return R_FAIL;
     if (!found) {
-        // v is a hull vertex: rotate clockwise from a0 over the rest of its fan
+        // n0 is a hull vertex: rotate clockwise from a0 over the rest of its fan
+        nvis = 0;
         cur = a0;
-        pc = c.pos[a0];
+        pcur = pa0;
         for (int step = 0; step < 2 * KMAX; ++step) {
-            const int pv = wrap(c, n0, v, cur, pc, -1.0, cx, cy, rr);
-            if (pv < 0) {
-                if (d2 == 0.0) return R_FAIL;
-                return R_OUTSIDE;  // q outside the cone of the open fan
-            }
-            const double2 pp = c.pos[pv];
-            if (d2 == 0.0 || (orient(v, pp, q) >= 0.0 && orient(v, pc, q) < 0.0)) {
-                ta = n0;
-                tb = pv;
-                tcc = cur;
+            const Key k = g.wrap(n0, v, cur, pcur, -1.0);
+            if (k.t == -2) return R_MORE;
+            if (k.t < 0) return d2 == 0.0 ? R_FAIL : R_OUTSIDE;  // q outside the open fan's cone
+            const double2 pk = make_double2(k.bx, k.by);
+            if (d2 == 0.0 || (orient(v, pk, q) >= 0.0 && orient(v, pcur, q) < 0.0)) {
+                T[0] = n0; T[1] = k.t; T[2] = cur;
+                PT[0] = v; PT[1] = pk; PT[2] = pcur;
                 found = true;
                 break;
             }
-            cur = pv;
-            pc = pp;
+            if (k.t == a0) return R_FAIL;
+            cur = k.t;
+            pcur = pk;
         }
         if (!found) return R_FAIL;
     }
-    // visibility walk towards q
-    for (int step = 0; step < 256; ++step) {
-        const double2 pa = c.pos[ta], pb = c.pos[tb], pcc = c.pos[tcc];
-        int X, Y;
-        if (orient(pb, pcc, q) < 0.0) {
-            X = tb;
-            Y = tcc;
-        } else if (orient(pcc, pa, q) < 0.0) {
-            X = tcc;
-            Y = ta;
-        } else if (orient(pa, pb, q) < 0.0) {
-            X = ta;
-            Y = tb;
-        } else {
-            T[0] = ta;
-            T[1] = tb;
-            T[2] = tcc;
-            return R_OK;
-        }
+
+    // ---- walk towards q
+    bool walked = false;
+    for (int step = 0;; ++step) {
+        int we;
+        if (orient(PT[1], PT[2], q) < 0.0) we = 1;
+        else if (orient(PT[2], PT[0], q) < 0.0) we = 2;
+        else if (orient(PT[0], PT[1], q) < 0.0) we = 0;
+        else break;
+        if (step >= 256) return R_FAIL;
         // across edge X -> Y lies the triangle (Y, X, D), D left of Y -> X
-        const int D = wrap(c, Y, c.pos[Y], X, c.pos[X], 1.0, cx, cy, rr);
-        if (D < 0) return c.R.global ? R_OUTSIDE : R_MORE;
-        if (!disk_inside(c.R, cx, cy, rr)) return R_MORE;
-        ta = Y;
-        tb = X;
-        tcc = D;
+        const int w1 = we == 2 ? 0 : we + 1;
+        const int tX = sel3(T, we), tY = sel3(T, w1);
+        const double2 qX = sel3(PT, we), qY = sel3(PT, w1);
+        const Key k = g.wrap(tY, qY, tX, qX, 1.0);
+        if (k.t == -2) return R_MORE;
+        if (k.t < 0) return g.global() ? R_OUTSIDE : R_MORE;
+        circumcircle(k, qY, qX, 1.0, cx, cy, rr);
+        if (!g.certify(cx, cy, rr)) return R_MORE;
+        T[0] = tY; T[1] = tX; T[2] = k.t;
+        PT[0] = qY; PT[1] = qX; PT[2] = make_double2(k.bx, k.by);
+        walked = true;
+    }
+
+    // ---- the three rings
+    bool reuse0 = !walked && nvis > 0 && T[0] == n0 && T[1] == vis[nvis - 1];
+    bool chain = true;   // no open fan so far: the shared-triangle shortcuts hold
+    bool cwise = false;  // rotating clockwise through the rest of an open fan
+    int x0 = -1;         // first apex of ring 0 (across edge T0-T2)
+    int nrot = 0;        // apexes found by rotation in the current ring
+    int rk = 0;
+    if (!S.add(T[1], 1) || !S.add(T[2], 1)) return R_CAP;
+    cur = T[2];
+    pcur = PT[2];
+    for (int it = 0; it < 8 * KMAX; ++it) {
+        const int f = rk == 2 ? 0 : rk + 1;
+        const int first = sel3(T, f);
+        const double2 pf = sel3(PT, f);
+        const double2 pvk = sel3(PT, rk);
+        bool closed = false;
+        int pred = cur;  // apex preceding `first` when the ring closes
+        double2 ppred = pcur;
+        int nt = -1;
+        double2 pk = pcur;
+        if (rk == 2 && chain && x0 >= 0 && cur == x0) {
+            closed = true;  // ring 2 reached x0: the next apex is T[0]
+        } else {
+            const double sgn = cwise ? -1.0 : 1.0;
+            const Key k = g.wrap(sel3(T, rk), pvk, cur, pcur, sgn);
+            if (k.t == -2) return R_MORE;
+            nt = k.t;
+            pk = make_double2(k.bx, k.by);
+            if (cwise) {
+                closed = nt < 0;
+            } else if (nt < 0) {
+                if (!g.global()) return R_MORE;
+                // open fan (hull vertex): the rest lies clockwise from `first`
+                cwise = true;
+                chain = false;
+                reuse0 = false;
+                cur = first;
+                pcur = pf;
+                continue;
+            } else {
+                circumcircle(k, pvk, pcur, 1.0, cx, cy, rr);
+                if (!g.certify(cx, cy, rr)) return R_MORE;
+                if (rk == 0 && reuse0) {
+                    // co-circular ties can step past the stop: the turn is then complete
+                    closed = nt == a0 || (orient(pvk, pcur, pa0) > 0.0 && orient(pvk, pa0, pk) > 0.0);
+                    if (closed) {
+                        for (int s = 0; s < nvis; ++s)
+                            if (!S.add(vis[s], 1)) return R_CAP;
+                        if (nvis >= 2) {
+                            pred = vis[nvis - 2];
+                            ppred = g.P(pred);
+                        }
+                    }
+                } else {
+                    closed = nt == first || (orient(pvk, pcur, pf) > 0.0 && orient(pvk, pf, pk) > 0.0);
+                }
+                if (!closed && rk == 0 && nrot == 0) x0 = nt;
+            }
+        }
+        if (closed) {
+            if (++rk == 3) return R_OK;
+            cwise = false;
+            const int f1 = rk == 2 ? 0 : rk + 1, f2 = rk == 0 ? 2 : rk - 1;
+            if (!S.add(sel3(T, f1), 1 << rk) || !S.add(sel3(T, f2), 1 << rk)) return R_CAP;
+            if (chain && pred != sel3(T, f2)) {
+                // the first apex of this ring is the one that preceded
+                // `first` in the ring just closed
+                if (!S.add(pred, 1 << rk)) return R_CAP;
+                cur = pred;
+                pcur = ppred;
+            } else {
+                cur = sel3(T, f2);
+                pcur = sel3(PT, f2);
+            }
+            nrot = 0;
+        } else {
+            if (!S.add(nt, 1 << rk)) return R_CAP;
+            cur = nt;
+            pcur = pk;
+            ++nrot;
+        }
     }
     return R_FAIL;
-}
-
-// Per-thread support list in LDS: sorted particle index | membership << 28.
-struct Support {
-    int32_t* u;  // [KMAX * WG], entry k of this thread at u[k * WG]
-    double* w;   // [KMAX * WG]
-    int n;
-    __device__ int find(int t) const {
-        for (int k = 0; k < n; ++k)
-            if ((u[k * WG] & 0x0fffffff) == t) return k;
-        return -1;
-    }
-    __device__ bool add(int t, int bit) {
-        for (int k = 0; k < n; ++k) {
-            const int e = u[k * WG];
-            if ((e & 0x0fffffff) == t) {
-                u[k * WG] = e | (bit << 28);
-                return true;
-            }
-        }
-        if (n >= KMAX) return false;
-        u[n * WG] = t | (bit << 28);
-        ++n;
-        return true;
-    }
-    __device__ int idx(int k) const { return u[k * WG] & 0x0fffffff; }
-    __device__ int bits(int k) const { return (u[k * WG] >> 28) & 7; }
-};
-
-// Ring of T[k] (rotation about T[k] starting with the known triangle T).
-__device__ int ring_into(Ctx& c, const int T[3], int k, Support& S) {
-    const int v = T[k], first = T[(k + 1) % 3], second = T[(k + 2) % 3];
-    const int bit = 1 << k;
-    const double2 pv = c.pos[v];
-    if (!S.add(first, bit) || !S.add(second, bit)) return R_CAP;
-    double cx, cy, rr;
-    int cur = second;
-    for (int step = 0; step < KMAX; ++step) {
-        const int nx = wrap(c, v, pv, cur, c.pos[cur], 1.0, cx, cy, rr);
-        if (nx < 0) {
-            if (!c.R.global) return R_MORE;
-            // open fan (hull vertex): the rest lies clockwise from `first`
-            cur = first;
-            for (int s2 = 0; s2 < KMAX; ++s2) {
-                const int pv2 = wrap(c, v, pv, cur, c.pos[cur], -1.0, cx, cy, rr);
-                if (pv2 < 0) return R_OK;
-                if (!S.add(pv2, bit)) return R_CAP;
-                cur = pv2;
-            }
-            return R_CAP;
-        }
-        if (!disk_inside(c.R, cx, cy, rr)) return R_MORE;
-        if (nx == first) return R_OK;
-        if (!S.add(nx, bit)) return R_CAP;
-        cur = nx;
-    }
-    return R_CAP;
 }
 
 // ---------------------------------------------------------------- algebra
@@ -341,38 +609,43 @@ __device__ __forceinline__ void monos(double x, double y, double p[6]) {
     p[5] = y * y;
 }
 
-// Accumulate the 15 power sums m_ab = sum x^a y^b (a + b <= 4).
+__device__ __forceinline__ double dot6(const double a[6], const double b[6]) {
+    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
+}
+
+// The 15 power sums m_ab = sum x^a y^b (a + b <= 4).
 struct Moments {
-    double m00, m10, m01, m20, m11, m02, m30, m21, m12, m03, m40, m31, m22, m13, m04;
+    double m[15];  // 00 10 01 20 11 02 30 21 12 03 40 31 22 13 04
     __device__ void zero() {
-        m00 = m10 = m01 = m20 = m11 = m02 = m30 = m21 = m12 = m03 = m40 = m31 = m22 = m13 = m04 = 0.0;
+#pragma unroll
+        for (int i = 0; i < 15; ++i) m[i] = 0.0;
     }
     __device__ void add(double x, double y) {
         const double x2 = x * x, y2 = y * y, xy = x * y;
-        m00 += 1.0;
-        m10 += x;
-        m01 += y;
-        m20 += x2;
-        m11 += xy;
-        m02 += y2;
-        m30 += x2 * x;
-        m21 += x2 * y;
-        m12 += x * y2;
-        m03 += y2 * y;
-        m40 += x2 * x2;
-        m31 += x2 * xy;
-        m22 += x2 * y2;
-        m13 += xy * y2;
-        m04 += y2 * y2;
+        m[0] += 1.0;
+        m[1] += x;
+        m[2] += y;
+        m[3] += x2;
+        m[4] += xy;
+        m[5] += y2;
+        m[6] += x2 * x;
+        m[7] += x2 * y;
+        m[8] += x * y2;
+        m[9] += y2 * y;
+        m[10] += x2 * x2;
+        m[11] += x2 * xy;
+        m[12] += x2 * y2;
+        m[13] += xy * y2;
+        m[14] += y2 * y2;
     }
     // Gram matrix of p = (1, x, y, x^2, xy, y^2), lower triangle.
     __device__ void gram(double G[6][6]) const {
-        G[0][0] = m00;
-        G[1][0] = m10; G[1][1] = m20;
-        G[2][0] = m01; G[2][1] = m11; G[2][2] = m02;
-        G[3][0] = m20; G[3][1] = m30; G[3][2] = m21; G[3][3] = m40;
-        G[4][0] = m11; G[4][1] = m21; G[4][2] = m12; G[4][3] = m31; G[4][4] = m22;
-        G[5][0] = m02; G[5][1] = m12; G[5][2] = m03; G[5][3] = m22; G[5][4] = m13; G[5][5] = m04;
+        G[0][0] = m[0];
+        G[1][0] = m[1]; G[1][1] = m[3];
+        G[2][0] = m[2]; G[2][1] = m[4]; G[2][2] = m[5];
+        G[3][0] = m[3]; G[3][1] = m[6]; G[3][2] = m[7]; G[3][3] = m[10];
+        G[4][0] = m[4]; G[4][1] = m[7]; G[4][2] = m[8]; G[4][3] = m[11]; G[4][4] = m[12];
+        G[5][0] = m[5]; G[5][1] = m[8]; G[5][2] = m[9]; G[5][3] = m[12]; G[5][4] = m[13]; G[5][5] = m[14];
     }
 };
 
@@ -421,8 +694,9 @@ __device__ void chol6_solve(const double L[6][6], const double b[6], double y[6]
 // Pseudo-inverse solve by cyclic Jacobi (rank-deficient systems only).
 // Eigenvalues below 1e-12 * lambda_max (singular values of the monomial
 // matrix below 1e-6 sigma_max) are dropped.
-__device__ void pinv6_solve(const double Gl[6][6], const double b[6], double y[6]) {
-    double A[6][6], V[6][6];
+__device__ void pinv6_solve(const Moments& mo, const double b[6], double y[6]) {
+    double Gl[6][6], A[6][6], V[6][6];
+    mo.gram(Gl);
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 6; ++j) {
             A[i][j] = i >= j ? Gl[i][j] : Gl[j][i];
@@ -474,43 +748,15 @@ __device__ void pinv6_solve(const double Gl[6][6], const double b[6], double y[6
     }
 }
 
-// Minimum-norm solution y of G y = b over the member set; `member(k)` says
-// whether support entry k is in the system, `coord(k, x, y)` its centred,
-// scaled coordinates.  Returns false when the pseudo-inverse was needed.
-template <class Member, class Coord>
-__device__ bool min_norm(const Moments& mo, const double b[6], int n, Member member, Coord coord, double y[6]) {
-    double L[6][6];
-    mo.gram(L);
-    double G[6][6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j) G[i][j] = L[i][j];
-    if (!chol6(L)) {
-        pinv6_solve(G, b, y);
-        return false;
-    }
-    chol6_solve(L, b, y);
-    // one refinement step with the residual formed from the monomials
-    double r[6] = {b[0], b[1], b[2], b[3], b[4], b[5]};
-    for (int k = 0; k < n; ++k) {
-        if (!member(k)) continue;
-        double x, yy;
-        coord(k, x, yy);
-        double p[6];
-        monos(x, yy, p);
-        const double a = p[0] * y[0] + p[1] * y[1] + p[2] * y[2] + p[3] * y[3] + p[4] * y[4] + p[5] * y[5];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) r[i] -= a * p[i];
-    }
-    double d[6];
-    chol6_solve(L, r, d);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) y[i] += d[i];
-    return true;
+// Sum over the four lanes of a quad; every lane gets the same bits
+// ((a+b)+(c+d) in all lanes, as FP addition is commutative).
+__device__ __forceinline__ double quad_sum(double v) {
+    v += __shfl_xor(v, 1, QL);
+    v += __shfl_xor(v, 2, QL);
+    return v;
 }
 
-// ------------------------------------------------------------- the kernel
+// ------------------------------------------------------------ kernel args
 struct KArgs {
     const double2* pos_s;
     const int32_t* perm;
@@ -520,269 +766,448 @@ struct KArgs {
     int64_t n_nodes;
     BuildOut out;
     int hw0, levels;
+    double Rf;    // fast-path candidate radius
+    int hwf;      // bins scanned around the node for the fast path
+    int tiles_x;  // fast kernel: node tiles of 8 x 8 per row
+    int32_t* slow;  // slow-path node list (capacity n_nodes)
     unsigned long long* diag;
 };
 
-__device__ void write_node(const KArgs& a, int64_t node, const Support& S, int n, uint32_t meta,
-                           const int32_t* perm) {
-    const int64_t nn = a.n_nodes;
-    for (int k = 0; k < n; ++k) {
-        a.out.idx[k * nn + node] = perm[S.idx(k)];
-        const double w = S.w[k * WG];
-        a.out.w64[k * nn + node] = w;
-        if (a.out.w32) a.out.w32[k * nn + node] = static_cast<float>(w);
-        a.out.mem[k * nn + node] = static_cast<uint8_t>(S.bits(k));
+// Interior weights of one node, computed by the four lanes of its quad.
+// The support entries come from `uget(k)` (sorted index | bits << 28); entry
+// k belongs to lane k % 4.
+template <class UGet>
+__device__ void quad_weights(const KArgs& a, int64_t node, double2 q, UGet uget, int n, const int T[3], int lane,
+                             uint32_t flags) {
+    int mt[MS];
+    int mb[MS];
+    double mx[MS], my[MS], mw[MS];
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int k = s * QL + lane;
+        mt[s] = -1;
+        mb[s] = 0;
+        mx[s] = my[s] = mw[s] = 0.0;
+        if (k < n) {
+            const uint32_t e = static_cast<uint32_t>(uget(k));
+            mt[s] = static_cast<int>(e & IDX_MASK);
+            mb[s] = static_cast<int>(e >> 28);
+            const double2 p = a.pos_s[mt[s]];
+            mx[s] = p.x;
+            my[s] = p.y;
+        }
     }
-    a.out.meta[node] = meta;
+    const double2 P[3] = {a.pos_s[T[0]], a.pos_s[T[1]], a.pos_s[T[2]]};
+    // barycentric coordinates of q in T (linear FE, eqs. C0, C1)
+    const double D = orient(P[0], P[1], P[2]);
+    const double phi[3] = {orient(q, P[1], P[2]) / D, orient(P[0], q, P[2]) / D, orient(P[0], P[1], q) / D};
+    int lt[3] = {-1, -1, -1};
+#pragma unroll
+    for (int s = 0; s < MS; ++s)
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            if (mt[s] == T[k]) {
+                mw[s] += phi[k];
+                lt[k] = s * QL + lane;
+            }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        lt[k] = max(lt[k], __shfl_xor(lt[k], 1, QL));
+        lt[k] = max(lt[k], __shfl_xor(lt[k], 2, QL));
+    }
+    for (int e = 0; e < 3; ++e) {
+        const int pa = e, pb = (e + 1) % 3;
+        const double2 rn = P[pa], rs = P[pb];
+        const double cxm = 0.5 * (rn.x + rs.x), cym = 0.5 * (rn.y + rs.y);
+        const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
+        const double is = 1.0 / sqrt(dxv * dxv + dyv * dyv);
+        const int mask = (1 << pa) | (1 << pb);
+        Moments mo;
+        mo.zero();
+#pragma unroll
+        for (int s = 0; s < MS; ++s)
+            if (mb[s] & mask) mo.add((mx[s] - cxm) * is, (my[s] - cym) * is);
+#pragma unroll
+        for (int i = 0; i < 15; ++i) mo.m[i] = quad_sum(mo.m[i]);
+        const double dx = dxv * is, dy = dyv * is;
+        const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
+        double y[6];
+        double L[6][6];
+        mo.gram(L);
+        if (chol6(L)) {
+            chol6_solve(L, b, y);
+            // one refinement step with the residual formed from the monomials
+            double r[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < MS; ++s) {
+                if (!(mb[s] & mask)) continue;
+                double p[6];
+                monos((mx[s] - cxm) * is, (my[s] - cym) * is, p);
+                const double A = dot6(p, y);
+#pragma unroll
+                for (int i = 0; i < 6; ++i) r[i] += A * p[i];
+            }
+#pragma unroll
+            for (int i = 0; i < 6; ++i) r[i] = b[i] - quad_sum(r[i]);
+            double d[6];
+            chol6_solve(L, r, d);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) y[i] += d[i];
+        } else {
+            // rank-deficient: pseudo-inverse (moments recomputed, so they are
+            // not kept live across the Cholesky on the common path)
+            Moments m2;
+            m2.zero();
+#pragma unroll
+            for (int s = 0; s < MS; ++s)
+                if (mb[s] & mask) m2.add((mx[s] - cxm) * is, (my[s] - cym) * is);
+#pragma unroll
+            for (int i = 0; i < 15; ++i) m2.m[i] = quad_sum(m2.m[i]);
+            pinv6_solve(m2, b, y);
+            flags |= MF_RANKDEF;
+            if (lane == 0) atomicAdd(&a.diag[D_RANKDEF], 1ull);
+        }
+        const double coef = 2.0 * phi[pa] * phi[pb];
+#pragma unroll
+        for (int s = 0; s < MS; ++s) {
+            if (!(mb[s] & mask)) continue;
+            double p[6];
+            monos((mx[s] - cxm) * is, (my[s] - cym) * is, p);
+            mw[s] += coef * dot6(p, y);
+        }
+    }
+    const int64_t nn = a.n_nodes;
+#pragma unroll
+    for (int s = 0; s < MS; ++s) {
+        const int k = s * QL + lane;
+        if (k >= n) continue;
+        a.out.idx[k * nn + node] = a.perm[mt[s]];
+        a.out.w64[k * nn + node] = mw[s];
+        if (a.out.w32) a.out.w32[k * nn + node] = static_cast<float>(mw[s]);
+        a.out.mem[k * nn + node] = static_cast<uint8_t>(mb[s]);
+    }
+    if (lane == 0) a.out.meta[node] = meta_pack(NT_INTERIOR, n, lt[0], lt[1], lt[2], flags);
 }
 
-__global__ void __launch_bounds__(WG) k_build(KArgs a) {
-    __shared__ int32_t su[KMAX * WG];
-    __shared__ double sw[KMAX * WG];
-    const int tid = threadIdx.x;
-    const int64_t node = static_cast<int64_t>(blockIdx.x) * WG + tid;
-    if (node >= a.n_nodes) return;
-
-    const int stride = a.m.nx + 1;
-    const int i = static_cast<int>(node % stride);
-    const int j = static_cast<int>(node / stride);
-    const double2 q = make_double2(add_rn(a.m.x0, mul_rn(static_cast<double>(i), a.m.H)),
-                                   add_rn(a.m.y0, mul_rn(static_cast<double>(j), a.m.H)));
+// ------------------------------------------------------------ fast kernel
+// Leaves the support of each node it certifies in the ELL arrays (sorted
+// index, membership bits) as a PENDING row for k_weights; the rest goes to
+// the slow list.
+__global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
+    __shared__ int32_t su[QPB * KMAX];
+    __shared__ int32_t svis[QPB * KMAX];
+    const int lane = threadIdx.x & (QL - 1);
+    const int qi = threadIdx.x / QL;
+    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
+    const bool valid = i <= a.m.nx && j <= a.m.ny;
+    const int64_t node = static_cast<int64_t>(j) * (a.m.nx + 1) + i;
+    const int64_t nn = a.n_nodes;
     const bool ring = i == 0 || j == 0 || i == a.m.nx || j == a.m.ny;
-    const int cbx = i * a.g.kb, cby = j * a.g.kb;
-
-    Ctx c;
-    c.pos = a.pos_s;
-    c.perm = a.perm;
-    c.start = a.start;
-    c.g = a.g;
-    c.neardeg = 0;
-    Support S;
-    S.u = su + tid;
-    S.w = sw + tid;
-    S.n = 0;
-
-    uint32_t type = ring ? NT_RING : NT_INTERIOR;
-    uint32_t flags = 0;
-    int T[3] = {0, 0, 0};
-    int st = R_FAIL;
-    const int big = max(a.g.nbx, a.g.nby) + 1;
-
-    if (!ring) {
-        for (int level = 0;; ++level) {
-            const int hw = level < a.levels ? (a.hw0 << level) : big;
-            c.R = make_region(a.g, cbx, cby, hw);
-            S.n = 0;
-            st = locate(c, q, T);
-            if (st == R_OK) st = ring_into(c, T, 0, S);
-            if (st == R_OK) st = ring_into(c, T, 1, S);
-            if (st == R_OK) st = ring_into(c, T, 2, S);
-            if (st != R_MORE) break;
-            if (c.R.global) {
-                st = R_FAIL;
-                break;
-            }
-            flags |= MF_ESCALATED;
-        }
-        if (c.R.global) flags |= MF_GLOBAL;
-        if (st == R_OUTSIDE) type = NT_OUTSIDE;
-        else if (st == R_CAP) {
-            type = NT_FAILED;
-            atomicAdd(&a.diag[D_CAP], 1ull);
-        } else if (st != R_OK) type = NT_FAILED;
-    }
-
-    // every vertex of T lies in the others' rings; guard the LDS indexing anyway
-    if (type == NT_INTERIOR && (S.find(T[0]) < 0 || S.find(T[1]) < 0 || S.find(T[2]) < 0)) type = NT_FAILED;
-    if (type == NT_INTERIOR) {
-        const int n = S.n;
-        const int lt[3] = {S.find(T[0]), S.find(T[1]), S.find(T[2])};
-        const double2 P0 = c.pos[T[0]], P1 = c.pos[T[1]], P2 = c.pos[T[2]];
-        // barycentric coordinates of q in T (linear FE, eqs. C0, C1)
-        const double D = orient(P0, P1, P2);
-        const double phi[3] = {orient(q, P1, P2) / D, orient(P0, q, P2) / D, orient(P0, P1, q) / D};
-        for (int k = 0; k < n; ++k) S.w[k * WG] = 0.0;
-        for (int k = 0; k < 3; ++k) S.w[lt[k] * WG] += phi[k];
-        for (int e = 0; e < 3; ++e) {
-            const int pa = e, pb = (e + 1) % 3;
-            const double2 rn = c.pos[T[pa]], rs = c.pos[T[pb]];
-            const double cxm = 0.5 * (rn.x + rs.x), cym = 0.5 * (rn.y + rs.y);
-            const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
-            const double is = 1.0 / sqrt(dxv * dxv + dyv * dyv);
-            const int mask = (1 << pa) | (1 << pb);
-            auto member = [&](int k) { return (S.bits(k) & mask) != 0; };
-            auto coord = [&](int k, double& x, double& y) {
-                const double2 p = c.pos[S.idx(k)];
-                x = (p.x - cxm) * is;
-                y = (p.y - cym) * is;
-            };
-            Moments mo;
-            mo.zero();
-            for (int k = 0; k < n; ++k) {
-                if (!member(k)) continue;
-                double x, y;
-                coord(k, x, y);
-                mo.add(x, y);
-            }
-            const double dx = dxv * is, dy = dyv * is;
-            const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
-            double y[6];
-            if (!min_norm(mo, b, n, member, coord, y)) {
-                flags |= MF_RANKDEF;
-                atomicAdd(&a.diag[D_RANKDEF], 1ull);
-            }
-            const double coef = 2.0 * phi[pa] * phi[pb];
-            for (int k = 0; k < n; ++k) {
-                if (!member(k)) continue;
-                double x, yy;
-                coord(k, x, yy);
-                double p[6];
-                monos(x, yy, p);
-                const double A = p[0] * y[0] + p[1] * y[1] + p[2] * y[2] + p[3] * y[3] + p[4] * y[4] + p[5] * y[5];
-                S.w[k * WG] += coef * A;
-            }
-        }
-        if (c.neardeg) flags |= MF_NEARDEG;
-        write_node(a, node, S, n, meta_pack(NT_INTERIOR, n, lt[0], lt[1], lt[2], flags), a.perm);
-    } else if (type == NT_RING || type == NT_OUTSIDE) {
-        // closure: K nearest particles (ties by user id), minimum-norm
-        // quadratic moment weights.
-        int nn[KNN];
-        double dd[KNN];
-        int uu[KNN];
-        int kk = 0;
-        for (int level = 0;; ++level) {
-            const int hw = level < a.levels ? (a.hw0 << level) : big;
-            c.R = make_region(a.g, cbx, cby, hw);
+    bool done = false;
+    int neardeg = 0;
+    int nsup = 0;
+    if (valid && !ring) {
+        QuadSource g;
+        g.pos = a.pos_s;
+        g.perm = a.perm;
+        g.q = node_pos(a.m, i, j);
+        g.Rf = a.Rf;
+        g.n = 0;
+        g.lane = lane;
+        // gather the particles within Rf, round-robin over the four lanes
+        const double R2 = a.Rf * a.Rf;
+        const int cbx = i * a.g.kb, cby = j * a.g.kb;
+        const int bx0 = max(cbx - a.hwf, 0), bx1 = min(cbx + a.hwf, a.g.nbx);
+        const int by0 = max(cby - a.hwf, 0), by1 = min(cby + a.hwf, a.g.nby);
+        int ovf = 0;
+        int flat = 0;
+        for (int by = by0; by < by1; ++by) {
+            const int row = by * a.g.nbx;
+            const int s = a.start[row + bx0], e = a.start[row + bx1];
+            for (int t = s + ((lane - flat) & (QL - 1)); t < e; t += QL) {
+                const double2 p = a.pos_s[t];
+                const double dx = p.x - g.q.x, dy = p.y - g.q.y;
+                if (dx * dx + dy * dy > R2) continue;
+                if (g.n >= NS) {
+                    ovf = 1;
+                    continue;
+                }
 #pragma unroll
-            for (int s = 0; s < KNN; ++s) {
-                nn[s] = -1;
-                dd[s] = INFINITY;
-                uu[s] = INT_MAX;
-            }
-            kk = 0;
-            for (int by = c.R.by0; by < c.R.by1; ++by) {
-                const int row = by * c.g.nbx;
-                const int s0 = c.start[row + c.R.bx0], e0 = c.start[row + c.R.bx1];
-                for (int t = s0; t < e0; ++t) {
-                    const double2 p = c.pos[t];
-                    const double dx = p.x - q.x, dy = p.y - q.y;
-                    const double d2 = dx * dx + dy * dy;
-                    if (d2 > dd[KNN - 1]) continue;
-                    const int u = c.perm[t];
-                    if (d2 == dd[KNN - 1] && u >= uu[KNN - 1]) continue;
-                    ++kk;
-                    nn[KNN - 1] = t;
-                    dd[KNN - 1] = d2;
-                    uu[KNN - 1] = u;
-#pragma unroll
-                    for (int s = KNN - 1; s > 0; --s) {
-                        const bool less = dd[s] < dd[s - 1] || (dd[s] == dd[s - 1] && uu[s] < uu[s - 1]);
-                        if (less) {
-                            const int tn = nn[s];
-                            nn[s] = nn[s - 1];
-                            nn[s - 1] = tn;
-                            const double td = dd[s];
-                            dd[s] = dd[s - 1];
-                            dd[s - 1] = td;
-                            const int tu = uu[s];
-                            uu[s] = uu[s - 1];
-                            uu[s - 1] = tu;
-                        }
+                for (int k = 0; k < NS; ++k)
+                    if (k == g.n) {
+                        g.cx_[k] = p.x;
+                        g.cy_[k] = p.y;
+                        g.ct_[k] = t;
                     }
+                ++g.n;
+            }
+            flat += e - s;
+        }
+        ovf |= __shfl_xor(ovf, 1, QL);
+        ovf |= __shfl_xor(ovf, 2, QL);
+        int st = R_MORE;
+        int T[3] = {0, 0, 0};
+        Support<QL> S;
+        S.u = su + qi * KMAX;
+        S.n = 0;
+        S.lane = lane;
+        if (!ovf) st = delaunay_node(g, g.q, T, S, svis + qi * KMAX);
+        if (st == R_OK) {
+            const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
+            if (lt0 >= 0 && lt1 >= 0 && lt2 >= 0) {
+                for (int k = lane; k < S.n; k += QL) {
+                    const uint32_t e = static_cast<uint32_t>(S.u[k]);
+                    a.out.idx[k * nn + node] = static_cast<int32_t>(e & IDX_MASK);
+                    a.out.mem[k * nn + node] = static_cast<uint8_t>(e >> 28);
+                }
+                if (lane == 0)
+                    a.out.meta[node] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, neardeg ? MF_NEARDEG : 0u);
+                done = true;
+                nsup = S.n;
+            }
+        }
+    }
+    if (valid && !done && lane == 0) {
+        const int slot = static_cast<int>(atomicAdd(&a.diag[D_SLOWCNT], 1ull));
+        a.slow[slot] = static_cast<int32_t>(node);
+    }
+    // diagnostics: per wave, one count per quad (lane 0)
+    const unsigned long long fast = __ballot(done && lane == 0);
+    int nd = (lane == 0 && done) ? neardeg : 0;
+    int sup = done ? nsup : 0;
+    for (int off = 32; off > 0; off >>= 1) {
+        nd += __shfl_xor(nd, off);
+        sup = max(sup, __shfl_xor(sup, off));
+    }
+    if (threadIdx.x % WAVE == 0) {
+        if (fast) atomicAdd(&a.diag[D_INTERIOR], static_cast<unsigned long long>(__popcll(fast)));
+        if (nd) atomicAdd(&a.diag[D_NEARDEG], static_cast<unsigned long long>(nd));
+        if (sup) atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(sup));
+    }
+}
+
+// ------------------------------------------------------------ slow kernel
+// One wave per listed node: certified Delaunay search over square bin
+// regions that double in half-width up to every particle; closure nodes get
+// their weights here, interior nodes leave their support (sorted indices,
+// membership bits) in the ELL arrays for k_weights.
+__global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
+    constexpr int WPB = SWG / WAVE;
+    __shared__ int32_t su[WPB * KMAX];
+    __shared__ int32_t svis[WPB * KMAX];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int count = static_cast<int>(a.diag[D_SLOWCNT]);
+    const int big = max(a.g.nbx, a.g.nby) + 1;
+    const int64_t nn = a.n_nodes;
+    for (int li = blockIdx.x * WPB + wv; li < count; li += gridDim.x * WPB) {
+        const int64_t node = a.slow[li];
+        const int i = static_cast<int>(node % (a.m.nx + 1));
+        const int j = static_cast<int>(node / (a.m.nx + 1));
+        const double2 q = node_pos(a.m, i, j);
+        const bool ring = i == 0 || j == 0 || i == a.m.nx || j == a.m.ny;
+        const int cbx = i * a.g.kb, cby = j * a.g.kb;
+        WaveSource c;
+        c.pos = a.pos_s;
+        c.perm = a.perm;
+        c.start = a.start;
+        c.g = a.g;
+        c.neardeg = 0;
+        c.lane = lane;
+        Support<WAVE> S;
+        S.u = su + wv * KMAX;
+        S.n = 0;
+        S.lane = lane;
+        uint32_t type = ring ? NT_RING : NT_INTERIOR;
+        uint32_t flags = ring ? 0u : MF_ESCALATED;
+        int T[3] = {0, 0, 0};
+        int st = R_FAIL;
+        if (!ring) {
+            for (int level = 0;; ++level) {
+                const int hw = level < a.levels ? (a.hw0 << level) : big;
+                c.R = make_region(a.g, cbx, cby, hw);
+                S.n = 0;
+                st = delaunay_node(c, q, T, S, svis + wv * KMAX);
+                if (st != R_MORE) break;
+                if (c.R.global) {
+                    st = R_FAIL;
+                    break;
                 }
             }
-            if (c.R.global) break;
-            if (kk >= KNN && disk_inside(c.R, q.x, q.y, sqrt(dd[KNN - 1]))) break;
-            flags |= MF_ESCALATED;
+            if (c.R.global) flags |= MF_GLOBAL;
+            if (st == R_OUTSIDE) type = NT_OUTSIDE;
+            else if (st == R_CAP) {
+                type = NT_FAILED;
+                if (lane == 0) atomicAdd(&a.diag[D_CAP], 1ull);
+            } else if (st != R_OK) type = NT_FAILED;
         }
-        if (c.R.global) flags |= MF_GLOBAL;
-        const int n = kk < KNN ? kk : KNN;
-        S.n = 0;
-        for (int s = 0; s < n; ++s) S.u[s * WG] = nn[s];
-        S.n = n;
-        if (n == 0) {
-            type = NT_FAILED;
-        } else {
-            // centroid and RMS radius: any centre and scale give the same
-            // weights; these keep the moment matrix well conditioned.
-            double mx = 0.0, my = 0.0;
-            for (int s = 0; s < n; ++s) {
-                const double2 p = c.pos[nn[s]];
-                mx += p.x;
-                my += p.y;
+        if (type == NT_INTERIOR) {
+            const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
+            if (lt0 < 0 || lt1 < 0 || lt2 < 0) {
+                type = NT_FAILED;
+            } else {
+                // pending: support in the ELL arrays, weights by k_weights
+                for (int k = lane; k < S.n; k += WAVE) {
+                    const uint32_t e = static_cast<uint32_t>(S.u[k]);
+                    a.out.idx[k * nn + node] = static_cast<int32_t>(e & IDX_MASK);
+                    a.out.mem[k * nn + node] = static_cast<uint8_t>(e >> 28);
+                }
+                if (c.neardeg) flags |= MF_NEARDEG;
+                if (lane == 0) {
+                    a.out.meta[node] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
+                    atomicAdd(&a.diag[D_INTERIOR], 1ull);
+                    atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(S.n));
+                }
             }
-            mx /= n;
-            my /= n;
-            double r2 = 0.0;
-            for (int s = 0; s < n; ++s) {
-                const double2 p = c.pos[nn[s]];
-                r2 += (p.x - mx) * (p.x - mx) + (p.y - my) * (p.y - my);
+        }
+        if (type == NT_RING || type == NT_OUTSIDE) {
+            // closure: the K nearest particles (ties by user id), picked one
+            // per round as the smallest (d^2, user id) above the previous pick;
+            // lane r keeps the r-th.
+            int mine = -1;
+            int kk = 0;
+            double dlast = 0.0;
+            for (int level = 0;; ++level) {
+                const int hw = level < a.levels ? (a.hw0 << level) : big;
+                c.R = make_region(a.g, cbx, cby, hw);
+                mine = -1;
+                kk = 0;
+                double pd = -1.0;
+                int pu = -1;
+                for (int r = 0; r < KNN; ++r) {
+                    double bd = INFINITY;
+                    int bu = INT_MAX, bt = -1;
+                    c.scan([&](int t, double2 p) {
+                        const double dx = p.x - q.x, dy = p.y - q.y;
+                        const double d2 = dx * dx + dy * dy;
+                        if (d2 < pd || d2 > bd) return;
+                        const int u = c.perm[t];
+                        if (d2 == pd && u <= pu) return;
+                        if (d2 < bd || u < bu) {
+                            bd = d2;
+                            bu = u;
+                            bt = t;
+                        }
+                    });
+#pragma unroll
+                    for (int m = 1; m < WAVE; m <<= 1) {
+                        const double od = __shfl_xor(bd, m);
+                        const int ou = __shfl_xor(bu, m), ot = __shfl_xor(bt, m);
+                        if (ot >= 0 && (bt < 0 || od < bd || (od == bd && ou < bu))) {
+                            bd = od;
+                            bu = ou;
+                            bt = ot;
+                        }
+                    }
+                    if (bt < 0) break;
+                    if (lane == r) mine = bt;
+                    pd = bd;
+                    pu = bu;
+                    ++kk;
+                }
+                dlast = pd;
+                if (c.R.global) break;
+                if (kk >= KNN && c.certify(q.x, q.y, sqrt(dlast))) break;
+                flags |= MF_ESCALATED;
             }
-            const double isc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
-            auto member = [&](int) { return true; };
-            auto coord = [&](int k, double& x, double& y) {
-                const double2 p = c.pos[S.idx(k)];
-                x = (p.x - mx) * isc;
-                y = (p.y - my) * isc;
-            };
-            Moments mo;
-            mo.zero();
-            for (int k = 0; k < n; ++k) {
-                double x, y;
-                coord(k, x, y);
-                mo.add(x, y);
+            if (c.R.global) flags |= MF_GLOBAL;
+            const int n = kk;
+            if (n == 0) {
+                type = NT_FAILED;
+            } else {
+                const bool have = lane < n;
+                const double2 p = have ? c.pos[mine] : make_double2(0.0, 0.0);
+                // centroid and RMS radius: any centre and scale give the same
+                // weights; these keep the moment matrix well conditioned.
+                const double mx = group_sum<WAVE>(have ? p.x : 0.0) / n;
+                const double my = group_sum<WAVE>(have ? p.y : 0.0) / n;
+                const double dxm = p.x - mx, dym = p.y - my;
+                const double r2 = group_sum<WAVE>(have ? dxm * dxm + dym * dym : 0.0);
+                const double isc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
+                const double xs = dxm * isc, ys = dym * isc;
+                Moments mo;
+                mo.zero();
+                if (have) mo.add(xs, ys);
+#pragma unroll
+                for (int k = 0; k < 15; ++k) mo.m[k] = group_sum<WAVE>(mo.m[k]);
+                double b[6];
+                monos((q.x - mx) * isc, (q.y - my) * isc, b);
+                double y[6];
+                double L[6][6];
+                mo.gram(L);
+                double pp[6];
+                monos(xs, ys, pp);
+                if (chol6(L)) {
+                    chol6_solve(L, b, y);
+                    const double A = have ? dot6(pp, y) : 0.0;
+                    double r[6];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) r[k] = b[k] - group_sum<WAVE>(A * pp[k]);
+                    double d[6];
+                    chol6_solve(L, r, d);
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) y[k] += d[k];
+                } else {
+                    pinv6_solve(mo, b, y);
+                    flags |= MF_RANKDEF;
+                    if (lane == 0) atomicAdd(&a.diag[D_RANKDEF], 1ull);
+                }
+                if (have) {
+                    const double w = dot6(pp, y);
+                    a.out.idx[lane * nn + node] = c.perm[mine];
+                    a.out.w64[lane * nn + node] = w;
+                    if (a.out.w32) a.out.w32[lane * nn + node] = static_cast<float>(w);
+                    a.out.mem[lane * nn + node] = 0;
+                }
+                if (c.neardeg) flags |= MF_NEARDEG;
+                if (lane == 0) {
+                    a.out.meta[node] = meta_pack(type, n, 0, 0, 0, flags);
+                    atomicAdd(&a.diag[D_CLOSURE], 1ull);
+                    atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(n));
+                    if (type == NT_OUTSIDE) atomicAdd(&a.diag[D_OUTSIDE], 1ull);
+                }
             }
-            double b[6];
-            monos((q.x - mx) * isc, (q.y - my) * isc, b);
-            double y[6];
-            if (!min_norm(mo, b, n, member, coord, y)) {
-                flags |= MF_RANKDEF;
-                atomicAdd(&a.diag[D_RANKDEF], 1ull);
+        }
+        if (lane == 0) {
+            if (type == NT_FAILED) {
+                a.out.meta[node] = meta_pack(NT_FAILED, 0, 0, 0, 0, flags);
+                atomicAdd(&a.diag[D_FAILED], 1ull);
             }
-            for (int k = 0; k < n; ++k) {
-                double x, yy;
-                coord(k, x, yy);
-                double p[6];
-                monos(x, yy, p);
-                S.w[k * WG] = p[0] * y[0] + p[1] * y[1] + p[2] * y[2] + p[3] * y[3] + p[4] * y[4] + p[5] * y[5];
-            }
-            if (c.neardeg) flags |= MF_NEARDEG;
-            write_node(a, node, S, n, meta_pack(type, n, 0, 0, 0, flags), a.perm);
+            if (flags & MF_ESCALATED) atomicAdd(&a.diag[D_ESCALATED], 1ull);
+            if (flags & MF_GLOBAL) atomicAdd(&a.diag[D_GLOBAL], 1ull);
+            if (c.neardeg) atomicAdd(&a.diag[D_NEARDEG], static_cast<unsigned long long>(c.neardeg));
         }
     }
-    if (type == NT_FAILED) {
-        a.out.meta[node] = meta_pack(NT_FAILED, 0, 0, 0, 0, flags);
-        atomicAdd(&a.diag[D_FAILED], 1ull);
-    }
+}
 
-    // diagnostics: one atomic per wave for the common counters
-    const unsigned long long interior = __ballot(type == NT_INTERIOR);
-    const unsigned long long clos = __ballot(type == NT_RING || type == NT_OUTSIDE);
-    const unsigned long long outside = __ballot(type == NT_OUTSIDE);
-    const unsigned long long esc = __ballot((flags & MF_ESCALATED) != 0);
-    const unsigned long long glob = __ballot((flags & MF_GLOBAL) != 0);
-    int sup = (type == NT_FAILED) ? 0 : S.n;
-    for (int off = 32; off > 0; off >>= 1) sup = max(sup, __shfl_xor(sup, off));
-    int nd = c.neardeg;
-    for (int off = 32; off > 0; off >>= 1) nd += __shfl_xor(nd, off);
-    const int lane = __lane_id();
-    const unsigned long long active = __ballot(true);
-    if (lane == __ffsll(static_cast<long long>(active)) - 1) {
-        if (interior) atomicAdd(&a.diag[D_INTERIOR], static_cast<unsigned long long>(__popcll(interior)));
-        if (clos) atomicAdd(&a.diag[D_CLOSURE], static_cast<unsigned long long>(__popcll(clos)));
-        if (outside) atomicAdd(&a.diag[D_OUTSIDE], static_cast<unsigned long long>(__popcll(outside)));
-        if (esc) atomicAdd(&a.diag[D_ESCALATED], static_cast<unsigned long long>(__popcll(esc)));
-        if (glob) atomicAdd(&a.diag[D_GLOBAL], static_cast<unsigned long long>(__popcll(glob)));
-        if (nd) atomicAdd(&a.diag[D_NEARDEG], static_cast<unsigned long long>(nd));
-        atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(sup));
-    }
+// Weights of every PENDING node (from either path), one quad per node,
+// nodes in the same 8 x 8 tiles as the fast kernel.
+__global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
+    const int lane = threadIdx.x & (QL - 1);
+    const int qi = threadIdx.x / QL;
+    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
+    if (i > a.m.nx || j > a.m.ny) return;  // quad-uniform
+    const int64_t nn = a.n_nodes;
+    const int64_t node = static_cast<int64_t>(j) * (a.m.nx + 1) + i;
+    const uint32_t meta = a.out.meta[node];
+    if (meta_type(meta) != NT_PENDING) return;  // quad-uniform
+    const int n = static_cast<int>(meta_cnt(meta));
+    int T[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) T[k] = a.out.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + node];
+    auto uget = [&](int k) {
+        return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + node]) |
+                                    (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28));
+    };
+    quad_weights(a, node, node_pos(a.m, i, j), uget, n, T, lane, meta_flags(meta));
 }
 
 }  // namespace
 
 int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N, const BuildOut& out,
-                  const BuildParams& prm, unsigned long long* diag, hipStream_t st) {
+                  const BuildParams& prm, int32_t* slow, unsigned long long* diag, hipStream_t st) {
     PhaseTimer _timer(PH_BUILD, st);
     (void)N;
     KArgs a;
@@ -795,9 +1220,28 @@ int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N,
     a.out = out;
     a.hw0 = prm.hw0;
     a.levels = prm.levels;
+    a.Rf = prm.Rf;
+    a.hwf = prm.hwf;
+    a.tiles_x = (m.nx + 1 + 7) / 8;
+    const int tiles_y = (m.ny + 1 + 7) / 8;
+    a.slow = slow;
     a.diag = diag;
-    const int blocks = static_cast<int>((a.n_nodes + WG - 1) / WG);
-    k_build<<<blocks, WG, 0, st>>>(a);
+    {
+        PhaseTimer t1(PH_BUILD_FAST, st);
+        k_build_fast<<<a.tiles_x * tiles_y, QWG, 0, st>>>(a);
+    }
+    {
+        // one wave per slow node: the boundary ring plus the few escalated
+        // nodes; the grid is sized for that and loops over the actual list
+        PhaseTimer t2(PH_BUILD_SLOW, st);
+        const int64_t expect = 2 * (static_cast<int64_t>(m.nx) + m.ny) + a.n_nodes / 256 + 64;
+        const int gs = static_cast<int>(std::min<int64_t>((expect + SWG / WAVE - 1) / (SWG / WAVE), 8192));
+        k_slow_geom<<<gs, SWG, 0, st>>>(a);
+    }
+    {
+        PhaseTimer t3(PH_WEIGHTS, st);
+        k_weights<<<a.tiles_x * tiles_y, QWG, 0, st>>>(a);
+    }
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }

@@ -16,7 +16,8 @@ thread_local std::string g_err = "no error";
 // Process-wide tuning knobs (set with p2m_set_option).
 struct Tuning {
     double bin_scale = 1.0;       // bin width ~ bin_scale * h
-    double region_h = 4.0;        // first search half-width, in units of h
+    double region_h = 4.0;        // slow path: first search half-width, in units of h
+    double fast_radius = 2.8;     // fast path: candidate radius, in units of h
     int levels = 3;               // doublings before the global scan
 } g_tune;
 }  // namespace
@@ -53,6 +54,7 @@ struct p2m_weights {
     BinBuffers bins{};
     uint32_t* meta = nullptr;
     int32_t* idx = nullptr;
+    int32_t* slow = nullptr;
     double* w64 = nullptr;
     float* w32 = nullptr;
     uint8_t* mem = nullptr;
@@ -79,7 +81,7 @@ int grow(T** p, int64_t count, int64_t have) {
 
 void release(p2m_weights* w) {
     void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.count, w->bins.start, w->bins.tsum, w->bins.pos_s,
-                    w->bins.perm, w->meta, w->idx, w->w64, w->w32, w->mem, w->diag};
+                    w->bins.perm, w->meta, w->idx, w->slow, w->w64, w->w32, w->mem, w->diag};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -174,6 +176,8 @@ int p2m_set_option(const char* name, double value) {
         g_tune.bin_scale = value;
     } else if (!std::strcmp(name, "region_h") && value >= 1.0 && value <= 64.0) {
         g_tune.region_h = value;
+    } else if (!std::strcmp(name, "fast_radius") && value >= 1.5 && value <= 8.0) {
+        g_tune.fast_radius = value;
     } else if (!std::strcmp(name, "levels") && value >= 0.0 && value <= 8.0) {
         g_tune.levels = static_cast<int>(value);
     } else {
@@ -257,6 +261,7 @@ int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t
     if (!rc) rc = grow(&w->bins.tsum, ntiles + 1, w->capTiles + 1);
     if (!rc) w->capTiles = std::max(w->capTiles, ntiles);
     if (!rc) rc = grow(&w->meta, n_nodes, w->capNodes);
+    if (!rc) rc = grow(&w->slow, n_nodes, w->capNodes);
     if (!rc) rc = grow(&w->idx, n_nodes * KMAX, w->capNodes * KMAX);
     if (!rc) rc = grow(&w->w64, n_nodes * KMAX, w->capNodes * KMAX);
     if (!rc) rc = grow(&w->mem, n_nodes * KMAX, w->capNodes * KMAX);
@@ -286,7 +291,9 @@ int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t
     BuildParams prm;
     prm.hw0 = std::max(2, static_cast<int>(std::ceil(g_tune.region_h * h / g.bw)));
     prm.levels = g_tune.levels;
-    return build_weights(w->bins, w->mesh, g, N, out, prm, w->diag, st);
+    prm.Rf = g_tune.fast_radius * h;
+    prm.hwf = std::max(1, static_cast<int>(std::ceil(prm.Rf / g.bw)));
+    return build_weights(w->bins, w->mesh, g, N, out, prm, w->slow, w->diag, st);
 }
 
 int p2m_weights_diag(const p2m_weights* w, p2m_diag* d, void* stream) {

@@ -36,6 +36,7 @@ enum DiagIdx : int {
     D_FAILED,
     D_SUPMAX,
     D_DUP,
+    D_SLOWCNT,  // length of the slow-path node list
     D_COUNT
 };
 
@@ -43,16 +44,20 @@ constexpr int KMAX = P2M_MAX_SUPPORT;  // ELL width
 constexpr int KNN = P2M_CLOSURE_K;
 
 // Per-node metadata word of the ELL weights.
-enum NodeType : uint32_t { NT_INTERIOR = 0, NT_RING = 1, NT_OUTSIDE = 2, NT_FAILED = 3 };
+// NT_PENDING: interior node whose support is known but whose weights are
+// still to be computed (transient inside one build).
+enum NodeType : uint32_t { NT_INTERIOR = 0, NT_RING = 1, NT_OUTSIDE = 2, NT_FAILED = 3, NT_PENDING = 4 };
+// bits 0-2 type, 3-8 count, 9-13 / 14-18 / 19-23 ELL slots of the triangle's
+// vertices, 24- flags
 __host__ __device__ inline uint32_t meta_pack(uint32_t type, uint32_t cnt, uint32_t ta, uint32_t tb,
                                               uint32_t tc, uint32_t flags) {
-    return type | (cnt << 2) | (ta << 8) | (tb << 13) | (tc << 18) | (flags << 23);
+    return type | (cnt << 3) | (ta << 9) | (tb << 14) | (tc << 19) | (flags << 24);
 }
-__host__ __device__ inline uint32_t meta_type(uint32_t m) { return m & 3u; }
-__host__ __device__ inline uint32_t meta_cnt(uint32_t m) { return (m >> 2) & 63u; }
-__host__ __device__ inline uint32_t meta_t(uint32_t m, int k) { return (m >> (8 + 5 * k)) & 31u; }
+__host__ __device__ inline uint32_t meta_type(uint32_t m) { return m & 7u; }
+__host__ __device__ inline uint32_t meta_cnt(uint32_t m) { return (m >> 3) & 63u; }
+__host__ __device__ inline uint32_t meta_t(uint32_t m, int k) { return (m >> (9 + 5 * k)) & 31u; }
 constexpr uint32_t MF_NEARDEG = 1u, MF_RANKDEF = 2u, MF_ESCALATED = 4u, MF_GLOBAL = 8u;
-__host__ __device__ inline uint32_t meta_flags(uint32_t m) { return m >> 23; }
+__host__ __device__ inline uint32_t meta_flags(uint32_t m) { return m >> 24; }
 
 // Membership bits stored per ELL entry: bit k set when the particle belongs to
 // the Delaunay ring of the k-th vertex of the node's triangle.

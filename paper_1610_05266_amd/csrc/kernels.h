@@ -6,7 +6,10 @@
 namespace p2m {
 
 // ---- optional event timing of kernel groups (profile.hip) ----
-enum Phase : int { PH_BIN = 0, PH_BUILD, PH_PROJECT, PH_M2P, PH_M2P_BWD, PH_PROJECT_BWD, PH_BUILD_BWD, PH_COUNT };
+enum Phase : int {
+    PH_BIN = 0, PH_BUILD, PH_PROJECT, PH_M2P, PH_M2P_BWD, PH_PROJECT_BWD, PH_BUILD_BWD,
+    PH_BUILD_FAST, PH_BUILD_SLOW, PH_WEIGHTS, PH_COUNT
+};
 class PhaseTimer {
   public:
     PhaseTimer(int phase, hipStream_t st);
@@ -49,11 +52,13 @@ struct BuildOut {
     uint8_t* mem;    // [KMAX][n_nodes]
 };
 struct BuildParams {
-    int hw0;         // half-width (bins) of the first search region
-    int levels;      // region doublings before the global scan
+    int hw0;         // slow path: half-width (bins) of the first search region
+    int levels;      // slow path: region doublings before the global scan
+    double Rf;       // fast path: candidate radius around the node
+    int hwf;         // fast path: half-width (bins) of the square scanned for it
 };
 int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N, const BuildOut& out,
-                  const BuildParams& prm, unsigned long long* diag, hipStream_t st);
+                  const BuildParams& prm, int32_t* slow, unsigned long long* diag, hipStream_t st);
 
 // ---- projection and interpolation (project.hip, m2p.hip) ----
 int project(const WeightsView& w, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st);
