@@ -1,0 +1,152 @@
+"""GPU parity of the adjoints (derivatives of eqs. p2m and m2p) against the
+oracle: transposes by dot-product tests, position gradients against the
+oracle's complex-step derivatives of its own forward construction, and the
+full M2P -> P2M -> loss gradient through torch.autograd."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import Mesh as OMesh, P2MOracle, m2p as o_m2p, m2p_grad_pos as o_m2p_grad_pos
+from oracle.adjoint import p2m_grad_pos as o_p2m_grad_pos, roundtrip as o_roundtrip
+from paper_1610_05266_amd import autograd, ops
+from paper_1610_05266_amd._lib import P2M_WEIGHTS_F32
+from tests._util import assert_close
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def _g(a, dt=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dt)
+
+
+@pytest.fixture(scope="module")
+def small():
+    c = wl.small_cloud(12, 2, 0.25, seed=41, channels=("u", "v", "q"))
+    om = OMesh.from_spec(c.mesh)
+    return c, om, P2MOracle(c.pos, om, c.h)
+
+
+def test_m2p_adjoint_dot_product_and_grad_pos(small):
+    c, om, _ = small
+    rng = np.random.default_rng(1)
+    f = rng.normal(size=(om.n_nodes, 3))
+    gb = rng.normal(size=(c.N, 3))
+    pos = _g(c.pos)
+    a = ops.m2p_interpolate(c.mesh, _g(f), pos).cpu().numpy()
+    gp = torch.zeros_like(pos)
+    gm, gp = ops.m2p_interpolate_backward(c.mesh, _g(f), pos, _g(gb), want_mesh=True, grad_pos=gp)
+    lhs = float((a * gb).sum())
+    rhs = float((f * gm.cpu().numpy()).sum())
+    assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+    assert_close(gp.cpu().numpy(), o_m2p_grad_pos(om, f, c.pos, gb), 1e-12, "M2P grad pos")
+
+
+def test_p2m_adjoint_dot_product_and_grad_vals(small):
+    c, om, orc = small
+    rng = np.random.default_rng(2)
+    vals = rng.normal(size=(c.N, 3))
+    gmesh = rng.normal(size=(om.n_nodes, 3))
+    w = ops.p2m_build_weights(c.mesh, c.h, _g(c.pos))
+    out = ops.p2m_project(w, _g(vals)).cpu().numpy()
+    gv, gw = ops.p2m_project_backward(w, _g(gmesh), _g(vals), want_vals=True, want_w=True)
+    lhs = float((out * gmesh).sum())
+    rhs = float((vals * gv.cpu().numpy()).sum())
+    assert abs(lhs - rhs) <= 1e-13 * max(1.0, abs(lhs))
+    W, _ = orc.matrix()
+    assert_close(gv.cpu().numpy(), W.T @ gmesh, 1e-12, "P2M grad vals")
+    # grad_w rows: sum_c gmesh[i,c] vals[idx,c] over each node's support
+    idx, _, cnt, _ = w.export()
+    gwn = gw.cpu().numpy()
+    for node in range(0, om.n_nodes, 7):
+        k = int(cnt[node])
+        ref = vals[idx[:k, node].numpy()] @ gmesh[node]
+        assert np.abs(gwn[:k, node] - ref).max() <= 1e-13
+        assert np.all(gwn[k:, node] == 0.0)
+
+
+def test_p2m_grad_pos_matches_oracle_complex_step(small):
+    c, om, orc = small
+    rng = np.random.default_rng(3)
+    gmesh = rng.normal(size=(om.n_nodes, 3))
+    pos = _g(c.pos)
+    w = ops.p2m_build_weights(c.mesh, c.h, pos)
+    _, gw = ops.p2m_project_backward(w, _g(gmesh), _g(c.vals), want_vals=False, want_w=True)
+    gp = ops.p2m_build_weights_backward(w, pos, gw).cpu().numpy()
+    ref = o_p2m_grad_pos(orc, c.vals, gmesh)
+    assert_close(gp, ref, 1e-10, "P2M grad pos")
+
+
+def test_roundtrip_autograd_matches_oracle(small):
+    c, om, orc = small
+    nodes = om.nodes()
+    f = np.stack([wl.tg_u(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03),
+                  wl.tg_v(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03)], 1)
+    gt = np.stack([wl.tg_u(nodes[:, 0], nodes[:, 1]), wl.tg_v(nodes[:, 0], nodes[:, 1])], 1)
+    ref = o_roundtrip(orc, f, gt)
+    pos = _g(c.pos).requires_grad_(True)
+    fm = _g(f).requires_grad_(True)
+    a = autograd.m2p(fm, pos, ops.Mesh.of(c.mesh))
+    a.retain_grad()
+    out = autograd.p2m(pos, a, ops.Mesh.of(c.mesh), c.h)
+    loss = 0.5 * ((out - _g(gt)) ** 2).sum()
+    loss.backward()
+    assert abs(loss.item() - ref["loss"]) <= 1e-12 * ref["loss"]
+    assert_close(a.grad.cpu().numpy(), ref["grad_vals"], 1e-10, "dL/d particle values")
+    assert_close(fm.grad.cpu().numpy(), ref["grad_mesh"], 1e-10, "dL/d mesh input")
+    assert_close(pos.grad.cpu().numpy(), ref["grad_pos"], 1e-10, "dL/d positions")
+
+
+def test_roundtrip_mixed_precision_gradients(small):
+    c, om, orc = small
+    nodes = om.nodes()
+    f = np.stack([wl.tg_u(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03),
+                  wl.tg_v(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03)], 1)
+    gt = np.stack([wl.tg_u(nodes[:, 0], nodes[:, 1]), wl.tg_v(nodes[:, 0], nodes[:, 1])], 1)
+    ref = o_roundtrip(orc, f, gt)
+    pos = _g(c.pos).requires_grad_(True)
+    fm = _g(f, torch.float32).requires_grad_(True)
+    a = autograd.m2p(fm, pos, ops.Mesh.of(c.mesh))
+    out = autograd.p2m(pos, a, ops.Mesh.of(c.mesh), c.h)
+    loss = 0.5 * ((out.double() - _g(gt)) ** 2).sum()
+    loss.backward()
+    assert_close(fm.grad.double().cpu().numpy(), ref["grad_mesh"], 1e-5, "mixed dL/d mesh input")
+    assert_close(pos.grad.cpu().numpy(), ref["grad_pos"], 1e-5, "mixed dL/d positions")
+
+
+def test_grad_pos_central_differences_on_gpu():
+    """Central differences (step 1e-6) of the GPU forward itself, skipping
+    samples whose step changes a triangle, a ring or a nearest set."""
+    c = wl.small_cloud(10, 2, 0.25, seed=77, channels=("u", "q"))
+    mesh = ops.Mesh.of(c.mesh)
+    rng = np.random.default_rng(5)
+    gmesh = rng.normal(size=(mesh.n_nodes, 2))
+    vals = _g(c.vals)
+
+    def forward(p):
+        w = ops.p2m_build_weights(mesh, c.h, _g(p))
+        out = ops.p2m_project(w, vals).cpu().numpy()
+        idx, _, cnt, tri = w.export()
+        return float((out * gmesh).sum()), (idx.numpy(), cnt.numpy(), tri.numpy())
+
+    pos = _g(c.pos)
+    w = ops.p2m_build_weights(mesh, c.h, pos)
+    _, gw = ops.p2m_project_backward(w, _g(gmesh), vals, want_vals=False, want_w=True)
+    gp = ops.p2m_build_weights_backward(w, pos, gw).cpu().numpy()
+    _, s0 = forward(c.pos)
+    d = 1e-6
+    used = 0
+    for mu in rng.choice(c.N, 40, replace=False):
+        for k in range(2):
+            pp, pm = c.pos.copy(), c.pos.copy()
+            pp[mu, k] += d
+            pm[mu, k] -= d
+            lp, sp = forward(pp)
+            lm, sm = forward(pm)
+            if any(not np.array_equal(a, b) for a, b in zip(sp + sm, s0 + s0)):
+                continue
+            fd = (lp - lm) / (2 * d)
+            assert abs(fd - gp[mu, k]) <= 1e-6 * max(1.0, abs(fd))
+            used += 1
+    assert used >= 50
