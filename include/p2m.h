@@ -207,6 +207,8 @@ void p2m_weights_destroy(p2m_weights* w);
  *   "bin_scale"  bin width ~ bin_scale * h        (0.25 .. 8,  default 1)
  *   "fast_radius" candidate radius / h of the
  *                register-resident first pass     (1.5 .. 8,   default 2.8)
+ *   "closure_radius" candidate radius / h of the
+ *                first pass for boundary-ring nodes (1.5 .. 8,   default 4)
  *   "region_h"   first search half-width / h of
  *                the fallback pass                (1 .. 64,    default 4)
  *   "levels"     region doublings before a scan

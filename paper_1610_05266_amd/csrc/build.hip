@@ -205,8 +205,12 @@ __device__ Region make_region(const Grid& g, int cbx, int cby, int hw) {
 }
 
 // A whole wave per node, scanning a square region of bins (sides on the
-// mesh boundary are walls: no particle lies beyond them); the candidates are
-// dealt round-robin over the 64 lanes.
+// mesh boundary are walls: no particle lies beyond them).  The region's
+// particles are staged once per region in LDS when they fit (STAGE entries
+// per wave), else streamed from the sorted arrays on every scan; either way
+// they are dealt round-robin over the 64 lanes.
+constexpr int STAGE = 512;
+
 struct WaveSource {
     const double2* __restrict__ pos;
     const int32_t* __restrict__ perm;
@@ -215,6 +219,9 @@ struct WaveSource {
     Region R;
     int neardeg;
     int lane;
+    double2* lp;   // LDS stage of this wave [STAGE]
+    int32_t* lt;   // sorted indices of the staged particles
+    int ln;        // staged count, -1 when streaming
 
     __device__ bool global() const { return R.global; }
     __device__ double2 P(int t) const { return pos[t]; }
@@ -222,8 +229,35 @@ struct WaveSource {
         r *= 1.0 + 1e-9;
         return cx - r >= R.xlo && cx + r <= R.xhi && cy - r >= R.ylo && cy + r <= R.yhi;
     }
+    __device__ void set_region(const Region& reg) {
+        R = reg;
+        int total = 0;
+        for (int by = R.by0; by < R.by1; ++by) {
+            const int row = by * g.nbx;
+            total += start[row + R.bx1] - start[row + R.bx0];
+        }
+        ln = total <= STAGE ? total : -1;
+        if (ln < 0) return;
+        int flat = 0;
+        for (int by = R.by0; by < R.by1; ++by) {
+            const int row = by * g.nbx;
+            const int s = start[row + R.bx0], e = start[row + R.bx1];
+            for (int t = s + lane; t < e; t += WAVE) {
+                lp[flat + t - s] = pos[t];
+                lt[flat + t - s] = t;
+            }
+            flat += e - s;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     template <class F>
     __device__ void scan(F&& f) const {
+        if (ln >= 0) {
+            for (int k = lane; k < ln; k += WAVE) f(lt[k], lp[k]);
+            return;
+        }
         int flat = 0;
         for (int by = R.by0; by < R.by1; ++by) {
             const int row = by * g.nbx;
@@ -766,12 +800,16 @@ struct KArgs {
     int64_t n_nodes;
     BuildOut out;
     int hw0, levels;
-    double Rf;    // fast-path candidate radius
-    int hwf;      // bins scanned around the node for the fast path
-    int tiles_x;  // fast kernel: node tiles of 8 x 8 per row
+    double Rf;      // fast path: candidate radius of interior nodes
+    int hwf;        // bins scanned around the node for it
+    double Rc;      // fast path: candidate radius of boundary-ring nodes
+    int hwc;
+    int tiles_x;    // node tiles of 8 x 8 per row
     int32_t* slow;  // slow-path node list (capacity n_nodes)
     unsigned long long* diag;
 };
+
+__device__ __forceinline__ uint32_t pending_type(uint32_t t) { return t == NT_OUTSIDE ? NT_PEND_OUT : NT_PEND_RING; }
 
 // Interior weights of one node, computed by the four lanes of its quad.
 // The support entries come from `uget(k)` (sorted index | bits << 28); entry
@@ -889,10 +927,96 @@ __device__ void quad_weights(const KArgs& a, int64_t node, double2 q, UGet uget,
     if (lane == 0) a.out.meta[node] = meta_pack(NT_INTERIOR, n, lt[0], lt[1], lt[2], flags);
 }
 
+// Closure weights of one node from its nearest particles (sorted indices in
+// the ELL row): minimum-norm solution of the quadratic moment conditions
+// sum_mu w_mu p(r_mu) = p(q), in coordinates centred at the particles'
+// centroid and scaled by their RMS radius (the weights do not depend on the
+// centre and scale; these keep the system well conditioned).
+constexpr int MC = (KNN + QL - 1) / QL;
+
+__device__ void quad_closure(const KArgs& a, int64_t node, double2 q, int n, int lane, uint32_t type,
+                             uint32_t flags) {
+    const int64_t nn = a.n_nodes;
+    int mt[MC];
+    double mx[MC], my[MC];
+    double sx = 0.0, sy = 0.0;
+#pragma unroll
+    for (int s = 0; s < MC; ++s) {
+        const int k = s * QL + lane;
+        mt[s] = -1;
+        mx[s] = my[s] = 0.0;
+        if (k < n) {
+            mt[s] = a.out.idx[k * nn + node];
+            const double2 p = a.pos_s[mt[s]];
+            mx[s] = p.x;
+            my[s] = p.y;
+            sx += p.x;
+            sy += p.y;
+        }
+    }
+    const double cx = quad_sum(sx) / n, cy = quad_sum(sy) / n;
+    double r2 = 0.0;
+#pragma unroll
+    for (int s = 0; s < MC; ++s)
+        if (mt[s] >= 0) r2 += (mx[s] - cx) * (mx[s] - cx) + (my[s] - cy) * (my[s] - cy);
+    r2 = quad_sum(r2);
+    const double isc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
+    Moments mo;
+    mo.zero();
+#pragma unroll
+    for (int s = 0; s < MC; ++s)
+        if (mt[s] >= 0) mo.add((mx[s] - cx) * isc, (my[s] - cy) * isc);
+#pragma unroll
+    for (int i = 0; i < 15; ++i) mo.m[i] = quad_sum(mo.m[i]);
+    double b[6];
+    monos((q.x - cx) * isc, (q.y - cy) * isc, b);
+    double y[6];
+    double L[6][6];
+    mo.gram(L);
+    if (chol6(L)) {
+        chol6_solve(L, b, y);
+        double r[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < MC; ++s) {
+            if (mt[s] < 0) continue;
+            double p[6];
+            monos((mx[s] - cx) * isc, (my[s] - cy) * isc, p);
+            const double A = dot6(p, y);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) r[i] += A * p[i];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) r[i] = b[i] - quad_sum(r[i]);
+        double d[6];
+        chol6_solve(L, r, d);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) y[i] += d[i];
+    } else {
+        pinv6_solve(mo, b, y);
+        flags |= MF_RANKDEF;
+        if (lane == 0) atomicAdd(&a.diag[D_RANKDEF], 1ull);
+    }
+#pragma unroll
+    for (int s = 0; s < MC; ++s) {
+        const int k = s * QL + lane;
+        if (mt[s] < 0) continue;
+        double p[6];
+        monos((mx[s] - cx) * isc, (my[s] - cy) * isc, p);
+        const double w = dot6(p, y);
+        a.out.idx[k * nn + node] = a.perm[mt[s]];
+        a.out.w64[k * nn + node] = w;
+        if (a.out.w32) a.out.w32[k * nn + node] = static_cast<float>(w);
+        a.out.mem[k * nn + node] = 0;
+    }
+    if (lane == 0) a.out.meta[node] = meta_pack(type, n, 0, 0, 0, flags);
+}
+
 // ------------------------------------------------------------ fast kernel
-// Leaves the support of each node it certifies in the ELL arrays (sorted
-// index, membership bits) as a PENDING row for k_weights; the rest goes to
-// the slow list.
+// One quad per node.  Interior nodes: certified Delaunay work in registers;
+// the support goes to the ELL row as a PENDING row (sorted indices and ring
+// bits) for k_weights.  Boundary-ring nodes: the KNN nearest particles,
+// picked one per round (smallest squared distance, ties by user id), as a
+// pending closure row.  Anything not certified goes to the slow list.
 __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     __shared__ int32_t su[QPB * KMAX];
     __shared__ int32_t svis[QPB * KMAX];
@@ -905,21 +1029,20 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     const int64_t nn = a.n_nodes;
     const bool ring = i == 0 || j == 0 || i == a.m.nx || j == a.m.ny;
     bool done = false;
-    int neardeg = 0;
-    int nsup = 0;
-    if (valid && !ring) {
+    if (valid) {
         QuadSource g;
         g.pos = a.pos_s;
         g.perm = a.perm;
         g.q = node_pos(a.m, i, j);
-        g.Rf = a.Rf;
+        g.Rf = ring ? a.Rc : a.Rf;
         g.n = 0;
         g.lane = lane;
-        // gather the particles within Rf, round-robin over the four lanes
-        const double R2 = a.Rf * a.Rf;
+        // gather the particles within the radius, round-robin over the lanes
+        const double R2 = g.Rf * g.Rf;
+        const int hw = ring ? a.hwc : a.hwf;
         const int cbx = i * a.g.kb, cby = j * a.g.kb;
-        const int bx0 = max(cbx - a.hwf, 0), bx1 = min(cbx + a.hwf, a.g.nbx);
-        const int by0 = max(cby - a.hwf, 0), by1 = min(cby + a.hwf, a.g.nby);
+        const int bx0 = max(cbx - hw, 0), bx1 = min(cbx + hw, a.g.nbx);
+        const int by0 = max(cby - hw, 0), by1 = min(cby + hw, a.g.nby);
         int ovf = 0;
         int flat = 0;
         for (int by = by0; by < by1; ++by) {
@@ -946,25 +1069,67 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
         }
         ovf |= __shfl_xor(ovf, 1, QL);
         ovf |= __shfl_xor(ovf, 2, QL);
-        int st = R_MORE;
-        int T[3] = {0, 0, 0};
-        Support<QL> S;
-        S.u = su + qi * KMAX;
-        S.n = 0;
-        S.lane = lane;
-        if (!ovf) st = delaunay_node(g, g.q, T, S, svis + qi * KMAX);
-        if (st == R_OK) {
-            const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
-            if (lt0 >= 0 && lt1 >= 0 && lt2 >= 0) {
-                for (int k = lane; k < S.n; k += QL) {
-                    const uint32_t e = static_cast<uint32_t>(S.u[k]);
-                    a.out.idx[k * nn + node] = static_cast<int32_t>(e & IDX_MASK);
-                    a.out.mem[k * nn + node] = static_cast<uint8_t>(e >> 28);
+        if (!ovf && !ring) {
+            int T[3] = {0, 0, 0};
+            Support<QL> S;
+            S.u = su + qi * KMAX;
+            S.n = 0;
+            S.lane = lane;
+            const int st = delaunay_node(g, g.q, T, S, svis + qi * KMAX);
+            if (st == R_OK) {
+                const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
+                if (lt0 >= 0 && lt1 >= 0 && lt2 >= 0) {
+                    for (int k = lane; k < S.n; k += QL) {
+                        const uint32_t e = static_cast<uint32_t>(S.u[k]);
+                        a.out.idx[k * nn + node] = static_cast<int32_t>(e & IDX_MASK);
+                        a.out.mem[k * nn + node] = static_cast<uint8_t>(e >> 28);
+                    }
+                    if (lane == 0) a.out.meta[node] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, 0u);
+                    done = true;
                 }
-                if (lane == 0)
-                    a.out.meta[node] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, neardeg ? MF_NEARDEG : 0u);
+            }
+        } else if (!ovf) {
+            double pd = -1.0;
+            int pt = -1, pu = -1, found = 0;
+            for (int r = 0; r < KNN; ++r) {
+                double bd = INFINITY;
+                int bt = -1;
+#pragma unroll
+                for (int s = 0; s < NS; ++s) {
+                    if (s >= g.n) continue;
+                    const int t = g.ct_[s];
+                    const double dx = g.cx_[s] - g.q.x, dy = g.cy_[s] - g.q.y;
+                    const double d2 = dx * dx + dy * dy;
+                    const bool after = d2 > pd || (d2 == pd && t != pt && a.perm[t] > pu);
+                    const bool better = d2 < bd || (d2 == bd && bt >= 0 && a.perm[t] < a.perm[bt]);
+                    if (after && better) {
+                        bd = d2;
+                        bt = t;
+                    }
+                }
+#pragma unroll
+                for (int m = 1; m < QL; m <<= 1) {
+                    const double od = __shfl_xor(bd, m, QL);
+                    const int ot = __shfl_xor(bt, m, QL);
+                    if (ot >= 0 && ot != bt && (bt < 0 || od < bd || (od == bd && a.perm[ot] < a.perm[bt]))) {
+                        bd = od;
+                        bt = ot;
+                    }
+                }
+                if (bt < 0) break;
+                if (lane == 0) {
+                    a.out.idx[r * nn + node] = bt;
+                    a.out.mem[r * nn + node] = 0;
+                }
+                pd = bd;
+                pt = bt;
+                pu = a.perm[bt];
+                ++found;
+            }
+            // certified when the K-th distance is inside the gathered disk
+            if (found == KNN && sqrt(pd) <= g.Rf * (1.0 - 1e-12)) {
+                if (lane == 0) a.out.meta[node] = meta_pack(NT_PEND_RING, KNN, 0, 0, 0, 0u);
                 done = true;
-                nsup = S.n;
             }
         }
     }
@@ -972,30 +1137,19 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
         const int slot = static_cast<int>(atomicAdd(&a.diag[D_SLOWCNT], 1ull));
         a.slow[slot] = static_cast<int32_t>(node);
     }
-    // diagnostics: per wave, one count per quad (lane 0)
-    const unsigned long long fast = __ballot(done && lane == 0);
-    int nd = (lane == 0 && done) ? neardeg : 0;
-    int sup = done ? nsup : 0;
-    for (int off = 32; off > 0; off >>= 1) {
-        nd += __shfl_xor(nd, off);
-        sup = max(sup, __shfl_xor(sup, off));
-    }
-    if (threadIdx.x % WAVE == 0) {
-        if (fast) atomicAdd(&a.diag[D_INTERIOR], static_cast<unsigned long long>(__popcll(fast)));
-        if (nd) atomicAdd(&a.diag[D_NEARDEG], static_cast<unsigned long long>(nd));
-        if (sup) atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(sup));
-    }
 }
 
 // ------------------------------------------------------------ slow kernel
-// One wave per listed node: certified Delaunay search over square bin
-// regions that double in half-width up to every particle; closure nodes get
-// their weights here, interior nodes leave their support (sorted indices,
-// membership bits) in the ELL arrays for k_weights.
+// One wave per listed node: certified Delaunay search (exact predicates)
+// over square bin regions that double in half-width up to every particle;
+// interior nodes leave their support in the ELL row, closure nodes (ring, or
+// outside the hull) their nearest particles; k_weights does the rest.
 __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     constexpr int WPB = SWG / WAVE;
     __shared__ int32_t su[WPB * KMAX];
     __shared__ int32_t svis[WPB * KMAX];
+    __shared__ double2 slp[WPB * STAGE];
+    __shared__ int32_t slt[WPB * STAGE];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int count = static_cast<int>(a.diag[D_SLOWCNT]);
@@ -1015,18 +1169,20 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         c.g = a.g;
         c.neardeg = 0;
         c.lane = lane;
+        c.lp = slp + wv * STAGE;
+        c.lt = slt + wv * STAGE;
         Support<WAVE> S;
         S.u = su + wv * KMAX;
         S.n = 0;
         S.lane = lane;
         uint32_t type = ring ? NT_RING : NT_INTERIOR;
-        uint32_t flags = ring ? 0u : MF_ESCALATED;
+        uint32_t flags = MF_ESCALATED;
         int T[3] = {0, 0, 0};
         int st = R_FAIL;
         if (!ring) {
             for (int level = 0;; ++level) {
                 const int hw = level < a.levels ? (a.hw0 << level) : big;
-                c.R = make_region(a.g, cbx, cby, hw);
+                c.set_region(make_region(a.g, cbx, cby, hw));
                 S.n = 0;
                 st = delaunay_node(c, q, T, S, svis + wv * KMAX);
                 if (st != R_MORE) break;
@@ -1042,36 +1198,27 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
                 if (lane == 0) atomicAdd(&a.diag[D_CAP], 1ull);
             } else if (st != R_OK) type = NT_FAILED;
         }
+        if (c.neardeg) flags |= MF_NEARDEG;
         if (type == NT_INTERIOR) {
             const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
             if (lt0 < 0 || lt1 < 0 || lt2 < 0) {
                 type = NT_FAILED;
             } else {
-                // pending: support in the ELL arrays, weights by k_weights
                 for (int k = lane; k < S.n; k += WAVE) {
                     const uint32_t e = static_cast<uint32_t>(S.u[k]);
                     a.out.idx[k * nn + node] = static_cast<int32_t>(e & IDX_MASK);
                     a.out.mem[k * nn + node] = static_cast<uint8_t>(e >> 28);
                 }
-                if (c.neardeg) flags |= MF_NEARDEG;
-                if (lane == 0) {
-                    a.out.meta[node] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
-                    atomicAdd(&a.diag[D_INTERIOR], 1ull);
-                    atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(S.n));
-                }
+                if (lane == 0) a.out.meta[node] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
             }
         }
         if (type == NT_RING || type == NT_OUTSIDE) {
             // closure: the K nearest particles (ties by user id), picked one
-            // per round as the smallest (d^2, user id) above the previous pick;
-            // lane r keeps the r-th.
-            int mine = -1;
+            // per round as the smallest (d^2, user id) above the previous pick
             int kk = 0;
-            double dlast = 0.0;
             for (int level = 0;; ++level) {
                 const int hw = level < a.levels ? (a.hw0 << level) : big;
-                c.R = make_region(a.g, cbx, cby, hw);
-                mine = -1;
+                c.set_region(make_region(a.g, cbx, cby, hw));
                 kk = 0;
                 double pd = -1.0;
                 int pu = -1;
@@ -1101,72 +1248,22 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
                         }
                     }
                     if (bt < 0) break;
-                    if (lane == r) mine = bt;
+                    if (lane == 0) {
+                        a.out.idx[r * nn + node] = bt;
+                        a.out.mem[r * nn + node] = 0;
+                    }
                     pd = bd;
                     pu = bu;
                     ++kk;
                 }
-                dlast = pd;
                 if (c.R.global) break;
-                if (kk >= KNN && c.certify(q.x, q.y, sqrt(dlast))) break;
-                flags |= MF_ESCALATED;
+                if (kk >= KNN && c.certify(q.x, q.y, sqrt(pd))) break;
             }
             if (c.R.global) flags |= MF_GLOBAL;
-            const int n = kk;
-            if (n == 0) {
+            if (kk == 0) {
                 type = NT_FAILED;
-            } else {
-                const bool have = lane < n;
-                const double2 p = have ? c.pos[mine] : make_double2(0.0, 0.0);
-                // centroid and RMS radius: any centre and scale give the same
-                // weights; these keep the moment matrix well conditioned.
-                const double mx = group_sum<WAVE>(have ? p.x : 0.0) / n;
-                const double my = group_sum<WAVE>(have ? p.y : 0.0) / n;
-                const double dxm = p.x - mx, dym = p.y - my;
-                const double r2 = group_sum<WAVE>(have ? dxm * dxm + dym * dym : 0.0);
-                const double isc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
-                const double xs = dxm * isc, ys = dym * isc;
-                Moments mo;
-                mo.zero();
-                if (have) mo.add(xs, ys);
-#pragma unroll
-                for (int k = 0; k < 15; ++k) mo.m[k] = group_sum<WAVE>(mo.m[k]);
-                double b[6];
-                monos((q.x - mx) * isc, (q.y - my) * isc, b);
-                double y[6];
-                double L[6][6];
-                mo.gram(L);
-                double pp[6];
-                monos(xs, ys, pp);
-                if (chol6(L)) {
-                    chol6_solve(L, b, y);
-                    const double A = have ? dot6(pp, y) : 0.0;
-                    double r[6];
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) r[k] = b[k] - group_sum<WAVE>(A * pp[k]);
-                    double d[6];
-                    chol6_solve(L, r, d);
-#pragma unroll
-                    for (int k = 0; k < 6; ++k) y[k] += d[k];
-                } else {
-                    pinv6_solve(mo, b, y);
-                    flags |= MF_RANKDEF;
-                    if (lane == 0) atomicAdd(&a.diag[D_RANKDEF], 1ull);
-                }
-                if (have) {
-                    const double w = dot6(pp, y);
-                    a.out.idx[lane * nn + node] = c.perm[mine];
-                    a.out.w64[lane * nn + node] = w;
-                    if (a.out.w32) a.out.w32[lane * nn + node] = static_cast<float>(w);
-                    a.out.mem[lane * nn + node] = 0;
-                }
-                if (c.neardeg) flags |= MF_NEARDEG;
-                if (lane == 0) {
-                    a.out.meta[node] = meta_pack(type, n, 0, 0, 0, flags);
-                    atomicAdd(&a.diag[D_CLOSURE], 1ull);
-                    atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(n));
-                    if (type == NT_OUTSIDE) atomicAdd(&a.diag[D_OUTSIDE], 1ull);
-                }
+            } else if (lane == 0) {
+                a.out.meta[node] = meta_pack(pending_type(type), kk, 0, 0, 0, flags);
             }
         }
         if (lane == 0) {
@@ -1174,34 +1271,52 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
                 a.out.meta[node] = meta_pack(NT_FAILED, 0, 0, 0, 0, flags);
                 atomicAdd(&a.diag[D_FAILED], 1ull);
             }
-            if (flags & MF_ESCALATED) atomicAdd(&a.diag[D_ESCALATED], 1ull);
+            if (!ring) atomicAdd(&a.diag[D_ESCALATED], 1ull);
             if (flags & MF_GLOBAL) atomicAdd(&a.diag[D_GLOBAL], 1ull);
             if (c.neardeg) atomicAdd(&a.diag[D_NEARDEG], static_cast<unsigned long long>(c.neardeg));
         }
     }
 }
 
-// Weights of every PENDING node (from either path), one quad per node,
-// nodes in the same 8 x 8 tiles as the fast kernel.
+// Weights of every pending row (interior or closure, from either path), one
+// quad per node, nodes in the same 8 x 8 tiles as the fast kernel.
 __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
-    if (i > a.m.nx || j > a.m.ny) return;  // quad-uniform
+    const bool valid = i <= a.m.nx && j <= a.m.ny;
     const int64_t nn = a.n_nodes;
     const int64_t node = static_cast<int64_t>(j) * (a.m.nx + 1) + i;
-    const uint32_t meta = a.out.meta[node];
-    if (meta_type(meta) != NT_PENDING) return;  // quad-uniform
+    const uint32_t meta = valid ? a.out.meta[node] : 0u;
+    const uint32_t type = valid ? meta_type(meta) : NT_FAILED;
     const int n = static_cast<int>(meta_cnt(meta));
-    int T[3];
+    if (type == NT_PENDING) {
+        int T[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) T[k] = a.out.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + node];
-    auto uget = [&](int k) {
-        return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + node]) |
-                                    (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28));
-    };
-    quad_weights(a, node, node_pos(a.m, i, j), uget, n, T, lane, meta_flags(meta));
+        for (int k = 0; k < 3; ++k) T[k] = a.out.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + node];
+        auto uget = [&](int k) {
+            return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + node]) |
+                                        (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28));
+        };
+        quad_weights(a, node, node_pos(a.m, i, j), uget, n, T, lane, meta_flags(meta));
+    } else if (type == NT_PEND_RING || type == NT_PEND_OUT) {
+        quad_closure(a, node, node_pos(a.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
+                     meta_flags(meta));
+    }
+    // diagnostics: one count per quad (lane 0), one atomic per wave
+    const bool q0 = lane == 0;
+    const unsigned long long inter = __ballot(q0 && type == NT_PENDING);
+    const unsigned long long clos = __ballot(q0 && (type == NT_PEND_RING || type == NT_PEND_OUT));
+    const unsigned long long outs = __ballot(q0 && type == NT_PEND_OUT);
+    int sup = (type == NT_PENDING || type == NT_PEND_RING || type == NT_PEND_OUT) ? n : 0;
+    for (int off = 32; off > 0; off >>= 1) sup = max(sup, __shfl_xor(sup, off));
+    if (threadIdx.x % WAVE == 0) {
+        if (inter) atomicAdd(&a.diag[D_INTERIOR], static_cast<unsigned long long>(__popcll(inter)));
+        if (clos) atomicAdd(&a.diag[D_CLOSURE], static_cast<unsigned long long>(__popcll(clos)));
+        if (outs) atomicAdd(&a.diag[D_OUTSIDE], static_cast<unsigned long long>(__popcll(outs)));
+        if (sup) atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(sup));
+    }
 }
 
 }  // namespace
@@ -1222,6 +1337,8 @@ int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N,
     a.levels = prm.levels;
     a.Rf = prm.Rf;
     a.hwf = prm.hwf;
+    a.Rc = prm.Rc;
+    a.hwc = prm.hwc;
     a.tiles_x = (m.nx + 1 + 7) / 8;
     const int tiles_y = (m.ny + 1 + 7) / 8;
     a.slow = slow;
@@ -1231,11 +1348,11 @@ int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N,
         k_build_fast<<<a.tiles_x * tiles_y, QWG, 0, st>>>(a);
     }
     {
-        // one wave per slow node: the boundary ring plus the few escalated
-        // nodes; the grid is sized for that and loops over the actual list
+        // one wave per slow node (few: escalated, undecided, corners); the
+        // grid loops over the actual list
         PhaseTimer t2(PH_BUILD_SLOW, st);
-        const int64_t expect = 2 * (static_cast<int64_t>(m.nx) + m.ny) + a.n_nodes / 256 + 64;
-        const int gs = static_cast<int>(std::min<int64_t>((expect + SWG / WAVE - 1) / (SWG / WAVE), 8192));
+        const int64_t expect = a.n_nodes / 256 + 64;
+        const int gs = static_cast<int>(std::min<int64_t>((expect + SWG / WAVE - 1) / (SWG / WAVE), 4096));
         k_slow_geom<<<gs, SWG, 0, st>>>(a);
     }
     {

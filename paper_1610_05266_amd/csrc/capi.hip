@@ -18,6 +18,7 @@ struct Tuning {
     double bin_scale = 1.0;       // bin width ~ bin_scale * h
     double region_h = 4.0;        // slow path: first search half-width, in units of h
     double fast_radius = 2.8;     // fast path: candidate radius, in units of h
+    double closure_radius = 4.0;  // fast path, boundary ring: candidate radius / h
     int levels = 3;               // doublings before the global scan
 } g_tune;
 }  // namespace
@@ -178,6 +179,8 @@ int p2m_set_option(const char* name, double value) {
         g_tune.region_h = value;
     } else if (!std::strcmp(name, "fast_radius") && value >= 1.5 && value <= 8.0) {
         g_tune.fast_radius = value;
+    } else if (!std::strcmp(name, "closure_radius") && value >= 1.5 && value <= 8.0) {
+        g_tune.closure_radius = value;
     } else if (!std::strcmp(name, "levels") && value >= 0.0 && value <= 8.0) {
         g_tune.levels = static_cast<int>(value);
     } else {
@@ -293,6 +296,8 @@ int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t
     prm.levels = g_tune.levels;
     prm.Rf = g_tune.fast_radius * h;
     prm.hwf = std::max(1, static_cast<int>(std::ceil(prm.Rf / g.bw)));
+    prm.Rc = g_tune.closure_radius * h;
+    prm.hwc = std::max(1, static_cast<int>(std::ceil(prm.Rc / g.bw)));
     return build_weights(w->bins, w->mesh, g, N, out, prm, w->slow, w->diag, st);
 }
 

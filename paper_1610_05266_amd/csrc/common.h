@@ -44,9 +44,13 @@ constexpr int KMAX = P2M_MAX_SUPPORT;  // ELL width
 constexpr int KNN = P2M_CLOSURE_K;
 
 // Per-node metadata word of the ELL weights.
-// NT_PENDING: interior node whose support is known but whose weights are
-// still to be computed (transient inside one build).
-enum NodeType : uint32_t { NT_INTERIOR = 0, NT_RING = 1, NT_OUTSIDE = 2, NT_FAILED = 3, NT_PENDING = 4 };
+// NT_PENDING*: node whose support is known (interior: ring union; closure:
+// nearest particles, ring or outside-hull) but whose weights are still to be
+// computed (transient inside one build).
+enum NodeType : uint32_t {
+    NT_INTERIOR = 0, NT_RING = 1, NT_OUTSIDE = 2, NT_FAILED = 3,
+    NT_PENDING = 4, NT_PEND_RING = 5, NT_PEND_OUT = 6
+};
 // bits 0-2 type, 3-8 count, 9-13 / 14-18 / 19-23 ELL slots of the triangle's
 // vertices, 24- flags
 __host__ __device__ inline uint32_t meta_pack(uint32_t type, uint32_t cnt, uint32_t ta, uint32_t tb,

@@ -54,8 +54,10 @@ struct BuildOut {
 struct BuildParams {
     int hw0;         // slow path: half-width (bins) of the first search region
     int levels;      // slow path: region doublings before the global scan
-    double Rf;       // fast path: candidate radius around the node
+    double Rf;       // fast path: candidate radius around interior nodes
     int hwf;         // fast path: half-width (bins) of the square scanned for it
+    double Rc;       // fast path: candidate radius around boundary-ring nodes
+    int hwc;
 };
 int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N, const BuildOut& out,
                   const BuildParams& prm, int32_t* slow, unsigned long long* diag, hipStream_t st);

@@ -56,5 +56,7 @@ def test_options():
     assert lib.p2m_set_option(b"region_h", 4.0) == 0
     assert lib.p2m_set_option(b"levels", 3) == 0
     assert lib.p2m_set_option(b"bin_scale", 1.0) == 0
+    assert lib.p2m_set_option(b"closure_radius", 4.0) == 0
+    assert lib.p2m_set_option(b"closure_radius", 0.5) == -1
     assert lib.p2m_set_option(b"nonsense", 1.0) == -1
     assert lib.p2m_set_option(b"region_h", 1000.0) == -1
