@@ -202,6 +202,61 @@ int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const do
 
 void p2m_weights_destroy(p2m_weights* w);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent particle sets, each with its own mesh and h,
+ * handled by one launch sequence.  The sets are the paper's problem
+ * (eqs. p2m, m2p and App. B) repeated; nothing couples them.
+ * ------------------------------------------------------------------------ */
+#define P2M_MAX_SETS 65536
+
+/* Opaque batch description (host data plus a small device table).  Owned by
+ * the library until p2m_batch_destroy(). */
+typedef struct p2m_batch p2m_batch;
+
+/*
+ * p2m_batch_create -- describe S sets.
+ *  meshes       host [S] meshes; set s owns mesh nodes
+ *               node_offsets[s] .. node_offsets[s+1]-1 of every mesh-side
+ *               array (sets in order, each mesh x-fastest).
+ *  h            host [S] particle spacings (hints, as in p2m_build_weights).
+ *  S            1 .. P2M_MAX_SETS.
+ *  set_offsets  host [S+1]: set s owns particles set_offsets[s] ..
+ *               set_offsets[s+1]-1 of every particle-side array;
+ *               set_offsets[0] = 0, at least 3 particles per set, total
+ *               below 2^28.
+ *  out          receives the handle.
+ * Synchronous (uploads the device table).  Errors: EINVAL, ENOMEM, EHIP.
+ */
+int p2m_batch_create(const p2m_mesh* meshes, const double* h, int S, const int64_t* set_offsets,
+                     p2m_batch** out);
+
+/* Total nodes and particles of a batch, and (if non-NULL) the host array
+ * node_offsets[S+1] of each set's first node. */
+int p2m_batch_shape(const p2m_batch* b, int64_t* n_nodes, int64_t* n_particles, int64_t* node_offsets);
+
+void p2m_batch_destroy(p2m_batch* b);
+
+/*
+ * p2m_build_weights_batched -- p2m_build_weights for every set of a batch in
+ * one pass: one binning of all particles (bins of set s after those of set
+ * s-1) and one launch of each build kernel over the node tiles of all sets.
+ * pos is device [N_total][2]; particle ids in the handle are batch-global.
+ * The resulting handle is used with p2m_project, p2m_project_backward,
+ * p2m_build_weights_backward, p2m_weights_diag (counts summed over the
+ * sets) and p2m_weights_export exactly like a single-set handle, with
+ * mesh-side arrays of all sets' nodes concatenated.
+ */
+int p2m_build_weights_batched(const p2m_batch* b, const double* pos, int flags, p2m_weights** w,
+                              void* stream);
+
+/* m2p_interpolate and its adjoint over every set of a batch in one launch;
+ * arrays as in the single-set calls, concatenated over the sets. */
+int m2p_interpolate_batched(const p2m_batch* b, const void* mesh_vals, int C, int dtype,
+                            const double* pos, void* vals, void* stream);
+int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, int C, int dtype,
+                                     const double* pos, const void* grad_vals, void* grad_mesh,
+                                     double* grad_pos, void* stream);
+
 /* Process-wide tuning knobs for the weight build (performance only; results
  * do not depend on them).  Not thread-safe with concurrent builds.
  *   "bin_scale"  bin width ~ bin_scale * h        (0.25 .. 8,  default 1)

@@ -19,6 +19,7 @@ P2M_F64, P2M_F32, P2M_BF16 = 0, 1, 2
 P2M_WEIGHTS_F32, P2M_STRICT = 0x1, 0x2
 MAX_SUPPORT = 32
 CLOSURE_K = 12
+MAX_SETS = 65536
 
 STATUS_NAMES = {0: "P2M_OK", -1: "P2M_EINVAL", -2: "P2M_EDOMAIN", -3: "P2M_ECAP", -4: "P2M_EGEOM",
                 -5: "P2M_EHIP", -6: "P2M_ENOMEM"}
@@ -67,6 +68,13 @@ _SIGS = {
     "p2m_project_backward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
     "p2m_build_weights_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "p2m_weights_destroy": (None, [c_void_p]),
+    "p2m_batch_create": (c_int, [POINTER(P2MMesh), POINTER(c_double), c_int, POINTER(c_int64), POINTER(c_void_p)]),
+    "p2m_batch_shape": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
+    "p2m_batch_destroy": (None, [c_void_p]),
+    "p2m_build_weights_batched": (c_int, [c_void_p, c_void_p, c_int, POINTER(c_void_p), c_void_p]),
+    "m2p_interpolate_batched": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p]),
+    "m2p_interpolate_backward_batched": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                                 c_void_p, c_void_p]),
     "p2m_last_error": (c_char_p, []),
     "p2m_version": (c_char_p, []),
     "p2m_set_option": (c_int, [c_char_p, c_double]),

@@ -173,11 +173,12 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
     const int n = static_cast<int>(meta_cnt(meta));
     if (type == NT_FAILED || n == 0) return;
     const int64_t nn = a.w.n_nodes;
-    const MeshD& m = a.w.mesh;
+    const SetDesc& sd = a.w.sets[set_search(a.w.S, node, [&](int s) { return a.w.sets[s].n0; })];
+    const MeshD m = sd.m;
     const int stride = m.nx + 1;
-    const int i = static_cast<int>(node % stride), j = static_cast<int>(node / stride);
-    const double2 q = make_double2(add_rn(m.x0, mul_rn(static_cast<double>(i), m.H)),
-                                   add_rn(m.y0, mul_rn(static_cast<double>(j), m.H)));
+    const int64_t ln = node - sd.n0;
+    const int i = static_cast<int>(ln % stride), j = static_cast<int>(ln / stride);
+    const double2 q = node_pos(m, i, j);
     double* gx = sgx + tid;
     double* gy = sgy + tid;
     for (int k = 0; k < n; ++k) {

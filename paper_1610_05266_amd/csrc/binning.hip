@@ -19,16 +19,19 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 
-__global__ void __launch_bounds__(256) k_bin_count(const double2* __restrict__ pos, int N, MeshD m, Grid g,
+__global__ void __launch_bounds__(256) k_bin_count(const double2* __restrict__ pos, int N,
+                                                   const SetDesc* __restrict__ sets, int S, uint32_t nbins,
                                                    uint32_t* __restrict__ key, int32_t* __restrict__ rank,
                                                    int32_t* __restrict__ count,
                                                    unsigned long long* __restrict__ diag) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= N) return;
+    const SetDesc& sd = sets[set_search(S, i, [&](int s) { return sets[s].p0; })];
+    const MeshD m = sd.m;
+    const Grid g = sd.g;
     const double2 p = pos[i];
-    const double x1 = m.x0 + m.nx * m.H;
-    const double y1 = m.y0 + m.ny * m.H;
-    const uint32_t nbins = static_cast<uint32_t>(g.nbx) * static_cast<uint32_t>(g.nby);
+    const double x1 = add_rn(m.x0, mul_rn(static_cast<double>(m.nx), m.H));
+    const double y1 = add_rn(m.y0, mul_rn(static_cast<double>(m.ny), m.H));
     uint32_t k;
     // NaN fails every comparison, so it is caught here as well.
     if (p.x >= m.x0 && p.x <= x1 && p.y >= m.y0 && p.y <= y1) {
@@ -36,7 +39,8 @@ __global__ void __launch_bounds__(256) k_bin_count(const double2* __restrict__ p
         int by = static_cast<int>(floor((p.y - g.y0) / g.bw));
         bx = min(max(bx, 0), g.nbx - 1);
         by = min(max(by, 0), g.nby - 1);
-        k = static_cast<uint32_t>(by) * static_cast<uint32_t>(g.nbx) + static_cast<uint32_t>(bx);
+        k = static_cast<uint32_t>(sd.b0) + static_cast<uint32_t>(by) * static_cast<uint32_t>(g.nbx) +
+            static_cast<uint32_t>(bx);
     } else {
         k = nbins;
         atomicAdd(&diag[D_BAD], 1ull);
@@ -173,15 +177,15 @@ int exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum, hi
     return P2M_OK;
 }
 
-int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const MeshD& m, const Grid& g,
+int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDesc* sets, int S, int64_t nbins,
                   unsigned long long* diag, hipStream_t st) {
     PhaseTimer _timer(PH_BIN, st);
-    const int64_t nbins = static_cast<int64_t>(g.nbx) * g.nby;
     // count[0..nbins] (the last entry collects invalid particles)
     int rc = fill_i32(b.count, 0, nbins + 1, st);
     if (rc) return rc;
     k_bin_count<<<blocks_for(N, 256), 256, 0, st>>>(reinterpret_cast<const double2*>(pos), static_cast<int>(N),
-                                                    m, g, b.key, b.rank, b.count, diag);
+                                                    sets, S, static_cast<uint32_t>(nbins), b.key, b.rank,
+                                                    b.count, diag);
     P2M_HIP(hipGetLastError());
     rc = exclusive_scan(b.count, b.start, nbins + 1, b.tsum, st);
     if (rc) return rc;

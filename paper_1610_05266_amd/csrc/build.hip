@@ -68,11 +68,6 @@ __device__ __forceinline__ double orient(double2 p, double2 q, double2 r) {
     return (q.x - p.x) * (r.y - p.y) - (q.y - p.y) * (r.x - p.x);
 }
 
-__device__ __forceinline__ double2 node_pos(const MeshD& m, int i, int j) {
-    return make_double2(add_rn(m.x0, mul_rn(static_cast<double>(i), m.H)),
-                        add_rn(m.y0, mul_rn(static_cast<double>(j), m.H)));
-}
-
 // ------------------------------------------------- candidate comparisons
 // Bisector key of candidate b for the edge v -> a on side sgn: the circumcentre
 // of (v, a, b) is v + A/2 + (num / 2cr) sgn perp(A), with A = a - v, B = b - v,
@@ -795,19 +790,24 @@ struct KArgs {
     const double2* pos_s;
     const int32_t* perm;
     const int32_t* start;
-    MeshD m;
-    Grid g;
-    int64_t n_nodes;
+    const SetDesc* sets;  // [S]
+    int S;
+    int levels;           // slow path: region doublings before the global scan
+    int64_t n_nodes;      // all sets
     BuildOut out;
-    int hw0, levels;
-    double Rf;      // fast path: candidate radius of interior nodes
-    int hwf;        // bins scanned around the node for it
-    double Rc;      // fast path: candidate radius of boundary-ring nodes
-    int hwc;
-    int tiles_x;    // node tiles of 8 x 8 per row
-    int32_t* slow;  // slow-path node list (capacity n_nodes)
+    int32_t* slow;        // slow-path node list (capacity n_nodes)
     unsigned long long* diag;
 };
+
+// The set of a node tile / a node, and the tile's node (i, j) for a quad.
+__device__ __forceinline__ SetDesc tile_set(const KArgs& a, int64_t tile) {
+    const int si = set_search(a.S, tile, [&](int s) { return a.sets[s].t0; });
+    return a.sets[si];
+}
+__device__ __forceinline__ SetDesc node_set(const KArgs& a, int64_t node) {
+    const int si = set_search(a.S, node, [&](int s) { return a.sets[s].n0; });
+    return a.sets[si];
+}
 
 __device__ __forceinline__ uint32_t pending_type(uint32_t t) { return t == NT_OUTSIDE ? NT_PEND_OUT : NT_PEND_RING; }
 
@@ -1022,32 +1022,35 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     __shared__ int32_t svis[QPB * KMAX];
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
-    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const SetDesc sd = tile_set(a, blockIdx.x);
+    const int tl = static_cast<int>(blockIdx.x - sd.t0);
+    const int tx = tl % sd.tiles_x, ty = tl / sd.tiles_x;
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
-    const bool valid = i <= a.m.nx && j <= a.m.ny;
-    const int64_t node = static_cast<int64_t>(j) * (a.m.nx + 1) + i;
+    const bool valid = i <= sd.m.nx && j <= sd.m.ny;
+    const int64_t node = sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;
     const int64_t nn = a.n_nodes;
-    const bool ring = i == 0 || j == 0 || i == a.m.nx || j == a.m.ny;
+    const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
+    const int32_t* start = a.start + sd.b0;
     bool done = false;
     if (valid) {
         QuadSource g;
         g.pos = a.pos_s;
         g.perm = a.perm;
-        g.q = node_pos(a.m, i, j);
-        g.Rf = ring ? a.Rc : a.Rf;
+        g.q = node_pos(sd.m, i, j);
+        g.Rf = ring ? sd.Rc : sd.Rf;
         g.n = 0;
         g.lane = lane;
         // gather the particles within the radius, round-robin over the lanes
         const double R2 = g.Rf * g.Rf;
-        const int hw = ring ? a.hwc : a.hwf;
-        const int cbx = i * a.g.kb, cby = j * a.g.kb;
-        const int bx0 = max(cbx - hw, 0), bx1 = min(cbx + hw, a.g.nbx);
-        const int by0 = max(cby - hw, 0), by1 = min(cby + hw, a.g.nby);
+        const int hw = ring ? sd.hwc : sd.hwf;
+        const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
+        const int bx0 = max(cbx - hw, 0), bx1 = min(cbx + hw, sd.g.nbx);
+        const int by0 = max(cby - hw, 0), by1 = min(cby + hw, sd.g.nby);
         int ovf = 0;
         int flat = 0;
         for (int by = by0; by < by1; ++by) {
-            const int row = by * a.g.nbx;
-            const int s = a.start[row + bx0], e = a.start[row + bx1];
+            const int row = by * sd.g.nbx;
+            const int s = start[row + bx0], e = start[row + bx1];
             for (int t = s + ((lane - flat) & (QL - 1)); t < e; t += QL) {
                 const double2 p = a.pos_s[t];
                 const double dx = p.x - g.q.x, dy = p.y - g.q.y;
@@ -1153,20 +1156,22 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int count = static_cast<int>(a.diag[D_SLOWCNT]);
-    const int big = max(a.g.nbx, a.g.nby) + 1;
     const int64_t nn = a.n_nodes;
     for (int li = blockIdx.x * WPB + wv; li < count; li += gridDim.x * WPB) {
         const int64_t node = a.slow[li];
-        const int i = static_cast<int>(node % (a.m.nx + 1));
-        const int j = static_cast<int>(node / (a.m.nx + 1));
-        const double2 q = node_pos(a.m, i, j);
-        const bool ring = i == 0 || j == 0 || i == a.m.nx || j == a.m.ny;
-        const int cbx = i * a.g.kb, cby = j * a.g.kb;
+        const SetDesc sd = node_set(a, node);
+        const int big = max(sd.g.nbx, sd.g.nby) + 1;
+        const int64_t ln = node - sd.n0;
+        const int i = static_cast<int>(ln % (sd.m.nx + 1));
+        const int j = static_cast<int>(ln / (sd.m.nx + 1));
+        const double2 q = node_pos(sd.m, i, j);
+        const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
+        const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
         WaveSource c;
         c.pos = a.pos_s;
         c.perm = a.perm;
-        c.start = a.start;
-        c.g = a.g;
+        c.start = a.start + sd.b0;
+        c.g = sd.g;
         c.neardeg = 0;
         c.lane = lane;
         c.lp = slp + wv * STAGE;
@@ -1181,8 +1186,8 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         int st = R_FAIL;
         if (!ring) {
             for (int level = 0;; ++level) {
-                const int hw = level < a.levels ? (a.hw0 << level) : big;
-                c.set_region(make_region(a.g, cbx, cby, hw));
+                const int hw = level < a.levels ? (sd.hw0 << level) : big;
+                c.set_region(make_region(sd.g, cbx, cby, hw));
                 S.n = 0;
                 st = delaunay_node(c, q, T, S, svis + wv * KMAX);
                 if (st != R_MORE) break;
@@ -1217,8 +1222,8 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             // per round as the smallest (d^2, user id) above the previous pick
             int kk = 0;
             for (int level = 0;; ++level) {
-                const int hw = level < a.levels ? (a.hw0 << level) : big;
-                c.set_region(make_region(a.g, cbx, cby, hw));
+                const int hw = level < a.levels ? (sd.hw0 << level) : big;
+                c.set_region(make_region(sd.g, cbx, cby, hw));
                 kk = 0;
                 double pd = -1.0;
                 int pu = -1;
@@ -1283,11 +1288,13 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
 __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
-    const int tx = blockIdx.x % a.tiles_x, ty = blockIdx.x / a.tiles_x;
+    const SetDesc sd = tile_set(a, blockIdx.x);
+    const int tl = static_cast<int>(blockIdx.x - sd.t0);
+    const int tx = tl % sd.tiles_x, ty = tl / sd.tiles_x;
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
-    const bool valid = i <= a.m.nx && j <= a.m.ny;
+    const bool valid = i <= sd.m.nx && j <= sd.m.ny;
     const int64_t nn = a.n_nodes;
-    const int64_t node = static_cast<int64_t>(j) * (a.m.nx + 1) + i;
+    const int64_t node = sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;
     const uint32_t meta = valid ? a.out.meta[node] : 0u;
     const uint32_t type = valid ? meta_type(meta) : NT_FAILED;
     const int n = static_cast<int>(meta_cnt(meta));
@@ -1299,9 +1306,9 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
             return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + node]) |
                                         (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28));
         };
-        quad_weights(a, node, node_pos(a.m, i, j), uget, n, T, lane, meta_flags(meta));
+        quad_weights(a, node, node_pos(sd.m, i, j), uget, n, T, lane, meta_flags(meta));
     } else if (type == NT_PEND_RING || type == NT_PEND_OUT) {
-        quad_closure(a, node, node_pos(a.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
+        quad_closure(a, node, node_pos(sd.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
                      meta_flags(meta));
     }
     // diagnostics: one count per quad (lane 0), one atomic per wave
@@ -1321,43 +1328,40 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
 
 }  // namespace
 
-int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N, const BuildOut& out,
-                  const BuildParams& prm, int32_t* slow, unsigned long long* diag, hipStream_t st) {
+int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
+                  const BuildOut& out, int levels, int32_t* slow, unsigned long long* diag, hipStream_t st) {
     PhaseTimer _timer(PH_BUILD, st);
-    (void)N;
+    if (n_tiles >= (int64_t(1) << 31)) {
+        set_error("too many node tiles (%lld)", static_cast<long long>(n_tiles));
+        return P2M_EINVAL;
+    }
     KArgs a;
     a.pos_s = reinterpret_cast<const double2*>(b.pos_s);
     a.perm = b.perm;
     a.start = b.start;
-    a.m = m;
-    a.g = g;
-    a.n_nodes = static_cast<int64_t>(m.nx + 1) * (m.ny + 1);
+    a.sets = sets;
+    a.S = S;
+    a.levels = levels;
+    a.n_nodes = n_nodes;
     a.out = out;
-    a.hw0 = prm.hw0;
-    a.levels = prm.levels;
-    a.Rf = prm.Rf;
-    a.hwf = prm.hwf;
-    a.Rc = prm.Rc;
-    a.hwc = prm.hwc;
-    a.tiles_x = (m.nx + 1 + 7) / 8;
-    const int tiles_y = (m.ny + 1 + 7) / 8;
     a.slow = slow;
     a.diag = diag;
+    const int tiles = static_cast<int>(n_tiles);
     {
         PhaseTimer t1(PH_BUILD_FAST, st);
-        k_build_fast<<<a.tiles_x * tiles_y, QWG, 0, st>>>(a);
+        k_build_fast<<<tiles, QWG, 0, st>>>(a);
     }
     {
         // one wave per slow node (few: escalated, undecided, corners); the
         // grid loops over the actual list
         PhaseTimer t2(PH_BUILD_SLOW, st);
-        const int64_t expect = a.n_nodes / 256 + 64;
+        const int64_t expect = n_nodes / 256 + 64 * static_cast<int64_t>(S);
         const int gs = static_cast<int>(std::min<int64_t>((expect + SWG / WAVE - 1) / (SWG / WAVE), 4096));
         k_slow_geom<<<gs, SWG, 0, st>>>(a);
     }
     {
         PhaseTimer t3(PH_WEIGHTS, st);
-        k_weights<<<a.tiles_x * tiles_y, QWG, 0, st>>>(a);
+        k_weights<<<tiles, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());
     return P2M_OK;

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 
@@ -37,20 +38,26 @@ int hip_check(hipError_t e, const char* what) {
     return e == hipErrorOutOfMemory ? P2M_ENOMEM : P2M_EHIP;
 }
 
+// Sizes of all sets of a batch together.
+struct SetTotals {
+    int64_t N = 0, n_nodes = 0, nbins = 0, n_tiles = 0;
+};
+
 }  // namespace p2m
 
 using namespace p2m;
 
 struct p2m_weights {
     int device = -1;
-    MeshD mesh{};
-    double h = 0.0;
-    Grid grid{};
+    int S = 0;                        // particle sets (1 unless built from a batch)
+    std::vector<p2m::SetDesc> hsets;  // host copy of the device set table
+    p2m::SetDesc* dsets = nullptr;    // device set table [capSets]
     int64_t N = 0;
     int64_t n_nodes = 0;
+    int64_t n_tiles = 0;
     int flags = 0;
     // capacities of the device buffers
-    int64_t capN = 0, capBins = 0, capNodes = 0, capTiles = 0;
+    int64_t capN = 0, capBins = 0, capNodes = 0, capTiles = 0, capSets = 0;
     bool capW32 = false;
     BinBuffers bins{};
     uint32_t* meta = nullptr;
@@ -60,6 +67,17 @@ struct p2m_weights {
     float* w32 = nullptr;
     uint8_t* mem = nullptr;
     unsigned long long* diag = nullptr;
+};
+
+struct p2m_batch {
+    int device = -1;
+    std::vector<p2m_mesh> meshes;
+    std::vector<double> h;
+    std::vector<int64_t> off;            // [S + 1] particle offsets
+    std::vector<p2m::SetDesc> sets;      // host copy of the device table
+    p2m::SetTotals tot;
+    p2m::SetDesc* dsets = nullptr;       // device [S], for the batched M2P
+    int S() const { return static_cast<int>(meshes.size()); }
 };
 
 namespace {
@@ -82,7 +100,7 @@ int grow(T** p, int64_t count, int64_t have) {
 
 void release(p2m_weights* w) {
     void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.count, w->bins.start, w->bins.tsum, w->bins.pos_s,
-                    w->bins.perm, w->meta, w->idx, w->slow, w->w64, w->w32, w->mem, w->diag};
+                    w->bins.perm, w->meta, w->idx, w->slow, w->w64, w->w32, w->mem, w->diag, w->dsets};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
 }
@@ -135,8 +153,8 @@ MeshD to_meshd(const p2m_mesh* m) { return MeshD{m->nx, m->ny, m->H, m->x0, m->y
 
 WeightsView view(const p2m_weights* w) {
     WeightsView v;
-    v.mesh = w->mesh;
-    v.grid = w->grid;
+    v.sets = w->dsets;
+    v.S = w->S;
     v.n_nodes = w->n_nodes;
     v.N = w->N;
     v.meta = w->meta;
@@ -160,9 +178,175 @@ int check_handle(const p2m_weights* w) {
     return P2M_OK;
 }
 
+// Set table of a batch: grid, fast-path radii and offsets of every set from
+// its mesh, its particle spacing h and the current tuning options.
+int make_sets(const p2m_mesh* meshes, const double* hs, const int64_t* off, int S, std::vector<SetDesc>& sets,
+              SetTotals& tot) {
+    sets.assign(S, SetDesc{});
+    tot = SetTotals{};
+    if (off[0] != 0) {
+        set_error("set_offsets[0] must be 0");
+        return P2M_EINVAL;
+    }
+    for (int s = 0; s < S; ++s) {
+        int rc = check_mesh(&meshes[s]);
+        if (rc) return rc;
+        const p2m_mesh& mesh = meshes[s];
+        const double h = hs[s];
+        if (!(h > 0.0) || !is_fin(h)) {
+            set_error("set %d: h must be positive and finite (got %g)", s, h);
+            return P2M_EINVAL;
+        }
+        const int64_t Ns = off[s + 1] - off[s];
+        if (Ns < 3) {
+            set_error("set %d has %lld particles (at least 3 needed)", s, static_cast<long long>(Ns));
+            return P2M_EINVAL;
+        }
+        // binning grid: kb x kb bins per cell, bin width close to bin_scale * h
+        const double want = g_tune.bin_scale * h;
+        int64_t kb = std::max<int64_t>(1, std::llround(mesh.H / want));
+        while (kb > 1 && static_cast<double>(mesh.nx) * kb * static_cast<double>(mesh.ny) * kb > 1.0e9) --kb;
+        SetDesc& d = sets[s];
+        d.m = to_meshd(&mesh);
+        d.g.kb = static_cast<int>(kb);
+        d.g.nbx = static_cast<int>(mesh.nx * kb);
+        d.g.nby = static_cast<int>(mesh.ny * kb);
+        d.g.bw = mesh.H / static_cast<double>(kb);
+        d.g.x0 = mesh.x0;
+        d.g.y0 = mesh.y0;
+        d.p0 = off[s];
+        d.n0 = tot.n_nodes;
+        d.b0 = tot.nbins;
+        d.t0 = tot.n_tiles;
+        d.tiles_x = (mesh.nx + 1 + 7) / 8;
+        d.hw0 = std::max(2, static_cast<int>(std::ceil(g_tune.region_h * h / d.g.bw)));
+        d.Rf = g_tune.fast_radius * h;
+        d.hwf = std::max(1, static_cast<int>(std::ceil(d.Rf / d.g.bw)));
+        d.Rc = g_tune.closure_radius * h;
+        d.hwc = std::max(1, static_cast<int>(std::ceil(d.Rc / d.g.bw)));
+        tot.n_nodes += static_cast<int64_t>(mesh.nx + 1) * (mesh.ny + 1);
+        tot.nbins += static_cast<int64_t>(d.g.nbx) * d.g.nby;
+        tot.n_tiles += static_cast<int64_t>(d.tiles_x) * ((mesh.ny + 1 + 7) / 8);
+    }
+    tot.N = off[S];
+    if (tot.N >= (int64_t(1) << 28)) {
+        set_error("N=%lld particles in all sets, at most 2^28 - 1", static_cast<long long>(tot.N));
+        return P2M_EINVAL;
+    }
+    if (tot.nbins >= (int64_t(1) << 31) - 2) {
+        set_error("binning grid too large (%lld bins)", static_cast<long long>(tot.nbins));
+        return P2M_EINVAL;
+    }
+    if (tot.n_nodes * KMAX >= (int64_t(1) << 40) || tot.n_tiles >= (int64_t(1) << 31)) {
+        set_error("meshes too large (%lld nodes)", static_cast<long long>(tot.n_nodes));
+        return P2M_EINVAL;
+    }
+    return P2M_OK;
+}
+
+// Shared by the single-set and batched builds: workspace, set table upload
+// (only when it changed), binning and the three build kernels.
+int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const double* pos, int flags,
+               p2m_weights** wout, hipStream_t st) {
+    if (!pos || !aligned(pos, 16)) {
+        set_error("pos is NULL or not 16-byte aligned");
+        return P2M_EINVAL;
+    }
+    if (!wout) {
+        set_error("output handle pointer is NULL");
+        return P2M_EINVAL;
+    }
+    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT)) {
+        set_error("unknown flags 0x%x", flags);
+        return P2M_EINVAL;
+    }
+    int dev = 0;
+    P2M_HIP(hipGetDevice(&dev));
+    p2m_weights* w = *wout;
+    bool fresh = false;
+    if (!w) {
+        w = new (std::nothrow) p2m_weights();
+        if (!w) {
+            set_error("host allocation failed");
+            return P2M_ENOMEM;
+        }
+        w->device = dev;
+        fresh = true;
+    } else if (w->device != dev) {
+        set_error("handle belongs to device %d, current device is %d", w->device, dev);
+        return P2M_EINVAL;
+    }
+    const int S = static_cast<int>(sets.size());
+    const int64_t N = tot.N, n_nodes = tot.n_nodes, nbins = tot.nbins;
+    const int64_t ntiles = scan_tile_count(nbins + 1) + 1;
+    const bool want32 = (flags & P2M_WEIGHTS_F32) != 0;
+    const bool new_table = !w->dsets || w->capSets < S;
+    int rc = P2M_OK;
+    if (!rc) rc = grow(&w->bins.key, N, w->capN);
+    if (!rc) rc = grow(&w->bins.rank, N, w->capN);
+    if (!rc) rc = grow(&w->bins.perm, N, w->capN);
+    if (!rc) rc = grow(&w->bins.pos_s, 2 * N, 2 * w->capN);
+    if (!rc) w->capN = std::max(w->capN, N);
+    if (!rc) rc = grow(&w->bins.count, nbins + 1, w->capBins + 1);
+    if (!rc) rc = grow(&w->bins.start, nbins + 2, w->capBins + 2);
+    if (!rc) w->capBins = std::max(w->capBins, nbins);
+    if (!rc) rc = grow(&w->bins.tsum, ntiles + 1, w->capTiles + 1);
+    if (!rc) w->capTiles = std::max(w->capTiles, ntiles);
+    if (!rc) rc = grow(&w->meta, n_nodes, w->capNodes);
+    if (!rc) rc = grow(&w->slow, n_nodes, w->capNodes);
+    if (!rc) rc = grow(&w->idx, n_nodes * KMAX, w->capNodes * KMAX);
+    if (!rc) rc = grow(&w->w64, n_nodes * KMAX, w->capNodes * KMAX);
+    if (!rc) rc = grow(&w->mem, n_nodes * KMAX, w->capNodes * KMAX);
+    if (!rc && want32) rc = grow(&w->w32, n_nodes * KMAX, w->capW32 ? w->capNodes * KMAX : 0);
+    if (!rc && !w->diag) rc = grow(&w->diag, D_COUNT, 0);
+    if (!rc) rc = grow(&w->dsets, S, w->capSets);
+    if (rc) {
+        if (fresh) {
+            release(w);
+            delete w;
+        }
+        return rc;
+    }
+    if (want32 && !w->capW32) w->capW32 = true;
+    w->capNodes = std::max(w->capNodes, n_nodes);
+    w->capSets = std::max<int64_t>(w->capSets, S);
+    if (new_table || w->hsets.size() != sets.size() ||
+        std::memcmp(w->hsets.data(), sets.data(), sizeof(SetDesc) * sets.size()) != 0) {
+        // stream-ordered, so kernels still running on the old table finish first
+        P2M_HIP(hipMemcpyAsync(w->dsets, sets.data(), sizeof(SetDesc) * S, hipMemcpyHostToDevice, st));
+        w->hsets = sets;
+    }
+    w->S = S;
+    w->N = N;
+    w->n_nodes = n_nodes;
+    w->n_tiles = tot.n_tiles;
+    w->flags = flags;
+    *wout = w;
+
+    rc = fill_u64(w->diag, 0ull, D_COUNT, st);
+    if (!rc) rc = bin_particles(w->bins, pos, N, w->dsets, S, nbins, w->diag, st);
+    if (rc) return rc;
+    BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem};
+    return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, w->slow, w->diag, st);
+}
+
+int check_batch(const p2m_batch* b) {
+    if (!b) {
+        set_error("batch handle is NULL");
+        return P2M_EINVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != b->device) {
+        set_error("batch handle belongs to device %d, current device is %d", b->device, dev);
+        return P2M_EINVAL;
+    }
+    return P2M_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
 
 const char* p2m_last_error(void) { return g_err.c_str(); }
 
@@ -194,111 +378,86 @@ int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t
                       p2m_weights** wout, void* stream) {
     int rc = check_mesh(mesh);
     if (rc) return rc;
-    if (!(h > 0.0) || !is_fin(h)) {
-        set_error("h must be positive and finite (got %g)", h);
-        return P2M_EINVAL;
-    }
-    if (!pos || !aligned(pos, 16)) {
-        set_error("pos is NULL or not 16-byte aligned");
-        return P2M_EINVAL;
-    }
     if (N < 3 || N >= (int64_t(1) << 28)) {
         set_error("N=%lld out of range [3, 2^28)", static_cast<long long>(N));
         return P2M_EINVAL;
     }
-    if (!wout) {
+    const int64_t off[2] = {0, N};
+    std::vector<SetDesc> sets;
+    SetTotals tot;
+    rc = make_sets(mesh, &h, off, 1, sets, tot);
+    if (rc) return rc;
+    return build_sets(sets, tot, pos, flags, wout, static_cast<hipStream_t>(stream));
+}
+
+int p2m_batch_create(const p2m_mesh* meshes, const double* h, int S, const int64_t* set_offsets, p2m_batch** out) {
+    if (!out) {
         set_error("output handle pointer is NULL");
         return P2M_EINVAL;
     }
-    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT)) {
-        set_error("unknown flags 0x%x", flags);
+    *out = nullptr;
+    if (!meshes || !h || !set_offsets) {
+        set_error("meshes / h / set_offsets is NULL");
         return P2M_EINVAL;
     }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    int dev = 0;
-    P2M_HIP(hipGetDevice(&dev));
-
-    // binning grid: kb x kb bins per cell, bin width close to bin_scale * h
-    const double want = g_tune.bin_scale * h;
-    int64_t kb = std::max<int64_t>(1, std::llround(mesh->H / want));
-    while (kb > 1 && static_cast<double>(mesh->nx) * kb * static_cast<double>(mesh->ny) * kb > 1.0e9) --kb;
-    const int64_t nbins = static_cast<int64_t>(mesh->nx) * kb * mesh->ny * kb;
-    if (nbins > (int64_t(1) << 30)) {
-        set_error("binning grid too large (%lld bins)", static_cast<long long>(nbins));
+    if (S < 1 || S > P2M_MAX_SETS) {
+        set_error("S=%d out of range [1, %d]", S, P2M_MAX_SETS);
         return P2M_EINVAL;
     }
-    Grid g;
-    g.kb = static_cast<int>(kb);
-    g.nbx = static_cast<int>(mesh->nx * kb);
-    g.nby = static_cast<int>(mesh->ny * kb);
-    g.bw = mesh->H / static_cast<double>(kb);
-    g.x0 = mesh->x0;
-    g.y0 = mesh->y0;
-
-    p2m_weights* w = *wout;
-    bool fresh = false;
-    if (!w) {
-        w = new (std::nothrow) p2m_weights();
-        if (!w) {
-            set_error("host allocation failed");
-            return P2M_ENOMEM;
-        }
-        w->device = dev;
-        fresh = true;
-    } else if (w->device != dev) {
-        set_error("handle belongs to device %d, current device is %d", w->device, dev);
-        return P2M_EINVAL;
+    p2m_batch* b = new (std::nothrow) p2m_batch();
+    if (!b) {
+        set_error("host allocation failed");
+        return P2M_ENOMEM;
     }
-    const int64_t n_nodes = static_cast<int64_t>(mesh->nx + 1) * (mesh->ny + 1);
-    const int64_t ntiles = scan_tile_count(nbins + 1) + 1;
-    const bool want32 = (flags & P2M_WEIGHTS_F32) != 0;
-    rc = P2M_OK;
-    if (!rc) rc = grow(&w->bins.key, N, w->capN);
-    if (!rc) rc = grow(&w->bins.rank, N, w->capN);
-    if (!rc) rc = grow(&w->bins.perm, N, w->capN);
-    if (!rc) rc = grow(&w->bins.pos_s, 2 * N, 2 * w->capN);
-    if (!rc) w->capN = std::max(w->capN, N);
-    if (!rc) rc = grow(&w->bins.count, nbins + 1, w->capBins + 1);
-    if (!rc) rc = grow(&w->bins.start, nbins + 2, w->capBins + 2);
-    if (!rc) w->capBins = std::max(w->capBins, nbins);
-    if (!rc) rc = grow(&w->bins.tsum, ntiles + 1, w->capTiles + 1);
-    if (!rc) w->capTiles = std::max(w->capTiles, ntiles);
-    if (!rc) rc = grow(&w->meta, n_nodes, w->capNodes);
-    if (!rc) rc = grow(&w->slow, n_nodes, w->capNodes);
-    if (!rc) rc = grow(&w->idx, n_nodes * KMAX, w->capNodes * KMAX);
-    if (!rc) rc = grow(&w->w64, n_nodes * KMAX, w->capNodes * KMAX);
-    if (!rc) rc = grow(&w->mem, n_nodes * KMAX, w->capNodes * KMAX);
-    if (!rc && want32) rc = grow(&w->w32, n_nodes * KMAX, w->capW32 ? w->capNodes * KMAX : 0);
-    if (!rc && !w->diag) rc = grow(&w->diag, D_COUNT, 0);
+    int rc = make_sets(meshes, h, set_offsets, S, b->sets, b->tot);
+    if (!rc) {
+        b->meshes.assign(meshes, meshes + S);
+        b->h.assign(h, h + S);
+        b->off.assign(set_offsets, set_offsets + S + 1);
+        hipError_t e = hipGetDevice(&b->device);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&b->dsets), sizeof(SetDesc) * S);
+        if (e == hipSuccess)
+            e = hipMemcpy(b->dsets, b->sets.data(), sizeof(SetDesc) * S, hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = hip_check(e, "p2m_batch_create");
+    }
     if (rc) {
-        if (fresh) {
-            release(w);
-            delete w;
-        }
+        if (b->dsets) (void)hipFree(b->dsets);
+        delete b;
         return rc;
     }
-    if (want32 && !w->capW32) w->capW32 = true;
-    w->capNodes = std::max(w->capNodes, n_nodes);
-    w->mesh = to_meshd(mesh);
-    w->h = h;
-    w->grid = g;
-    w->N = N;
-    w->n_nodes = n_nodes;
-    w->flags = flags;
-    *wout = w;
+    *out = b;
+    return P2M_OK;
+}
 
-    rc = fill_u64(w->diag, 0ull, D_COUNT, st);
-    if (!rc) rc = bin_particles(w->bins, pos, N, w->mesh, g, w->diag, st);
+int p2m_batch_shape(const p2m_batch* b, int64_t* n_nodes, int64_t* n_particles, int64_t* node_offsets) {
+    if (!b) {
+        set_error("batch handle is NULL");
+        return P2M_EINVAL;
+    }
+    if (n_nodes) *n_nodes = b->tot.n_nodes;
+    if (n_particles) *n_particles = b->tot.N;
+    if (node_offsets) {
+        for (int s = 0; s < b->S(); ++s) node_offsets[s] = b->sets[s].n0;
+        node_offsets[b->S()] = b->tot.n_nodes;
+    }
+    return P2M_OK;
+}
+
+void p2m_batch_destroy(p2m_batch* b) {
+    if (!b) return;
+    if (b->dsets) (void)hipFree(b->dsets);
+    delete b;
+}
+
+int p2m_build_weights_batched(const p2m_batch* b, const double* pos, int flags, p2m_weights** wout, void* stream) {
+    int rc = check_batch(b);
     if (rc) return rc;
-    BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem};
-    BuildParams prm;
-    prm.hw0 = std::max(2, static_cast<int>(std::ceil(g_tune.region_h * h / g.bw)));
-    prm.levels = g_tune.levels;
-    prm.Rf = g_tune.fast_radius * h;
-    prm.hwf = std::max(1, static_cast<int>(std::ceil(prm.Rf / g.bw)));
-    prm.Rc = g_tune.closure_radius * h;
-    prm.hwc = std::max(1, static_cast<int>(std::ceil(prm.Rc / g.bw)));
-    return build_weights(w->bins, w->mesh, g, N, out, prm, w->slow, w->diag, st);
+    std::vector<SetDesc> sets;
+    SetTotals tot;
+    // recomputed so that the current tuning options apply
+    rc = make_sets(b->meshes.data(), b->h.data(), b->off.data(), b->S(), sets, tot);
+    if (rc) return rc;
+    return build_sets(sets, tot, pos, flags, wout, static_cast<hipStream_t>(stream));
 }
 
 int p2m_weights_diag(const p2m_weights* w, p2m_diag* d, void* stream) {
@@ -379,7 +538,23 @@ int m2p_interpolate(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtyp
         set_error("pos is NULL/misaligned or N=%lld out of range", static_cast<long long>(N));
         return P2M_EINVAL;
     }
-    return m2p(to_meshd(mesh), mesh_vals, C, dtype, pos, N, vals, static_cast<hipStream_t>(stream));
+    const MeshD m = to_meshd(mesh);
+    return m2p(m, nullptr, 1, static_cast<int64_t>(m.nx + 1) * (m.ny + 1), mesh_vals, C, dtype, pos, N, vals,
+               static_cast<hipStream_t>(stream));
+}
+
+int m2p_interpolate_batched(const p2m_batch* b, const void* mesh_vals, int C, int dtype, const double* pos,
+                            void* vals, void* stream) {
+    int rc = check_batch(b);
+    if (!rc) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (!rc) rc = check_vals(vals, C, dtype, "vals", false);
+    if (rc) return rc;
+    if (!pos || !aligned(pos, 16)) {
+        set_error("pos is NULL or misaligned");
+        return P2M_EINVAL;
+    }
+    return m2p(MeshD{}, b->dsets, b->S(), b->tot.n_nodes, mesh_vals, C, dtype, pos, b->tot.N, vals,
+               static_cast<hipStream_t>(stream));
 }
 
 int m2p_interpolate_backward(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtype, const double* pos,
@@ -397,8 +572,25 @@ int m2p_interpolate_backward(const p2m_mesh* mesh, const void* mesh_vals, int C,
         set_error("grad_pos is misaligned");
         return P2M_EINVAL;
     }
-    return m2p_backward(to_meshd(mesh), mesh_vals, C, dtype, pos, N, grad_vals, grad_mesh, grad_pos,
-                        static_cast<hipStream_t>(stream));
+    const MeshD m = to_meshd(mesh);
+    return m2p_backward(m, nullptr, 1, static_cast<int64_t>(m.nx + 1) * (m.ny + 1), mesh_vals, C, dtype, pos, N,
+                        grad_vals, grad_mesh, grad_pos, static_cast<hipStream_t>(stream));
+}
+
+int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, int C, int dtype,
+                                     const double* pos, const void* grad_vals, void* grad_mesh, double* grad_pos,
+                                     void* stream) {
+    int rc = check_batch(b);
+    if (!rc) rc = check_vals(grad_vals, C, dtype == P2M_BF16 ? P2M_F32 : dtype, "grad_vals", true);
+    if (!rc && grad_mesh) rc = check_vals(grad_mesh, C, dtype, "grad_mesh", true);
+    if (!rc && grad_pos) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (rc) return rc;
+    if (!pos || !aligned(pos, 16) || (grad_pos && !aligned(grad_pos, 16))) {
+        set_error("pos / grad_pos NULL or misaligned");
+        return P2M_EINVAL;
+    }
+    return m2p_backward(MeshD{}, b->dsets, b->S(), b->tot.n_nodes, mesh_vals, C, dtype, pos, b->tot.N, grad_vals,
+                        grad_mesh, grad_pos, static_cast<hipStream_t>(stream));
 }
 
 int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int dtype, const void* vals,

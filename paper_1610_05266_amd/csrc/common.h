@@ -67,12 +67,43 @@ __host__ __device__ inline uint32_t meta_flags(uint32_t m) { return m >> 24; }
 // the Delaunay ring of the k-th vertex of the node's triangle.
 constexpr uint8_t MB_RING_A = 1, MB_RING_B = 2, MB_RING_C = 4;
 
+// One particle set of a batch: its own mesh, binning grid and fast-path
+// radii, and where its particles, nodes, bins and node tiles start in the
+// concatenated arrays.  A single-set build is a batch of one.
+struct SetDesc {
+    MeshD m;
+    Grid g;
+    int64_t p0;       // first particle (user order)
+    int64_t n0;       // first mesh node
+    int64_t b0;       // first bin
+    int64_t t0;       // first 8 x 8 node tile
+    int32_t tiles_x;  // node tiles per row
+    int32_t hw0;      // slow path: half-width (bins) of the first region
+    int32_t hwf;      // fast path: half-width (bins) scanned for interior nodes
+    int32_t hwc;      // fast path: half-width (bins) scanned for ring nodes
+    double Rf;        // fast path: candidate radius of interior nodes
+    double Rc;        // fast path: candidate radius of boundary-ring nodes
+};
+
+// Index of the set that holds item v, where first(s) is the first item of
+// set s (non-decreasing in s).  Uniform loads; S = 1 costs nothing.
+template <class F>
+__device__ __forceinline__ int set_search(int S, int64_t v, F&& first) {
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (first(mid) <= v) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Everything the kernels need to know about one weights handle.
 struct WeightsView {
-    MeshD mesh;
-    Grid grid;
-    int64_t n_nodes;
-    int64_t N;
+    const SetDesc* sets;    // [S] device
+    int S;
+    int64_t n_nodes;        // all sets
+    int64_t N;              // all sets
     const uint32_t* meta;   // [n_nodes]
     const int32_t* idx;     // [KMAX][n_nodes] user particle ids
     const double* w64;      // [KMAX][n_nodes]
@@ -84,6 +115,13 @@ struct WeightsView {
 // FMAs (node coordinates are defined as x0 + i*H with two roundings).
 __device__ __forceinline__ double mul_rn(double a, double b) { return __dmul_rn(a, b); }
 __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+
+// Position of mesh node (i, j): (x0 + i H, y0 + j H), each coordinate rounded
+// twice (product, then sum), never fused.
+__device__ __forceinline__ double2 node_pos(const MeshD& m, int i, int j) {
+    return make_double2(add_rn(m.x0, mul_rn(static_cast<double>(i), m.H)),
+                        add_rn(m.y0, mul_rn(static_cast<double>(j), m.H)));
+}
 
 // Field element loads/stores with widening to the accumulation type.
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) {

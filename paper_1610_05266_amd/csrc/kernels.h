@@ -40,7 +40,9 @@ struct BinBuffers {
 };
 int64_t scan_tile_count(int64_t n);
 int exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum, hipStream_t st);
-int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const MeshD& m, const Grid& g,
+// Bins of set s are b0(s) .. b0(s) + nbx nby - 1; key nbins (all sets)
+// collects particles outside their set's mesh or non-finite.
+int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDesc* sets, int S, int64_t nbins,
                   unsigned long long* diag, hipStream_t st);
 
 // ---- weight build (build.hip) ----
@@ -51,25 +53,23 @@ struct BuildOut {
     float* w32;      // [KMAX][n_nodes] or null
     uint8_t* mem;    // [KMAX][n_nodes]
 };
-struct BuildParams {
-    int hw0;         // slow path: half-width (bins) of the first search region
-    int levels;      // slow path: region doublings before the global scan
-    double Rf;       // fast path: candidate radius around interior nodes
-    int hwf;         // fast path: half-width (bins) of the square scanned for it
-    double Rc;       // fast path: candidate radius around boundary-ring nodes
-    int hwc;
-};
-int build_weights(const BinBuffers& b, const MeshD& m, const Grid& g, int64_t N, const BuildOut& out,
-                  const BuildParams& prm, int32_t* slow, unsigned long long* diag, hipStream_t st);
+// All sets of a batch in one pass of three kernels (fast quad path, slow
+// wave path, weights); sets[S] is device memory, n_tiles the 8 x 8 node
+// tiles of all sets.
+int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
+                  const BuildOut& out, int levels, int32_t* slow, unsigned long long* diag, hipStream_t st);
 
 // ---- projection and interpolation (project.hip, m2p.hip) ----
 int project(const WeightsView& w, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st);
 int project_backward(const WeightsView& w, const void* grad_mesh, int C, int dtype, const void* vals,
                      void* grad_vals, double* grad_w, hipStream_t st);
-int m2p(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N, void* vals,
-        hipStream_t st);
-int m2p_backward(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N,
-                 const void* grad_vals, void* grad_mesh, double* grad_pos, hipStream_t st);
+// sets == nullptr: one mesh m; else particles/nodes of set s start at
+// sets[s].p0 / sets[s].n0 and m is ignored.  n_nodes: all sets.
+int m2p(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C, int dtype,
+        const double* pos, int64_t N, void* vals, hipStream_t st);
+int m2p_backward(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C,
+                 int dtype, const double* pos, int64_t N, const void* grad_vals, void* grad_mesh, double* grad_pos,
+                 hipStream_t st);
 
 // ---- adjoint of the weights (adjoint.hip) ----
 int build_backward(const WeightsView& w, const double* pos, const double* grad_w, double* grad_pos,

@@ -63,14 +63,36 @@ __device__ __forceinline__ void st(uint16_t* p, int64_t i, float v) { p[i] = f32
 __device__ __forceinline__ double ldv(const double* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ldv(const float* p, int64_t i) { return p[i]; }
 
+// The mesh of particle mu and the offset of that mesh's nodes: one mesh, or
+// the set of a batch that holds mu.
+struct MeshOf {
+    MeshD m;
+    const SetDesc* sets;
+    int S;
+    __device__ __forceinline__ MeshD get(int64_t mu, int64_t& n0) const {
+        if (!sets) {
+            n0 = 0;
+            return m;
+        }
+        const SetDesc& sd = sets[set_search(S, mu, [&](int s) { return sets[s].p0; })];
+        n0 = sd.n0;
+        return sd.m;
+    }
+};
+
 // TM mesh value type (accumulation type), TO particle output type
 template <typename TM, typename TO, int CC>
-__global__ void __launch_bounds__(256) k_m2p(MeshD m, const TM* __restrict__ mv, int Crt,
+__global__ void __launch_bounds__(256) k_m2p(MeshOf mo, const TM* __restrict__ mv, int Crt,
                                              const double2* __restrict__ pos, int64_t N, TO* __restrict__ out) {
     const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mu >= N) return;
     const int C = CC > 0 ? CC : Crt;
-    const Loc L = locate_cell(m, pos[mu]);
+    int64_t n0;
+    const MeshD m = mo.get(mu, n0);
+    Loc L = locate_cell(m, pos[mu]);
+    L.n0 += n0;
+    L.n1 += n0;
+    L.n2 += n0;
     const TM w0 = static_cast<TM>(L.w0), w1 = static_cast<TM>(L.w1), w2 = static_cast<TM>(L.w2);
 #pragma unroll
     for (int c = 0; c < (CC > 0 ? CC : CMAX); ++c) {
@@ -82,7 +104,7 @@ __global__ void __launch_bounds__(256) k_m2p(MeshD m, const TM* __restrict__ mv,
 }
 
 template <typename TM, typename TO>
-void launch_m2p(const MeshD& m, const void* mv, int C, const double* pos, int64_t N, void* out, hipStream_t s) {
+void launch_m2p(const MeshOf& m, const void* mv, int C, const double* pos, int64_t N, void* out, hipStream_t s) {
     const int blocks = static_cast<int>((N + 255) / 256);
     const TM* M = static_cast<const TM*>(mv);
     const double2* P = reinterpret_cast<const double2*>(pos);
@@ -98,14 +120,19 @@ void launch_m2p(const MeshD& m, const void* mv, int C, const double* pos, int64_
 
 // grad_mesh += phi_i(r_mu) g_mu (atomics); grad_pos[mu] += sum_c g_mu,c grad u_c
 template <typename TM>
-__global__ void __launch_bounds__(256) k_m2p_bwd(MeshD m, const TM* __restrict__ mv, int C,
+__global__ void __launch_bounds__(256) k_m2p_bwd(MeshOf mo, const TM* __restrict__ mv, int C,
                                                  const double2* __restrict__ pos, int64_t N,
                                                  const TM* __restrict__ gv, TM* __restrict__ gmesh,
                                                  double2* __restrict__ gpos) {
     const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mu >= N) return;
-    const Loc L = locate_cell(m, pos[mu]);
+    int64_t n0;
+    const MeshD m = mo.get(mu, n0);
+    Loc L = locate_cell(m, pos[mu]);
     if (!L.ok) return;
+    L.n0 += n0;
+    L.n1 += n0;
+    L.n2 += n0;
     // d(weights)/dxi and d/deta on the particle's triangle
     const double dxi0 = L.lower ? -1.0 : 0.0, dxi1 = 1.0, dxi2 = L.lower ? 0.0 : -1.0;
     const double det0 = L.lower ? 0.0 : -1.0, det1 = L.lower ? -1.0 : 0.0, det2 = 1.0;
@@ -134,9 +161,11 @@ __global__ void __launch_bounds__(256) k_m2p_bwd(MeshD m, const TM* __restrict__
 
 }  // namespace
 
-int m2p(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N, void* vals,
-        hipStream_t st) {
+int m2p(const MeshD& mesh, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C, int dtype,
+        const double* pos, int64_t N, void* vals, hipStream_t st) {
     PhaseTimer _timer(PH_M2P, st);
+    (void)n_nodes;
+    const MeshOf m{mesh, sets, S};
     if (dtype == P2M_F64)
         launch_m2p<double, double>(m, mesh_vals, C, pos, N, vals, st);
     else if (dtype == P2M_F32)
@@ -147,11 +176,13 @@ int m2p(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* p
     return P2M_OK;
 }
 
-int m2p_backward(const MeshD& m, const void* mesh_vals, int C, int dtype, const double* pos, int64_t N,
-                 const void* grad_vals, void* grad_mesh, double* grad_pos, hipStream_t st) {
+int m2p_backward(const MeshD& mesh, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C,
+                 int dtype, const double* pos, int64_t N, const void* grad_vals, void* grad_mesh, double* grad_pos,
+                 hipStream_t st) {
     PhaseTimer _timer(PH_M2P_BWD, st);
     const int blocks = static_cast<int>((N + 255) / 256);
-    const int64_t nn = static_cast<int64_t>(m.nx + 1) * (m.ny + 1);
+    const int64_t nn = n_nodes;
+    const MeshOf m{mesh, sets, S};
     const double2* P = reinterpret_cast<const double2*>(pos);
     double2* GP = reinterpret_cast<double2*>(grad_pos);
     if (dtype == P2M_F64) {

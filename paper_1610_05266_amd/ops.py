@@ -24,6 +24,10 @@ __all__ = [
     "p2m_project_backward",
     "p2m_build_weights_backward",
     "p2m_set_option",
+    "Batch",
+    "p2m_build_weights_batched",
+    "m2p_interpolate_batched",
+    "m2p_interpolate_backward_batched",
     "P2MError",
     "P2M_WEIGHTS_F32",
     "P2M_STRICT",
@@ -90,7 +94,8 @@ class Weights:
 
     def __init__(self):
         self._h = ctypes.c_void_p(0)
-        self.mesh: Optional[Mesh] = None
+        self.mesh: Optional[Mesh] = None   # None for a batched handle
+        self.n_nodes = 0
         self.N = 0
         self.flags = 0
         self.device = None
@@ -100,10 +105,6 @@ class Weights:
         if not self._h.value:
             raise ValueError("weights were never built")
         return self._h
-
-    @property
-    def n_nodes(self) -> int:
-        return self.mesh.n_nodes
 
     def diag(self, check_status: bool = True) -> dict:
         d = P2MDiag()
@@ -159,7 +160,7 @@ def p2m_build_weights(mesh, h: float, pos: torch.Tensor, flags: int = 0,
         rc = lib.p2m_build_weights(ctypes.byref(cm), float(h), _ptr(pos), pos.shape[0], int(flags),
                                    ctypes.byref(w._h), _stream(pos))
     check(rc)
-    w.mesh, w.N, w.flags, w.device = mesh, pos.shape[0], int(flags), pos.device
+    w.mesh, w.n_nodes, w.N, w.flags, w.device = mesh, mesh.n_nodes, pos.shape[0], int(flags), pos.device
     if check_diag:
         w.diag(check_status=True)
     return w
@@ -264,3 +265,101 @@ def p2m_build_weights_backward(w: Weights, pos: torch.Tensor, grad_w: torch.Tens
     with torch.cuda.device(pos.device):
         check(load().p2m_build_weights_backward(w.handle, _ptr(pos), _ptr(grad_w), _ptr(grad_pos), _stream(pos)))
     return grad_pos
+
+
+class Batch:
+    """Owner of a p2m_batch handle: S particle sets, each with its own mesh
+    and spacing h; set s owns particles offsets[s]:offsets[s+1] and mesh
+    nodes node_offsets[s]:node_offsets[s+1] of the concatenated arrays."""
+
+    def __init__(self, meshes, hs, offsets):
+        meshes = [Mesh.of(m) for m in meshes]
+        S = len(meshes)
+        if len(hs) != S or len(offsets) != S + 1:
+            raise ValueError("need S meshes, S spacings and S+1 offsets")
+        cm = (P2MMesh * S)(*[m.c() for m in meshes])
+        ch = (ctypes.c_double * S)(*[float(h) for h in hs])
+        co = (ctypes.c_int64 * (S + 1))(*[int(o) for o in offsets])
+        self._h = ctypes.c_void_p(0)
+        check(load().p2m_batch_create(cm, ch, S, co, ctypes.byref(self._h)))
+        nn, npart = ctypes.c_int64(), ctypes.c_int64()
+        no = (ctypes.c_int64 * (S + 1))()
+        check(load().p2m_batch_shape(self._h, ctypes.byref(nn), ctypes.byref(npart), no))
+        self.meshes = meshes
+        self.hs = [float(h) for h in hs]
+        self.offsets = [int(o) for o in offsets]
+        self.node_offsets = [int(v) for v in no]
+        self.S = S
+        self.n_nodes = int(nn.value)
+        self.N = int(npart.value)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def close(self):
+        if self._h.value:
+            load().p2m_batch_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def p2m_build_weights_batched(b: Batch, pos: torch.Tensor, flags: int = 0, weights: Optional[Weights] = None,
+                              check_diag: bool = True) -> Weights:
+    """Weights of every set of a batch in one pass (C call of the same name)."""
+    _need(pos, "pos", torch.float64, (b.N, 2))
+    w = weights if weights is not None else Weights()
+    with torch.cuda.device(pos.device):
+        rc = load().p2m_build_weights_batched(b.handle, _ptr(pos), int(flags), ctypes.byref(w._h), _stream(pos))
+    check(rc)
+    w.mesh, w.n_nodes, w.N, w.flags, w.device = None, b.n_nodes, b.N, int(flags), pos.device
+    if check_diag:
+        w.diag(check_status=True)
+    return w
+
+
+def m2p_interpolate_batched(b: Batch, mesh_vals: torch.Tensor, pos: torch.Tensor,
+                            out: Optional[torch.Tensor] = None, bf16_out: bool = False) -> torch.Tensor:
+    """m2p_interpolate over every set of a batch in one launch."""
+    _need(mesh_vals, "mesh_vals")
+    _need(pos, "pos", torch.float64, (b.N, 2))
+    if mesh_vals.dim() != 2 or mesh_vals.shape[0] != b.n_nodes:
+        raise ValueError(f"mesh_vals must have shape [{b.n_nodes}, C]")
+    C = mesh_vals.shape[1]
+    if mesh_vals.dtype == torch.float64:
+        code, odt = P2M_F64, torch.float64
+    elif mesh_vals.dtype == torch.float32:
+        code, odt = (P2M_BF16, torch.bfloat16) if bf16_out else (P2M_F32, torch.float32)
+    else:
+        raise ValueError("mesh_vals must be float64 or float32")
+    if out is None:
+        out = torch.empty((b.N, C), dtype=odt, device=pos.device)
+    _need(out, "out", odt, (b.N, C))
+    with torch.cuda.device(pos.device):
+        check(load().m2p_interpolate_batched(b.handle, _ptr(mesh_vals), C, code, _ptr(pos), _ptr(out),
+                                             _stream(pos)))
+    return out
+
+
+def m2p_interpolate_backward_batched(b: Batch, mesh_vals: Optional[torch.Tensor], pos: torch.Tensor,
+                                     grad_vals: torch.Tensor, want_mesh: bool = True,
+                                     grad_pos: Optional[torch.Tensor] = None):
+    """Adjoint of m2p_interpolate_batched: (grad_mesh or None, grad_pos or None)."""
+    _need(pos, "pos", torch.float64, (b.N, 2))
+    _need(grad_vals, "grad_vals")
+    C = grad_vals.shape[1]
+    code = P2M_F64 if grad_vals.dtype == torch.float64 else P2M_F32
+    mdt = _mesh_dtype(code)
+    gm = torch.empty((b.n_nodes, C), dtype=mdt, device=pos.device) if want_mesh else None
+    if grad_pos is not None:
+        _need(grad_pos, "grad_pos", torch.float64, tuple(pos.shape))
+        _need(mesh_vals, "mesh_vals", mdt, (b.n_nodes, C))
+    with torch.cuda.device(pos.device):
+        check(load().m2p_interpolate_backward_batched(b.handle, _ptr(mesh_vals), C, code, _ptr(pos),
+                                                      _ptr(grad_vals), _ptr(gm), _ptr(grad_pos), _stream(pos)))
+    return gm, grad_pos

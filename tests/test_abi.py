@@ -60,3 +60,27 @@ def test_options():
     assert lib.p2m_set_option(b"closure_radius", 0.5) == -1
     assert lib.p2m_set_option(b"nonsense", 1.0) == -1
     assert lib.p2m_set_option(b"region_h", 1000.0) == -1
+
+
+def test_batch_argument_validation_without_device():
+    lib = pkg.load()
+    out = ctypes.c_void_p(0)
+    M = _lib.P2MMesh * 2
+    H = ctypes.c_double * 2
+    O = ctypes.c_int64 * 3
+    meshes = M(_lib.P2MMesh(4, 4, 0.25, 0.0, 0.0), _lib.P2MMesh(2, 3, 0.5, 1.0, 0.0))
+    assert lib.p2m_batch_create(meshes, H(0.1, 0.2), 0, O(0, 10, 20), ctypes.byref(out)) == -1
+    assert lib.p2m_batch_create(None, H(0.1, 0.2), 2, O(0, 10, 20), ctypes.byref(out)) == -1
+    assert lib.p2m_batch_create(meshes, H(0.1, 0.2), 2, O(1, 10, 20), ctypes.byref(out)) == -1
+    assert lib.p2m_batch_create(meshes, H(0.1, 0.2), 2, O(0, 10, 12), ctypes.byref(out)) == -1
+    assert b"set 1" in lib.p2m_last_error()
+    assert lib.p2m_batch_create(meshes, H(0.1, -0.2), 2, O(0, 10, 20), ctypes.byref(out)) == -1
+    bad = M(_lib.P2MMesh(4, 4, 0.25, 0.0, 0.0), _lib.P2MMesh(2, 0, 0.5, 1.0, 0.0))
+    assert lib.p2m_batch_create(bad, H(0.1, 0.2), 2, O(0, 10, 20), ctypes.byref(out)) == -1
+    assert lib.p2m_batch_create(meshes, H(0.1, 0.2), 2, O(0, 10, 20), None) == -1
+    assert out.value is None
+    assert lib.p2m_build_weights_batched(None, ctypes.c_void_p(16), 0, ctypes.byref(out), None) == -1
+    assert lib.m2p_interpolate_batched(None, ctypes.c_void_p(16), 1, 0, ctypes.c_void_p(16),
+                                       ctypes.c_void_p(16), None) == -1
+    assert lib.p2m_batch_shape(None, None, None, None) == -1
+    lib.p2m_batch_destroy(None)
