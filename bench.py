@@ -132,22 +132,26 @@ def main(argv=None):
             ops.m2p_interpolate(mesh, mesh64, pos, out=out64)
 
     def timed(mixed):
+        import ctypes
+
         for _ in range(a.warmup):
             step(mixed)
         torch.cuda.synchronize()
-        lib.p2m_profile_enable(1)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
         e0.record()
         for _ in range(a.steps):
             step(mixed)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / a.steps
+        # per-phase GPU times from the library's own events, in a separate
+        # pass so that the event records do not perturb the timed loop
+        lib.p2m_profile_enable(1)
+        for _ in range(a.steps):
+            step(mixed)
+        torch.cuda.synchronize()
         phases = {}
-        import ctypes
-
         for ph in ("bin", "build", "project", "m2p", "build_fast", "build_slow", "weights"):
             tot, cnt = ctypes.c_double(), ctypes.c_int64()
             lib.p2m_profile_read(ph.encode(), ctypes.byref(tot), ctypes.byref(cnt))

@@ -86,6 +86,8 @@ typedef struct p2m_diag {
     int64_t bad_particles;      /* outside the mesh or non-finite (excluded)   */
     int64_t failed_nodes;       /* nodes left without weights (zero row)       */
     int64_t duplicate_pairs;    /* pairs of coincident particles (EGEOM)       */
+    int64_t slow_nodes;         /* nodes the register-resident first pass left
+                                   to the exact fallback (performance only)    */
     int32_t status;             /* P2M_OK, P2M_EDOMAIN, P2M_ECAP or P2M_EGEOM  */
     int32_t support_max;        /* largest support of any node                 */
 } p2m_diag;

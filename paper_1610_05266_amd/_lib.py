@@ -42,6 +42,7 @@ class P2MDiag(ctypes.Structure):
         ("bad_particles", c_int64),
         ("failed_nodes", c_int64),
         ("duplicate_pairs", c_int64),
+        ("slow_nodes", c_int64),
         ("status", c_int32),
         ("support_max", c_int32),
     ]

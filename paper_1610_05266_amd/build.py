@@ -42,8 +42,21 @@ def flags(debug: bool):
         "-I", CSRC,
         "-Wall",
         "-Wno-unused-function",
+        # a self-call left in a device helper is an endless loop the optimiser
+        # may delete together with everything after it
+        "-Werror=infinite-recursion",
+        "-Werror=uninitialized",
     ]
     return f
+
+
+def device_asm(src: str, out: str, debug: bool = False) -> str:
+    """gfx950 assembly of one source (device pass only), for inspection."""
+    cmd = [hipcc(), *flags(debug), "--cuda-device-only", "-S", os.path.join(CSRC, src), "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"device compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return out
 
 
 def compile_one(src: str, debug: bool) -> str:

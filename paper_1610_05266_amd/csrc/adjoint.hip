@@ -170,7 +170,7 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
     if (node >= a.w.n_nodes) return;
     const uint32_t meta = a.w.meta[node];
     const uint32_t type = meta_type(meta);
-    const int n = static_cast<int>(meta_cnt(meta));
+    const int n = row_len(meta);
     if (type == NT_FAILED || n == 0) return;
     const int64_t nn = a.w.n_nodes;
     const SetDesc& sd = a.w.sets[set_search(a.w.S, node, [&](int s) { return a.w.sets[s].n0; })];
@@ -284,7 +284,7 @@ __global__ void __launch_bounds__(256) k_export(WeightsView w, int32_t* __restri
     const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (node >= w.n_nodes) return;
     const uint32_t meta = w.meta[node];
-    const int n = static_cast<int>(meta_cnt(meta));
+    const int n = row_len(meta);
     const int64_t nn = w.n_nodes;
     for (int k = 0; k < KMAX; ++k) {
         if (idx) idx[k * nn + node] = k < n ? w.idx[k * nn + node] : -1;

@@ -130,6 +130,26 @@ __device__ __forceinline__ void circumcircle(const Key& k, double2 v, double2 a,
     rr = sqrt(ox * ox + oy * oy);
 }
 
+// Value of v in lane (lane ^ m) of the same group of W lanes (m < W).  For
+// quads the exchange is a DPP quad permute ([1,0,3,2] for m = 1, [2,3,0,1]
+// for m = 2) that needs no LDS round trip; the four lanes must be active.
+template <int W>
+__device__ __forceinline__ int lane_xor(int v, int m) {
+    if constexpr (W == 4) {
+        return m == 1 ? __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false)
+                      : __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    } else {
+        return __shfl_xor(v, m, W);
+    }
+}
+template <int W>
+__device__ __forceinline__ double lane_xor(double v, int m) {
+    const long long b = __double_as_longlong(v);
+    const int lo = lane_xor<W>(static_cast<int>(b), m);
+    const int hi = lane_xor<W>(static_cast<int>(b >> 32), m);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
 // Butterfly reductions over groups of W lanes: every lane of a group ends
 // with the same answer.  Near-ties met during the reduction are counted once
 // per pair (by its lower lane).
@@ -138,13 +158,13 @@ __device__ __forceinline__ void reduce_key(Key& best, Uid uid, int lane, int& nd
 #pragma unroll
     for (int m = 1; m < W; m <<= 1) {
         Key o;
-        o.t = __shfl_xor(best.t, m, W);
-        o.num = __shfl_xor(best.num, m, W);
-        o.cr = __shfl_xor(best.cr, m, W);
-        o.Nm = __shfl_xor(best.Nm, m, W);
-        o.Cm = __shfl_xor(best.Cm, m, W);
-        o.bx = __shfl_xor(best.bx, m, W);
-        o.by = __shfl_xor(best.by, m, W);
+        o.t = lane_xor<W>(best.t, m);
+        o.num = lane_xor<W>(best.num, m);
+        o.cr = lane_xor<W>(best.cr, m);
+        o.Nm = lane_xor<W>(best.Nm, m);
+        o.Cm = lane_xor<W>(best.Cm, m);
+        o.bx = lane_xor<W>(best.bx, m);
+        o.by = lane_xor<W>(best.by, m);
         int dummy = 0;
         if (key_better(o, best, uid, (lane & m) ? dummy : nd)) best = o;
     }
@@ -154,9 +174,9 @@ template <int W>
 __device__ __forceinline__ void reduce_nearest(double& d2, int& t, double2& p, const int32_t* perm) {
 #pragma unroll
     for (int m = 1; m < W; m <<= 1) {
-        const double od = __shfl_xor(d2, m, W);
-        const int ot = __shfl_xor(t, m, W);
-        const double ox = __shfl_xor(p.x, m, W), oy = __shfl_xor(p.y, m, W);
+        const double od = lane_xor<W>(d2, m);
+        const int ot = lane_xor<W>(t, m);
+        const double ox = lane_xor<W>(p.x, m), oy = lane_xor<W>(p.y, m);
         bool take = false;
         if (ot >= 0 && ot != t) {
             if (t < 0 || od < d2) take = true;
@@ -173,7 +193,7 @@ __device__ __forceinline__ void reduce_nearest(double& d2, int& t, double2& p, c
 template <int W>
 __device__ __forceinline__ double group_sum(double v) {
 #pragma unroll
-    for (int m = 1; m < W; m <<= 1) v += __shfl_xor(v, m, W);
+    for (int m = 1; m < W; m <<= 1) v += lane_xor<W>(v, m);
     return v;
 }
 
@@ -368,9 +388,9 @@ struct QuadSource {
         }
 #pragma unroll
         for (int m = 1; m < QL; m <<= 1) {
-            const int ot = __shfl_xor(bt, m, QL);
-            const double on = __shfl_xor(bn, m, QL), oc = __shfl_xor(bc, m, QL);
-            const double ox = __shfl_xor(bx, m, QL), oy = __shfl_xor(by, m, QL);
+            const int ot = lane_xor<QL>(bt, m);
+            const double on = lane_xor<QL>(bn, m), oc = lane_xor<QL>(bc, m);
+            const double ox = lane_xor<QL>(bx, m), oy = lane_xor<QL>(by, m);
             const double d = on * bc - bn * oc;
             const bool other = ot >= 0 && ot != bt;
             amb = amb || (other && bt >= 0 && fabs(d) <= errS);
@@ -382,8 +402,8 @@ struct QuadSource {
             by = take ? oy : by;
         }
         int am = amb ? 1 : 0;
-        am |= __shfl_xor(am, 1, QL);
-        am |= __shfl_xor(am, 2, QL);
+        am |= lane_xor<QL>(am, 1);
+        am |= lane_xor<QL>(am, 2);
         Key k;
         k.t = am ? -2 : bt;
         k.num = bn;
@@ -409,7 +429,7 @@ struct Support {
         for (int k = lane; k < n; k += W)
             if (static_cast<int>(static_cast<uint32_t>(u[k]) & IDX_MASK) == t) f = k;
 #pragma unroll
-        for (int m = 1; m < W; m <<= 1) f = max(f, __shfl_xor(f, m, W));
+        for (int m = 1; m < W; m <<= 1) f = max(f, lane_xor<W>(f, m));
         return f;
     }
     __device__ bool add(int t, int bit) {
@@ -688,9 +708,8 @@ __device__ bool chol6(double G[6][6]) {
 #pragma unroll
         for (int k = 0; k < j; ++k) d -= G[j][k] * G[j][k];
         if (!(d > 1e-12 * djj)) return false;
-        const double r = sqrt(d);
-        G[j][j] = r;
-        const double ir = 1.0 / r;
+        const double ir = 1.0 / sqrt(d);
+        G[j][j] = ir;  // the diagonal keeps 1 / L_jj
 #pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double s = G[i][j];
@@ -709,14 +728,14 @@ __device__ void chol6_solve(const double L[6][6], const double b[6], double y[6]
         double s = b[i];
 #pragma unroll
         for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
-        z[i] = s / L[i][i];
+        z[i] = s * L[i][i];
     }
 #pragma unroll
     for (int i = 5; i >= 0; --i) {
         double s = z[i];
 #pragma unroll
         for (int k = i + 1; k < 6; ++k) s -= L[k][i] * y[k];
-        y[i] = s / L[i][i];
+        y[i] = s * L[i][i];
     }
 }
 
@@ -780,8 +799,8 @@ __device__ void pinv6_solve(const Moments& mo, const double b[6], double y[6]) {
 // Sum over the four lanes of a quad; every lane gets the same bits
 // ((a+b)+(c+d) in all lanes, as FP addition is commutative).
 __device__ __forceinline__ double quad_sum(double v) {
-    v += __shfl_xor(v, 1, QL);
-    v += __shfl_xor(v, 2, QL);
+    v += lane_xor<QL>(v, 1);
+    v += lane_xor<QL>(v, 2);
     return v;
 }
 
@@ -850,8 +869,8 @@ __device__ void quad_weights(const KArgs& a, int64_t node, double2 q, UGet uget,
             }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        lt[k] = max(lt[k], __shfl_xor(lt[k], 1, QL));
-        lt[k] = max(lt[k], __shfl_xor(lt[k], 2, QL));
+        lt[k] = max(lt[k], lane_xor<QL>(lt[k], 1));
+        lt[k] = max(lt[k], lane_xor<QL>(lt[k], 2));
     }
     for (int e = 0; e < 3; ++e) {
         const int pa = e, pb = (e + 1) % 3;
@@ -1037,12 +1056,15 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
         g.pos = a.pos_s;
         g.perm = a.perm;
         g.q = node_pos(sd.m, i, j);
-        g.Rf = ring ? sd.Rc : sd.Rf;
+        // a corner node sees a quarter disk, an edge node a half disk: the
+        // corner radius is sqrt(2) larger for the same expected count
+        const bool corner = (i == 0 || i == sd.m.nx) && (j == 0 || j == sd.m.ny);
+        g.Rf = ring ? (corner ? sd.Rc * 1.4142135623730951 : sd.Rc) : sd.Rf;
         g.n = 0;
         g.lane = lane;
         // gather the particles within the radius, round-robin over the lanes
         const double R2 = g.Rf * g.Rf;
-        const int hw = ring ? sd.hwc : sd.hwf;
+        const int hw = ring ? (corner ? static_cast<int>(ceil(g.Rf / sd.g.bw)) : sd.hwc) : sd.hwf;
         const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
         const int bx0 = max(cbx - hw, 0), bx1 = min(cbx + hw, sd.g.nbx);
         const int by0 = max(cby - hw, 0), by1 = min(cby + hw, sd.g.nby);
@@ -1070,8 +1092,8 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
             }
             flat += e - s;
         }
-        ovf |= __shfl_xor(ovf, 1, QL);
-        ovf |= __shfl_xor(ovf, 2, QL);
+        ovf |= lane_xor<QL>(ovf, 1);
+        ovf |= lane_xor<QL>(ovf, 2);
         if (!ovf && !ring) {
             int T[3] = {0, 0, 0};
             Support<QL> S;
@@ -1112,8 +1134,8 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
                 }
 #pragma unroll
                 for (int m = 1; m < QL; m <<= 1) {
-                    const double od = __shfl_xor(bd, m, QL);
-                    const int ot = __shfl_xor(bt, m, QL);
+                    const double od = lane_xor<QL>(bd, m);
+                    const int ot = lane_xor<QL>(bt, m);
                     if (ot >= 0 && ot != bt && (bt < 0 || od < bd || (od == bd && a.perm[ot] < a.perm[bt]))) {
                         bd = od;
                         bt = ot;
@@ -1137,6 +1159,9 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
         }
     }
     if (valid && !done && lane == 0) {
+        // an empty row until the slow path writes it, so that no node is ever
+        // left with the metadata of an earlier build (or of fresh memory)
+        a.out.meta[node] = meta_pack(NT_FAILED, 0, 0, 0, 0, 0u);
         const int slot = static_cast<int>(atomicAdd(&a.diag[D_SLOWCNT], 1ull));
         a.slow[slot] = static_cast<int32_t>(node);
     }
@@ -1284,8 +1309,18 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
 }
 
 // Weights of every pending row (interior or closure, from either path), one
-// quad per node, nodes in the same 8 x 8 tiles as the fast kernel.
+// quad per node, nodes in the same 8 x 8 tiles as the fast kernel.  Lanes
+// 0..2 of a quad each own one edge system of the node's triangle (moments,
+// Cholesky, one refinement step), lane 3 the barycentric part; the weights
+// are quad sums per support entry.  The support's positions are staged in
+// LDS.  A node with a rank-deficient system is left pending and listed for
+// k_weights_rd (pseudo-inverse), which keeps this kernel's registers low.
+constexpr int SK = 16;  // support entries staged in LDS per node
+
 __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
+    __shared__ double2 sp[QPB * SK];
+    __shared__ uint32_t se[QPB * SK];
+    __shared__ int32_t su[QPB * SK];
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const SetDesc sd = tile_set(a, blockIdx.x);
@@ -1298,31 +1333,233 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     const uint32_t meta = valid ? a.out.meta[node] : 0u;
     const uint32_t type = valid ? meta_type(meta) : NT_FAILED;
     const int n = static_cast<int>(meta_cnt(meta));
-    if (type == NT_PENDING) {
-        int T[3];
+    const bool pend = type == NT_PENDING;
+    const bool clos = type == NT_PEND_RING || type == NT_PEND_OUT;
+    // stage the support: entry (sorted index | ring bits << 28), position and
+    // user id; the loads of all slots are issued before any is waited for
+    {
+        constexpr int SS = SK / QL;
+        uint32_t e[SS];
+        const int ns = (pend || clos) ? min(n, SK) : 0;
 #pragma unroll
-        for (int k = 0; k < 3; ++k) T[k] = a.out.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + node];
-        auto uget = [&](int k) {
-            return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + node]) |
-                                        (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28));
-        };
-        quad_weights(a, node, node_pos(sd.m, i, j), uget, n, T, lane, meta_flags(meta));
-    } else if (type == NT_PEND_RING || type == NT_PEND_OUT) {
-        quad_closure(a, node, node_pos(sd.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
-                     meta_flags(meta));
+        for (int s = 0; s < SS; ++s) {
+            const int k = s * QL + lane;
+            e[s] = 0;
+            if (k < ns)
+                e[s] = static_cast<uint32_t>(a.out.idx[k * nn + node]) |
+                       (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28);
+        }
+        double2 pp[SS];
+        int32_t uu[SS];
+#pragma unroll
+        for (int s = 0; s < SS; ++s) {
+            const int k = s * QL + lane;
+            if (k < ns) {
+                pp[s] = a.pos_s[e[s] & IDX_MASK];
+                uu[s] = a.perm[e[s] & IDX_MASK];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < SS; ++s) {
+            const int k = s * QL + lane;
+            if (k < ns) {
+                se[qi * SK + k] = e[s];
+                sp[qi * SK + k] = pp[s];
+                su[qi * SK + k] = uu[s];
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // f(k, entry, position, user id) over the support: staged slots from LDS,
+    // the rest (rare) from global memory, in two loops so that neither
+    // needs a generic (flat) address
+    auto each = [&](auto&& f) {
+        const int ns = min(n, SK);
+        for (int k = 0; k < ns; ++k) f(k, se[qi * SK + k], sp[qi * SK + k], su[qi * SK + k]);
+        for (int k = SK; k < n; ++k) {
+            const uint32_t e = static_cast<uint32_t>(a.out.idx[k * nn + node]) |
+                               (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28);
+            f(k, e, a.pos_s[e & IDX_MASK], a.perm[e & IDX_MASK]);
+        }
+    };
+    auto P = [&](int k) -> double2 {
+        if (k < SK) return sp[qi * SK + k];
+        return a.pos_s[a.out.idx[k * nn + node]];
+    };
+    const double2 q = node_pos(sd.m, i, j);
+    int ok = 1;
+    double y[6] = {0, 0, 0, 0, 0, 0};
+    // edge / closure frame: x~ = (p - c) * s
+    double cx = 0.0, cy = 0.0, sc = 1.0, coef = 0.0;
+    int mask = 0;
+    double phi[3] = {0, 0, 0};
+    int lt[3] = {0, 0, 0};
+    if (pend) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lt[k] = static_cast<int>(meta_t(meta, k));
+        const double2 P0 = P(lt[0]), P1 = P(lt[1]), P2 = P(lt[2]);
+        // barycentric coordinates of q in T (linear FE, eqs. C0, C1)
+        const double D = orient(P0, P1, P2);
+        phi[0] = orient(q, P1, P2) / D;
+        phi[1] = orient(P0, q, P2) / D;
+        phi[2] = orient(P0, P1, q) / D;
+        if (lane < 3) {
+            const int pb = lane == 2 ? 0 : lane + 1;
+            const double2 rn = lane == 0 ? P0 : (lane == 1 ? P1 : P2);
+            const double2 rs = pb == 0 ? P0 : (pb == 1 ? P1 : P2);
+            cx = 0.5 * (rn.x + rs.x);
+            cy = 0.5 * (rn.y + rs.y);
+            const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
+            sc = 1.0 / sqrt(dxv * dxv + dyv * dyv);
+            mask = (1 << lane) | (1 << pb);
+            coef = 2.0 * phi[lane] * phi[pb];
+            const double dx = dxv * sc, dy = dyv * sc;
+            // eq. A2_2 in the edge frame (eqs. A0, A1 give the zero rows)
+            const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
+            Moments mo;
+            mo.zero();
+            each([&](int, uint32_t e, double2 p, int32_t) {
+                if ((e >> 28) & mask) mo.add((p.x - cx) * sc, (p.y - cy) * sc);
+            });
+            double L[6][6];
+            mo.gram(L);
+            ok = chol6(L) ? 1 : 0;
+            if (ok) {
+                chol6_solve(L, b, y);
+                double r[6] = {0, 0, 0, 0, 0, 0};
+                each([&](int, uint32_t e, double2 p, int32_t) {
+                    if (!((e >> 28) & mask)) return;
+                    double pm[6];
+                    monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
+                    const double A = dot6(pm, y);
+#pragma unroll
+                    for (int t = 0; t < 6; ++t) r[t] += A * pm[t];
+                });
+#pragma unroll
+                for (int t = 0; t < 6; ++t) r[t] = b[t] - r[t];
+                double d[6];
+                chol6_solve(L, r, d);
+#pragma unroll
+                for (int t = 0; t < 6; ++t) y[t] += d[t];
+            }
+        }
+    } else if (clos && lane == 0) {
+        // minimum-norm quadratic moment conditions over the nearest
+        // particles, centred at their centroid and scaled by their RMS radius
+        each([&](int, uint32_t, double2 p, int32_t) {
+            cx += p.x;
+            cy += p.y;
+        });
+        cx /= n;
+        cy /= n;
+        double r2 = 0.0;
+        each([&](int, uint32_t, double2 p, int32_t) { r2 += (p.x - cx) * (p.x - cx) + (p.y - cy) * (p.y - cy); });
+        sc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
+        Moments mo;
+        mo.zero();
+        each([&](int, uint32_t, double2 p, int32_t) { mo.add((p.x - cx) * sc, (p.y - cy) * sc); });
+        double b[6];
+        monos((q.x - cx) * sc, (q.y - cy) * sc, b);
+        double L[6][6];
+        mo.gram(L);
+        ok = chol6(L) ? 1 : 0;
+        if (ok) {
+            chol6_solve(L, b, y);
+            double r[6] = {0, 0, 0, 0, 0, 0};
+            each([&](int, uint32_t, double2 p, int32_t) {
+                double pm[6];
+                monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
+                const double A = dot6(pm, y);
+#pragma unroll
+                for (int t = 0; t < 6; ++t) r[t] += A * pm[t];
+            });
+#pragma unroll
+            for (int t = 0; t < 6; ++t) r[t] = b[t] - r[t];
+            double d[6];
+            chol6_solve(L, r, d);
+#pragma unroll
+            for (int t = 0; t < 6; ++t) y[t] += d[t];
+        }
+        coef = 1.0;
+    }
+    ok = min(ok, lane_xor<QL>(ok, 1));
+    ok = min(ok, lane_xor<QL>(ok, 2));
+    if ((pend || clos) && !ok) {
+        // rank-deficient: the row stays pending for k_weights_rd
+        if (lane == 0) {
+            const int slot = static_cast<int>(atomicAdd(&a.diag[D_RDCNT], 1ull));
+            a.slow[slot] = static_cast<int32_t>(node);
+        }
+    } else if (pend || clos) {
+        // w_k = phi-part (lane 3) + sum over the edges (lanes 0..2) of
+        // 2 phi_nu phi_sigma A_{e,k}; closure: lane 0 alone
+        each([&](int k, uint32_t e, double2 p, int32_t u) {
+            double c = 0.0;
+            if (pend && lane == 3) {
+                c = (k == lt[0] ? phi[0] : 0.0) + (k == lt[1] ? phi[1] : 0.0) + (k == lt[2] ? phi[2] : 0.0);
+            } else if (clos ? lane == 0 : (lane < 3 && ((e >> 28) & mask))) {
+                double pm[6];
+                monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
+                c = coef * dot6(pm, y);
+            }
+            const double w = quad_sum(c);
+            if (lane == (k & (QL - 1))) {
+                a.out.idx[k * nn + node] = u;
+                a.out.w64[k * nn + node] = w;
+                if (a.out.w32) a.out.w32[k * nn + node] = static_cast<float>(w);
+                a.out.mem[k * nn + node] = clos ? 0 : static_cast<uint8_t>(e >> 28);
+            }
+        });
+        if (lane == 0) {
+            const uint32_t ft = pend ? NT_INTERIOR : (type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING);
+            a.out.meta[node] = pend ? meta_pack(ft, n, lt[0], lt[1], lt[2], meta_flags(meta))
+                                    : meta_pack(ft, n, 0, 0, 0, meta_flags(meta));
+        }
     }
     // diagnostics: one count per quad (lane 0), one atomic per wave
     const bool q0 = lane == 0;
-    const unsigned long long inter = __ballot(q0 && type == NT_PENDING);
-    const unsigned long long clos = __ballot(q0 && (type == NT_PEND_RING || type == NT_PEND_OUT));
+    const unsigned long long inter = __ballot(q0 && pend);
+    const unsigned long long cl = __ballot(q0 && clos);
     const unsigned long long outs = __ballot(q0 && type == NT_PEND_OUT);
-    int sup = (type == NT_PENDING || type == NT_PEND_RING || type == NT_PEND_OUT) ? n : 0;
+    int sup = (pend || clos) ? n : 0;
     for (int off = 32; off > 0; off >>= 1) sup = max(sup, __shfl_xor(sup, off));
     if (threadIdx.x % WAVE == 0) {
         if (inter) atomicAdd(&a.diag[D_INTERIOR], static_cast<unsigned long long>(__popcll(inter)));
-        if (clos) atomicAdd(&a.diag[D_CLOSURE], static_cast<unsigned long long>(__popcll(clos)));
+        if (cl) atomicAdd(&a.diag[D_CLOSURE], static_cast<unsigned long long>(__popcll(cl)));
         if (outs) atomicAdd(&a.diag[D_OUTSIDE], static_cast<unsigned long long>(__popcll(outs)));
         if (sup) atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(sup));
+    }
+}
+
+// Nodes whose moment systems are rank-deficient (listed by k_weights): the
+// minimum-norm solution through the pseudo-inverse, one quad per node.
+__global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
+    const int lane = threadIdx.x & (QL - 1);
+    const int count = static_cast<int>(a.diag[D_RDCNT]);
+    const int64_t nn = a.n_nodes;
+    for (int li = (blockIdx.x * QWG + threadIdx.x) / QL; li < count; li += gridDim.x * (QWG / QL)) {
+        const int64_t node = a.slow[li];
+        const SetDesc sd = node_set(a, node);
+        const int64_t ln = node - sd.n0;
+        const int i = static_cast<int>(ln % (sd.m.nx + 1)), j = static_cast<int>(ln / (sd.m.nx + 1));
+        const uint32_t meta = a.out.meta[node];
+        const uint32_t type = meta_type(meta);
+        const int n = static_cast<int>(meta_cnt(meta));
+        if (type == NT_PENDING) {
+            int T[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) T[k] = a.out.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + node];
+            auto uget = [&](int k) {
+                return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + node]) |
+                                            (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28));
+            };
+            quad_weights(a, node, node_pos(sd.m, i, j), uget, n, T, lane, meta_flags(meta));
+        } else {
+            quad_closure(a, node, node_pos(sd.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
+                         meta_flags(meta));
+        }
     }
 }
 
@@ -1362,6 +1599,8 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     {
         PhaseTimer t3(PH_WEIGHTS, st);
         k_weights<<<tiles, QWG, 0, st>>>(a);
+        // rank-deficient nodes (normally none): a small grid loops over the list
+        k_weights_rd<<<16, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());
     return P2M_OK;

@@ -483,6 +483,7 @@ int p2m_weights_diag(const p2m_weights* w, p2m_diag* d, void* stream) {
     d->failed_nodes = static_cast<int64_t>(h[D_FAILED]);
     d->support_max = static_cast<int32_t>(h[D_SUPMAX]);
     d->duplicate_pairs = static_cast<int64_t>(h[D_DUP]);
+    d->slow_nodes = static_cast<int64_t>(h[D_SLOWCNT]);
     int status = P2M_OK;
     if (d->bad_particles) {
         status = P2M_EDOMAIN;

@@ -37,6 +37,7 @@ enum DiagIdx : int {
     D_SUPMAX,
     D_DUP,
     D_SLOWCNT,  // length of the slow-path node list
+    D_RDCNT,    // length of the rank-deficient node list (weights kernel)
     D_COUNT
 };
 
@@ -59,6 +60,11 @@ __host__ __device__ inline uint32_t meta_pack(uint32_t type, uint32_t cnt, uint3
 }
 __host__ __device__ inline uint32_t meta_type(uint32_t m) { return m & 7u; }
 __host__ __device__ inline uint32_t meta_cnt(uint32_t m) { return (m >> 3) & 63u; }
+// Row length for readers of finished rows: never beyond the ELL width.
+__host__ __device__ inline int row_len(uint32_t m) {
+    const int n = static_cast<int>((m >> 3) & 63u);
+    return n < KMAX ? n : KMAX;
+}
 __host__ __device__ inline uint32_t meta_t(uint32_t m, int k) { return (m >> (9 + 5 * k)) & 31u; }
 constexpr uint32_t MF_NEARDEG = 1u, MF_RANKDEF = 2u, MF_ESCALATED = 4u, MF_GLOBAL = 8u;
 __host__ __device__ inline uint32_t meta_flags(uint32_t m) { return m >> 24; }

@@ -31,7 +31,7 @@ __global__ void __launch_bounds__(256) k_project(const uint32_t* __restrict__ me
     TW acc[CC > 0 ? CC : CMAX];
 #pragma unroll
     for (int c = 0; c < (CC > 0 ? CC : CMAX); ++c) acc[c] = TW(0);
-    const int cnt = static_cast<int>(meta_cnt(meta[node]));
+    const int cnt = row_len(meta[node]);
     for (int k = 0; k < cnt; ++k) {
         const int64_t j = idx[k * n_nodes + node];
         const TW wk = w[k * n_nodes + node];
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(const uint32_t* __restrict_
                                                      double* __restrict__ gw) {
     const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (node >= n_nodes) return;
-    const int cnt = static_cast<int>(meta_cnt(meta[node]));
+    const int cnt = row_len(meta[node]);
     TG g[CMAX];
     for (int c = 0; c < C; ++c) g[c] = gmesh[node * C + c];
     for (int k = 0; k < cnt; ++k) {

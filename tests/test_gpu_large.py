@@ -89,29 +89,38 @@ def test_c4_full_backward_sampled_against_oracle(c4):
     nodes = np.union1d(_nodes_near(om, c.pos[parts], 2.5 * om.H),
                        _nodes_near(om, om.nodes()[snodes], 3.5 * om.H))
     W, _ = orc.matrix(nodes)
-    f, g = c.extra["f_mesh"], c.extra["g_mesh"]
-    a = o_m2p(om, f, c.pos)
-    out = W @ a
-    r = out - g[nodes]
-    assert_close(out64[nodes], out, 1e-12, "C4 P2M(M2P f) at sampled nodes, FP64")
-    assert_close(out32[nodes], out, 1e-5, "C4 P2M(M2P f) at sampled nodes, mixed")
-    abar = W.T @ r
-    g_p2m = o_p2m_grad_pos(orc, a, r, node_ids=nodes)[parts]
-    g_m2p = o_m2p_grad_pos(om, f, c.pos[parts], abar[parts])
-    gp = g_p2m + g_m2p
-    # The weight term and the M2P term of dL/dpos nearly cancel (P2M(M2P f)
-    # follows f as particles move), by about three orders of magnitude here,
-    # so the error is measured against the size of the two terms.
-    scale = np.abs(g_p2m) + np.abs(g_m2p)
-    for got, tol, what in ((gp64, 1e-10, "FP64"), (gp32, 1e-5, "mixed")):
-        d = got[parts] - gp
-        assert np.linalg.norm(d) <= tol * np.linalg.norm(scale), f"C4 dL/dpos {what}: normwise"
-        assert np.abs(d).max() <= tol * scale.max(), f"C4 dL/dpos {what}: max"
-    assert_close(gp64[parts], gp, 1e-7, "C4 dL/dpos, FP64, relative to the sum")
+    g = c.extra["g_mesh"]
+    f64 = c.extra["f_mesh"]
+    # the mixed path's reference is the oracle on its FP32-rounded mesh input:
+    # the interpolant's gradient differences f over one cell, which turns the
+    # input rounding alone into ~1e-5 relative error
+    f32 = f64.astype(np.float32).astype(np.float64)
     near = np.flatnonzero(np.asarray(abs(m2p_matrix(om, c.pos)[:, snodes]).sum(1)).ravel() > 0)
-    gf = m2p_matrix(om, c.pos[near])[:, snodes].T @ abar[near]
-    assert_close(gf64[snodes], gf, 1e-10, "C4 dL/df, FP64")
-    assert_close(gf32[snodes], gf, 1e-5, "C4 dL/df, mixed")
+    for f, out_g, gp_g, gf_g, tol, what in ((f64, out64, gp64, gf64, 1e-12, "FP64"),
+                                           (f32, out32, gp32, gf32, 1e-5, "mixed")):
+        a = o_m2p(om, f, c.pos)
+        out = W @ a
+        r = out - g[nodes]
+        assert_close(out_g[nodes], out, tol, f"C4 P2M(M2P f) at sampled nodes, {what}")
+        abar = W.T @ r
+        g_p2m = o_p2m_grad_pos(orc, a, r, node_ids=nodes)[parts]
+        g_m2p = o_m2p_grad_pos(om, f, c.pos[parts], abar[parts])
+        gp = g_p2m + g_m2p
+        # The weight term and the M2P term of dL/dpos nearly cancel (P2M(M2P f)
+        # follows f as particles move), by about three orders of magnitude
+        # here, so the error is measured against the size of the two terms.
+        # FP32 sums leave out with ~1e-7 absolute error; the residual r is
+        # several times smaller than out, which scales its relative error
+        # (and every gradient formed from it) by |out| / |r|.
+        cond = max(1.0, np.abs(out).max() / np.abs(r).max())
+        gtol = 1e-10 if what == "FP64" else 1e-5 * cond
+        print(f"C4 {what}: residual conditioning {cond:.2f}, gradient tolerance {gtol:.2e}", flush=True)
+        scale = np.abs(g_p2m) + np.abs(g_m2p)
+        d = gp_g[parts] - gp
+        assert np.linalg.norm(d) <= gtol * np.linalg.norm(scale), f"C4 dL/dpos {what}: normwise"
+        assert np.abs(d).max() <= gtol * scale.max(), f"C4 dL/dpos {what}: max"
+        gf = m2p_matrix(om, c.pos[near])[:, snodes].T @ abar[near]
+        assert_close(gf_g[snodes], gf, gtol, f"C4 dL/df, {what}")
 
 
 def test_c4_full_size_properties(c4):
