@@ -37,6 +37,8 @@ def parse(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the sampled oracle comparison")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="launch every step from the host instead of replaying a captured HIP graph")
     ap.add_argument("--cpu-side", type=float, default=1.0,
                     help="side of the sub-square of the workload the CPU oracle is timed on")
     return ap.parse_args(argv)
@@ -131,22 +133,82 @@ def main(argv=None):
             ops.p2m_project(w, v64, out=mesh64)
             ops.m2p_interpolate(mesh, mesh64, pos, out=out64)
 
-    def timed(mixed):
-        import ctypes
+    def eager_cached(mixed):
+        if mixed:
+            ops.p2m_project(w, v32, out=mesh32)
+            ops.m2p_interpolate(mesh, mesh32, pos, out=out32)
+        else:
+            ops.p2m_project(w, v64, out=mesh64)
+            ops.m2p_interpolate(mesh, mesh64, pos, out=out64)
 
+    graph_notes = []
+
+    def as_graph(fn):
+        """fn captured as a HIP graph (replays without host launch overhead),
+        or fn itself when graphs are off or capture fails."""
+        if a.no_graph:
+            return fn
+        try:
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                fn()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn()
+            torch.cuda.synchronize()
+            graphs.append(g)
+            return g.replay
+        except Exception as exc:  # noqa: BLE001 - report and time eagerly
+            graph_notes.append(f"graph capture failed ({exc}); eager launches timed")
+            torch.cuda.synchronize()
+            return fn
+
+    graphs = []
+
+    def check_replay(run, fn, outs):
+        """Every replay must reproduce the eager step bit for bit."""
+        fn()
+        torch.cuda.synchronize()
+        ref = [o.clone() for o in outs]
+        for _ in range(3):
+            run()
+            torch.cuda.synchronize()
+            for o, r in zip(outs, ref):
+                if not torch.equal(o, r):
+                    raise RuntimeError("graph replay differs from the eager step")
+            fn()
+            torch.cuda.synchronize()
+
+    def time_loop(run):
         for _ in range(a.warmup):
-            step(mixed)
+            run()
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(a.steps):
-            step(mixed)
+            run()
         e1.record()
         torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / a.steps
+        return e0.elapsed_time(e1) / a.steps
+
+    def timed(mixed):
+        import ctypes
+
+        fn = (lambda: step(mixed))
+        run = as_graph(fn)
+        if run is not fn:
+            try:
+                check_replay(run, fn, [mesh32, out32] if mixed else [mesh64, out64])
+            except RuntimeError as exc:
+                graph_notes.append(f"{exc}; eager launches timed")
+                run = fn
+        ms = time_loop(run)
         # per-phase GPU times from the library's own events, in a separate
-        # pass so that the event records do not perturb the timed loop
+        # eager pass so that the event records do not perturb the timed loop
         lib.p2m_profile_enable(1)
         for _ in range(a.steps):
             step(mixed)
@@ -159,12 +221,28 @@ def main(argv=None):
         lib.p2m_profile_enable(0)
         return ms, phases
 
+    def cached(mixed):
+        """P2M + M2P with the weights of the last build (no rebuild)."""
+        fn = (lambda: eager_cached(mixed))
+        run = as_graph(fn)
+        if run is not fn:
+            try:
+                check_replay(run, fn, [mesh32, out32] if mixed else [mesh64, out64])
+            except RuntimeError as exc:
+                graph_notes.append(f"{exc}; eager launches timed")
+                run = fn
+        return time_loop(run)
+
     log("timing FP64 form")
     ms64, ph64 = timed(False)
     log(f"FP64 {ms64:.4f} ms/step phases {ph64}")
     log("timing mixed form")
     ms32, ph32 = timed(True)
     log(f"mixed {ms32:.4f} ms/step phases {ph32}")
+    # the weights handle now holds the mixed build (FP64 and FP32 weights)
+    cms32 = cached(True)
+    cms64 = cached(False)
+    log(f"cached weights: mixed {cms32:.4f} ms, FP64 {cms64:.4f} ms per round trip")
     torch.cuda.synchronize()
 
     # accuracy of the mixed form against the FP64 form (both full outputs)
@@ -206,6 +284,16 @@ def main(argv=None):
     rt64 = {"algorithmic_bytes": b64, "achieved_GBs": round(b64 / (ms64 * 1e-3) / 1e9, 2),
             "frac": round(b64 / (ms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
 
+    cached_rt = {
+        "note": "P2M + M2P with the weights of the last build (no rebuild); same algorithmic bytes",
+        "mixed": {"ms_per_step": round(cms32, 5), "Mparticles_per_s": round(N / (cms32 * 1e-3) / 1e6, 3),
+                  "achieved_GBs": round(b32 / (cms32 * 1e-3) / 1e9, 2),
+                  "frac": round(b32 / (cms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
+        "fp64": {"ms_per_step": round(cms64, 5), "Mparticles_per_s": round(N / (cms64 * 1e-3) / 1e6, 3),
+                 "achieved_GBs": round(b64 / (cms64 * 1e-3) / 1e9, 2),
+                 "frac": round(b64 / (cms64 * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)},
+    }
+
     cpu = None
     if not a.no_cpu_baseline:
         log("timing the CPU oracle")
@@ -230,6 +318,9 @@ def main(argv=None):
                                "every step", "particles": N, "nodes": nn, "channels": C},
         "roofline": roof,
         "round_trip_hbm": rt,
+        "cached_weights": cached_rt,
+        "launch": "eager" if (a.no_graph or graph_notes) else "HIP graph replay of the whole step",
+        "launch_notes": graph_notes,
         "cpu_baseline": cpu,
         "fp64": {"value": round(N / (ms64 * 1e-3) / 1e6, 3), "ms_per_step": round(ms64, 5),
                  "round_trip_hbm": rt64, "phases_ms": {k: round(v, 5) for k, v in ph64.items()}},

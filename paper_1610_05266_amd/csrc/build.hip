@@ -60,6 +60,7 @@ constexpr int NS = 10;         // candidate slots per lane (fast kernel)
 constexpr int QWG = 256;       // quad kernels: 64 nodes per block
 constexpr int QPB = QWG / QL;
 constexpr int MS = KMAX / QL;  // support entries per lane
+constexpr int KPITCH = KMAX + 1;  // LDS row pitch of per-quad support lists
 constexpr uint32_t IDX_MASK = 0x0fffffffu;
 
 enum Result : int { R_OK = 0, R_MORE = 1, R_OUTSIDE = 2, R_FAIL = 3, R_CAP = 4 };
@@ -130,26 +131,6 @@ __device__ __forceinline__ void circumcircle(const Key& k, double2 v, double2 a,
     rr = sqrt(ox * ox + oy * oy);
 }
 
-// Value of v in lane (lane ^ m) of the same group of W lanes (m < W).  For
-// quads the exchange is a DPP quad permute ([1,0,3,2] for m = 1, [2,3,0,1]
-// for m = 2) that needs no LDS round trip; the four lanes must be active.
-template <int W>
-__device__ __forceinline__ int lane_xor(int v, int m) {
-    if constexpr (W == 4) {
-        return m == 1 ? __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false)
-                      : __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
-    } else {
-        return __shfl_xor(v, m, W);
-    }
-}
-template <int W>
-__device__ __forceinline__ double lane_xor(double v, int m) {
-    const long long b = __double_as_longlong(v);
-    const int lo = lane_xor<W>(static_cast<int>(b), m);
-    const int hi = lane_xor<W>(static_cast<int>(b >> 32), m);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
-}
-
 // Butterfly reductions over groups of W lanes: every lane of a group ends
 // with the same answer.  Near-ties met during the reduction are counted once
 // per pair (by its lower lane).
@@ -188,6 +169,82 @@ __device__ __forceinline__ void reduce_nearest(double& d2, int& t, double2& p, c
             p = make_double2(ox, oy);
         }
     }
+}
+
+// ---- whole-wave selections by ballot -------------------------------------
+// A wave-wide argmin needs the butterfly only to agree on a value: the
+// minimum of one double is found first, the lanes that might tie it are
+// singled out by a ballot, and the winner is read from its lane.  The full
+// exact butterfly runs only when a near-tie is possible.
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int m = 1; m < WAVE; m <<= 1) v = fmin(v, lane_xor<WAVE>(v, m));
+    return v;
+}
+__device__ __forceinline__ int read_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double read_lane(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
+    const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ Key read_key(const Key& k, int l) {
+    Key o;
+    o.t = read_lane(k.t, l);
+    o.num = read_lane(k.num, l);
+    o.cr = read_lane(k.cr, l);
+    o.Nm = read_lane(k.Nm, l);
+    o.Cm = read_lane(k.Cm, l);
+    o.bx = read_lane(k.bx, l);
+    o.by = read_lane(k.by, l);
+    return o;
+}
+
+// Exact wave argmin of bisector keys (key_better order).  The lane whose
+// rounded quotient num/cr is smallest is the answer unless some other lane's
+// key is within the forward error bound of it (or below): then, and only
+// then, the exact butterfly decides (and counts the near-ties).
+template <class Uid>
+__device__ __forceinline__ void wave_best_key(Key& best, Uid uid, int lane, int& nd) {
+    const double kv = best.t >= 0 ? best.num / best.cr : INFINITY;
+    const double km = wave_min(kv);
+    if (km == INFINITY) {
+        best = no_key();
+        return;
+    }
+    const int ml = __ffsll(static_cast<long long>(__ballot(kv == km))) - 1;
+    const Key m = read_key(best, ml);
+    bool cont = false;
+    if (best.t >= 0 && best.t != m.t) {
+        const double lhs = best.num * m.cr, rhs = m.num * best.cr;
+        const double err = 16.0 * EPS * (best.Nm * m.Cm + m.Nm * best.Cm);
+        cont = !(lhs > rhs + err);
+    }
+    if (__ballot(cont) == 0) {
+        best = m;
+        return;
+    }
+    reduce_key<WAVE>(best, uid, lane, nd);
+}
+
+// Wave argmin of squared distances, ties by user id.
+__device__ __forceinline__ void wave_nearest(double& d2, int& t, double2& p, const int32_t* perm) {
+    const double v = t >= 0 ? d2 : INFINITY;
+    const double mv = wave_min(v);
+    const unsigned long long tied = __ballot(t >= 0 && v == mv);
+    if (tied == 0) {
+        t = -1;
+        d2 = INFINITY;
+        return;
+    }
+    if (__popcll(tied) == 1) {
+        const int l = __ffsll(static_cast<long long>(tied)) - 1;
+        t = read_lane(t, l);
+        d2 = read_lane(d2, l);
+        p = make_double2(read_lane(p.x, l), read_lane(p.y, l));
+        return;
+    }
+    reduce_nearest<WAVE>(d2, t, p, perm);
 }
 
 template <int W>
@@ -295,7 +352,7 @@ struct WaveSource {
                 pbest = p;
             }
         });
-        reduce_nearest<WAVE>(d2best, best, pbest, perm);
+        wave_nearest(d2best, best, pbest, perm);
         return best;
     }
     __device__ Key wrap(int iv, double2 v, int ia, double2 a, double sgn) {
@@ -307,7 +364,7 @@ struct WaveSource {
             const Key k = key_of(t, v, a, b, sgn, nd);
             if (key_better(k, best, uid, nd)) best = k;
         });
-        reduce_key<WAVE>(best, uid, lane, nd);
+        wave_best_key(best, uid, lane, nd);
         neardeg += nd;
         return best;
     }
@@ -428,9 +485,15 @@ struct Support {
         int f = -1;
         for (int k = lane; k < n; k += W)
             if (static_cast<int>(static_cast<uint32_t>(u[k]) & IDX_MASK) == t) f = k;
+        if constexpr (W == WAVE) {
+            // entries are distinct: at most one lane found t
+            const unsigned long long b = __ballot(f >= 0);
+            return b ? read_lane(f, __ffsll(static_cast<long long>(b)) - 1) : -1;
+        } else {
 #pragma unroll
-        for (int m = 1; m < W; m <<= 1) f = max(f, lane_xor<W>(f, m));
-        return f;
+            for (int m = 1; m < W; m <<= 1) f = max(f, lane_xor<W>(f, m));
+            return f;
+        }
     }
     __device__ bool add(int t, int bit) {
         const int f = find(t);
@@ -815,6 +878,7 @@ struct KArgs {
     int64_t n_nodes;      // all sets
     BuildOut out;
     int32_t* slow;        // slow-path node list (capacity n_nodes)
+    int32_t* rd;          // rank-deficient node list (capacity n_nodes)
     unsigned long long* diag;
 };
 
@@ -1037,8 +1101,10 @@ __device__ void quad_closure(const KArgs& a, int64_t node, double2 q, int n, int
 // picked one per round (smallest squared distance, ties by user id), as a
 // pending closure row.  Anything not certified goes to the slow list.
 __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
-    __shared__ int32_t su[QPB * KMAX];
-    __shared__ int32_t svis[QPB * KMAX];
+    // per-quad rows padded by one word: the 16 quads of a wave then hit
+    // distinct LDS banks when they touch the same slot
+    __shared__ int32_t su[QPB * KPITCH];
+    __shared__ int32_t svis[QPB * KPITCH];
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const SetDesc sd = tile_set(a, blockIdx.x);
@@ -1097,10 +1163,10 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
         if (!ovf && !ring) {
             int T[3] = {0, 0, 0};
             Support<QL> S;
-            S.u = su + qi * KMAX;
+            S.u = su + qi * KPITCH;
             S.n = 0;
             S.lane = lane;
-            const int st = delaunay_node(g, g.q, T, S, svis + qi * KMAX);
+            const int st = delaunay_node(g, g.q, T, S, svis + qi * KPITCH);
             if (st == R_OK) {
                 const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
                 if (lt0 >= 0 && lt1 >= 0 && lt2 >= 0) {
@@ -1178,6 +1244,9 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     __shared__ int32_t svis[WPB * KMAX];
     __shared__ double2 slp[WPB * STAGE];
     __shared__ int32_t slt[WPB * STAGE];
+    // These few waves are a serial latency chain that runs beside the
+    // weights kernel: they take issue priority over its waves.
+    __builtin_amdgcn_s_setprio(3);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int count = static_cast<int>(a.diag[D_SLOWCNT]);
@@ -1315,23 +1384,19 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
 // are quad sums per support entry.  The support's positions are staged in
 // LDS.  A node with a rank-deficient system is left pending and listed for
 // k_weights_rd (pseudo-inverse), which keeps this kernel's registers low.
-constexpr int SK = 16;  // support entries staged in LDS per node
+constexpr int SK = 16;       // support entries staged in LDS per node
+constexpr int SKP = SK + 1;  // row pitch: conflict-free LDS banks across quads
 
-__global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
-    __shared__ double2 sp[QPB * SK];
-    __shared__ uint32_t se[QPB * SK];
-    __shared__ int32_t su[QPB * SK];
-    const int lane = threadIdx.x & (QL - 1);
-    const int qi = threadIdx.x / QL;
-    const SetDesc sd = tile_set(a, blockIdx.x);
-    const int tl = static_cast<int>(blockIdx.x - sd.t0);
-    const int tx = tl % sd.tiles_x, ty = tl / sd.tiles_x;
-    const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
-    const bool valid = i <= sd.m.nx && j <= sd.m.ny;
+// The rows a weights pass owns: the fast path's (written before the pass
+// starts) or the slow path's (flagged MF_ESCALATED, finished on the side
+// stream while the fast rows are being weighted).
+__device__ __forceinline__ void weights_node(const KArgs& a, const SetDesc& sd, int i, int j, bool valid,
+                                             int64_t node, int lane, int qi, double2* sp, uint32_t* se,
+                                             int32_t* su, bool escalated_rows) {
     const int64_t nn = a.n_nodes;
-    const int64_t node = sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;
     const uint32_t meta = valid ? a.out.meta[node] : 0u;
-    const uint32_t type = valid ? meta_type(meta) : NT_FAILED;
+    const bool mine = valid && (((meta_flags(meta) & MF_ESCALATED) != 0) == escalated_rows);
+    const uint32_t type = mine ? meta_type(meta) : NT_FAILED;
     const int n = static_cast<int>(meta_cnt(meta));
     const bool pend = type == NT_PENDING;
     const bool clos = type == NT_PEND_RING || type == NT_PEND_OUT;
@@ -1363,9 +1428,9 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
         for (int s = 0; s < SS; ++s) {
             const int k = s * QL + lane;
             if (k < ns) {
-                se[qi * SK + k] = e[s];
-                sp[qi * SK + k] = pp[s];
-                su[qi * SK + k] = uu[s];
+                se[qi * SKP + k] = e[s];
+                sp[qi * SKP + k] = pp[s];
+                su[qi * SKP + k] = uu[s];
             }
         }
     }
@@ -1377,7 +1442,8 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     // needs a generic (flat) address
     auto each = [&](auto&& f) {
         const int ns = min(n, SK);
-        for (int k = 0; k < ns; ++k) f(k, se[qi * SK + k], sp[qi * SK + k], su[qi * SK + k]);
+#pragma unroll 4
+        for (int k = 0; k < ns; ++k) f(k, se[qi * SKP + k], sp[qi * SKP + k], su[qi * SKP + k]);
         for (int k = SK; k < n; ++k) {
             const uint32_t e = static_cast<uint32_t>(a.out.idx[k * nn + node]) |
                                (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28);
@@ -1385,7 +1451,7 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
         }
     };
     auto P = [&](int k) -> double2 {
-        if (k < SK) return sp[qi * SK + k];
+        if (k < SK) return sp[qi * SKP + k];
         return a.pos_s[a.out.idx[k * nn + node]];
     };
     const double2 q = node_pos(sd.m, i, j);
@@ -1490,7 +1556,7 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
         // rank-deficient: the row stays pending for k_weights_rd
         if (lane == 0) {
             const int slot = static_cast<int>(atomicAdd(&a.diag[D_RDCNT], 1ull));
-            a.slow[slot] = static_cast<int32_t>(node);
+            a.rd[slot] = static_cast<int32_t>(node);
         }
     } else if (pend || clos) {
         // w_k = phi-part (lane 3) + sum over the edges (lanes 0..2) of
@@ -1533,6 +1599,45 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     }
 }
 
+// Weights of the fast path's pending rows, one quad per node, nodes in the
+// same 8 x 8 tiles as the fast kernel.
+__global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
+    __shared__ double2 sp[QPB * SKP];
+    __shared__ uint32_t se[QPB * SKP];
+    __shared__ int32_t su[QPB * SKP];
+    const int lane = threadIdx.x & (QL - 1);
+    const int qi = threadIdx.x / QL;
+    const SetDesc sd = tile_set(a, blockIdx.x);
+    const int tl = static_cast<int>(blockIdx.x - sd.t0);
+    const int tx = tl % sd.tiles_x, ty = tl / sd.tiles_x;
+    const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
+    const bool valid = i <= sd.m.nx && j <= sd.m.ny;
+    const int64_t node = sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;
+    weights_node(a, sd, i, j, valid, node, lane, qi, sp, se, su, false);
+}
+
+// Weights of the slow path's rows: one quad per listed node; every quad of
+// a block takes the same number of turns (wave-wide ballots inside).
+__global__ void __launch_bounds__(QWG) k_weights_slow(KArgs a) {
+    __shared__ double2 sp[QPB * SKP];
+    __shared__ uint32_t se[QPB * SKP];
+    __shared__ int32_t su[QPB * SKP];
+    __builtin_amdgcn_s_setprio(3);
+    const int lane = threadIdx.x & (QL - 1);
+    const int qi = threadIdx.x / QL;
+    const int count = static_cast<int>(a.diag[D_SLOWCNT]);
+    for (int base = blockIdx.x * QPB; base < count; base += gridDim.x * QPB) {
+        const int li = base + qi;
+        const bool valid = li < count;
+        const int64_t node = valid ? a.slow[li] : 0;
+        const SetDesc sd = node_set(a, node);
+        const int64_t ln = node - sd.n0;
+        const int i = static_cast<int>(ln % (sd.m.nx + 1)), j = static_cast<int>(ln / (sd.m.nx + 1));
+        weights_node(a, sd, i, j, valid, node, lane, qi, sp, se, su, true);
+        __syncthreads();  // the LDS rows are reused by the next turn
+    }
+}
+
 // Nodes whose moment systems are rank-deficient (listed by k_weights): the
 // minimum-norm solution through the pseudo-inverse, one quad per node.
 __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
@@ -1540,7 +1645,7 @@ __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
     const int count = static_cast<int>(a.diag[D_RDCNT]);
     const int64_t nn = a.n_nodes;
     for (int li = (blockIdx.x * QWG + threadIdx.x) / QL; li < count; li += gridDim.x * (QWG / QL)) {
-        const int64_t node = a.slow[li];
+        const int64_t node = a.rd[li];
         const SetDesc sd = node_set(a, node);
         const int64_t ln = node - sd.n0;
         const int i = static_cast<int>(ln % (sd.m.nx + 1)), j = static_cast<int>(ln / (sd.m.nx + 1));
@@ -1566,7 +1671,8 @@ __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
 }  // namespace
 
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
-                  const BuildOut& out, int levels, int32_t* slow, unsigned long long* diag, hipStream_t st) {
+                  const BuildOut& out, int levels, int32_t* slow, int32_t* rd, unsigned long long* diag,
+                  const SideWork& side, hipStream_t st) {
     PhaseTimer _timer(PH_BUILD, st);
     if (n_tiles >= (int64_t(1) << 31)) {
         set_error("too many node tiles (%lld)", static_cast<long long>(n_tiles));
@@ -1582,24 +1688,35 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     a.n_nodes = n_nodes;
     a.out = out;
     a.slow = slow;
+    a.rd = rd;
     a.diag = diag;
     const int tiles = static_cast<int>(n_tiles);
     {
         PhaseTimer t1(PH_BUILD_FAST, st);
         k_build_fast<<<tiles, QWG, 0, st>>>(a);
     }
+    P2M_HIP(hipGetLastError());
+    // The few nodes the fast pass could not certify take the exact wave path
+    // on a side stream, concurrently with the weights of all other nodes.
+    P2M_HIP(hipEventRecord(side.fork, st));
+    P2M_HIP(hipStreamWaitEvent(side.stream, side.fork, 0));
     {
-        // one wave per slow node (few: escalated, undecided, corners); the
-        // grid loops over the actual list
-        PhaseTimer t2(PH_BUILD_SLOW, st);
+        PhaseTimer t2(PH_BUILD_SLOW, side.stream);
+        // one wave per slow node (few: escalated, undecided); the grids loop
+        // over the actual list
         const int64_t expect = n_nodes / 256 + 64 * static_cast<int64_t>(S);
         const int gs = static_cast<int>(std::min<int64_t>((expect + SWG / WAVE - 1) / (SWG / WAVE), 4096));
-        k_slow_geom<<<gs, SWG, 0, st>>>(a);
+        k_slow_geom<<<gs, SWG, 0, side.stream>>>(a);
+        const int gw = static_cast<int>(std::min<int64_t>((expect + QPB - 1) / QPB, 1024));
+        k_weights_slow<<<gw, QWG, 0, side.stream>>>(a);
     }
+    P2M_HIP(hipGetLastError());
+    P2M_HIP(hipEventRecord(side.join, side.stream));
     {
         PhaseTimer t3(PH_WEIGHTS, st);
         k_weights<<<tiles, QWG, 0, st>>>(a);
-        // rank-deficient nodes (normally none): a small grid loops over the list
+        P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
+        // rank-deficient nodes of either pass (normally none)
         k_weights_rd<<<16, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());

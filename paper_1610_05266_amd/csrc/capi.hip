@@ -63,6 +63,8 @@ struct p2m_weights {
     uint32_t* meta = nullptr;
     int32_t* idx = nullptr;
     int32_t* slow = nullptr;
+    int32_t* rd = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // side-stream fork / join
     double* w64 = nullptr;
     float* w32 = nullptr;
     uint8_t* mem = nullptr;
@@ -100,9 +102,11 @@ int grow(T** p, int64_t count, int64_t have) {
 
 void release(p2m_weights* w) {
     void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.count, w->bins.start, w->bins.tsum, w->bins.pos_s,
-                    w->bins.perm, w->meta, w->idx, w->slow, w->w64, w->w32, w->mem, w->diag, w->dsets};
+                    w->bins.perm, w->meta, w->idx, w->slow, w->rd, w->w64, w->w32, w->mem, w->diag, w->dsets};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
+    if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
+    if (w->ev_join) (void)hipEventDestroy(w->ev_join);
 }
 
 bool is_fin(double v) { return std::isfinite(v); }
@@ -294,6 +298,12 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     if (!rc) w->capTiles = std::max(w->capTiles, ntiles);
     if (!rc) rc = grow(&w->meta, n_nodes, w->capNodes);
     if (!rc) rc = grow(&w->slow, n_nodes, w->capNodes);
+    if (!rc) rc = grow(&w->rd, n_nodes, w->capNodes);
+    if (!rc && !w->ev_fork) {
+        hipError_t e = hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming);
+        if (e != hipSuccess) rc = hip_check(e, "hipEventCreateWithFlags");
+    }
     if (!rc) rc = grow(&w->idx, n_nodes * KMAX, w->capNodes * KMAX);
     if (!rc) rc = grow(&w->w64, n_nodes * KMAX, w->capNodes * KMAX);
     if (!rc) rc = grow(&w->mem, n_nodes * KMAX, w->capNodes * KMAX);
@@ -327,7 +337,11 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     if (!rc) rc = bin_particles(w->bins, pos, N, w->dsets, S, nbins, w->diag, st);
     if (rc) return rc;
     BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem};
-    return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, w->slow, w->diag, st);
+    SideWork side{nullptr, w->ev_fork, w->ev_join};
+    rc = side_stream(dev, &side.stream);
+    if (rc) return rc;
+    return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, w->slow, w->rd, w->diag,
+                         side, st);
 }
 
 int check_batch(const p2m_batch* b) {

@@ -129,6 +129,31 @@ __device__ __forceinline__ double2 node_pos(const MeshD& m, int i, int j) {
                         add_rn(m.y0, mul_rn(static_cast<double>(j), m.H)));
 }
 
+// Value of v in lane (lane ^ m) of the same group of W lanes (m < W).  For
+// quads the exchange is a DPP quad permute ([1,0,3,2] for m = 1, [2,3,0,1]
+// for m = 2) that needs no LDS round trip; the four lanes must be active.
+template <int W>
+__device__ __forceinline__ int lane_xor(int v, int m) {
+    if constexpr (W == 4) {
+        return m == 1 ? __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false)
+                      : __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    } else {
+        return __shfl_xor(v, m, W);
+    }
+}
+template <int W>
+__device__ __forceinline__ double lane_xor(double v, int m) {
+    const long long b = __double_as_longlong(v);
+    const int lo = lane_xor<W>(static_cast<int>(b), m);
+    const int hi = lane_xor<W>(static_cast<int>(b >> 32), m);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+template <int W>
+__device__ __forceinline__ float lane_xor(float v, int m) {
+    return __int_as_float(lane_xor<W>(__float_as_int(v), m));
+}
+
 // Field element loads/stores with widening to the accumulation type.
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) {
     return __uint_as_float(static_cast<uint32_t>(v) << 16);

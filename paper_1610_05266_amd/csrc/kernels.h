@@ -53,11 +53,20 @@ struct BuildOut {
     float* w32;      // [KMAX][n_nodes] or null
     uint8_t* mem;    // [KMAX][n_nodes]
 };
-// All sets of a batch in one pass of three kernels (fast quad path, slow
-// wave path, weights); sets[S] is device memory, n_tiles the 8 x 8 node
-// tiles of all sets.
+// All sets of a batch in one pass: fast quad path, then the weights of its
+// rows on the caller's stream while the slow wave path (and the weights of
+// its rows) runs on the side stream; sets[S] is device memory, n_tiles the
+// 8 x 8 node tiles of all sets.
+// A second stream (per device, owned by the library) and the two events
+// that fork it from and join it back to the caller's stream.
+struct SideWork {
+    hipStream_t stream;
+    hipEvent_t fork, join;
+};
+int side_stream(int device, hipStream_t* out);
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
-                  const BuildOut& out, int levels, int32_t* slow, unsigned long long* diag, hipStream_t st);
+                  const BuildOut& out, int levels, int32_t* slow, int32_t* rd, unsigned long long* diag,
+                  const SideWork& side, hipStream_t st);
 
 // ---- projection and interpolation (project.hip, m2p.hip) ----
 int project(const WeightsView& w, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st);

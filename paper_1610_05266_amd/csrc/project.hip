@@ -20,33 +20,43 @@ __device__ __forceinline__ double ld(const double* p, int64_t i) { return p[i]; 
 __device__ __forceinline__ float ld(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ld(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
 
-// vals element type TV, weights TW, output TO (accumulate in TW)
+// vals element type TV, weights TW, output TO (accumulate in TW).  Four
+// lanes per node: lane l takes ELL entries l, l + 4, ...; the partial sums
+// are combined by a quad reduction (fixed order, so results are bitwise
+// reproducible), and lane c % 4 stores channel c.
 template <typename TV, typename TW, typename TO, int CC>
 __global__ void __launch_bounds__(256) k_project(const uint32_t* __restrict__ meta, const int32_t* __restrict__ idx,
                                                  const TW* __restrict__ w, int64_t n_nodes,
                                                  const TV* __restrict__ vals, int Crt, TO* __restrict__ out) {
-    const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (node >= n_nodes) return;
+    constexpr int NC = CC > 0 ? CC : CMAX;
+    const int lane = threadIdx.x & 3;
+    const int64_t node = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 2;
+    if (node >= n_nodes) return;  // the four lanes of a node leave together
     const int C = CC > 0 ? CC : Crt;
-    TW acc[CC > 0 ? CC : CMAX];
+    TW acc[NC];
 #pragma unroll
-    for (int c = 0; c < (CC > 0 ? CC : CMAX); ++c) acc[c] = TW(0);
+    for (int c = 0; c < NC; ++c) acc[c] = TW(0);
     const int cnt = row_len(meta[node]);
-    for (int k = 0; k < cnt; ++k) {
+    for (int k = lane; k < cnt; k += 4) {
         const int64_t j = idx[k * n_nodes + node];
         const TW wk = w[k * n_nodes + node];
 #pragma unroll
-        for (int c = 0; c < (CC > 0 ? CC : CMAX); ++c)
+        for (int c = 0; c < NC; ++c)
             if (c < C) acc[c] += wk * static_cast<TW>(ld(vals, j * C + c));
     }
 #pragma unroll
-    for (int c = 0; c < (CC > 0 ? CC : CMAX); ++c)
-        if (c < C) out[node * C + c] = static_cast<TO>(acc[c]);
+    for (int c = 0; c < NC; ++c) {
+        if (c >= C) break;
+        TW v = acc[c];
+        v += lane_xor<4>(v, 1);
+        v += lane_xor<4>(v, 2);
+        if (lane == (c & 3)) out[node * C + c] = static_cast<TO>(v);
+    }
 }
 
 template <typename TV, typename TW, typename TO>
 void launch_project(const WeightsView& wv, const TW* w, const void* vals, int C, void* out, hipStream_t st) {
-    const int blocks = static_cast<int>((wv.n_nodes + 255) / 256);
+    const int blocks = static_cast<int>((4 * wv.n_nodes + 255) / 256);
     const TV* v = static_cast<const TV*>(vals);
     TO* o = static_cast<TO*>(out);
     switch (C) {

@@ -1,5 +1,7 @@
 // Small fill kernels (used instead of hipMemsetAsync so that every clear is an
 // ordinary kernel node if a caller captures the stream in a graph).
+#include <mutex>
+
 #include "kernels.h"
 
 namespace p2m {
@@ -60,6 +62,23 @@ int fill_bytes_zero(void* p, int64_t nbytes, hipStream_t st) {
         k_zero_bytes<<<grid_for(nbytes), 256, 0, st>>>(static_cast<uint8_t*>(p), nbytes);
     }
     P2M_HIP(hipGetLastError());
+    return P2M_OK;
+}
+
+// One non-blocking stream per device for work the library overlaps with the
+// caller's stream (default priority); created on first use, kept for the
+// life of the process.
+int side_stream(int device, hipStream_t* out) {
+    constexpr int MAXDEV = 64;
+    static hipStream_t streams[MAXDEV] = {};
+    static std::mutex mu;
+    if (device < 0 || device >= MAXDEV) {
+        set_error("device %d out of range", device);
+        return P2M_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!streams[device]) P2M_HIP(hipStreamCreateWithFlags(&streams[device], hipStreamNonBlocking));
+    *out = streams[device];
     return P2M_OK;
 }
 
