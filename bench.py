@@ -26,8 +26,18 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFS = 78.6    # MI355X FP64 vector
 # algorithmic FP64 work of the weight build per node (moment assembly of the
 # three edge systems, Gram/Cholesky/solve with one refinement, weights)
-BUILD_FLOP_INTERIOR = 2100.0
-BUILD_FLOP_CLOSURE = 700.0
+# algorithmic FP64 work of the weight build per node, by kernel:
+#   fast pass (certified local Delaunay): ~20 gift-wrap steps over ~25
+#     candidates at ~12 flop per bisector key, plus one nearest search;
+#     boundary-ring nodes: 12 nearest-particle rounds over ~25 candidates;
+#   weights: three edge systems (moments, Cholesky, one refinement step,
+#     weights), or one closure system.
+FAST_FLOP_INTERIOR = 6000.0
+FAST_FLOP_RING = 900.0
+WEIGHTS_FLOP_INTERIOR = 2100.0
+WEIGHTS_FLOP_CLOSURE = 700.0
+TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                            "roundtrip_256x256_1M_hbm_traffic.md")
 
 
 def parse(argv=None):
@@ -37,6 +47,11 @@ def parse(argv=None):
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the sampled oracle comparison")
+    ap.add_argument("--no-tune", action="store_true", help="keep the library's default build options")
+    ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a build option (p2m_set_option) instead of autotuning")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="end with one plain device copy of MIB MiB (calibrates profiler byte counters)")
     ap.add_argument("--no-graph", action="store_true",
                     help="launch every step from the host instead of replaying a captured HIP graph")
     ap.add_argument("--cpu-side", type=float, default=1.0,
@@ -53,6 +68,36 @@ def rel_errs(got, ref):
 
     d = np.asarray(got, np.float64) - np.asarray(ref, np.float64)
     return (float(np.linalg.norm(d) / np.linalg.norm(ref)), float(np.abs(d).max() / np.abs(ref).max()))
+
+
+def source_digest():
+    """Digest of the HIP sources the measured kernels are built from."""
+    import hashlib
+
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1610_05266_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
+    when there is none or the sources changed since it was taken."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    import re
+
+    m = re.search(r"^source_digest: (\w+)$", text, flags=re.M)
+    if not m or m.group(1) != source_digest():
+        return None
+    m = re.search(r"^traffic_bytes_per_launch " + re.escape(kernel) + r" (\d+)$", text, flags=re.M)
+    return int(m.group(1)) if m else None
 
 
 def cpu_baseline(cloud, side):
@@ -123,6 +168,24 @@ def main(argv=None):
     ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32, weights=w, check_diag=True)
     diag = w.diag()
     log(f"diag {diag}")
+
+    tuning = None
+    if a.set:
+        for kv in a.set:
+            k, v = kv.split("=", 1)
+            ops.p2m_set_option(k, float(v))
+        tuning = {"options": dict(kv.split("=", 1) for kv in a.set), "fixed": True}
+    elif not a.no_tune:
+        from paper_1610_05266_amd import tune
+
+        log("autotuning the build options")
+        key = tune.workload_key(torch.cuda.get_device_name(dev), N, nn, cloud.h / mesh.H, P2M_WEIGHTS_F32)
+        res = tune.autotune(
+            lambda: ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32, weights=w, check_diag=False),
+            lambda h: ops.p2m_project(h, v32), key)
+        tuning = {"options": res.options, "build_ms_tuned": round(res.median_ms, 5),
+                  "build_ms_default": round(res.default_ms, 5), "cached": res.cached}
+        log(f"tuning {tuning}")
 
     def step(mixed):
         ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 if mixed else 0, weights=w, check_diag=False)
@@ -263,21 +326,34 @@ def main(argv=None):
         result_err["fp64_vs_oracle_sampled_nodes"] = rel_errs(mesh64.cpu().numpy()[sample], ref)
         result_err["mixed_vs_oracle_sampled_nodes"] = rel_errs(mesh32.cpu().numpy()[sample], ref)
 
-    # roofline of the dominant kernel group
-    top = {k: ph32[k] for k in ("bin", "build", "project", "m2p")}
-    dom = max(top, key=top.get)
-    flops = BUILD_FLOP_INTERIOR * diag["interior_nodes"] + BUILD_FLOP_CLOSURE * diag["closure_nodes"]
-    if dom == "build":
-        achieved = flops / (ph32["build"] * 1e-3) / 1e12
-        roof = {"kernel": "k_build (weight build)", "bound": "alu", "achieved": round(achieved, 4),
-                "peak": FP64_VECTOR_PEAK_TFS, "unit": "TFLOP/s", "frac": round(achieved / FP64_VECTOR_PEAK_TFS, 5),
-                "traffic": None, "algorithmic_per_launch": f"{flops:.4g} FP64 flop "
-                f"({BUILD_FLOP_INTERIOR:g}/interior node, {BUILD_FLOP_CLOSURE:g}/closure node)",
-                "avg_launch_ms": round(ph32["build"], 5)}
-    else:
-        roof = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": None, "traffic": None, "avg_launch_ms": round(ph32[dom], 5)}
+    # per-kernel rooflines (times: the library's events around each launch)
     b32 = N * (2 * 16 + (4 + 4) * C) + nn * C * (4 + 4)
+    ni, nc = diag["interior_nodes"], diag["closure_nodes"]
+    kern = {
+        "k_build_fast": ("alu", FAST_FLOP_INTERIOR * ni + FAST_FLOP_RING * nc, ph32["build_fast"],
+                         f"{FAST_FLOP_INTERIOR:g} FP64 flop/interior node, {FAST_FLOP_RING:g}/ring node"),
+        "k_weights": ("alu", WEIGHTS_FLOP_INTERIOR * ni + WEIGHTS_FLOP_CLOSURE * nc, ph32["weights"],
+                      f"{WEIGHTS_FLOP_INTERIOR:g} FP64 flop/interior node, {WEIGHTS_FLOP_CLOSURE:g}/closure node"),
+        "binning": ("hbm", 36.0 * N, ph32["bin"], "36 B/particle (16 in, 20 out)"),
+        "k_project": ("hbm", N * 4 * C + nn * C * 4, ph32["project"], "values in + mesh out, FP32"),
+        "k_m2p": ("hbm", N * (16 + 4 * C) + nn * 4 * C, ph32["m2p"], "positions + mesh in + values out, FP32"),
+    }
+    kernels = {}
+    for name, (bound, work, ms, per_unit) in kern.items():
+        if bound == "alu":
+            ach = work / (ms * 1e-3) / 1e12
+            kernels[name] = {"bound": "alu", "achieved": round(ach, 4), "peak": FP64_VECTOR_PEAK_TFS,
+                             "unit": "TFLOP/s", "frac": round(ach / FP64_VECTOR_PEAK_TFS, 5),
+                             "avg_launch_ms": round(ms, 5), "algorithmic_per_launch": f"{work:.4g} flop ({per_unit})"}
+        else:
+            ach = work / (ms * 1e-3) / 1e9
+            kernels[name] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(ach / HBM_PEAK_GBS, 5), "avg_launch_ms": round(ms, 5),
+                             "algorithmic_per_launch": f"{work:.4g} B ({per_unit})"}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_launch_ms"])
+    roof = dict(kernels[dom])
+    roof["kernel"] = dom
+    roof["traffic"] = measured_traffic(dom)
     b64 = N * (2 * 16 + (8 + 8) * C) + nn * C * (8 + 8)
     rt = {"algorithmic_bytes": b32, "achieved_GBs": round(b32 / (ms32 * 1e-3) / 1e9, 2),
           "frac": round(b32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)}
@@ -317,10 +393,12 @@ def main(argv=None):
                                "(h=H/4, jitter 0.3h, seed 2, permuted), 3 channels (u, v, p), weights rebuilt "
                                "every step", "particles": N, "nodes": nn, "channels": C},
         "roofline": roof,
+        "kernels": kernels,
         "round_trip_hbm": rt,
         "cached_weights": cached_rt,
         "launch": "eager" if (a.no_graph or graph_notes) else "HIP graph replay of the whole step",
         "launch_notes": graph_notes,
+        "tuning": tuning,
         "cpu_baseline": cpu,
         "fp64": {"value": round(N / (ms64 * 1e-3) / 1e6, 3), "ms_per_step": round(ms64, 5),
                  "round_trip_hbm": rt64, "phases_ms": {k: round(v, 5) for k, v in ph64.items()}},
@@ -329,6 +407,14 @@ def main(argv=None):
         "diag": diag,
     }
     print(json.dumps(out), flush=True)
+    if a.copy_probe:
+        n = a.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {n * 4} bytes read, {n * 4} bytes written")
     return 0
 
 

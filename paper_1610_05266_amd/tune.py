@@ -1,0 +1,166 @@
+"""Autotuner of the weight build's performance options.
+
+The build has knobs that change only its speed, never its result (they size
+the binning grid and the candidate radii of the fast pass and of the exact
+fallback; see p2m_set_option): this module picks them for a workload by
+measuring builds on the GPU, and caches the choice per device and workload
+shape in a JSON file.
+
+Search: coordinate descent from the library defaults, one knob at a time
+over a short list of candidate values, keeping a change only when the median
+build time drops by more than a noise margin.  Every candidate build is
+checked: its diagnostics must be clean and its projection of a probe field
+must equal the default build's bit for bit (the knobs may not change
+results), else the candidate is rejected.
+"""
+from __future__ import annotations
+
+import json
+import os
+import statistics
+from dataclasses import dataclass, field
+from typing import Callable, Dict, List, Optional, Sequence
+
+DEFAULTS: Dict[str, float] = {
+    "bin_scale": 1.0,
+    "fast_radius": 2.8,
+    "closure_radius": 4.0,
+    "region_h": 4.0,
+    "levels": 3.0,
+}
+
+# candidate values per knob, in search order
+SPACE: Dict[str, Sequence[float]] = {
+    "bin_scale": (0.75, 1.0, 1.5, 2.0),
+    "fast_radius": (2.6, 2.8, 3.0, 3.3),
+    "closure_radius": (3.5, 4.0, 4.5),
+    "region_h": (3.0, 4.0, 6.0),
+}
+
+NOISE = 0.02  # a change must win by more than 2 %
+
+CACHE_ENV = "P2M_TUNE_CACHE"
+
+
+def default_cache_path() -> str:
+    base = os.environ.get(CACHE_ENV)
+    if base:
+        return base
+    root = os.environ.get("XDG_CACHE_HOME", os.path.join(os.path.expanduser("~"), ".cache"))
+    return os.path.join(root, "p2m_tune.json")
+
+
+def _bucket(x: float) -> int:
+    """Coarse log2 bucket, so that nearby sizes share a cache entry."""
+    import math
+
+    return int(round(math.log2(max(float(x), 1.0)) * 2))
+
+
+def workload_key(device_name: str, n_particles: int, n_nodes: int, h_over_H: float, flags: int,
+                 n_sets: int = 1) -> str:
+    return (f"{device_name}|N~{_bucket(n_particles)}|nodes~{_bucket(n_nodes)}|h/H={h_over_H:.3f}"
+            f"|flags={flags}|sets~{_bucket(n_sets)}")
+
+
+@dataclass
+class TuneResult:
+    options: Dict[str, float]
+    median_ms: float
+    default_ms: float
+    trials: List[dict] = field(default_factory=list)
+    cached: bool = False
+
+
+def coordinate_search(measure: Callable[[Dict[str, float]], Optional[float]],
+                      space: Dict[str, Sequence[float]] = SPACE,
+                      start: Optional[Dict[str, float]] = None, noise: float = NOISE) -> TuneResult:
+    """Coordinate descent over ``space``.  ``measure(options)`` returns the
+    time of a configuration, or None when the configuration is rejected."""
+    best = dict(DEFAULTS if start is None else start)
+    t0 = measure(best)
+    if t0 is None:
+        raise RuntimeError("the default configuration was rejected")
+    best_t = t0
+    trials = [{"options": dict(best), "ms": t0}]
+    for knob, values in space.items():
+        for v in values:
+            if v == best[knob]:
+                continue
+            cand = dict(best)
+            cand[knob] = v
+            t = measure(cand)
+            trials.append({"options": dict(cand), "ms": t})
+            if t is not None and t < best_t * (1.0 - noise):
+                best, best_t = cand, t
+    return TuneResult(options=best, median_ms=best_t, default_ms=t0, trials=trials)
+
+
+def _load(path: str) -> dict:
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path: str, data: dict) -> None:
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply_options(options: Dict[str, float]) -> None:
+    from . import ops
+
+    for k, v in options.items():
+        ops.p2m_set_option(k, float(v))
+
+
+def autotune(build: Callable[[], object], probe: Callable[[object], "object"], key: str,
+             cache_path: Optional[str] = None, repeats: int = 5, retune: bool = False) -> TuneResult:
+    """Tune the build options for one workload and leave them applied.
+
+    ``build()`` runs one weight build on the current stream and returns its
+    handle; ``probe(handle)`` returns a tensor that must not depend on the
+    options (a projection of a fixed field).  Times are GPU event times of
+    ``build`` (median of ``repeats`` after one warm-up)."""
+    import torch
+
+    path = cache_path or default_cache_path()
+    data = _load(path)
+    if not retune and key in data:
+        ent = data[key]
+        apply_options(ent["options"])
+        return TuneResult(options=dict(ent["options"]), median_ms=ent["median_ms"],
+                          default_ms=ent["default_ms"], cached=True)
+
+    apply_options(DEFAULTS)
+    ref = probe(build()).clone()
+
+    def measure(options: Dict[str, float]) -> Optional[float]:
+        apply_options(options)
+        w = build()
+        d = w.diag(check_status=False)
+        if d["status"] != 0 or d["failed_nodes"]:
+            return None
+        if not torch.equal(probe(w), ref):
+            return None
+        times = []
+        for _ in range(repeats):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            build()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return statistics.median(times)
+
+    res = coordinate_search(measure)
+    apply_options(res.options)
+    data[key] = {"options": res.options, "median_ms": res.median_ms, "default_ms": res.default_ms}
+    _store(path, data)
+    return res
