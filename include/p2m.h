@@ -205,6 +205,33 @@ int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const do
 void p2m_weights_destroy(p2m_weights* w);
 
 /* ------------------------------------------------------------------------
+ * Recompute forms: the weights are rebuilt inside the call in a workspace
+ * the library keeps per device (grown on demand, never freed), so a caller
+ * keeps no weights between a forward and its backward -- the form for the
+ * largest sizes.  Calls on one device are serialised; results are those of
+ * p2m_build_weights + p2m_project (+ the backward calls) bit for bit, since
+ * the build is deterministic.
+ * ------------------------------------------------------------------------ */
+
+/* eq. (p2m) with the App. B weights built for this call (arguments as in
+ * p2m_build_weights and p2m_project; FP32/BF16 values use FP32 weights). */
+int p2m_project_fused(const p2m_mesh* mesh, double h, const double* pos, int64_t N,
+                      const void* vals, int C, int dtype, void* mesh_vals, void* stream);
+
+/* The current device's workspace handle of the recompute forms (NULL before
+ * the first call): p2m_weights_diag / p2m_weights_export on it describe the
+ * last recompute build.  Owned by the library; do not destroy. */
+const p2m_weights* p2m_fused_handle(void);
+
+/* Adjoint of p2m_project_fused for the upstream gradient grad_mesh
+ * ([(nx+1)(ny+1)][C], dtype; FP32 for BF16): grad_vals [N][C] is
+ * OVERWRITTEN (may be NULL); grad_pos [N][2] FP64 is ACCUMULATED through the
+ * weights (may be NULL; needs vals).  The weights are rebuilt from pos. */
+int p2m_backward_fused(const p2m_mesh* mesh, double h, const double* pos, int64_t N,
+                       const void* vals, int C, int dtype, const void* grad_mesh,
+                       void* grad_vals, double* grad_pos, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many independent particle sets, each with its own mesh and h,
  * handled by one launch sequence.  The sets are the paper's problem
  * (eqs. p2m, m2p and App. B) repeated; nothing couples them.

@@ -12,14 +12,25 @@ from ._lib import P2M_WEIGHTS_F32
 
 
 class P2MFunction(torch.autograd.Function):
-    """mesh_vals = P2M(pos, vals): gradients w.r.t. vals and pos."""
+    """mesh_vals = P2M(pos, vals): gradients w.r.t. vals and pos.
+
+    recompute=False keeps the weights handle from forward to backward;
+    recompute=True keeps nothing but the inputs and rebuilds the weights in
+    backward (the same deterministic build, so the same bits) -- the form
+    for the largest sizes."""
 
     @staticmethod
-    def forward(ctx, pos, vals, mesh, h, flags):
-        flags = int(flags) | (0 if vals.dtype == torch.float64 else P2M_WEIGHTS_F32)
-        w = ops.p2m_build_weights(mesh, h, pos.detach().contiguous(), flags, check_diag=True)
-        out = ops.p2m_project(w, vals.detach().contiguous())
-        ctx.w = w
+    def forward(ctx, pos, vals, mesh, h, flags, recompute):
+        p, v = pos.detach().contiguous(), vals.detach().contiguous()
+        if recompute:
+            out = ops.p2m_project_fused(mesh, h, p, v, check_diag=True)
+            ctx.w = None
+        else:
+            flags = int(flags) | (0 if vals.dtype == torch.float64 else P2M_WEIGHTS_F32)
+            w = ops.p2m_build_weights(mesh, h, p, flags, check_diag=True)
+            out = ops.p2m_project(w, v)
+            ctx.w = w
+        ctx.mesh, ctx.h = mesh, h
         ctx.vals_dtype = vals.dtype
         ctx.save_for_backward(pos, vals)
         return out
@@ -28,12 +39,16 @@ class P2MFunction(torch.autograd.Function):
     def backward(ctx, grad_out):
         pos, vals = ctx.saved_tensors
         need_pos, need_vals = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
-        gv, gw = ops.p2m_project_backward(ctx.w, grad_out.contiguous(), vals.detach().contiguous(),
-                                          want_vals=need_vals, want_w=need_pos)
-        gp = ops.p2m_build_weights_backward(ctx.w, pos.detach().contiguous(), gw) if need_pos else None
+        p, v, g = pos.detach().contiguous(), vals.detach().contiguous(), grad_out.contiguous()
+        if ctx.w is None:
+            gp = torch.zeros_like(p) if need_pos else None
+            gv, gp = ops.p2m_backward_fused(ctx.mesh, ctx.h, p, v, g, want_vals=need_vals, grad_pos=gp)
+        else:
+            gv, gw = ops.p2m_project_backward(ctx.w, g, v, want_vals=need_vals, want_w=need_pos)
+            gp = ops.p2m_build_weights_backward(ctx.w, p, gw) if need_pos else None
         if gv is not None and gv.dtype != ctx.vals_dtype:
             gv = gv.to(ctx.vals_dtype)
-        return gp, gv, None, None, None
+        return gp, gv, None, None, None, None
 
 
 class M2PFunction(torch.autograd.Function):
@@ -62,8 +77,8 @@ class M2PFunction(torch.autograd.Function):
         return gm, gp, None, None
 
 
-def p2m(pos, vals, mesh, h, flags=0):
-    return P2MFunction.apply(pos, vals, ops.Mesh.of(mesh), float(h), int(flags))
+def p2m(pos, vals, mesh, h, flags=0, recompute=False):
+    return P2MFunction.apply(pos, vals, ops.Mesh.of(mesh), float(h), int(flags), bool(recompute))
 
 
 def m2p(mesh_vals, pos, mesh, bf16_out=False):

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -344,6 +345,20 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
                          side, st);
 }
 
+// Per-device workspace of the fused (recompute) entry points: a weights
+// handle and an ELL-shaped gradient buffer, grown on demand and kept for the
+// life of the process.  Calls on one device are serialised by a lock.
+struct FusedWork {
+    std::mutex mu;
+    p2m_weights* w = nullptr;
+    double* grad_w = nullptr;
+    int64_t cap_gw = 0;
+};
+FusedWork& fused_work(int device) {
+    static FusedWork works[64];
+    return works[device & 63];
+}
+
 int check_batch(const p2m_batch* b) {
     if (!b) {
         set_error("batch handle is NULL");
@@ -631,6 +646,55 @@ int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const do
         return P2M_EINVAL;
     }
     return build_backward(view(w), pos, grad_w, grad_pos, static_cast<hipStream_t>(stream));
+}
+
+const p2m_weights* p2m_fused_handle(void) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    return fused_work(dev).w;
+}
+
+int p2m_project_fused(const p2m_mesh* mesh, double h, const double* pos, int64_t N, const void* vals, int C,
+                      int dtype, void* mesh_vals, void* stream) {
+    int rc = check_vals(vals, C, dtype, "vals", false);
+    if (!rc) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (rc) return rc;
+    int dev = 0;
+    P2M_HIP(hipGetDevice(&dev));
+    FusedWork& fw = fused_work(dev);
+    std::lock_guard<std::mutex> lock(fw.mu);
+    rc = p2m_build_weights(mesh, h, pos, N, dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32, &fw.w, stream);
+    if (!rc) rc = p2m_project(fw.w, vals, C, dtype, mesh_vals, stream);
+    return rc;
+}
+
+int p2m_backward_fused(const p2m_mesh* mesh, double h, const double* pos, int64_t N, const void* vals, int C,
+                       int dtype, const void* grad_mesh, void* grad_vals, double* grad_pos, void* stream) {
+    int rc = check_vals(grad_mesh, C, dtype, "grad_mesh", true);
+    if (!rc && grad_pos) rc = check_vals(vals, C, dtype, "vals", false);
+    if (rc) return rc;
+    if (grad_pos && !aligned(grad_pos, 16)) {
+        set_error("grad_pos is misaligned");
+        return P2M_EINVAL;
+    }
+    int dev = 0;
+    P2M_HIP(hipGetDevice(&dev));
+    FusedWork& fw = fused_work(dev);
+    std::lock_guard<std::mutex> lock(fw.mu);
+    rc = p2m_build_weights(mesh, h, pos, N, dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32, &fw.w, stream);
+    if (rc) return rc;
+    double* gw = nullptr;
+    if (grad_pos) {
+        const int64_t need = fw.w->n_nodes * KMAX;
+        rc = grow(&fw.grad_w, need, fw.cap_gw);
+        if (rc) return rc;
+        fw.cap_gw = std::max(fw.cap_gw, need);
+        gw = fw.grad_w;
+    }
+    if (!grad_vals && !gw) return P2M_OK;
+    rc = p2m_project_backward(fw.w, grad_mesh, C, dtype, vals, grad_vals, gw, stream);
+    if (!rc && gw) rc = p2m_build_weights_backward(fw.w, pos, gw, grad_pos, stream);
+    return rc;
 }
 
 void p2m_weights_destroy(p2m_weights* w) {

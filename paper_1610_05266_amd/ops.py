@@ -24,6 +24,8 @@ __all__ = [
     "p2m_project_backward",
     "p2m_build_weights_backward",
     "p2m_set_option",
+    "p2m_project_fused",
+    "p2m_backward_fused",
     "Batch",
     "p2m_build_weights_batched",
     "m2p_interpolate_batched",
@@ -265,6 +267,63 @@ def p2m_build_weights_backward(w: Weights, pos: torch.Tensor, grad_w: torch.Tens
     with torch.cuda.device(pos.device):
         check(load().p2m_build_weights_backward(w.handle, _ptr(pos), _ptr(grad_w), _ptr(grad_pos), _stream(pos)))
     return grad_pos
+
+
+def fused_diag() -> dict:
+    """Diagnostics of the last recompute build on the current device."""
+    h = load().p2m_fused_handle()
+    if not h:
+        raise ValueError("no recompute build on this device yet")
+    d = P2MDiag()
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    load().p2m_weights_diag(ctypes.c_void_p(h), ctypes.byref(d), st)
+    return d.as_dict()
+
+
+def p2m_project_fused(mesh, h: float, pos: torch.Tensor, vals: torch.Tensor,
+                      out: Optional[torch.Tensor] = None, check_diag: bool = False) -> torch.Tensor:
+    """Eq. (p2m) with the weights rebuilt inside the call (no handle kept).
+    ``check_diag`` synchronises and raises on data errors of that build."""
+    mesh = Mesh.of(mesh)
+    _need(pos, "pos", torch.float64)
+    _need(vals, "vals")
+    if vals.dim() != 2 or vals.shape[0] != pos.shape[0]:
+        raise ValueError(f"vals must have shape [{pos.shape[0]}, C]")
+    code = _dtype_code(vals.dtype)
+    C = vals.shape[1]
+    if out is None:
+        out = torch.empty((mesh.n_nodes, C), dtype=_mesh_dtype(code), device=vals.device)
+    _need(out, "out", _mesh_dtype(code), (mesh.n_nodes, C))
+    cm = mesh.c()
+    with torch.cuda.device(pos.device):
+        check(load().p2m_project_fused(ctypes.byref(cm), float(h), _ptr(pos), pos.shape[0], _ptr(vals), C, code,
+                                       _ptr(out), _stream(pos)))
+        if check_diag:
+            d = fused_diag()
+            if d["status"] != 0:
+                check(d["status"])
+    return out
+
+
+def p2m_backward_fused(mesh, h: float, pos: torch.Tensor, vals: torch.Tensor, grad_mesh: torch.Tensor,
+                       want_vals: bool = True, grad_pos: Optional[torch.Tensor] = None):
+    """Adjoint of p2m_project_fused (weights rebuilt from pos): (grad_vals or
+    None, grad_pos or None); grad_pos, when given, is accumulated into."""
+    mesh = Mesh.of(mesh)
+    _need(pos, "pos", torch.float64)
+    _need(vals, "vals", None, (pos.shape[0], grad_mesh.shape[1]))
+    code = _dtype_code(vals.dtype)
+    gdt = _mesh_dtype(code)
+    C = grad_mesh.shape[1]
+    _need(grad_mesh, "grad_mesh", gdt, (mesh.n_nodes, C))
+    gv = torch.empty((pos.shape[0], C), dtype=gdt, device=pos.device) if want_vals else None
+    if grad_pos is not None:
+        _need(grad_pos, "grad_pos", torch.float64, tuple(pos.shape))
+    cm = mesh.c()
+    with torch.cuda.device(pos.device):
+        check(load().p2m_backward_fused(ctypes.byref(cm), float(h), _ptr(pos), pos.shape[0], _ptr(vals), C, code,
+                                        _ptr(grad_mesh), _ptr(gv), _ptr(grad_pos), _stream(pos)))
+    return gv, grad_pos
 
 
 class Batch:

@@ -150,3 +150,47 @@ def test_grad_pos_central_differences_on_gpu():
             assert abs(fd - gp[mu, k]) <= 1e-6 * max(1.0, abs(fd))
             used += 1
     assert used >= 50
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_recompute_forms_equal_the_stored_weights_bitwise(small, dt):
+    """p2m_project_fused / p2m_backward_fused rebuild the weights inside the
+    call; the build is deterministic, so they must give the stored-handle
+    results bit for bit."""
+    c, om, _ = small
+    rng = np.random.default_rng(8)
+    pos = _g(c.pos)
+    vals = _g(c.vals, dt)
+    gmesh = _g(rng.normal(size=(om.n_nodes, vals.shape[1])), dt)
+    flags = 0 if dt == torch.float64 else P2M_WEIGHTS_F32
+    w = ops.p2m_build_weights(c.mesh, c.h, pos, flags)
+    ref = ops.p2m_project(w, vals)
+    gv_ref, gw = ops.p2m_project_backward(w, gmesh, vals, want_vals=True, want_w=True)
+    gp_ref = ops.p2m_build_weights_backward(w, pos, gw)
+    out = ops.p2m_project_fused(c.mesh, c.h, pos, vals, check_diag=True)
+    assert torch.equal(out, ref)
+    gv, gp = ops.p2m_backward_fused(c.mesh, c.h, pos, vals, gmesh, want_vals=True,
+                                    grad_pos=torch.zeros_like(pos))
+    assert torch.allclose(gv, gv_ref, rtol=0, atol=1e-15 if dt == torch.float64 else 1e-6)
+    # position gradients are accumulated with atomics: equal up to the order
+    assert torch.allclose(gp, gp_ref, rtol=0, atol=1e-13 * gp_ref.abs().max().item())
+    assert ops.fused_diag()["status"] == 0
+
+
+def test_autograd_recompute_mode_matches_stored_mode(small):
+    c, om, _ = small
+    nodes = om.nodes()
+    f = np.stack([wl.tg_u(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03),
+                  wl.tg_v(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03)], 1)
+    grads = []
+    for rec in (False, True):
+        pos = _g(c.pos).requires_grad_(True)
+        fm = _g(f).requires_grad_(True)
+        a = autograd.m2p(fm, pos, ops.Mesh.of(c.mesh))
+        out = autograd.p2m(pos, a, ops.Mesh.of(c.mesh), c.h, recompute=rec)
+        (0.5 * (out ** 2).sum()).backward()
+        grads.append((pos.grad.clone(), fm.grad.clone(), out.detach().clone()))
+    assert torch.equal(grads[0][2], grads[1][2])
+    # gradients are accumulated with atomics: equal up to the summation order
+    for k in (0, 1):
+        assert torch.allclose(grads[0][k], grads[1][k], rtol=0, atol=1e-13 * grads[0][k].abs().max().item())

@@ -123,6 +123,24 @@ def test_c4_full_backward_sampled_against_oracle(c4):
         assert_close(gf_g[snodes], gf, gtol, f"C4 dL/df, {what}")
 
 
+def test_c4_recompute_mode_gives_the_stored_mode_gradients(c4):
+    """At full size the autograd P2M may keep no weights between forward and
+    backward (rebuilt in backward); the build is deterministic, so the
+    forward is bitwise the same and the position gradient equal up to the
+    order of its atomic sums."""
+    c, om, _ = c4
+    mesh = ops.Mesh.of(c.mesh)
+    res = []
+    for rec in (False, True):
+        pos = _g(c.pos).requires_grad_(True)
+        a = _g(c.vals, torch.float32).requires_grad_(True)
+        out = autograd.p2m(pos, a, mesh, c.h, recompute=rec)
+        (0.5 * ((out.double() - _g(c.extra["g_mesh"])) ** 2).sum()).backward()
+        res.append((out.detach(), pos.grad))
+    assert torch.equal(res[0][0], res[1][0])
+    assert torch.allclose(res[0][1], res[1][1], rtol=0, atol=1e-12 * res[0][1].abs().max().item())
+
+
 def test_c4_full_size_properties(c4):
     """Every node reproduces a quadratic; the FP64 build is bitwise
     repeatable; the diagnostics are clean."""
