@@ -3,12 +3,18 @@
 // The Delaunay step of App. B needs, for every mesh node, the particles near
 // it.  Instead of a global triangulation (the paper used CGAL, App. A), the
 // particles are sorted by bin so that every bin row segment is a contiguous
-// range of a sorted position array.  Four kernels:
-//   1. count:   key and in-bin rank per particle (atomic histogram);
-//   2. scan:    exclusive prefix sum of the histogram (three-phase);
-//   3. scatter: sorted positions and the sorted -> user permutation;
-//   4. fix:     per-bin insertion sort by user id, so the sorted order equals
-//               a stable sort by key (bitwise deterministic).
+// range of a sorted position array.  The sort is a two-level counting sort
+// without global atomics; bins are grouped into super-bins of 2^SBS
+// consecutive bin keys (rows of bins):
+//   1. key:   bin key per particle, and per chunk of particles an LDS
+//             histogram over super-bins;
+//   2. scan:  exclusive prefix sum of the (super-bin, chunk) histogram;
+//   3. part:  each chunk scatters (position, key, user id) into its super-bin
+//             ranges (runs of consecutive slots per chunk);
+//   4. local: one block per super-bin counts its bins in LDS, writes their
+//             start offsets, places its particles, and sorts each bin by user
+//             id, so the sorted order equals a stable sort by key (bitwise
+//             deterministic, independent of atomic arrival order).
 #include "kernels.h"
 
 namespace p2m {
@@ -18,35 +24,56 @@ namespace {
 constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
+constexpr int BT = 1024;         // threads of the binning kernels (16 waves)
+constexpr int MAX_SB = 8192;     // super-bins (LDS counters of kernels 1 and 3)
+constexpr int MAX_SBS = 14;      // bins per super-bin <= 2^14 (LDS of kernel 4)
 
-__global__ void __launch_bounds__(256) k_bin_count(const double2* __restrict__ pos, int N,
-                                                   const SetDesc* __restrict__ sets, int S, uint32_t nbins,
-                                                   uint32_t* __restrict__ key, int32_t* __restrict__ rank,
-                                                   int32_t* __restrict__ count,
-                                                   unsigned long long* __restrict__ diag) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const SetDesc& sd = sets[set_search(S, i, [&](int s) { return sets[s].p0; })];
+// Bin key of particle i (key nbins: outside its set's mesh, or non-finite).
+__device__ __forceinline__ uint32_t bin_key(const double2 p, const SetDesc& sd, uint32_t nbins) {
     const MeshD m = sd.m;
     const Grid g = sd.g;
-    const double2 p = pos[i];
     const double x1 = add_rn(m.x0, mul_rn(static_cast<double>(m.nx), m.H));
     const double y1 = add_rn(m.y0, mul_rn(static_cast<double>(m.ny), m.H));
-    uint32_t k;
     // NaN fails every comparison, so it is caught here as well.
-    if (p.x >= m.x0 && p.x <= x1 && p.y >= m.y0 && p.y <= y1) {
-        int bx = static_cast<int>(floor((p.x - g.x0) / g.bw));
-        int by = static_cast<int>(floor((p.y - g.y0) / g.bw));
-        bx = min(max(bx, 0), g.nbx - 1);
-        by = min(max(by, 0), g.nby - 1);
-        k = static_cast<uint32_t>(sd.b0) + static_cast<uint32_t>(by) * static_cast<uint32_t>(g.nbx) +
-            static_cast<uint32_t>(bx);
-    } else {
-        k = nbins;
-        atomicAdd(&diag[D_BAD], 1ull);
+    if (!(p.x >= m.x0 && p.x <= x1 && p.y >= m.y0 && p.y <= y1)) return nbins;
+    int bx = static_cast<int>(floor((p.x - g.x0) / g.bw));
+    int by = static_cast<int>(floor((p.y - g.y0) / g.bw));
+    bx = min(max(bx, 0), g.nbx - 1);
+    by = min(max(by, 0), g.nby - 1);
+    return static_cast<uint32_t>(sd.b0) + static_cast<uint32_t>(by) * static_cast<uint32_t>(g.nbx) +
+           static_cast<uint32_t>(bx);
+}
+
+struct BinGeom {
+    int64_t N;
+    uint32_t nbins;
+    int nch;       // chunks of particles (one block each in kernels 1 and 3)
+    int64_t cs;    // particles per chunk
+    int sbs;       // log2(bins per super-bin)
+    int nsb;       // super-bins
+};
+
+// 1. keys and the (super-bin, chunk) histogram, super-bin major
+__global__ void __launch_bounds__(BT) k_bin_key(const double2* __restrict__ pos, const SetDesc* __restrict__ sets,
+                                               int S, BinGeom bg, uint32_t* __restrict__ key,
+                                               int32_t* __restrict__ hist, unsigned long long* __restrict__ diag) {
+    __shared__ int32_t lh[MAX_SB];
+    __shared__ int32_t nbad;
+    const int c = blockIdx.x;
+    for (int k = threadIdx.x; k < bg.nsb; k += BT) lh[k] = 0;
+    if (threadIdx.x == 0) nbad = 0;
+    __syncthreads();
+    const int64_t lo = c * bg.cs, hi = min(bg.N, lo + bg.cs);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BT) {
+        const SetDesc& sd = sets[set_search(S, i, [&](int s) { return sets[s].p0; })];
+        const uint32_t k = bin_key(pos[i], sd, bg.nbins);
+        key[i] = k;
+        atomicAdd(&lh[k >> bg.sbs], 1);
+        if (k == bg.nbins) atomicAdd(&nbad, 1);
     }
-    key[i] = k;
-    rank[i] = atomicAdd(&count[k], 1);
+    __syncthreads();
+    for (int k = threadIdx.x; k < bg.nsb; k += BT) hist[static_cast<int64_t>(k) * bg.nch + c] = lh[k];
+    if (threadIdx.x == 0 && nbad) atomicAdd(&diag[D_BAD], static_cast<unsigned long long>(nbad));
 }
 
 // Phase 1 of the scan: per-tile exclusive scan, tile totals to tsum.
@@ -117,49 +144,109 @@ __global__ void __launch_bounds__(256) k_scan_add(int32_t* __restrict__ out, int
     if (i == n) out[n] = tsum[ntiles];
 }
 
-__global__ void __launch_bounds__(256) k_bin_scatter(const double2* __restrict__ pos, int N,
-                                                     const uint32_t* __restrict__ key,
-                                                     const int32_t* __restrict__ rank,
-                                                     const int32_t* __restrict__ start,
-                                                     double2* __restrict__ pos_s,
-                                                     int32_t* __restrict__ perm) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
-    const int slot = start[key[i]] + rank[i];
-    pos_s[slot] = pos[i];
-    perm[slot] = i;
+// 3. each chunk scatters its particles into its slots of every super-bin
+__global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos, const uint32_t* __restrict__ key,
+                                                BinGeom bg, const int32_t* __restrict__ offs,
+                                                double2* __restrict__ part_pos, uint32_t* __restrict__ part_key,
+                                                int32_t* __restrict__ part_uid) {
+    __shared__ int32_t cur[MAX_SB];
+    const int c = blockIdx.x;
+    for (int k = threadIdx.x; k < bg.nsb; k += BT) cur[k] = offs[static_cast<int64_t>(k) * bg.nch + c];
+    __syncthreads();
+    const int64_t lo = c * bg.cs, hi = min(bg.N, lo + bg.cs);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BT) {
+        const uint32_t k = key[i];
+        const int slot = atomicAdd(&cur[k >> bg.sbs], 1);
+        part_pos[slot] = pos[i];
+        part_key[slot] = k;
+        part_uid[slot] = static_cast<int32_t>(i);
+    }
 }
 
-// Bins hold O(1) particles at the intended bin width; insertion sort is fine
-// and keeps the result independent of the atomic arrival order.
-__global__ void __launch_bounds__(256) k_bin_fix(const int32_t* __restrict__ start, int nbins,
-                                                 double2* __restrict__ pos_s, int32_t* __restrict__ perm,
-                                                 unsigned long long* __restrict__ diag) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nbins) return;
-    const int s = start[b], e = start[b + 1];
-    for (int i = s + 1; i < e; ++i) {
-        const int32_t pi = perm[i];
-        const double2 xi = pos_s[i];
-        int j = i - 1;
-        while (j >= s && perm[j] > pi) {
-            perm[j + 1] = perm[j];
-            pos_s[j + 1] = pos_s[j];
-            --j;
-        }
-        perm[j + 1] = pi;
-        pos_s[j + 1] = xi;
+// 4. one block per super-bin: bin counts and start offsets, placement, and a
+// per-bin sort by user id (bins hold O(1) particles at the intended width)
+__global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __restrict__ offs,
+                                                 const double2* __restrict__ part_pos,
+                                                 const uint32_t* __restrict__ part_key,
+                                                 const int32_t* __restrict__ part_uid, int32_t* __restrict__ rank,
+                                                 int32_t* __restrict__ start, double2* __restrict__ pos_s,
+                                                 int32_t* __restrict__ perm, unsigned long long* __restrict__ diag) {
+    __shared__ int32_t pre[(1 << MAX_SBS) + 1];
+    __shared__ int32_t part[BT];
+    __shared__ int32_t ndup;
+    const int b = blockIdx.x;
+    const int M = 1 << bg.sbs;
+    const int lo = offs[static_cast<int64_t>(b) * bg.nch];
+    const int hi = offs[static_cast<int64_t>(b + 1) * bg.nch];
+    const uint32_t k0 = static_cast<uint32_t>(b) << bg.sbs;
+    for (int k = threadIdx.x; k <= M; k += BT) pre[k] = 0;
+    if (threadIdx.x == 0) ndup = 0;
+    __syncthreads();
+    // counts (pre[k + 1] collects bin k) and each particle's rank in its bin
+    for (int e = lo + threadIdx.x; e < hi; e += BT) rank[e] = atomicAdd(&pre[part_key[e] - k0 + 1], 1);
+    __syncthreads();
+    // inclusive scan of pre[1..M]: thread t sums a run of M / BT entries
+    const int run = M / BT;
+    const int r0 = 1 + threadIdx.x * run;
+    int acc = 0;
+    for (int k = 0; k < run; ++k) acc += pre[r0 + k];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 1; off < BT; off <<= 1) {
+        const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
     }
-    // coincident particles always share a bin: no Delaunay triangulation
+    int run_base = part[threadIdx.x] - acc;
+    for (int k = 0; k < run; ++k) {
+        run_base += pre[r0 + k];
+        pre[r0 + k] = run_base;
+    }
+    __syncthreads();
+    // start offsets of this super-bin's bins (and of the excluded bucket)
+    for (int k = threadIdx.x; k < M; k += BT) {
+        const uint32_t gk = k0 + static_cast<uint32_t>(k);
+        if (gk <= bg.nbins) start[gk] = lo + pre[k];
+    }
+    if (k0 <= bg.nbins && bg.nbins < k0 + static_cast<uint32_t>(M) && threadIdx.x == 0)
+        start[bg.nbins + 1] = static_cast<int32_t>(bg.N);
+    // placement
+    for (int e = lo + threadIdx.x; e < hi; e += BT) {
+        const int slot = lo + pre[part_key[e] - k0] + rank[e];
+        pos_s[slot] = part_pos[e];
+        perm[slot] = part_uid[e];
+    }
+    __syncthreads();
+    // per bin: insertion sort by user id; coincident particles always share a
+    // bin, so pairs of them are counted here (no Delaunay triangulation)
     int dup = 0;
-    for (int i = s + 1; i < e; ++i) {
-        const double2 a = pos_s[i];
-        for (int k = s; k < i; ++k) {
-            const double2 b = pos_s[k];
-            dup += (a.x == b.x && a.y == b.y) ? 1 : 0;
+    for (int k = threadIdx.x; k < M; k += BT) {
+        if (k0 + static_cast<uint32_t>(k) >= bg.nbins) break;  // the excluded bucket is not sorted
+        const int s = lo + pre[k], e = lo + pre[k + 1];
+        for (int i = s + 1; i < e; ++i) {
+            const int32_t pi = perm[i];
+            const double2 xi = pos_s[i];
+            int j = i - 1;
+            while (j >= s && perm[j] > pi) {
+                perm[j + 1] = perm[j];
+                pos_s[j + 1] = pos_s[j];
+                --j;
+            }
+            perm[j + 1] = pi;
+            pos_s[j + 1] = xi;
+        }
+        for (int i = s + 1; i < e; ++i) {
+            const double2 a = pos_s[i];
+            for (int q = s; q < i; ++q) {
+                const double2 c = pos_s[q];
+                dup += (a.x == c.x && a.y == c.y) ? 1 : 0;
+            }
         }
     }
-    if (dup) atomicAdd(&diag[D_DUP], static_cast<unsigned long long>(dup));
+    if (dup) atomicAdd(&ndup, dup);
+    __syncthreads();
+    if (threadIdx.x == 0 && ndup) atomicAdd(&diag[D_DUP], static_cast<unsigned long long>(ndup));
 }
 
 inline int blocks_for(int64_t n, int threads) { return static_cast<int>((n + threads - 1) / threads); }
@@ -177,23 +264,39 @@ int exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum, hi
     return P2M_OK;
 }
 
+int bin_layout(int64_t N, int64_t nbins, int* nch, int* sbs, int* nsb) {
+    int shift = 12;
+    while (shift < MAX_SBS && (nbins >> shift) + 1 > MAX_SB) ++shift;
+    if ((nbins >> shift) + 1 > MAX_SB) {
+        set_error("binning grid too large (%lld bins)", static_cast<long long>(nbins));
+        return P2M_EINVAL;
+    }
+    *sbs = shift;
+    *nsb = static_cast<int>((nbins >> shift) + 1);
+    *nch = static_cast<int>(std::min<int64_t>(256, std::max<int64_t>(1, (N + 4095) / 4096)));
+    return P2M_OK;
+}
+
 int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDesc* sets, int S, int64_t nbins,
                   unsigned long long* diag, hipStream_t st) {
     PhaseTimer _timer(PH_BIN, st);
-    // count[0..nbins] (the last entry collects invalid particles)
-    int rc = fill_i32(b.count, 0, nbins + 1, st);
+    BinGeom bg;
+    int rc = bin_layout(N, nbins, &bg.nch, &bg.sbs, &bg.nsb);
     if (rc) return rc;
-    k_bin_count<<<blocks_for(N, 256), 256, 0, st>>>(reinterpret_cast<const double2*>(pos), static_cast<int>(N),
-                                                    sets, S, static_cast<uint32_t>(nbins), b.key, b.rank,
-                                                    b.count, diag);
+    bg.N = N;
+    bg.nbins = static_cast<uint32_t>(nbins);
+    bg.cs = (N + bg.nch - 1) / bg.nch;
+    const int64_t nh = static_cast<int64_t>(bg.nsb) * bg.nch;
+    const double2* P = reinterpret_cast<const double2*>(pos);
+    k_bin_key<<<bg.nch, BT, 0, st>>>(P, sets, S, bg, b.key, b.hist, diag);
     P2M_HIP(hipGetLastError());
-    rc = exclusive_scan(b.count, b.start, nbins + 1, b.tsum, st);
+    rc = exclusive_scan(b.hist, b.hist, nh, b.tsum, st);
     if (rc) return rc;
-    k_bin_scatter<<<blocks_for(N, 256), 256, 0, st>>>(reinterpret_cast<const double2*>(pos), static_cast<int>(N),
-                                                      b.key, b.rank, b.start,
-                                                      reinterpret_cast<double2*>(b.pos_s), b.perm);
-    k_bin_fix<<<blocks_for(nbins, 256), 256, 0, st>>>(b.start, static_cast<int>(nbins),
-                                                      reinterpret_cast<double2*>(b.pos_s), b.perm, diag);
+    k_bin_part<<<bg.nch, BT, 0, st>>>(P, b.key, bg, b.hist, reinterpret_cast<double2*>(b.part_pos), b.part_key,
+                                      b.part_uid);
+    k_bin_local<<<bg.nsb, BT, 0, st>>>(bg, b.hist, reinterpret_cast<const double2*>(b.part_pos), b.part_key,
+                                       b.part_uid, b.rank, b.start, reinterpret_cast<double2*>(b.pos_s), b.perm,
+                                       diag);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }

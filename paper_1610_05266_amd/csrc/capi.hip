@@ -58,7 +58,7 @@ struct p2m_weights {
     int64_t n_tiles = 0;
     int flags = 0;
     // capacities of the device buffers
-    int64_t capN = 0, capBins = 0, capNodes = 0, capTiles = 0, capSets = 0;
+    int64_t capN = 0, capBins = 0, capNodes = 0, capTiles = 0, capSets = 0, capHist = 0;
     bool capW32 = false;
     BinBuffers bins{};
     uint32_t* meta = nullptr;
@@ -102,8 +102,9 @@ int grow(T** p, int64_t count, int64_t have) {
 }
 
 void release(p2m_weights* w) {
-    void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.count, w->bins.start, w->bins.tsum, w->bins.pos_s,
-                    w->bins.perm, w->meta, w->idx, w->slow, w->rd, w->w64, w->w32, w->mem, w->diag, w->dsets};
+    void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.hist, w->bins.start, w->bins.tsum, w->bins.pos_s,
+                    w->bins.perm, w->bins.part_pos, w->bins.part_key, w->bins.part_uid, w->meta, w->idx, w->slow,
+                    w->rd, w->w64, w->w32, w->mem, w->diag, w->dsets};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
@@ -265,6 +266,9 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
         set_error("unknown flags 0x%x", flags);
         return P2M_EINVAL;
     }
+    int nch = 0, sbs = 0, nsb = 0;
+    int rc = bin_layout(tot.N, tot.nbins, &nch, &sbs, &nsb);
+    if (rc) return rc;
     int dev = 0;
     P2M_HIP(hipGetDevice(&dev));
     p2m_weights* w = *wout;
@@ -283,18 +287,22 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     }
     const int S = static_cast<int>(sets.size());
     const int64_t N = tot.N, n_nodes = tot.n_nodes, nbins = tot.nbins;
-    const int64_t ntiles = scan_tile_count(nbins + 1) + 1;
+    const int64_t nhist = static_cast<int64_t>(nsb) * nch;
+    const int64_t ntiles = scan_tile_count(nhist + 1) + 1;
     const bool want32 = (flags & P2M_WEIGHTS_F32) != 0;
     const bool new_table = !w->dsets || w->capSets < S;
-    int rc = P2M_OK;
     if (!rc) rc = grow(&w->bins.key, N, w->capN);
     if (!rc) rc = grow(&w->bins.rank, N, w->capN);
     if (!rc) rc = grow(&w->bins.perm, N, w->capN);
     if (!rc) rc = grow(&w->bins.pos_s, 2 * N, 2 * w->capN);
+    if (!rc) rc = grow(&w->bins.part_pos, 2 * N, 2 * w->capN);
+    if (!rc) rc = grow(&w->bins.part_key, N, w->capN);
+    if (!rc) rc = grow(&w->bins.part_uid, N, w->capN);
     if (!rc) w->capN = std::max(w->capN, N);
-    if (!rc) rc = grow(&w->bins.count, nbins + 1, w->capBins + 1);
     if (!rc) rc = grow(&w->bins.start, nbins + 2, w->capBins + 2);
     if (!rc) w->capBins = std::max(w->capBins, nbins);
+    if (!rc) rc = grow(&w->bins.hist, nhist + 1, w->capHist + 1);
+    if (!rc) w->capHist = std::max(w->capHist, nhist);
     if (!rc) rc = grow(&w->bins.tsum, ntiles + 1, w->capTiles + 1);
     if (!rc) w->capTiles = std::max(w->capTiles, ntiles);
     if (!rc) rc = grow(&w->meta, n_nodes, w->capNodes);

@@ -30,14 +30,19 @@ int fill_bytes_zero(void* p, int64_t nbytes, hipStream_t st);
 
 // ---- binning (binning.hip) ----
 struct BinBuffers {
-    uint32_t* key;   // [N]
-    int32_t* rank;   // [N]
-    int32_t* count;  // [nbins + 1]
-    int32_t* start;  // [nbins + 2]
-    int32_t* tsum;   // [scan tiles + 1]
-    double* pos_s;   // [N][2] sorted positions
-    int32_t* perm;   // [N] sorted -> user id
+    uint32_t* key;       // [N] bin key per particle (user order)
+    int32_t* rank;       // [N] rank of a particle in its bin (scratch)
+    int32_t* hist;       // [nsb * nch + 1] (super-bin, chunk) counts, scanned in place
+    int32_t* tsum;       // [scan tiles + 1]
+    double* part_pos;    // [N][2] positions grouped by super-bin
+    uint32_t* part_key;  // [N]
+    int32_t* part_uid;   // [N]
+    int32_t* start;      // [nbins + 2] first sorted slot of every bin
+    double* pos_s;       // [N][2] sorted positions
+    int32_t* perm;       // [N] sorted -> user id
 };
+// Chunks, log2(bins per super-bin) and super-bins of the two-level sort.
+int bin_layout(int64_t N, int64_t nbins, int* nch, int* sbs, int* nsb);
 int64_t scan_tile_count(int64_t n);
 int exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum, hipStream_t st);
 // Bins of set s are b0(s) .. b0(s) + nbx nby - 1; key nbins (all sets)
