@@ -25,7 +25,7 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 constexpr int BT = 1024;         // threads of the binning kernels (16 waves)
-constexpr int MAX_SB = 8192;     // super-bins (LDS counters of kernels 1 and 3)
+constexpr int MAX_SB = 4096;     // super-bins (LDS counters of kernels 1 and 3)
 constexpr int MAX_SBS = 14;      // bins per super-bin <= 2^14 (LDS of kernel 4)
 
 // Bin key of particle i (key nbins: outside its set's mesh, or non-finite).
@@ -64,6 +64,7 @@ __global__ void __launch_bounds__(BT) k_bin_key(const double2* __restrict__ pos,
     if (threadIdx.x == 0) nbad = 0;
     __syncthreads();
     const int64_t lo = c * bg.cs, hi = min(bg.N, lo + bg.cs);
+#pragma unroll 4
     for (int64_t i = lo + threadIdx.x; i < hi; i += BT) {
         const SetDesc& sd = sets[set_search(S, i, [&](int s) { return sets[s].p0; })];
         const uint32_t k = bin_key(pos[i], sd, bg.nbins);
@@ -144,22 +145,92 @@ __global__ void __launch_bounds__(256) k_scan_add(int32_t* __restrict__ out, int
     if (i == n) out[n] = tsum[ntiles];
 }
 
-// 3. each chunk scatters its particles into its slots of every super-bin
+// 3. each chunk scatters its particles into its slots of every super-bin.
+// A sub-chunk of `sub` particles is first ordered by super-bin in LDS, so that
+// consecutive threads write consecutive slots of each run (coalesced).
+// Dynamic LDS: gcur[nsb], lcnt[nsb], lstart[nsb], then sub (position, key,
+// user id) records.
+constexpr int PART_PER_THREAD = 2;  // sub <= PART_PER_THREAD * BT
+
+__device__ void block_exclusive_scan(const int32_t* in, int32_t* out, int n, int32_t* part) {
+    const int per = (n + BT - 1) / BT;
+    const int r0 = threadIdx.x * per;
+    int acc = 0;
+    for (int k = 0; k < per; ++k)
+        if (r0 + k < n) acc += in[r0 + k];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 1; off < BT; off <<= 1) {
+        const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int run = part[threadIdx.x] - acc;
+    for (int k = 0; k < per; ++k)
+        if (r0 + k < n) {
+            out[r0 + k] = run;
+            run += in[r0 + k];
+        }
+    __syncthreads();
+}
+
 __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos, const uint32_t* __restrict__ key,
-                                                BinGeom bg, const int32_t* __restrict__ offs,
+                                                BinGeom bg, const int32_t* __restrict__ offs, int sub,
                                                 double2* __restrict__ part_pos, uint32_t* __restrict__ part_key,
                                                 int32_t* __restrict__ part_uid) {
-    __shared__ int32_t cur[MAX_SB];
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t part[BT];
+    const int nsb = bg.nsb;
+    double2* spos = reinterpret_cast<double2*>(smem);
+    uint32_t* skey = reinterpret_cast<uint32_t*>(spos + sub);
+    int32_t* suid = reinterpret_cast<int32_t*>(skey + sub);
+    int32_t* gcur = suid + sub;
+    int32_t* lcnt = gcur + nsb;
+    int32_t* lstart = lcnt + nsb;
     const int c = blockIdx.x;
-    for (int k = threadIdx.x; k < bg.nsb; k += BT) cur[k] = offs[static_cast<int64_t>(k) * bg.nch + c];
-    __syncthreads();
+    for (int k = threadIdx.x; k < nsb; k += BT) gcur[k] = offs[static_cast<int64_t>(k) * bg.nch + c];
     const int64_t lo = c * bg.cs, hi = min(bg.N, lo + bg.cs);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += BT) {
-        const uint32_t k = key[i];
-        const int slot = atomicAdd(&cur[k >> bg.sbs], 1);
-        part_pos[slot] = pos[i];
-        part_key[slot] = k;
-        part_uid[slot] = static_cast<int32_t>(i);
+    for (int64_t b0 = lo; b0 < hi; b0 += sub) {
+        const int n = static_cast<int>(min<int64_t>(sub, hi - b0));
+        for (int k = threadIdx.x; k < nsb; k += BT) lcnt[k] = 0;
+        __syncthreads();
+        uint32_t kk[PART_PER_THREAD];
+        int rr[PART_PER_THREAD];
+        double2 pp[PART_PER_THREAD];
+#pragma unroll
+        for (int j = 0; j < PART_PER_THREAD; ++j) {
+            const int e = threadIdx.x + j * BT;
+            if (e < n) {
+                kk[j] = key[b0 + e];
+                pp[j] = pos[b0 + e];
+                rr[j] = atomicAdd(&lcnt[kk[j] >> bg.sbs], 1);
+            }
+        }
+        __syncthreads();
+        block_exclusive_scan(lcnt, lstart, nsb, part);
+#pragma unroll
+        for (int j = 0; j < PART_PER_THREAD; ++j) {
+            const int e = threadIdx.x + j * BT;
+            if (e < n) {
+                const int sl = lstart[kk[j] >> bg.sbs] + rr[j];
+                spos[sl] = pp[j];
+                skey[sl] = kk[j];
+                suid[sl] = static_cast<int32_t>(b0 + e);
+            }
+        }
+        __syncthreads();
+        for (int sl = threadIdx.x; sl < n; sl += BT) {
+            const uint32_t k = skey[sl];
+            const int sb = static_cast<int>(k >> bg.sbs);
+            const int slot = gcur[sb] + (sl - lstart[sb]);
+            part_pos[slot] = spos[sl];
+            part_key[slot] = k;
+            part_uid[slot] = suid[sl];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nsb; k += BT) gcur[k] += lcnt[k];
+        __syncthreads();
     }
 }
 
@@ -183,6 +254,7 @@ __global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __r
     if (threadIdx.x == 0) ndup = 0;
     __syncthreads();
     // counts (pre[k + 1] collects bin k) and each particle's rank in its bin
+#pragma unroll 4
     for (int e = lo + threadIdx.x; e < hi; e += BT) rank[e] = atomicAdd(&pre[part_key[e] - k0 + 1], 1);
     __syncthreads();
     // inclusive scan of pre[1..M]: thread t sums a run of M / BT entries
@@ -212,6 +284,7 @@ __global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __r
     if (k0 <= bg.nbins && bg.nbins < k0 + static_cast<uint32_t>(M) && threadIdx.x == 0)
         start[bg.nbins + 1] = static_cast<int32_t>(bg.N);
     // placement
+#pragma unroll 4
     for (int e = lo + threadIdx.x; e < hi; e += BT) {
         const int slot = lo + pre[part_key[e] - k0] + rank[e];
         pos_s[slot] = part_pos[e];
@@ -292,8 +365,16 @@ int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDe
     P2M_HIP(hipGetLastError());
     rc = exclusive_scan(b.hist, b.hist, nh, b.tsum, st);
     if (rc) return rc;
-    k_bin_part<<<bg.nch, BT, 0, st>>>(P, b.key, bg, b.hist, reinterpret_cast<double2*>(b.part_pos), b.part_key,
-                                      b.part_uid);
+    // sub-chunk size: as many records as fit beside the counters in 64 KB
+    int sub = PART_PER_THREAD * BT;
+    while (sub > 256 && 12 * static_cast<int64_t>(bg.nsb) + 24 * static_cast<int64_t>(sub) > 65536) sub >>= 1;
+    if (12 * static_cast<int64_t>(bg.nsb) + 24 * static_cast<int64_t>(sub) > 65536) {
+        set_error("binning: too many super-bins (%d)", bg.nsb);
+        return P2M_EINVAL;
+    }
+    const size_t lds = static_cast<size_t>(24) * sub + static_cast<size_t>(12) * bg.nsb;
+    k_bin_part<<<bg.nch, BT, lds, st>>>(P, b.key, bg, b.hist, sub, reinterpret_cast<double2*>(b.part_pos),
+                                        b.part_key, b.part_uid);
     k_bin_local<<<bg.nsb, BT, 0, st>>>(bg, b.hist, reinterpret_cast<const double2*>(b.part_pos), b.part_key,
                                        b.part_uid, b.rank, b.start, reinterpret_cast<double2*>(b.pos_s), b.perm,
                                        diag);
