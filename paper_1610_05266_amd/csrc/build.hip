@@ -511,10 +511,6 @@ struct Support {
     }
 };
 
-template <class T>
-__device__ __forceinline__ T sel3(const T a[3], int i) {
-    return i == 0 ? a[0] : (i == 1 ? a[1] : a[2]);
-}
 
 // Delaunay work of one node q: the triangle T (CCW, sorted indices) of the
 // particles' Delaunay triangulation that contains q, and the rings of its
@@ -533,7 +529,11 @@ __device__ __forceinline__ T sel3(const T a[3], int i) {
 // Returns R_OK, R_OUTSIDE (q outside the convex hull), R_MORE (not
 // certified by this source), R_FAIL or R_CAP.
 template <class G, class S_>
-__device__ int delaunay_node(G& g, double2 q, int T[3], S_& S, int32_t* vis) {
+__device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis) {
+    // the current triangle as scalars, selected by value (an array indexed
+    // at run time would live in scratch memory)
+    int T0 = -1, T1 = -1, T2 = -1;
+    auto tsel = [&](int i) { return i == 0 ? T0 : (i == 1 ? T1 : T2); };
     double d2;
     double2 v;
     const int n0 = g.nearest(q, -1, d2, v);
@@ -548,7 +548,8 @@ __device__ int delaunay_node(G& g, double2 q, int T[3], S_& S, int32_t* vis) {
     double cx, cy, rr;
 
     // ---- wedge: T = (n0, cur, next) with q between cur and next
-    double2 PT[3] = {v, v, v};
+    double2 P0 = v, P1 = v, P2 = v;
+    auto psel = [&](int i) { return i == 0 ? P0 : (i == 1 ? P1 : P2); };
     int cur = a0;
     double2 pcur = pa0;
     int nvis = 1;
@@ -566,8 +567,8 @@ __device__ int delaunay_node(G& g, double2 q, int T[3], S_& S, int32_t* vis) {
         if (!g.certify(cx, cy, rr)) return R_MORE;
         const double2 pk = make_double2(k.bx, k.by);
         if (d2 == 0.0 || (orient(v, pcur, q) >= 0.0 && orient(v, pk, q) < 0.0)) {
-            T[0] = n0; T[1] = cur; T[2] = k.t;
-            PT[0] = v; PT[1] = pcur; PT[2] = pk;
+            T0 = n0; T1 = cur; T2 = k.t;
+            P0 = v; P1 = pcur; P2 = pk;
             found = true;
             break;
         }
@@ -591,8 +592,8 @@ __device__ int delaunay_node(G& g, double2 q, int T[3], S_& S, int32_t* vis) {
             if (k.t < 0) return d2 == 0.0 ? R_FAIL : R_OUTSIDE;  // q outside the open fan's cone
             const double2 pk = make_double2(k.bx, k.by);
             if (d2 == 0.0 || (orient(v, pk, q) >= 0.0 && orient(v, pcur, q) < 0.0)) {
-                T[0] = n0; T[1] = k.t; T[2] = cur;
-                PT[0] = v; PT[1] = pk; PT[2] = pcur;
+                T0 = n0; T1 = k.t; T2 = cur;
+                P0 = v; P1 = pk; P2 = pcur;
                 found = true;
                 break;
             }
@@ -607,40 +608,40 @@ __device__ int delaunay_node(G& g, double2 q, int T[3], S_& S, int32_t* vis) {
     bool walked = false;
     for (int step = 0;; ++step) {
         int we;
-        if (orient(PT[1], PT[2], q) < 0.0) we = 1;
-        else if (orient(PT[2], PT[0], q) < 0.0) we = 2;
-        else if (orient(PT[0], PT[1], q) < 0.0) we = 0;
+        if (orient(P1, P2, q) < 0.0) we = 1;
+        else if (orient(P2, P0, q) < 0.0) we = 2;
+        else if (orient(P0, P1, q) < 0.0) we = 0;
         else break;
         if (step >= 256) return R_FAIL;
         // across edge X -> Y lies the triangle (Y, X, D), D left of Y -> X
         const int w1 = we == 2 ? 0 : we + 1;
-        const int tX = sel3(T, we), tY = sel3(T, w1);
-        const double2 qX = sel3(PT, we), qY = sel3(PT, w1);
+        const int tX = tsel(we), tY = tsel(w1);
+        const double2 qX = psel(we), qY = psel(w1);
         const Key k = g.wrap(tY, qY, tX, qX, 1.0);
         if (k.t == -2) return R_MORE;
         if (k.t < 0) return g.global() ? R_OUTSIDE : R_MORE;
         circumcircle(k, qY, qX, 1.0, cx, cy, rr);
         if (!g.certify(cx, cy, rr)) return R_MORE;
-        T[0] = tY; T[1] = tX; T[2] = k.t;
-        PT[0] = qY; PT[1] = qX; PT[2] = make_double2(k.bx, k.by);
+        T0 = tY; T1 = tX; T2 = k.t;
+        P0 = qY; P1 = qX; P2 = make_double2(k.bx, k.by);
         walked = true;
     }
 
     // ---- the three rings
-    bool reuse0 = !walked && nvis > 0 && T[0] == n0 && T[1] == vis[nvis - 1];
+    bool reuse0 = !walked && nvis > 0 && T0 == n0 && T1 == vis[nvis - 1];
     bool chain = true;   // no open fan so far: the shared-triangle shortcuts hold
     bool cwise = false;  // rotating clockwise through the rest of an open fan
     int x0 = -1;         // first apex of ring 0 (across edge T0-T2)
     int nrot = 0;        // apexes found by rotation in the current ring
     int rk = 0;
-    if (!S.add(T[1], 1) || !S.add(T[2], 1)) return R_CAP;
-    cur = T[2];
-    pcur = PT[2];
+    if (!S.add(T1, 1) || !S.add(T2, 1)) return R_CAP;
+    cur = T2;
+    pcur = P2;
     for (int it = 0; it < 8 * KMAX; ++it) {
         const int f = rk == 2 ? 0 : rk + 1;
-        const int first = sel3(T, f);
-        const double2 pf = sel3(PT, f);
-        const double2 pvk = sel3(PT, rk);
+        const int first = tsel(f);
+        const double2 pf = psel(f);
+        const double2 pvk = psel(rk);
         bool closed = false;
         int pred = cur;  // apex preceding `first` when the ring closes
         double2 ppred = pcur;
@@ -650,7 +651,7 @@ __device__ int delaunay_node(G& g, double2 q, int T[3], S_& S, int32_t* vis) {
             closed = true;  // ring 2 reached x0: the next apex is T[0]
         } else {
             const double sgn = cwise ? -1.0 : 1.0;
-            const Key k = g.wrap(sel3(T, rk), pvk, cur, pcur, sgn);
+            const Key k = g.wrap(tsel(rk), pvk, cur, pcur, sgn);
             if (k.t == -2) return R_MORE;
             nt = k.t;
             pk = make_double2(k.bx, k.by);
@@ -686,19 +687,24 @@ __device__ int delaunay_node(G& g, double2 q, int T[3], S_& S, int32_t* vis) {
             }
         }
         if (closed) {
-            if (++rk == 3) return R_OK;
+            if (++rk == 3) {
+                Tout[0] = T0;
+                Tout[1] = T1;
+                Tout[2] = T2;
+                return R_OK;
+            }
             cwise = false;
             const int f1 = rk == 2 ? 0 : rk + 1, f2 = rk == 0 ? 2 : rk - 1;
-            if (!S.add(sel3(T, f1), 1 << rk) || !S.add(sel3(T, f2), 1 << rk)) return R_CAP;
-            if (chain && pred != sel3(T, f2)) {
+            if (!S.add(tsel(f1), 1 << rk) || !S.add(tsel(f2), 1 << rk)) return R_CAP;
+            if (chain && pred != tsel(f2)) {
                 // the first apex of this ring is the one that preceded
                 // `first` in the ring just closed
                 if (!S.add(pred, 1 << rk)) return R_CAP;
                 cur = pred;
                 pcur = ppred;
             } else {
-                cur = sel3(T, f2);
-                pcur = sel3(PT, f2);
+                cur = tsel(f2);
+                pcur = psel(f2);
             }
             nrot = 0;
         } else {
@@ -1480,7 +1486,10 @@ __device__ __forceinline__ void weights_node(const KArgs& a, const SetDesc& sd, 
             const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
             sc = 1.0 / sqrt(dxv * dxv + dyv * dyv);
             mask = (1 << lane) | (1 << pb);
-            coef = 2.0 * phi[lane] * phi[pb];
+            // selected by value: a run-time index would put phi in scratch
+            const double pa_ = lane == 0 ? phi[0] : (lane == 1 ? phi[1] : phi[2]);
+            const double pb_ = pb == 0 ? phi[0] : (pb == 1 ? phi[1] : phi[2]);
+            coef = 2.0 * pa_ * pb_;
             const double dx = dxv * sc, dy = dyv * sc;
             // eq. A2_2 in the edge frame (eqs. A0, A1 give the zero rows)
             const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
