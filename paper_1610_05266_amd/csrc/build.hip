@@ -56,7 +56,7 @@ constexpr double EPS = DBL_EPSILON;
 constexpr int WAVE = 64;
 constexpr int SWG = 256;       // slow kernel: four waves, one node per wave
 constexpr int QL = 4;          // lanes per node in the quad kernels
-constexpr int NS = 10;         // candidate slots per lane (fast kernel)
+constexpr int NS_MAX = 10;     // candidate slots per lane (fast kernel), at most
 constexpr int QWG = 256;       // quad kernels: 64 nodes per block
 constexpr int QPB = QWG / QL;
 constexpr int MS = KMAX / QL;  // support entries per lane
@@ -374,6 +374,7 @@ struct WaveSource {
 // Four lanes of a quad hold the node's candidates (particles within Rf of
 // the node q) in registers; every query is a lane-local loop plus a
 // two-step reduction, after which all four lanes agree on the answer.
+template <int NS>
 struct QuadSource {
     const double2* __restrict__ pos;
     const int32_t* __restrict__ perm;
@@ -1106,11 +1107,21 @@ __device__ void quad_closure(const KArgs& a, int64_t node, double2 q, int n, int
 // bits) for k_weights.  Boundary-ring nodes: the KNN nearest particles,
 // picked one per round (smallest squared distance, ties by user id), as a
 // pending closure row.  Anything not certified goes to the slow list.
+constexpr int TCAP = 2048;  // particles of a tile's bin region staged in LDS
+constexpr int TDIM = 48;    // bin rows / columns of that region (at most)
+
+template <int NS>
 __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     // per-quad rows padded by one word: the 16 quads of a wave then hit
     // distinct LDS banks when they touch the same slot
     __shared__ int32_t su[QPB * KPITCH];
     __shared__ int32_t svis[QPB * KPITCH];
+    // the tile's bin region (its nodes' search windows): bin starts, row
+    // bases and the particles, copied once with coalesced row reads
+    __shared__ double2 tpos[TCAP];
+    __shared__ int32_t tsi[TCAP];
+    __shared__ int32_t tst[TDIM * (TDIM + 1)];
+    __shared__ int32_t trb[TDIM + 1];
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const SetDesc sd = tile_set(a, blockIdx.x);
@@ -1123,8 +1134,47 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
     const int32_t* start = a.start + sd.b0;
     bool done = false;
+    // ---- stage the region (block-uniform decision)
+    const int hcor = static_cast<int>(ceil(sd.Rc * 1.4142135623730951 / sd.g.bw));
+    const int hmax = max(max(sd.hwf, sd.hwc), hcor);
+    const int rbx0 = max(tx * 8 * sd.g.kb - hmax, 0);
+    const int rbx1 = min(min(tx * 8 + 7, sd.m.nx) * sd.g.kb + hmax, sd.g.nbx);
+    const int rby0 = max(ty * 8 * sd.g.kb - hmax, 0);
+    const int rby1 = min(min(ty * 8 + 7, sd.m.ny) * sd.g.kb + hmax, sd.g.nby);
+    const int ncol = rbx1 - rbx0, nrow = rby1 - rby0;
+    bool staged = ncol <= TDIM && nrow <= TDIM;
+    if (staged) {
+        for (int e = threadIdx.x; e < nrow * (ncol + 1); e += QWG) {
+            const int r = e / (ncol + 1), c = e - r * (ncol + 1);
+            tst[r * (TDIM + 1) + c] = start[(rby0 + r) * sd.g.nbx + rbx0 + c];
+        }
+        __syncthreads();
+        if (threadIdx.x <= nrow) {
+            int acc = 0;
+            for (int r = 0; r < static_cast<int>(threadIdx.x); ++r)
+                acc += tst[r * (TDIM + 1) + ncol] - tst[r * (TDIM + 1)];
+            trb[threadIdx.x] = acc;
+        }
+        __syncthreads();
+        const int total = trb[nrow];
+        staged = total <= TCAP;
+        if (staged) {
+            for (int e = threadIdx.x; e < total; e += QWG) {
+                int lo = 0, hi = nrow - 1;  // the row holding staged entry e
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (trb[mid] <= e) lo = mid;
+                    else hi = mid - 1;
+                }
+                const int src = tst[lo * (TDIM + 1)] + (e - trb[lo]);
+                tpos[e] = a.pos_s[src];
+                tsi[e] = src;
+            }
+        }
+        __syncthreads();
+    }
     if (valid) {
-        QuadSource g;
+        QuadSource<NS> g;
         g.pos = a.pos_s;
         g.perm = a.perm;
         g.q = node_pos(sd.m, i, j);
@@ -1142,27 +1192,38 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
         const int by0 = max(cby - hw, 0), by1 = min(cby + hw, sd.g.nby);
         int ovf = 0;
         int flat = 0;
-        for (int by = by0; by < by1; ++by) {
-            const int row = by * sd.g.nbx;
-            const int s = start[row + bx0], e = start[row + bx1];
-            for (int t = s + ((lane - flat) & (QL - 1)); t < e; t += QL) {
-                const double2 p = a.pos_s[t];
-                const double dx = p.x - g.q.x, dy = p.y - g.q.y;
-                if (dx * dx + dy * dy > R2) continue;
-                if (g.n >= NS) {
-                    ovf = 1;
-                    continue;
-                }
-#pragma unroll
-                for (int k = 0; k < NS; ++k)
-                    if (k == g.n) {
-                        g.cx_[k] = p.x;
-                        g.cy_[k] = p.y;
-                        g.ct_[k] = t;
-                    }
-                ++g.n;
+        auto take = [&](double2 p, int t) {
+            const double dx = p.x - g.q.x, dy = p.y - g.q.y;
+            if (dx * dx + dy * dy > R2) return;
+            if (g.n >= NS) {
+                ovf = 1;
+                return;
             }
-            flat += e - s;
+#pragma unroll
+            for (int k = 0; k < NS; ++k)
+                if (k == g.n) {
+                    g.cx_[k] = p.x;
+                    g.cy_[k] = p.y;
+                    g.ct_[k] = t;
+                }
+            ++g.n;
+        };
+        if (staged) {
+            // the same particles in the same order as the global walk below
+            for (int by = by0; by < by1; ++by) {
+                const int* rs = tst + (by - rby0) * (TDIM + 1);
+                const int base = trb[by - rby0] - rs[0];
+                const int s = base + rs[bx0 - rbx0], e = base + rs[bx1 - rbx0];
+                for (int t = s + ((lane - flat) & (QL - 1)); t < e; t += QL) take(tpos[t], tsi[t]);
+                flat += e - s;
+            }
+        } else {
+            for (int by = by0; by < by1; ++by) {
+                const int row = by * sd.g.nbx;
+                const int s = start[row + bx0], e = start[row + bx1];
+                for (int t = s + ((lane - flat) & (QL - 1)); t < e; t += QL) take(a.pos_s[t], t);
+                flat += e - s;
+            }
         }
         ovf |= lane_xor<QL>(ovf, 1);
         ovf |= lane_xor<QL>(ovf, 2);
@@ -1680,8 +1741,8 @@ __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
 }  // namespace
 
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
-                  const BuildOut& out, int levels, int32_t* slow, int32_t* rd, unsigned long long* diag,
-                  const SideWork& side, hipStream_t st) {
+                  const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd,
+                  unsigned long long* diag, const SideWork& side, hipStream_t st) {
     PhaseTimer _timer(PH_BUILD, st);
     if (n_tiles >= (int64_t(1) << 31)) {
         set_error("too many node tiles (%lld)", static_cast<long long>(n_tiles));
@@ -1702,7 +1763,10 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     const int tiles = static_cast<int>(n_tiles);
     {
         PhaseTimer t1(PH_BUILD_FAST, st);
-        k_build_fast<<<tiles, QWG, 0, st>>>(a);
+        // slots per lane for the expected candidate count of an interior
+        // node (pi (Rf/h)^2 over four lanes, with room for fluctuation)
+        if (fast_slots <= 8) k_build_fast<8><<<tiles, QWG, 0, st>>>(a);
+        else k_build_fast<NS_MAX><<<tiles, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());
     // The few nodes the fast pass could not certify take the exact wave path

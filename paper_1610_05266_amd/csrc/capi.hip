@@ -15,6 +15,8 @@ namespace p2m {
 namespace {
 thread_local std::string g_err = "no error";
 
+constexpr int NS_FAST_MAX = 10;  // candidate slots per lane of the fast pass, at most
+
 // Process-wide tuning knobs (set with p2m_set_option).
 struct Tuning {
     double bin_scale = 1.0;       // bin width ~ bin_scale * h
@@ -349,8 +351,12 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     SideWork side{nullptr, w->ev_fork, w->ev_join};
     rc = side_stream(dev, &side.stream);
     if (rc) return rc;
-    return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, w->slow, w->rd, w->diag,
-                         side, st);
+    // 8 slots per lane hold pi (Rf/h)^2 <= 26 candidates with a margin for
+    // the fluctuation of the count; larger radii take 10
+    const double expect = 3.14159265358979 * g_tune.fast_radius * g_tune.fast_radius;
+    const int slots = expect <= 26.0 ? 8 : NS_FAST_MAX;
+    return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, slots, w->slow, w->rd,
+                         w->diag, side, st);
 }
 
 // Per-device workspace of the fused (recompute) entry points: a weights
