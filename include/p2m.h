@@ -300,6 +300,13 @@ int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, 
  * Returns P2M_EINVAL for an unknown name or a value out of range. */
 int p2m_set_option(const char* name, double value);
 
+/* Current value of a tuning knob above, written to *value (host pointer).
+ * One derived, read-only name as well:
+ *   "fast_slots" candidate slots per lane of the first pass that builds
+ *                launched with the current fast_radius use (8 or 10).
+ * Returns P2M_EINVAL for an unknown name or a NULL pointer. */
+int p2m_get_option(const char* name, double* value);
+
 /* Event timing of the library's kernel groups, for measurement.
  * p2m_profile_enable(1) clears the totals and starts recording a pair of HIP
  * events on the caller's stream around each group ("bin", "build",

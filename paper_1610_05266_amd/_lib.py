@@ -84,6 +84,7 @@ _SIGS = {
     "p2m_last_error": (c_char_p, []),
     "p2m_version": (c_char_p, []),
     "p2m_set_option": (c_int, [c_char_p, c_double]),
+    "p2m_get_option": (c_int, [c_char_p, POINTER(c_double)]),
     "p2m_profile_enable": (c_int, [c_int]),
     "p2m_profile_read": (c_int, [c_char_p, POINTER(c_double), POINTER(c_int64)]),
 }

@@ -894,6 +894,31 @@ __device__ __forceinline__ SetDesc tile_set(const KArgs& a, int64_t tile) {
     const int si = set_search(a.S, tile, [&](int s) { return a.sets[s].t0; });
     return a.sets[si];
 }
+// Tile tl of a set's 8 x 8 node tiles: the full tiles first (row-major),
+// then the partial tiles of the last column and of the last row.  The
+// hardware dispatches blocks in index order and a launch holds a fixed
+// number of blocks at a time, so full tiles taken in whole rounds and the
+// cheap partial ones filling the last slots finish earlier than the row-major
+// order, which leaves full tiles for a nearly empty last round.
+__device__ __forceinline__ void tile_xy(const SetDesc& sd, int tl, int& tx, int& ty) {
+    const int fx = (sd.m.nx + 1) / 8, fy = (sd.m.ny + 1) / 8;  // full tile columns, rows
+    if (tl < fx * fy) {
+        tx = tl % fx;
+        ty = tl / fx;
+        return;
+    }
+    int r = tl - fx * fy;
+    if (sd.tiles_x > fx) {
+        if (r < fy) {
+            tx = fx;
+            ty = r;
+            return;
+        }
+        r -= fy;
+    }
+    tx = r;
+    ty = fy;
+}
 __device__ __forceinline__ SetDesc node_set(const KArgs& a, int64_t node) {
     const int si = set_search(a.S, node, [&](int s) { return a.sets[s].n0; });
     return a.sets[si];
@@ -1125,8 +1150,8 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const SetDesc sd = tile_set(a, blockIdx.x);
-    const int tl = static_cast<int>(blockIdx.x - sd.t0);
-    const int tx = tl % sd.tiles_x, ty = tl / sd.tiles_x;
+    int tx, ty;
+    tile_xy(sd, static_cast<int>(blockIdx.x - sd.t0), tx, ty);
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
     const int64_t node = sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;
@@ -1678,8 +1703,8 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const SetDesc sd = tile_set(a, blockIdx.x);
-    const int tl = static_cast<int>(blockIdx.x - sd.t0);
-    const int tx = tl % sd.tiles_x, ty = tl / sd.tiles_x;
+    int tx, ty;
+    tile_xy(sd, static_cast<int>(blockIdx.x - sd.t0), tx, ty);
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
     const int64_t node = sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;

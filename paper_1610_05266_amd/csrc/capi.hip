@@ -25,6 +25,13 @@ struct Tuning {
     double closure_radius = 4.0;  // fast path, boundary ring: candidate radius / h
     int levels = 3;               // doublings before the global scan
 } g_tune;
+
+// 8 candidate slots per lane hold pi (Rf/h)^2 <= 26 expected candidates with
+// a margin for the fluctuation of the count; larger radii take 10
+int fast_slots() {
+    const double expect = 3.14159265358979 * g_tune.fast_radius * g_tune.fast_radius;
+    return expect <= 26.0 ? 8 : NS_FAST_MAX;
+}
 }  // namespace
 
 void set_error(const char* fmt, ...) {
@@ -351,12 +358,8 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     SideWork side{nullptr, w->ev_fork, w->ev_join};
     rc = side_stream(dev, &side.stream);
     if (rc) return rc;
-    // 8 slots per lane hold pi (Rf/h)^2 <= 26 candidates with a margin for
-    // the fluctuation of the count; larger radii take 10
-    const double expect = 3.14159265358979 * g_tune.fast_radius * g_tune.fast_radius;
-    const int slots = expect <= 26.0 ? 8 : NS_FAST_MAX;
-    return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, slots, w->slow, w->rd,
-                         w->diag, side, st);
+    return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, fast_slots(), w->slow,
+                         w->rd, w->diag, side, st);
 }
 
 // Per-device workspace of the fused (recompute) entry points: a weights
@@ -412,6 +415,30 @@ int p2m_set_option(const char* name, double value) {
         g_tune.levels = static_cast<int>(value);
     } else {
         set_error("unknown option or value out of range: %s=%g", name, value);
+        return P2M_EINVAL;
+    }
+    return P2M_OK;
+}
+
+int p2m_get_option(const char* name, double* value) {
+    if (!name || !value) {
+        set_error("p2m_get_option: NULL name or value pointer");
+        return P2M_EINVAL;
+    }
+    if (!std::strcmp(name, "bin_scale")) {
+        *value = g_tune.bin_scale;
+    } else if (!std::strcmp(name, "region_h")) {
+        *value = g_tune.region_h;
+    } else if (!std::strcmp(name, "fast_radius")) {
+        *value = g_tune.fast_radius;
+    } else if (!std::strcmp(name, "closure_radius")) {
+        *value = g_tune.closure_radius;
+    } else if (!std::strcmp(name, "levels")) {
+        *value = g_tune.levels;
+    } else if (!std::strcmp(name, "fast_slots")) {
+        *value = fast_slots();
+    } else {
+        set_error("unknown option: %s", name);
         return P2M_EINVAL;
     }
     return P2M_OK;

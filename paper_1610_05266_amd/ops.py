@@ -24,6 +24,7 @@ __all__ = [
     "p2m_project_backward",
     "p2m_build_weights_backward",
     "p2m_set_option",
+    "p2m_get_option",
     "p2m_project_fused",
     "p2m_backward_fused",
     "Batch",
@@ -142,6 +143,12 @@ class Weights:
 
 def p2m_set_option(name: str, value: float):
     check(load().p2m_set_option(name.encode(), float(value)))
+
+
+def p2m_get_option(name: str) -> float:
+    out = ctypes.c_double()
+    check(load().p2m_get_option(name.encode(), ctypes.byref(out)))
+    return out.value
 
 
 def p2m_build_weights(mesh, h: float, pos: torch.Tensor, flags: int = 0,

@@ -62,6 +62,24 @@ def test_options():
     assert lib.p2m_set_option(b"region_h", 1000.0) == -1
 
 
+def test_get_option_reads_back_and_derives_slots():
+    lib = pkg.load()
+    v = ctypes.c_double()
+    try:
+        assert lib.p2m_set_option(b"fast_radius", 2.8) == 0
+        assert lib.p2m_get_option(b"fast_radius", ctypes.byref(v)) == 0 and v.value == 2.8
+        # pi * 2.8^2 = 24.6 expected candidates fit 8 slots per lane, pi * 3^2 = 28.3 need 10
+        assert lib.p2m_get_option(b"fast_slots", ctypes.byref(v)) == 0 and v.value == 8
+        assert lib.p2m_set_option(b"fast_radius", 3.0) == 0
+        assert lib.p2m_get_option(b"fast_slots", ctypes.byref(v)) == 0 and v.value == 10
+        assert lib.p2m_get_option(b"levels", ctypes.byref(v)) == 0 and v.value == 3
+        assert lib.p2m_get_option(b"nonsense", ctypes.byref(v)) == -1
+        assert lib.p2m_get_option(b"levels", None) == -1
+        assert b"NULL" in lib.p2m_last_error()
+    finally:
+        lib.p2m_set_option(b"fast_radius", 2.8)
+
+
 def test_batch_argument_validation_without_device():
     lib = pkg.load()
     out = ctypes.c_void_p(0)
