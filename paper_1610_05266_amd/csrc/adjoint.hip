@@ -168,16 +168,17 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
     const int tid = threadIdx.x;
     const int64_t node = static_cast<int64_t>(blockIdx.x) * WG + tid;
     if (node >= a.w.n_nodes) return;
-    const uint32_t meta = a.w.meta[node];
-    const uint32_t type = meta_type(meta);
-    const int n = row_len(meta);
-    if (type == NT_FAILED || n == 0) return;
-    const int64_t nn = a.w.n_nodes;
     const SetDesc& sd = a.w.sets[set_search(a.w.S, node, [&](int s) { return a.w.sets[s].n0; })];
     const MeshD m = sd.m;
     const int stride = m.nx + 1;
     const int64_t ln = node - sd.n0;
     const int i = static_cast<int>(ln % stride), j = static_cast<int>(ln / stride);
+    const int64_t slot = node_slot(sd, i, j);
+    const uint32_t meta = a.w.meta[slot];
+    const uint32_t type = meta_type(meta);
+    const int n = row_len(meta);
+    if (type == NT_FAILED || n == 0) return;
+    const int64_t nn = a.w.n_nodes, ns = a.w.n_slots;
     const double2 q = node_pos(m, i, j);
     double* gx = sgx + tid;
     double* gy = sgy + tid;
@@ -185,7 +186,7 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
         gx[k * WG] = 0.0;
         gy[k * WG] = 0.0;
     }
-    auto P = [&](int k) { return a.pos[a.w.idx[k * nn + node]]; };
+    auto P = [&](int k) { return a.pos[a.w.idx[k * ns + slot]]; };
     auto wbar = [&](int k) { return a.gw[k * nn + node]; };
     auto add = [&](int k, double dx, double dy) {
         gx[k * WG] += dx;
@@ -208,7 +209,7 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
             const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
             const double is = 1.0 / sqrt(dxv * dxv + dyv * dyv);
             const int mask = (1 << pa) | (1 << pb);
-            auto member = [&](int k) { return (a.w.mem[k * nn + node] & mask) != 0; };
+            auto member = [&](int k) { return (a.w.mem[k * ns + slot] & mask) != 0; };
             auto coord = [&](int k, double& x, double& y) {
                 const double2 p = P(k);
                 x = (p.x - cxm) * is;
@@ -273,7 +274,7 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
         block_backward(n, member, coord, b, wbar, addsc, y, bb);
     }
     for (int k = 0; k < n; ++k) {
-        const int64_t u = a.w.idx[k * nn + node];
+        const int64_t u = a.w.idx[k * ns + slot];
         atomicAdd(&a.gpos[u].x, gx[k * WG]);
         atomicAdd(&a.gpos[u].y, gy[k * WG]);
     }
@@ -283,18 +284,21 @@ __global__ void __launch_bounds__(256) k_export(WeightsView w, int32_t* __restri
                                                 int32_t* __restrict__ cnt, int32_t* __restrict__ tri) {
     const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (node >= w.n_nodes) return;
-    const uint32_t meta = w.meta[node];
+    const SetDesc& sd = w.sets[set_search(w.S, node, [&](int s) { return w.sets[s].n0; })];
+    const int64_t ln = node - sd.n0;
+    const int64_t slot = node_slot(sd, static_cast<int>(ln % (sd.m.nx + 1)), static_cast<int>(ln / (sd.m.nx + 1)));
+    const uint32_t meta = w.meta[slot];
     const int n = row_len(meta);
-    const int64_t nn = w.n_nodes;
+    const int64_t nn = w.n_nodes, ns = w.n_slots;
     for (int k = 0; k < KMAX; ++k) {
-        if (idx) idx[k * nn + node] = k < n ? w.idx[k * nn + node] : -1;
-        if (wts) wts[k * nn + node] = k < n ? w.w64[k * nn + node] : 0.0;
+        if (idx) idx[k * nn + node] = k < n ? w.idx[k * ns + slot] : -1;
+        if (wts) wts[k * nn + node] = k < n ? w.w64[k * ns + slot] : 0.0;
     }
     if (cnt) cnt[node] = n;
     if (tri) {
         const bool in = meta_type(meta) == NT_INTERIOR;
         for (int k = 0; k < 3; ++k)
-            tri[node * 3 + k] = in ? w.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + node] : -1;
+            tri[node * 3 + k] = in ? w.idx[static_cast<int64_t>(meta_t(meta, k)) * ns + slot] : -1;
     }
 }
 

@@ -152,7 +152,7 @@ __global__ void __launch_bounds__(256) k_scan_add(int32_t* __restrict__ out, int
 // user id) records.
 constexpr int PART_PER_THREAD = 2;  // sub <= PART_PER_THREAD * BT
 
-__device__ void block_exclusive_scan(const int32_t* in, int32_t* out, int n, int32_t* part) {
+__device__ __forceinline__ void block_exclusive_scan(const int32_t* in, int32_t* out, int n, int32_t* part) {
     const int per = (n + BT - 1) / BT;
     const int r0 = threadIdx.x * per;
     int acc = 0;
@@ -195,17 +195,25 @@ __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos
         const int n = static_cast<int>(min<int64_t>(sub, hi - b0));
         for (int k = threadIdx.x; k < nsb; k += BT) lcnt[k] = 0;
         __syncthreads();
+        // loads at clamped indices (n >= 1), so that the staging arrays stay
+        // in registers; only real elements are counted and placed
+        // (coordinates as plain doubles: an array of the vector type would be
+        // kept in scratch memory across the scan)
         uint32_t kk[PART_PER_THREAD];
         int rr[PART_PER_THREAD];
-        double2 pp[PART_PER_THREAD];
+        double px[PART_PER_THREAD], py[PART_PER_THREAD];
+#pragma unroll
+        for (int j = 0; j < PART_PER_THREAD; ++j) {
+            const int e = min(static_cast<int>(threadIdx.x) + j * BT, n - 1);
+            kk[j] = key[b0 + e];
+            const double2 p = pos[b0 + e];
+            px[j] = p.x;
+            py[j] = p.y;
+        }
 #pragma unroll
         for (int j = 0; j < PART_PER_THREAD; ++j) {
             const int e = threadIdx.x + j * BT;
-            if (e < n) {
-                kk[j] = key[b0 + e];
-                pp[j] = pos[b0 + e];
-                rr[j] = atomicAdd(&lcnt[kk[j] >> bg.sbs], 1);
-            }
+            rr[j] = e < n ? atomicAdd(&lcnt[kk[j] >> bg.sbs], 1) : 0;
         }
         __syncthreads();
         block_exclusive_scan(lcnt, lstart, nsb, part);
@@ -214,7 +222,7 @@ __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos
             const int e = threadIdx.x + j * BT;
             if (e < n) {
                 const int sl = lstart[kk[j] >> bg.sbs] + rr[j];
-                spos[sl] = pp[j];
+                spos[sl] = make_double2(px[j], py[j]);
                 skey[sl] = kk[j];
                 suid[sl] = static_cast<int32_t>(b0 + e);
             }

@@ -883,46 +883,20 @@ struct KArgs {
     int S;
     int levels;           // slow path: region doublings before the global scan
     int64_t n_nodes;      // all sets
+    int64_t n_slots;      // ELL row slots of all sets (TILE_N per node tile)
     BuildOut out;
-    int32_t* slow;        // slow-path node list (capacity n_nodes)
-    int32_t* rd;          // rank-deficient node list (capacity n_nodes)
+    int32_t* slow;        // slow-path list of row slots (capacity n_nodes)
+    int32_t* rd;          // rank-deficient list of row slots (capacity n_nodes)
+    int32_t* tdiag;       // [n_slots / TILE_N][4] per-tile counts of k_weights
     unsigned long long* diag;
 };
 
-// The set of a node tile / a node, and the tile's node (i, j) for a quad.
+// The set of a node tile / of a row slot.
 __device__ __forceinline__ SetDesc tile_set(const KArgs& a, int64_t tile) {
     const int si = set_search(a.S, tile, [&](int s) { return a.sets[s].t0; });
     return a.sets[si];
 }
-// Tile tl of a set's 8 x 8 node tiles: the full tiles first (row-major),
-// then the partial tiles of the last column and of the last row.  The
-// hardware dispatches blocks in index order and a launch holds a fixed
-// number of blocks at a time, so full tiles taken in whole rounds and the
-// cheap partial ones filling the last slots finish earlier than the row-major
-// order, which leaves full tiles for a nearly empty last round.
-__device__ __forceinline__ void tile_xy(const SetDesc& sd, int tl, int& tx, int& ty) {
-    const int fx = (sd.m.nx + 1) / 8, fy = (sd.m.ny + 1) / 8;  // full tile columns, rows
-    if (tl < fx * fy) {
-        tx = tl % fx;
-        ty = tl / fx;
-        return;
-    }
-    int r = tl - fx * fy;
-    if (sd.tiles_x > fx) {
-        if (r < fy) {
-            tx = fx;
-            ty = r;
-            return;
-        }
-        r -= fy;
-    }
-    tx = r;
-    ty = fy;
-}
-__device__ __forceinline__ SetDesc node_set(const KArgs& a, int64_t node) {
-    const int si = set_search(a.S, node, [&](int s) { return a.sets[s].n0; });
-    return a.sets[si];
-}
+__device__ __forceinline__ SetDesc slot_set(const KArgs& a, int64_t slot) { return tile_set(a, slot / TILE_N); }
 
 __device__ __forceinline__ uint32_t pending_type(uint32_t t) { return t == NT_OUTSIDE ? NT_PEND_OUT : NT_PEND_RING; }
 
@@ -930,7 +904,7 @@ __device__ __forceinline__ uint32_t pending_type(uint32_t t) { return t == NT_OU
 // The support entries come from `uget(k)` (sorted index | bits << 28); entry
 // k belongs to lane k % 4.
 template <class UGet>
-__device__ void quad_weights(const KArgs& a, int64_t node, double2 q, UGet uget, int n, const int T[3], int lane,
+__device__ void quad_weights(const KArgs& a, int64_t slot, double2 q, UGet uget, int n, const int T[3], int lane,
                              uint32_t flags) {
     int mt[MS];
     int mb[MS];
@@ -1029,17 +1003,17 @@ __device__ void quad_weights(const KArgs& a, int64_t node, double2 q, UGet uget,
             mw[s] += coef * dot6(p, y);
         }
     }
-    const int64_t nn = a.n_nodes;
+    const int64_t nn = a.n_slots;
 #pragma unroll
     for (int s = 0; s < MS; ++s) {
         const int k = s * QL + lane;
         if (k >= n) continue;
-        a.out.idx[k * nn + node] = a.perm[mt[s]];
-        a.out.w64[k * nn + node] = mw[s];
-        if (a.out.w32) a.out.w32[k * nn + node] = static_cast<float>(mw[s]);
-        a.out.mem[k * nn + node] = static_cast<uint8_t>(mb[s]);
+        a.out.idx[k * nn + slot] = a.perm[mt[s]];
+        a.out.w64[k * nn + slot] = mw[s];
+        if (a.out.w32) a.out.w32[k * nn + slot] = static_cast<float>(mw[s]);
+        a.out.mem[k * nn + slot] = static_cast<uint8_t>(mb[s]);
     }
-    if (lane == 0) a.out.meta[node] = meta_pack(NT_INTERIOR, n, lt[0], lt[1], lt[2], flags);
+    if (lane == 0) a.out.meta[slot] = meta_pack(NT_INTERIOR, n, lt[0], lt[1], lt[2], flags);
 }
 
 // Closure weights of one node from its nearest particles (sorted indices in
@@ -1049,9 +1023,9 @@ __device__ void quad_weights(const KArgs& a, int64_t node, double2 q, UGet uget,
 // centre and scale; these keep the system well conditioned).
 constexpr int MC = (KNN + QL - 1) / QL;
 
-__device__ void quad_closure(const KArgs& a, int64_t node, double2 q, int n, int lane, uint32_t type,
+__device__ void quad_closure(const KArgs& a, int64_t slot, double2 q, int n, int lane, uint32_t type,
                              uint32_t flags) {
-    const int64_t nn = a.n_nodes;
+    const int64_t nn = a.n_slots;
     int mt[MC];
     double mx[MC], my[MC];
     double sx = 0.0, sy = 0.0;
@@ -1061,7 +1035,7 @@ __device__ void quad_closure(const KArgs& a, int64_t node, double2 q, int n, int
         mt[s] = -1;
         mx[s] = my[s] = 0.0;
         if (k < n) {
-            mt[s] = a.out.idx[k * nn + node];
+            mt[s] = a.out.idx[k * nn + slot];
             const double2 p = a.pos_s[mt[s]];
             mx[s] = p.x;
             my[s] = p.y;
@@ -1118,12 +1092,12 @@ __device__ void quad_closure(const KArgs& a, int64_t node, double2 q, int n, int
         double p[6];
         monos((mx[s] - cx) * isc, (my[s] - cy) * isc, p);
         const double w = dot6(p, y);
-        a.out.idx[k * nn + node] = a.perm[mt[s]];
-        a.out.w64[k * nn + node] = w;
-        if (a.out.w32) a.out.w32[k * nn + node] = static_cast<float>(w);
-        a.out.mem[k * nn + node] = 0;
+        a.out.idx[k * nn + slot] = a.perm[mt[s]];
+        a.out.w64[k * nn + slot] = w;
+        if (a.out.w32) a.out.w32[k * nn + slot] = static_cast<float>(w);
+        a.out.mem[k * nn + slot] = 0;
     }
-    if (lane == 0) a.out.meta[node] = meta_pack(type, n, 0, 0, 0, flags);
+    if (lane == 0) a.out.meta[slot] = meta_pack(type, n, 0, 0, 0, flags);
 }
 
 // ------------------------------------------------------------ fast kernel
@@ -1154,8 +1128,8 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     tile_xy(sd, static_cast<int>(blockIdx.x - sd.t0), tx, ty);
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
-    const int64_t node = sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;
-    const int64_t nn = a.n_nodes;
+    const int64_t slot = static_cast<int64_t>(blockIdx.x) * TILE_N + qi;
+    const int64_t nn = a.n_slots;
     const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
     const int32_t* start = a.start + sd.b0;
     bool done = false;
@@ -1264,10 +1238,10 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
                 if (lt0 >= 0 && lt1 >= 0 && lt2 >= 0) {
                     for (int k = lane; k < S.n; k += QL) {
                         const uint32_t e = static_cast<uint32_t>(S.u[k]);
-                        a.out.idx[k * nn + node] = static_cast<int32_t>(e & IDX_MASK);
-                        a.out.mem[k * nn + node] = static_cast<uint8_t>(e >> 28);
+                        a.out.idx[k * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
+                        a.out.mem[k * nn + slot] = static_cast<uint8_t>(e >> 28);
                     }
-                    if (lane == 0) a.out.meta[node] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, 0u);
+                    if (lane == 0) a.out.meta[slot] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, 0u);
                     done = true;
                 }
             }
@@ -1301,8 +1275,8 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
                 }
                 if (bt < 0) break;
                 if (lane == 0) {
-                    a.out.idx[r * nn + node] = bt;
-                    a.out.mem[r * nn + node] = 0;
+                    a.out.idx[r * nn + slot] = bt;
+                    a.out.mem[r * nn + slot] = 0;
                 }
                 pd = bd;
                 pt = bt;
@@ -1311,17 +1285,18 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
             }
             // certified when the K-th distance is inside the gathered disk
             if (found == KNN && sqrt(pd) <= g.Rf * (1.0 - 1e-12)) {
-                if (lane == 0) a.out.meta[node] = meta_pack(NT_PEND_RING, KNN, 0, 0, 0, 0u);
+                if (lane == 0) a.out.meta[slot] = meta_pack(NT_PEND_RING, KNN, 0, 0, 0, 0u);
                 done = true;
             }
         }
     }
+    if (!valid && lane == 0) a.out.meta[slot] = meta_pack(NT_FAILED, 0, 0, 0, 0, 0u);  // beyond the mesh
     if (valid && !done && lane == 0) {
         // an empty row until the slow path writes it, so that no node is ever
         // left with the metadata of an earlier build (or of fresh memory)
-        a.out.meta[node] = meta_pack(NT_FAILED, 0, 0, 0, 0, 0u);
-        const int slot = static_cast<int>(atomicAdd(&a.diag[D_SLOWCNT], 1ull));
-        a.slow[slot] = static_cast<int32_t>(node);
+        a.out.meta[slot] = meta_pack(NT_FAILED, 0, 0, 0, 0, 0u);
+        const int lpos = static_cast<int>(atomicAdd(&a.diag[D_SLOWCNT], 1ull));
+        a.slow[lpos] = static_cast<int32_t>(slot);
     }
 }
 
@@ -1342,14 +1317,13 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const int count = static_cast<int>(a.diag[D_SLOWCNT]);
-    const int64_t nn = a.n_nodes;
+    const int64_t nn = a.n_slots;
     for (int li = blockIdx.x * WPB + wv; li < count; li += gridDim.x * WPB) {
-        const int64_t node = a.slow[li];
-        const SetDesc sd = node_set(a, node);
+        const int64_t slot = a.slow[li];
+        const SetDesc sd = slot_set(a, slot);
         const int big = max(sd.g.nbx, sd.g.nby) + 1;
-        const int64_t ln = node - sd.n0;
-        const int i = static_cast<int>(ln % (sd.m.nx + 1));
-        const int j = static_cast<int>(ln / (sd.m.nx + 1));
+        int i, j;
+        slot_ij(sd, slot, i, j);
         const double2 q = node_pos(sd.m, i, j);
         const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
         const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
@@ -1397,10 +1371,10 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             } else {
                 for (int k = lane; k < S.n; k += WAVE) {
                     const uint32_t e = static_cast<uint32_t>(S.u[k]);
-                    a.out.idx[k * nn + node] = static_cast<int32_t>(e & IDX_MASK);
-                    a.out.mem[k * nn + node] = static_cast<uint8_t>(e >> 28);
+                    a.out.idx[k * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
+                    a.out.mem[k * nn + slot] = static_cast<uint8_t>(e >> 28);
                 }
-                if (lane == 0) a.out.meta[node] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
+                if (lane == 0) a.out.meta[slot] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
             }
         }
         if (type == NT_RING || type == NT_OUTSIDE) {
@@ -1440,8 +1414,8 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
                     }
                     if (bt < 0) break;
                     if (lane == 0) {
-                        a.out.idx[r * nn + node] = bt;
-                        a.out.mem[r * nn + node] = 0;
+                        a.out.idx[r * nn + slot] = bt;
+                        a.out.mem[r * nn + slot] = 0;
                     }
                     pd = bd;
                     pu = bu;
@@ -1454,12 +1428,12 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             if (kk == 0) {
                 type = NT_FAILED;
             } else if (lane == 0) {
-                a.out.meta[node] = meta_pack(pending_type(type), kk, 0, 0, 0, flags);
+                a.out.meta[slot] = meta_pack(pending_type(type), kk, 0, 0, 0, flags);
             }
         }
         if (lane == 0) {
             if (type == NT_FAILED) {
-                a.out.meta[node] = meta_pack(NT_FAILED, 0, 0, 0, 0, flags);
+                a.out.meta[slot] = meta_pack(NT_FAILED, 0, 0, 0, 0, flags);
                 atomicAdd(&a.diag[D_FAILED], 1ull);
             }
             if (!ring) atomicAdd(&a.diag[D_ESCALATED], 1ull);
@@ -1482,18 +1456,27 @@ constexpr int SKP = SK + 1;  // row pitch: conflict-free LDS banks across quads
 // The rows a weights pass owns: the fast path's (written before the pass
 // starts) or the slow path's (flagged MF_ESCALATED, finished on the side
 // stream while the fast rows are being weighted).
-__device__ __forceinline__ void weights_node(const KArgs& a, const SetDesc& sd, int i, int j, bool valid,
-                                             int64_t node, int lane, int qi, double2* sp, uint32_t* se,
-                                             int32_t* su, bool escalated_rows) {
-    const int64_t nn = a.n_nodes;
-    const uint32_t meta = valid ? a.out.meta[node] : 0u;
+// Diagnostic counts of one wave's rows: interior, closure and outside-hull
+// rows, and the largest support.
+struct WaveCounts {
+    int c[4];
+};
+enum { WC_INTERIOR, WC_CLOSURE, WC_OUTSIDE, WC_SUPMAX };
+
+__device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc& sd, int i, int j, bool valid,
+                                                   int64_t slot, int lane, int qi, double2* sp, uint32_t* se,
+                                                   int32_t* su, bool escalated_rows) {
+    const int64_t nn = a.n_slots;
+    const uint32_t meta = valid ? a.out.meta[slot] : 0u;
     const bool mine = valid && (((meta_flags(meta) & MF_ESCALATED) != 0) == escalated_rows);
     const uint32_t type = mine ? meta_type(meta) : NT_FAILED;
     const int n = static_cast<int>(meta_cnt(meta));
     const bool pend = type == NT_PENDING;
     const bool clos = type == NT_PEND_RING || type == NT_PEND_OUT;
     // stage the support: entry (sorted index | ring bits << 28), position and
-    // user id; the loads of all slots are issued before any is waited for
+    // user id.  The loads are unconditional, so that all of them are issued
+    // before any is waited for: entries past the row (k < SK <= KMAX stays
+    // inside the row storage) are replaced by particle 0 and not stored.
     {
         constexpr int SS = SK / QL;
         uint32_t e[SS];
@@ -1501,20 +1484,16 @@ __device__ __forceinline__ void weights_node(const KArgs& a, const SetDesc& sd, 
 #pragma unroll
         for (int s = 0; s < SS; ++s) {
             const int k = s * QL + lane;
-            e[s] = 0;
-            if (k < ns)
-                e[s] = static_cast<uint32_t>(a.out.idx[k * nn + node]) |
-                       (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28);
+            const uint32_t v = static_cast<uint32_t>(a.out.idx[k * nn + slot]) |
+                               (static_cast<uint32_t>(a.out.mem[k * nn + slot]) << 28);
+            e[s] = k < ns ? v : 0u;
         }
         double2 pp[SS];
         int32_t uu[SS];
 #pragma unroll
         for (int s = 0; s < SS; ++s) {
-            const int k = s * QL + lane;
-            if (k < ns) {
-                pp[s] = a.pos_s[e[s] & IDX_MASK];
-                uu[s] = a.perm[e[s] & IDX_MASK];
-            }
+            pp[s] = a.pos_s[e[s] & IDX_MASK];
+            uu[s] = a.perm[e[s] & IDX_MASK];
         }
 #pragma unroll
         for (int s = 0; s < SS; ++s) {
@@ -1537,14 +1516,14 @@ __device__ __forceinline__ void weights_node(const KArgs& a, const SetDesc& sd, 
 #pragma unroll 4
         for (int k = 0; k < ns; ++k) f(k, se[qi * SKP + k], sp[qi * SKP + k], su[qi * SKP + k]);
         for (int k = SK; k < n; ++k) {
-            const uint32_t e = static_cast<uint32_t>(a.out.idx[k * nn + node]) |
-                               (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28);
+            const uint32_t e = static_cast<uint32_t>(a.out.idx[k * nn + slot]) |
+                               (static_cast<uint32_t>(a.out.mem[k * nn + slot]) << 28);
             f(k, e, a.pos_s[e & IDX_MASK], a.perm[e & IDX_MASK]);
         }
     };
     auto P = [&](int k) -> double2 {
         if (k < SK) return sp[qi * SKP + k];
-        return a.pos_s[a.out.idx[k * nn + node]];
+        return a.pos_s[a.out.idx[k * nn + slot]];
     };
     const double2 q = node_pos(sd.m, i, j);
     int ok = 1;
@@ -1650,8 +1629,8 @@ __device__ __forceinline__ void weights_node(const KArgs& a, const SetDesc& sd, 
     if ((pend || clos) && !ok) {
         // rank-deficient: the row stays pending for k_weights_rd
         if (lane == 0) {
-            const int slot = static_cast<int>(atomicAdd(&a.diag[D_RDCNT], 1ull));
-            a.rd[slot] = static_cast<int32_t>(node);
+            const int lpos = static_cast<int>(atomicAdd(&a.diag[D_RDCNT], 1ull));
+            a.rd[lpos] = static_cast<int32_t>(slot);
         }
     } else if (pend || clos) {
         // w_k = phi-part (lane 3) + sum over the edges (lanes 0..2) of
@@ -1667,31 +1646,37 @@ __device__ __forceinline__ void weights_node(const KArgs& a, const SetDesc& sd, 
             }
             const double w = quad_sum(c);
             if (lane == (k & (QL - 1))) {
-                a.out.idx[k * nn + node] = u;
-                a.out.w64[k * nn + node] = w;
-                if (a.out.w32) a.out.w32[k * nn + node] = static_cast<float>(w);
-                a.out.mem[k * nn + node] = clos ? 0 : static_cast<uint8_t>(e >> 28);
+                a.out.idx[k * nn + slot] = u;
+                a.out.w64[k * nn + slot] = w;
+                if (a.out.w32) a.out.w32[k * nn + slot] = static_cast<float>(w);
+                a.out.mem[k * nn + slot] = clos ? 0 : static_cast<uint8_t>(e >> 28);
             }
         });
         if (lane == 0) {
             const uint32_t ft = pend ? NT_INTERIOR : (type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING);
-            a.out.meta[node] = pend ? meta_pack(ft, n, lt[0], lt[1], lt[2], meta_flags(meta))
+            a.out.meta[slot] = pend ? meta_pack(ft, n, lt[0], lt[1], lt[2], meta_flags(meta))
                                     : meta_pack(ft, n, 0, 0, 0, meta_flags(meta));
         }
     }
-    // diagnostics: one count per quad (lane 0), one atomic per wave
+    // diagnostics: one count per quad (lane 0), wave-uniform totals
     const bool q0 = lane == 0;
-    const unsigned long long inter = __ballot(q0 && pend);
-    const unsigned long long cl = __ballot(q0 && clos);
-    const unsigned long long outs = __ballot(q0 && type == NT_PEND_OUT);
+    WaveCounts wc;
+    wc.c[WC_INTERIOR] = __popcll(__ballot(q0 && pend));
+    wc.c[WC_CLOSURE] = __popcll(__ballot(q0 && clos));
+    wc.c[WC_OUTSIDE] = __popcll(__ballot(q0 && type == NT_PEND_OUT));
     int sup = (pend || clos) ? n : 0;
     for (int off = 32; off > 0; off >>= 1) sup = max(sup, __shfl_xor(sup, off));
-    if (threadIdx.x % WAVE == 0) {
-        if (inter) atomicAdd(&a.diag[D_INTERIOR], static_cast<unsigned long long>(__popcll(inter)));
-        if (cl) atomicAdd(&a.diag[D_CLOSURE], static_cast<unsigned long long>(__popcll(cl)));
-        if (outs) atomicAdd(&a.diag[D_OUTSIDE], static_cast<unsigned long long>(__popcll(outs)));
-        if (sup) atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(sup));
-    }
+    wc.c[WC_SUPMAX] = sup;
+    return wc;
+}
+
+// Adds one wave's counts to the diagnostics (the few slow-path rows).
+__device__ __forceinline__ void count_wave(const KArgs& a, const WaveCounts& wc) {
+    if (threadIdx.x % WAVE != 0) return;
+    if (wc.c[WC_INTERIOR]) atomicAdd(&a.diag[D_INTERIOR], static_cast<unsigned long long>(wc.c[WC_INTERIOR]));
+    if (wc.c[WC_CLOSURE]) atomicAdd(&a.diag[D_CLOSURE], static_cast<unsigned long long>(wc.c[WC_CLOSURE]));
+    if (wc.c[WC_OUTSIDE]) atomicAdd(&a.diag[D_OUTSIDE], static_cast<unsigned long long>(wc.c[WC_OUTSIDE]));
+    if (wc.c[WC_SUPMAX]) atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(wc.c[WC_SUPMAX]));
 }
 
 // Weights of the fast path's pending rows, one quad per node, nodes in the
@@ -1700,6 +1685,7 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     __shared__ double2 sp[QPB * SKP];
     __shared__ uint32_t se[QPB * SKP];
     __shared__ int32_t su[QPB * SKP];
+    __shared__ int wsum[QWG / WAVE][4];
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const SetDesc sd = tile_set(a, blockIdx.x);
@@ -1707,8 +1693,20 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     tile_xy(sd, static_cast<int>(blockIdx.x - sd.t0), tx, ty);
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
-    const int64_t node = sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;
-    weights_node(a, sd, i, j, valid, node, lane, qi, sp, se, su, false);
+    const int64_t slot = static_cast<int64_t>(blockIdx.x) * TILE_N + qi;
+    const WaveCounts wc = weights_node(a, sd, i, j, valid, slot, lane, qi, sp, se, su, false);
+    // the tile's counts as one plain record, folded into the diagnostics by
+    // k_weights_rd: device-wide atomics from every wave on the same few
+    // counters serialise at their memory partition and stall the pass
+    if (threadIdx.x % WAVE == 0)
+        for (int c = 0; c < 4; ++c) wsum[threadIdx.x / WAVE][c] = wc.c[c];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        int v = 0;
+        for (int w = 0; w < QWG / WAVE; ++w)
+            v = threadIdx.x == WC_SUPMAX ? max(v, wsum[w][threadIdx.x]) : v + wsum[w][threadIdx.x];
+        a.tdiag[blockIdx.x * 4 + threadIdx.x] = v;
+    }
 }
 
 // Weights of the slow path's rows: one quad per listed node; every quad of
@@ -1724,40 +1722,64 @@ __global__ void __launch_bounds__(QWG) k_weights_slow(KArgs a) {
     for (int base = blockIdx.x * QPB; base < count; base += gridDim.x * QPB) {
         const int li = base + qi;
         const bool valid = li < count;
-        const int64_t node = valid ? a.slow[li] : 0;
-        const SetDesc sd = node_set(a, node);
-        const int64_t ln = node - sd.n0;
-        const int i = static_cast<int>(ln % (sd.m.nx + 1)), j = static_cast<int>(ln / (sd.m.nx + 1));
-        weights_node(a, sd, i, j, valid, node, lane, qi, sp, se, su, true);
+        const int64_t slot = valid ? a.slow[li] : 0;
+        const SetDesc sd = slot_set(a, slot);
+        int i, j;
+        slot_ij(sd, slot, i, j);
+        count_wave(a, weights_node(a, sd, i, j, valid, slot, lane, qi, sp, se, su, true));
         __syncthreads();  // the LDS rows are reused by the next turn
     }
 }
 
 // Nodes whose moment systems are rank-deficient (listed by k_weights): the
-// minimum-norm solution through the pseudo-inverse, one quad per node.
+// minimum-norm solution through the pseudo-inverse, one quad per node.  Block
+// 0 first folds k_weights' per-tile counts into the diagnostics.
 __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
+    if (blockIdx.x == 0) {
+        unsigned long long v[4] = {0, 0, 0, 0};
+        const int64_t tiles = a.n_slots / TILE_N;
+        for (int64_t t = threadIdx.x; t < tiles; t += QWG) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const unsigned long long x = static_cast<unsigned long long>(a.tdiag[t * 4 + c]);
+                v[c] = c == WC_SUPMAX ? max(v[c], x) : v[c] + x;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned long long o = __shfl_xor(v[c], off);
+                v[c] = c == WC_SUPMAX ? max(v[c], o) : v[c] + o;
+            }
+        if (threadIdx.x % WAVE == 0) {
+            if (v[WC_INTERIOR]) atomicAdd(&a.diag[D_INTERIOR], v[WC_INTERIOR]);
+            if (v[WC_CLOSURE]) atomicAdd(&a.diag[D_CLOSURE], v[WC_CLOSURE]);
+            if (v[WC_OUTSIDE]) atomicAdd(&a.diag[D_OUTSIDE], v[WC_OUTSIDE]);
+            if (v[WC_SUPMAX]) atomicMax(&a.diag[D_SUPMAX], v[WC_SUPMAX]);
+        }
+    }
     const int lane = threadIdx.x & (QL - 1);
     const int count = static_cast<int>(a.diag[D_RDCNT]);
-    const int64_t nn = a.n_nodes;
+    const int64_t nn = a.n_slots;
     for (int li = (blockIdx.x * QWG + threadIdx.x) / QL; li < count; li += gridDim.x * (QWG / QL)) {
-        const int64_t node = a.rd[li];
-        const SetDesc sd = node_set(a, node);
-        const int64_t ln = node - sd.n0;
-        const int i = static_cast<int>(ln % (sd.m.nx + 1)), j = static_cast<int>(ln / (sd.m.nx + 1));
-        const uint32_t meta = a.out.meta[node];
+        const int64_t slot = a.rd[li];
+        const SetDesc sd = slot_set(a, slot);
+        int i, j;
+        slot_ij(sd, slot, i, j);
+        const uint32_t meta = a.out.meta[slot];
         const uint32_t type = meta_type(meta);
         const int n = static_cast<int>(meta_cnt(meta));
         if (type == NT_PENDING) {
             int T[3];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) T[k] = a.out.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + node];
+            for (int k = 0; k < 3; ++k) T[k] = a.out.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + slot];
             auto uget = [&](int k) {
-                return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + node]) |
-                                            (static_cast<uint32_t>(a.out.mem[k * nn + node]) << 28));
+                return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + slot]) |
+                                            (static_cast<uint32_t>(a.out.mem[k * nn + slot]) << 28));
             };
-            quad_weights(a, node, node_pos(sd.m, i, j), uget, n, T, lane, meta_flags(meta));
+            quad_weights(a, slot, node_pos(sd.m, i, j), uget, n, T, lane, meta_flags(meta));
         } else {
-            quad_closure(a, node, node_pos(sd.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
+            quad_closure(a, slot, node_pos(sd.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
                          meta_flags(meta));
         }
     }
@@ -1766,10 +1788,11 @@ __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
 }  // namespace
 
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
-                  const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd,
+                  const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,
                   unsigned long long* diag, const SideWork& side, hipStream_t st) {
     PhaseTimer _timer(PH_BUILD, st);
-    if (n_tiles >= (int64_t(1) << 31)) {
+    // row slots are listed as int32
+    if (n_tiles * TILE_N >= (int64_t(1) << 31)) {
         set_error("too many node tiles (%lld)", static_cast<long long>(n_tiles));
         return P2M_EINVAL;
     }
@@ -1781,9 +1804,11 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     a.S = S;
     a.levels = levels;
     a.n_nodes = n_nodes;
+    a.n_slots = n_tiles * TILE_N;
     a.out = out;
     a.slow = slow;
     a.rd = rd;
+    a.tdiag = tdiag;
     a.diag = diag;
     const int tiles = static_cast<int>(n_tiles);
     {

@@ -67,13 +67,14 @@ struct p2m_weights {
     int64_t n_tiles = 0;
     int flags = 0;
     // capacities of the device buffers
-    int64_t capN = 0, capBins = 0, capNodes = 0, capTiles = 0, capSets = 0, capHist = 0;
+    int64_t capN = 0, capBins = 0, capNodes = 0, capSlots = 0, capTiles = 0, capSets = 0, capHist = 0;
     bool capW32 = false;
     BinBuffers bins{};
-    uint32_t* meta = nullptr;
+    uint32_t* meta = nullptr;  // ELL rows per node slot (64 per node tile)
     int32_t* idx = nullptr;
     int32_t* slow = nullptr;
     int32_t* rd = nullptr;
+    int32_t* tdiag = nullptr;  // per node tile counts of the weights pass [4 per tile]
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // side-stream fork / join
     double* w64 = nullptr;
     float* w32 = nullptr;
@@ -113,7 +114,7 @@ int grow(T** p, int64_t count, int64_t have) {
 void release(p2m_weights* w) {
     void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.hist, w->bins.start, w->bins.tsum, w->bins.pos_s,
                     w->bins.perm, w->bins.part_pos, w->bins.part_key, w->bins.part_uid, w->meta, w->idx, w->slow,
-                    w->rd, w->w64, w->w32, w->mem, w->diag, w->dsets};
+                    w->rd, w->tdiag, w->w64, w->w32, w->mem, w->diag, w->dsets};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
@@ -171,6 +172,7 @@ WeightsView view(const p2m_weights* w) {
     v.sets = w->dsets;
     v.S = w->S;
     v.n_nodes = w->n_nodes;
+    v.n_slots = w->n_tiles * TILE_N;
     v.N = w->N;
     v.meta = w->meta;
     v.idx = w->idx;
@@ -252,7 +254,8 @@ int make_sets(const p2m_mesh* meshes, const double* hs, const int64_t* off, int 
         set_error("binning grid too large (%lld bins)", static_cast<long long>(tot.nbins));
         return P2M_EINVAL;
     }
-    if (tot.n_nodes * KMAX >= (int64_t(1) << 40) || tot.n_tiles >= (int64_t(1) << 31)) {
+    // row slots (64 per node tile) are listed as int32
+    if (tot.n_nodes * KMAX >= (int64_t(1) << 40) || tot.n_tiles * TILE_N >= (int64_t(1) << 31)) {
         set_error("meshes too large (%lld nodes)", static_cast<long long>(tot.n_nodes));
         return P2M_EINVAL;
     }
@@ -314,18 +317,20 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     if (!rc) w->capHist = std::max(w->capHist, nhist);
     if (!rc) rc = grow(&w->bins.tsum, ntiles + 1, w->capTiles + 1);
     if (!rc) w->capTiles = std::max(w->capTiles, ntiles);
-    if (!rc) rc = grow(&w->meta, n_nodes, w->capNodes);
+    const int64_t n_slots = tot.n_tiles * TILE_N;
+    if (!rc) rc = grow(&w->meta, n_slots, w->capSlots);
     if (!rc) rc = grow(&w->slow, n_nodes, w->capNodes);
     if (!rc) rc = grow(&w->rd, n_nodes, w->capNodes);
+    if (!rc) rc = grow(&w->tdiag, 4 * tot.n_tiles, 4 * (w->capSlots / TILE_N));
     if (!rc && !w->ev_fork) {
         hipError_t e = hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming);
         if (e != hipSuccess) rc = hip_check(e, "hipEventCreateWithFlags");
     }
-    if (!rc) rc = grow(&w->idx, n_nodes * KMAX, w->capNodes * KMAX);
-    if (!rc) rc = grow(&w->w64, n_nodes * KMAX, w->capNodes * KMAX);
-    if (!rc) rc = grow(&w->mem, n_nodes * KMAX, w->capNodes * KMAX);
-    if (!rc && want32) rc = grow(&w->w32, n_nodes * KMAX, w->capW32 ? w->capNodes * KMAX : 0);
+    if (!rc) rc = grow(&w->idx, n_slots * KMAX, w->capSlots * KMAX);
+    if (!rc) rc = grow(&w->w64, n_slots * KMAX, w->capSlots * KMAX);
+    if (!rc) rc = grow(&w->mem, n_slots * KMAX, w->capSlots * KMAX);
+    if (!rc && want32) rc = grow(&w->w32, n_slots * KMAX, w->capW32 ? w->capSlots * KMAX : 0);
     if (!rc && !w->diag) rc = grow(&w->diag, D_COUNT, 0);
     if (!rc) rc = grow(&w->dsets, S, w->capSets);
     if (rc) {
@@ -337,6 +342,7 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     }
     if (want32 && !w->capW32) w->capW32 = true;
     w->capNodes = std::max(w->capNodes, n_nodes);
+    w->capSlots = std::max(w->capSlots, n_slots);
     w->capSets = std::max<int64_t>(w->capSets, S);
     if (new_table || w->hsets.size() != sets.size() ||
         std::memcmp(w->hsets.data(), sets.data(), sizeof(SetDesc) * sets.size()) != 0) {
@@ -359,7 +365,7 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     rc = side_stream(dev, &side.stream);
     if (rc) return rc;
     return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, fast_slots(), w->slow,
-                         w->rd, w->diag, side, st);
+                         w->rd, w->tdiag, w->diag, side, st);
 }
 
 // Per-device workspace of the fused (recompute) entry points: a weights

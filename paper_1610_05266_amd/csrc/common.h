@@ -104,17 +104,75 @@ __device__ __forceinline__ int set_search(int S, int64_t v, F&& first) {
     return lo;
 }
 
+// ---- node slots of the ELL rows
+// Rows are stored per node slot rather than per mesh node: node (i, j) of
+// node tile t (8 x 8 nodes) has slot 64 t + 8 (j % 8) + (i % 8), with tiles
+// numbered as the build launches take them (tile_xy).  The 64 nodes of a
+// tile, and the 16 nodes of a wave, occupy consecutive slots, so one entry
+// of a wave's rows is a single aligned 128-byte FP64 segment.  Slots of a
+// partial tile that lie beyond the mesh hold empty rows.
+constexpr int TILE_N = 64;
+
+// Tile tl of a set's node tiles: the full tiles first (row-major), then the
+// partial tiles of the last column and of the last row.  The hardware
+// dispatches blocks in index order and holds a fixed number at a time, so
+// full tiles taken in whole rounds, with the cheap partial ones filling the
+// last slots, finish earlier than the row-major order.
+__host__ __device__ inline void tile_xy(const SetDesc& sd, int tl, int& tx, int& ty) {
+    const int fx = (sd.m.nx + 1) / 8, fy = (sd.m.ny + 1) / 8;  // full tile columns, rows
+    if (tl < fx * fy) {
+        tx = tl % fx;
+        ty = tl / fx;
+        return;
+    }
+    int r = tl - fx * fy;
+    if (sd.tiles_x > fx) {
+        if (r < fy) {
+            tx = fx;
+            ty = r;
+            return;
+        }
+        r -= fy;
+    }
+    tx = r;
+    ty = fy;
+}
+// Inverse of tile_xy.
+__host__ __device__ inline int tile_index(const SetDesc& sd, int tx, int ty) {
+    const int fx = (sd.m.nx + 1) / 8, fy = (sd.m.ny + 1) / 8;
+    if (tx < fx && ty < fy) return ty * fx + tx;
+    if (ty < fy) return fx * fy + ty;                  // the partial column
+    return fx * fy + (sd.tiles_x > fx ? fy : 0) + tx;  // the partial row
+}
+__host__ __device__ inline int64_t node_slot(const SetDesc& sd, int i, int j) {
+    return (sd.t0 + tile_index(sd, i >> 3, j >> 3)) * TILE_N + (j & 7) * 8 + (i & 7);
+}
+// Node (i, j) of a slot of set sd (the slot's tile must belong to sd); false
+// beyond the mesh.
+__host__ __device__ inline bool slot_ij(const SetDesc& sd, int64_t slot, int& i, int& j) {
+    int tx, ty;
+    tile_xy(sd, static_cast<int>(slot / TILE_N - sd.t0), tx, ty);
+    const int l = static_cast<int>(slot % TILE_N);
+    i = tx * 8 + (l & 7);
+    j = ty * 8 + (l >> 3);
+    return i <= sd.m.nx && j <= sd.m.ny;
+}
+__host__ __device__ inline int64_t ij_node(const SetDesc& sd, int i, int j) {
+    return sd.n0 + static_cast<int64_t>(j) * (sd.m.nx + 1) + i;
+}
+
 // Everything the kernels need to know about one weights handle.
 struct WeightsView {
     const SetDesc* sets;    // [S] device
     int S;
     int64_t n_nodes;        // all sets
+    int64_t n_slots;        // node slots of all sets (64 per node tile)
     int64_t N;              // all sets
-    const uint32_t* meta;   // [n_nodes]
-    const int32_t* idx;     // [KMAX][n_nodes] user particle ids
-    const double* w64;      // [KMAX][n_nodes]
-    const float* w32;       // [KMAX][n_nodes] or null
-    const uint8_t* mem;     // [KMAX][n_nodes]
+    const uint32_t* meta;   // [n_slots]
+    const int32_t* idx;     // [KMAX][n_slots] user particle ids
+    const double* w64;      // [KMAX][n_slots]
+    const float* w32;       // [KMAX][n_slots] or null
+    const uint8_t* mem;     // [KMAX][n_slots]
 };
 
 // Exact-rounding helpers: products/sums that must not be contracted into

@@ -1,9 +1,10 @@
 // P2M weighted sum, eq. (p2m): mesh[i][c] = sum_mu psi_mu(r_i) vals[mu][c],
 // and its adjoint for fixed weights.
 //
-// One thread per mesh node walks its ELL row (slot-major layout, so the k-th
-// entries of consecutive nodes are contiguous) and gathers the C channels of
-// each particle from the user-ordered value array.
+// The ELL rows are stored per node slot (64 slots per 8 x 8 node tile, entry
+// k of consecutive slots contiguous); a block takes one node tile and its
+// quads walk the rows, gathering the C channels of each particle from the
+// user-ordered value array.
 #include "kernels.h"
 
 namespace p2m {
@@ -20,26 +21,37 @@ __device__ __forceinline__ double ld(const double* p, int64_t i) { return p[i]; 
 __device__ __forceinline__ float ld(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ld(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
 
+// The mesh node of a quad's slot in a one-tile block (false beyond the mesh).
+__device__ __forceinline__ bool tile_node(const WeightsView& wv, int64_t& slot, int64_t& node) {
+    const int64_t tile = blockIdx.x;
+    const SetDesc& sd = wv.sets[set_search(wv.S, tile, [&](int s) { return wv.sets[s].t0; })];
+    slot = tile * TILE_N + (threadIdx.x >> 2);
+    int i, j;
+    if (!slot_ij(sd, slot, i, j)) return false;
+    node = ij_node(sd, i, j);
+    return true;
+}
+
 // vals element type TV, weights TW, output TO (accumulate in TW).  Four
 // lanes per node: lane l takes ELL entries l, l + 4, ...; the partial sums
 // are combined by a quad reduction (fixed order, so results are bitwise
 // reproducible), and lane c % 4 stores channel c.
 template <typename TV, typename TW, typename TO, int CC>
-__global__ void __launch_bounds__(256) k_project(const uint32_t* __restrict__ meta, const int32_t* __restrict__ idx,
-                                                 const TW* __restrict__ w, int64_t n_nodes,
+__global__ void __launch_bounds__(256) k_project(WeightsView wv, const TW* __restrict__ w,
                                                  const TV* __restrict__ vals, int Crt, TO* __restrict__ out) {
     constexpr int NC = CC > 0 ? CC : CMAX;
     const int lane = threadIdx.x & 3;
-    const int64_t node = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 2;
-    if (node >= n_nodes) return;  // the four lanes of a node leave together
+    int64_t slot, node;
+    if (!tile_node(wv, slot, node)) return;  // the four lanes of a node leave together
+    const int64_t ns = wv.n_slots;
     const int C = CC > 0 ? CC : Crt;
     TW acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = TW(0);
-    const int cnt = row_len(meta[node]);
+    const int cnt = row_len(wv.meta[slot]);
     for (int k = lane; k < cnt; k += 4) {
-        const int64_t j = idx[k * n_nodes + node];
-        const TW wk = w[k * n_nodes + node];
+        const int64_t j = wv.idx[k * ns + slot];
+        const TW wk = w[k * ns + slot];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (c < C) acc[c] += wk * static_cast<TW>(ld(vals, j * C + c));
@@ -56,44 +68,49 @@ __global__ void __launch_bounds__(256) k_project(const uint32_t* __restrict__ me
 
 template <typename TV, typename TW, typename TO>
 void launch_project(const WeightsView& wv, const TW* w, const void* vals, int C, void* out, hipStream_t st) {
-    const int blocks = static_cast<int>((4 * wv.n_nodes + 255) / 256);
+    const int blocks = static_cast<int>(wv.n_slots / TILE_N);  // one node tile (64 quads) per block
     const TV* v = static_cast<const TV*>(vals);
     TO* o = static_cast<TO*>(out);
     switch (C) {
-        case 1: k_project<TV, TW, TO, 1><<<blocks, 256, 0, st>>>(wv.meta, wv.idx, w, wv.n_nodes, v, C, o); break;
-        case 2: k_project<TV, TW, TO, 2><<<blocks, 256, 0, st>>>(wv.meta, wv.idx, w, wv.n_nodes, v, C, o); break;
-        case 3: k_project<TV, TW, TO, 3><<<blocks, 256, 0, st>>>(wv.meta, wv.idx, w, wv.n_nodes, v, C, o); break;
-        case 4: k_project<TV, TW, TO, 4><<<blocks, 256, 0, st>>>(wv.meta, wv.idx, w, wv.n_nodes, v, C, o); break;
-        default: k_project<TV, TW, TO, 0><<<blocks, 256, 0, st>>>(wv.meta, wv.idx, w, wv.n_nodes, v, C, o); break;
+        case 1: k_project<TV, TW, TO, 1><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
+        case 2: k_project<TV, TW, TO, 2><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
+        case 3: k_project<TV, TW, TO, 3><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
+        case 4: k_project<TV, TW, TO, 4><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
+        default: k_project<TV, TW, TO, 0><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
     }
 }
 
 // grad_vals[j][c] += w * grad_mesh[i][c] (atomics) ; grad_w[k][i] = sum_c grad_mesh[i][c] vals[j][c]
+// (grad_w in mesh-node order [KMAX][n_nodes]).  One thread per row slot.
 template <typename TV, typename TW, typename TG>
-__global__ void __launch_bounds__(256) k_project_bwd(const uint32_t* __restrict__ meta,
-                                                     const int32_t* __restrict__ idx, const TW* __restrict__ w,
-                                                     int64_t n_nodes, const TG* __restrict__ gmesh, int C,
+__global__ void __launch_bounds__(256) k_project_bwd(WeightsView wv, const TW* __restrict__ w,
+                                                     const TG* __restrict__ gmesh, int C,
                                                      const TV* __restrict__ vals, TG* __restrict__ gvals,
                                                      double* __restrict__ gw) {
-    const int64_t node = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (node >= n_nodes) return;
-    const int cnt = row_len(meta[node]);
+    const int64_t slot = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (slot >= wv.n_slots) return;
+    const SetDesc& sd = wv.sets[set_search(wv.S, slot / TILE_N, [&](int s) { return wv.sets[s].t0; })];
+    int i, j;
+    if (!slot_ij(sd, slot, i, j)) return;
+    const int64_t node = ij_node(sd, i, j);
+    const int64_t ns = wv.n_slots, nn = wv.n_nodes;
+    const int cnt = row_len(wv.meta[slot]);
     TG g[CMAX];
     for (int c = 0; c < C; ++c) g[c] = gmesh[node * C + c];
     for (int k = 0; k < cnt; ++k) {
-        const int64_t j = idx[k * n_nodes + node];
+        const int64_t p = wv.idx[k * ns + slot];
         if (gvals) {
-            const TG wk = static_cast<TG>(w[k * n_nodes + node]);
-            for (int c = 0; c < C; ++c) atomicAdd(&gvals[j * C + c], wk * g[c]);
+            const TG wk = static_cast<TG>(w[k * ns + slot]);
+            for (int c = 0; c < C; ++c) atomicAdd(&gvals[p * C + c], wk * g[c]);
         }
         if (gw) {
             double s = 0.0;
-            for (int c = 0; c < C; ++c) s += static_cast<double>(g[c]) * static_cast<double>(ld(vals, j * C + c));
-            gw[k * n_nodes + node] = s;
+            for (int c = 0; c < C; ++c) s += static_cast<double>(g[c]) * static_cast<double>(ld(vals, p * C + c));
+            gw[k * nn + node] = s;
         }
     }
     if (gw)
-        for (int k = cnt; k < KMAX; ++k) gw[k * n_nodes + node] = 0.0;
+        for (int k = cnt; k < KMAX; ++k) gw[k * nn + node] = 0.0;
 }
 
 }  // namespace
@@ -119,14 +136,14 @@ int project(const WeightsView& wv, const void* vals, int C, int dtype, void* mes
 int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dtype, const void* vals,
                      void* grad_vals, double* grad_w, hipStream_t st) {
     PhaseTimer _timer(PH_PROJECT_BWD, st);
-    const int blocks = static_cast<int>((wv.n_nodes + 255) / 256);
+    const int blocks = static_cast<int>((wv.n_slots + 255) / 256);
     if (dtype == P2M_F64) {
         if (grad_vals) {
             int rc = fill_bytes_zero(grad_vals, sizeof(double) * wv.N * C, st);
             if (rc) return rc;
         }
         k_project_bwd<double, double, double><<<blocks, 256, 0, st>>>(
-            wv.meta, wv.idx, wv.w64, wv.n_nodes, static_cast<const double*>(grad_mesh), C,
+            wv, wv.w64, static_cast<const double*>(grad_mesh), C,
             static_cast<const double*>(vals), static_cast<double*>(grad_vals), grad_w);
     } else {
         if (!wv.w32) {
@@ -139,11 +156,11 @@ int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dt
         }
         if (dtype == P2M_F32)
             k_project_bwd<float, float, float><<<blocks, 256, 0, st>>>(
-                wv.meta, wv.idx, wv.w32, wv.n_nodes, static_cast<const float*>(grad_mesh), C,
+                wv, wv.w32, static_cast<const float*>(grad_mesh), C,
                 static_cast<const float*>(vals), static_cast<float*>(grad_vals), grad_w);
         else
             k_project_bwd<uint16_t, float, float><<<blocks, 256, 0, st>>>(
-                wv.meta, wv.idx, wv.w32, wv.n_nodes, static_cast<const float*>(grad_mesh), C,
+                wv, wv.w32, static_cast<const float*>(grad_mesh), C,
                 static_cast<const uint16_t*>(vals), static_cast<float*>(grad_vals), grad_w);
     }
     P2M_HIP(hipGetLastError());

@@ -56,3 +56,18 @@ def test_exact_fallback_kernel_keeps_its_delaunay_code(listings):
     slow = [b for n, b in bodies.items() if "k_slow_geom" in n]
     assert len(slow) == 1
     assert slow[0].count("ds_bpermute_b32") >= 200
+
+
+def test_no_kernel_uses_scratch_memory(listings):
+    """Staging arrays kept in scratch memory serialise the loads they stage
+    (every load waits before its spill) and limit how many waves the
+    dispatcher starts; every kernel keeps its state in registers and LDS."""
+    seen = 0
+    for src, asm in listings.items():
+        for m in re.finditer(r"^\s*\.amdhsa_kernel\s+(\S+)(.*?)^\s*\.end_amdhsa_kernel", asm, flags=re.M | re.S):
+            name, desc = m.group(1), m.group(2)
+            size = re.search(r"\.amdhsa_private_segment_fixed_size\s+(\d+)", desc)
+            assert size, f"{src}: {name} has no private segment size"
+            assert int(size.group(1)) == 0, f"{src}: {name} uses {size.group(1)} bytes of scratch per lane"
+            seen += 1
+    assert seen >= 12
