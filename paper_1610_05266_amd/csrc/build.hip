@@ -29,19 +29,18 @@
 // Near-ties of the FP64 predicates (|det| within a forward error bound) are
 // counted and broken by the user particle id.
 //
-// Execution (three kernels): the FAST kernel gives each interior node a quad
-// of four lanes.
-// The lanes hold the particles within a radius Rf of the node in registers,
-// split round-robin, so each gift-wrapping step is a short register loop plus
-// a two-step quad reduction; a decision is certified when its disk lies in
-// the disk of radius Rf around the node.  A node whose decisions cannot all
-// be certified there (or any node on the mesh's outer ring) is appended to a
-// list for the SLOW kernel: one wave per node scanning square bin regions
-// that double in size up to all particles (closure nodes get their weights
-// there).  Both leave each interior node's support in its ELL row, and the
-// WEIGHTS kernel (again a quad per node) turns every such row into weights,
-// so the result of a node does not depend on the path that found its
-// triangle.
+// Execution: the FAST kernel gives each node a quad of four lanes that hold
+// the particles within a radius Rf of the node in registers, split
+// round-robin, so each gift-wrapping step is a short register loop plus a
+// two-step quad reduction; a decision is certified when its disk lies in the
+// disk of radius Rf around the node (boundary-ring nodes take their K nearest
+// particles, certified the same way).  A node that cannot be certified there
+// is appended to a list for the SLOW kernel on a side stream: one wave per
+// node scanning square bin regions that double in size up to all particles,
+// which then weights the row it found.  Meanwhile the WEIGHTS kernel (a quad
+// per node) turns every row of the fast pass into weights.  Both passes use
+// the same rows and the same weighting code, so the result of a node does
+// not depend on the pass that found its triangle.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
@@ -176,17 +175,32 @@ __device__ __forceinline__ void reduce_nearest(double& d2, int& t, double2& p, c
 // minimum of one double is found first, the lanes that might tie it are
 // singled out by a ballot, and the winner is read from its lane.  The full
 // exact butterfly runs only when a near-tie is possible.
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int m = 1; m < WAVE; m <<= 1) v = fmin(v, lane_xor<WAVE>(v, m));
-    return v;
-}
 __device__ __forceinline__ int read_lane(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ double read_lane(double v, int l) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), l);
     const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), l);
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+// Value of v in the mirrored lane of the same 16-lane row (DPP, no LDS round
+// trip): CTRL 0x141 mirrors each half row (lane i <-> 7 - i), 0x140 the
+// whole row (i <-> 15 - i).
+template <int CTRL>
+__device__ __forceinline__ double row_mirror(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+// Minimum over the wave, in every lane (every lane active).  Within a row of
+// 16 lanes each exchange merges two disjoint groups (quad permutes, then the
+// half-row and row mirrors); the four row minima are then read as scalars.
+__device__ __forceinline__ double wave_min(double v) {
+    v = fmin(v, lane_xor<4>(v, 1));
+    v = fmin(v, lane_xor<4>(v, 2));
+    v = fmin(v, row_mirror<0x141>(v));
+    v = fmin(v, row_mirror<0x140>(v));
+    return fmin(fmin(read_lane(v, 0), read_lane(v, 16)), fmin(read_lane(v, 32), read_lane(v, 48)));
 }
 __device__ __forceinline__ Key read_key(const Key& k, int l) {
     Key o;
@@ -462,14 +476,38 @@ struct QuadSource {
         int am = amb ? 1 : 0;
         am |= lane_xor<QL>(am, 1);
         am |= lane_xor<QL>(am, 2);
+        if (am) return wrap_exact(iv, v, ia, a, sgn);
         Key k;
-        k.t = am ? -2 : bt;
+        k.t = bt;
         k.num = bn;
         k.cr = bc;
         k.Nm = k.Cm = 0.0;
         k.bx = bx;
         k.by = by;
         return k;
+    }
+    // The same step with each candidate's own forward error bound, as the
+    // wave path compares (key_of, key_better): it decides the steps the
+    // static bound leaves open because that bound is loose.  A true near tie
+    // or a candidate nearly on the line through v and a still gives t = -2:
+    // those are broken by user id on the wave path alone, so that no result
+    // depends on the order in which a pass meets tied candidates.
+    __device__ Key wrap_exact(int iv, double2 v, int ia, double2 a, double sgn) {
+        auto uid = [&](int t) { return perm[t]; };
+        Key best = no_key();
+        int nd = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (s >= n || ct_[s] == iv || ct_[s] == ia) continue;
+            const Key k = key_of(ct_[s], v, a, make_double2(cx_[s], cy_[s]), sgn, nd);
+            if (key_better(k, best, uid, nd)) best = k;
+        }
+        reduce_key<QL>(best, uid, lane, nd);
+        int tie = nd > 0 ? 1 : 0;
+        tie |= lane_xor<QL>(tie, 1);
+        tie |= lane_xor<QL>(tie, 2);
+        if (tie) best.t = -2;
+        return best;
     }
 };
 
@@ -1301,148 +1339,6 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
 }
 
 // ------------------------------------------------------------ slow kernel
-// One wave per listed node: certified Delaunay search (exact predicates)
-// over square bin regions that double in half-width up to every particle;
-// interior nodes leave their support in the ELL row, closure nodes (ring, or
-// outside the hull) their nearest particles; k_weights does the rest.
-__global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
-    constexpr int WPB = SWG / WAVE;
-    __shared__ int32_t su[WPB * KMAX];
-    __shared__ int32_t svis[WPB * KMAX];
-    __shared__ double2 slp[WPB * STAGE];
-    __shared__ int32_t slt[WPB * STAGE];
-    // These few waves are a serial latency chain that runs beside the
-    // weights kernel: they take issue priority over its waves.
-    __builtin_amdgcn_s_setprio(3);
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int wv = threadIdx.x / WAVE;
-    const int count = static_cast<int>(a.diag[D_SLOWCNT]);
-    const int64_t nn = a.n_slots;
-    for (int li = blockIdx.x * WPB + wv; li < count; li += gridDim.x * WPB) {
-        const int64_t slot = a.slow[li];
-        const SetDesc sd = slot_set(a, slot);
-        const int big = max(sd.g.nbx, sd.g.nby) + 1;
-        int i, j;
-        slot_ij(sd, slot, i, j);
-        const double2 q = node_pos(sd.m, i, j);
-        const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
-        const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
-        WaveSource c;
-        c.pos = a.pos_s;
-        c.perm = a.perm;
-        c.start = a.start + sd.b0;
-        c.g = sd.g;
-        c.neardeg = 0;
-        c.lane = lane;
-        c.lp = slp + wv * STAGE;
-        c.lt = slt + wv * STAGE;
-        Support<WAVE> S;
-        S.u = su + wv * KMAX;
-        S.n = 0;
-        S.lane = lane;
-        uint32_t type = ring ? NT_RING : NT_INTERIOR;
-        uint32_t flags = MF_ESCALATED;
-        int T[3] = {0, 0, 0};
-        int st = R_FAIL;
-        if (!ring) {
-            for (int level = 0;; ++level) {
-                const int hw = level < a.levels ? (sd.hw0 << level) : big;
-                c.set_region(make_region(sd.g, cbx, cby, hw));
-                S.n = 0;
-                st = delaunay_node(c, q, T, S, svis + wv * KMAX);
-                if (st != R_MORE) break;
-                if (c.R.global) {
-                    st = R_FAIL;
-                    break;
-                }
-            }
-            if (c.R.global) flags |= MF_GLOBAL;
-            if (st == R_OUTSIDE) type = NT_OUTSIDE;
-            else if (st == R_CAP) {
-                type = NT_FAILED;
-                if (lane == 0) atomicAdd(&a.diag[D_CAP], 1ull);
-            } else if (st != R_OK) type = NT_FAILED;
-        }
-        if (c.neardeg) flags |= MF_NEARDEG;
-        if (type == NT_INTERIOR) {
-            const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
-            if (lt0 < 0 || lt1 < 0 || lt2 < 0) {
-                type = NT_FAILED;
-            } else {
-                for (int k = lane; k < S.n; k += WAVE) {
-                    const uint32_t e = static_cast<uint32_t>(S.u[k]);
-                    a.out.idx[k * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
-                    a.out.mem[k * nn + slot] = static_cast<uint8_t>(e >> 28);
-                }
-                if (lane == 0) a.out.meta[slot] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
-            }
-        }
-        if (type == NT_RING || type == NT_OUTSIDE) {
-            // closure: the K nearest particles (ties by user id), picked one
-            // per round as the smallest (d^2, user id) above the previous pick
-            int kk = 0;
-            for (int level = 0;; ++level) {
-                const int hw = level < a.levels ? (sd.hw0 << level) : big;
-                c.set_region(make_region(sd.g, cbx, cby, hw));
-                kk = 0;
-                double pd = -1.0;
-                int pu = -1;
-                for (int r = 0; r < KNN; ++r) {
-                    double bd = INFINITY;
-                    int bu = INT_MAX, bt = -1;
-                    c.scan([&](int t, double2 p) {
-                        const double dx = p.x - q.x, dy = p.y - q.y;
-                        const double d2 = dx * dx + dy * dy;
-                        if (d2 < pd || d2 > bd) return;
-                        const int u = c.perm[t];
-                        if (d2 == pd && u <= pu) return;
-                        if (d2 < bd || u < bu) {
-                            bd = d2;
-                            bu = u;
-                            bt = t;
-                        }
-                    });
-#pragma unroll
-                    for (int m = 1; m < WAVE; m <<= 1) {
-                        const double od = __shfl_xor(bd, m);
-                        const int ou = __shfl_xor(bu, m), ot = __shfl_xor(bt, m);
-                        if (ot >= 0 && (bt < 0 || od < bd || (od == bd && ou < bu))) {
-                            bd = od;
-                            bu = ou;
-                            bt = ot;
-                        }
-                    }
-                    if (bt < 0) break;
-                    if (lane == 0) {
-                        a.out.idx[r * nn + slot] = bt;
-                        a.out.mem[r * nn + slot] = 0;
-                    }
-                    pd = bd;
-                    pu = bu;
-                    ++kk;
-                }
-                if (c.R.global) break;
-                if (kk >= KNN && c.certify(q.x, q.y, sqrt(pd))) break;
-            }
-            if (c.R.global) flags |= MF_GLOBAL;
-            if (kk == 0) {
-                type = NT_FAILED;
-            } else if (lane == 0) {
-                a.out.meta[slot] = meta_pack(pending_type(type), kk, 0, 0, 0, flags);
-            }
-        }
-        if (lane == 0) {
-            if (type == NT_FAILED) {
-                a.out.meta[slot] = meta_pack(NT_FAILED, 0, 0, 0, 0, flags);
-                atomicAdd(&a.diag[D_FAILED], 1ull);
-            }
-            if (!ring) atomicAdd(&a.diag[D_ESCALATED], 1ull);
-            if (flags & MF_GLOBAL) atomicAdd(&a.diag[D_GLOBAL], 1ull);
-            if (c.neardeg) atomicAdd(&a.diag[D_NEARDEG], static_cast<unsigned long long>(c.neardeg));
-        }
-    }
-}
-
 // Weights of every pending row (interior or closure, from either path), one
 // quad per node, nodes in the same 8 x 8 tiles as the fast kernel.  Lanes
 // 0..2 of a quad each own one edge system of the node's triangle (moments,
@@ -1679,6 +1575,158 @@ __device__ __forceinline__ void count_wave(const KArgs& a, const WaveCounts& wc)
     if (wc.c[WC_SUPMAX]) atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(wc.c[WC_SUPMAX]));
 }
 
+// One wave per listed node: certified Delaunay search (exact predicates)
+// over square bin regions that double in half-width up to every particle;
+// interior nodes leave their support in the ELL row, closure nodes (ring, or
+// outside the hull) their nearest particles; k_weights does the rest.
+__global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
+    constexpr int WPB = SWG / WAVE;
+    __shared__ int32_t su[WPB * KMAX];
+    __shared__ int32_t svis[WPB * KMAX];
+    __shared__ double2 slp[WPB * STAGE];
+    __shared__ int32_t slt[WPB * STAGE];
+    // the weights of each finished row, by the first quad of its wave
+    __shared__ double2 wsp[QPB * SKP];
+    __shared__ uint32_t wse[QPB * SKP];
+    __shared__ int32_t wsu[QPB * SKP];
+    // These few waves are a serial latency chain that runs beside the
+    // weights kernel: they take issue priority over its waves.
+    __builtin_amdgcn_s_setprio(3);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const int count = static_cast<int>(a.diag[D_SLOWCNT]);
+    const int64_t nn = a.n_slots;
+    for (int li = blockIdx.x * WPB + wv; li < count; li += gridDim.x * WPB) {
+        const int64_t slot = a.slow[li];
+        const SetDesc sd = slot_set(a, slot);
+        const int big = max(sd.g.nbx, sd.g.nby) + 1;
+        int i, j;
+        slot_ij(sd, slot, i, j);
+        const double2 q = node_pos(sd.m, i, j);
+        const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
+        const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
+        WaveSource c;
+        c.pos = a.pos_s;
+        c.perm = a.perm;
+        c.start = a.start + sd.b0;
+        c.g = sd.g;
+        c.neardeg = 0;
+        c.lane = lane;
+        c.lp = slp + wv * STAGE;
+        c.lt = slt + wv * STAGE;
+        Support<WAVE> S;
+        S.u = su + wv * KMAX;
+        S.n = 0;
+        S.lane = lane;
+        uint32_t type = ring ? NT_RING : NT_INTERIOR;
+        uint32_t flags = MF_ESCALATED;
+        int T[3] = {0, 0, 0};
+        int st = R_FAIL;
+        if (!ring) {
+            for (int level = 0;; ++level) {
+                const int hw = level < a.levels ? (sd.hw0 << level) : big;
+                c.set_region(make_region(sd.g, cbx, cby, hw));
+                S.n = 0;
+                st = delaunay_node(c, q, T, S, svis + wv * KMAX);
+                if (st != R_MORE) break;
+                if (c.R.global) {
+                    st = R_FAIL;
+                    break;
+                }
+            }
+            if (c.R.global) flags |= MF_GLOBAL;
+            if (st == R_OUTSIDE) type = NT_OUTSIDE;
+            else if (st == R_CAP) {
+                type = NT_FAILED;
+                if (lane == 0) atomicAdd(&a.diag[D_CAP], 1ull);
+            } else if (st != R_OK) type = NT_FAILED;
+        }
+        if (c.neardeg) flags |= MF_NEARDEG;
+        if (type == NT_INTERIOR) {
+            const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
+            if (lt0 < 0 || lt1 < 0 || lt2 < 0) {
+                type = NT_FAILED;
+            } else {
+                for (int k = lane; k < S.n; k += WAVE) {
+                    const uint32_t e = static_cast<uint32_t>(S.u[k]);
+                    a.out.idx[k * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
+                    a.out.mem[k * nn + slot] = static_cast<uint8_t>(e >> 28);
+                }
+                if (lane == 0) a.out.meta[slot] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
+            }
+        }
+        if (type == NT_RING || type == NT_OUTSIDE) {
+            // closure: the K nearest particles (ties by user id), picked one
+            // per round as the smallest (d^2, user id) above the previous pick
+            int kk = 0;
+            for (int level = 0;; ++level) {
+                const int hw = level < a.levels ? (sd.hw0 << level) : big;
+                c.set_region(make_region(sd.g, cbx, cby, hw));
+                kk = 0;
+                double pd = -1.0;
+                int pu = -1;
+                for (int r = 0; r < KNN; ++r) {
+                    double bd = INFINITY;
+                    int bu = INT_MAX, bt = -1;
+                    c.scan([&](int t, double2 p) {
+                        const double dx = p.x - q.x, dy = p.y - q.y;
+                        const double d2 = dx * dx + dy * dy;
+                        if (d2 < pd || d2 > bd) return;
+                        const int u = c.perm[t];
+                        if (d2 == pd && u <= pu) return;
+                        if (d2 < bd || u < bu) {
+                            bd = d2;
+                            bu = u;
+                            bt = t;
+                        }
+                    });
+#pragma unroll
+                    for (int m = 1; m < WAVE; m <<= 1) {
+                        const double od = __shfl_xor(bd, m);
+                        const int ou = __shfl_xor(bu, m), ot = __shfl_xor(bt, m);
+                        if (ot >= 0 && (bt < 0 || od < bd || (od == bd && ou < bu))) {
+                            bd = od;
+                            bu = ou;
+                            bt = ot;
+                        }
+                    }
+                    if (bt < 0) break;
+                    if (lane == 0) {
+                        a.out.idx[r * nn + slot] = bt;
+                        a.out.mem[r * nn + slot] = 0;
+                    }
+                    pd = bd;
+                    pu = bu;
+                    ++kk;
+                }
+                if (c.R.global) break;
+                if (kk >= KNN && c.certify(q.x, q.y, sqrt(pd))) break;
+            }
+            if (c.R.global) flags |= MF_GLOBAL;
+            if (kk == 0) {
+                type = NT_FAILED;
+            } else if (lane == 0) {
+                a.out.meta[slot] = meta_pack(pending_type(type), kk, 0, 0, 0, flags);
+            }
+        }
+        if (lane == 0) {
+            if (type == NT_FAILED) {
+                a.out.meta[slot] = meta_pack(NT_FAILED, 0, 0, 0, 0, flags);
+                atomicAdd(&a.diag[D_FAILED], 1ull);
+            }
+            if (!ring) atomicAdd(&a.diag[D_ESCALATED], 1ull);
+            if (flags & MF_GLOBAL) atomicAdd(&a.diag[D_GLOBAL], 1ull);
+            if (c.neardeg) atomicAdd(&a.diag[D_NEARDEG], static_cast<unsigned long long>(c.neardeg));
+        }
+        // the row (written by several lanes) is complete before it is weighted
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        count_wave(a, weights_node(a, sd, i, j, lane < QL, slot, lane & (QL - 1), static_cast<int>(threadIdx.x) / QL,
+                                   wsp, wse, wsu, true));
+    }
+}
+
 // Weights of the fast path's pending rows, one quad per node, nodes in the
 // same 8 x 8 tiles as the fast kernel.
 __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
@@ -1706,28 +1754,6 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
         for (int w = 0; w < QWG / WAVE; ++w)
             v = threadIdx.x == WC_SUPMAX ? max(v, wsum[w][threadIdx.x]) : v + wsum[w][threadIdx.x];
         a.tdiag[blockIdx.x * 4 + threadIdx.x] = v;
-    }
-}
-
-// Weights of the slow path's rows: one quad per listed node; every quad of
-// a block takes the same number of turns (wave-wide ballots inside).
-__global__ void __launch_bounds__(QWG) k_weights_slow(KArgs a) {
-    __shared__ double2 sp[QPB * SKP];
-    __shared__ uint32_t se[QPB * SKP];
-    __shared__ int32_t su[QPB * SKP];
-    __builtin_amdgcn_s_setprio(3);
-    const int lane = threadIdx.x & (QL - 1);
-    const int qi = threadIdx.x / QL;
-    const int count = static_cast<int>(a.diag[D_SLOWCNT]);
-    for (int base = blockIdx.x * QPB; base < count; base += gridDim.x * QPB) {
-        const int li = base + qi;
-        const bool valid = li < count;
-        const int64_t slot = valid ? a.slow[li] : 0;
-        const SetDesc sd = slot_set(a, slot);
-        int i, j;
-        slot_ij(sd, slot, i, j);
-        count_wave(a, weights_node(a, sd, i, j, valid, slot, lane, qi, sp, se, su, true));
-        __syncthreads();  // the LDS rows are reused by the next turn
     }
 }
 
@@ -1830,8 +1856,6 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         const int64_t expect = n_nodes / 256 + 64 * static_cast<int64_t>(S);
         const int gs = static_cast<int>(std::min<int64_t>((expect + SWG / WAVE - 1) / (SWG / WAVE), 4096));
         k_slow_geom<<<gs, SWG, 0, side.stream>>>(a);
-        const int gw = static_cast<int>(std::min<int64_t>((expect + QPB - 1) / QPB, 1024));
-        k_weights_slow<<<gw, QWG, 0, side.stream>>>(a);
     }
     P2M_HIP(hipGetLastError());
     P2M_HIP(hipEventRecord(side.join, side.stream));

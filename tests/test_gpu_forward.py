@@ -118,3 +118,29 @@ def test_cluster_and_void_cloud():
     assert d["failed_nodes"] == 0
     got = ops.p2m_project(w, _gpu(c.vals)).cpu().numpy()
     assert_close(got, W @ c.vals, TOL64, "cluster P2M")
+
+
+def test_c1_exact_path_for_most_nodes_is_bitwise_the_default_build(c1):
+    """With the smallest first-pass radius most interior nodes take the exact
+    wave path, and a first region of one h makes it double its regions; the
+    rows, weights and triangles still equal the default build's bit for bit
+    (the build options change only which pass certifies a node)."""
+    c, orc, W, info = c1
+    w0, pos = _build(c)
+    ref = w0.export()
+    saved = {k: ops.p2m_get_option(k) for k in ("fast_radius", "region_h")}
+    try:
+        ops.p2m_set_option("fast_radius", 1.5)
+        ops.p2m_set_option("region_h", 1.0)
+        w1, _ = _build(c)
+        d = w1.diag()
+        got = w1.export()
+    finally:
+        for k, v in saved.items():
+            ops.p2m_set_option(k, v)
+    assert d["failed_nodes"] == 0
+    assert d["slow_nodes"] > d["interior_nodes"] // 2, d
+    for g, r, name in zip(got, ref, ("idx", "w", "cnt", "tri")):
+        assert torch.equal(g, r), name
+    G = ell_to_csr(got[0].numpy(), got[1].numpy(), got[2].numpy(), c.N)
+    assert abs(G - W).max() <= 1e-12
