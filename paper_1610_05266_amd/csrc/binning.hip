@@ -15,6 +15,8 @@
 //             start offsets, places its particles, and sorts each bin by user
 //             id, so the sorted order equals a stable sort by key (bitwise
 //             deterministic, independent of atomic arrival order).
+#include <mutex>
+
 #include "kernels.h"
 
 namespace p2m {
@@ -152,21 +154,38 @@ __global__ void __launch_bounds__(256) k_scan_add(int32_t* __restrict__ out, int
 // user id) records.
 constexpr int PART_PER_THREAD = 2;  // sub <= PART_PER_THREAD * BT
 
-__device__ __forceinline__ void block_exclusive_scan(const int32_t* in, int32_t* out, int n, int32_t* part) {
+// Exclusive prefix of v over the block (BT threads, all active) and the
+// block total in *total: shuffle scans within each wave, one pass over the
+// wave totals in LDS (two barriers; wsum holds BT / 64 entries).
+__device__ __forceinline__ int block_exclusive_prefix(int v, int32_t* wsum, int* total = nullptr) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int o = __shfl_up(inc, d);
+        if (lane >= d) inc += o;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    int before = 0, all = 0;
+    for (int k = 0; k < BT / 64; ++k) {
+        const int t = wsum[k];
+        before += k < w ? t : 0;
+        all += t;
+    }
+    __syncthreads();  // wsum may be reused after this
+    if (total) *total = all;
+    return before + inc - v;
+}
+
+// Exclusive scan of in[0..n) into out (n <= a few entries per thread).
+__device__ __forceinline__ void block_exclusive_scan(const int32_t* in, int32_t* out, int n, int32_t* wsum) {
     const int per = (n + BT - 1) / BT;
     const int r0 = threadIdx.x * per;
     int acc = 0;
     for (int k = 0; k < per; ++k)
         if (r0 + k < n) acc += in[r0 + k];
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 1; off < BT; off <<= 1) {
-        const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
-    }
-    int run = part[threadIdx.x] - acc;
+    int run = block_exclusive_prefix(acc, wsum);
     for (int k = 0; k < per; ++k)
         if (r0 + k < n) {
             out[r0 + k] = run;
@@ -180,7 +199,7 @@ __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos
                                                 double2* __restrict__ part_pos, uint32_t* __restrict__ part_key,
                                                 int32_t* __restrict__ part_uid) {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ int32_t part[BT];
+    __shared__ int32_t part[BT / 64];
     const int nsb = bg.nsb;
     double2* spos = reinterpret_cast<double2*>(smem);
     uint32_t* skey = reinterpret_cast<uint32_t*>(spos + sub);
@@ -243,45 +262,62 @@ __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos
 }
 
 // 4. one block per super-bin: bin counts and start offsets, placement, and a
-// per-bin sort by user id (bins hold O(1) particles at the intended width)
-__global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __restrict__ offs,
+// per-bin sort by user id (bins hold O(1) particles at the intended width).
+// When the super-bin's particles fit (`cap`), they are staged in LDS and
+// placed and sorted there, and the sorted run is written once, coalesced;
+// otherwise the ranks go through global memory and the bins are sorted in
+// place.  Dynamic LDS: positions [cap], user ids [cap], bin starts [M + 1],
+// then 16-bit keys, ranks and output order [cap] each.
+__global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __restrict__ offs, int cap,
                                                  const double2* __restrict__ part_pos,
                                                  const uint32_t* __restrict__ part_key,
                                                  const int32_t* __restrict__ part_uid, int32_t* __restrict__ rank,
                                                  int32_t* __restrict__ start, double2* __restrict__ pos_s,
                                                  int32_t* __restrict__ perm, unsigned long long* __restrict__ diag) {
-    __shared__ int32_t pre[(1 << MAX_SBS) + 1];
-    __shared__ int32_t part[BT];
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int32_t wsum[BT / 64];
     __shared__ int32_t ndup;
-    const int b = blockIdx.x;
     const int M = 1 << bg.sbs;
+    double2* lpos = reinterpret_cast<double2*>(smem);
+    int32_t* luid = reinterpret_cast<int32_t*>(lpos + cap);
+    int32_t* pre = luid + cap;
+    uint16_t* lkey = reinterpret_cast<uint16_t*>(pre + M + 1);
+    uint16_t* lrank = lkey + cap;
+    uint16_t* lord = lrank + cap;
+    const int b = blockIdx.x;
     const int lo = offs[static_cast<int64_t>(b) * bg.nch];
     const int hi = offs[static_cast<int64_t>(b + 1) * bg.nch];
+    const int n = hi - lo;
+    const bool staged = n <= cap;
     const uint32_t k0 = static_cast<uint32_t>(b) << bg.sbs;
     for (int k = threadIdx.x; k <= M; k += BT) pre[k] = 0;
     if (threadIdx.x == 0) ndup = 0;
     __syncthreads();
     // counts (pre[k + 1] collects bin k) and each particle's rank in its bin
+    if (staged) {
+        for (int e = threadIdx.x; e < n; e += BT) {
+            const int k = static_cast<int>(part_key[lo + e] - k0);
+            lkey[e] = static_cast<uint16_t>(k);
+            lpos[e] = part_pos[lo + e];
+            luid[e] = part_uid[lo + e];
+            lrank[e] = static_cast<uint16_t>(atomicAdd(&pre[k + 1], 1));
+        }
+    } else {
 #pragma unroll 4
-    for (int e = lo + threadIdx.x; e < hi; e += BT) rank[e] = atomicAdd(&pre[part_key[e] - k0 + 1], 1);
+        for (int e = lo + threadIdx.x; e < hi; e += BT) rank[e] = atomicAdd(&pre[part_key[e] - k0 + 1], 1);
+    }
     __syncthreads();
     // inclusive scan of pre[1..M]: thread t sums a run of M / BT entries
-    const int run = M / BT;
-    const int r0 = 1 + threadIdx.x * run;
-    int acc = 0;
-    for (int k = 0; k < run; ++k) acc += pre[r0 + k];
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 1; off < BT; off <<= 1) {
-        const int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += add;
-        __syncthreads();
-    }
-    int run_base = part[threadIdx.x] - acc;
-    for (int k = 0; k < run; ++k) {
-        run_base += pre[r0 + k];
-        pre[r0 + k] = run_base;
+    {
+        const int run = M / BT;
+        const int r0 = 1 + threadIdx.x * run;
+        int acc = 0;
+        for (int k = 0; k < run; ++k) acc += pre[r0 + k];
+        int base = block_exclusive_prefix(acc, wsum);
+        for (int k = 0; k < run; ++k) {
+            base += pre[r0 + k];
+            pre[r0 + k] = base;
+        }
     }
     __syncthreads();
     // start offsets of this super-bin's bins (and of the excluded bucket)
@@ -291,37 +327,69 @@ __global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __r
     }
     if (k0 <= bg.nbins && bg.nbins < k0 + static_cast<uint32_t>(M) && threadIdx.x == 0)
         start[bg.nbins + 1] = static_cast<int32_t>(bg.N);
-    // placement
-#pragma unroll 4
-    for (int e = lo + threadIdx.x; e < hi; e += BT) {
-        const int slot = lo + pre[part_key[e] - k0] + rank[e];
-        pos_s[slot] = part_pos[e];
-        perm[slot] = part_uid[e];
-    }
-    __syncthreads();
-    // per bin: insertion sort by user id; coincident particles always share a
-    // bin, so pairs of them are counted here (no Delaunay triangulation)
     int dup = 0;
-    for (int k = threadIdx.x; k < M; k += BT) {
-        if (k0 + static_cast<uint32_t>(k) >= bg.nbins) break;  // the excluded bucket is not sorted
-        const int s = lo + pre[k], e = lo + pre[k + 1];
-        for (int i = s + 1; i < e; ++i) {
-            const int32_t pi = perm[i];
-            const double2 xi = pos_s[i];
-            int j = i - 1;
-            while (j >= s && perm[j] > pi) {
-                perm[j + 1] = perm[j];
-                pos_s[j + 1] = pos_s[j];
-                --j;
+    if (staged) {
+        for (int e = threadIdx.x; e < n; e += BT) lord[pre[lkey[e]] + lrank[e]] = static_cast<uint16_t>(e);
+        __syncthreads();
+        // per bin: insertion sort by user id; coincident particles always
+        // share a bin, so pairs of them are counted here
+        for (int k = threadIdx.x; k < M; k += BT) {
+            if (k0 + static_cast<uint32_t>(k) >= bg.nbins) break;  // the excluded bucket is not sorted
+            const int s0 = pre[k], s1 = pre[k + 1];
+            for (int i = s0 + 1; i < s1; ++i) {
+                const uint16_t oi = lord[i];
+                const int32_t ui = luid[oi];
+                int j = i - 1;
+                while (j >= s0 && luid[lord[j]] > ui) {
+                    lord[j + 1] = lord[j];
+                    --j;
+                }
+                lord[j + 1] = oi;
             }
-            perm[j + 1] = pi;
-            pos_s[j + 1] = xi;
+            for (int i = s0 + 1; i < s1; ++i) {
+                const double2 pa = lpos[lord[i]];
+                for (int q = s0; q < i; ++q) {
+                    const double2 pc = lpos[lord[q]];
+                    dup += (pa.x == pc.x && pa.y == pc.y) ? 1 : 0;
+                }
+            }
         }
-        for (int i = s + 1; i < e; ++i) {
-            const double2 a = pos_s[i];
-            for (int q = s; q < i; ++q) {
-                const double2 c = pos_s[q];
-                dup += (a.x == c.x && a.y == c.y) ? 1 : 0;
+        __syncthreads();
+        for (int d = threadIdx.x; d < n; d += BT) {
+            const int e = lord[d];
+            pos_s[lo + d] = lpos[e];
+            perm[lo + d] = luid[e];
+        }
+    } else {
+        // placement
+#pragma unroll 4
+        for (int e = lo + threadIdx.x; e < hi; e += BT) {
+            const int slot = lo + pre[part_key[e] - k0] + rank[e];
+            pos_s[slot] = part_pos[e];
+            perm[slot] = part_uid[e];
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < M; k += BT) {
+            if (k0 + static_cast<uint32_t>(k) >= bg.nbins) break;  // the excluded bucket is not sorted
+            const int s0 = lo + pre[k], s1 = lo + pre[k + 1];
+            for (int i = s0 + 1; i < s1; ++i) {
+                const int32_t pi = perm[i];
+                const double2 xi = pos_s[i];
+                int j = i - 1;
+                while (j >= s0 && perm[j] > pi) {
+                    perm[j + 1] = perm[j];
+                    pos_s[j + 1] = pos_s[j];
+                    --j;
+                }
+                perm[j + 1] = pi;
+                pos_s[j + 1] = xi;
+            }
+            for (int i = s0 + 1; i < s1; ++i) {
+                const double2 pa = pos_s[i];
+                for (int q = s0; q < i; ++q) {
+                    const double2 pc = pos_s[q];
+                    dup += (pa.x == pc.x && pa.y == pc.y) ? 1 : 0;
+                }
             }
         }
     }
@@ -383,9 +451,23 @@ int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDe
     const size_t lds = static_cast<size_t>(24) * sub + static_cast<size_t>(12) * bg.nsb;
     k_bin_part<<<bg.nch, BT, lds, st>>>(P, b.key, bg, b.hist, sub, reinterpret_cast<double2*>(b.part_pos),
                                         b.part_key, b.part_uid);
-    k_bin_local<<<bg.nsb, BT, 0, st>>>(bg, b.hist, reinterpret_cast<const double2*>(b.part_pos), b.part_key,
-                                       b.part_uid, b.rank, b.start, reinterpret_cast<double2*>(b.pos_s), b.perm,
-                                       diag);
+    // particles of a super-bin staged in LDS: as many as fit beside the bin
+    // starts in 160 KB (16-byte position, user id, three 16-bit fields)
+    const int M = 1 << bg.sbs;
+    const int64_t room = 163840 - 2048 - 4 * static_cast<int64_t>(M + 1);
+    const int cap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(room / 26, 0) & ~int64_t(7), 65535));
+    const size_t llds = static_cast<size_t>(cap) * 26 + 4 * static_cast<size_t>(M + 1);
+    // dynamic LDS beyond 64 KB must be allowed once per function
+    static std::once_flag lds_once;
+    static hipError_t lds_err = hipSuccess;
+    std::call_once(lds_once, [] {
+        lds_err = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bin_local),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 163840 - 2048);
+    });
+    P2M_HIP(lds_err);
+    k_bin_local<<<bg.nsb, BT, llds, st>>>(bg, b.hist, cap, reinterpret_cast<const double2*>(b.part_pos), b.part_key,
+                                          b.part_uid, b.rank, b.start, reinterpret_cast<double2*>(b.pos_s), b.perm,
+                                          diag);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }

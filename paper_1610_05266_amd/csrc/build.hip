@@ -1186,26 +1186,52 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
             tst[r * (TDIM + 1) + c] = start[(rby0 + r) * sd.g.nbx + rbx0 + c];
         }
         __syncthreads();
-        if (threadIdx.x <= nrow) {
-            int acc = 0;
-            for (int r = 0; r < static_cast<int>(threadIdx.x); ++r)
-                acc += tst[r * (TDIM + 1) + ncol] - tst[r * (TDIM + 1)];
-            trb[threadIdx.x] = acc;
+        if (threadIdx.x < WAVE) {
+            // row bases: an exclusive prefix sum of the row lengths over the
+            // first wave (nrow <= TDIM < 64 rows)
+            const int r = threadIdx.x;
+            const int len = r < nrow ? tst[r * (TDIM + 1) + ncol] - tst[r * (TDIM + 1)] : 0;
+            int inc = len;
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1) {
+                const int o = __shfl_up(inc, d);
+                if (r >= d) inc += o;
+            }
+            if (r <= nrow) trb[r] = inc - len;
         }
         __syncthreads();
         const int total = trb[nrow];
         staged = total <= TCAP;
         if (staged) {
-            for (int e = threadIdx.x; e < total; e += QWG) {
+            // every source index first, then all loads in flight together
+            // (entries past the total load particle 0 and are not stored)
+            constexpr int EPT = TCAP / QWG;
+            int src[EPT];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int e = static_cast<int>(threadIdx.x) + u * QWG;
                 int lo = 0, hi = nrow - 1;  // the row holding staged entry e
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
                     if (trb[mid] <= e) lo = mid;
                     else hi = mid - 1;
                 }
-                const int src = tst[lo * (TDIM + 1)] + (e - trb[lo]);
-                tpos[e] = a.pos_s[src];
-                tsi[e] = src;
+                src[u] = e < total ? tst[lo * (TDIM + 1)] + (e - trb[lo]) : 0;
+            }
+            double px[EPT], py[EPT];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const double2 v = a.pos_s[src[u]];
+                px[u] = v.x;
+                py[u] = v.y;
+            }
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int e = static_cast<int>(threadIdx.x) + u * QWG;
+                if (e < total) {
+                    tpos[e] = make_double2(px[u], py[u]);
+                    tsi[e] = src[u];
+                }
             }
         }
         __syncthreads();
