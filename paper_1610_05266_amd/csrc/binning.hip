@@ -8,13 +8,16 @@
 // consecutive bin keys (rows of bins):
 //   1. key:   bin key per particle, and per chunk of particles an LDS
 //             histogram over super-bins;
-//   2. scan:  exclusive prefix sum of the (super-bin, chunk) histogram;
+//   2. scan:  exclusive prefix sums of the (super-bin, chunk) histogram
+//             within tiles, and the tile totals (their prefix is formed by
+//             the consumers); this kernel also clears the diagnostics;
 //   3. part:  each chunk scatters (position, key, user id) into its super-bin
 //             ranges (runs of consecutive slots per chunk);
 //   4. local: one block per super-bin counts its bins in LDS, writes their
 //             start offsets, places its particles, and sorts each bin by user
 //             id, so the sorted order equals a stable sort by key (bitwise
 //             deterministic, independent of atomic arrival order).
+// Four launches in all: each dependent launch costs microseconds by itself.
 #include <mutex>
 
 #include "kernels.h"
@@ -55,108 +58,10 @@ struct BinGeom {
     int nsb;       // super-bins
 };
 
-// 1. keys and the (super-bin, chunk) histogram, super-bin major
-__global__ void __launch_bounds__(BT) k_bin_key(const double2* __restrict__ pos, const SetDesc* __restrict__ sets,
-                                               int S, BinGeom bg, uint32_t* __restrict__ key,
-                                               int32_t* __restrict__ hist, unsigned long long* __restrict__ diag) {
-    __shared__ int32_t lh[MAX_SB];
-    __shared__ int32_t nbad;
-    const int c = blockIdx.x;
-    for (int k = threadIdx.x; k < bg.nsb; k += BT) lh[k] = 0;
-    if (threadIdx.x == 0) nbad = 0;
-    __syncthreads();
-    const int64_t lo = c * bg.cs, hi = min(bg.N, lo + bg.cs);
-#pragma unroll 4
-    for (int64_t i = lo + threadIdx.x; i < hi; i += BT) {
-        const SetDesc& sd = sets[set_search(S, i, [&](int s) { return sets[s].p0; })];
-        const uint32_t k = bin_key(pos[i], sd, bg.nbins);
-        key[i] = k;
-        atomicAdd(&lh[k >> bg.sbs], 1);
-        if (k == bg.nbins) atomicAdd(&nbad, 1);
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < bg.nsb; k += BT) hist[static_cast<int64_t>(k) * bg.nch + c] = lh[k];
-    if (threadIdx.x == 0 && nbad) atomicAdd(&diag[D_BAD], static_cast<unsigned long long>(nbad));
-}
-
-// Phase 1 of the scan: per-tile exclusive scan, tile totals to tsum.
-__global__ void __launch_bounds__(SCAN_THREADS) k_scan_tile(const int32_t* __restrict__ in,
-                                                            int32_t* __restrict__ out, int n,
-                                                            int32_t* __restrict__ tsum) {
-    __shared__ int32_t s[SCAN_THREADS];
-    const int t = threadIdx.x;
-    const int base = blockIdx.x * SCAN_TILE + t * SCAN_ITEMS;
-    int32_t v[SCAN_ITEMS];
-    int32_t sum = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int idx = base + k;
-        v[k] = idx < n ? in[idx] : 0;
-        sum += v[k];
-    }
-    s[t] = sum;
-    __syncthreads();
-    for (int off = 1; off < SCAN_THREADS; off <<= 1) {
-        const int32_t add = t >= off ? s[t - off] : 0;
-        __syncthreads();
-        s[t] += add;
-        __syncthreads();
-    }
-    int32_t run = s[t] - sum;  // exclusive prefix of this thread within the tile
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int idx = base + k;
-        if (idx < n) out[idx] = run;
-        run += v[k];
-    }
-    if (t == SCAN_THREADS - 1) tsum[blockIdx.x] = s[t];
-}
-
-// Phase 2: exclusive scan of the tile totals (one block); tsum[ntiles] = total.
-__global__ void __launch_bounds__(1024) k_scan_sums(int32_t* __restrict__ tsum, int ntiles) {
-    __shared__ int32_t s[1024];
-    __shared__ int32_t carry;
-    const int t = threadIdx.x;
-    if (t == 0) carry = 0;
-    __syncthreads();
-    for (int base = 0; base < ntiles; base += 1024) {
-        const int idx = base + t;
-        const int32_t v = idx < ntiles ? tsum[idx] : 0;
-        s[t] = v;
-        __syncthreads();
-        for (int off = 1; off < 1024; off <<= 1) {
-            const int32_t add = t >= off ? s[t - off] : 0;
-            __syncthreads();
-            s[t] += add;
-            __syncthreads();
-        }
-        const int32_t c = carry;
-        if (idx < ntiles) tsum[idx] = c + s[t] - v;
-        __syncthreads();
-        if (t == 1023) carry = c + s[t];
-        __syncthreads();
-    }
-    if (t == 0) tsum[ntiles] = carry;
-}
-
-// Phase 3: add tile offsets; out[n] = total.
-__global__ void __launch_bounds__(256) k_scan_add(int32_t* __restrict__ out, int n,
-                                                  const int32_t* __restrict__ tsum, int ntiles) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] += tsum[i / SCAN_TILE];
-    if (i == n) out[n] = tsum[ntiles];
-}
-
-// 3. each chunk scatters its particles into its slots of every super-bin.
-// A sub-chunk of `sub` particles is first ordered by super-bin in LDS, so that
-// consecutive threads write consecutive slots of each run (coalesced).
-// Dynamic LDS: gcur[nsb], lcnt[nsb], lstart[nsb], then sub (position, key,
-// user id) records.
-constexpr int PART_PER_THREAD = 2;  // sub <= PART_PER_THREAD * BT
-
-// Exclusive prefix of v over the block (BT threads, all active) and the
+// Exclusive prefix of v over the block (NT threads, all active) and the
 // block total in *total: shuffle scans within each wave, one pass over the
-// wave totals in LDS (two barriers; wsum holds BT / 64 entries).
+// wave totals in LDS (two barriers; wsum holds NT / 64 entries).
+template <int NT = BT>
 __device__ __forceinline__ int block_exclusive_prefix(int v, int32_t* wsum, int* total = nullptr) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     int inc = v;
@@ -168,7 +73,7 @@ __device__ __forceinline__ int block_exclusive_prefix(int v, int32_t* wsum, int*
     if (lane == 63) wsum[w] = inc;
     __syncthreads();
     int before = 0, all = 0;
-    for (int k = 0; k < BT / 64; ++k) {
+    for (int k = 0; k < NT / 64; ++k) {
         const int t = wsum[k];
         before += k < w ? t : 0;
         all += t;
@@ -194,8 +99,71 @@ __device__ __forceinline__ void block_exclusive_scan(const int32_t* in, int32_t*
     __syncthreads();
 }
 
+// 1. keys and the (super-bin, chunk) histogram, super-bin major
+__global__ void __launch_bounds__(BT) k_bin_key(const double2* __restrict__ pos, const SetDesc* __restrict__ sets,
+                                               int S, BinGeom bg, uint32_t* __restrict__ key,
+                                               int32_t* __restrict__ hist) {
+    __shared__ int32_t lh[MAX_SB];
+    const int c = blockIdx.x;
+    for (int k = threadIdx.x; k < bg.nsb; k += BT) lh[k] = 0;
+    __syncthreads();
+    const int64_t lo = c * bg.cs, hi = min(bg.N, lo + bg.cs);
+#pragma unroll 4
+    for (int64_t i = lo + threadIdx.x; i < hi; i += BT) {
+        const SetDesc& sd = sets[set_search(S, i, [&](int s) { return sets[s].p0; })];
+        const uint32_t k = bin_key(pos[i], sd, bg.nbins);
+        key[i] = k;
+        atomicAdd(&lh[k >> bg.sbs], 1);
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < bg.nsb; k += BT) hist[static_cast<int64_t>(k) * bg.nch + c] = lh[k];
+}
+
+// 2. exclusive scan of hist[0..n) within tiles of SCAN_TILE entries (entry n,
+// the end offset, scans a zero), tile totals to tsum; block 0 clears the
+// diagnostics (nothing before this kernel counts into them).
+__global__ void __launch_bounds__(SCAN_THREADS) k_hist_scan(int32_t* __restrict__ hist, int n,
+                                                            int32_t* __restrict__ tsum,
+                                                            unsigned long long* __restrict__ diag) {
+    __shared__ int32_t wsum[SCAN_THREADS / 64];
+    const int t = threadIdx.x;
+    if (blockIdx.x == 0 && t < D_COUNT) diag[t] = 0ull;
+    const int base = blockIdx.x * SCAN_TILE + t * SCAN_ITEMS;
+    int32_t v[SCAN_ITEMS];
+    int32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int idx = base + k;
+        v[k] = idx < n ? hist[idx] : 0;
+        sum += v[k];
+    }
+    int total = 0;
+    int32_t run = block_exclusive_prefix<SCAN_THREADS>(sum, wsum, &total);
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int idx = base + k;
+        if (idx <= n) hist[idx] = run;
+        run += v[k];
+    }
+    if (t == 0) tsum[blockIdx.x] = total;
+}
+
+// Global exclusive offset of histogram entry i: its tile-local prefix plus
+// the totals of the tiles before it (tpre: their exclusive prefix in LDS).
+__device__ __forceinline__ int hist_offset(const int32_t* hist, const int32_t* tpre, int64_t i) {
+    return hist[i] + tpre[i / SCAN_TILE];
+}
+
+// 3. each chunk scatters its particles into its slots of every super-bin.
+// A sub-chunk of `sub` particles is first ordered by super-bin in LDS, so that
+// consecutive threads write consecutive slots of each run (coalesced).
+// Dynamic LDS: gcur[nsb], lcnt[nsb], lstart[nsb], then sub (position, key,
+// user id) records.
+constexpr int PART_PER_THREAD = 2;  // sub <= PART_PER_THREAD * BT
+
 __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos, const uint32_t* __restrict__ key,
-                                                BinGeom bg, const int32_t* __restrict__ offs, int sub,
+                                                BinGeom bg, const int32_t* __restrict__ offs,
+                                                const int32_t* __restrict__ tsum, int ntiles, int sub,
                                                 double2* __restrict__ part_pos, uint32_t* __restrict__ part_key,
                                                 int32_t* __restrict__ part_uid) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -207,8 +175,10 @@ __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos
     int32_t* gcur = suid + sub;
     int32_t* lcnt = gcur + nsb;
     int32_t* lstart = lcnt + nsb;
+    int32_t* tpre = lstart + nsb;  // [ntiles]
     const int c = blockIdx.x;
-    for (int k = threadIdx.x; k < nsb; k += BT) gcur[k] = offs[static_cast<int64_t>(k) * bg.nch + c];
+    block_exclusive_scan(tsum, tpre, ntiles, part);
+    for (int k = threadIdx.x; k < nsb; k += BT) gcur[k] = hist_offset(offs, tpre, static_cast<int64_t>(k) * bg.nch + c);
     const int64_t lo = c * bg.cs, hi = min(bg.N, lo + bg.cs);
     for (int64_t b0 = lo; b0 < hi; b0 += sub) {
         const int n = static_cast<int>(min<int64_t>(sub, hi - b0));
@@ -268,7 +238,8 @@ __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos
 // otherwise the ranks go through global memory and the bins are sorted in
 // place.  Dynamic LDS: positions [cap], user ids [cap], bin starts [M + 1],
 // then 16-bit keys, ranks and output order [cap] each.
-__global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __restrict__ offs, int cap,
+__global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __restrict__ offs,
+                                                 const int32_t* __restrict__ tsum, int cap,
                                                  const double2* __restrict__ part_pos,
                                                  const uint32_t* __restrict__ part_key,
                                                  const int32_t* __restrict__ part_uid, int32_t* __restrict__ rank,
@@ -285,8 +256,24 @@ __global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __r
     uint16_t* lrank = lkey + cap;
     uint16_t* lord = lrank + cap;
     const int b = blockIdx.x;
-    const int lo = offs[static_cast<int64_t>(b) * bg.nch];
-    const int hi = offs[static_cast<int64_t>(b + 1) * bg.nch];
+    // the super-bin's range: tile-local offsets plus the totals of the tiles
+    // before them
+    int lo, hi;
+    {
+        const int64_t ilo = static_cast<int64_t>(b) * bg.nch, ihi = static_cast<int64_t>(b + 1) * bg.nch;
+        const int tlo = static_cast<int>(ilo / SCAN_TILE), thi = static_cast<int>(ihi / SCAN_TILE);
+        int slo = 0, shi = 0;
+        for (int k = threadIdx.x; k < thi; k += BT) {
+            const int v = tsum[k];
+            slo += k < tlo ? v : 0;
+            shi += v;
+        }
+        int tot_lo = 0, tot_hi = 0;
+        (void)block_exclusive_prefix(slo, wsum, &tot_lo);
+        (void)block_exclusive_prefix(shi, wsum, &tot_hi);
+        lo = offs[ilo] + tot_lo;
+        hi = offs[ihi] + tot_hi;
+    }
     const int n = hi - lo;
     const bool staged = n <= cap;
     const uint32_t k0 = static_cast<uint32_t>(b) << bg.sbs;
@@ -325,8 +312,11 @@ __global__ void __launch_bounds__(BT) k_bin_local(BinGeom bg, const int32_t* __r
         const uint32_t gk = k0 + static_cast<uint32_t>(k);
         if (gk <= bg.nbins) start[gk] = lo + pre[k];
     }
-    if (k0 <= bg.nbins && bg.nbins < k0 + static_cast<uint32_t>(M) && threadIdx.x == 0)
+    if (k0 <= bg.nbins && bg.nbins < k0 + static_cast<uint32_t>(M) && threadIdx.x == 0) {
         start[bg.nbins + 1] = static_cast<int32_t>(bg.N);
+        // particles outside their mesh (or non-finite) make up the excluded bucket
+        diag[D_BAD] = static_cast<unsigned long long>(bg.N - (lo + pre[bg.nbins - k0]));
+    }
     int dup = 0;
     if (staged) {
         for (int e = threadIdx.x; e < n; e += BT) lord[pre[lkey[e]] + lrank[e]] = static_cast<uint16_t>(e);
@@ -404,15 +394,6 @@ inline int blocks_for(int64_t n, int threads) { return static_cast<int>((n + thr
 
 int64_t scan_tile_count(int64_t n) { return (n + SCAN_TILE - 1) / SCAN_TILE; }
 
-int exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum, hipStream_t st) {
-    const int ntiles = static_cast<int>(scan_tile_count(n));
-    k_scan_tile<<<ntiles, SCAN_THREADS, 0, st>>>(in, out, static_cast<int>(n), tsum);
-    k_scan_sums<<<1, 1024, 0, st>>>(tsum, ntiles);
-    k_scan_add<<<blocks_for(n + 1, 256), 256, 0, st>>>(out, static_cast<int>(n), tsum, ntiles);
-    P2M_HIP(hipGetLastError());
-    return P2M_OK;
-}
-
 int bin_layout(int64_t N, int64_t nbins, int* nch, int* sbs, int* nsb) {
     int shift = 12;
     while (shift < MAX_SBS && (nbins >> shift) + 1 > MAX_SB) ++shift;
@@ -437,20 +418,20 @@ int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDe
     bg.cs = (N + bg.nch - 1) / bg.nch;
     const int64_t nh = static_cast<int64_t>(bg.nsb) * bg.nch;
     const double2* P = reinterpret_cast<const double2*>(pos);
-    k_bin_key<<<bg.nch, BT, 0, st>>>(P, sets, S, bg, b.key, b.hist, diag);
-    P2M_HIP(hipGetLastError());
-    rc = exclusive_scan(b.hist, b.hist, nh, b.tsum, st);
-    if (rc) return rc;
+    k_bin_key<<<bg.nch, BT, 0, st>>>(P, sets, S, bg, b.key, b.hist);
+    const int ntiles = static_cast<int>(scan_tile_count(nh + 1));
+    k_hist_scan<<<ntiles, SCAN_THREADS, 0, st>>>(b.hist, static_cast<int>(nh), b.tsum, diag);
     // sub-chunk size: as many records as fit beside the counters in 64 KB
     int sub = PART_PER_THREAD * BT;
-    while (sub > 256 && 12 * static_cast<int64_t>(bg.nsb) + 24 * static_cast<int64_t>(sub) > 65536) sub >>= 1;
-    if (12 * static_cast<int64_t>(bg.nsb) + 24 * static_cast<int64_t>(sub) > 65536) {
+    const int64_t fixed = 12 * static_cast<int64_t>(bg.nsb) + 4 * static_cast<int64_t>(ntiles);
+    while (sub > 256 && fixed + 24 * static_cast<int64_t>(sub) > 65536) sub >>= 1;
+    if (fixed + 24 * static_cast<int64_t>(sub) > 65536) {
         set_error("binning: too many super-bins (%d)", bg.nsb);
         return P2M_EINVAL;
     }
-    const size_t lds = static_cast<size_t>(24) * sub + static_cast<size_t>(12) * bg.nsb;
-    k_bin_part<<<bg.nch, BT, lds, st>>>(P, b.key, bg, b.hist, sub, reinterpret_cast<double2*>(b.part_pos),
-                                        b.part_key, b.part_uid);
+    const size_t lds = static_cast<size_t>(24) * sub + static_cast<size_t>(fixed);
+    k_bin_part<<<bg.nch, BT, lds, st>>>(P, b.key, bg, b.hist, b.tsum, ntiles, sub,
+                                        reinterpret_cast<double2*>(b.part_pos), b.part_key, b.part_uid);
     // particles of a super-bin staged in LDS: as many as fit beside the bin
     // starts in 160 KB (16-byte position, user id, three 16-bit fields)
     const int M = 1 << bg.sbs;
@@ -465,7 +446,7 @@ int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDe
                                       hipFuncAttributeMaxDynamicSharedMemorySize, 163840 - 2048);
     });
     P2M_HIP(lds_err);
-    k_bin_local<<<bg.nsb, BT, llds, st>>>(bg, b.hist, cap, reinterpret_cast<const double2*>(b.part_pos), b.part_key,
+    k_bin_local<<<bg.nsb, BT, llds, st>>>(bg, b.hist, b.tsum, cap, reinterpret_cast<const double2*>(b.part_pos), b.part_key,
                                           b.part_uid, b.rank, b.start, reinterpret_cast<double2*>(b.pos_s), b.perm,
                                           diag);
     P2M_HIP(hipGetLastError());

@@ -357,8 +357,8 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     w->flags = flags;
     *wout = w;
 
-    rc = fill_u64(w->diag, 0ull, D_COUNT, st);
-    if (!rc) rc = bin_particles(w->bins, pos, N, w->dsets, S, nbins, w->diag, st);
+    // (the binning clears the diagnostics before anything counts into them)
+    rc = bin_particles(w->bins, pos, N, w->dsets, S, nbins, w->diag, st);
     if (rc) return rc;
     BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem};
     SideWork side{nullptr, w->ev_fork, w->ev_join};

@@ -44,7 +44,6 @@ struct BinBuffers {
 // Chunks, log2(bins per super-bin) and super-bins of the two-level sort.
 int bin_layout(int64_t N, int64_t nbins, int* nch, int* sbs, int* nsb);
 int64_t scan_tile_count(int64_t n);
-int exclusive_scan(const int32_t* in, int32_t* out, int64_t n, int32_t* tsum, hipStream_t st);
 // Bins of set s are b0(s) .. b0(s) + nbx nby - 1; key nbins (all sets)
 // collects particles outside their set's mesh or non-finite.
 int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDesc* sets, int S, int64_t nbins,
