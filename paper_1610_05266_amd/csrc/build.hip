@@ -476,38 +476,14 @@ struct QuadSource {
         int am = amb ? 1 : 0;
         am |= lane_xor<QL>(am, 1);
         am |= lane_xor<QL>(am, 2);
-        if (am) return wrap_exact(iv, v, ia, a, sgn);
         Key k;
-        k.t = bt;
+        k.t = am ? -2 : bt;
         k.num = bn;
         k.cr = bc;
         k.Nm = k.Cm = 0.0;
         k.bx = bx;
         k.by = by;
         return k;
-    }
-    // The same step with each candidate's own forward error bound, as the
-    // wave path compares (key_of, key_better): it decides the steps the
-    // static bound leaves open because that bound is loose.  A true near tie
-    // or a candidate nearly on the line through v and a still gives t = -2:
-    // those are broken by user id on the wave path alone, so that no result
-    // depends on the order in which a pass meets tied candidates.
-    __device__ Key wrap_exact(int iv, double2 v, int ia, double2 a, double sgn) {
-        auto uid = [&](int t) { return perm[t]; };
-        Key best = no_key();
-        int nd = 0;
-#pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            if (s >= n || ct_[s] == iv || ct_[s] == ia) continue;
-            const Key k = key_of(ct_[s], v, a, make_double2(cx_[s], cy_[s]), sgn, nd);
-            if (key_better(k, best, uid, nd)) best = k;
-        }
-        reduce_key<QL>(best, uid, lane, nd);
-        int tie = nd > 0 ? 1 : 0;
-        tie |= lane_xor<QL>(tie, 1);
-        tie |= lane_xor<QL>(tie, 2);
-        if (tie) best.t = -2;
-        return best;
     }
 };
 
@@ -1144,21 +1120,24 @@ __device__ void quad_closure(const KArgs& a, int64_t slot, double2 q, int n, int
 // bits) for k_weights.  Boundary-ring nodes: the KNN nearest particles,
 // picked one per round (smallest squared distance, ties by user id), as a
 // pending closure row.  Anything not certified goes to the slow list.
-constexpr int TCAP = 2048;  // particles of a tile's bin region staged in LDS
+constexpr int TCAP = 1792;  // particles of a tile's bin region staged in LDS
 constexpr int TDIM = 48;    // bin rows / columns of that region (at most)
 
 template <int NS>
 __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
-    // per-quad rows padded by one word: the 16 quads of a wave then hit
-    // distinct LDS banks when they touch the same slot
-    __shared__ int32_t su[QPB * KPITCH];
-    __shared__ int32_t svis[QPB * KPITCH];
     // the tile's bin region (its nodes' search windows): bin starts, row
-    // bases and the particles, copied once with coalesced row reads
+    // bases and the particles, copied once with coalesced row reads.  The
+    // bin starts are needed only until every quad has gathered; the per-quad
+    // support rows (padded by one word, so that the 16 quads of a wave hit
+    // distinct LDS banks) take their place afterwards.
+    constexpr int TSH = TDIM * (TDIM + 1) > 2 * QPB * KPITCH ? TDIM * (TDIM + 1) : 2 * QPB * KPITCH;
     __shared__ double2 tpos[TCAP];
     __shared__ int32_t tsi[TCAP];
-    __shared__ int32_t tst[TDIM * (TDIM + 1)];
+    __shared__ int32_t tsh[TSH];
     __shared__ int32_t trb[TDIM + 1];
+    int32_t* const tst = tsh;
+    int32_t* const su = tsh;
+    int32_t* const svis = tsh + QPB * KPITCH;
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const SetDesc sd = tile_set(a, blockIdx.x);
@@ -1171,9 +1150,12 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
     const int32_t* start = a.start + sd.b0;
     bool done = false;
-    // ---- stage the region (block-uniform decision)
+    // ---- stage the region (block-uniform decision): it covers the window
+    // of every node of the tile, interior, edge or corner
     const int hcor = static_cast<int>(ceil(sd.Rc * 1.4142135623730951 / sd.g.bw));
-    const int hmax = max(max(sd.hwf, sd.hwc), hcor);
+    const bool xedge = tx == 0 || tx * 8 + 7 >= sd.m.nx, yedge = ty == 0 || ty * 8 + 7 >= sd.m.ny;
+    const int hmax = (xedge && yedge) ? max(max(sd.hwf, sd.hwc), hcor)
+                                      : (xedge || yedge) ? max(sd.hwf, sd.hwc) : sd.hwf;
     const int rbx0 = max(tx * 8 * sd.g.kb - hmax, 0);
     const int rbx1 = min(min(tx * 8 + 7, sd.m.nx) * sd.g.kb + hmax, sd.g.nbx);
     const int rby0 = max(ty * 8 * sd.g.kb - hmax, 0);
@@ -1236,24 +1218,24 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
         }
         __syncthreads();
     }
+    QuadSource<NS> g;
+    g.pos = a.pos_s;
+    g.perm = a.perm;
+    g.n = 0;
+    g.lane = lane;
+    int ovf = 0;
     if (valid) {
-        QuadSource<NS> g;
-        g.pos = a.pos_s;
-        g.perm = a.perm;
         g.q = node_pos(sd.m, i, j);
         // a corner node sees a quarter disk, an edge node a half disk: the
         // corner radius is sqrt(2) larger for the same expected count
         const bool corner = (i == 0 || i == sd.m.nx) && (j == 0 || j == sd.m.ny);
         g.Rf = ring ? (corner ? sd.Rc * 1.4142135623730951 : sd.Rc) : sd.Rf;
-        g.n = 0;
-        g.lane = lane;
         // gather the particles within the radius, round-robin over the lanes
         const double R2 = g.Rf * g.Rf;
         const int hw = ring ? (corner ? static_cast<int>(ceil(g.Rf / sd.g.bw)) : sd.hwc) : sd.hwf;
         const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
         const int bx0 = max(cbx - hw, 0), bx1 = min(cbx + hw, sd.g.nbx);
         const int by0 = max(cby - hw, 0), by1 = min(cby + hw, sd.g.nby);
-        int ovf = 0;
         int flat = 0;
         auto take = [&](double2 p, int t) {
             const double dx = p.x - g.q.x, dy = p.y - g.q.y;
@@ -1288,6 +1270,9 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
                 flat += e - s;
             }
         }
+    }
+    __syncthreads();  // every quad has gathered: the support rows replace the bin starts
+    if (valid) {
         ovf |= lane_xor<QL>(ovf, 1);
         ovf |= lane_xor<QL>(ovf, 2);
         if (!ovf && !ring) {
