@@ -303,7 +303,7 @@ int p2m_set_option(const char* name, double value);
 /* Current value of a tuning knob above, written to *value (host pointer).
  * One derived, read-only name as well:
  *   "fast_slots" candidate slots per lane of the first pass that builds
- *                launched with the current fast_radius use (8 or 10).
+ *                launched with the current fast_radius use (7, 8 or 10).
  * Returns P2M_EINVAL for an unknown name or a NULL pointer. */
 int p2m_get_option(const char* name, double* value);
 

@@ -1852,7 +1852,8 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         PhaseTimer t1(PH_BUILD_FAST, st);
         // slots per lane for the expected candidate count of an interior
         // node (pi (Rf/h)^2 over four lanes, with room for fluctuation)
-        if (fast_slots <= 8) k_build_fast<8><<<tiles, QWG, 0, st>>>(a);
+        if (fast_slots <= 7) k_build_fast<7><<<tiles, QWG, 0, st>>>(a);
+        else if (fast_slots <= 8) k_build_fast<8><<<tiles, QWG, 0, st>>>(a);
         else k_build_fast<NS_MAX><<<tiles, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());

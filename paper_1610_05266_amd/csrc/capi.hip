@@ -26,11 +26,12 @@ struct Tuning {
     int levels = 3;               // doublings before the global scan
 } g_tune;
 
-// 8 candidate slots per lane hold pi (Rf/h)^2 <= 26 expected candidates with
-// a margin for the fluctuation of the count; larger radii take 10
+// Candidate slots per lane for pi (Rf/h)^2 expected candidates, with a margin
+// for the fluctuation of the count: 7 up to 21.5 (Rf <= ~2.6h), 8 up to 26
+// (~2.9h), else 10.  Every slot is evaluated in every gift-wrapping step.
 int fast_slots() {
     const double expect = 3.14159265358979 * g_tune.fast_radius * g_tune.fast_radius;
-    return expect <= 26.0 ? 8 : NS_FAST_MAX;
+    return expect <= 21.5 ? 7 : (expect <= 26.0 ? 8 : NS_FAST_MAX);
 }
 }  // namespace
 

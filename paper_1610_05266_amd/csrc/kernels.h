@@ -68,7 +68,7 @@ struct SideWork {
     hipEvent_t fork, join;
 };
 int side_stream(int device, hipStream_t* out);
-// fast_slots: candidate slots per lane of the fast pass (8 or 10); slow, rd:
+// fast_slots: candidate slots per lane of the fast pass (7, 8 or 10); slow, rd:
 // row-slot lists (capacity n_nodes); tdiag: per-tile counts [n_tiles][4].
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
                   const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,

@@ -8,7 +8,9 @@ shape in a JSON file.
 
 Search: coordinate descent from the library defaults, one knob at a time
 over a short list of candidate values, keeping a change only when the median
-build time drops by more than a noise margin.  Every candidate build is
+build time drops by more than a noise margin; a winner other than the
+defaults is then timed again against them, interleaved, and kept only if it
+still wins by that margin.  Every candidate build is
 checked: its diagnostics must be clean and its projection of a probe field
 must equal the default build's bit for bit (the knobs may not change
 results), else the candidate is rejected.
@@ -160,6 +162,22 @@ def autotune(build: Callable[[], object], probe: Callable[[object], "object"], k
         return statistics.median(times)
 
     res = coordinate_search(measure)
+    if res.options != dict(DEFAULTS):
+        # confirm the winner against the defaults, interleaved, before trusting
+        # a margin measured once
+        t_best, t_def = [], []
+        for _ in range(3):
+            tb = measure(res.options)
+            td = measure(dict(DEFAULTS))
+            if tb is not None:
+                t_best.append(tb)
+            if td is not None:
+                t_def.append(td)
+        if t_best and t_def and statistics.median(t_best) < statistics.median(t_def) * (1.0 - NOISE):
+            res.median_ms, res.default_ms = statistics.median(t_best), statistics.median(t_def)
+        else:
+            res.options, res.median_ms = dict(DEFAULTS), res.default_ms
+        res.trials.append({"confirm_best_ms": t_best, "confirm_default_ms": t_def})
     apply_options(res.options)
     data[key] = {"options": res.options, "median_ms": res.median_ms, "default_ms": res.default_ms}
     _store(path, data)

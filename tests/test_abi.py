@@ -68,8 +68,11 @@ def test_get_option_reads_back_and_derives_slots():
     try:
         assert lib.p2m_set_option(b"fast_radius", 2.8) == 0
         assert lib.p2m_get_option(b"fast_radius", ctypes.byref(v)) == 0 and v.value == 2.8
-        # pi * 2.8^2 = 24.6 expected candidates fit 8 slots per lane, pi * 3^2 = 28.3 need 10
+        # pi * 2.8^2 = 24.6 expected candidates fit 8 slots per lane, pi * 3^2 = 28.3 need 10,
+        # pi * 2.6^2 = 21.2 fit 7
         assert lib.p2m_get_option(b"fast_slots", ctypes.byref(v)) == 0 and v.value == 8
+        assert lib.p2m_set_option(b"fast_radius", 2.6) == 0
+        assert lib.p2m_get_option(b"fast_slots", ctypes.byref(v)) == 0 and v.value == 7
         assert lib.p2m_set_option(b"fast_radius", 3.0) == 0
         assert lib.p2m_get_option(b"fast_slots", ctypes.byref(v)) == 0 and v.value == 10
         assert lib.p2m_get_option(b"levels", ctypes.byref(v)) == 0 and v.value == 3
