@@ -308,6 +308,12 @@ struct WaveSource {
     double2* lp;   // LDS stage of this wave [STAGE]
     int32_t* lt;   // sorted indices of the staged particles
     int ln;        // staged count, -1 when streaming
+    // regions of at most 2 WAVE particles (and WAVE bin rows) are held in
+    // registers instead: flat element f by lane f % WAVE, as the staged loop
+    // deals them
+    int nreg;      // particles held in registers, -1 when not
+    double2 rp0, rp1;
+    int rt0, rt1;
 
     __device__ bool global() const { return R.global; }
     __device__ double2 P(int t) const { return pos[t]; }
@@ -317,10 +323,46 @@ struct WaveSource {
     }
     __device__ void set_region(const Region& reg) {
         R = reg;
-        int total = 0;
-        for (int by = R.by0; by < R.by1; ++by) {
-            const int row = by * g.nbx;
-            total += start[row + R.bx1] - start[row + R.bx0];
+        // row lengths, one lane per row, 64 rows at a time
+        const int nrow = R.by1 - R.by0;
+        int total = 0, rs = 0, rpre = 0;  // this lane's row (first 64 rows): start, flat offset
+        for (int r0 = 0; r0 < nrow; r0 += WAVE) {
+            const int r = r0 + lane;
+            int len = 0, s0 = 0;
+            if (r < nrow) {
+                const int row = (R.by0 + r) * g.nbx;
+                s0 = start[row + R.bx0];
+                len = start[row + R.bx1] - s0;
+            }
+            int inc = len;
+#pragma unroll
+            for (int d = 1; d < WAVE; d <<= 1) {
+                const int o = __shfl_up(inc, d);
+                if (lane >= d) inc += o;
+            }
+            if (r0 == 0) {
+                rs = s0;
+                rpre = inc - len;
+            }
+            total += read_lane(inc, WAVE - 1);
+        }
+        nreg = -1;
+        if (total <= 2 * WAVE && nrow <= WAVE) {
+            // each lane finds the rows of its flat elements lane and lane + WAVE
+            int t0 = -1, t1 = -1;
+            for (int r = 0; r < nrow; ++r) {
+                const int sr = read_lane(rs, r), pr = read_lane(rpre, r);
+                const int pe = r + 1 < nrow ? read_lane(rpre, r + 1) : total;
+                if (lane >= pr && lane < pe) t0 = sr + lane - pr;
+                if (lane + WAVE >= pr && lane + WAVE < pe) t1 = sr + lane + WAVE - pr;
+            }
+            rt0 = t0;
+            rt1 = t1;
+            rp0 = pos[t0 >= 0 ? t0 : 0];
+            rp1 = pos[t1 >= 0 ? t1 : 0];
+            nreg = total;
+            ln = -1;
+            return;
         }
         ln = total <= STAGE ? total : -1;
         if (ln < 0) return;
@@ -340,6 +382,11 @@ struct WaveSource {
     }
     template <class F>
     __device__ void scan(F&& f) const {
+        if (nreg >= 0) {
+            if (lane < nreg) f(rt0, rp0);
+            if (lane + WAVE < nreg) f(rt1, rp1);
+            return;
+        }
         if (ln >= 0) {
             for (int k = lane; k < ln; k += WAVE) f(lt[k], lp[k]);
             return;
@@ -526,6 +573,31 @@ struct Support {
     }
 };
 
+
+// Support list of one node on the wave path, entry k in lane k (KMAX <= 64):
+// a search is one compare and a ballot, an insertion a select, with no LDS
+// round trip.  Same entries and order as Support.
+struct WaveSupport {
+    int e;  // this lane's entry: sorted index | membership << 28 (lane < n)
+    int n;
+    int lane;
+    __device__ int find(int t) const {
+        const unsigned long long b =
+            __ballot(lane < n && static_cast<int>(static_cast<uint32_t>(e) & IDX_MASK) == t);
+        return b ? __ffsll(static_cast<long long>(b)) - 1 : -1;
+    }
+    __device__ bool add(int t, int bit) {
+        const int f = find(t);
+        if (f >= 0) {
+            if (lane == f) e |= bit << 28;
+        } else {
+            if (n >= KMAX) return false;
+            if (lane == n) e = t | (bit << 28);
+            ++n;
+        }
+        return true;
+    }
+};
 
 // Delaunay work of one node q: the triangle T (CCW, sorted indices) of the
 // particles' Delaunay triangulation that contains q, and the rings of its
@@ -1592,7 +1664,6 @@ __device__ __forceinline__ void count_wave(const KArgs& a, const WaveCounts& wc)
 // outside the hull) their nearest particles; k_weights does the rest.
 __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     constexpr int WPB = SWG / WAVE;
-    __shared__ int32_t su[WPB * KMAX];
     __shared__ int32_t svis[WPB * KMAX];
     __shared__ double2 slp[WPB * STAGE];
     __shared__ int32_t slt[WPB * STAGE];
@@ -1625,8 +1696,9 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         c.lane = lane;
         c.lp = slp + wv * STAGE;
         c.lt = slt + wv * STAGE;
-        Support<WAVE> S;
-        S.u = su + wv * KMAX;
+        static_assert(KMAX <= WAVE, "one support entry per lane");
+        WaveSupport S;
+        S.e = 0;
         S.n = 0;
         S.lane = lane;
         uint32_t type = ring ? NT_RING : NT_INTERIOR;
@@ -1658,10 +1730,10 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             if (lt0 < 0 || lt1 < 0 || lt2 < 0) {
                 type = NT_FAILED;
             } else {
-                for (int k = lane; k < S.n; k += WAVE) {
-                    const uint32_t e = static_cast<uint32_t>(S.u[k]);
-                    a.out.idx[k * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
-                    a.out.mem[k * nn + slot] = static_cast<uint8_t>(e >> 28);
+                if (lane < S.n) {
+                    const uint32_t e = static_cast<uint32_t>(S.e);
+                    a.out.idx[lane * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
+                    a.out.mem[lane * nn + slot] = static_cast<uint8_t>(e >> 28);
                 }
                 if (lane == 0) a.out.meta[slot] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
             }
