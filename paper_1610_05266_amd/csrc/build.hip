@@ -1302,16 +1302,17 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
         // corner radius is sqrt(2) larger for the same expected count
         const bool corner = (i == 0 || i == sd.m.nx) && (j == 0 || j == sd.m.ny);
         g.Rf = ring ? (corner ? sd.Rc * 1.4142135623730951 : sd.Rc) : sd.Rf;
-        // gather the particles within the radius, round-robin over the lanes
+        // gather the particles within the radius.  The quad walks each row
+        // segment of the window four particles at a time; the k-th particle
+        // accepted (in the order of the walk) goes to lane k % 4, so that no
+        // lane holds more than ceil(n / 4) of the node's n candidates.
         const double R2 = g.Rf * g.Rf;
         const int hw = ring ? (corner ? static_cast<int>(ceil(g.Rf / sd.g.bw)) : sd.hwc) : sd.hwf;
         const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
         const int bx0 = max(cbx - hw, 0), bx1 = min(cbx + hw, sd.g.nbx);
         const int by0 = max(cby - hw, 0), by1 = min(cby + hw, sd.g.nby);
-        int flat = 0;
-        auto take = [&](double2 p, int t) {
-            const double dx = p.x - g.q.x, dy = p.y - g.q.y;
-            if (dx * dx + dy * dy > R2) return;
+        int acc = 0;  // particles accepted so far (the same in the four lanes)
+        auto insert = [&](double2 p, int t) {
             if (g.n >= NS) {
                 ovf = 1;
                 return;
@@ -1325,21 +1326,44 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
                 }
             ++g.n;
         };
+        // particles s .. e - 1 of one row segment; P(t) its position, id(t)
+        // the sorted index
+        auto segment = [&](int s, int e, auto&& P, auto&& id) {
+            for (int t0 = s; t0 < e; t0 += QL) {
+                const int t = t0 + lane;
+                bool in = false;
+                if (t < e) {
+                    const double2 p = P(t);
+                    const double dx = p.x - g.q.x, dy = p.y - g.q.y;
+                    in = dx * dx + dy * dy <= R2;
+                }
+                int m = in ? 1 << lane : 0;
+                m |= lane_xor<QL>(m, 1);
+                m |= lane_xor<QL>(m, 2);
+                const int c = __popc(m);
+                const int k = (lane - acc) & (QL - 1);
+                if (k < c) {
+                    int mm = m;  // the k-th set bit of m
+                    for (int r = 0; r < k; ++r) mm &= mm - 1;
+                    const int tt = t0 + __ffs(mm) - 1;
+                    insert(P(tt), id(tt));
+                }
+                acc += c;
+            }
+        };
         if (staged) {
             // the same particles in the same order as the global walk below
             for (int by = by0; by < by1; ++by) {
                 const int* rs = tst + (by - rby0) * (TDIM + 1);
                 const int base = trb[by - rby0] - rs[0];
-                const int s = base + rs[bx0 - rbx0], e = base + rs[bx1 - rbx0];
-                for (int t = s + ((lane - flat) & (QL - 1)); t < e; t += QL) take(tpos[t], tsi[t]);
-                flat += e - s;
+                segment(base + rs[bx0 - rbx0], base + rs[bx1 - rbx0], [&](int t) { return tpos[t]; },
+                        [&](int t) { return tsi[t]; });
             }
         } else {
             for (int by = by0; by < by1; ++by) {
                 const int row = by * sd.g.nbx;
-                const int s = start[row + bx0], e = start[row + bx1];
-                for (int t = s + ((lane - flat) & (QL - 1)); t < e; t += QL) take(a.pos_s[t], t);
-                flat += e - s;
+                segment(start[row + bx0], start[row + bx1], [&](int t) { return a.pos_s[t]; },
+                        [&](int t) { return t; });
             }
         }
     }
