@@ -1588,21 +1588,32 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
                 for (int t = 0; t < 6; ++t) y[t] += d[t];
             }
         }
-    } else if (clos && lane == 0) {
+    } else if (clos) {
         // minimum-norm quadratic moment conditions over the nearest
-        // particles, centred at their centroid and scaled by their RMS radius
-        each([&](int, uint32_t, double2 p, int32_t) {
-            cx += p.x;
-            cy += p.y;
+        // particles, centred at their centroid and scaled by their RMS radius.
+        // The four lanes share every pass over the entries (lane l takes
+        // entries l, l + 4, ...; quad sums), so all of them hold the solution.
+        auto each4 = [&](auto&& f) {
+            const int ns = min(n, SK);
+            for (int k = lane; k < ns; k += QL) f(sp[qi * SKP + k]);
+            for (int k = SK + lane; k < n; k += QL) f(P(k));
+        };
+        double sx = 0.0, sy = 0.0;
+        each4([&](double2 p) {
+            sx += p.x;
+            sy += p.y;
         });
-        cx /= n;
-        cy /= n;
+        cx = quad_sum(sx) / n;
+        cy = quad_sum(sy) / n;
         double r2 = 0.0;
-        each([&](int, uint32_t, double2 p, int32_t) { r2 += (p.x - cx) * (p.x - cx) + (p.y - cy) * (p.y - cy); });
+        each4([&](double2 p) { r2 += (p.x - cx) * (p.x - cx) + (p.y - cy) * (p.y - cy); });
+        r2 = quad_sum(r2);
         sc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
         Moments mo;
         mo.zero();
-        each([&](int, uint32_t, double2 p, int32_t) { mo.add((p.x - cx) * sc, (p.y - cy) * sc); });
+        each4([&](double2 p) { mo.add((p.x - cx) * sc, (p.y - cy) * sc); });
+#pragma unroll
+        for (int t = 0; t < 15; ++t) mo.m[t] = quad_sum(mo.m[t]);
         double b[6];
         monos((q.x - cx) * sc, (q.y - cy) * sc, b);
         double L[6][6];
@@ -1611,7 +1622,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
         if (ok) {
             chol6_solve(L, b, y);
             double r[6] = {0, 0, 0, 0, 0, 0};
-            each([&](int, uint32_t, double2 p, int32_t) {
+            each4([&](double2 p) {
                 double pm[6];
                 monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
                 const double A = dot6(pm, y);
@@ -1619,7 +1630,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
                 for (int t = 0; t < 6; ++t) r[t] += A * pm[t];
             });
 #pragma unroll
-            for (int t = 0; t < 6; ++t) r[t] = b[t] - r[t];
+            for (int t = 0; t < 6; ++t) r[t] = b[t] - quad_sum(r[t]);
             double d[6];
             chol6_solve(L, r, d);
 #pragma unroll
@@ -1642,7 +1653,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
             double c = 0.0;
             if (pend && lane == 3) {
                 c = (k == lt[0] ? phi[0] : 0.0) + (k == lt[1] ? phi[1] : 0.0) + (k == lt[2] ? phi[2] : 0.0);
-            } else if (clos ? lane == 0 : (lane < 3 && ((e >> 28) & mask))) {
+            } else if (clos ? lane == (k & (QL - 1)) : (lane < 3 && ((e >> 28) & mask))) {
                 double pm[6];
                 monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
                 c = coef * dot6(pm, y);
