@@ -604,14 +604,15 @@ struct WaveSupport {
 // three vertices (into S, bit k for the ring of T[k]).  Three phases, each a
 // loop around one gift-wrapping step:
 //   wedge   rotate about the nearest particle n0 (from its nearest
-//           neighbour a0, a Delaunay neighbour) to the wedge holding q;
-//           clockwise as well for a hull vertex (only a global source sees one);
+//           neighbour a0, a Delaunay neighbour, on the side of q) to the
+//           wedge holding q; the other way as well for a hull vertex (only a
+//           global source sees one);
 //   walk    visibility walk across the edge facing q;
 //   rings   rotate about T[k] from the known triangle T back to it (clockwise
 //           for the rest of an open fan of a hull vertex).
 // Work is reused: when q lies in a triangle at n0, the ring of n0 only
-// rotates until it meets the neighbours the wedge search visited (kept in
-// `vis`); the first step of rings 1 and 2 and the last step of ring 2 are
+// rotates over the part the wedge search did not visit (its apexes are kept
+// in `vis`); the first step of rings 1 and 2 and the last step of ring 2 are
 // triangles across an edge of T that an earlier ring already found.
 // Returns R_OK, R_OUTSIDE (q outside the convex hull), R_MORE (not
 // certified by this source), R_FAIL or R_CAP.
@@ -634,34 +635,44 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis) 
     if (!g.certify(v.x, v.y, sqrt(e2))) return R_MORE;
     double cx, cy, rr;
 
-    // ---- wedge: T = (n0, cur, next) with q between cur and next
+    // ---- wedge: rotate about n0 from a0 towards q (counter-clockwise when
+    // q lies left of or on the ray n0 -> a0, else clockwise) to the triangle
+    // T = (n0, T1, T2) whose cone holds q: q left of or on n0 -> T1 and
+    // strictly right of n0 -> T2.  The cones are half-open, so either
+    // direction ends at the same triangle.  `vis` keeps a0 and the apexes
+    // passed after it.
     double2 P0 = v, P1 = v, P2 = v;
     auto psel = [&](int i) { return i == 0 ? P0 : (i == 1 ? P1 : P2); };
+    const double dir = orient(v, pa0, q) >= 0.0 ? 1.0 : -1.0;
     int cur = a0;
     double2 pcur = pa0;
     int nvis = 1;
     vis[0] = a0;
     bool found = false, open = false;
     for (int step = 0; step < 2 * KMAX; ++step) {
-        const Key k = g.wrap(n0, v, cur, pcur, 1.0);
+        const Key k = g.wrap(n0, v, cur, pcur, dir);
         if (k.t == -2) return R_MORE;
         if (k.t < 0) {
             if (!g.global()) return R_MORE;
             open = true;
             break;
         }
-        circumcircle(k, v, pcur, 1.0, cx, cy, rr);
+        circumcircle(k, v, pcur, dir, cx, cy, rr);
         if (!g.certify(cx, cy, rr)) return R_MORE;
         const double2 pk = make_double2(k.bx, k.by);
-        if (d2 == 0.0 || (orient(v, pcur, q) >= 0.0 && orient(v, pk, q) < 0.0)) {
-            T0 = n0; T1 = cur; T2 = k.t;
-            P0 = v; P1 = pcur; P2 = pk;
+        // the triangle's two rays in counter-clockwise order
+        const double2 plo = dir > 0.0 ? pcur : pk, phi = dir > 0.0 ? pk : pcur;
+        if (d2 == 0.0 || (orient(v, plo, q) >= 0.0 && orient(v, phi, q) < 0.0)) {
+            T0 = n0;
+            T1 = dir > 0.0 ? cur : k.t;
+            T2 = dir > 0.0 ? k.t : cur;
+            P0 = v; P1 = plo; P2 = phi;
             found = true;
             break;
         }
         // a full turn (or a step past a0 through co-circular ties) without
         // finding the wedge: numerically inconsistent
-        if (k.t == a0 || (orient(v, pcur, pa0) > 0.0 && orient(v, pa0, pk) > 0.0)) return R_FAIL;
+        if (k.t == a0 || (orient(v, plo, pa0) > 0.0 && orient(v, pa0, phi) > 0.0)) return R_FAIL;
         if (nvis >= KMAX) return R_CAP;
         vis[nvis++] = k.t;
         cur = k.t;
@@ -669,18 +680,21 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis) 
     }
     if (!found && !open) return R_FAIL;
     if (!found) {
-        // n0 is a hull vertex: rotate clockwise from a0 over the rest of its fan
+        // n0 is a hull vertex: rotate the other way from a0 over the rest of its fan
         nvis = 0;
         cur = a0;
         pcur = pa0;
         for (int step = 0; step < 2 * KMAX; ++step) {
-            const Key k = g.wrap(n0, v, cur, pcur, -1.0);
+            const Key k = g.wrap(n0, v, cur, pcur, -dir);
             if (k.t == -2) return R_MORE;
             if (k.t < 0) return d2 == 0.0 ? R_FAIL : R_OUTSIDE;  // q outside the open fan's cone
             const double2 pk = make_double2(k.bx, k.by);
-            if (d2 == 0.0 || (orient(v, pk, q) >= 0.0 && orient(v, pcur, q) < 0.0)) {
-                T0 = n0; T1 = k.t; T2 = cur;
-                P0 = v; P1 = pk; P2 = pcur;
+            const double2 plo = dir > 0.0 ? pk : pcur, phi = dir > 0.0 ? pcur : pk;
+            if (d2 == 0.0 || (orient(v, plo, q) >= 0.0 && orient(v, phi, q) < 0.0)) {
+                T0 = n0;
+                T1 = dir > 0.0 ? k.t : cur;
+                T2 = dir > 0.0 ? cur : k.t;
+                P0 = v; P1 = plo; P2 = phi;
                 found = true;
                 break;
             }
@@ -715,7 +729,11 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis) 
     }
 
     // ---- the three rings
-    bool reuse0 = !walked && nvis > 0 && T0 == n0 && T1 == vis[nvis - 1];
+    // A counter-clockwise wedge search passed the ring of n0 from a0 to T1:
+    // ring 0 rotates from T2 until it meets a0.  A clockwise one passed it
+    // from T2 back to a0, which continues ring 0 counter-clockwise from T2.
+    const bool kept = !walked && T0 == n0 && nvis > 0;
+    bool reuse0 = kept && dir > 0.0 && T1 == vis[nvis - 1];
     bool chain = true;   // no open fan so far: the shared-triangle shortcuts hold
     bool cwise = false;  // rotating clockwise through the rest of an open fan
     int x0 = -1;         // first apex of ring 0 (across edge T0-T2)
@@ -724,6 +742,14 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis) 
     if (!S.add(T1, 1) || !S.add(T2, 1)) return R_CAP;
     cur = T2;
     pcur = P2;
+    if (kept && dir < 0.0 && nvis >= 2 && T2 == vis[nvis - 1]) {
+        for (int s = nvis - 2; s >= 0; --s)
+            if (!S.add(vis[s], 1)) return R_CAP;
+        x0 = vis[nvis - 2];
+        nrot = nvis - 1;
+        cur = a0;
+        pcur = pa0;
+    }
     for (int it = 0; it < 8 * KMAX; ++it) {
         const int f = rk == 2 ? 0 : rk + 1;
         const int first = tsel(f);
