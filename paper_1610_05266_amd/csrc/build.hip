@@ -239,6 +239,9 @@ __device__ __forceinline__ void wave_best_key(Key& best, Uid uid, int lane, int&
         return;
     }
     reduce_key<WAVE>(best, uid, lane, nd);
+    // every lane holds the answer; read as a scalar it is visibly
+    // wave-uniform, so the branches that depend on it stay scalar
+    best = read_key(best, 0);
 }
 
 // Wave argmin of squared distances, ties by user id.
@@ -249,6 +252,7 @@ __device__ __forceinline__ void wave_nearest(double& d2, int& t, double2& p, con
     if (tied == 0) {
         t = -1;
         d2 = INFINITY;
+        p = make_double2(0.0, 0.0);
         return;
     }
     if (__popcll(tied) == 1) {
@@ -259,6 +263,9 @@ __device__ __forceinline__ void wave_nearest(double& d2, int& t, double2& p, con
         return;
     }
     reduce_nearest<WAVE>(d2, t, p, perm);
+    t = read_lane(t, 0);
+    d2 = read_lane(d2, 0);
+    p = make_double2(read_lane(p.x, 0), read_lane(p.y, 0));
 }
 
 template <int W>
@@ -1221,8 +1228,12 @@ __device__ void quad_closure(const KArgs& a, int64_t slot, double2 q, int n, int
 constexpr int TCAP = 1792;  // particles of a tile's bin region staged in LDS
 constexpr int TDIM = 48;    // bin rows / columns of that region (at most)
 
+// Seven slots per lane fit 168 registers, so three waves per SIMD (three
+// blocks per CU, within the LDS): the extra wave hides the latency of the
+// dependent FP64 chains of the gift-wrapping steps.
 template <int NS>
-__global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
+__global__ void __launch_bounds__(QWG) __attribute__((amdgpu_waves_per_eu(NS == 7 ? 3 : 1, 8)))
+k_build_fast(KArgs a) {
     // the tile's bin region (its nodes' search windows): bin starts, row
     // bases and the particles, copied once with coalesced row reads.  The
     // bin starts are needed only until every quad has gathered; the per-quad
@@ -1243,7 +1254,7 @@ __global__ void __launch_bounds__(QWG) k_build_fast(KArgs a) {
     tile_xy(sd, static_cast<int>(blockIdx.x - sd.t0), tx, ty);
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
-    const int64_t slot = static_cast<int64_t>(blockIdx.x) * TILE_N + qi;
+    const int slot = static_cast<int>(blockIdx.x) * TILE_N + qi;  // < 2^31, checked on the host
     const int64_t nn = a.n_slots;
     const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
     const int32_t* start = a.start + sd.b0;
@@ -1736,7 +1747,10 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     // weights kernel: they take issue priority over its waves.
     __builtin_amdgcn_s_setprio(3);
     const int lane = threadIdx.x & (WAVE - 1);
-    const int wv = threadIdx.x / WAVE;
+    // the wave's index, read as a scalar: every value derived from it (the
+    // node, its position, its search) is then visibly wave-uniform and its
+    // branches stay scalar
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
     const int count = static_cast<int>(a.diag[D_SLOWCNT]);
     const int64_t nn = a.n_slots;
     for (int li = blockIdx.x * WPB + wv; li < count; li += gridDim.x * WPB) {
