@@ -290,7 +290,7 @@ int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, 
  * do not depend on them).  Not thread-safe with concurrent builds.
  *   "bin_scale"  bin width ~ bin_scale * h        (0.25 .. 8,  default 1)
  *   "fast_radius" candidate radius / h of the
- *                register-resident first pass     (1.5 .. 8,   default 2.8)
+ *                register-resident first pass     (1.5 .. 8,   default 2.6)
  *   "closure_radius" candidate radius / h of the
  *                first pass for boundary-ring nodes (1.5 .. 8,   default 4)
  *   "region_h"   first search half-width / h of

@@ -21,7 +21,7 @@ constexpr int NS_FAST_MAX = 10;  // candidate slots per lane of the fast pass, a
 struct Tuning {
     double bin_scale = 1.0;       // bin width ~ bin_scale * h
     double region_h = 4.0;        // slow path: first search half-width, in units of h
-    double fast_radius = 2.8;     // fast path: candidate radius, in units of h
+    double fast_radius = 2.6;     // fast path: candidate radius, in units of h
     double closure_radius = 4.0;  // fast path, boundary ring: candidate radius / h
     int levels = 3;               // doublings before the global scan
 } g_tune;

@@ -25,7 +25,7 @@ from typing import Callable, Dict, List, Optional, Sequence
 
 DEFAULTS: Dict[str, float] = {
     "bin_scale": 1.0,
-    "fast_radius": 2.8,
+    "fast_radius": 2.6,
     "closure_radius": 4.0,
     "region_h": 4.0,
     "levels": 3.0,

@@ -80,7 +80,7 @@ def test_get_option_reads_back_and_derives_slots():
         assert lib.p2m_get_option(b"levels", None) == -1
         assert b"NULL" in lib.p2m_last_error()
     finally:
-        lib.p2m_set_option(b"fast_radius", 2.8)
+        lib.p2m_set_option(b"fast_radius", 2.6)
 
 
 def test_batch_argument_validation_without_device():

@@ -120,13 +120,14 @@ def test_cluster_and_void_cloud():
     assert_close(got, W @ c.vals, TOL64, "cluster P2M")
 
 
-@pytest.mark.parametrize("fast_radius,region_h,min_slow_share", [(1.5, 1.0, 0.5), (2.6, 4.0, 0.0)])
+@pytest.mark.parametrize("fast_radius,region_h,min_slow_share",
+                         [(1.5, 1.0, 0.5), (2.8, 4.0, 0.0), (3.0, 6.0, 0.0)])
 def test_c1_build_options_change_no_bit(c1, fast_radius, region_h, min_slow_share):
     """The build options change only which pass certifies a node: the rows,
-    weights and triangles equal the default build's bit for bit.  With the
-    smallest first-pass radius most interior nodes take the exact wave path,
-    and a first region of one h makes it double its regions; 2.6h runs the
-    fast pass with 7 candidate slots per lane."""
+    weights and triangles equal the default build's (2.6h, 7 candidate slots
+    per lane) bit for bit.  With the smallest first-pass radius most interior
+    nodes take the exact wave path, and a first region of one h makes it
+    double its regions; 2.8h and 3h run the fast pass with 8 and 10 slots."""
     c, orc, W, info = c1
     w0, pos = _build(c)
     ref = w0.export()
