@@ -53,7 +53,7 @@ namespace {
 
 constexpr double EPS = DBL_EPSILON;
 constexpr int WAVE = 64;
-constexpr int SWG = 256;       // slow kernel: four waves, one node per wave
+constexpr int SWG = 192;       // slow kernel: three waves per node, one per ring
 constexpr int QL = 4;          // lanes per node in the quad kernels
 constexpr int NS_MAX = 10;     // candidate slots per lane (fast kernel), at most
 constexpr int QWG = 256;       // quad kernels: 64 nodes per block
@@ -311,6 +311,7 @@ struct WaveSource {
     Grid g;
     Region R;
     int neardeg;
+    int ring_mark;
     int lane;
     double2* lp;   // LDS stage of this wave [STAGE]
     int32_t* lt;   // sorted indices of the staged particles
@@ -323,6 +324,8 @@ struct WaveSource {
     int rt0, rt1;
 
     __device__ bool global() const { return R.global; }
+    // near-tie count when the rings phase begins
+    __device__ void mark_rings() { ring_mark = neardeg; }
     __device__ double2 P(int t) const { return pos[t]; }
     __device__ bool certify(double cx, double cy, double r) const {
         r *= 1.0 + 1e-9;
@@ -479,6 +482,7 @@ struct QuadSource {
         return best;
     }
     __device__ double2 P(int t) const { return pos[t]; }
+    __device__ void mark_rings() {}
     // A branch-free loop that compares bisector keys against a static
     // forward error bound valid for every candidate (all candidates, and v
     // and a, lie within Rf of q, so |A|, |B| <= 2 Rf and both error
@@ -623,8 +627,13 @@ struct WaveSupport {
 // triangles across an edge of T that an earlier ring already found.
 // Returns R_OK, R_OUTSIDE (q outside the convex hull), R_MORE (not
 // certified by this source), R_FAIL or R_CAP.
+// With `only` in 0..2 the rings phase does just that ring: several waves
+// can then run the three rings of one node side by side; the lists they
+// return, merged in ring order, are this routine's list in the same order
+// (ring k > 0 starting at T[k-1] meets first the apex that the previous
+// ring saw last before T[k], where the chained version starts).
 template <class G, class S_>
-__device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis) {
+__device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, int only = -1) {
     // the current triangle as scalars, selected by value (an array indexed
     // at run time would live in scratch memory)
     int T0 = -1, T1 = -1, T2 = -1;
@@ -739,16 +748,20 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis) 
     // A counter-clockwise wedge search passed the ring of n0 from a0 to T1:
     // ring 0 rotates from T2 until it meets a0.  A clockwise one passed it
     // from T2 back to a0, which continues ring 0 counter-clockwise from T2.
-    const bool kept = !walked && T0 == n0 && nvis > 0;
+    g.mark_rings();
+    int rk = only < 0 ? 0 : only;
+    const bool kept = !walked && T0 == n0 && nvis > 0 && rk == 0;
     bool reuse0 = kept && dir > 0.0 && T1 == vis[nvis - 1];
-    bool chain = true;   // no open fan so far: the shared-triangle shortcuts hold
-    bool cwise = false;  // rotating clockwise through the rest of an open fan
-    int x0 = -1;         // first apex of ring 0 (across edge T0-T2)
-    int nrot = 0;        // apexes found by rotation in the current ring
-    int rk = 0;
-    if (!S.add(T1, 1) || !S.add(T2, 1)) return R_CAP;
-    cur = T2;
-    pcur = P2;
+    bool chain = only < 0;  // no open fan so far: the shared-triangle shortcuts hold
+    bool cwise = false;     // rotating clockwise through the rest of an open fan
+    int x0 = -1;            // first apex of ring 0 (across edge T0-T2)
+    int nrot = 0;           // apexes found by rotation in the current ring
+    {
+        const int f1 = rk == 2 ? 0 : rk + 1, f2 = rk == 0 ? 2 : rk - 1;
+        if (!S.add(tsel(f1), 1 << rk) || !S.add(tsel(f2), 1 << rk)) return R_CAP;
+        cur = tsel(f2);
+        pcur = psel(f2);
+    }
     if (kept && dir < 0.0 && nvis >= 2 && T2 == vis[nvis - 1]) {
         for (int s = nvis - 2; s >= 0; --s)
             if (!S.add(vis[s], 1)) return R_CAP;
@@ -807,7 +820,7 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis) 
             }
         }
         if (closed) {
-            if (++rk == 3) {
+            if (++rk == 3 || only >= 0) {
                 Tout[0] = T0;
                 Tout[1] = T1;
                 Tout[2] = T2;
@@ -1736,13 +1749,18 @@ __device__ __forceinline__ void count_wave(const KArgs& a, const WaveCounts& wc)
 // outside the hull) their nearest particles; k_weights does the rest.
 __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     constexpr int WPB = SWG / WAVE;
+    static_assert(WPB == 3, "one wave per ring");
     __shared__ int32_t svis[WPB * KMAX];
     __shared__ double2 slp[WPB * STAGE];
     __shared__ int32_t slt[WPB * STAGE];
-    // the weights of each finished row, by the first quad of its wave
-    __shared__ double2 wsp[QPB * SKP];
-    __shared__ uint32_t wse[QPB * SKP];
-    __shared__ int32_t wsu[QPB * SKP];
+    // each ring's list (entry | ring bit << 28), its status, length and
+    // near-tie count, for the ring-0 wave to merge
+    __shared__ int32_t sring[WPB][KMAX];
+    __shared__ int sinfo[WPB][3];
+    // the weights of the finished row, by the first quad of the ring-0 wave
+    __shared__ double2 wsp[(WAVE / QL) * SKP];
+    __shared__ uint32_t wse[(WAVE / QL) * SKP];
+    __shared__ int32_t wsu[(WAVE / QL) * SKP];
     // These few waves are a serial latency chain that runs beside the
     // weights kernel: they take issue priority over its waves.
     __builtin_amdgcn_s_setprio(3);
@@ -1753,7 +1771,9 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
     const int count = static_cast<int>(a.diag[D_SLOWCNT]);
     const int64_t nn = a.n_slots;
-    for (int li = blockIdx.x * WPB + wv; li < count; li += gridDim.x * WPB) {
+    for (int li = blockIdx.x; li < count; li += gridDim.x) {
+        // the previous node's lists have been read
+        __syncthreads();
         const int64_t slot = a.slow[li];
         const SetDesc sd = slot_set(a, slot);
         const int big = max(sd.g.nbx, sd.g.nby) + 1;
@@ -1768,6 +1788,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         c.start = a.start + sd.b0;
         c.g = sd.g;
         c.neardeg = 0;
+        c.ring_mark = 0;
         c.lane = lane;
         c.lp = slp + wv * STAGE;
         c.lt = slt + wv * STAGE;
@@ -1780,18 +1801,50 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         uint32_t flags = MF_ESCALATED;
         int T[3] = {0, 0, 0};
         int st = R_FAIL;
+        int ndeg = 0;  // near ties of the node, over its three waves
         if (!ring) {
+            // wave k finds the triangle and then the ring of its vertex k
             for (int level = 0;; ++level) {
                 const int hw = level < a.levels ? (sd.hw0 << level) : big;
                 c.set_region(make_region(sd.g, cbx, cby, hw));
                 S.n = 0;
-                st = delaunay_node(c, q, T, S, svis + wv * KMAX);
+                const int sk = delaunay_node(c, q, T, S, svis + wv * KMAX, wv);
+                if (lane < S.n) sring[wv][lane] = S.e;
+                if (lane == 0) {
+                    sinfo[wv][0] = sk;
+                    sinfo[wv][1] = S.n;
+                    // the wedge and walk counted once, by the ring-0 wave
+                    sinfo[wv][2] = wv == 0 ? c.neardeg : c.neardeg - c.ring_mark;
+                }
+                __syncthreads();
+                // the chained routine returns the first failure in ring order
+                st = R_OK;
+                for (int w = 0; w < WPB; ++w)
+                    if (st == R_OK) st = sinfo[w][0];
+                ndeg = sinfo[0][2] + sinfo[1][2] + sinfo[2][2];
                 if (st != R_MORE) break;
+                __syncthreads();  // every wave has read this level's results
                 if (c.R.global) {
                     st = R_FAIL;
                     break;
                 }
             }
+        }
+        // the rest of the node is the ring-0 wave's
+        if (wv != 0) continue;
+        if (st == R_OK) {
+            // ring 0's list, then the new entries of rings 1 and 2 in their
+            // order (ring bits of shared entries OR-ed): the chained order
+            for (int w = 1; w < WPB && st == R_OK; ++w)
+                for (int k = 0; k < sinfo[w][1]; ++k) {
+                    const uint32_t e = static_cast<uint32_t>(sring[w][k]);
+                    if (!S.add(static_cast<int>(e & IDX_MASK), static_cast<int>(e >> 28))) {
+                        st = R_CAP;
+                        break;
+                    }
+                }
+        }
+        if (!ring) {
             if (c.R.global) flags |= MF_GLOBAL;
             if (st == R_OUTSIDE) type = NT_OUTSIDE;
             else if (st == R_CAP) {
@@ -1799,6 +1852,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
                 if (lane == 0) atomicAdd(&a.diag[D_CAP], 1ull);
             } else if (st != R_OK) type = NT_FAILED;
         }
+        c.neardeg = ndeg;
         if (c.neardeg) flags |= MF_NEARDEG;
         if (type == NT_INTERIOR) {
             const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
@@ -2010,10 +2064,10 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     P2M_HIP(hipStreamWaitEvent(side.stream, side.fork, 0));
     {
         PhaseTimer t2(PH_BUILD_SLOW, side.stream);
-        // one wave per slow node (few: escalated, undecided); the grids loop
-        // over the actual list
+        // one block per slow node (few: escalated, undecided); the grid
+        // loops over the actual list
         const int64_t expect = n_nodes / 256 + 64 * static_cast<int64_t>(S);
-        const int gs = static_cast<int>(std::min<int64_t>((expect + SWG / WAVE - 1) / (SWG / WAVE), 4096));
+        const int gs = static_cast<int>(std::min<int64_t>(expect, 4096));
         k_slow_geom<<<gs, SWG, 0, side.stream>>>(a);
     }
     P2M_HIP(hipGetLastError());
