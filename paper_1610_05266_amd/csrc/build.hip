@@ -1516,9 +1516,14 @@ struct WaveCounts {
 };
 enum { WC_INTERIOR, WC_CLOSURE, WC_OUTSIDE, WC_SUPMAX };
 
+// QS quads may share one row (quad `sub` of them): each computes the whole
+// row's systems, identically, and they split the final pass over the support
+// entries (quad sub takes entries sub, sub + QS, ...), whose weights do not
+// depend on one another, so the row is the same bit for bit for any QS.
+template <int QS = 1>
 __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc& sd, int i, int j, bool valid,
                                                    int64_t slot, int lane, int qi, double2* sp, uint32_t* se,
-                                                   int32_t* su, bool escalated_rows) {
+                                                   int32_t* su, bool escalated_rows, int sub = 0) {
     const int64_t nn = a.n_slots;
     const uint32_t meta = valid ? a.out.meta[slot] : 0u;
     const bool mine = valid && (((meta_flags(meta) & MF_ESCALATED) != 0) == escalated_rows);
@@ -1692,14 +1697,23 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
     ok = min(ok, lane_xor<QL>(ok, 2));
     if ((pend || clos) && !ok) {
         // rank-deficient: the row stays pending for k_weights_rd
-        if (lane == 0) {
+        if (lane == 0 && sub == 0) {
             const int lpos = static_cast<int>(atomicAdd(&a.diag[D_RDCNT], 1ull));
             a.rd[lpos] = static_cast<int32_t>(slot);
         }
     } else if (pend || clos) {
         // w_k = phi-part (lane 3) + sum over the edges (lanes 0..2) of
-        // 2 phi_nu phi_sigma A_{e,k}; closure: lane 0 alone
-        each([&](int k, uint32_t e, double2 p, int32_t u) {
+        // 2 phi_nu phi_sigma A_{e,k}; closure: lane k mod 4 alone
+        auto each_sub = [&](auto&& f) {
+            const int ns = min(n, SK);
+            for (int k = sub; k < ns; k += QS) f(k, se[qi * SKP + k], sp[qi * SKP + k], su[qi * SKP + k]);
+            for (int k = SK + sub; k < n; k += QS) {
+                const uint32_t e = static_cast<uint32_t>(a.out.idx[k * nn + slot]) |
+                                   (static_cast<uint32_t>(a.out.mem[k * nn + slot]) << 28);
+                f(k, e, a.pos_s[e & IDX_MASK], a.perm[e & IDX_MASK]);
+            }
+        };
+        each_sub([&](int k, uint32_t e, double2 p, int32_t u) {
             double c = 0.0;
             if (pend && lane == 3) {
                 c = (k == lt[0] ? phi[0] : 0.0) + (k == lt[1] ? phi[1] : 0.0) + (k == lt[2] ? phi[2] : 0.0);
@@ -1716,14 +1730,14 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
                 a.out.mem[k * nn + slot] = clos ? 0 : static_cast<uint8_t>(e >> 28);
             }
         });
-        if (lane == 0) {
+        if (lane == 0 && sub == 0) {
             const uint32_t ft = pend ? NT_INTERIOR : (type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING);
             a.out.meta[slot] = pend ? meta_pack(ft, n, lt[0], lt[1], lt[2], meta_flags(meta))
                                     : meta_pack(ft, n, 0, 0, 0, meta_flags(meta));
         }
     }
-    // diagnostics: one count per quad (lane 0), wave-uniform totals
-    const bool q0 = lane == 0;
+    // diagnostics: one count per row (lane 0 of quad 0), wave-uniform totals
+    const bool q0 = lane == 0 && sub == 0;
     WaveCounts wc;
     wc.c[WC_INTERIOR] = __popcll(__ballot(q0 && pend));
     wc.c[WC_CLOSURE] = __popcll(__ballot(q0 && clos));
@@ -1934,8 +1948,10 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-        count_wave(a, weights_node(a, sd, i, j, lane < QL, slot, lane & (QL - 1), static_cast<int>(threadIdx.x) / QL,
-                                   wsp, wse, wsu, true));
+        // every quad of the wave computes the row's systems; they share
+        // its final pass
+        count_wave(a, weights_node<WAVE / QL>(a, sd, i, j, true, slot, lane & (QL - 1), lane / QL, wsp, wse, wsu,
+                                              true, lane / QL));
     }
 }
 
