@@ -150,8 +150,8 @@ __device__ __forceinline__ void reduce_key(Key& best, Uid uid, int lane, int& nd
     }
 }
 
-template <int W>
-__device__ __forceinline__ void reduce_nearest(double& d2, int& t, double2& p, const int32_t* perm) {
+template <int W, class Uid>
+__device__ __forceinline__ void reduce_nearest(double& d2, int& t, double2& p, Uid uid) {
 #pragma unroll
     for (int m = 1; m < W; m <<= 1) {
         const double od = lane_xor<W>(d2, m);
@@ -160,7 +160,7 @@ __device__ __forceinline__ void reduce_nearest(double& d2, int& t, double2& p, c
         bool take = false;
         if (ot >= 0 && ot != t) {
             if (t < 0 || od < d2) take = true;
-            else if (od == d2) take = perm[ot] < perm[t];
+            else if (od == d2) take = uid(ot) < uid(t);
         }
         if (take) {
             d2 = od;
@@ -262,7 +262,7 @@ __device__ __forceinline__ void wave_nearest(double& d2, int& t, double2& p, con
         p = make_double2(read_lane(p.x, l), read_lane(p.y, l));
         return;
     }
-    reduce_nearest<WAVE>(d2, t, p, perm);
+    reduce_nearest<WAVE>(d2, t, p, [&](int u) { return perm[u]; });
     t = read_lane(t, 0);
     d2 = read_lane(d2, 0);
     p = make_double2(read_lane(p.x, 0), read_lane(p.y, 0));
@@ -443,19 +443,36 @@ struct WaveSource {
 
 // -------------------------------------------------- fast candidate source
 // Four lanes of a quad hold the node's candidates (particles within Rf of
-// the node q) in registers; every query is a lane-local loop plus a
-// two-step reduction, after which all four lanes agree on the answer.
+// the node q); every query is a lane-local loop plus a two-step reduction,
+// after which all four lanes agree on the answer.  The candidates are
+// 16-bit indices into the tile's region staged in LDS (two per register),
+// positions are read from there: the registers they free let four blocks
+// share a CU.  Indices t of this source are staged indices; sorted(t) is the
+// particle's index in the sorted arrays.
 template <int NS>
 struct QuadSource {
-    const double2* __restrict__ pos;
     const int32_t* __restrict__ perm;
+    const double2* lpos;  // the staged positions
+    const int32_t* lrb;   // staged index of the first particle of each staged row (nrow + 1)
+    const int32_t* lrs;   // sorted index of the first particle of each staged row
+    int nrow;
     double2 q;
     double Rf;
-    double cx_[NS], cy_[NS];
-    int ct_[NS];
+    uint32_t ci_[(NS + 1) / 2];  // candidate s in bits 16 (s & 1) .. of word s / 2
     int n;
     int lane;  // 0..3
 
+    __device__ int cand(int s) const { return static_cast<int>((ci_[s >> 1] >> ((s & 1) << 4)) & 0xFFFFu); }
+    __device__ int sorted(int t) const {
+        int lo = 0, hi = nrow - 1;  // the staged row holding t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (lrb[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        return lrs[lo] + (t - lrb[lo]);
+    }
+    __device__ int uid(int t) const { return perm[sorted(t)]; }
     __device__ bool global() const { return false; }
     __device__ bool certify(double cx, double cy, double r) const {
         const double dx = cx - q.x, dy = cy - q.y;
@@ -468,20 +485,21 @@ struct QuadSource {
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             if (s >= n) continue;
-            const int t = ct_[s];
+            const int t = cand(s);
             if (t == exclude) continue;
-            const double dx = cx_[s] - c.x, dy = cy_[s] - c.y;
+            const double2 b = lpos[t];
+            const double dx = b.x - c.x, dy = b.y - c.y;
             const double d2 = dx * dx + dy * dy;
-            if (d2 < d2best || (d2 == d2best && best >= 0 && perm[t] < perm[best])) {
+            if (d2 < d2best || (d2 == d2best && best >= 0 && uid(t) < uid(best))) {
                 best = t;
                 d2best = d2;
-                pbest = make_double2(cx_[s], cy_[s]);
+                pbest = b;
             }
         }
-        reduce_nearest<QL>(d2best, best, pbest, perm);
+        reduce_nearest<QL>(d2best, best, pbest, [&](int u) { return uid(u); });
         return best;
     }
-    __device__ double2 P(int t) const { return pos[t]; }
+    __device__ double2 P(int t) const { return lpos[t]; }
     __device__ void mark_rings() {}
     // A branch-free loop that compares bisector keys against a static
     // forward error bound valid for every candidate (all candidates, and v
@@ -502,19 +520,24 @@ struct QuadSource {
         bool amb = false;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const double Bx = cx_[s] - v.x, By = cy_[s] - v.y;
+            const int t = cand(s);  // slots past n hold index 0
+            const double2 b = lpos[t];
+            const double Bx = b.x - v.x, By = b.y - v.y;
             const double cr = nx * Bx + ny * By;
             const double num = Bx * (Bx - Ax) + By * (By - Ay);
-            const bool ok = s < n && ct_[s] != iv && ct_[s] != ia;
+            const bool ok = s < n && t != iv && t != ia;
             const bool left = ok && cr > crmin;
             const double d = num * bc - bn * cr;
             amb = amb || (ok && fabs(cr) <= crmin) || (left && bt >= 0 && fabs(d) <= errS);
             const bool take = left && (bt < 0 || d < -errS);
-            bt = take ? ct_[s] : bt;
+            bt = take ? t : bt;
             bn = take ? num : bn;
             bc = take ? cr : bc;
-            bx = take ? cx_[s] : bx;
-            by = take ? cy_[s] : by;
+            bx = take ? b.x : bx;
+            by = take ? b.y : by;
+            // at most two candidates' loads in flight: the registers of all
+            // of them would cost the fourth wave per SIMD
+            if (s & 1) __builtin_amdgcn_sched_barrier(0);
         }
 #pragma unroll
         for (int m = 1; m < QL; m <<= 1) {
@@ -633,7 +656,7 @@ struct WaveSupport {
 // (ring k > 0 starting at T[k-1] meets first the apex that the previous
 // ring saw last before T[k], where the chained version starts).
 template <class G, class S_>
-__device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, int only = -1) {
+__device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, int only = -1, int vcap = KMAX) {
     // the current triangle as scalars, selected by value (an array indexed
     // at run time would live in scratch memory)
     int T0 = -1, T1 = -1, T2 = -1;
@@ -689,7 +712,7 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
         // a full turn (or a step past a0 through co-circular ties) without
         // finding the wedge: numerically inconsistent
         if (k.t == a0 || (orient(v, plo, pa0) > 0.0 && orient(v, pa0, phi) > 0.0)) return R_FAIL;
-        if (nvis >= KMAX) return R_CAP;
+        if (nvis >= vcap) return R_CAP;
         vis[nvis++] = k.t;
         cur = k.t;
         pcur = pk;
@@ -1238,25 +1261,28 @@ __device__ void quad_closure(const KArgs& a, int64_t slot, double2 q, int n, int
 // bits) for k_weights.  Boundary-ring nodes: the KNN nearest particles,
 // picked one per round (smallest squared distance, ties by user id), as a
 // pending closure row.  Anything not certified goes to the slow list.
-constexpr int TCAP = 1792;  // particles of a tile's bin region staged in LDS
+constexpr int TCAP = 1664;  // particles of a tile's bin region staged in LDS
 constexpr int TDIM = 48;    // bin rows / columns of that region (at most)
+constexpr int VPITCH = 16;  // wedge-search visit list per quad (longer: the exact path)
 
-// Seven slots per lane fit 168 registers, so three waves per SIMD (three
-// blocks per CU, within the LDS): the extra wave hides the latency of the
-// dependent FP64 chains of the gift-wrapping steps.
+// Candidates in LDS fit 128 registers and 40 KB of LDS per block, so four
+// waves per SIMD (four blocks per CU): the waves are bound by the latency of
+// the dependent FP64 chains of the gift-wrapping steps, which more resident
+// waves hide, and a 257 x 257 node mesh's 1024 full tiles run in one round.
 template <int NS>
-__global__ void __launch_bounds__(QWG) __attribute__((amdgpu_waves_per_eu(NS == 7 ? 3 : 1, 8)))
+__global__ void __launch_bounds__(QWG) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_build_fast(KArgs a) {
     // the tile's bin region (its nodes' search windows): bin starts, row
     // bases and the particles, copied once with coalesced row reads.  The
     // bin starts are needed only until every quad has gathered; the per-quad
     // support rows (padded by one word, so that the 16 quads of a wave hit
     // distinct LDS banks) take their place afterwards.
-    constexpr int TSH = TDIM * (TDIM + 1) > 2 * QPB * KPITCH ? TDIM * (TDIM + 1) : 2 * QPB * KPITCH;
+    constexpr int TSU = QPB * (KPITCH + VPITCH);
+    constexpr int TSH = TDIM * (TDIM + 1) > TSU ? TDIM * (TDIM + 1) : TSU;
     __shared__ double2 tpos[TCAP];
-    __shared__ int32_t tsi[TCAP];
     __shared__ int32_t tsh[TSH];
     __shared__ int32_t trb[TDIM + 1];
+    __shared__ int32_t trs[TDIM];  // sorted index of each staged row's first particle
     int32_t* const tst = tsh;
     int32_t* const su = tsh;
     int32_t* const svis = tsh + QPB * KPITCH;
@@ -1265,9 +1291,15 @@ k_build_fast(KArgs a) {
     const SetDesc sd = tile_set(a, blockIdx.x);
     int tx, ty;
     tile_xy(sd, static_cast<int>(blockIdx.x - sd.t0), tx, ty);
-    const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
+    // A tile holding the left or right boundary column takes its nodes
+    // column by column: that column's ring nodes (the closure path) then
+    // share one wave instead of adding their path to every wave of the tile.
+    // The rows go to the same slots either way.
+    const bool bycol = tx == 0 || tx * 8 + 7 >= sd.m.nx;
+    const int lx = bycol ? (qi >> 3) : (qi & 7), ly = bycol ? (qi & 7) : (qi >> 3);
+    const int i = tx * 8 + lx, j = ty * 8 + ly;
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
-    const int slot = static_cast<int>(blockIdx.x) * TILE_N + qi;  // < 2^31, checked on the host
+    const int slot = static_cast<int>(blockIdx.x) * TILE_N + ly * 8 + lx;  // < 2^31, checked on the host
     const int64_t nn = a.n_slots;
     const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
     const int32_t* start = a.start + sd.b0;
@@ -1302,6 +1334,7 @@ k_build_fast(KArgs a) {
                 if (r >= d) inc += o;
             }
             if (r <= nrow) trb[r] = inc - len;
+            if (r < nrow) trs[r] = tst[r * (TDIM + 1)];
         }
         __syncthreads();
         const int total = trb[nrow];
@@ -1309,7 +1342,7 @@ k_build_fast(KArgs a) {
         if (staged) {
             // every source index first, then all loads in flight together
             // (entries past the total load particle 0 and are not stored)
-            constexpr int EPT = TCAP / QWG;
+            constexpr int EPT = (TCAP + QWG - 1) / QWG;
             int src[EPT];
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
@@ -1332,21 +1365,24 @@ k_build_fast(KArgs a) {
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
                 const int e = static_cast<int>(threadIdx.x) + u * QWG;
-                if (e < total) {
-                    tpos[e] = make_double2(px[u], py[u]);
-                    tsi[e] = src[u];
-                }
+                if (e < total) tpos[e] = make_double2(px[u], py[u]);
             }
         }
         __syncthreads();
     }
     QuadSource<NS> g;
-    g.pos = a.pos_s;
     g.perm = a.perm;
+    g.lpos = tpos;
+    g.lrb = trb;
+    g.lrs = trs;
+    g.nrow = nrow;
+#pragma unroll
+    for (int k = 0; k < (NS + 1) / 2; ++k) g.ci_[k] = 0u;
     g.n = 0;
     g.lane = lane;
-    int ovf = 0;
-    if (valid) {
+    // a region too large to stage leaves its nodes to the exact path
+    int ovf = staged ? 0 : 1;
+    if (valid && staged) {
         g.q = node_pos(sd.m, i, j);
         // a corner node sees a quarter disk, an edge node a half disk: the
         // corner radius is sqrt(2) larger for the same expected count
@@ -1362,28 +1398,26 @@ k_build_fast(KArgs a) {
         const int bx0 = max(cbx - hw, 0), bx1 = min(cbx + hw, sd.g.nbx);
         const int by0 = max(cby - hw, 0), by1 = min(cby + hw, sd.g.nby);
         int acc = 0;  // particles accepted so far (the same in the four lanes)
-        auto insert = [&](double2 p, int t) {
+        auto insert = [&](int t) {
             if (g.n >= NS) {
                 ovf = 1;
                 return;
             }
+            // every word rewritten through a select: a store at a run-time
+            // index would put the array in scratch memory
+            const uint32_t bits = static_cast<uint32_t>(t) << ((g.n & 1) << 4);
+            const int word = g.n >> 1;
 #pragma unroll
-            for (int k = 0; k < NS; ++k)
-                if (k == g.n) {
-                    g.cx_[k] = p.x;
-                    g.cy_[k] = p.y;
-                    g.ct_[k] = t;
-                }
+            for (int k = 0; k < (NS + 1) / 2; ++k) g.ci_[k] = k == word ? (g.ci_[k] | bits) : g.ci_[k];
             ++g.n;
         };
-        // particles s .. e - 1 of one row segment; P(t) its position, id(t)
-        // the sorted index
-        auto segment = [&](int s, int e, auto&& P, auto&& id) {
+        // staged particles s .. e - 1 of one row segment
+        auto segment = [&](int s, int e) {
             for (int t0 = s; t0 < e; t0 += QL) {
                 const int t = t0 + lane;
                 bool in = false;
                 if (t < e) {
-                    const double2 p = P(t);
+                    const double2 p = tpos[t];
                     const double dx = p.x - g.q.x, dy = p.y - g.q.y;
                     in = dx * dx + dy * dy <= R2;
                 }
@@ -1395,26 +1429,15 @@ k_build_fast(KArgs a) {
                 if (k < c) {
                     int mm = m;  // the k-th set bit of m
                     for (int r = 0; r < k; ++r) mm &= mm - 1;
-                    const int tt = t0 + __ffs(mm) - 1;
-                    insert(P(tt), id(tt));
+                    insert(t0 + __ffs(mm) - 1);
                 }
                 acc += c;
             }
         };
-        if (staged) {
-            // the same particles in the same order as the global walk below
-            for (int by = by0; by < by1; ++by) {
-                const int* rs = tst + (by - rby0) * (TDIM + 1);
-                const int base = trb[by - rby0] - rs[0];
-                segment(base + rs[bx0 - rbx0], base + rs[bx1 - rbx0], [&](int t) { return tpos[t]; },
-                        [&](int t) { return tsi[t]; });
-            }
-        } else {
-            for (int by = by0; by < by1; ++by) {
-                const int row = by * sd.g.nbx;
-                segment(start[row + bx0], start[row + bx1], [&](int t) { return a.pos_s[t]; },
-                        [&](int t) { return t; });
-            }
+        for (int by = by0; by < by1; ++by) {
+            const int* rs = tst + (by - rby0) * (TDIM + 1);
+            const int base = trb[by - rby0] - rs[0];
+            segment(base + rs[bx0 - rbx0], base + rs[bx1 - rbx0]);
         }
     }
     __syncthreads();  // every quad has gathered: the support rows replace the bin starts
@@ -1427,13 +1450,13 @@ k_build_fast(KArgs a) {
             S.u = su + qi * KPITCH;
             S.n = 0;
             S.lane = lane;
-            const int st = delaunay_node(g, g.q, T, S, svis + qi * KPITCH);
+            const int st = delaunay_node(g, g.q, T, S, svis + qi * VPITCH, -1, VPITCH);
             if (st == R_OK) {
                 const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
                 if (lt0 >= 0 && lt1 >= 0 && lt2 >= 0) {
                     for (int k = lane; k < S.n; k += QL) {
                         const uint32_t e = static_cast<uint32_t>(S.u[k]);
-                        a.out.idx[k * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
+                        a.out.idx[k * nn + slot] = g.sorted(static_cast<int>(e & IDX_MASK));
                         a.out.mem[k * nn + slot] = static_cast<uint8_t>(e >> 28);
                     }
                     if (lane == 0) a.out.meta[slot] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, 0u);
@@ -1449,11 +1472,12 @@ k_build_fast(KArgs a) {
 #pragma unroll
                 for (int s = 0; s < NS; ++s) {
                     if (s >= g.n) continue;
-                    const int t = g.ct_[s];
-                    const double dx = g.cx_[s] - g.q.x, dy = g.cy_[s] - g.q.y;
+                    const int t = g.cand(s);
+                    const double2 b = tpos[t];
+                    const double dx = b.x - g.q.x, dy = b.y - g.q.y;
                     const double d2 = dx * dx + dy * dy;
-                    const bool after = d2 > pd || (d2 == pd && t != pt && a.perm[t] > pu);
-                    const bool better = d2 < bd || (d2 == bd && bt >= 0 && a.perm[t] < a.perm[bt]);
+                    const bool after = d2 > pd || (d2 == pd && t != pt && g.uid(t) > pu);
+                    const bool better = d2 < bd || (d2 == bd && bt >= 0 && g.uid(t) < g.uid(bt));
                     if (after && better) {
                         bd = d2;
                         bt = t;
@@ -1463,19 +1487,19 @@ k_build_fast(KArgs a) {
                 for (int m = 1; m < QL; m <<= 1) {
                     const double od = lane_xor<QL>(bd, m);
                     const int ot = lane_xor<QL>(bt, m);
-                    if (ot >= 0 && ot != bt && (bt < 0 || od < bd || (od == bd && a.perm[ot] < a.perm[bt]))) {
+                    if (ot >= 0 && ot != bt && (bt < 0 || od < bd || (od == bd && g.uid(ot) < g.uid(bt)))) {
                         bd = od;
                         bt = ot;
                     }
                 }
                 if (bt < 0) break;
                 if (lane == 0) {
-                    a.out.idx[r * nn + slot] = bt;
+                    a.out.idx[r * nn + slot] = g.sorted(bt);
                     a.out.mem[r * nn + slot] = 0;
                 }
                 pd = bd;
                 pt = bt;
-                pu = a.perm[bt];
+                pu = g.uid(bt);
                 ++found;
             }
             // certified when the K-th distance is inside the gathered disk

@@ -113,7 +113,8 @@ __device__ __forceinline__ int set_search(int S, int64_t v, F&& first) {
 // partial tile that lie beyond the mesh hold empty rows.
 constexpr int TILE_N = 64;
 
-// Tile tl of a set's node tiles: the full tiles first (row-major), then the
+// Tile tl of a set's node tiles: the full tiles first (by rows, each row
+// rotated by its index), then the
 // partial tiles of the last column and of the last row.  The hardware
 // dispatches blocks in index order and holds a fixed number at a time, so
 // full tiles taken in whole rounds, with the cheap partial ones filling the
@@ -121,8 +122,12 @@ constexpr int TILE_N = 64;
 __host__ __device__ inline void tile_xy(const SetDesc& sd, int tl, int& tx, int& ty) {
     const int fx = (sd.m.nx + 1) / 8, fy = (sd.m.ny + 1) / 8;  // full tile columns, rows
     if (tl < fx * fy) {
-        tx = tl % fx;
+        // rows of full tiles rotated by their row index: consecutive blocks
+        // go to the eight XCDs in turn, and the tiles of one mesh column
+        // (the heavier edge columns among them) are spread over all XCDs
+        // instead of sharing one when fx is a multiple of eight
         ty = tl / fx;
+        tx = (tl % fx + ty) % fx;
         return;
     }
     int r = tl - fx * fy;
@@ -140,7 +145,7 @@ __host__ __device__ inline void tile_xy(const SetDesc& sd, int tl, int& tx, int&
 // Inverse of tile_xy.
 __host__ __device__ inline int tile_index(const SetDesc& sd, int tx, int ty) {
     const int fx = (sd.m.nx + 1) / 8, fy = (sd.m.ny + 1) / 8;
-    if (tx < fx && ty < fy) return ty * fx + tx;
+    if (tx < fx && ty < fy) return ty * fx + (tx - ty % fx + fx) % fx;
     if (ty < fy) return fx * fy + ty;                  // the partial column
     return fx * fy + (sd.tiles_x > fx ? fy : 0) + tx;  // the partial row
 }
