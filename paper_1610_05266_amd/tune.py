@@ -121,14 +121,42 @@ def apply_options(options: Dict[str, float]) -> None:
         ops.p2m_set_option(k, float(v))
 
 
+def _timer(build: Callable[[], object], graph: bool):
+    """A callable that runs ``build`` once: as a replay of a HIP graph
+    captured from it (the way a time-stepping caller runs it, and the
+    cheapest launch), or directly when ``graph`` is false or capture fails."""
+    import torch
+
+    if not graph:
+        return build
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            build()
+        torch.cuda.current_stream().wait_stream(side)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            build()
+        torch.cuda.synchronize()
+    except RuntimeError:
+        torch.cuda.synchronize()
+        return build
+    return g.replay
+
+
 def autotune(build: Callable[[], object], probe: Callable[[object], "object"], key: str,
-             cache_path: Optional[str] = None, repeats: int = 5, retune: bool = False) -> TuneResult:
+             cache_path: Optional[str] = None, repeats: int = 5, retune: bool = False,
+             graph: bool = True) -> TuneResult:
     """Tune the build options for one workload and leave them applied.
 
     ``build()`` runs one weight build on the current stream and returns its
     handle; ``probe(handle)`` returns a tensor that must not depend on the
     options (a projection of a fixed field).  Times are GPU event times of
-    ``build`` (median of ``repeats`` after one warm-up)."""
+    graph replays of ``build`` (direct calls when ``graph`` is false or the
+    build cannot be captured), median of ``repeats`` after one warm-up: the
+    overlap of the build's two streams differs between the two launch forms
+    enough to change which options win."""
     import torch
 
     path = cache_path or default_cache_path()
@@ -150,15 +178,18 @@ def autotune(build: Callable[[], object], probe: Callable[[object], "object"], k
             return None
         if not torch.equal(probe(w), ref):
             return None
+        run = _timer(build, graph)
+        run()
         times = []
         for _ in range(repeats):
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
-            build()
+            run()
             e1.record()
             torch.cuda.synchronize()
             times.append(e0.elapsed_time(e1))
+        del run
         return statistics.median(times)
 
     res = coordinate_search(measure)
