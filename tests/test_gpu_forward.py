@@ -120,21 +120,25 @@ def test_cluster_and_void_cloud():
     assert_close(got, W @ c.vals, TOL64, "cluster P2M")
 
 
-@pytest.mark.parametrize("fast_radius,region_h,min_slow_share",
-                         [(1.5, 1.0, 0.5), (2.8, 4.0, 0.0), (3.0, 6.0, 0.0)])
-def test_c1_build_options_change_no_bit(c1, fast_radius, region_h, min_slow_share):
+@pytest.mark.parametrize("fast_radius,region_h,bin_scale,min_slow_share",
+                         [(1.5, 1.0, 1.0, 0.5), (2.8, 4.0, 1.0, 0.0), (3.0, 6.0, 1.0, 0.0),
+                          (2.6, 4.0, 0.25, 0.99)])
+def test_c1_build_options_change_no_bit(c1, fast_radius, region_h, bin_scale, min_slow_share):
     """The build options change only which pass certifies a node: the rows,
     weights and triangles equal the default build's (2.6h, 7 candidate slots
     per lane) bit for bit.  With the smallest first-pass radius most interior
     nodes take the exact wave path, and a first region of one h makes it
-    double its regions; 2.8h and 3h run the fast pass with 8 and 10 slots."""
+    double its regions; 2.8h and 3h run the fast pass with 8 and 10 slots;
+    bins of h/8 make every tile's region too wide to stage, so every node
+    takes the exact path."""
     c, orc, W, info = c1
     w0, pos = _build(c)
     ref = w0.export()
-    saved = {k: ops.p2m_get_option(k) for k in ("fast_radius", "region_h")}
+    saved = {k: ops.p2m_get_option(k) for k in ("fast_radius", "region_h", "bin_scale")}
     try:
         ops.p2m_set_option("fast_radius", fast_radius)
         ops.p2m_set_option("region_h", region_h)
+        ops.p2m_set_option("bin_scale", bin_scale)
         w1, _ = _build(c)
         d = w1.diag()
         got = w1.export()
