@@ -308,6 +308,27 @@ def main(argv=None):
     log(f"cached weights: mixed {cms32:.4f} ms, FP64 {cms64:.4f} ms per round trip")
     torch.cuda.synchronize()
 
+    # the same round trip with the linear FE particle functions (P2M_LINEAR:
+    # triangle located, rings and solves skipped), weights rebuilt every step
+    wlin = ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 | ops.P2M_LINEAR, check_diag=True)
+    lmesh32, lout32 = torch.empty_like(mesh32), torch.empty_like(out32)
+
+    def step_linear():
+        ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 | ops.P2M_LINEAR, weights=wlin,
+                              check_diag=False)
+        ops.p2m_project(wlin, v32, out=lmesh32)
+        ops.m2p_interpolate(mesh, lmesh32, pos, out=lout32)
+
+    run_lin = as_graph(step_linear)
+    if run_lin is not step_linear:
+        try:
+            check_replay(run_lin, step_linear, [lmesh32, lout32])
+        except RuntimeError as exc:
+            graph_notes.append(f"{exc}; eager launches timed")
+            run_lin = step_linear
+    lms32 = time_loop(run_lin)
+    log(f"linear FE round trip (mixed) {lms32:.4f} ms")
+
     # accuracy of the mixed form against the FP64 form (both full outputs)
     e_mesh = rel_errs(mesh32.cpu().numpy(), mesh64.cpu().numpy())
     e_part = rel_errs(out32.cpu().numpy(), out64.cpu().numpy())
@@ -399,6 +420,10 @@ def main(argv=None):
         "kernels": kernels,
         "round_trip_hbm": rt,
         "cached_weights": cached_rt,
+        "linear_fe": {"note": "the same round trip with linear FE particle functions at interior nodes "
+                              "(P2M_LINEAR: the node's particle triangle located, rings and solves skipped), "
+                              "mixed form, weights rebuilt every step",
+                      "ms_per_step": round(lms32, 5), "Mparticles_per_s": round(N / (lms32 * 1e-3) / 1e6, 3)},
         "launch": "eager" if (a.no_graph or graph_notes) else "HIP graph replay of the whole step",
         "launch_notes": graph_notes,
         "tuning": tuning,

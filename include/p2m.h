@@ -67,6 +67,8 @@ typedef enum p2m_dtype {
 /* Flags of p2m_build_weights. */
 #define P2M_WEIGHTS_F32 0x1  /* also keep FP32 copies of the weights (mixed path) */
 #define P2M_STRICT      0x2  /* rank-deficient systems make diag report EGEOM   */
+#define P2M_LINEAR      0x4  /* linear FE particle functions phi_mu at interior
+                                nodes instead of psi_mu (see p2m_build_weights) */
 
 /* Largest number of particles one node's weights may involve (ELL width). */
 #define P2M_MAX_SUPPORT 32
@@ -113,7 +115,14 @@ typedef struct p2m_weights p2m_weights;
  *         it sizes the binning grid; results do not depend on it.
  *  pos    device [N][2] FP64 particle positions (user order).
  *  N      number of particles, 3 <= N < 2^28.
- *  flags  P2M_WEIGHTS_F32 | P2M_STRICT.
+ *  flags  P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR.  With P2M_LINEAR an
+ *         interior node's row is phi_mu alone (App. B: the linear FE functions
+ *         of the particles' Delaunay triangulation, eqs. C0 and C1, i.e. the
+ *         barycentric coordinates of the node in T, three entries; the
+ *         particle side of the paper's linear-FE projection): the triangle is
+ *         located as above, rings and solves are skipped.  Closure nodes keep
+ *         their quadratic-moment weights.  Such a handle serves p2m_project
+ *         and p2m_project_backward; p2m_build_weights_backward rejects it.
  *  w      in/out: *w == NULL allocates a new handle; a handle from an earlier
  *         call is reused (its buffers grow if needed; previous contents are
  *         overwritten, so no work may still be pending on them on another
@@ -198,6 +207,7 @@ int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int
  * handle was built from; geometry is recomputed, not stored).  The
  * combinatorial structure (triangles, rings, nearest sets) is held fixed.
  *  grad_pos  device [N][2] FP64, ACCUMULATED with atomic adds.
+ * Errors: EINVAL also for a handle built with P2M_LINEAR.
  */
 int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const double* grad_w,
                                double* grad_pos, void* stream);

@@ -650,6 +650,8 @@ struct WaveSupport {
 // triangles across an edge of T that an earlier ring already found.
 // Returns R_OK, R_OUTSIDE (q outside the convex hull), R_MORE (not
 // certified by this source), R_FAIL or R_CAP.
+// With `only` == -2 the routine stops at the triangle: the list is T's three
+// vertices (the linear FE functions need nothing else).
 // With `only` in 0..2 the rings phase does just that ring: several waves
 // can then run the three rings of one node side by side; the lists they
 // return, merged in ring order, are this routine's list in the same order
@@ -772,6 +774,13 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
     // ring 0 rotates from T2 until it meets a0.  A clockwise one passed it
     // from T2 back to a0, which continues ring 0 counter-clockwise from T2.
     g.mark_rings();
+    if (only == -2) {
+        if (!S.add(T0, 0) || !S.add(T1, 0) || !S.add(T2, 0)) return R_CAP;
+        Tout[0] = T0;
+        Tout[1] = T1;
+        Tout[2] = T2;
+        return R_OK;
+    }
     int rk = only < 0 ? 0 : only;
     const bool kept = !walked && T0 == n0 && nvis > 0 && rk == 0;
     bool reuse0 = kept && dir > 0.0 && T1 == vis[nvis - 1];
@@ -1044,6 +1053,7 @@ struct KArgs {
     int32_t* rd;          // rank-deficient list of row slots (capacity n_nodes)
     int32_t* tdiag;       // [n_slots / TILE_N][4] per-tile counts of k_weights
     unsigned long long* diag;
+    int linear;           // interior rows: barycentric coordinates in T only
 };
 
 // The set of a node tile / of a row slot.
@@ -1450,7 +1460,7 @@ k_build_fast(KArgs a) {
             S.u = su + qi * KPITCH;
             S.n = 0;
             S.lane = lane;
-            const int st = delaunay_node(g, g.q, T, S, svis + qi * VPITCH, -1, VPITCH);
+            const int st = delaunay_node(g, g.q, T, S, svis + qi * VPITCH, a.linear ? -2 : -1, VPITCH);
             if (st == R_OK) {
                 const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
                 if (lt0 >= 0 && lt1 >= 0 && lt2 >= 0) {
@@ -1624,7 +1634,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
         phi[0] = orient(q, P1, P2) / D;
         phi[1] = orient(P0, q, P2) / D;
         phi[2] = orient(P0, P1, q) / D;
-        if (lane < 3) {
+        if (lane < 3 && !a.linear) {
             const int pb = lane == 2 ? 0 : lane + 1;
             const double2 rn = lane == 0 ? P0 : (lane == 1 ? P1 : P2);
             const double2 rs = pb == 0 ? P0 : (pb == 1 ? P1 : P2);
@@ -1846,7 +1856,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
                 const int hw = level < a.levels ? (sd.hw0 << level) : big;
                 c.set_region(make_region(sd.g, cbx, cby, hw));
                 S.n = 0;
-                const int sk = delaunay_node(c, q, T, S, svis + wv * KMAX, wv);
+                const int sk = delaunay_node(c, q, T, S, svis + wv * KMAX, a.linear ? -2 : wv);
                 if (lane < S.n) sring[wv][lane] = S.e;
                 if (lane == 0) {
                     sinfo[wv][0] = sk;
@@ -2067,7 +2077,7 @@ __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
 
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
                   const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,
-                  unsigned long long* diag, const SideWork& side, hipStream_t st) {
+                  unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear) {
     PhaseTimer _timer(PH_BUILD, st);
     // row slots are listed as int32
     if (n_tiles * TILE_N >= (int64_t(1) << 31)) {
@@ -2088,6 +2098,7 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     a.rd = rd;
     a.tdiag = tdiag;
     a.diag = diag;
+    a.linear = linear ? 1 : 0;
     const int tiles = static_cast<int>(n_tiles);
     {
         PhaseTimer t1(PH_BUILD_FAST, st);

@@ -275,7 +275,7 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
         set_error("output handle pointer is NULL");
         return P2M_EINVAL;
     }
-    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT)) {
+    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR)) {
         set_error("unknown flags 0x%x", flags);
         return P2M_EINVAL;
     }
@@ -366,7 +366,7 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     rc = side_stream(dev, &side.stream);
     if (rc) return rc;
     return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, fast_slots(), w->slow,
-                         w->rd, w->tdiag, w->diag, side, st);
+                         w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0);
 }
 
 // Per-device workspace of the fused (recompute) entry points: a weights
@@ -691,6 +691,10 @@ int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const do
     if (rc) return rc;
     if (!pos || !aligned(pos, 16) || !grad_w || !aligned(grad_w, 8) || !grad_pos || !aligned(grad_pos, 16)) {
         set_error("pos / grad_w / grad_pos NULL or misaligned");
+        return P2M_EINVAL;
+    }
+    if (w->flags & P2M_LINEAR) {
+        set_error("weights built with P2M_LINEAR: position gradients are not provided");
         return P2M_EINVAL;
     }
     return build_backward(view(w), pos, grad_w, grad_pos, static_cast<hipStream_t>(stream));
