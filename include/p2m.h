@@ -174,6 +174,20 @@ int m2p_interpolate(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtyp
                     const double* pos, int64_t N, void* vals, void* stream);
 
 /*
+ * p2m_advect -- moves the particles one time step with the prescribed
+ * velocity of a kinematic test (the paper's kinematic procedures rebuild the
+ * particle functions after every move): the cellular flow of streamfunction
+ * amp sin(pi (x-x0)/Lx) sin(pi (y-y0)/Ly) on the mesh box (Lx = nx H,
+ * Ly = ny H; u = d psi/dy, v = -d psi/dx, no flow through the box walls),
+ * one explicit midpoint step r* = r + dt/2 u(r), r' = r + dt u(r*), then
+ * clamped into the box.  A loop step of the kinematic projection is
+ * m2p_interpolate, p2m_advect, p2m_build_weights, p2m_project.
+ *  pos   device [N][2] FP64, updated in place.
+ * Errors: EINVAL (mesh, pointer, N, non-finite amp or dt), EHIP.
+ */
+int p2m_advect(const p2m_mesh* mesh, double* pos, int64_t N, double amp, double dt, void* stream);
+
+/*
  * m2p_interpolate_backward -- adjoint of m2p_interpolate.
  *  grad_vals  device [N][C] upstream gradient (type dtype; FP32 for BF16).
  *  grad_mesh  device [(nx+1)(ny+1)][C] output, OVERWRITTEN with

@@ -19,6 +19,9 @@ project from particles onto a fixed mesh"):
   linear FE functions on the fixed uniform mesh.
 * Derivatives of both (by transposition for the linear parts, by complex-step
   differentiation of the forward construction for the position dependence).
+* The kinematic loop of the paper's transport tests (``advect``): particles
+  moved by a prescribed velocity (explicit midpoint rule), their functions
+  rebuilt, M2P and P2M every step.
 
 Library routines serve as steps where the paper itself used one: Qhull
 (scipy.spatial.Delaunay) for the Delaunay triangulation the paper built with

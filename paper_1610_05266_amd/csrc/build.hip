@@ -2115,9 +2115,11 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     P2M_HIP(hipStreamWaitEvent(side.stream, side.fork, 0));
     {
         PhaseTimer t2(PH_BUILD_SLOW, side.stream);
-        // one block per slow node (few: escalated, undecided); the grid
-        // loops over the actual list
-        const int64_t expect = n_nodes / 256 + 64 * static_cast<int64_t>(S);
+        // one block per slow node; the grid loops over the actual list.  It
+        // is sized for many more nodes than an ordered cloud leaves here (a
+        // sheared one leaves thousands), beyond the blocks resident at once:
+        // the blocks past the list leave at once
+        const int64_t expect = n_nodes / 64 + 64 * static_cast<int64_t>(S);
         const int gs = static_cast<int>(std::min<int64_t>(expect, 4096));
         k_slow_geom<<<gs, SWG, 0, side.stream>>>(a);
     }

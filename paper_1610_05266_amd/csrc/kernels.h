@@ -81,6 +81,9 @@ int project_backward(const WeightsView& w, const void* grad_mesh, int C, int dty
                      void* grad_vals, double* grad_w, hipStream_t st);
 // sets == nullptr: one mesh m; else particles/nodes of set s start at
 // sets[s].p0 / sets[s].n0 and m is ignored.  n_nodes: all sets.
+// One explicit midpoint step of every particle in the cellular flow of the
+// mesh box, clamped into the box (advect.hip).
+int advect_midpoint(const MeshD& m, double* pos, int64_t N, double amp, double dt, hipStream_t st);
 int m2p(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C, int dtype,
         const double* pos, int64_t N, void* vals, hipStream_t st);
 int m2p_backward(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C,

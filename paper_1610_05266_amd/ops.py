@@ -6,7 +6,7 @@ from __future__ import annotations
 
 import ctypes
 from dataclasses import dataclass
-from typing import Optional
+from typing import Optional, Tuple
 
 import torch
 
@@ -35,6 +35,8 @@ __all__ = [
     "P2M_WEIGHTS_F32",
     "P2M_STRICT",
     "P2M_LINEAR",
+    "p2m_advect",
+    "kinematic_step",
 ]
 
 
@@ -189,6 +191,31 @@ def p2m_project(w: Weights, vals: torch.Tensor, out: Optional[torch.Tensor] = No
     with torch.cuda.device(vals.device):
         check(load().p2m_project(w.handle, _ptr(vals), C, code, _ptr(out), _stream(vals)))
     return out
+
+
+def p2m_advect(mesh, pos: torch.Tensor, amp: float, dt: float) -> torch.Tensor:
+    """One midpoint step of the particles in the cellular flow of the mesh box
+    (C call of the same name); ``pos`` is updated in place and returned."""
+    mesh = Mesh.of(mesh)
+    _need(pos, "pos", torch.float64)
+    if pos.dim() != 2 or pos.shape[1] != 2:
+        raise ValueError("pos must have shape [N, 2]")
+    cm = mesh.c()
+    with torch.cuda.device(pos.device):
+        check(load().p2m_advect(ctypes.byref(cm), _ptr(pos), pos.shape[0], float(amp), float(dt), _stream(pos)))
+    return pos
+
+
+def kinematic_step(mesh, h: float, pos: torch.Tensor, mesh_vals: torch.Tensor, amp: float, dt: float,
+                   flags: int = 0, weights: Optional[Weights] = None) -> Tuple[torch.Tensor, Weights]:
+    """One step of the kinematic projection loop, every step on the GPU:
+    particle values from the mesh (M2P), the particles moved one step
+    (p2m_advect), their functions rebuilt, and projected back (P2M).
+    ``pos`` is updated in place; returns (new mesh values, weights)."""
+    vals = m2p_interpolate(mesh, mesh_vals, pos)
+    p2m_advect(mesh, pos, amp, dt)
+    w = p2m_build_weights(mesh, h, pos, flags, weights=weights, check_diag=False)
+    return p2m_project(w, vals), w
 
 
 def m2p_interpolate(mesh, mesh_vals: torch.Tensor, pos: torch.Tensor, out: Optional[torch.Tensor] = None,
