@@ -48,6 +48,8 @@ def parse(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip timing the CPU oracle")
     ap.add_argument("--no-oracle-check", action="store_true", help="skip the sampled oracle comparison")
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default build options")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the linear-FE and kinematic-loop measurements (profiles of the headline step)")
     ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE",
                     help="set a build option (p2m_set_option) instead of autotuning")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -308,68 +310,71 @@ def main(argv=None):
     log(f"cached weights: mixed {cms32:.4f} ms, FP64 {cms64:.4f} ms per round trip")
     torch.cuda.synchronize()
 
-    # the same round trip with the linear FE particle functions (P2M_LINEAR:
-    # triangle located, rings and solves skipped), weights rebuilt every step
-    wlin = ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 | ops.P2M_LINEAR, check_diag=True)
-    lmesh32, lout32 = torch.empty_like(mesh32), torch.empty_like(out32)
+    lms32 = kms32 = None
+    kdiag, ktuning = {}, None
+    if not a.no_extras:
+        # the same round trip with the linear FE particle functions (P2M_LINEAR:
+        # triangle located, rings and solves skipped), weights rebuilt every step
+        wlin = ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 | ops.P2M_LINEAR, check_diag=True)
+        lmesh32, lout32 = torch.empty_like(mesh32), torch.empty_like(out32)
 
-    def step_linear():
-        ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 | ops.P2M_LINEAR, weights=wlin,
-                              check_diag=False)
-        ops.p2m_project(wlin, v32, out=lmesh32)
-        ops.m2p_interpolate(mesh, lmesh32, pos, out=lout32)
+        def step_linear():
+            ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 | ops.P2M_LINEAR, weights=wlin,
+                                  check_diag=False)
+            ops.p2m_project(wlin, v32, out=lmesh32)
+            ops.m2p_interpolate(mesh, lmesh32, pos, out=lout32)
 
-    run_lin = as_graph(step_linear)
-    if run_lin is not step_linear:
-        try:
-            check_replay(run_lin, step_linear, [lmesh32, lout32])
-        except RuntimeError as exc:
-            graph_notes.append(f"{exc}; eager launches timed")
-            run_lin = step_linear
-    lms32 = time_loop(run_lin)
-    log(f"linear FE round trip (mixed) {lms32:.4f} ms")
+        run_lin = as_graph(step_linear)
+        if run_lin is not step_linear:
+            try:
+                check_replay(run_lin, step_linear, [lmesh32, lout32])
+            except RuntimeError as exc:
+                graph_notes.append(f"{exc}; eager launches timed")
+                run_lin = step_linear
+        lms32 = time_loop(run_lin)
+        log(f"linear FE round trip (mixed) {lms32:.4f} ms")
 
-    # one step of the kinematic projection loop (mixed form): particle values
-    # from the mesh, the particles moved one midpoint step in the cellular flow
-    # of the box (about a quarter cell), their functions rebuilt, and P2M.  The
-    # particles move at every replay, so replays are not compared with an
-    # eager step; a copy of the positions keeps the other measurements intact.
-    kpos = pos.clone()
-    kamp, kdt = 0.1, 0.25 * mesh.H / (0.1 * math.pi)
-    wk = ops.p2m_build_weights(mesh, cloud.h, kpos, P2M_WEIGHTS_F32, check_diag=True)
-    kmesh, kvals = mesh32.clone(), torch.empty_like(out32)
+        # one step of the kinematic projection loop (mixed form): particle values
+        # from the mesh, the particles moved one midpoint step in the cellular flow
+        # of the box (about a quarter cell), their functions rebuilt, and P2M.  The
+        # particles move at every replay, so replays are not compared with an
+        # eager step; a copy of the positions keeps the other measurements intact.
+        kpos = pos.clone()
+        kamp, kdt = 0.1, 0.25 * mesh.H / (0.1 * math.pi)
+        wk = ops.p2m_build_weights(mesh, cloud.h, kpos, P2M_WEIGHTS_F32, check_diag=True)
+        kmesh, kvals = mesh32.clone(), torch.empty_like(out32)
 
-    def step_kinematic():
-        ops.m2p_interpolate(mesh, kmesh, kpos, out=kvals)
-        ops.p2m_advect(mesh, kpos, kamp, kdt)
-        ops.p2m_build_weights(mesh, cloud.h, kpos, P2M_WEIGHTS_F32, weights=wk, check_diag=False)
-        ops.p2m_project(wk, kvals, out=kmesh)
+        def step_kinematic():
+            ops.m2p_interpolate(mesh, kmesh, kpos, out=kvals)
+            ops.p2m_advect(mesh, kpos, kamp, kdt)
+            ops.p2m_build_weights(mesh, cloud.h, kpos, P2M_WEIGHTS_F32, weights=wk, check_diag=False)
+            ops.p2m_project(wk, kvals, out=kmesh)
 
-    # shear the cloud first (as a loop does within a few dozen steps), then
-    # tune the build options for that cloud unless tuning is off: a sheared
-    # cloud has long thin triangles whose circumdisks leave the default radius
-    for _ in range(24):
-        step_kinematic()
-    torch.cuda.synchronize()
-    ktuning = None
-    if not a.no_tune and not a.set:
-        from paper_1610_05266_amd import tune
+        # shear the cloud first (as a loop does within a few dozen steps), then
+        # tune the build options for that cloud unless tuning is off: a sheared
+        # cloud has long thin triangles whose circumdisks leave the default radius
+        for _ in range(24):
+            step_kinematic()
+        torch.cuda.synchronize()
+        ktuning = None
+        if not a.no_tune and not a.set:
+            from paper_1610_05266_amd import tune
 
-        kkey = tune.workload_key(torch.cuda.get_device_name(dev), N, nn, cloud.h / mesh.H, P2M_WEIGHTS_F32) + "|sheared"
-        kres = tune.autotune(
-            lambda: ops.p2m_build_weights(mesh, cloud.h, kpos, P2M_WEIGHTS_F32, weights=wk, check_diag=False),
-            lambda hd: ops.p2m_project(hd, kvals), kkey)
-        ktuning = {"options": kres.options, "build_ms_tuned": round(kres.median_ms, 5),
-                   "build_ms_default": round(kres.default_ms, 5), "cached": kres.cached}
-        log(f"kinematic tuning {ktuning}")
-    kms32 = time_loop(as_graph(step_kinematic))
-    kdiag = wk.diag(check_status=False)
-    log(f"kinematic loop step (mixed) {kms32:.4f} ms, diag after the loop {kdiag}")
-    if ktuning is not None:
-        # the other measurements keep the options tuned for the ordered cloud
-        from paper_1610_05266_amd import tune
+            kkey = tune.workload_key(torch.cuda.get_device_name(dev), N, nn, cloud.h / mesh.H, P2M_WEIGHTS_F32) + "|sheared"
+            kres = tune.autotune(
+                lambda: ops.p2m_build_weights(mesh, cloud.h, kpos, P2M_WEIGHTS_F32, weights=wk, check_diag=False),
+                lambda hd: ops.p2m_project(hd, kvals), kkey)
+            ktuning = {"options": kres.options, "build_ms_tuned": round(kres.median_ms, 5),
+                       "build_ms_default": round(kres.default_ms, 5), "cached": kres.cached}
+            log(f"kinematic tuning {ktuning}")
+        kms32 = time_loop(as_graph(step_kinematic))
+        kdiag = wk.diag(check_status=False)
+        log(f"kinematic loop step (mixed) {kms32:.4f} ms, diag after the loop {kdiag}")
+        if ktuning is not None:
+            # the other measurements keep the options tuned for the ordered cloud
+            from paper_1610_05266_amd import tune
 
-        tune.apply_options(tuning["options"])
+            tune.apply_options(tuning["options"])
 
     # accuracy of the mixed form against the FP64 form (both full outputs)
     e_mesh = rel_errs(mesh32.cpu().numpy(), mesh64.cpu().numpy())
@@ -462,14 +467,14 @@ def main(argv=None):
         "kernels": kernels,
         "round_trip_hbm": rt,
         "cached_weights": cached_rt,
-        "kinematic_loop": {"note": "one step of the kinematic projection loop, mixed form: M2P, the particles "
+        "kinematic_loop": None if kms32 is None else {"note": "one step of the kinematic projection loop, mixed form: M2P, the particles "
                                    "moved one midpoint step in the cellular flow of the box (a quarter cell), "
                                    "functions rebuilt, P2M; HIP graph replays, particles moving at every replay; "
                                    "build options tuned on the cloud after 24 steps of shear",
                            "ms_per_step": round(kms32, 5), "Mparticles_per_s": round(N / (kms32 * 1e-3) / 1e6, 3),
                            "failed_nodes_after": int(kdiag["failed_nodes"]),
                            "slow_nodes_after": int(kdiag["slow_nodes"]), "tuning": ktuning},
-        "linear_fe": {"note": "the same round trip with linear FE particle functions at interior nodes "
+        "linear_fe": None if lms32 is None else {"note": "the same round trip with linear FE particle functions at interior nodes "
                               "(P2M_LINEAR: the node's particle triangle located, rings and solves skipped), "
                               "mixed form, weights rebuilt every step",
                       "ms_per_step": round(lms32, 5), "Mparticles_per_s": round(N / (lms32 * 1e-3) / 1e6, 3)},
