@@ -310,9 +310,32 @@ def main(argv=None):
     log(f"cached weights: mixed {cms32:.4f} ms, FP64 {cms64:.4f} ms per round trip")
     torch.cuda.synchronize()
 
-    lms32 = kms32 = None
+    lms32 = kms32 = qms32 = qsetup = None
     kdiag, ktuning = {}, None
     if not a.no_extras:
+        # M2P with the mesh's quadratically consistent functions (FP32), on the
+        # mesh values of the mixed step; the edge table is built once per mesh
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        mq = ops.MeshQCSF(mesh, dev)
+        e1.record()
+        torch.cuda.synchronize()
+        qsetup = e0.elapsed_time(e1)
+        qout = torch.empty_like(out32)
+
+        def m2p_q():
+            mq.interpolate(mesh32, pos, out=qout)
+
+        run_q = as_graph(m2p_q)
+        if run_q is not m2p_q:
+            try:
+                check_replay(run_q, m2p_q, [qout])
+            except RuntimeError as exc:
+                graph_notes.append(f"{exc}; eager launches timed")
+                run_q = m2p_q
+        qms32 = time_loop(run_q)
+        log(f"M2P with mesh QCSF (FP32) {qms32:.4f} ms, table {qsetup:.3f} ms once")
+
         # the same round trip with the linear FE particle functions (P2M_LINEAR:
         # triangle located, rings and solves skipped), weights rebuilt every step
         wlin = ops.p2m_build_weights(mesh, cloud.h, pos, P2M_WEIGHTS_F32 | ops.P2M_LINEAR, check_diag=True)
@@ -474,6 +497,11 @@ def main(argv=None):
                            "ms_per_step": round(kms32, 5), "Mparticles_per_s": round(N / (kms32 * 1e-3) / 1e6, 3),
                            "failed_nodes_after": int(kdiag["failed_nodes"]),
                            "slow_nodes_after": int(kdiag["slow_nodes"]), "tuning": ktuning},
+        "m2p_qcsf": None if qms32 is None else {
+            "note": "M2P with the mesh's quadratically consistent functions (FP32 sums, FP64 edge table built "
+                    "once per mesh), HIP graph replays; compare the linear M2P's phases_ms.m2p",
+            "ms": round(qms32, 5), "Mparticles_per_s": round(N / (qms32 * 1e-3) / 1e6, 3),
+            "table_ms_once": round(qsetup, 4)},
         "linear_fe": None if lms32 is None else {"note": "the same round trip with linear FE particle functions at interior nodes "
                               "(P2M_LINEAR: the node's particle triangle located, rings and solves skipped), "
                               "mixed form, weights rebuilt every step",

@@ -188,6 +188,34 @@ int m2p_interpolate(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtyp
 int p2m_advect(const p2m_mesh* mesh, double* pos, int64_t N, double amp, double dt, void* stream);
 
 /*
+ * Mesh-side quadratically consistent shape functions (App. B's construction
+ * applied to the fixed mesh): psi^m_i = phi^m_i + 2 sum over the edges
+ * e = (nu, sigma) of the particle's mesh triangle of phi^m_nu phi^m_sigma
+ * A^m_{i e}, with phi^m the linear FE functions of m2p_interpolate's
+ * triangulation and A^m_{. e} the minimum-norm solution of eqs. (A0), (A1),
+ * (A2_2) over S_e = ring(nu) U ring(sigma), ring(v) = v and its neighbours
+ * (i+-1, j), (i, j+-1), (i+1, j+1), (i-1, j-1) inside the mesh (a
+ * pseudo-inverse where the mesh boundary costs a system its rank).  The
+ * coefficients depend on the mesh only: p2m_mesh_qcsf_create computes them
+ * once (10 per edge, ~3 (nx+1)(ny+1) edges, 120 bytes each, device memory of
+ * the current device); p2m_mesh_qcsf_destroy frees them.  The handle is
+ * read-only once created and may serve any number of calls and streams.
+ * Errors: EINVAL (mesh, out), ENOMEM, EHIP.
+ */
+typedef struct p2m_mesh_qcsf p2m_mesh_qcsf;
+int p2m_mesh_qcsf_create(const p2m_mesh* mesh, p2m_mesh_qcsf** out, void* stream);
+void p2m_mesh_qcsf_destroy(p2m_mesh_qcsf* q);
+
+/*
+ * m2p_interpolate_qcsf -- eq. (m2p) with the mesh's quadratically consistent
+ * functions: vals[mu][c] = sum_i psi^m_i(r_mu) mesh_vals[i][c]; arguments
+ * and types as m2p_interpolate (FP64 coefficients, sums in the dtype's
+ * precision).  Reproduces every quadratic field exactly.  No adjoint.
+ */
+int m2p_interpolate_qcsf(const p2m_mesh_qcsf* q, const void* mesh_vals, int C, int dtype, const double* pos,
+                         int64_t N, void* vals, void* stream);
+
+/*
  * m2p_interpolate_backward -- adjoint of m2p_interpolate.
  *  grad_vals  device [N][C] upstream gradient (type dtype; FP32 for BF16).
  *  grad_mesh  device [(nx+1)(ny+1)][C] output, OVERWRITTEN with

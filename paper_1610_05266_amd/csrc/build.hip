@@ -2073,6 +2073,77 @@ __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
     }
 }
 
+
+// ------------------------------------------------ mesh-side coefficients
+// The construction of App. B on the fixed mesh: for every mesh edge
+// e = (a, b) of the fixed-diagonal triangulation, the minimum-norm A^m_{. e}
+// solving eqs. (A0), (A1), (A2_2) over S_e = ring(a) U ring(b), ring(v) being
+// v and its neighbours (i +- 1, j), (i, j +- 1), (i + 1, j + 1),
+// (i - 1, j - 1) inside the mesh.  Relative to a, S_e covers ten fixed
+// offsets per orientation (fewer at the mesh boundary, where the systems can
+// lose rank: hence the pseudo-inverse).  Edges: horizontal (i, j)-(i+1, j)
+// first, then vertical (i, j)-(i, j+1), then diagonal (i, j)-(i+1, j+1), each
+// set row-major by its first end; row e of the table holds the node ids and
+// coefficients of the ten offsets (coefficient 0 and node a off the mesh).
+__constant__ int8_t kEdgeOff[3][MESH_SUP][2] = {
+    {{-1, -1}, {-1, 0}, {0, -1}, {0, 0}, {0, 1}, {1, -1}, {1, 0}, {1, 1}, {2, 0}, {2, 1}},
+    {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}, {0, 0}, {0, 1}, {0, 2}, {1, 0}, {1, 1}, {1, 2}},
+    {{-1, -1}, {-1, 0}, {0, -1}, {0, 0}, {0, 1}, {1, 0}, {1, 1}, {1, 2}, {2, 1}, {2, 2}}};
+
+__global__ void __launch_bounds__(64) k_mesh_edges(MeshD m, int64_t E, int32_t* __restrict__ idx,
+                                                   double* __restrict__ coef) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int64_t nh = static_cast<int64_t>(m.nx) * (m.ny + 1), nv = static_cast<int64_t>(m.nx + 1) * m.ny;
+    int o, i, j;
+    if (e < nh) {
+        o = 0;
+        i = static_cast<int>(e % m.nx);
+        j = static_cast<int>(e / m.nx);
+    } else if (e < nh + nv) {
+        o = 1;
+        i = static_cast<int>((e - nh) % (m.nx + 1));
+        j = static_cast<int>((e - nh) / (m.nx + 1));
+    } else {
+        o = 2;
+        i = static_cast<int>((e - nh - nv) % m.nx);
+        j = static_cast<int>((e - nh - nv) / m.nx);
+    }
+    const int ib = i + (o == 1 ? 0 : 1), jb = j + (o == 0 ? 0 : 1);
+    const double2 pa = node_pos(m, i, j), pb = node_pos(m, ib, jb);
+    // edge frame: origin at the midpoint, unit length
+    const double cx = 0.5 * (pa.x + pb.x), cy = 0.5 * (pa.y + pb.y);
+    const double dxv = pa.x - pb.x, dyv = pa.y - pb.y;
+    const double sc = 1.0 / sqrt(dxv * dxv + dyv * dyv);
+    const double dx = dxv * sc, dy = dyv * sc;
+    Moments mo;
+    mo.zero();
+#pragma unroll
+    for (int k = 0; k < MESH_SUP; ++k) {
+        const int a = i + kEdgeOff[o][k][0], b = j + kEdgeOff[o][k][1];
+        if (a < 0 || b < 0 || a > m.nx || b > m.ny) continue;
+        const double2 p = node_pos(m, a, b);
+        mo.add((p.x - cx) * sc, (p.y - cy) * sc);
+    }
+    const double rhs[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
+    double y[6];
+    pinv6_solve(mo, rhs, y);
+#pragma unroll
+    for (int k = 0; k < MESH_SUP; ++k) {
+        const int a = i + kEdgeOff[o][k][0], b = j + kEdgeOff[o][k][1];
+        const bool in = a >= 0 && b >= 0 && a <= m.nx && b <= m.ny;
+        double c = 0.0;
+        if (in) {
+            const double2 p = node_pos(m, a, b);
+            double pm[6];
+            monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
+            c = dot6(pm, y);
+        }
+        idx[e * MESH_SUP + k] = in ? b * (m.nx + 1) + a : j * (m.nx + 1) + i;
+        coef[e * MESH_SUP + k] = c;
+    }
+}
+
 }  // namespace
 
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
@@ -2132,6 +2203,18 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         // rank-deficient nodes of either pass (normally none)
         k_weights_rd<<<16, QWG, 0, st>>>(a);
     }
+    P2M_HIP(hipGetLastError());
+    return P2M_OK;
+}
+
+int64_t mesh_edge_count(const MeshD& m) {
+    return static_cast<int64_t>(m.nx) * (m.ny + 1) + static_cast<int64_t>(m.nx + 1) * m.ny +
+           static_cast<int64_t>(m.nx) * m.ny;
+}
+
+int mesh_edge_table(const MeshD& m, int32_t* idx, double* coef, hipStream_t st) {
+    const int64_t E = mesh_edge_count(m);
+    k_mesh_edges<<<static_cast<unsigned>((E + 63) / 64), 64, 0, st>>>(m, E, idx, coef);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }

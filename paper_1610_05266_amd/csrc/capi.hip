@@ -94,6 +94,14 @@ struct p2m_batch {
     int S() const { return static_cast<int>(meshes.size()); }
 };
 
+// Mesh-side quadratically consistent functions: the edge table of one mesh.
+struct p2m_mesh_qcsf {
+    p2m::MeshD m{};
+    int64_t E = 0;
+    int32_t* idx = nullptr;  // [E][MESH_SUP] support node ids
+    double* coef = nullptr;  // [E][MESH_SUP] coefficients A^m
+};
+
 namespace {
 
 template <typename T>
@@ -761,6 +769,55 @@ int p2m_backward_fused(const p2m_mesh* mesh, double h, const double* pos, int64_
     rc = p2m_project_backward(fw.w, grad_mesh, C, dtype, vals, grad_vals, gw, stream);
     if (!rc && gw) rc = p2m_build_weights_backward(fw.w, pos, gw, grad_pos, stream);
     return rc;
+}
+
+int p2m_mesh_qcsf_create(const p2m_mesh* mesh, p2m_mesh_qcsf** out, void* stream) {
+    int rc = check_mesh(mesh);
+    if (rc) return rc;
+    if (!out) {
+        set_error("out is NULL");
+        return P2M_EINVAL;
+    }
+    *out = nullptr;
+    auto* q = new (std::nothrow) p2m_mesh_qcsf();
+    if (!q) {
+        set_error("out of host memory");
+        return P2M_ENOMEM;
+    }
+    q->m = to_meshd(mesh);
+    q->E = mesh_edge_count(q->m);
+    rc = grow(&q->idx, q->E * MESH_SUP, 0);
+    if (!rc) rc = grow(&q->coef, q->E * MESH_SUP, 0);
+    if (!rc) rc = mesh_edge_table(q->m, q->idx, q->coef, static_cast<hipStream_t>(stream));
+    if (rc) {
+        p2m_mesh_qcsf_destroy(q);
+        return rc;
+    }
+    *out = q;
+    return P2M_OK;
+}
+
+int m2p_interpolate_qcsf(const p2m_mesh_qcsf* q, const void* mesh_vals, int C, int dtype, const double* pos,
+                         int64_t N, void* vals, void* stream) {
+    if (!q || !q->idx || !q->coef) {
+        set_error("invalid mesh-function handle");
+        return P2M_EINVAL;
+    }
+    int rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (!rc) rc = check_vals(vals, C, dtype, "vals", false);
+    if (rc) return rc;
+    if (!pos || !aligned(pos, 16) || N < 1 || N >= (int64_t(1) << 31)) {
+        set_error("pos is NULL/misaligned or N=%lld out of range", static_cast<long long>(N));
+        return P2M_EINVAL;
+    }
+    return m2p_qcsf(q->m, q->idx, q->coef, mesh_vals, C, dtype, pos, N, vals, static_cast<hipStream_t>(stream));
+}
+
+void p2m_mesh_qcsf_destroy(p2m_mesh_qcsf* q) {
+    if (!q) return;
+    if (q->idx) (void)hipFree(q->idx);
+    if (q->coef) (void)hipFree(q->coef);
+    delete q;
 }
 
 void p2m_weights_destroy(p2m_weights* w) {

@@ -81,6 +81,14 @@ int project_backward(const WeightsView& w, const void* grad_mesh, int C, int dty
                      void* grad_vals, double* grad_w, hipStream_t st);
 // sets == nullptr: one mesh m; else particles/nodes of set s start at
 // sets[s].p0 / sets[s].n0 and m is ignored.  n_nodes: all sets.
+// Mesh-side quadratically consistent functions: edge count and the table of
+// every mesh edge's support node ids and coefficients [E][MESH_SUP] (build.hip),
+// and M2P with them (m2p.hip).
+constexpr int MESH_SUP = 10;
+int64_t mesh_edge_count(const MeshD& m);
+int mesh_edge_table(const MeshD& m, int32_t* idx, double* coef, hipStream_t st);
+int m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void* mesh_vals, int C, int dtype,
+             const double* pos, int64_t N, void* vals, hipStream_t st);
 // One explicit midpoint step of every particle in the cellular flow of the
 // mesh box, clamped into the box (advect.hip).
 int advect_midpoint(const MeshD& m, double* pos, int64_t N, double amp, double dt, hipStream_t st);

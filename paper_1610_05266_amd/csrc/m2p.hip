@@ -118,6 +118,73 @@ void launch_m2p(const MeshOf& m, const void* mv, int C, const double* pos, int64
     }
 }
 
+// M2P with the mesh's quadratically consistent functions (App. B on the
+// mesh): the linear part above plus, for each edge (p, q) of the particle's
+// triangle, 2 phi_p phi_q times the edge's stencil of ten coefficients
+// (table row, computed once per mesh).  The triangle's edges in the order
+// (0,1), (1,2), (0,2): lower triangle horizontal (i,j), vertical (i+1,j),
+// diagonal (i,j); upper triangle diagonal (i,j), horizontal (i,j+1),
+// vertical (i,j).  One thread per particle.
+template <typename TM, typename TO, int CC>
+__global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __restrict__ eidx,
+                                                  const double* __restrict__ ecoef, const TM* __restrict__ mv,
+                                                  int Crt, const double2* __restrict__ pos, int64_t N,
+                                                  TO* __restrict__ out) {
+    constexpr int NC = CC > 0 ? CC : CMAX;
+    const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (mu >= N) return;
+    const int C = CC > 0 ? CC : Crt;
+    const Loc L = locate_cell(m, pos[mu]);
+    const int64_t s = m.nx + 1;
+    const int i = static_cast<int>(L.n0 % s), j = static_cast<int>(L.n0 / s);
+    const int64_t nh = static_cast<int64_t>(m.nx) * (m.ny + 1), nv = s * m.ny;
+    const int64_t eh = static_cast<int64_t>(j) * m.nx + i, ed = nh + nv + static_cast<int64_t>(j) * m.nx + i;
+    const int64_t e01 = L.lower ? eh : ed;
+    const int64_t e12 = L.lower ? nh + static_cast<int64_t>(j) * s + i + 1 : eh + m.nx;
+    const int64_t e02 = L.lower ? ed : nh + static_cast<int64_t>(j) * s + i;
+    const double c01 = 2.0 * L.w0 * L.w1, c12 = 2.0 * L.w1 * L.w2, c02 = 2.0 * L.w0 * L.w2;
+    TM acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        acc[c] = TM(0);
+        if (c < C)
+            acc[c] = static_cast<TM>(L.w0) * ldm(mv, L.n0 * C + c) + static_cast<TM>(L.w1) * ldm(mv, L.n1 * C + c) +
+                     static_cast<TM>(L.w2) * ldm(mv, L.n2 * C + c);
+    }
+    auto edge = [&](int64_t e, double ce) {
+#pragma unroll
+        for (int k = 0; k < MESH_SUP; ++k) {
+            const int64_t node = eidx[e * MESH_SUP + k];
+            const TM f = static_cast<TM>(ce * ecoef[e * MESH_SUP + k]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < C) acc[c] += f * ldm(mv, node * C + c);
+        }
+    };
+    edge(e01, c01);
+    edge(e12, c12);
+    edge(e02, c02);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (c < C) st(out, mu * C + c, L.ok ? acc[c] : static_cast<TM>(NAN));
+}
+
+template <typename TM, typename TO>
+void launch_m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void* mv, int C,
+                     const double* pos, int64_t N, void* out, hipStream_t s) {
+    const int blocks = static_cast<int>((N + 255) / 256);
+    const TM* M = static_cast<const TM*>(mv);
+    const double2* P = reinterpret_cast<const double2*>(pos);
+    TO* O = static_cast<TO*>(out);
+    switch (C) {
+        case 1: k_m2p_qcsf<TM, TO, 1><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        case 2: k_m2p_qcsf<TM, TO, 2><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        case 3: k_m2p_qcsf<TM, TO, 3><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        case 4: k_m2p_qcsf<TM, TO, 4><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        default: k_m2p_qcsf<TM, TO, 0><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+    }
+}
+
 // grad_mesh += phi_i(r_mu) g_mu (atomics); grad_pos[mu] += sum_c g_mu,c grad u_c
 template <typename TM>
 __global__ void __launch_bounds__(256) k_m2p_bwd(MeshOf mo, const TM* __restrict__ mv, int C,
@@ -172,6 +239,19 @@ int m2p(const MeshD& mesh, const SetDesc* sets, int S, int64_t n_nodes, const vo
         launch_m2p<float, float>(m, mesh_vals, C, pos, N, vals, st);
     else
         launch_m2p<float, uint16_t>(m, mesh_vals, C, pos, N, vals, st);
+    P2M_HIP(hipGetLastError());
+    return P2M_OK;
+}
+
+int m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void* mesh_vals, int C, int dtype,
+             const double* pos, int64_t N, void* vals, hipStream_t st) {
+    PhaseTimer _timer(PH_M2P, st);
+    if (dtype == P2M_F64)
+        launch_m2p_qcsf<double, double>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
+    else if (dtype == P2M_F32)
+        launch_m2p_qcsf<float, float>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
+    else
+        launch_m2p_qcsf<float, uint16_t>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }

@@ -36,6 +36,7 @@ __all__ = [
     "P2M_STRICT",
     "P2M_LINEAR",
     "p2m_advect",
+    "MeshQCSF",
     "kinematic_step",
 ]
 
@@ -191,6 +192,53 @@ def p2m_project(w: Weights, vals: torch.Tensor, out: Optional[torch.Tensor] = No
     with torch.cuda.device(vals.device):
         check(load().p2m_project(w.handle, _ptr(vals), C, code, _ptr(out), _stream(vals)))
     return out
+
+
+class MeshQCSF:
+    """Owner of a p2m_mesh_qcsf handle: the edge coefficients of one mesh's
+    quadratically consistent functions, computed once on ``device``."""
+
+    def __init__(self, mesh, device="cuda:0"):
+        self.mesh = Mesh.of(mesh)
+        self.device = torch.device(device)
+        self._h = ctypes.c_void_p(0)
+        cm = self.mesh.c()
+        with torch.cuda.device(self.device):
+            st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+            check(load().p2m_mesh_qcsf_create(ctypes.byref(cm), ctypes.byref(self._h), st))
+
+    def __del__(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            try:
+                load().p2m_mesh_qcsf_destroy(self._h)
+            except Exception:  # noqa: BLE001 - interpreter shutdown
+                pass
+            self._h = ctypes.c_void_p(0)
+
+    def interpolate(self, mesh_vals: torch.Tensor, pos: torch.Tensor, out: Optional[torch.Tensor] = None,
+                    bf16_out: bool = False) -> torch.Tensor:
+        """Eq. (m2p) with the mesh's quadratically consistent functions (C call
+        m2p_interpolate_qcsf): particle values [N, C]."""
+        mesh = self.mesh
+        _need(mesh_vals, "mesh_vals")
+        _need(pos, "pos", torch.float64)
+        if mesh_vals.dim() != 2 or mesh_vals.shape[0] != mesh.n_nodes:
+            raise ValueError(f"mesh_vals must have shape [{mesh.n_nodes}, C]")
+        C = mesh_vals.shape[1]
+        if mesh_vals.dtype == torch.float64:
+            code, odt = P2M_F64, torch.float64
+        elif mesh_vals.dtype == torch.float32:
+            code, odt = (P2M_BF16, torch.bfloat16) if bf16_out else (P2M_F32, torch.float32)
+        else:
+            raise ValueError("mesh_vals must be float64 or float32")
+        N = pos.shape[0]
+        if out is None:
+            out = torch.empty((N, C), dtype=odt, device=pos.device)
+        _need(out, "out", odt, (N, C))
+        with torch.cuda.device(pos.device):
+            check(load().m2p_interpolate_qcsf(self._h, _ptr(mesh_vals), C, code, _ptr(pos), N, _ptr(out),
+                                              _stream(pos)))
+        return out
 
 
 def p2m_advect(mesh, pos: torch.Tensor, amp: float, dt: float) -> torch.Tensor:
