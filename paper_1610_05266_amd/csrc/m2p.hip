@@ -143,6 +143,15 @@ __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __rest
     const int64_t e12 = L.lower ? nh + static_cast<int64_t>(j) * s + i + 1 : eh + m.nx;
     const int64_t e02 = L.lower ? ed : nh + static_cast<int64_t>(j) * s + i;
     const double c01 = 2.0 * L.w0 * L.w1, c12 = 2.0 * L.w1 * L.w2, c02 = 2.0 * L.w0 * L.w2;
+    // A cell at least one cell from the wall has complete supports on all
+    // three edges, whose coefficients then equal those of the same
+    // orientation at node (1, 1) (the construction is translation
+    // invariant): every such particle reads those three rows (the same
+    // addresses for all, cached) and shifts their node ids, instead of three
+    // rows of its own.
+    const bool inner = m.nx >= 3 && m.ny >= 3 && i >= 1 && j >= 1 && i + 2 <= m.nx && j + 2 <= m.ny;
+    const int64_t r11 = s + 1, rh = m.nx + 1, rv = nh + s + 1, rd = nh + nv + m.nx + 1;
+    const int64_t n00 = L.n0;
     TM acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -151,19 +160,23 @@ __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __rest
             acc[c] = static_cast<TM>(L.w0) * ldm(mv, L.n0 * C + c) + static_cast<TM>(L.w1) * ldm(mv, L.n1 * C + c) +
                      static_cast<TM>(L.w2) * ldm(mv, L.n2 * C + c);
     }
-    auto edge = [&](int64_t e, double ce) {
+    // edge e (first end node a) or, inside, its representative r
+    auto edge = [&](int64_t e, int64_t r, int64_t a, double ce) {
+        const int64_t row = inner ? r : e, shift = inner ? a - r11 : 0;
 #pragma unroll
         for (int k = 0; k < MESH_SUP; ++k) {
-            const int64_t node = eidx[e * MESH_SUP + k];
-            const TM f = static_cast<TM>(ce * ecoef[e * MESH_SUP + k]);
+            const int64_t node = eidx[row * MESH_SUP + k] + shift;
+            const TM f = static_cast<TM>(ce * ecoef[row * MESH_SUP + k]);
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 if (c < C) acc[c] += f * ldm(mv, node * C + c);
         }
     };
-    edge(e01, c01);
-    edge(e12, c12);
-    edge(e02, c02);
+    // lower: horizontal (i,j), vertical (i+1,j), diagonal (i,j);
+    // upper: diagonal (i,j), horizontal (i,j+1), vertical (i,j)
+    edge(e01, L.lower ? rh : rd, n00, c01);
+    edge(e12, L.lower ? rv : rh, L.lower ? n00 + 1 : n00 + s, c12);
+    edge(e02, L.lower ? rd : rv, n00, c02);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
         if (c < C) st(out, mu * C + c, L.ok ? acc[c] : static_cast<TM>(NAN));
