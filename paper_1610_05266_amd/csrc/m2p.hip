@@ -118,6 +118,14 @@ void launch_m2p(const MeshOf& m, const void* mv, int C, const double* pos, int64
     }
 }
 
+// Offsets (relative to an edge's first end) of the ten support slots of a
+// horizontal, vertical and diagonal edge, in the order of the edge table's
+// rows.
+constexpr int kSupOff[3][10][2] = {
+    {{-1, -1}, {-1, 0}, {0, -1}, {0, 0}, {0, 1}, {1, -1}, {1, 0}, {1, 1}, {2, 0}, {2, 1}},
+    {{-1, -1}, {-1, 0}, {-1, 1}, {0, -1}, {0, 0}, {0, 1}, {0, 2}, {1, 0}, {1, 1}, {1, 2}},
+    {{-1, -1}, {-1, 0}, {0, -1}, {0, 0}, {0, 1}, {1, 0}, {1, 1}, {1, 2}, {2, 1}, {2, 2}}};
+
 // M2P with the mesh's quadratically consistent functions (App. B on the
 // mesh): the linear part above plus, for each edge (p, q) of the particle's
 // triangle, 2 phi_p phi_q times the edge's stencil of ten coefficients
@@ -154,12 +162,56 @@ __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __rest
     const int64_t n00 = L.n0;
     TM acc[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        acc[c] = TM(0);
+    for (int c = 0; c < NC; ++c) acc[c] = TM(0);
+    if (inner) {
+        // the node weights on the 4 x 4 offsets (-1..2)^2 from node (i, j):
+        // linear part, then each edge's stencil at its place (lower: H at
+        // (0,0), V at (1,0), D at (0,0); upper: D at (0,0), H at (0,1), V at
+        // (0,0)), both triangles' placements written with the other's
+        // coefficients zero so that every index is a constant; then one
+        // gather per node (14 offsets can carry weight) instead of one per
+        // stencil entry
+        double g[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) g[k] = 0.0;
+        g[5] += L.w0;                       // (0,0)
+        g[6] += L.lower ? L.w1 : 0.0;       // (1,0)
+        g[10] += L.lower ? L.w2 : L.w1;     // (1,1)
+        g[9] += L.lower ? 0.0 : L.w2;       // (0,1)
+        const double cH0 = L.lower ? c01 : 0.0, cH1 = L.lower ? 0.0 : c12;
+        const double cV1 = L.lower ? c12 : 0.0, cV0 = L.lower ? 0.0 : c02;
+        const double cD = L.lower ? c02 : c01;
+        const double* rowH = ecoef + rh * MESH_SUP;
+        const double* rowV = ecoef + rv * MESH_SUP;
+        const double* rowD = ecoef + rd * MESH_SUP;
+#pragma unroll
+        for (int k = 0; k < MESH_SUP; ++k) {
+            const double aH = rowH[k], aV = rowV[k], aD = rowD[k];
+            g[(kSupOff[0][k][1] + 1) * 4 + kSupOff[0][k][0] + 1] += cH0 * aH;
+            g[(kSupOff[0][k][1] + 2) * 4 + kSupOff[0][k][0] + 1] += cH1 * aH;
+            g[(kSupOff[1][k][1] + 1) * 4 + kSupOff[1][k][0] + 2] += cV1 * aV;
+            g[(kSupOff[1][k][1] + 1) * 4 + kSupOff[1][k][0] + 1] += cV0 * aV;
+            g[(kSupOff[2][k][1] + 1) * 4 + kSupOff[2][k][0] + 1] += cD * aD;
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            if (k == 3 || k == 12) continue;  // offsets (2,-1) and (-1,2): never in a support
+            const int64_t node = n00 + static_cast<int64_t>(k / 4 - 1) * s + (k % 4 - 1);
+            const TM f = static_cast<TM>(g[k]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < C) acc[c] += f * ldm(mv, node * C + c);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < C) st(out, mu * C + c, L.ok ? acc[c] : static_cast<TM>(NAN));
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
         if (c < C)
             acc[c] = static_cast<TM>(L.w0) * ldm(mv, L.n0 * C + c) + static_cast<TM>(L.w1) * ldm(mv, L.n1 * C + c) +
                      static_cast<TM>(L.w2) * ldm(mv, L.n2 * C + c);
-    }
     // edge e (first end node a) or, inside, its representative r
     auto edge = [&](int64_t e, int64_t r, int64_t a, double ce) {
         const int64_t row = inner ? r : e, shift = inner ? a - r11 : 0;
