@@ -29,18 +29,23 @@
 // Near-ties of the FP64 predicates (|det| within a forward error bound) are
 // counted and broken by the user particle id.
 //
-// Execution: the FAST kernel gives each node a quad of four lanes that hold
-// the particles within a radius Rf of the node in registers, split
-// round-robin, so each gift-wrapping step is a short register loop plus a
-// two-step quad reduction; a decision is certified when its disk lies in the
-// disk of radius Rf around the node (boundary-ring nodes take their K nearest
-// particles, certified the same way).  A node that cannot be certified there
-// is appended to a list for the SLOW kernel on a side stream: one wave per
-// node scanning square bin regions that double in size up to all particles,
-// which then weights the row it found.  Meanwhile the WEIGHTS kernel (a quad
-// per node) turns every row of the fast pass into weights.  Both passes use
-// the same rows and the same weighting code, so the result of a node does
-// not depend on the pass that found its triangle.
+// Execution: the FAST kernel stages each 8 x 8-node tile's bin region in LDS
+// and gives each node a quad of four lanes holding the particles within a
+// radius Rf of the node as 16-bit indices into that region, dealt in turn
+// over the lanes, so each gift-wrapping step is a short loop over LDS
+// positions plus a two-step quad reduction; a decision is certified when its
+// disk lies in the disk of radius Rf around the node (boundary-ring nodes
+// take their K nearest particles, certified the same way).  A node that
+// cannot be certified there is appended to a list for the SLOW kernel on a
+// side stream: three waves per node, each running the same wedge and walk
+// and then the ring of one vertex, over square bin regions that double in
+// size up to all particles; the first wave merges the rings and weights the
+// row.  Meanwhile the WEIGHTS kernel (a quad per node) turns every row of the
+// fast pass into weights.  Both passes produce the same rows in the same
+// order and use the same weighting code, so the result of a node does not
+// depend on the pass that found its triangle.  With the linear option the
+// search stops at T and the row is phi alone.  The end of the file builds
+// the mesh-side counterpart: the coefficient table of every mesh edge.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
