@@ -22,6 +22,9 @@ project from particles onto a fixed mesh"):
 * The kinematic loop of the paper's transport tests (``advect``): particles
   moved by a prescribed velocity (explicit midpoint rule), their functions
   rebuilt, M2P and P2M every step.
+* P2M in the periodic box of the paper's runs (``periodic``): the Delaunay
+  triangulation of the cloud tiled by the box periods, the same construction
+  on image positions, no closure nodes.
 
 Library routines serve as steps where the paper itself used one: Qhull
 (scipy.spatial.Delaunay) for the Delaunay triangulation the paper built with
@@ -47,3 +50,4 @@ from .qcsf import (  # noqa: F401
     CLOSURE_K,
 )
 from .m2p import m2p_locate, m2p, m2p_matrix, m2p_grad_pos  # noqa: F401
+from .periodic import PeriodicP2MOracle  # noqa: F401

@@ -3,7 +3,8 @@
 The paper's fixed mesh has spacing H (Sec. 1, Fig. idea).  The oracle works on
 a bounded rectangle of (nx+1) x (ny+1) nodes at (x0 + i*H, y0 + j*H), node id
 k = j*(nx+1) + i.  (The paper's runs are periodic; the bounded rectangle is the
-reading taken for this build, periodic images are not formed.)
+default reading here, and ``periodic`` forms the periodic box on the same
+node layout.)
 """
 from __future__ import annotations
 

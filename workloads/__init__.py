@@ -244,6 +244,16 @@ def small_cloud(n: int, ratio: int, jitter: float, seed: int,
     return Cloud(f"small{n}x{ratio}", mesh, h, pos, _fields(pos, channels), channels)
 
 
+def periodic_tg_cloud(n: int, ratio: int, jitter: float, seed: int,
+                      channels: Tuple[str, ...] = ("u", "v", "p")) -> Cloud:
+    """The paper's periodic Taylor-Green box (Sec. 3.2): (-1, 1)^2, k = pi
+    (period 2 = the box), n x n cells, a (ratio*n)^2 jittered lattice."""
+    rng = np.random.default_rng(seed)
+    pos, h = jittered_lattice(ratio * n, jitter, rng, lo=-1.0, length=2.0)
+    mesh = MeshSpec(n, n, 2.0 / n, -1.0, -1.0)
+    return Cloud(f"periodic{n}x{ratio}", mesh, h, pos, _fields(pos, channels), channels)
+
+
 def cluster_void_cloud(n: int, N: int, seed: int,
                        channels: Tuple[str, ...] = ("u", "v", "q")) -> Cloud:
     """Conditioning stress input: Gaussian clusters plus a uniform background
