@@ -36,8 +36,9 @@ extern "C" {
 
 /* Fixed uniform mesh: (nx+1)*(ny+1) nodes at (x0 + i*H, y0 + j*H),
  * 0 <= i <= nx, 0 <= j <= ny.  H is the mesh spacing of the paper (Sec. 1,
- * Fig. idea).  The domain is bounded (the paper's periodic boxes are not
- * formed); particles must lie in [x0, x0+nx*H] x [y0, y0+ny*H]. */
+ * Fig. idea).  The domain is the bounded rectangle [x0, x0+nx*H] x
+ * [y0, y0+ny*H], where particles must lie, or with P2M_PERIODIC the periodic
+ * box of the paper's runs (same node layout; see that flag). */
 typedef struct p2m_mesh {
     int32_t nx, ny;
     double H;
@@ -69,6 +70,7 @@ typedef enum p2m_dtype {
 #define P2M_STRICT      0x2  /* rank-deficient systems make diag report EGEOM   */
 #define P2M_LINEAR      0x4  /* linear FE particle functions phi_mu at interior
                                 nodes instead of psi_mu (see p2m_build_weights) */
+#define P2M_PERIODIC    0x8  /* periodic box (see p2m_build_weights)            */
 
 /* Largest number of particles one node's weights may involve (ELL width). */
 #define P2M_MAX_SUPPORT 32
@@ -115,7 +117,7 @@ typedef struct p2m_weights p2m_weights;
  *         it sizes the binning grid; results do not depend on it.
  *  pos    device [N][2] FP64 particle positions (user order).
  *  N      number of particles, 3 <= N < 2^28.
- *  flags  P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR.  With P2M_LINEAR an
+ *  flags  P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR | P2M_PERIODIC.  With P2M_LINEAR an
  *         interior node's row is phi_mu alone (App. B: the linear FE functions
  *         of the particles' Delaunay triangulation, eqs. C0 and C1, i.e. the
  *         barycentric coordinates of the node in T, three entries; the
@@ -123,6 +125,17 @@ typedef struct p2m_weights p2m_weights;
  *         located as above, rings and solves are skipped.  Closure nodes keep
  *         their quadratic-moment weights.  Such a handle serves p2m_project
  *         and p2m_project_backward; p2m_build_weights_backward rejects it.
+ *         With P2M_PERIODIC the box [x0, x0+nx*H) x [y0, y0+ny*H) is periodic,
+ *         as in every run of the paper (Sec. 3; App. A: a periodic Delaunay
+ *         triangulation): the triangulation is that of the particles and
+ *         their images across the box sides, a particle enters a node's
+ *         weights at its image nearest to the node (the support positions of
+ *         eqs. A0-A2_2), and there are no closure nodes.  The node layout is
+ *         unchanged: node (nx, j) is node (0, j) and (i, ny) is (i, 0), and
+ *         their rows are equal; M2P needs no flag on that layout (mesh values
+ *         must repeat the first column and row).  Needs nx, ny >= 4; a node
+ *         whose triangles do not fit within about half a period fails
+ *         (EGEOM).  p2m_build_weights_backward rejects such a handle.
  *  w      in/out: *w == NULL allocates a new handle; a handle from an earlier
  *         call is reused (its buffers grow if needed; previous contents are
  *         overwritten, so no work may still be pending on them on another
@@ -249,7 +262,7 @@ int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int
  * handle was built from; geometry is recomputed, not stored).  The
  * combinatorial structure (triangles, rings, nearest sets) is held fixed.
  *  grad_pos  device [N][2] FP64, ACCUMULATED with atomic adds.
- * Errors: EINVAL also for a handle built with P2M_LINEAR.
+ * Errors: EINVAL also for a handle built with P2M_LINEAR or P2M_PERIODIC.
  */
 int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const double* grad_w,
                                double* grad_pos, void* stream);

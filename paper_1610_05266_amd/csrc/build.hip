@@ -73,6 +73,20 @@ __device__ __forceinline__ double orient(double2 p, double2 q, double2 r) {
     return (q.x - p.x) * (r.y - p.y) - (q.y - p.y) * (r.x - p.x);
 }
 
+// ------------------------------------------------------------ periodic box
+// With the periodic option the box [x0, x0 + nx H) x [y0, y0 + ny H) is a
+// torus: a particle enters every computation of a node as its image nearest
+// to the node (position plus a multiple of the period, one rounding per
+// coordinate), and node (nx, j) / (i, ny) is node (0, j) / (i, 0).
+__device__ __forceinline__ double2 image_near(const MeshD& m, double2 p, double2 q) {
+    const double Lx = mul_rn(static_cast<double>(m.nx), m.H), Ly = mul_rn(static_cast<double>(m.ny), m.H);
+    const double kx = rint((q.x - p.x) / Lx), ky = rint((q.y - p.y) / Ly);
+    return make_double2(add_rn(p.x, mul_rn(kx, Lx)), add_rn(p.y, mul_rn(ky, Ly)));
+}
+__device__ __forceinline__ double2 node_at(const MeshD& m, int i, int j, bool per) {
+    return per ? node_pos(m, i == m.nx ? 0 : i, j == m.ny ? 0 : j) : node_pos(m, i, j);
+}
+
 // ------------------------------------------------- candidate comparisons
 // Bisector key of candidate b for the edge v -> a on side sgn: the circumcentre
 // of (v, a, b) is v + A/2 + (num / 2cr) sgn perp(A), with A = a - v, B = b - v,
@@ -282,13 +296,66 @@ __device__ __forceinline__ double group_sum(double v) {
 
 // ------------------------------------------------ slow candidate source
 struct Region {
+    // bins [bx0, bx1) x [by0, by1); in a periodic box unwrapped (they may
+    // pass the box sides), each bin row then read as nseg runs of columns
     int bx0, bx1, by0, by1;
+    int nseg;
     double xlo, xhi, ylo, yhi;
     bool global;
+
+    __device__ int nrun() const { return (by1 - by0) * nseg; }
+    // run v: key of its bin row's first bin and its columns [c0, c1)
+    __device__ void run(const Grid& g, int v, int& base, int& c0, int& c1) const {
+        int by = by0 + (nseg == 1 ? v : v >> 1);
+        by += by < 0 ? g.nby : (by >= g.nby ? -g.nby : 0);
+        base = by * g.nbx;
+        c0 = bx0;
+        c1 = bx1;
+        if (nseg == 2) {
+            const bool first = (v & 1) == 0;
+            if (bx0 < 0) {
+                c0 = first ? bx0 + g.nbx : 0;
+                c1 = first ? g.nbx : bx1;
+            } else {
+                c0 = first ? bx0 : 0;
+                c1 = first ? g.nbx : bx1 - g.nbx;
+            }
+        }
+    }
 };
+
+// Periodic region: half-width hw bins around the node's bin corner, kept one
+// bin inside the half-period on every side so that the particles read in it
+// are the images nearest to the node; wider, every particle at its nearest
+// image, certified inside that largest window.
+__device__ Region make_region_periodic(const Grid& g, int cbx, int cby, int hw) {
+    Region R;
+    const double m = 1e-9 * g.bw;
+    const int hx = (g.nbx - 2) / 2, hy = (g.nby - 2) / 2;
+    R.global = hw > hx || hw > hy;
+    const int wx = R.global ? hx : hw, wy = R.global ? hy : hw;
+    R.xlo = g.x0 + (cbx - wx) * g.bw + m;
+    R.xhi = g.x0 + (cbx + wx) * g.bw - m;
+    R.ylo = g.y0 + (cby - wy) * g.bw + m;
+    R.yhi = g.y0 + (cby + wy) * g.bw - m;
+    if (R.global) {
+        R.bx0 = 0;
+        R.bx1 = g.nbx;
+        R.by0 = 0;
+        R.by1 = g.nby;
+    } else {
+        R.bx0 = cbx - hw;
+        R.bx1 = cbx + hw;
+        R.by0 = cby - hw;
+        R.by1 = cby + hw;
+    }
+    R.nseg = (R.bx0 < 0 || R.bx1 > g.nbx) ? 2 : 1;
+    return R;
+}
 
 __device__ Region make_region(const Grid& g, int cbx, int cby, int hw) {
     Region R;
+    R.nseg = 1;
     R.bx0 = max(cbx - hw, 0);
     R.bx1 = min(cbx + hw, g.nbx);
     R.by0 = max(cby - hw, 0);
@@ -309,12 +376,16 @@ __device__ Region make_region(const Grid& g, int cbx, int cby, int hw) {
 // they are dealt round-robin over the 64 lanes.
 constexpr int STAGE = 512;
 
+template <bool PER>
 struct WaveSource {
+    static constexpr bool per = PER;
     const double2* __restrict__ pos;
     const int32_t* __restrict__ perm;
     const int32_t* __restrict__ start;
     Grid g;
     Region R;
+    MeshD m;
+    double2 q;     // the node (periodic box: positions are its nearest images)
     int neardeg;
     int ring_mark;
     int lane;
@@ -328,26 +399,34 @@ struct WaveSource {
     double2 rp0, rp1;
     int rt0, rt1;
 
-    __device__ bool global() const { return R.global; }
+    // every particle was a candidate (a periodic box has no hull: its widest
+    // window answers only what it certifies)
+    __device__ bool global() const { return R.global && !per; }
     // near-tie count when the rings phase begins
     __device__ void mark_rings() { ring_mark = neardeg; }
-    __device__ double2 P(int t) const { return pos[t]; }
+    __device__ double2 at(int t) const {
+        const double2 p = pos[t];
+        return per ? image_near(m, p, q) : p;
+    }
+    __device__ double2 P(int t) const { return at(t); }
     __device__ bool certify(double cx, double cy, double r) const {
         r *= 1.0 + 1e-9;
         return cx - r >= R.xlo && cx + r <= R.xhi && cy - r >= R.ylo && cy + r <= R.yhi;
     }
     __device__ void set_region(const Region& reg) {
         R = reg;
-        // row lengths, one lane per row, 64 rows at a time
-        const int nrow = R.by1 - R.by0;
-        int total = 0, rs = 0, rpre = 0;  // this lane's row (first 64 rows): start, flat offset
+        // run lengths, one lane per run (a bin row, or a part of one that
+        // wraps), 64 runs at a time
+        const int nrow = R.nrun();
+        int total = 0, rs = 0, rpre = 0;  // this lane's run (first 64 runs): start, flat offset
         for (int r0 = 0; r0 < nrow; r0 += WAVE) {
             const int r = r0 + lane;
             int len = 0, s0 = 0;
             if (r < nrow) {
-                const int row = (R.by0 + r) * g.nbx;
-                s0 = start[row + R.bx0];
-                len = start[row + R.bx1] - s0;
+                int row, c0, c1;
+                R.run(g, r, row, c0, c1);
+                s0 = start[row + c0];
+                len = start[row + c1] - s0;
             }
             int inc = len;
 #pragma unroll
@@ -373,8 +452,8 @@ struct WaveSource {
             }
             rt0 = t0;
             rt1 = t1;
-            rp0 = pos[t0 >= 0 ? t0 : 0];
-            rp1 = pos[t1 >= 0 ? t1 : 0];
+            rp0 = at(t0 >= 0 ? t0 : 0);
+            rp1 = at(t1 >= 0 ? t1 : 0);
             nreg = total;
             ln = -1;
             return;
@@ -382,11 +461,12 @@ struct WaveSource {
         ln = total <= STAGE ? total : -1;
         if (ln < 0) return;
         int flat = 0;
-        for (int by = R.by0; by < R.by1; ++by) {
-            const int row = by * g.nbx;
-            const int s = start[row + R.bx0], e = start[row + R.bx1];
+        for (int v = 0; v < nrow; ++v) {
+            int row, c0, c1;
+            R.run(g, v, row, c0, c1);
+            const int s = start[row + c0], e = start[row + c1];
             for (int t = s + lane; t < e; t += WAVE) {
-                lp[flat + t - s] = pos[t];
+                lp[flat + t - s] = at(t);
                 lt[flat + t - s] = t;
             }
             flat += e - s;
@@ -407,10 +487,11 @@ struct WaveSource {
             return;
         }
         int flat = 0;
-        for (int by = R.by0; by < R.by1; ++by) {
-            const int row = by * g.nbx;
-            const int s = start[row + R.bx0], e = start[row + R.bx1];
-            for (int t = s + ((lane - flat) & (WAVE - 1)); t < e; t += WAVE) f(t, pos[t]);
+        for (int v = 0, nv = R.nrun(); v < nv; ++v) {
+            int row, c0, c1;
+            R.run(g, v, row, c0, c1);
+            const int s = start[row + c0], e = start[row + c1];
+            for (int t = s + ((lane - flat) & (WAVE - 1)); t < e; t += WAVE) f(t, at(t));
             flat += e - s;
         }
     }
@@ -1059,6 +1140,7 @@ struct KArgs {
     int32_t* tdiag;       // [n_slots / TILE_N][4] per-tile counts of k_weights
     unsigned long long* diag;
     int linear;           // interior rows: barycentric coordinates in T only
+    int per;              // periodic box: nearest images, no boundary ring
 };
 
 // The set of a node tile / of a row slot.
@@ -1073,9 +1155,10 @@ __device__ __forceinline__ uint32_t pending_type(uint32_t t) { return t == NT_OU
 // Interior weights of one node, computed by the four lanes of its quad.
 // The support entries come from `uget(k)` (sorted index | bits << 28); entry
 // k belongs to lane k % 4.
-template <class UGet>
-__device__ void quad_weights(const KArgs& a, int64_t slot, double2 q, UGet uget, int n, const int T[3], int lane,
-                             uint32_t flags) {
+template <bool PER, class UGet>
+__device__ void quad_weights(const KArgs& a, const MeshD& m, int64_t slot, double2 q, UGet uget, int n,
+                             const int T[3], int lane, uint32_t flags) {
+    auto img = [&](double2 p) { return PER ? image_near(m, p, q) : p; };
     int mt[MS];
     int mb[MS];
     double mx[MS], my[MS], mw[MS];
@@ -1089,12 +1172,12 @@ __device__ void quad_weights(const KArgs& a, int64_t slot, double2 q, UGet uget,
             const uint32_t e = static_cast<uint32_t>(uget(k));
             mt[s] = static_cast<int>(e & IDX_MASK);
             mb[s] = static_cast<int>(e >> 28);
-            const double2 p = a.pos_s[mt[s]];
+            const double2 p = img(a.pos_s[mt[s]]);
             mx[s] = p.x;
             my[s] = p.y;
         }
     }
-    const double2 P[3] = {a.pos_s[T[0]], a.pos_s[T[1]], a.pos_s[T[2]]};
+    const double2 P[3] = {img(a.pos_s[T[0]]), img(a.pos_s[T[1]]), img(a.pos_s[T[2]])};
     // barycentric coordinates of q in T (linear FE, eqs. C0, C1)
     const double D = orient(P[0], P[1], P[2]);
     const double phi[3] = {orient(q, P[1], P[2]) / D, orient(P[0], q, P[2]) / D, orient(P[0], P[1], q) / D};
@@ -1316,21 +1399,27 @@ k_build_fast(KArgs a) {
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
     const int slot = static_cast<int>(blockIdx.x) * TILE_N + ly * 8 + lx;  // < 2^31, checked on the host
     const int64_t nn = a.n_slots;
-    const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
+    const bool per = a.per != 0;
+    const bool ring = !per && (i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny);
     const int32_t* start = a.start + sd.b0;
     bool done = false;
     // ---- stage the region (block-uniform decision): it covers the window
     // of every node of the tile, interior, edge or corner
     const int hcor = static_cast<int>(ceil(sd.Rc * 1.4142135623730951 / sd.g.bw));
     const bool xedge = tx == 0 || tx * 8 + 7 >= sd.m.nx, yedge = ty == 0 || ty * 8 + 7 >= sd.m.ny;
-    const int hmax = (xedge && yedge) ? max(max(sd.hwf, sd.hwc), hcor)
-                                      : (xedge || yedge) ? max(sd.hwf, sd.hwc) : sd.hwf;
-    const int rbx0 = max(tx * 8 * sd.g.kb - hmax, 0);
-    const int rbx1 = min(min(tx * 8 + 7, sd.m.nx) * sd.g.kb + hmax, sd.g.nbx);
-    const int rby0 = max(ty * 8 * sd.g.kb - hmax, 0);
-    const int rby1 = min(min(ty * 8 + 7, sd.m.ny) * sd.g.kb + hmax, sd.g.nby);
+    const int hmax = per ? sd.hwf
+                         : (xedge && yedge) ? max(max(sd.hwf, sd.hwc), hcor)
+                                            : (xedge || yedge) ? max(sd.hwf, sd.hwc) : sd.hwf;
+    const int ubx0 = tx * 8 * sd.g.kb - hmax, ubx1 = min(tx * 8 + 7, sd.m.nx) * sd.g.kb + hmax;
+    const int uby0 = ty * 8 * sd.g.kb - hmax, uby1 = min(ty * 8 + 7, sd.m.ny) * sd.g.kb + hmax;
+    const int rbx0 = max(ubx0, 0), rbx1 = min(ubx1, sd.g.nbx);
+    const int rby0 = max(uby0, 0), rby1 = min(uby1, sd.g.nby);
     const int ncol = rbx1 - rbx0, nrow = rby1 - rby0;
-    bool staged = ncol <= TDIM && nrow <= TDIM;
+    // in a periodic box only a tile whose windows stay a bin inside the box
+    // sides runs here (its particles are then every node's nearest images);
+    // the others take the exact path, whose regions wrap
+    bool staged = ncol <= TDIM && nrow <= TDIM &&
+                  (!per || (ubx0 >= 1 && ubx1 <= sd.g.nbx - 1 && uby0 >= 1 && uby1 <= sd.g.nby - 1));
     if (staged) {
         for (int e = threadIdx.x; e < nrow * (ncol + 1); e += QWG) {
             const int r = e / (ncol + 1), c = e - r * (ncol + 1);
@@ -1398,7 +1487,7 @@ k_build_fast(KArgs a) {
     // a region too large to stage leaves its nodes to the exact path
     int ovf = staged ? 0 : 1;
     if (valid && staged) {
-        g.q = node_pos(sd.m, i, j);
+        g.q = node_at(sd.m, i, j, per);
         // a corner node sees a quarter disk, an edge node a half disk: the
         // corner radius is sqrt(2) larger for the same expected count
         const bool corner = (i == 0 || i == sd.m.nx) && (j == 0 || j == sd.m.ny);
@@ -1559,7 +1648,7 @@ enum { WC_INTERIOR, WC_CLOSURE, WC_OUTSIDE, WC_SUPMAX };
 // row's systems, identically, and they split the final pass over the support
 // entries (quad sub takes entries sub, sub + QS, ...), whose weights do not
 // depend on one another, so the row is the same bit for bit for any QS.
-template <int QS = 1>
+template <bool PER, int QS = 1>
 __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc& sd, int i, int j, bool valid,
                                                    int64_t slot, int lane, int qi, double2* sp, uint32_t* se,
                                                    int32_t* su, bool escalated_rows, int sub = 0) {
@@ -1570,6 +1659,8 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
     const int n = static_cast<int>(meta_cnt(meta));
     const bool pend = type == NT_PENDING;
     const bool clos = type == NT_PEND_RING || type == NT_PEND_OUT;
+    const double2 q = node_at(sd.m, i, j, PER);
+    auto img = [&](double2 p) { return PER ? image_near(sd.m, p, q) : p; };
     // stage the support: entry (sorted index | ring bits << 28), position and
     // user id.  The loads are unconditional, so that all of them are issued
     // before any is waited for: entries past the row (k < SK <= KMAX stays
@@ -1589,7 +1680,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
         int32_t uu[SS];
 #pragma unroll
         for (int s = 0; s < SS; ++s) {
-            pp[s] = a.pos_s[e[s] & IDX_MASK];
+            pp[s] = img(a.pos_s[e[s] & IDX_MASK]);
             uu[s] = a.perm[e[s] & IDX_MASK];
         }
 #pragma unroll
@@ -1615,14 +1706,13 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
         for (int k = SK; k < n; ++k) {
             const uint32_t e = static_cast<uint32_t>(a.out.idx[k * nn + slot]) |
                                (static_cast<uint32_t>(a.out.mem[k * nn + slot]) << 28);
-            f(k, e, a.pos_s[e & IDX_MASK], a.perm[e & IDX_MASK]);
+            f(k, e, img(a.pos_s[e & IDX_MASK]), a.perm[e & IDX_MASK]);
         }
     };
     auto P = [&](int k) -> double2 {
         if (k < SK) return sp[qi * SKP + k];
-        return a.pos_s[a.out.idx[k * nn + slot]];
+        return img(a.pos_s[a.out.idx[k * nn + slot]]);
     };
-    const double2 q = node_pos(sd.m, i, j);
     int ok = 1;
     double y[6] = {0, 0, 0, 0, 0, 0};
     // edge / closure frame: x~ = (p - c) * s
@@ -1749,7 +1839,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
             for (int k = SK + sub; k < n; k += QS) {
                 const uint32_t e = static_cast<uint32_t>(a.out.idx[k * nn + slot]) |
                                    (static_cast<uint32_t>(a.out.mem[k * nn + slot]) << 28);
-                f(k, e, a.pos_s[e & IDX_MASK], a.perm[e & IDX_MASK]);
+                f(k, e, img(a.pos_s[e & IDX_MASK]), a.perm[e & IDX_MASK]);
             }
         };
         each_sub([&](int k, uint32_t e, double2 p, int32_t u) {
@@ -1800,6 +1890,7 @@ __device__ __forceinline__ void count_wave(const KArgs& a, const WaveCounts& wc)
 // over square bin regions that double in half-width up to every particle;
 // interior nodes leave their support in the ELL row, closure nodes (ring, or
 // outside the hull) their nearest particles; k_weights does the rest.
+template <bool PER>
 __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     constexpr int WPB = SWG / WAVE;
     static_assert(WPB == 3, "one wave per ring");
@@ -1832,14 +1923,17 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         const int big = max(sd.g.nbx, sd.g.nby) + 1;
         int i, j;
         slot_ij(sd, slot, i, j);
-        const double2 q = node_pos(sd.m, i, j);
-        const bool ring = i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny;
-        const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
-        WaveSource c;
+        constexpr bool per = PER;
+        const double2 q = node_at(sd.m, i, j, per);
+        const bool ring = !per && (i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny);
+        const int cbx = (per && i == sd.m.nx ? 0 : i) * sd.g.kb, cby = (per && j == sd.m.ny ? 0 : j) * sd.g.kb;
+        WaveSource<PER> c;
         c.pos = a.pos_s;
         c.perm = a.perm;
         c.start = a.start + sd.b0;
         c.g = sd.g;
+        c.m = sd.m;
+        c.q = q;
         c.neardeg = 0;
         c.ring_mark = 0;
         c.lane = lane;
@@ -1859,7 +1953,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             // wave k finds the triangle and then the ring of its vertex k
             for (int level = 0;; ++level) {
                 const int hw = level < a.levels ? (sd.hw0 << level) : big;
-                c.set_region(make_region(sd.g, cbx, cby, hw));
+                c.set_region(per ? make_region_periodic(sd.g, cbx, cby, hw) : make_region(sd.g, cbx, cby, hw));
                 S.n = 0;
                 const int sk = delaunay_node(c, q, T, S, svis + wv * KMAX, a.linear ? -2 : wv);
                 if (lane < S.n) sring[wv][lane] = S.e;
@@ -1926,7 +2020,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             int kk = 0;
             for (int level = 0;; ++level) {
                 const int hw = level < a.levels ? (sd.hw0 << level) : big;
-                c.set_region(make_region(sd.g, cbx, cby, hw));
+                c.set_region(per ? make_region_periodic(sd.g, cbx, cby, hw) : make_region(sd.g, cbx, cby, hw));
                 kk = 0;
                 double pd = -1.0;
                 int pu = -1;
@@ -1989,13 +2083,14 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         // every quad of the wave computes the row's systems; they share
         // its final pass
-        count_wave(a, weights_node<WAVE / QL>(a, sd, i, j, true, slot, lane & (QL - 1), lane / QL, wsp, wse, wsu,
+        count_wave(a, weights_node<PER, WAVE / QL>(a, sd, i, j, true, slot, lane & (QL - 1), lane / QL, wsp, wse, wsu,
                                               true, lane / QL));
     }
 }
 
 // Weights of the fast path's pending rows, one quad per node, nodes in the
 // same 8 x 8 tiles as the fast kernel.
+template <bool PER>
 __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     __shared__ double2 sp[QPB * SKP];
     __shared__ uint32_t se[QPB * SKP];
@@ -2009,7 +2104,7 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
     const int64_t slot = static_cast<int64_t>(blockIdx.x) * TILE_N + qi;
-    const WaveCounts wc = weights_node(a, sd, i, j, valid, slot, lane, qi, sp, se, su, false);
+    const WaveCounts wc = weights_node<PER>(a, sd, i, j, valid, slot, lane, qi, sp, se, su, false);
     // the tile's counts as one plain record, folded into the diagnostics by
     // k_weights_rd: device-wide atomics from every wave on the same few
     // counters serialise at their memory partition and stall the pass
@@ -2027,6 +2122,7 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
 // Nodes whose moment systems are rank-deficient (listed by k_weights): the
 // minimum-norm solution through the pseudo-inverse, one quad per node.  Block
 // 0 first folds k_weights' per-tile counts into the diagnostics.
+template <bool PER>
 __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
     if (blockIdx.x == 0) {
         unsigned long long v[4] = {0, 0, 0, 0};
@@ -2070,7 +2166,7 @@ __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
                 return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + slot]) |
                                             (static_cast<uint32_t>(a.out.mem[k * nn + slot]) << 28));
             };
-            quad_weights(a, slot, node_pos(sd.m, i, j), uget, n, T, lane, meta_flags(meta));
+            quad_weights<PER>(a, sd.m, slot, node_at(sd.m, i, j, PER), uget, n, T, lane, meta_flags(meta));
         } else {
             quad_closure(a, slot, node_pos(sd.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
                          meta_flags(meta));
@@ -2153,7 +2249,8 @@ __global__ void __launch_bounds__(64) k_mesh_edges(MeshD m, int64_t E, int32_t* 
 
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
                   const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,
-                  unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear) {
+                  unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear,
+                  bool periodic) {
     PhaseTimer _timer(PH_BUILD, st);
     // row slots are listed as int32
     if (n_tiles * TILE_N >= (int64_t(1) << 31)) {
@@ -2175,6 +2272,7 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     a.tdiag = tdiag;
     a.diag = diag;
     a.linear = linear ? 1 : 0;
+    a.per = periodic ? 1 : 0;
     const int tiles = static_cast<int>(n_tiles);
     {
         PhaseTimer t1(PH_BUILD_FAST, st);
@@ -2197,16 +2295,21 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         // the blocks past the list leave at once
         const int64_t expect = n_nodes / 64 + 64 * static_cast<int64_t>(S);
         const int gs = static_cast<int>(std::min<int64_t>(expect, 4096));
-        k_slow_geom<<<gs, SWG, 0, side.stream>>>(a);
+        if (periodic) k_slow_geom<true><<<gs, SWG, 0, side.stream>>>(a);
+        else k_slow_geom<false><<<gs, SWG, 0, side.stream>>>(a);
     }
     P2M_HIP(hipGetLastError());
     P2M_HIP(hipEventRecord(side.join, side.stream));
     {
         PhaseTimer t3(PH_WEIGHTS, st);
-        k_weights<<<tiles, QWG, 0, st>>>(a);
+        // (one weighting code for both passes, so that a row does not depend
+        // on the pass that found it)
+        if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
+        else k_weights<false><<<tiles, QWG, 0, st>>>(a);
         P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
         // rank-deficient nodes of either pass (normally none)
-        k_weights_rd<<<16, QWG, 0, st>>>(a);
+        if (periodic) k_weights_rd<true><<<16, QWG, 0, st>>>(a);
+        else k_weights_rd<false><<<16, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());
     return P2M_OK;

@@ -283,10 +283,16 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
         set_error("output handle pointer is NULL");
         return P2M_EINVAL;
     }
-    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR)) {
+    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR | P2M_PERIODIC)) {
         set_error("unknown flags 0x%x", flags);
         return P2M_EINVAL;
     }
+    if (flags & P2M_PERIODIC)
+        for (const SetDesc& d : sets)
+            if (d.m.nx < 4 || d.m.ny < 4) {
+                set_error("a periodic box needs at least 4 cells per side (nx=%d ny=%d)", d.m.nx, d.m.ny);
+                return P2M_EINVAL;
+            }
     int nch = 0, sbs = 0, nsb = 0;
     int rc = bin_layout(tot.N, tot.nbins, &nch, &sbs, &nsb);
     if (rc) return rc;
@@ -374,7 +380,8 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     rc = side_stream(dev, &side.stream);
     if (rc) return rc;
     return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, fast_slots(), w->slow,
-                         w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0);
+                         w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0,
+                         (flags & P2M_PERIODIC) != 0);
 }
 
 // Per-device workspace of the fused (recompute) entry points: a weights
@@ -715,8 +722,8 @@ int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const do
         set_error("pos / grad_w / grad_pos NULL or misaligned");
         return P2M_EINVAL;
     }
-    if (w->flags & P2M_LINEAR) {
-        set_error("weights built with P2M_LINEAR: position gradients are not provided");
+    if (w->flags & (P2M_LINEAR | P2M_PERIODIC)) {
+        set_error("weights built with P2M_LINEAR or P2M_PERIODIC: position gradients are not provided");
         return P2M_EINVAL;
     }
     return build_backward(view(w), pos, grad_w, grad_pos, static_cast<hipStream_t>(stream));

@@ -73,7 +73,8 @@ int side_stream(int device, hipStream_t* out);
 // linear: interior rows are the triangle's barycentric coordinates alone.
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
                   const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,
-                  unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear);
+                  unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear,
+                  bool periodic);
 
 // ---- projection and interpolation (project.hip, m2p.hip) ----
 int project(const WeightsView& w, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st);
