@@ -310,7 +310,8 @@ def main(argv=None):
     log(f"cached weights: mixed {cms32:.4f} ms, FP64 {cms64:.4f} ms per round trip")
     torch.cuda.synchronize()
 
-    lms32 = kms32 = qms32 = qsetup = None
+    lms32 = kms32 = qms32 = qsetup = pms32 = None
+    pdiag = {}
     kdiag, ktuning = {}, None
     if not a.no_extras:
         # M2P with the mesh's quadratically consistent functions (FP32), on the
@@ -356,6 +357,33 @@ def main(argv=None):
                 run_lin = step_linear
         lms32 = time_loop(run_lin)
         log(f"linear FE round trip (mixed) {lms32:.4f} ms")
+
+        # the same round trip in the paper's periodic box: (-1, 1)^2, k = pi,
+        # the same mesh and lattice sizes, weights rebuilt every step
+        pcl = wl.periodic_tg_cloud(mesh.nx, 4, 0.30, seed=2)
+        ppos = torch.from_numpy(pcl.pos).to(dev)
+        pv32 = torch.from_numpy(pcl.vals).to(dev, torch.float32)
+        pflags = P2M_WEIGHTS_F32 | ops.P2M_PERIODIC
+        wper = ops.p2m_build_weights(pcl.mesh, pcl.h, ppos, pflags, check_diag=True)
+        pmesh32 = torch.empty((pcl.mesh.n_nodes, pv32.shape[1]), dtype=torch.float32, device=dev)
+        pout32 = torch.empty_like(pv32)
+
+        def step_periodic():
+            ops.p2m_build_weights(pcl.mesh, pcl.h, ppos, pflags, weights=wper, check_diag=False)
+            ops.p2m_project(wper, pv32, out=pmesh32)
+            ops.m2p_interpolate(pcl.mesh, pmesh32, ppos, out=pout32)
+
+        run_per = as_graph(step_periodic)
+        if run_per is not step_periodic:
+            try:
+                check_replay(run_per, step_periodic, [pmesh32, pout32])
+            except RuntimeError as exc:
+                graph_notes.append(f"{exc}; eager launches timed")
+                run_per = step_periodic
+        pms32 = time_loop(run_per)
+        pdiag = wper.diag(check_status=False)
+        log(f"periodic round trip (mixed) {pms32:.4f} ms, diag {pdiag}")
+        del wper, ppos, pv32, pmesh32, pout32
 
         # one step of the kinematic projection loop (mixed form): particle values
         # from the mesh, the particles moved one midpoint step in the cellular flow
@@ -506,6 +534,14 @@ def main(argv=None):
                               "(P2M_LINEAR: the node's particle triangle located, rings and solves skipped), "
                               "mixed form, weights rebuilt every step",
                       "ms_per_step": round(lms32, 5), "Mparticles_per_s": round(N / (lms32 * 1e-3) / 1e6, 3)},
+        "periodic": None if pms32 is None else {
+            "note": "the round trip in the paper's periodic box (-1, 1)^2 with k = pi (P2M_PERIODIC): the same "
+                    "mesh and lattice sizes (256x256 cells, 1024x1024 jittered lattice, h=H/4, jitter 0.3h, "
+                    "seed 2), mixed form, weights rebuilt every step; nodes whose search window reaches a box "
+                    "side take the exact path",
+            "ms_per_step": round(pms32, 5), "Mparticles_per_s": round(N / (pms32 * 1e-3) / 1e6, 3),
+            "slow_nodes": int(pdiag["slow_nodes"]), "failed_nodes": int(pdiag["failed_nodes"]),
+            "closure_nodes": int(pdiag["closure_nodes"])},
         "launch": "eager" if (a.no_graph or graph_notes) else "HIP graph replay of the whole step",
         "launch_notes": graph_notes,
         "tuning": tuning,

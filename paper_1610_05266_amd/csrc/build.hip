@@ -1410,16 +1410,12 @@ k_build_fast(KArgs a) {
     const int hmax = per ? sd.hwf
                          : (xedge && yedge) ? max(max(sd.hwf, sd.hwc), hcor)
                                             : (xedge || yedge) ? max(sd.hwf, sd.hwc) : sd.hwf;
-    const int ubx0 = tx * 8 * sd.g.kb - hmax, ubx1 = min(tx * 8 + 7, sd.m.nx) * sd.g.kb + hmax;
-    const int uby0 = ty * 8 * sd.g.kb - hmax, uby1 = min(ty * 8 + 7, sd.m.ny) * sd.g.kb + hmax;
-    const int rbx0 = max(ubx0, 0), rbx1 = min(ubx1, sd.g.nbx);
-    const int rby0 = max(uby0, 0), rby1 = min(uby1, sd.g.nby);
+    const int rbx0 = max(tx * 8 * sd.g.kb - hmax, 0);
+    const int rbx1 = min(min(tx * 8 + 7, sd.m.nx) * sd.g.kb + hmax, sd.g.nbx);
+    const int rby0 = max(ty * 8 * sd.g.kb - hmax, 0);
+    const int rby1 = min(min(ty * 8 + 7, sd.m.ny) * sd.g.kb + hmax, sd.g.nby);
     const int ncol = rbx1 - rbx0, nrow = rby1 - rby0;
-    // in a periodic box only a tile whose windows stay a bin inside the box
-    // sides runs here (its particles are then every node's nearest images);
-    // the others take the exact path, whose regions wrap
-    bool staged = ncol <= TDIM && nrow <= TDIM &&
-                  (!per || (ubx0 >= 1 && ubx1 <= sd.g.nbx - 1 && uby0 >= 1 && uby1 <= sd.g.nby - 1));
+    bool staged = ncol <= TDIM && nrow <= TDIM;
     if (staged) {
         for (int e = threadIdx.x; e < nrow * (ncol + 1); e += QWG) {
             const int r = e / (ncol + 1), c = e - r * (ncol + 1);
@@ -1501,6 +1497,11 @@ k_build_fast(KArgs a) {
         const int cbx = i * sd.g.kb, cby = j * sd.g.kb;
         const int bx0 = max(cbx - hw, 0), bx1 = min(cbx + hw, sd.g.nbx);
         const int by0 = max(cby - hw, 0), by1 = min(cby + hw, sd.g.nby);
+        // in a periodic box a node runs here only when its window stays a bin
+        // inside the box sides (its particles are then their own nearest
+        // images and no image lies in the window); the others take the exact
+        // path, whose regions wrap
+        if (per && (cbx - hw < 1 || cbx + hw > sd.g.nbx - 1 || cby - hw < 1 || cby + hw > sd.g.nby - 1)) ovf = 1;
         int acc = 0;  // particles accepted so far (the same in the four lanes)
         auto insert = [&](int t) {
             if (g.n >= NS) {
@@ -1538,7 +1539,7 @@ k_build_fast(KArgs a) {
                 acc += c;
             }
         };
-        for (int by = by0; by < by1; ++by) {
+        for (int by = by0; by < (ovf ? by0 : by1); ++by) {
             const int* rs = tst + (by - rby0) * (TDIM + 1);
             const int base = trb[by - rby0] - rs[0];
             segment(base + rs[bx0 - rbx0], base + rs[bx1 - rbx0]);

@@ -50,8 +50,8 @@ def small():
 
 @pytest.fixture(scope="module")
 def medium():
-    # 64 x 64 cells: interior tiles take the fast pass, the tiles at the box
-    # sides the exact path with regions that wrap
+    # 64 x 64 cells: most nodes take the fast pass, those whose search window
+    # reaches a box side the exact path, whose regions wrap
     return _case(64, 2, 0.3, 12)
 
 
@@ -157,3 +157,64 @@ def test_periodic_rejections():
     small = wl.MeshSpec(3, 3, 2.0 / 3, -1.0, -1.0)
     with pytest.raises(ops.P2MError):
         ops.p2m_build_weights(small, c.h, pos, ops.P2M_PERIODIC)
+
+
+@pytest.fixture(scope="module")
+def full():
+    # the benchmark's periodic workload: 256 x 256 cells on (-1, 1)^2, a
+    # 1024 x 1024 jittered lattice (h = H/4, jitter 0.3h, seed 2)
+    c = wl.periodic_tg_cloud(256, 4, 0.30, 2)
+    pos = _gpu(c.pos)
+    print(f"[gpu] periodic build {c.name} N={c.N}", flush=True)
+    w = ops.p2m_build_weights(c.mesh, c.h, pos, ops.P2M_PERIODIC)
+    return c, pos, w
+
+
+def test_periodic_full_size_consistency(full):
+    """Eqs. C0, C1, C2 at every node in minimum-image offsets (a wrong image
+    is off by a period, 256 mesh spacings)."""
+    c, pos, w = full
+    d = w.diag()
+    assert d["failed_nodes"] == 0 and d["closure_nodes"] == 0 and d["interior_nodes"] == c.mesh.n_nodes
+    idx, wt, cnt, tri = (t.numpy() for t in w.export())
+    m = OMesh.from_spec(c.mesh)
+    from oracle.periodic import wrapped_nodes
+    nodes = wrapped_nodes(m)
+    L = np.array([m.nx * m.H, m.ny * m.H])
+    valid = np.arange(idx.shape[0])[:, None] < cnt[None, :]
+    P = c.pos[np.where(valid, idx, 0)]
+    off = P - nodes[None]
+    off -= L * np.rint(off / L)
+    s = off / m.H
+    ww = np.where(valid, wt, 0.0)
+    assert np.abs(ww.sum(0) - 1.0).max() < 1e-12
+    assert np.abs(np.einsum("kn,kna->na", ww, s)).max() < 1e-10
+    assert np.abs(np.einsum("kn,kna,knb->nab", ww, s, s)).max() < 1e-10
+
+
+def test_periodic_full_size_sampled_oracle_rows(full):
+    """Sampled nodes (box corners and sides among them) against the oracle's
+    certified local triangulation of the cloud translated by half a period,
+    which puts the node far from every side of the bounded box."""
+    from oracle import P2MOracle
+    c, pos, w = full
+    idx, wt, cnt, tri = (t.numpy() for t in w.export())
+    m = OMesh.from_spec(c.mesh)
+    L = m.nx * m.H
+    shifted = c.pos + L / 2
+    shifted[shifted >= m.x0 + L] -= L
+    orc = P2MOracle(shifted, m, c.h, mode="local")
+    rng = np.random.default_rng(5)
+    # (translated by half a period, nodes near the middle of the box would
+    # land next to the bounded box's sides: they are not sampled)
+    ij = [(0, 0), (1, 0), (0, 1), (255, 255), (256, 3), (7, 256), (256, 256), (100, 0), (0, 200)]
+    ij += [tuple(v) for v in rng.integers(0, 257, size=(40, 2)) if min(abs(v % 256 - 128)) > 10][:12]
+    n1 = m.nx + 1
+    ks = [j * n1 + i for i, j in ij]
+    kshift = [((j % m.ny + m.ny // 2) % m.ny) * n1 + (i % m.nx + m.nx // 2) % m.nx for i, j in ij]
+    cols, vals, _ = orc.node_weights(np.asarray(kshift))
+    for k, cc, vv in zip(ks, cols, vals):
+        n = cnt[k]
+        got = dict(zip(idx[:n, k].tolist(), wt[:n, k].tolist()))
+        assert sorted(got) == sorted(cc.tolist()), k
+        assert max(abs(got[u] - x) for u, x in zip(cc.tolist(), vv.tolist())) < 1e-11, k
