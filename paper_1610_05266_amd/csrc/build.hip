@@ -1616,11 +1616,14 @@ k_build_fast(KArgs a) {
     }
     if (!valid && lane == 0) a.out.meta[slot] = meta_pack(NT_FAILED, 0, 0, 0, 0, 0u);  // beyond the mesh
     if (valid && !done && lane == 0) {
-        // an empty row until the slow path writes it, so that no node is ever
-        // left with the metadata of an earlier build (or of fresh memory)
+        // an empty row until the slow path (or, for a periodic box's seam
+        // node, k_seam_copy) writes it, so that no node is ever left with the
+        // metadata of an earlier build (or of fresh memory)
         a.out.meta[slot] = meta_pack(NT_FAILED, 0, 0, 0, 0, 0u);
-        const int lpos = static_cast<int>(atomicAdd(&a.diag[D_SLOWCNT], 1ull));
-        a.slow[lpos] = static_cast<int32_t>(slot);
+        if (!(per && (i == sd.m.nx || j == sd.m.ny))) {
+            const int lpos = static_cast<int>(atomicAdd(&a.diag[D_SLOWCNT], 1ull));
+            a.slow[lpos] = static_cast<int32_t>(slot);
+        }
     }
 }
 
@@ -2246,6 +2249,36 @@ __global__ void __launch_bounds__(64) k_mesh_edges(MeshD m, int64_t E, int32_t* 
     }
 }
 
+// Periodic box: the seam nodes (nx, j) and (i, ny) are nodes (0, j) and
+// (i, 0).  The passes above skip them; their rows are copied here once the
+// rows they repeat are weighted (both passes and the pseudo-inverse pass).
+// A quad per node slot, in the node tiles of the other passes.
+__global__ void __launch_bounds__(QWG) k_seam_copy(KArgs a) {
+    const SetDesc sd = tile_set(a, blockIdx.x);
+    int tx, ty;
+    tile_xy(sd, static_cast<int>(blockIdx.x - sd.t0), tx, ty);
+    if (tx * 8 + 7 < sd.m.nx && ty * 8 + 7 < sd.m.ny) return;  // no seam node in the tile
+    const int lane = threadIdx.x & (QL - 1), qi = threadIdx.x / QL;
+    const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
+    if (i > sd.m.nx || j > sd.m.ny || (i != sd.m.nx && j != sd.m.ny)) return;
+    const int64_t nn = a.n_slots;
+    const int64_t dst = static_cast<int64_t>(blockIdx.x) * TILE_N + (qi >> 3) * 8 + (qi & 7);
+    const int64_t src = node_slot(sd, i == sd.m.nx ? 0 : i, j == sd.m.ny ? 0 : j);
+    for (int k = lane; k < KMAX; k += QL) {
+        a.out.idx[k * nn + dst] = a.out.idx[k * nn + src];
+        a.out.mem[k * nn + dst] = a.out.mem[k * nn + src];
+        a.out.w64[k * nn + dst] = a.out.w64[k * nn + src];
+        if (a.out.w32) a.out.w32[k * nn + dst] = a.out.w32[k * nn + src];
+    }
+    if (lane == 0) {
+        const uint32_t meta = a.out.meta[src];
+        a.out.meta[dst] = meta;
+        if (meta_type(meta) == NT_INTERIOR) atomicAdd(&a.diag[D_INTERIOR], 1ull);
+        if (meta_flags(meta) & MF_RANKDEF) atomicAdd(&a.diag[D_RANKDEF], 1ull);
+        if (meta_type(meta) == NT_FAILED) atomicAdd(&a.diag[D_FAILED], 1ull);
+    }
+}
+
 }  // namespace
 
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
@@ -2311,6 +2344,7 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         // rank-deficient nodes of either pass (normally none)
         if (periodic) k_weights_rd<true><<<16, QWG, 0, st>>>(a);
         else k_weights_rd<false><<<16, QWG, 0, st>>>(a);
+        if (periodic) k_seam_copy<<<tiles, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());
     return P2M_OK;

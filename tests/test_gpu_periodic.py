@@ -218,3 +218,19 @@ def test_periodic_full_size_sampled_oracle_rows(full):
         got = dict(zip(idx[:n, k].tolist(), wt[:n, k].tolist()))
         assert sorted(got) == sorted(cc.tolist()), k
         assert max(abs(got[u] - x) for u, x in zip(cc.tolist(), vv.tolist())) < 1e-11, k
+
+
+def test_periodic_voids_across_the_sides():
+    """Voids centred on the box corner and on a side, and a cluster across
+    the right side: searches escalate through wrapped regions (up to the
+    whole box at nearest images) and still match the oracle."""
+    c = wl.periodic_void_cloud(16, 3000, 9)
+    W, info = PeriodicP2MOracle(c.pos, OMesh.from_spec(c.mesh), c.h).matrix()
+    print(f"[gpu] periodic build {c.name} N={c.N}", flush=True)
+    w = ops.p2m_build_weights(c.mesh, c.h, _gpu(c.pos), ops.P2M_PERIODIC)
+    d = w.diag()
+    assert d["failed_nodes"] == 0 and d["closure_nodes"] == 0 and d["escalated_nodes"] > 0, d
+    idx, wt, cnt, tri = w.export()
+    assert np.array_equal(np.sort(tri.numpy(), 1), np.sort(info["triangle"], 1))
+    got = ops.p2m_project(w, _gpu(c.vals)).cpu().numpy()
+    assert_close(got, W @ c.vals, 1e-12, "periodic voids P2M")

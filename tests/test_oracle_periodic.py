@@ -17,8 +17,8 @@ from oracle.delaunay import circumcircle
 from oracle.periodic import tiled, wrapped_nodes
 
 
-def _oracle(n=8, ratio=2, jitter=0.25, seed=3, pos=None):
-    c = wl.periodic_tg_cloud(n, ratio, jitter, seed)
+def _oracle(n=8, ratio=2, jitter=0.25, seed=3, pos=None, voids=False):
+    c = wl.periodic_void_cloud(n, 3000, seed) if voids else wl.periodic_tg_cloud(n, ratio, jitter, seed)
     m = Mesh.from_spec(c.mesh)
     return c, m, PeriodicP2MOracle(c.pos if pos is None else pos, m, c.h)
 
@@ -27,9 +27,9 @@ def _min_image(d, L):
     return d - L * np.rint(d / L)
 
 
-@pytest.mark.parametrize("seed,jitter", [(3, 0.25), (4, 0.45)])
-def test_consistency_in_minimum_image_offsets(seed, jitter):
-    c, m, o = _oracle(seed=seed, jitter=jitter)
+@pytest.mark.parametrize("seed,jitter,voids", [(3, 0.25, False), (4, 0.45, False), (9, 0.0, True)])
+def test_consistency_in_minimum_image_offsets(seed, jitter, voids):
+    c, m, o = _oracle(n=16 if voids else 8, seed=seed, jitter=jitter, voids=voids)
     cols, vals, imgs, info = o.node_weights()
     L = np.array([m.nx * m.H, m.ny * m.H])
     nodes = wrapped_nodes(m)

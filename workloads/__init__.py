@@ -278,6 +278,30 @@ def cluster_void_cloud(n: int, N: int, seed: int,
     return Cloud(f"cluster{n}", mesh, h, pos, _fields(pos, channels), channels)
 
 
+def periodic_void_cloud(n: int, N: int, seed: int,
+                        channels: Tuple[str, ...] = ("u", "v", "p")) -> Cloud:
+    """Periodic stress input on the Taylor-Green box (-1, 1)^2 (not a
+    benchmark): uniform particles with two circular voids centred on the box
+    corner and on a side, so that both wrap across the sides, plus a Gaussian
+    cluster that crosses the right side, wrapped into the box."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(-1.0, 1.0, size=(N, 2))
+    keep = np.ones(N, bool)
+    for (cx, cy), rad in (((-1.0, -1.0), 0.25), ((-1.0, 0.3), 0.18)):
+        dx = pos[:, 0] - cx
+        dy = pos[:, 1] - cy
+        dx -= 2.0 * np.rint(dx / 2.0)
+        dy -= 2.0 * np.rint(dy / 2.0)
+        keep &= dx * dx + dy * dy > rad * rad
+    cl = np.array([0.95, -0.4]) + rng.normal(0.0, 0.05, size=(N // 8, 2))
+    cl = np.mod(cl + 1.0, 2.0) - 1.0
+    pos = np.concatenate([pos[keep], cl])
+    pos = np.ascontiguousarray(pos[rng.permutation(pos.shape[0])])
+    mesh = MeshSpec(n, n, 2.0 / n, -1.0, -1.0)
+    h = 2.0 / math.sqrt(pos.shape[0])
+    return Cloud(f"periodic_void{n}", mesh, h, pos, _fields(pos, channels), channels)
+
+
 CONFIGS = {
     "C1": config1,
     "C2": config2,
