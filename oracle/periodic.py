@@ -119,3 +119,35 @@ class PeriodicP2MOracle:
     def project(self, vals):
         W, _ = self.matrix()
         return W @ np.asarray(vals, dtype=np.float64)
+
+
+CS_STEP = 1e-30
+
+
+def periodic_p2m_grad_pos(orc: PeriodicP2MOracle, vals, gbar_mesh):
+    """d/d r of L = sum_{i,c} gbar[i,c] (P2M vals)[i,c] in the periodic box
+    (positions only; the triangulation held fixed).
+
+    An image moves with its particle, so the derivative with respect to an
+    image position is added to that particle.  Derivatives by complex step of
+    the forward construction (normal-equation form of the minimum-norm solve,
+    which is holomorphic), as for the bounded box."""
+    vals = np.asarray(vals, dtype=np.float64)
+    g = np.asarray(gbar_mesh, dtype=np.float64)
+    nodes = wrapped_nodes(orc.mesh)
+    s = orc.tri.locate(nodes)
+    st = NodeStructure.build([orc.tri.triangle(t) for t in s], orc.tri.ring)
+    pid = orc.origin[st.U]
+    wbar = np.where(st.valid, np.einsum("nkc,nc->nk", vals[pid], g), 0.0)
+    P = orc.images[st.U].astype(np.complex128)
+    r = nodes.astype(np.complex128)
+    grad = np.zeros_like(orc.pos)
+    for k in range(st.U.shape[1]):
+        for d in range(2):
+            Pc = P.copy()
+            Pc[:, k, d] += 1j * CS_STEP
+            w = interior_weights_local(Pc, st.tri, st.member, st.valid, r, solver="normal")
+            contrib = (wbar * (w.imag / CS_STEP)).sum(1)
+            m = st.valid[:, k]
+            np.add.at(grad[:, d], pid[m, k], contrib[m])
+    return grad

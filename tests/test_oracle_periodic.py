@@ -105,3 +105,31 @@ def test_far_from_the_sides_rows_equal_the_bounded_ones():
         rp, rb = Wp.getrow(k), Wb.getrow(k)
         assert np.array_equal(np.sort(rp.indices), np.sort(rb.indices))
         assert abs(rp - rb).max() < 1e-12
+
+
+def test_position_gradient_matches_central_differences():
+    """The complex-step gradient of sum gbar * P2M(vals) against central
+    differences of the periodic forward (retriangulated at each offset) for
+    particles next to the box corner and sides, whose images carry the
+    dependence across the sides."""
+    from oracle.periodic import periodic_p2m_grad_pos
+    c, m, o = _oracle(seed=13)
+    rng = np.random.default_rng(0)
+    g = rng.normal(size=(m.n_nodes, c.vals.shape[1]))
+    grad = periodic_p2m_grad_pos(o, c.vals, g)
+    L = m.nx * m.H
+
+    def loss(pos):
+        W, _ = PeriodicP2MOracle(pos, m, c.h).matrix()
+        return float(((W @ c.vals) * g).sum())
+
+    d_side = np.minimum(c.pos - [m.x0, m.y0], [m.x0 + L, m.y0 + L] - c.pos).min(1)
+    picks = list(np.argsort(d_side)[:4]) + [int(np.argmax(d_side))]
+    step = 1e-6 * c.h
+    for p in picks:
+        for d in range(2):
+            a, b = c.pos.copy(), c.pos.copy()
+            a[p, d] += step
+            b[p, d] -= step
+            fd = (loss(a) - loss(b)) / (2 * step)
+            assert abs(fd - grad[p, d]) <= 1e-6 * (1 + abs(fd)), (p, d, fd, grad[p, d])
