@@ -135,7 +135,8 @@ typedef struct p2m_weights p2m_weights;
  *         their rows are equal; M2P needs no flag on that layout (mesh values
  *         must repeat the first column and row).  Needs nx, ny >= 4; a node
  *         whose triangles do not fit within about half a period fails
- *         (EGEOM).  p2m_build_weights_backward rejects such a handle.
+ *         (EGEOM).  p2m_build_weights_backward differentiates through the
+ *         nearest images (an image moves with its particle).
  *  w      in/out: *w == NULL allocates a new handle; a handle from an earlier
  *         call is reused (its buffers grow if needed; previous contents are
  *         overwritten, so no work may still be pending on them on another
@@ -262,7 +263,7 @@ int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int
  * handle was built from; geometry is recomputed, not stored).  The
  * combinatorial structure (triangles, rings, nearest sets) is held fixed.
  *  grad_pos  device [N][2] FP64, ACCUMULATED with atomic adds.
- * Errors: EINVAL also for a handle built with P2M_LINEAR or P2M_PERIODIC.
+ * Errors: EINVAL also for a handle built with P2M_LINEAR.
  */
 int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const double* grad_w,
                                double* grad_pos, void* stream);

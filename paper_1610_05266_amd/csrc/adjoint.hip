@@ -91,6 +91,7 @@ struct BArgs {
     const double2* pos;
     const double* gw;
     double2* gpos;
+    int per;  // periodic box: support positions are the nearest images
 };
 
 // Reverse-mode of one minimum-norm block.  Entries k < n with member(k);
@@ -179,14 +180,19 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
     const int n = row_len(meta);
     if (type == NT_FAILED || n == 0) return;
     const int64_t nn = a.w.n_nodes, ns = a.w.n_slots;
-    const double2 q = node_pos(m, i, j);
+    const bool per = a.per != 0;
+    const double2 q = node_at(m, i, j, per);
     double* gx = sgx + tid;
     double* gy = sgy + tid;
     for (int k = 0; k < n; ++k) {
         gx[k * WG] = 0.0;
         gy[k * WG] = 0.0;
     }
-    auto P = [&](int k) { return a.pos[a.w.idx[k * ns + slot]]; };
+    // (an image moves with its particle: its derivative is the particle's)
+    auto P = [&](int k) {
+        const double2 p = a.pos[a.w.idx[k * ns + slot]];
+        return per ? image_near(m, p, q) : p;
+    };
     auto wbar = [&](int k) { return a.gw[k * nn + node]; };
     auto add = [&](int k, double dx, double dy) {
         gx[k * WG] += dx;
@@ -305,13 +311,14 @@ __global__ void __launch_bounds__(256) k_export(WeightsView w, int32_t* __restri
 }  // namespace
 
 int build_backward(const WeightsView& w, const double* pos, const double* grad_w, double* grad_pos,
-                   hipStream_t st) {
+                   hipStream_t st, bool periodic) {
     PhaseTimer _timer(PH_BUILD_BWD, st);
     BArgs a;
     a.w = w;
     a.pos = reinterpret_cast<const double2*>(pos);
     a.gw = grad_w;
     a.gpos = reinterpret_cast<double2*>(grad_pos);
+    a.per = periodic ? 1 : 0;
     const int blocks = static_cast<int>((w.n_nodes + WG - 1) / WG);
     k_build_bwd<<<blocks, WG, 0, st>>>(a);
     P2M_HIP(hipGetLastError());

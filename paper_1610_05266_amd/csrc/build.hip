@@ -73,20 +73,6 @@ __device__ __forceinline__ double orient(double2 p, double2 q, double2 r) {
     return (q.x - p.x) * (r.y - p.y) - (q.y - p.y) * (r.x - p.x);
 }
 
-// ------------------------------------------------------------ periodic box
-// With the periodic option the box [x0, x0 + nx H) x [y0, y0 + ny H) is a
-// torus: a particle enters every computation of a node as its image nearest
-// to the node (position plus a multiple of the period, one rounding per
-// coordinate), and node (nx, j) / (i, ny) is node (0, j) / (i, 0).
-__device__ __forceinline__ double2 image_near(const MeshD& m, double2 p, double2 q) {
-    const double Lx = mul_rn(static_cast<double>(m.nx), m.H), Ly = mul_rn(static_cast<double>(m.ny), m.H);
-    const double kx = rint((q.x - p.x) / Lx), ky = rint((q.y - p.y) / Ly);
-    return make_double2(add_rn(p.x, mul_rn(kx, Lx)), add_rn(p.y, mul_rn(ky, Ly)));
-}
-__device__ __forceinline__ double2 node_at(const MeshD& m, int i, int j, bool per) {
-    return per ? node_pos(m, i == m.nx ? 0 : i, j == m.ny ? 0 : j) : node_pos(m, i, j);
-}
-
 // ------------------------------------------------- candidate comparisons
 // Bisector key of candidate b for the edge v -> a on side sgn: the circumcentre
 // of (v, a, b) is v + A/2 + (num / 2cr) sgn perp(A), with A = a - v, B = b - v,

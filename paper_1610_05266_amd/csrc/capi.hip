@@ -722,11 +722,12 @@ int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const do
         set_error("pos / grad_w / grad_pos NULL or misaligned");
         return P2M_EINVAL;
     }
-    if (w->flags & (P2M_LINEAR | P2M_PERIODIC)) {
-        set_error("weights built with P2M_LINEAR or P2M_PERIODIC: position gradients are not provided");
+    if (w->flags & P2M_LINEAR) {
+        set_error("weights built with P2M_LINEAR: position gradients are not provided");
         return P2M_EINVAL;
     }
-    return build_backward(view(w), pos, grad_w, grad_pos, static_cast<hipStream_t>(stream));
+    return build_backward(view(w), pos, grad_w, grad_pos, static_cast<hipStream_t>(stream),
+                          (w->flags & P2M_PERIODIC) != 0);
 }
 
 const p2m_weights* p2m_fused_handle(void) {

@@ -192,6 +192,20 @@ __device__ __forceinline__ double2 node_pos(const MeshD& m, int i, int j) {
                         add_rn(m.y0, mul_rn(static_cast<double>(j), m.H)));
 }
 
+// ------------------------------------------------------------ periodic box
+// With the periodic option the box [x0, x0 + nx H) x [y0, y0 + ny H) is a
+// torus: a particle enters every computation of a node as its image nearest
+// to the node (position plus a multiple of the period, one rounding per
+// coordinate), and node (nx, j) / (i, ny) is node (0, j) / (i, 0).
+__device__ __forceinline__ double2 image_near(const MeshD& m, double2 p, double2 q) {
+    const double Lx = mul_rn(static_cast<double>(m.nx), m.H), Ly = mul_rn(static_cast<double>(m.ny), m.H);
+    const double kx = rint((q.x - p.x) / Lx), ky = rint((q.y - p.y) / Ly);
+    return make_double2(add_rn(p.x, mul_rn(kx, Lx)), add_rn(p.y, mul_rn(ky, Ly)));
+}
+__device__ __forceinline__ double2 node_at(const MeshD& m, int i, int j, bool per) {
+    return per ? node_pos(m, i == m.nx ? 0 : i, j == m.ny ? 0 : j) : node_pos(m, i, j);
+}
+
 // Value of v in lane (lane ^ m) of the same group of W lanes (m < W).  For
 // quads the exchange is a DPP quad permute ([1,0,3,2] for m = 1, [2,3,0,1]
 // for m = 2) that needs no LDS round trip; the four lanes must be active.

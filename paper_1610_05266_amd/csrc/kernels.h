@@ -101,7 +101,7 @@ int m2p_backward(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, co
 
 // ---- adjoint of the weights (adjoint.hip) ----
 int build_backward(const WeightsView& w, const double* pos, const double* grad_w, double* grad_pos,
-                   hipStream_t st);
+                   hipStream_t st, bool periodic);
 int export_weights(const WeightsView& w, int32_t* idx, double* wts, int32_t* cnt, int32_t* tri,
                    hipStream_t st);
 
