@@ -21,6 +21,9 @@ class P2MFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, pos, vals, mesh, h, flags, recompute):
+        if recompute and int(flags) & ~P2M_WEIGHTS_F32:
+            # the recompute entry points build the default (bounded, quadratic) weights
+            raise ValueError("recompute=True takes no build flags (P2M_LINEAR, P2M_PERIODIC, P2M_STRICT)")
         p, v = pos.detach().contiguous(), vals.detach().contiguous()
         if recompute:
             out = ops.p2m_project_fused(mesh, h, p, v, check_diag=True)

@@ -105,3 +105,16 @@ def test_batch_argument_validation_without_device():
                                        ctypes.c_void_p(16), None) == -1
     assert lib.p2m_batch_shape(None, None, None, None) == -1
     lib.p2m_batch_destroy(None)
+
+
+def test_autograd_recompute_refuses_build_flags():
+    """The recompute form builds the default weights: a flag that changes
+    them must be refused, not dropped (checked before any device call)."""
+    import torch
+    from paper_1610_05266_amd import autograd, ops
+    pos = torch.zeros((4, 2), dtype=torch.float64)
+    vals = torch.zeros((4, 1), dtype=torch.float64)
+    mesh = ops.Mesh(4, 4, 0.25, 0.0, 0.0)
+    for f in (ops.P2M_PERIODIC, ops.P2M_LINEAR):
+        with pytest.raises(ValueError):
+            autograd.p2m(pos, vals, mesh, 0.1, flags=f, recompute=True)
