@@ -91,3 +91,42 @@ def test_loop_step_without_motion_keeps_a_linear_mesh_field():
     new_pos, new_field = kinematic_step(mesh, 1.0 / 32, 0.0, 0.01, pos, field)
     assert np.array_equal(new_pos, pos)
     assert np.abs(new_field - field).max() < 1e-11
+
+
+def test_periodic_flow_is_the_curl_of_its_streamfunction_and_periodic():
+    from oracle import Mesh
+    from oracle.advect import velocity
+    m = Mesh(8, 8, 0.25, -1.0, -1.0)
+    L = 2.0
+    amp = 0.3
+    rng = np.random.default_rng(1)
+    p = rng.uniform(-1.0, 1.0, size=(50, 2))
+
+    def psi(x, y):
+        return amp * np.cos(2 * np.pi * (x + 1.0) / L) * np.cos(2 * np.pi * (y + 1.0) / L)
+
+    e = 1e-6
+    u = velocity(m, amp, p, periodic=True)
+    fu = (psi(p[:, 0], p[:, 1] + e) - psi(p[:, 0], p[:, 1] - e)) / (2 * e)
+    fv = -(psi(p[:, 0] + e, p[:, 1]) - psi(p[:, 0] - e, p[:, 1])) / (2 * e)
+    assert np.abs(u[:, 0] - fu).max() < 1e-8 and np.abs(u[:, 1] - fv).max() < 1e-8
+    for shift in ((L, 0.0), (0.0, -L), (L, L)):
+        assert np.abs(velocity(m, amp, p + shift, periodic=True) - u).max() < 1e-12
+
+
+def test_periodic_step_is_the_free_step_modulo_the_period():
+    """Wrapped positions lie in the box and equal the unclamped midpoint
+    step up to whole periods; particles near the sides cross them."""
+    from oracle import Mesh
+    from oracle.advect import midpoint_step, velocity
+    m = Mesh(8, 8, 0.25, -1.0, -1.0)
+    L = 2.0
+    rng = np.random.default_rng(2)
+    p = rng.uniform(-1.0, 1.0, size=(400, 2))
+    amp, dt = 0.5, 0.4
+    free = p + dt * velocity(m, amp, p + 0.5 * dt * velocity(m, amp, p, True), True)
+    got = midpoint_step(m, amp, dt, p, periodic=True)
+    assert (got >= -1.0).all() and (got < 1.0).all()
+    k = (free - got) / L
+    assert np.abs(k - np.rint(k)).max() < 1e-12
+    assert np.abs(np.rint(k)).sum() > 0  # some particles crossed a side
