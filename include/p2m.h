@@ -202,6 +202,21 @@ int m2p_interpolate(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtyp
 int p2m_advect(const p2m_mesh* mesh, double* pos, int64_t N, double amp, double dt, void* stream);
 
 /*
+ * p2m_advect_periodic -- p2m_advect in the periodic box of P2M_PERIODIC
+ * (the paper's transport tests run in periodic boxes): the cellular flow of
+ * streamfunction amp cos(2 pi (x-x0)/Lx) cos(2 pi (y-y0)/Ly), periodic on the
+ * box, whose cells are centred on the box corners and centre so that
+ * particles cross the box sides; the same midpoint step, then every
+ * coordinate wrapped into [x0, x0+Lx) by whole periods (x - Lx floor((x-x0)/Lx),
+ * one rounding; a result that rounds onto x0+Lx is x0).  A loop step of the
+ * periodic kinematic projection is m2p_interpolate, p2m_advect_periodic,
+ * p2m_build_weights with P2M_PERIODIC, p2m_project.
+ *  pos   device [N][2] FP64, updated in place.
+ * Errors: as p2m_advect.
+ */
+int p2m_advect_periodic(const p2m_mesh* mesh, double* pos, int64_t N, double amp, double dt, void* stream);
+
+/*
  * Mesh-side quadratically consistent shape functions (App. B's construction
  * applied to the fixed mesh): psi^m_i = phi^m_i + 2 sum over the edges
  * e = (nu, sigma) of the particle's mesh triangle of phi^m_nu phi^m_sigma

@@ -65,6 +65,7 @@ _SIGS = {
     "p2m_project": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p]),
     "m2p_interpolate": (c_int, [POINTER(P2MMesh), c_void_p, c_int, c_int, c_void_p, c_int64, c_void_p, c_void_p]),
     "p2m_advect": (c_int, [POINTER(P2MMesh), c_void_p, c_int64, c_double, c_double, c_void_p]),
+    "p2m_advect_periodic": (c_int, [POINTER(P2MMesh), c_void_p, c_int64, c_double, c_double, c_void_p]),
     "m2p_interpolate_backward": (c_int, [POINTER(P2MMesh), c_void_p, c_int, c_int, c_void_p, c_int64, c_void_p,
                                          c_void_p, c_void_p, c_void_p]),
     "p2m_project_backward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),

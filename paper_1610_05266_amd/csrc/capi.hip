@@ -647,7 +647,21 @@ int p2m_advect(const p2m_mesh* mesh, double* pos, int64_t N, double amp, double 
         set_error("amp and dt must be finite");
         return P2M_EINVAL;
     }
-    return advect_midpoint(to_meshd(mesh), pos, N, amp, dt, static_cast<hipStream_t>(stream));
+    return advect_midpoint(to_meshd(mesh), pos, N, amp, dt, static_cast<hipStream_t>(stream), false);
+}
+
+int p2m_advect_periodic(const p2m_mesh* mesh, double* pos, int64_t N, double amp, double dt, void* stream) {
+    int rc = check_mesh(mesh);
+    if (rc) return rc;
+    if (!pos || !aligned(pos, 16) || N < 1 || N >= (int64_t(1) << 31)) {
+        set_error("pos is NULL/misaligned or N=%lld out of range", static_cast<long long>(N));
+        return P2M_EINVAL;
+    }
+    if (!std::isfinite(amp) || !std::isfinite(dt)) {
+        set_error("amp and dt must be finite");
+        return P2M_EINVAL;
+    }
+    return advect_midpoint(to_meshd(mesh), pos, N, amp, dt, static_cast<hipStream_t>(stream), true);
 }
 
 int m2p_interpolate_batched(const p2m_batch* b, const void* mesh_vals, int C, int dtype, const double* pos,

@@ -92,7 +92,8 @@ int m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void*
              const double* pos, int64_t N, void* vals, hipStream_t st);
 // One explicit midpoint step of every particle in the cellular flow of the
 // mesh box, clamped into the box (advect.hip).
-int advect_midpoint(const MeshD& m, double* pos, int64_t N, double amp, double dt, hipStream_t st);
+int advect_midpoint(const MeshD& m, double* pos, int64_t N, double amp, double dt, hipStream_t st,
+                    bool periodic);
 int m2p(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C, int dtype,
         const double* pos, int64_t N, void* vals, hipStream_t st);
 int m2p_backward(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C,

@@ -242,16 +242,19 @@ class MeshQCSF:
         return out
 
 
-def p2m_advect(mesh, pos: torch.Tensor, amp: float, dt: float) -> torch.Tensor:
+def p2m_advect(mesh, pos: torch.Tensor, amp: float, dt: float, periodic: bool = False) -> torch.Tensor:
     """One midpoint step of the particles in the cellular flow of the mesh box
-    (C call of the same name); ``pos`` is updated in place and returned."""
+    (C call of the same name; ``periodic``: p2m_advect_periodic, the periodic
+    flow with positions wrapped into the box); ``pos`` is updated in place
+    and returned."""
     mesh = Mesh.of(mesh)
     _need(pos, "pos", torch.float64)
     if pos.dim() != 2 or pos.shape[1] != 2:
         raise ValueError("pos must have shape [N, 2]")
     cm = mesh.c()
     with torch.cuda.device(pos.device):
-        check(load().p2m_advect(ctypes.byref(cm), _ptr(pos), pos.shape[0], float(amp), float(dt), _stream(pos)))
+        fn = load().p2m_advect_periodic if periodic else load().p2m_advect
+        check(fn(ctypes.byref(cm), _ptr(pos), pos.shape[0], float(amp), float(dt), _stream(pos)))
     return pos
 
 
@@ -260,9 +263,10 @@ def kinematic_step(mesh, h: float, pos: torch.Tensor, mesh_vals: torch.Tensor, a
     """One step of the kinematic projection loop, every step on the GPU:
     particle values from the mesh (M2P), the particles moved one step
     (p2m_advect), their functions rebuilt, and projected back (P2M).
-    ``pos`` is updated in place; returns (new mesh values, weights)."""
+    ``pos`` is updated in place; returns (new mesh values, weights).  With
+    P2M_PERIODIC in ``flags`` the particles move in the periodic flow."""
     vals = m2p_interpolate(mesh, mesh_vals, pos)
-    p2m_advect(mesh, pos, amp, dt)
+    p2m_advect(mesh, pos, amp, dt, periodic=bool(flags & P2M_PERIODIC))
     w = p2m_build_weights(mesh, h, pos, flags, weights=weights, check_diag=False)
     return p2m_project(w, vals), w
 

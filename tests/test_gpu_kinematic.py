@@ -67,3 +67,52 @@ def test_three_loop_steps_match_the_oracle_loop():
     assert_close(mv.cpu().numpy(), o_mv, 1e-11, "kinematic loop mesh values")
     # the particles moved by about half a cell in all
     assert np.abs(pos.cpu().numpy() - c.pos).max() > 0.2 / 32
+
+
+def _periodic_diff(a, b, L):
+    d = a - b
+    return np.abs(d - L * np.rint(d / L)).max()
+
+
+def test_periodic_advect_matches_the_oracle_and_wraps():
+    """p2m_advect_periodic: the periodic flow crosses the box sides and the
+    particles are wrapped back in; positions compared up to whole periods
+    (a particle within rounding of a side may wrap on one side only)."""
+    c = wl.periodic_tg_cloud(16, 2, 0.3, 11)
+    om = OMesh.from_spec(c.mesh)
+    L = om.nx * om.H
+    for amp, dt in ((0.05, 0.1), (0.5, 0.4)):
+        print(f"[gpu] periodic advect amp={amp} dt={dt}", flush=True)
+        pos = _gpu(c.pos)
+        ops.p2m_advect(c.mesh, pos, amp, dt, periodic=True)
+        got = pos.cpu().numpy()
+        want = midpoint_step(om, amp, dt, c.pos, periodic=True)
+        k = 2 * np.pi / L
+        umax, gmax = amp * k, amp * k * k
+        tol = 8 * np.finfo(float).eps * (1 + np.abs(c.pos).max() + dt * umax) * (1 + dt * gmax)
+        assert _periodic_diff(got, want, L) <= tol
+        assert (got >= -1.0).all() and (got < 1.0).all()
+        assert np.abs(got - want).max() < L / 2  # the same wrap almost everywhere
+
+
+def test_periodic_loop_steps_match_the_oracle_loop():
+    c = wl.periodic_tg_cloud(16, 2, 0.3, 11)
+    om = OMesh.from_spec(c.mesh)
+    nodes = om.nodes()
+    field = np.stack([wl.tg_u(nodes[:, 0], nodes[:, 1]), wl.tg_p(nodes[:, 0], nodes[:, 1])], 1)
+    amp, dt = 0.2, 0.15
+    pos = _gpu(c.pos)
+    mv = _gpu(field)
+    o_pos, o_mv = c.pos.copy(), field
+    w = None
+    for k in range(3):
+        print(f"[gpu] periodic kinematic step {k}", flush=True)
+        mv, w = ops.kinematic_step(c.mesh, c.h, pos, mv, amp, dt, flags=ops.P2M_PERIODIC, weights=w)
+        o_pos, o_mv = o_step(om, c.h, amp, dt, o_pos, o_mv, periodic=True)
+        assert _periodic_diff(pos.cpu().numpy(), o_pos, om.nx * om.H) <= 1e-14
+        d = w.diag()
+        assert d["failed_nodes"] == 0 and d["closure_nodes"] == 0
+    assert_close(mv.cpu().numpy(), o_mv, 1e-11, "periodic kinematic loop mesh values")
+    # particles crossed the box sides
+    moved = pos.cpu().numpy() - c.pos
+    assert np.abs(moved).max() > 1.0
