@@ -310,8 +310,9 @@ def main(argv=None):
     log(f"cached weights: mixed {cms32:.4f} ms, FP64 {cms64:.4f} ms per round trip")
     torch.cuda.synchronize()
 
-    lms32 = kms32 = qms32 = qsetup = pms32 = None
-    pdiag = {}
+    lms32 = kms32 = qms32 = qsetup = pms32 = pkms32 = None
+    pdiag, pkdiag = {}, {}
+    pktuning = None
     kdiag, ktuning = {}, None
     if not a.no_extras:
         # M2P with the mesh's quadratically consistent functions (FP32), on the
@@ -383,7 +384,42 @@ def main(argv=None):
         pms32 = time_loop(run_per)
         pdiag = wper.diag(check_status=False)
         log(f"periodic round trip (mixed) {pms32:.4f} ms, diag {pdiag}")
-        del wper, ppos, pv32, pmesh32, pout32
+
+        # one step of the periodic kinematic loop: the periodic flow (a quarter
+        # cell per step) carries particles across the box sides, wrapped back
+        pamp, pdt = 0.1, 0.25 * pcl.mesh.H / (0.1 * 2.0 * math.pi)
+        pkmesh = pmesh32.clone()
+
+        def step_periodic_kinematic():
+            ops.m2p_interpolate(pcl.mesh, pkmesh, ppos, out=pout32)
+            ops.p2m_advect(pcl.mesh, ppos, pamp, pdt, periodic=True)
+            ops.p2m_build_weights(pcl.mesh, pcl.h, ppos, pflags, weights=wper, check_diag=False)
+            ops.p2m_project(wper, pout32, out=pkmesh)
+
+        # as for the bounded loop: shear the cloud, then tune the options for it
+        for _ in range(24):
+            step_periodic_kinematic()
+        torch.cuda.synchronize()
+        pktuning = None
+        if not a.no_tune and not a.set:
+            from paper_1610_05266_amd import tune
+
+            pkkey = tune.workload_key(torch.cuda.get_device_name(dev), N, pcl.mesh.n_nodes, pcl.h / pcl.mesh.H,
+                                      pflags) + "|sheared"
+            pkres = tune.autotune(
+                lambda: ops.p2m_build_weights(pcl.mesh, pcl.h, ppos, pflags, weights=wper, check_diag=False),
+                lambda hd: ops.p2m_project(hd, pout32), pkkey)
+            pktuning = {"options": pkres.options, "build_ms_tuned": round(pkres.median_ms, 5),
+                        "build_ms_default": round(pkres.default_ms, 5), "cached": pkres.cached}
+            log(f"periodic kinematic tuning {pktuning}")
+        pkms32 = time_loop(as_graph(step_periodic_kinematic))
+        if pktuning is not None:
+            from paper_1610_05266_amd import tune
+
+            tune.apply_options(tuning["options"])
+        pkdiag = wper.diag(check_status=False)
+        log(f"periodic kinematic step (mixed) {pkms32:.4f} ms, diag {pkdiag}")
+        del wper, ppos, pv32, pmesh32, pout32, pkmesh
 
         # one step of the kinematic projection loop (mixed form): particle values
         # from the mesh, the particles moved one midpoint step in the cellular flow
@@ -541,7 +577,15 @@ def main(argv=None):
                     "side take the exact path",
             "ms_per_step": round(pms32, 5), "Mparticles_per_s": round(N / (pms32 * 1e-3) / 1e6, 3),
             "slow_nodes": int(pdiag["slow_nodes"]), "failed_nodes": int(pdiag["failed_nodes"]),
-            "closure_nodes": int(pdiag["closure_nodes"])},
+            "closure_nodes": int(pdiag["closure_nodes"]),
+            "kinematic_step_ms": round(pkms32, 5),
+            "kinematic_note": "one step of the periodic kinematic loop (M2P, p2m_advect_periodic: a quarter cell per "
+                              "step in the periodic cellular flow, particles wrapped across the sides, rebuild, "
+                              "P2M), HIP graph replays, particles moving at every replay; build options tuned on "
+                              "the cloud after 24 steps of shear",
+            "kinematic_tuning": pktuning,
+            "kinematic_failed_nodes_after": int(pkdiag["failed_nodes"]),
+            "kinematic_slow_nodes_after": int(pkdiag["slow_nodes"])},
         "launch": "eager" if (a.no_graph or graph_notes) else "HIP graph replay of the whole step",
         "launch_notes": graph_notes,
         "tuning": tuning,
