@@ -86,3 +86,27 @@ def m2p_qcsf_matrix(mesh: Mesh, pos):
 def m2p_qcsf(mesh: Mesh, mesh_vals, pos):
     """Eq. (m2p) with the mesh's quadratically consistent shape functions."""
     return m2p_qcsf_matrix(mesh, pos) @ np.asarray(mesh_vals, dtype=np.float64)
+
+
+def m2p_qcsf_periodic_matrix(mesh: Mesh, pos):
+    """Sparse [N, n_nodes] matrix of psi^m_i(r_mu) in the periodic box.
+
+    The mesh tiled 3 x 3 by the box periods: every edge a particle of the box
+    uses is then an interior edge of the tiled mesh, with the periodic box's
+    support (the rings wrapped across the sides), and its columns are folded
+    back onto node (i mod nx, j mod ny) of the box (the repeated last column
+    and row get none)."""
+    Lx, Ly = mesh.nx * mesh.H, mesh.ny * mesh.H
+    ext = Mesh(3 * mesh.nx, 3 * mesh.ny, mesh.H, mesh.x0 - Lx, mesh.y0 - Ly)
+    W = m2p_qcsf_matrix(ext, pos)
+    k = np.arange(ext.n_nodes)
+    I, J = k % (ext.nx + 1), k // (ext.nx + 1)
+    col = ((J - mesh.ny) % mesh.ny) * (mesh.nx + 1) + (I - mesh.nx) % mesh.nx
+    F = sp.csr_matrix((np.ones(ext.n_nodes), (k, col)), shape=(ext.n_nodes, mesh.n_nodes))
+    return (W @ F).tocsr()
+
+
+def m2p_qcsf_periodic(mesh: Mesh, mesh_vals, pos):
+    """Eq. (m2p) with the mesh's quadratically consistent shape functions in
+    the periodic box (mesh values repeat the first column and row)."""
+    return m2p_qcsf_periodic_matrix(mesh, pos) @ np.asarray(mesh_vals, dtype=np.float64)

@@ -55,3 +55,35 @@ def test_equally_oriented_interior_edges_share_coefficients():
         # supports sorted by node id: the same offsets in the same order
         assert np.array_equal(U[0] - E[0, 0], U[1] - E[1, 0])
         assert np.abs(A[0] - A[1]).max() < 1e-12
+
+
+def test_periodic_mesh_functions_are_consistent_in_minimum_image_offsets():
+    """Periodic box: sum psi = 1, sum psi d = 0, sum psi d d^t = 0 with d the
+    minimum-image offsets of the nodes from the particle (computed here from
+    the box's node positions), interpolation at the nodes, and agreement with
+    the bounded functions two cells away from the sides."""
+    from oracle import Mesh
+    from oracle.m2p_qcsf import m2p_qcsf_matrix, m2p_qcsf_periodic_matrix
+    m = Mesh(8, 6, 0.25, -1.0, -0.75)
+    L = np.array([m.nx * m.H, m.ny * m.H])
+    rng = np.random.default_rng(4)
+    pos = np.array([m.x0, m.y0]) + rng.random((400, 2)) * L
+    W = m2p_qcsf_periodic_matrix(m, pos)
+    nodes = m.nodes()
+    for p in range(len(pos)):
+        r = W.getrow(p)
+        d = nodes[r.indices] - pos[p]
+        d -= L * np.rint(d / L)
+        w = r.data
+        assert abs(w.sum() - 1) < 1e-12
+        assert np.abs(w @ d).max() < 1e-12
+        assert np.abs(np.einsum("k,ka,kb->ab", w, d, d)).max() < 1e-12
+    i = np.arange(m.nx); j = np.arange(m.ny)
+    kk = (j[:, None] * (m.nx + 1) + i[None, :]).ravel()
+    Wn = m2p_qcsf_periodic_matrix(m, nodes[kk]).toarray()
+    assert np.abs(Wn[:, kk] - np.eye(len(kk))).max() < 1e-12
+    far = ((pos[:, 0] > m.x0 + 2 * m.H) & (pos[:, 0] < m.x0 + L[0] - 2 * m.H) &
+           (pos[:, 1] > m.y0 + 2 * m.H) & (pos[:, 1] < m.y0 + L[1] - 2 * m.H))
+    assert far.sum() > 50
+    Wb = m2p_qcsf_matrix(m, pos[far])
+    assert abs(W[np.flatnonzero(far)] - Wb).max() < 1e-12
