@@ -233,6 +233,12 @@ int p2m_advect_periodic(const p2m_mesh* mesh, double* pos, int64_t N, double amp
  */
 typedef struct p2m_mesh_qcsf p2m_mesh_qcsf;
 int p2m_mesh_qcsf_create(const p2m_mesh* mesh, p2m_mesh_qcsf** out, void* stream);
+/* The same functions in the periodic box of P2M_PERIODIC: every mesh edge is
+ * interior there, with the rings wrapped across the box sides, so every edge
+ * takes the coefficients of an interior edge of its orientation (translation
+ * invariance) and M2P reads node ids wrapped to the first column and row
+ * (which the mesh values' last column and row repeat).  Needs nx, ny >= 4. */
+int p2m_mesh_qcsf_create_periodic(const p2m_mesh* mesh, p2m_mesh_qcsf** out, void* stream);
 void p2m_mesh_qcsf_destroy(p2m_mesh_qcsf* q);
 
 /*

@@ -72,6 +72,7 @@ _SIGS = {
     "p2m_build_weights_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "p2m_weights_destroy": (None, [c_void_p]),
     "p2m_mesh_qcsf_create": (c_int, [POINTER(P2MMesh), POINTER(c_void_p), c_void_p]),
+    "p2m_mesh_qcsf_create_periodic": (c_int, [POINTER(P2MMesh), POINTER(c_void_p), c_void_p]),
     "p2m_mesh_qcsf_destroy": (None, [c_void_p]),
     "m2p_interpolate_qcsf": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int64, c_void_p, c_void_p]),
     "p2m_project_fused": (c_int, [POINTER(P2MMesh), c_double, c_void_p, c_int64, c_void_p, c_int, c_int, c_void_p,

@@ -100,6 +100,7 @@ struct p2m_mesh_qcsf {
     int64_t E = 0;
     int32_t* idx = nullptr;  // [E][MESH_SUP] support node ids
     double* coef = nullptr;  // [E][MESH_SUP] coefficients A^m
+    bool per = false;        // periodic box: every edge takes its interior coefficients
 };
 
 namespace {
@@ -819,6 +820,18 @@ int p2m_mesh_qcsf_create(const p2m_mesh* mesh, p2m_mesh_qcsf** out, void* stream
     return P2M_OK;
 }
 
+int p2m_mesh_qcsf_create_periodic(const p2m_mesh* mesh, p2m_mesh_qcsf** out, void* stream) {
+    int rc = check_mesh(mesh);
+    if (rc) return rc;
+    if (mesh->nx < 4 || mesh->ny < 4) {
+        set_error("a periodic box needs at least 4 cells per side (nx=%d ny=%d)", mesh->nx, mesh->ny);
+        return P2M_EINVAL;
+    }
+    rc = p2m_mesh_qcsf_create(mesh, out, stream);
+    if (!rc) (*out)->per = true;
+    return rc;
+}
+
 int m2p_interpolate_qcsf(const p2m_mesh_qcsf* q, const void* mesh_vals, int C, int dtype, const double* pos,
                          int64_t N, void* vals, void* stream) {
     if (!q || !q->idx || !q->coef) {
@@ -832,7 +845,8 @@ int m2p_interpolate_qcsf(const p2m_mesh_qcsf* q, const void* mesh_vals, int C, i
         set_error("pos is NULL/misaligned or N=%lld out of range", static_cast<long long>(N));
         return P2M_EINVAL;
     }
-    return m2p_qcsf(q->m, q->idx, q->coef, mesh_vals, C, dtype, pos, N, vals, static_cast<hipStream_t>(stream));
+    return m2p_qcsf(q->m, q->idx, q->coef, mesh_vals, C, dtype, pos, N, vals, static_cast<hipStream_t>(stream),
+                    q->per);
 }
 
 void p2m_mesh_qcsf_destroy(p2m_mesh_qcsf* q) {

@@ -89,7 +89,7 @@ constexpr int MESH_SUP = 10;
 int64_t mesh_edge_count(const MeshD& m);
 int mesh_edge_table(const MeshD& m, int32_t* idx, double* coef, hipStream_t st);
 int m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void* mesh_vals, int C, int dtype,
-             const double* pos, int64_t N, void* vals, hipStream_t st);
+             const double* pos, int64_t N, void* vals, hipStream_t st, bool periodic);
 // One explicit midpoint step of every particle in the cellular flow of the
 // mesh box, clamped into the box (advect.hip).
 int advect_midpoint(const MeshD& m, double* pos, int64_t N, double amp, double dt, hipStream_t st,

@@ -137,7 +137,7 @@ template <typename TM, typename TO, int CC>
 __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __restrict__ eidx,
                                                   const double* __restrict__ ecoef, const TM* __restrict__ mv,
                                                   int Crt, const double2* __restrict__ pos, int64_t N,
-                                                  TO* __restrict__ out) {
+                                                  TO* __restrict__ out, int per) {
     constexpr int NC = CC > 0 ? CC : CMAX;
     const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mu >= N) return;
@@ -157,7 +157,10 @@ __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __rest
     // invariant): every such particle reads those three rows (the same
     // addresses for all, cached) and shifts their node ids, instead of three
     // rows of its own.
-    const bool inner = m.nx >= 3 && m.ny >= 3 && i >= 1 && j >= 1 && i + 2 <= m.nx && j + 2 <= m.ny;
+    // In a periodic box every edge is such an edge, and the node ids wrap
+    // across the box sides (to the first column and row, which the last
+    // repeat).
+    const bool inner = per || (m.nx >= 3 && m.ny >= 3 && i >= 1 && j >= 1 && i + 2 <= m.nx && j + 2 <= m.ny);
     const int64_t r11 = s + 1, rh = m.nx + 1, rv = nh + s + 1, rd = nh + nv + m.nx + 1;
     const int64_t n00 = L.n0;
     TM acc[NC];
@@ -196,7 +199,13 @@ __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __rest
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
             if (k == 3 || k == 12) continue;  // offsets (2,-1) and (-1,2): never in a support
-            const int64_t node = n00 + static_cast<int64_t>(k / 4 - 1) * s + (k % 4 - 1);
+            int64_t node = n00 + static_cast<int64_t>(k / 4 - 1) * s + (k % 4 - 1);
+            if (per) {
+                int a = i + (k % 4 - 1), b = j + (k / 4 - 1);
+                a += a < 0 ? m.nx : (a >= m.nx ? -m.nx : 0);
+                b += b < 0 ? m.ny : (b >= m.ny ? -m.ny : 0);
+                node = static_cast<int64_t>(b) * s + a;
+            }
             const TM f = static_cast<TM>(g[k]);
 #pragma unroll
             for (int c = 0; c < NC; ++c)
@@ -236,17 +245,17 @@ __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __rest
 
 template <typename TM, typename TO>
 void launch_m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void* mv, int C,
-                     const double* pos, int64_t N, void* out, hipStream_t s) {
+                     const double* pos, int64_t N, void* out, hipStream_t s, int per) {
     const int blocks = static_cast<int>((N + 255) / 256);
     const TM* M = static_cast<const TM*>(mv);
     const double2* P = reinterpret_cast<const double2*>(pos);
     TO* O = static_cast<TO*>(out);
     switch (C) {
-        case 1: k_m2p_qcsf<TM, TO, 1><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
-        case 2: k_m2p_qcsf<TM, TO, 2><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
-        case 3: k_m2p_qcsf<TM, TO, 3><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
-        case 4: k_m2p_qcsf<TM, TO, 4><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
-        default: k_m2p_qcsf<TM, TO, 0><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        case 1: k_m2p_qcsf<TM, TO, 1><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
+        case 2: k_m2p_qcsf<TM, TO, 2><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
+        case 3: k_m2p_qcsf<TM, TO, 3><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
+        case 4: k_m2p_qcsf<TM, TO, 4><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
+        default: k_m2p_qcsf<TM, TO, 0><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
     }
 }
 
@@ -309,14 +318,15 @@ int m2p(const MeshD& mesh, const SetDesc* sets, int S, int64_t n_nodes, const vo
 }
 
 int m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void* mesh_vals, int C, int dtype,
-             const double* pos, int64_t N, void* vals, hipStream_t st) {
+             const double* pos, int64_t N, void* vals, hipStream_t st, bool periodic) {
     PhaseTimer _timer(PH_M2P, st);
+    const int per = periodic ? 1 : 0;
     if (dtype == P2M_F64)
-        launch_m2p_qcsf<double, double>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
+        launch_m2p_qcsf<double, double>(m, idx, coef, mesh_vals, C, pos, N, vals, st, per);
     else if (dtype == P2M_F32)
-        launch_m2p_qcsf<float, float>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
+        launch_m2p_qcsf<float, float>(m, idx, coef, mesh_vals, C, pos, N, vals, st, per);
     else
-        launch_m2p_qcsf<float, uint16_t>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
+        launch_m2p_qcsf<float, uint16_t>(m, idx, coef, mesh_vals, C, pos, N, vals, st, per);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }

@@ -197,16 +197,19 @@ def p2m_project(w: Weights, vals: torch.Tensor, out: Optional[torch.Tensor] = No
 
 class MeshQCSF:
     """Owner of a p2m_mesh_qcsf handle: the edge coefficients of one mesh's
-    quadratically consistent functions, computed once on ``device``."""
+    quadratically consistent functions, computed once on ``device``
+    (``periodic``: in the periodic box, p2m_mesh_qcsf_create_periodic)."""
 
-    def __init__(self, mesh, device="cuda:0"):
+    def __init__(self, mesh, device="cuda:0", periodic: bool = False):
         self.mesh = Mesh.of(mesh)
         self.device = torch.device(device)
+        self.periodic = bool(periodic)
         self._h = ctypes.c_void_p(0)
         cm = self.mesh.c()
         with torch.cuda.device(self.device):
             st = ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
-            check(load().p2m_mesh_qcsf_create(ctypes.byref(cm), ctypes.byref(self._h), st))
+            fn = load().p2m_mesh_qcsf_create_periodic if periodic else load().p2m_mesh_qcsf_create
+            check(fn(ctypes.byref(cm), ctypes.byref(self._h), st))
 
     def __del__(self):
         if getattr(self, "_h", None) is not None and self._h.value:

@@ -53,3 +53,31 @@ def test_m2p_qcsf_matches_the_oracle_and_reproduces_quadratics(case):
                      pos_np[:, 0] * pos_np[:, 1], pos_np[:, 1] ** 2], 1)
     got_q = q.interpolate(_gpu(quad), pos).cpu().numpy()
     assert np.abs(got_q - want).max() <= 1e-12
+
+
+def test_periodic_mesh_qcsf_matches_the_oracle():
+    """The periodic box: every particle, next to the sides too, against the
+    oracle's tiled-mesh functions (FP64 1e-12, FP32 5e-6)."""
+    import workloads as wl
+    from oracle import Mesh as OMesh
+    from oracle.m2p_qcsf import m2p_qcsf_periodic
+    c = wl.periodic_tg_cloud(16, 2, 0.3, 11)
+    om = OMesh.from_spec(c.mesh)
+    nodes = om.nodes()
+    f = np.stack([wl.tg_u(nodes[:, 0], nodes[:, 1]), wl.tg_p(nodes[:, 0], nodes[:, 1])], 1)
+    # the repeated last column and row hold the first's values
+    n1 = om.nx + 1
+    g = f.reshape(om.ny + 1, n1, -1)
+    g[:, -1] = g[:, 0]
+    g[-1] = g[0]
+    f = g.reshape(-1, f.shape[1])
+    want = m2p_qcsf_periodic(om, f, c.pos)
+    print("[gpu] periodic mesh qcsf", flush=True)
+    q = ops.MeshQCSF(c.mesh, DEV, periodic=True)
+    pos = torch.from_numpy(c.pos).to(DEV)
+    got = q.interpolate(torch.from_numpy(f).to(DEV), pos).cpu().numpy()
+    assert_close(got, want, 1e-12, "periodic QCSF M2P FP64")
+    got32 = q.interpolate(torch.from_numpy(f).to(DEV, torch.float32), pos).cpu().numpy()
+    assert_close(got32, want, 5e-6, "periodic QCSF M2P FP32")
+    with pytest.raises(ops.P2MError):
+        ops.MeshQCSF(wl.MeshSpec(3, 3, 2.0 / 3, -1.0, -1.0), DEV, periodic=True)
