@@ -133,11 +133,12 @@ constexpr int kSupOff[3][10][2] = {
 // (0,1), (1,2), (0,2): lower triangle horizontal (i,j), vertical (i+1,j),
 // diagonal (i,j); upper triangle diagonal (i,j), horizontal (i,j+1),
 // vertical (i,j).  One thread per particle.
-template <typename TM, typename TO, int CC>
+template <typename TM, typename TO, int CC, bool PER>
 __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __restrict__ eidx,
                                                   const double* __restrict__ ecoef, const TM* __restrict__ mv,
                                                   int Crt, const double2* __restrict__ pos, int64_t N,
-                                                  TO* __restrict__ out, int per) {
+                                                  TO* __restrict__ out) {
+    constexpr bool per = PER;
     constexpr int NC = CC > 0 ? CC : CMAX;
     const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mu >= N) return;
@@ -243,19 +244,19 @@ __global__ void __launch_bounds__(256) k_m2p_qcsf(MeshD m, const int32_t* __rest
         if (c < C) st(out, mu * C + c, L.ok ? acc[c] : static_cast<TM>(NAN));
 }
 
-template <typename TM, typename TO>
+template <typename TM, typename TO, bool PER>
 void launch_m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void* mv, int C,
-                     const double* pos, int64_t N, void* out, hipStream_t s, int per) {
+                     const double* pos, int64_t N, void* out, hipStream_t s) {
     const int blocks = static_cast<int>((N + 255) / 256);
     const TM* M = static_cast<const TM*>(mv);
     const double2* P = reinterpret_cast<const double2*>(pos);
     TO* O = static_cast<TO*>(out);
     switch (C) {
-        case 1: k_m2p_qcsf<TM, TO, 1><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
-        case 2: k_m2p_qcsf<TM, TO, 2><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
-        case 3: k_m2p_qcsf<TM, TO, 3><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
-        case 4: k_m2p_qcsf<TM, TO, 4><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
-        default: k_m2p_qcsf<TM, TO, 0><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O, per); break;
+        case 1: k_m2p_qcsf<TM, TO, 1, PER><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        case 2: k_m2p_qcsf<TM, TO, 2, PER><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        case 3: k_m2p_qcsf<TM, TO, 3, PER><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        case 4: k_m2p_qcsf<TM, TO, 4, PER><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
+        default: k_m2p_qcsf<TM, TO, 0, PER><<<blocks, 256, 0, s>>>(m, idx, coef, M, C, P, N, O); break;
     }
 }
 
@@ -322,11 +323,14 @@ int m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void*
     PhaseTimer _timer(PH_M2P, st);
     const int per = periodic ? 1 : 0;
     if (dtype == P2M_F64)
-        launch_m2p_qcsf<double, double>(m, idx, coef, mesh_vals, C, pos, N, vals, st, per);
+        per ? launch_m2p_qcsf<double, double, true>(m, idx, coef, mesh_vals, C, pos, N, vals, st)
+            : launch_m2p_qcsf<double, double, false>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
     else if (dtype == P2M_F32)
-        launch_m2p_qcsf<float, float>(m, idx, coef, mesh_vals, C, pos, N, vals, st, per);
+        per ? launch_m2p_qcsf<float, float, true>(m, idx, coef, mesh_vals, C, pos, N, vals, st)
+            : launch_m2p_qcsf<float, float, false>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
     else
-        launch_m2p_qcsf<float, uint16_t>(m, idx, coef, mesh_vals, C, pos, N, vals, st, per);
+        per ? launch_m2p_qcsf<float, uint16_t, true>(m, idx, coef, mesh_vals, C, pos, N, vals, st)
+            : launch_m2p_qcsf<float, uint16_t, false>(m, idx, coef, mesh_vals, C, pos, N, vals, st);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }
