@@ -44,8 +44,13 @@
 // fast pass into weights.  Both passes produce the same rows in the same
 // order and use the same weighting code, so the result of a node does not
 // depend on the pass that found its triangle.  With the linear option the
-// search stops at T and the row is phi alone.  The end of the file builds
-// the mesh-side counterpart: the coefficient table of every mesh edge.
+// search stops at T and the row is phi alone.  With the periodic option
+// the box is a torus: the exact path's regions wrap across its sides and read
+// every particle at its image nearest to the node, the fast pass keeps the
+// nodes whose windows stay inside the box, there are no closure nodes, and
+// the seam nodes' rows are copies of the first column and row.  The end of
+// the file builds the mesh-side counterpart: the coefficient table of every
+// mesh edge.
 #include <algorithm>
 #include <cfloat>
 #include <climits>
