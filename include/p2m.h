@@ -110,7 +110,8 @@ typedef struct p2m_weights p2m_weights;
  * particle mu is phi_mu + 2 sum_e phi_nu phi_sigma A_{mu e}.  Nodes on the
  * mesh's outer ring and nodes outside the particles' convex hull use the
  * minimum-norm quadratic-moment weights of their P2M_CLOSURE_K nearest
- * particles (a closure the paper's periodic runs never needed).
+ * particles (a closure of the bounded box; the paper's periodic runs need
+ * none, and P2M_PERIODIC has no such nodes).
  *
  *  mesh   host pointer to the mesh description.
  *  h      mean particle spacing (the paper's h).  A performance hint only:

@@ -27,7 +27,8 @@ Follows App. B of the paper:
 * P2M, eq. (p2m): alpha_i = sum_mu alpha_mu psi_mu(r_i).
 
 Nodes where the construction above is unusable are handled by a reading the
-paper does not cover (it only runs periodic boxes): every node on the outer
+paper does not cover (it only runs periodic boxes, which ``periodic`` forms
+without closure nodes): every node on the outer
 ring of the mesh and every node outside the particles' convex hull is a
 CLOSURE node whose weights are the minimum-norm solution of the six
 quadratic moment conditions sum_mu w_mu p(r_mu - r_i) = p(0) over its
