@@ -6,7 +6,10 @@ not against a retyped copy of its own formulas:
   * eq. noC2: linear FE alone fail C2 (negative control);
   * the coefficient system of each edge (eqs. A0, A1, condquad) is solved
     exactly and with minimum norm; on an equilateral lattice the result equals
-    an exact symbolic computation from the raw eq. (condquad);
+    an exact symbolic computation from the raw eq. (condquad), and a whole
+    row equals the exact row built from lattice geometry alone (each edge's
+    coefficients over that edge's own S_e = ring(nu) U ring(sigma): the
+    node's full support would give another row);
   * interpolation at a particle (psi_mu(r_nu) = delta_mu nu from eq. phiquad);
   * translation/rotation/scale invariance (eq. A2_2);
   * the projection error order of Sec. 2.1 (h^2 for linear FE, h^3 for a
@@ -147,6 +150,92 @@ def test_equilateral_lattice_matches_exact_symbolic():
         A, rank, _ = min_norm_svd(M, rhs, np.array([len(S)]))
         assert rank[0] == 6
         assert np.abs(A[0] - As).max() <= 1e-13
+
+
+def _lattice_row(q, support_of_edge):
+    """Exact row psi_mu(q) on the equilateral lattice (i + j/2, j sqrt(3)/2),
+    built from lattice geometry alone (no triangulation): T is the lattice
+    triangle holding q, a vertex's ring is its six lattice neighbours, and
+    A_e is the exact minimum-norm solution of eqs. (A0), (A1), (condquad)
+    over support_of_edge(nu, sigma).  Returns {(i, j): psi}."""
+    rt3 = sympy.sqrt(3)
+    half = sympy.Rational(1, 2)
+    qx, qy = sympy.nsimplify(q[0]), sympy.nsimplify(q[1])   # dyadic, exact
+    jf = 2 * qy / rt3
+    i_f = qx - jf / 2
+    i0, j0 = int(sympy.floor(i_f)), int(sympy.floor(jf))
+    if (i_f - i0) + (jf - j0) < 1:
+        T = [(i0, j0), (i0 + 1, j0), (i0, j0 + 1)]
+    else:
+        T = [(i0 + 1, j0), (i0 + 1, j0 + 1), (i0, j0 + 1)]
+
+    def xy(k):
+        return (sympy.Integer(k[0]) + half * k[1], k[1] * rt3 / 2)
+
+    # barycentric coordinates of q in T (eqs. C0, C1), exact
+    P = [xy(k) for k in T]
+    D = (P[1][0] - P[0][0]) * (P[2][1] - P[0][1]) - (P[1][1] - P[0][1]) * (P[2][0] - P[0][0])
+    phi = [((P[1][0] - qx) * (P[2][1] - qy) - (P[1][1] - qy) * (P[2][0] - qx)) / D,
+           ((qx - P[0][0]) * (P[2][1] - P[0][1]) - (qy - P[0][1]) * (P[2][0] - P[0][0])) / D,
+           ((P[1][0] - P[0][0]) * (qy - P[0][1]) - (P[1][1] - P[0][1]) * (qx - P[0][0])) / D]
+    row = {}
+    for k, f in zip(T, phi):
+        row[k] = row.get(k, 0) + f
+    for a, b in ((0, 1), (1, 2), (2, 0)):
+        nu, sg = T[a], T[b]
+        S = sorted(support_of_edge(nu, sg))
+        pts = [xy(k) for k in S]
+        (xn, yn), (xs, ys) = xy(nu), xy(sg)
+        Ms = sympy.Matrix([[1] * len(S), [p[0] for p in pts], [p[1] for p in pts],
+                           [p[0] ** 2 for p in pts], [p[0] * p[1] for p in pts],
+                           [p[1] ** 2 for p in pts]])
+        bs = sympy.Matrix([0, 0, 0,
+                           half * (2 * xn * xs - xn ** 2 - xs ** 2),
+                           half * (xn * ys + xs * yn - xn * yn - xs * ys),
+                           half * (2 * yn * ys - yn ** 2 - ys ** 2)])
+        As = Ms.T * (Ms * Ms.T).LUsolve(bs)
+        for k, v in zip(S, As):
+            row[k] = row.get(k, 0) + 2 * phi[a] * phi[b] * v
+    return {k: float(sympy.N(v, 30)) for k, v in row.items()}
+
+
+def test_equilateral_lattice_whole_row_from_lattice_rings():
+    """A whole oracle row equals phi + 2 sum_e phi_nu phi_sigma A_e with each
+    A_e solved exactly over its own edge's support ring(nu) U ring(sigma),
+    where the rings are the lattice's six neighbours (not the oracle's
+    triangulation).  The same construction with the node's full support for
+    every edge gives a different row, so the oracle's choice of S_e is what
+    this test pins."""
+    ij = [(i, j) for j in range(-6, 7) for i in range(-6, 7)]
+    rt3 = np.sqrt(3.0)
+    pos = np.array([[i + 0.5 * j, 0.5 * rt3 * j] for i, j in ij])
+    col = {k: n for n, k in enumerate(ij)}
+    # dyadic mesh offsets put the nodes strictly inside lattice triangles
+    mesh = Mesh(19, 12, 1.0, -9.75, -5.875)
+    nodes = mesh.nodes()
+    node_ids = [6 * 20 + 10, 5 * 20 + 9, 7 * 20 + 11]
+    W, info = P2MOracle(pos, mesh, 0.5).matrix(np.asarray(node_ids))
+    nbr = ((1, 0), (-1, 0), (0, 1), (0, -1), (1, -1), (-1, 1))
+
+    def ring(k):
+        return {(k[0] + di, k[1] + dj) for di, dj in nbr}
+
+    for t, k in enumerate(node_ids):
+        assert not info["closure"][t]
+        got = W[t].toarray().ravel()
+        want = np.zeros_like(got)
+        for key, v in _lattice_row(nodes[k], lambda a, b: ring(a) | ring(b)).items():
+            want[col[key]] = v
+        assert np.count_nonzero(got) == np.count_nonzero(want)
+        assert np.abs(got - want).max() <= 1e-13
+        # negative control: every edge over the node's whole support U
+        U = set()
+        for key in _lattice_row(nodes[k], lambda a, b: ring(a) | ring(b)):
+            U |= {key}
+        alt = np.zeros_like(got)
+        for key, v in _lattice_row(nodes[k], lambda a, b: U).items():
+            alt[col[key]] = v
+        assert np.abs(alt - want).max() > 1e-3
 
 
 def test_interpolates_at_a_particle():
