@@ -82,7 +82,9 @@ typedef struct p2m_diag {
     int64_t interior_nodes;     /* nodes with a Delaunay triangle              */
     int64_t closure_nodes;      /* boundary-ring + outside-hull nodes          */
     int64_t outside_hull_nodes; /* subset of closure_nodes                     */
-    int64_t rank_deficient;     /* moment systems solved by the pseudo-inverse */
+    int64_t rank_deficient;     /* moment systems of rank below 6: their
+                                   weights are the minimum-norm least-squares
+                                   answer (see svd_systems)                    */
     int64_t cap_overflow;       /* nodes whose support exceeded the ELL width  */
     int64_t escalated_nodes;    /* nodes that needed a larger search region    */
     int64_t global_nodes;       /* nodes that needed a scan of every particle  */
@@ -94,7 +96,32 @@ typedef struct p2m_diag {
                                    to the exact fallback (performance only)    */
     int32_t status;             /* P2M_OK, P2M_EDOMAIN, P2M_ECAP or P2M_EGEOM  */
     int32_t support_max;        /* largest support of any node                 */
+    int64_t svd_systems;        /* moment systems solved by the rank-revealing
+                                   solver (below)                              */
+    double max_gram_cond;       /* largest cond2(G), G = M M^t, of a full-rank
+                                   moment system: an estimate within a factor
+                                   36 above it for systems solved by Cholesky,
+                                   exact for the others                        */
+    int64_t bwd_rank_deficient; /* rank-deficient systems whose position
+                                   derivative the last
+                                   p2m_build_weights_backward on this handle
+                                   left out (see that call)                    */
 } p2m_diag;
+
+/* How each moment system M A = b (6 conditions, K support particles) is
+ * solved.  The paper solves them by SVD with automatic rank detection
+ * (App. A); the answer is the minimum-norm solution, with singular values of
+ * M at or below eps * max(6, K) * s_max taken as zero (LAPACK's default
+ * threshold).  For speed, a system is first solved through its Gram matrix
+ * G = M M^t (Cholesky, one step of iterative refinement), which gives that
+ * answer to about eps * cond(M) as long as G is well conditioned: a system
+ * whose estimate trace(G) trace(G^-1) exceeds the option "svd_cond"
+ * (default 1e8, i.e. cond(M) of about 1e4), or whose Cholesky breaks down,
+ * is solved instead by a one-sided Jacobi SVD of M, with the rule above, in
+ * the frame in which its conditions are stated (edge systems: relative to
+ * the edge's ends, scaled by its length; closure systems: relative to the
+ * node, in units of h).  Such a row is flagged, and counted in svd_systems;
+ * a system of rank below 6 is counted in rank_deficient. */
 
 /* Opaque weights handle: the P2M operator of one particle set on one mesh.
  * Owned by the library; holds device memory until p2m_weights_destroy(). */
@@ -375,7 +402,8 @@ int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, 
                                      double* grad_pos, void* stream);
 
 /* Process-wide tuning knobs for the weight build (performance only; results
- * do not depend on them).  Not thread-safe with concurrent builds.
+ * do not depend on them, "svd_cond" aside, which moves them by rounding
+ * only).  Not thread-safe with concurrent builds.
  *   "bin_scale"  bin width ~ bin_scale * h        (0.25 .. 8,  default 1)
  *   "fast_radius" candidate radius / h of the
  *                register-resident first pass     (1.5 .. 8,   default 2.6)
@@ -385,6 +413,9 @@ int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, 
  *                the fallback pass                (1 .. 64,    default 4)
  *   "levels"     region doublings before a scan
  *                of every particle                (0 .. 8,     default 3)
+ *   "svd_cond"   condition estimate of a moment system above which it is
+ *                solved by the SVD (see p2m_diag)  (1 .. 1e16, default 1e8;
+ *                results change only by rounding)
  * Returns P2M_EINVAL for an unknown name or a value out of range. */
 int p2m_set_option(const char* name, double value);
 

@@ -45,6 +45,9 @@ class P2MDiag(ctypes.Structure):
         ("slow_nodes", c_int64),
         ("status", c_int32),
         ("support_max", c_int32),
+        ("svd_systems", c_int64),
+        ("max_gram_cond", c_double),
+        ("bwd_rank_deficient", c_int64),
     ]
 
     def as_dict(self):

@@ -17,8 +17,19 @@
 //     depends on the two edge ends.
 // Contributions are accumulated per support entry in LDS and added to
 // grad_pos with one pair of atomics per entry.
+//
+// Rows the forward solved with the rank-revealing solver (flag MF_SVD) are
+// differentiated by a second kernel, one wave per row, from the SVD of each
+// system: for a full-rank system the formula above with G^-1 = V S^-2 V^t.
+// A system of rank below 6 has least-squares weights that are not
+// differentiable where the rank changes (and depend on the frame of its
+// conditions): the derivative through its coefficients is left out and
+// counted (diag D_BWDSKIP); its part through the barycentric factors is kept.
+// Both kernels use the forward's algebra (algebra.h): its Cholesky with
+// reciprocal pivots and the same SVD.
 #include <cfloat>
 
+#include "algebra.h"
 #include "kernels.h"
 
 namespace p2m {
@@ -26,65 +37,6 @@ namespace p2m {
 namespace {
 
 constexpr int WG = 64;
-
-__device__ __forceinline__ void monos(double x, double y, double p[6]) {
-    p[0] = 1.0;
-    p[1] = x;
-    p[2] = y;
-    p[3] = x * x;
-    p[4] = x * y;
-    p[5] = y * y;
-}
-
-__device__ void gram_add(double G[6][6], const double p[6]) {
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j <= i; ++j) G[i][j] += p[i] * p[j];
-}
-
-__device__ bool chol(double G[6][6]) {
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const double djj = G[j][j];
-        double d = djj;
-#pragma unroll
-        for (int k = 0; k < j; ++k) d -= G[j][k] * G[j][k];
-        if (!(d > 1e-12 * djj)) return false;
-        const double r = sqrt(d);
-        G[j][j] = r;
-#pragma unroll
-        for (int i = j + 1; i < 6; ++i) {
-            double s = G[i][j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) s -= G[i][k] * G[j][k];
-            G[i][j] = s / r;
-        }
-    }
-    return true;
-}
-
-__device__ void csolve(const double L[6][6], const double b[6], double y[6]) {
-    double z[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        double s = b[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
-        z[i] = s / L[i][i];
-    }
-#pragma unroll
-    for (int i = 5; i >= 0; --i) {
-        double s = z[i];
-#pragma unroll
-        for (int k = i + 1; k < 6; ++k) s -= L[k][i] * y[k];
-        y[i] = s / L[i][i];
-    }
-}
-
-__device__ __forceinline__ double dot6(const double a[6], const double b[6]) {
-    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
-}
 
 struct BArgs {
     WeightsView w;
@@ -111,10 +63,13 @@ __device__ bool block_backward(int n, Member member, Coord coord, const double b
         double x, yy, p[6];
         coord(k, x, yy);
         monos(x, yy, p);
-        gram_add(L, p);
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+#pragma unroll
+            for (int j2 = 0; j2 <= i; ++j2) L[i][j2] += p[i] * p[j2];
     }
-    if (!chol(L)) return false;
-    csolve(L, b, y);
+    if (!chol6(L)) return false;
+    chol6_solve(L, b, y);
     // refine y as the forward does
     double r[6] = {b[0], b[1], b[2], b[3], b[4], b[5]};
     double v[6] = {0, 0, 0, 0, 0, 0};
@@ -128,7 +83,7 @@ __device__ bool block_backward(int n, Member member, Coord coord, const double b
         for (int i = 0; i < 6; ++i) r[i] -= a * p[i];
     }
     double d[6];
-    csolve(L, r, d);
+    chol6_solve(L, r, d);
 #pragma unroll
     for (int i = 0; i < 6; ++i) y[i] += d[i];
     for (int k = 0; k < n; ++k) {
@@ -141,7 +96,7 @@ __device__ bool block_backward(int n, Member member, Coord coord, const double b
         for (int i = 0; i < 6; ++i) v[i] += ab * p[i];
     }
     double z[6];
-    csolve(L, v, z);
+    chol6_solve(L, v, z);
     for (int k = 0; k < n; ++k) {
         if (!member(k)) continue;
         double x, yy, p[6];
@@ -179,6 +134,7 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
     const uint32_t type = meta_type(meta);
     const int n = row_len(meta);
     if (type == NT_FAILED || n == 0) return;
+    if (meta_flags(meta) & MF_SVD) return;  // k_build_bwd_svd
     const int64_t nn = a.w.n_nodes, ns = a.w.n_slots;
     const bool per = a.per != 0;
     const double2 q = node_at(m, i, j, per);
@@ -227,7 +183,12 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
             const double dx = dxv * is, dy = dyv * is;
             const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
             double y[6], bb[6];
-            if (!block_backward(n, member, coord, b, abar, addsc, y, bb)) continue;
+            if (!block_backward(n, member, coord, b, abar, addsc, y, bb)) {
+                // (the forward's Cholesky accepted this system with a wide
+                // margin, so this does not happen; counted if it does)
+                atomicAdd(&a.w.diag[D_BWDSKIP], 1ull);
+                continue;
+            }
             // sum_mu wbar_mu A_mu feeds phibar of the two edge ends
             double sa = 0.0;
             for (int k = 0; k < n; ++k) {
@@ -277,12 +238,173 @@ __global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
         double b[6];
         monos((q.x - mx) * isc, (q.y - my) * isc, b);
         double y[6], bb[6];
-        block_backward(n, member, coord, b, wbar, addsc, y, bb);
+        if (!block_backward(n, member, coord, b, wbar, addsc, y, bb)) atomicAdd(&a.w.diag[D_BWDSKIP], 1ull);
     }
     for (int k = 0; k < n; ++k) {
         const int64_t u = a.w.idx[k * ns + slot];
         atomicAdd(&a.gpos[u].x, gx[k * WG]);
         atomicAdd(&a.gpos[u].y, gy[k * WG]);
+    }
+}
+
+// Rows of the rank-revealing solver (listed by the build): one wave per row,
+// support entry k in lane k.  Each system is factored exactly as the forward
+// factored it (same frame, same SVD), so its coefficients are the forward's.
+// For a full-rank system, y = V S^-2 V^t b and z = V S^-2 (B V)^t Abar give
+// Mbar = y Abar^t - z A^t - y (z^t M) and bbar = z, chained through the
+// condition vectors of the frame (relative to the edge ends, or to the node
+// in units of h), whose reference points are held fixed: the solution of a
+// full-rank system does not depend on them.
+__global__ void __launch_bounds__(256) k_build_bwd_svd(BArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int count = static_cast<int>(a.w.diag[D_RDCNT]);
+    const int waves = static_cast<int>(gridDim.x) * 4;
+    const int w0 = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * 4 + threadIdx.x / 64));
+    const int64_t nn = a.w.n_nodes, ns = a.w.n_slots;
+    const bool per = a.per != 0;
+    for (int li = w0; li < count; li += waves) {
+        const int64_t slot = a.w.rd[li];
+        const SetDesc& sd = a.w.sets[set_search(a.w.S, slot / TILE_N, [&](int s) { return a.w.sets[s].t0; })];
+        int i, j;
+        if (!slot_ij(sd, slot, i, j)) continue;
+        const int64_t node = ij_node(sd, i, j);
+        const uint32_t meta = a.w.meta[slot];
+        const uint32_t type = meta_type(meta);
+        const uint32_t flags = meta_flags(meta);
+        const int n = row_len(meta);
+        if (type == NT_FAILED || n == 0 || !(flags & MF_SVD)) continue;
+        const double2 q = node_at(sd.m, i, j, per);
+        const bool in = lane < n;
+        int64_t u = 0;
+        double2 p = make_double2(0.0, 0.0);
+        double wb = 0.0;
+        uint32_t bits = 0;
+        if (in) {
+            u = a.w.idx[lane * ns + slot];
+            const double2 r = a.pos[u];
+            p = per ? image_near(sd.m, r, q) : r;
+            wb = a.gw[lane * nn + node];
+            bits = a.w.mem[lane * ns + slot];
+        }
+        double gx = 0.0, gy = 0.0;
+        int skipped = 0;
+        WaveSVD sv;
+        // the full-rank adjoint of one factored system, this lane's share:
+        // dL/d(condition vector pk) in pbar
+        auto adjoint = [&](const double b[6], const double pk[6], double ab, double pbar[6], double z[6]) {
+            double c[6], t[6], y[6], uu[6];
+            wave_vt(sv, b, lane, c);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) t[k] = c[k] / (sv.s[k] * sv.s[k]);
+            wave_v(sv, t, y);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) uu[k] = uniform(wave_sum(sv.B[k] * ab)) / (sv.s[k] * sv.s[k]);
+            wave_v(sv, uu, z);
+            const double Ak = dot6(pk, y), zp = dot6(z, pk);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) pbar[k] = y[k] * ab - z[k] * Ak - y[k] * zp;
+        };
+        if (type == NT_INTERIOR) {
+            const int lt[3] = {static_cast<int>(meta_t(meta, 0)), static_cast<int>(meta_t(meta, 1)),
+                               static_cast<int>(meta_t(meta, 2))};
+            double2 P[3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) P[k] = make_double2(lane_value(p.x, lt[k]), lane_value(p.y, lt[k]));
+            const double D = (P[1].x - P[0].x) * (P[2].y - P[0].y) - (P[1].y - P[0].y) * (P[2].x - P[0].x);
+            const double phi[3] = {((P[1].x - q.x) * (P[2].y - q.y) - (P[1].y - q.y) * (P[2].x - q.x)) / D,
+                                   ((q.x - P[0].x) * (P[2].y - P[0].y) - (q.y - P[0].y) * (P[2].x - P[0].x)) / D,
+                                   ((P[1].x - P[0].x) * (q.y - P[0].y) - (P[1].y - P[0].y) * (q.x - P[0].x)) / D};
+            double phib[3] = {lane_value(wb, lt[0]), lane_value(wb, lt[1]), lane_value(wb, lt[2])};
+#pragma unroll
+            for (int ed = 0; ed < 3; ++ed) {
+                const int pa = ed, pb = ed == 2 ? 0 : ed + 1;
+                const double2 rn = P[pa], rs = P[pb];
+                const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
+                const double is = 1.0 / sqrt(dxv * dxv + dyv * dyv);
+                const bool mem = in && (((bits >> pa) & 1u) || ((bits >> pb) & 1u));
+                const int keff = __popcll(__ballot(mem));
+                const double ax = (p.x - rn.x) * is, ay = (p.y - rn.y) * is;
+                const double cx = (p.x - rs.x) * is, cy = (p.y - rs.y) * is;
+                double pk[6] = {1.0, ax, ay, ax * cx, 0.5 * (ax * cy + ay * cx), ay * cy};
+                if (!mem) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) pk[k] = 0.0;
+                }
+#pragma unroll
+                for (int k = 0; k < 6; ++k) sv.B[k] = pk[k];
+                wave_svd(sv, lane, keff);
+                const double dx = dxv * is, dy = dyv * is;
+                const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
+                const double A = wave_svd_solve(sv, b, lane);
+                // sum_mu wbar_mu A_mu feeds phibar of the two edge ends
+                const double sa = uniform(wave_sum(mem ? wb * A : 0.0));
+                phib[pa] += 2.0 * phi[pb] * sa;
+                phib[pb] += 2.0 * phi[pa] * sa;
+                if (flags & (MF_RD0 << ed)) {
+                    ++skipped;
+                    continue;
+                }
+                const double coef = 2.0 * phi[pa] * phi[pb];
+                double pbar[6], z[6];
+                adjoint(b, pk, mem ? coef * wb : 0.0, pbar, z);
+                if (mem) {
+                    // d pk / dx = (0, 1, 0, a_x + c_x, (a_y + c_y) / 2, 0) / s, likewise y
+                    gx += is * (pbar[1] + (ax + cx) * pbar[3] + 0.5 * (ay + cy) * pbar[4]);
+                    gy += is * (pbar[2] + 0.5 * (ax + cx) * pbar[4] + (ay + cy) * pbar[5]);
+                }
+                // right-hand side: d = (r_nu - r_sigma) / s
+                const double ddx = -z[3] * dx - 0.5 * z[4] * dy;
+                const double ddy = -0.5 * z[4] * dx - z[5] * dy;
+                if (lane == lt[pa]) {
+                    gx += ddx * is;
+                    gy += ddy * is;
+                }
+                if (lane == lt[pb]) {
+                    gx -= ddx * is;
+                    gy -= ddy * is;
+                }
+            }
+            // barycentric coordinates
+            const double e1x = P[1].x - P[0].x, e1y = P[1].y - P[0].y, e2x = P[2].x - P[0].x, e2y = P[2].y - P[0].y;
+            const double f1 = phib[1] - phib[0], f2 = phib[2] - phib[0];
+            const double lx = (f1 * e2y - f2 * e1y) / D;
+            const double ly = (-f1 * e2x + f2 * e1x) / D;
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                if (lane == lt[k]) {
+                    gx -= phi[k] * lx;
+                    gy -= phi[k] * ly;
+                }
+        } else {
+            // closure: the monomials of (r - q) / h against p(0)
+            const double ih = 1.0 / sd.h;
+            const double x = (p.x - q.x) * ih, y = (p.y - q.y) * ih;
+            double pk[6];
+            monos(x, y, pk);
+            if (!in) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) pk[k] = 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) sv.B[k] = pk[k];
+            wave_svd(sv, lane, n);
+            if (flags & MF_RD0) {
+                skipped = 1;
+            } else {
+                const double b[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+                double pbar[6], z[6];
+                adjoint(b, pk, in ? wb : 0.0, pbar, z);
+                if (in) {
+                    gx += ih * (pbar[1] + 2.0 * x * pbar[3] + y * pbar[4]);
+                    gy += ih * (pbar[2] + x * pbar[4] + 2.0 * y * pbar[5]);
+                }
+            }
+        }
+        if (in) {
+            atomicAdd(&a.gpos[u].x, gx);
+            atomicAdd(&a.gpos[u].y, gy);
+        }
+        if (lane == 0 && skipped) atomicAdd(&a.w.diag[D_BWDSKIP], static_cast<unsigned long long>(skipped));
     }
 }
 
@@ -319,8 +441,16 @@ int build_backward(const WeightsView& w, const double* pos, const double* grad_w
     a.gw = grad_w;
     a.gpos = reinterpret_cast<double2*>(grad_pos);
     a.per = periodic ? 1 : 0;
+    // (the count of left-out systems starts at zero for every call: a fill
+    // kernel, so that the call can be captured in a graph)
+    int rc = fill_u64(w.diag + D_BWDSKIP, 0ull, 1, st);
+    if (rc) return rc;
     const int blocks = static_cast<int>((w.n_nodes + WG - 1) / WG);
     k_build_bwd<<<blocks, WG, 0, st>>>(a);
+    P2M_HIP(hipGetLastError());
+    // rows of the rank-revealing solver (normally none; the grid loops over
+    // the list)
+    k_build_bwd_svd<<<16, 256, 0, st>>>(a);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }

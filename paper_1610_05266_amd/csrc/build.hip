@@ -55,6 +55,7 @@
 #include <cfloat>
 #include <climits>
 
+#include "algebra.h"
 #include "kernels.h"
 
 namespace p2m {
@@ -960,99 +961,12 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
 }
 
 // ---------------------------------------------------------------- algebra
-__device__ __forceinline__ void monos(double x, double y, double p[6]) {
-    p[0] = 1.0;
-    p[1] = x;
-    p[2] = y;
-    p[3] = x * x;
-    p[4] = x * y;
-    p[5] = y * y;
-}
+// (moment sums, Cholesky and the rank-revealing solver: algebra.h)
 
-__device__ __forceinline__ double dot6(const double a[6], const double b[6]) {
-    return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3] + a[4] * b[4] + a[5] * b[5];
-}
-
-// The 15 power sums m_ab = sum x^a y^b (a + b <= 4).
-struct Moments {
-    double m[15];  // 00 10 01 20 11 02 30 21 12 03 40 31 22 13 04
-    __device__ void zero() {
-#pragma unroll
-        for (int i = 0; i < 15; ++i) m[i] = 0.0;
-    }
-    __device__ void add(double x, double y) {
-        const double x2 = x * x, y2 = y * y, xy = x * y;
-        m[0] += 1.0;
-        m[1] += x;
-        m[2] += y;
-        m[3] += x2;
-        m[4] += xy;
-        m[5] += y2;
-        m[6] += x2 * x;
-        m[7] += x2 * y;
-        m[8] += x * y2;
-        m[9] += y2 * y;
-        m[10] += x2 * x2;
-        m[11] += x2 * xy;
-        m[12] += x2 * y2;
-        m[13] += xy * y2;
-        m[14] += y2 * y2;
-    }
-    // Gram matrix of p = (1, x, y, x^2, xy, y^2), lower triangle.
-    __device__ void gram(double G[6][6]) const {
-        G[0][0] = m[0];
-        G[1][0] = m[1]; G[1][1] = m[3];
-        G[2][0] = m[2]; G[2][1] = m[4]; G[2][2] = m[5];
-        G[3][0] = m[3]; G[3][1] = m[6]; G[3][2] = m[7]; G[3][3] = m[10];
-        G[4][0] = m[4]; G[4][1] = m[7]; G[4][2] = m[8]; G[4][3] = m[11]; G[4][4] = m[12];
-        G[5][0] = m[5]; G[5][1] = m[8]; G[5][2] = m[9]; G[5][3] = m[12]; G[5][4] = m[13]; G[5][5] = m[14];
-    }
-};
-
-// In-place Cholesky of the lower triangle; false if a pivot is not clearly
-// positive (relative threshold on the squared pivot).
-__device__ bool chol6(double G[6][6]) {
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        const double djj = G[j][j];
-        double d = djj;
-#pragma unroll
-        for (int k = 0; k < j; ++k) d -= G[j][k] * G[j][k];
-        if (!(d > 1e-12 * djj)) return false;
-        const double ir = 1.0 / sqrt(d);
-        G[j][j] = ir;  // the diagonal keeps 1 / L_jj
-#pragma unroll
-        for (int i = j + 1; i < 6; ++i) {
-            double s = G[i][j];
-#pragma unroll
-            for (int k = 0; k < j; ++k) s -= G[i][k] * G[j][k];
-            G[i][j] = s * ir;
-        }
-    }
-    return true;
-}
-
-__device__ void chol6_solve(const double L[6][6], const double b[6], double y[6]) {
-    double z[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        double s = b[i];
-#pragma unroll
-        for (int k = 0; k < i; ++k) s -= L[i][k] * z[k];
-        z[i] = s * L[i][i];
-    }
-#pragma unroll
-    for (int i = 5; i >= 0; --i) {
-        double s = z[i];
-#pragma unroll
-        for (int k = i + 1; k < 6; ++k) s -= L[k][i] * y[k];
-        y[i] = s * L[i][i];
-    }
-}
-
-// Pseudo-inverse solve by cyclic Jacobi (rank-deficient systems only).
-// Eigenvalues below 1e-12 * lambda_max (singular values of the monomial
-// matrix below 1e-6 sigma_max) are dropped.
+// Pseudo-inverse solve by cyclic Jacobi of the Gram matrix, for the mesh-side
+// edge table (one thread per mesh edge; the systems of edges at the mesh
+// boundary lose rank exactly, the others are well conditioned).  Eigenvalues
+// below 1e-12 * lambda_max are dropped.
 __device__ void pinv6_solve(const Moments& mo, const double b[6], double y[6]) {
     double Gl[6][6], A[6][6], V[6][6];
     mo.gram(Gl);
@@ -1128,10 +1042,12 @@ struct KArgs {
     BuildOut out;
     int32_t* slow;        // slow-path list of row slots (capacity n_nodes)
     int32_t* rd;          // rank-deficient list of row slots (capacity n_nodes)
-    int32_t* tdiag;       // [n_slots / TILE_N][4] per-tile counts of k_weights
+    int32_t* tdiag;       // [n_slots / TILE_N][5] per-tile counts of k_weights
     unsigned long long* diag;
     int linear;           // interior rows: barycentric coordinates in T only
     int per;              // periodic box: nearest images, no boundary ring
+    double svd_kappa;     // a system whose estimate trace(G) trace(G^-1)
+                          // exceeds this goes to the rank-revealing solver
 };
 
 // The set of a node tile / of a row slot.
@@ -1143,205 +1059,118 @@ __device__ __forceinline__ SetDesc slot_set(const KArgs& a, int64_t slot) { retu
 
 __device__ __forceinline__ uint32_t pending_type(uint32_t t) { return t == NT_OUTSIDE ? NT_PEND_OUT : NT_PEND_RING; }
 
-// Interior weights of one node, computed by the four lanes of its quad.
-// The support entries come from `uget(k)` (sorted index | bits << 28); entry
-// k belongs to lane k % 4.
-template <bool PER, class UGet>
-__device__ void quad_weights(const KArgs& a, const MeshD& m, int64_t slot, double2 q, UGet uget, int n,
-                             const int T[3], int lane, uint32_t flags) {
-    auto img = [&](double2 p) { return PER ? image_near(m, p, q) : p; };
-    int mt[MS];
-    int mb[MS];
-    double mx[MS], my[MS], mw[MS];
-#pragma unroll
-    for (int s = 0; s < MS; ++s) {
-        const int k = s * QL + lane;
-        mt[s] = -1;
-        mb[s] = 0;
-        mx[s] = my[s] = mw[s] = 0.0;
-        if (k < n) {
-            const uint32_t e = static_cast<uint32_t>(uget(k));
-            mt[s] = static_cast<int>(e & IDX_MASK);
-            mb[s] = static_cast<int>(e >> 28);
-            const double2 p = img(a.pos_s[mt[s]]);
-            mx[s] = p.x;
-            my[s] = p.y;
-        }
+// Weights of one row by the rank-revealing solver, one wave per row, support
+// entry k in lane k (KMAX <= WAVE).  Every system of the row is solved by
+// one-sided Jacobi in the frame in which the conditions are stated:
+//  * interior: for each edge e = (nu, sigma) of T, the rows of eqs. (A0),
+//    (A1), (A2_2) relative to the edge ends, a = (r - r_nu) / s and
+//    c = (r - r_sigma) / s with s = |r_nu - r_sigma|:
+//    (1, a_x, a_y, a_x c_x, (a_x c_y + a_y c_x) / 2, a_y c_y) A = (0, 0, 0,
+//    -d_x^2 / 2, -d_x d_y / 2, -d_y^2 / 2), d = (r_nu - r_sigma) / s;
+//  * closure: the monomials of (r - q) / h against p(0).
+// For a full-rank system the answer does not depend on the frame; below
+// rank 6 the least-squares answer does, and this is the frame of the
+// conditions as written.  Singular values below eps max(6, K) s_max are
+// dropped.  Writes the finished row (user ids, weights, ring bits, meta);
+// returns the number of systems solved, with the number of them below rank
+// 6 in `nrd` and the largest cond2(G) of the full-rank ones in `kmax`.
+template <bool PER>
+__device__ int wave_row_svd(const KArgs& a, const SetDesc& sd, int64_t slot, double2 q, int lane, int& nrd,
+                            double& kmax) {
+    const int64_t nn = a.n_slots;
+    const uint32_t meta = a.out.meta[slot];
+    const uint32_t type = meta_type(meta);
+    const int n = static_cast<int>(meta_cnt(meta));
+    const bool in = lane < n;
+    uint32_t e = 0;
+    double2 p = make_double2(0.0, 0.0);
+    int32_t uid = 0;
+    if (in) {
+        e = static_cast<uint32_t>(a.out.idx[lane * nn + slot]) | (static_cast<uint32_t>(a.out.mem[lane * nn + slot]) << 28);
+        const double2 r = a.pos_s[e & IDX_MASK];
+        p = PER ? image_near(sd.m, r, q) : r;
+        uid = a.perm[e & IDX_MASK];
     }
-    const double2 P[3] = {img(a.pos_s[T[0]]), img(a.pos_s[T[1]]), img(a.pos_s[T[2]])};
-    // barycentric coordinates of q in T (linear FE, eqs. C0, C1)
-    const double D = orient(P[0], P[1], P[2]);
-    const double phi[3] = {orient(q, P[1], P[2]) / D, orient(P[0], q, P[2]) / D, orient(P[0], P[1], q) / D};
-    int lt[3] = {-1, -1, -1};
+    uint32_t flags = meta_flags(meta) | MF_SVD;
+    int nsys = 0;
+    nrd = 0;
+    kmax = 0.0;
+    double w = 0.0;
+    WaveSVD sv;
+    if (type == NT_PENDING) {
+        const int lt[3] = {static_cast<int>(meta_t(meta, 0)), static_cast<int>(meta_t(meta, 1)),
+                           static_cast<int>(meta_t(meta, 2))};
+        double2 P[3];
 #pragma unroll
-    for (int s = 0; s < MS; ++s)
+        for (int k = 0; k < 3; ++k) P[k] = make_double2(lane_value(p.x, lt[k]), lane_value(p.y, lt[k]));
+        // barycentric coordinates of q in T (linear FE, eqs. C0, C1)
+        const double D = orient(P[0], P[1], P[2]);
+        const double phi[3] = {orient(q, P[1], P[2]) / D, orient(P[0], q, P[2]) / D, orient(P[0], P[1], q) / D};
 #pragma unroll
         for (int k = 0; k < 3; ++k)
-            if (mt[s] == T[k]) {
-                mw[s] += phi[k];
-                lt[k] = s * QL + lane;
+            if (lane == lt[k]) w += phi[k];
+        if (!a.linear) {
+#pragma unroll
+            for (int ed = 0; ed < 3; ++ed) {
+                const int pa = ed, pb = ed == 2 ? 0 : ed + 1;
+                const double2 rn = P[pa], rs = P[pb];
+                const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
+                const double is = 1.0 / sqrt(dxv * dxv + dyv * dyv);
+                const bool mem = in && (((e >> 28) >> pa) & 1u || ((e >> 28) >> pb) & 1u);
+                const int keff = __popcll(__ballot(mem));
+                const double ax = (p.x - rn.x) * is, ay = (p.y - rn.y) * is;
+                const double cx = (p.x - rs.x) * is, cy = (p.y - rs.y) * is;
+                sv.B[0] = mem ? 1.0 : 0.0;
+                sv.B[1] = mem ? ax : 0.0;
+                sv.B[2] = mem ? ay : 0.0;
+                sv.B[3] = mem ? ax * cx : 0.0;
+                sv.B[4] = mem ? 0.5 * (ax * cy + ay * cx) : 0.0;
+                sv.B[5] = mem ? ay * cy : 0.0;
+                wave_svd(sv, lane, keff);
+                const double dx = dxv * is, dy = dyv * is;
+                const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
+                const double A = wave_svd_solve(sv, b, lane);
+                if (mem) w += 2.0 * phi[pa] * phi[pb] * A;
+                if (sv.rank < 6) {
+                    flags |= MF_RANKDEF | (MF_RD0 << ed);
+                    ++nrd;
+                } else {
+                    kmax = fmax(kmax, wave_svd_gram_cond(sv));
+                }
+                ++nsys;
             }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        lt[k] = max(lt[k], lane_xor<QL>(lt[k], 1));
-        lt[k] = max(lt[k], lane_xor<QL>(lt[k], 2));
-    }
-    for (int e = 0; e < 3; ++e) {
-        const int pa = e, pb = (e + 1) % 3;
-        const double2 rn = P[pa], rs = P[pb];
-        const double cxm = 0.5 * (rn.x + rs.x), cym = 0.5 * (rn.y + rs.y);
-        const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
-        const double is = 1.0 / sqrt(dxv * dxv + dyv * dyv);
-        const int mask = (1 << pa) | (1 << pb);
-        Moments mo;
-        mo.zero();
-#pragma unroll
-        for (int s = 0; s < MS; ++s)
-            if (mb[s] & mask) mo.add((mx[s] - cxm) * is, (my[s] - cym) * is);
-#pragma unroll
-        for (int i = 0; i < 15; ++i) mo.m[i] = quad_sum(mo.m[i]);
-        const double dx = dxv * is, dy = dyv * is;
-        const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
-        double y[6];
-        double L[6][6];
-        mo.gram(L);
-        if (chol6(L)) {
-            chol6_solve(L, b, y);
-            // one refinement step with the residual formed from the monomials
-            double r[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-            for (int s = 0; s < MS; ++s) {
-                if (!(mb[s] & mask)) continue;
-                double p[6];
-                monos((mx[s] - cxm) * is, (my[s] - cym) * is, p);
-                const double A = dot6(p, y);
-#pragma unroll
-                for (int i = 0; i < 6; ++i) r[i] += A * p[i];
-            }
-#pragma unroll
-            for (int i = 0; i < 6; ++i) r[i] = b[i] - quad_sum(r[i]);
-            double d[6];
-            chol6_solve(L, r, d);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) y[i] += d[i];
-        } else {
-            // rank-deficient: pseudo-inverse (moments recomputed, so they are
-            // not kept live across the Cholesky on the common path)
-            Moments m2;
-            m2.zero();
-#pragma unroll
-            for (int s = 0; s < MS; ++s)
-                if (mb[s] & mask) m2.add((mx[s] - cxm) * is, (my[s] - cym) * is);
-#pragma unroll
-            for (int i = 0; i < 15; ++i) m2.m[i] = quad_sum(m2.m[i]);
-            pinv6_solve(m2, b, y);
-            flags |= MF_RANKDEF;
-            if (lane == 0) atomicAdd(&a.diag[D_RANKDEF], 1ull);
         }
-        const double coef = 2.0 * phi[pa] * phi[pb];
-#pragma unroll
-        for (int s = 0; s < MS; ++s) {
-            if (!(mb[s] & mask)) continue;
-            double p[6];
-            monos((mx[s] - cxm) * is, (my[s] - cym) * is, p);
-            mw[s] += coef * dot6(p, y);
-        }
-    }
-    const int64_t nn = a.n_slots;
-#pragma unroll
-    for (int s = 0; s < MS; ++s) {
-        const int k = s * QL + lane;
-        if (k >= n) continue;
-        a.out.idx[k * nn + slot] = a.perm[mt[s]];
-        a.out.w64[k * nn + slot] = mw[s];
-        if (a.out.w32) a.out.w32[k * nn + slot] = static_cast<float>(mw[s]);
-        a.out.mem[k * nn + slot] = static_cast<uint8_t>(mb[s]);
-    }
-    if (lane == 0) a.out.meta[slot] = meta_pack(NT_INTERIOR, n, lt[0], lt[1], lt[2], flags);
-}
-
-// Closure weights of one node from its nearest particles (sorted indices in
-// the ELL row): minimum-norm solution of the quadratic moment conditions
-// sum_mu w_mu p(r_mu) = p(q), in coordinates centred at the particles'
-// centroid and scaled by their RMS radius (the weights do not depend on the
-// centre and scale; these keep the system well conditioned).
-constexpr int MC = (KNN + QL - 1) / QL;
-
-__device__ void quad_closure(const KArgs& a, int64_t slot, double2 q, int n, int lane, uint32_t type,
-                             uint32_t flags) {
-    const int64_t nn = a.n_slots;
-    int mt[MC];
-    double mx[MC], my[MC];
-    double sx = 0.0, sy = 0.0;
-#pragma unroll
-    for (int s = 0; s < MC; ++s) {
-        const int k = s * QL + lane;
-        mt[s] = -1;
-        mx[s] = my[s] = 0.0;
-        if (k < n) {
-            mt[s] = a.out.idx[k * nn + slot];
-            const double2 p = a.pos_s[mt[s]];
-            mx[s] = p.x;
-            my[s] = p.y;
-            sx += p.x;
-            sy += p.y;
-        }
-    }
-    const double cx = quad_sum(sx) / n, cy = quad_sum(sy) / n;
-    double r2 = 0.0;
-#pragma unroll
-    for (int s = 0; s < MC; ++s)
-        if (mt[s] >= 0) r2 += (mx[s] - cx) * (mx[s] - cx) + (my[s] - cy) * (my[s] - cy);
-    r2 = quad_sum(r2);
-    const double isc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
-    Moments mo;
-    mo.zero();
-#pragma unroll
-    for (int s = 0; s < MC; ++s)
-        if (mt[s] >= 0) mo.add((mx[s] - cx) * isc, (my[s] - cy) * isc);
-#pragma unroll
-    for (int i = 0; i < 15; ++i) mo.m[i] = quad_sum(mo.m[i]);
-    double b[6];
-    monos((q.x - cx) * isc, (q.y - cy) * isc, b);
-    double y[6];
-    double L[6][6];
-    mo.gram(L);
-    if (chol6(L)) {
-        chol6_solve(L, b, y);
-        double r[6] = {0, 0, 0, 0, 0, 0};
-#pragma unroll
-        for (int s = 0; s < MC; ++s) {
-            if (mt[s] < 0) continue;
-            double p[6];
-            monos((mx[s] - cx) * isc, (my[s] - cy) * isc, p);
-            const double A = dot6(p, y);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) r[i] += A * p[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 6; ++i) r[i] = b[i] - quad_sum(r[i]);
-        double d[6];
-        chol6_solve(L, r, d);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) y[i] += d[i];
     } else {
-        pinv6_solve(mo, b, y);
-        flags |= MF_RANKDEF;
-        if (lane == 0) atomicAdd(&a.diag[D_RANKDEF], 1ull);
-    }
+        // closure: minimum-norm weights of the quadratic moment conditions
+        const double ih = 1.0 / sd.h;
+        monos((p.x - q.x) * ih, (p.y - q.y) * ih, sv.B);
+        if (!in) {
 #pragma unroll
-    for (int s = 0; s < MC; ++s) {
-        const int k = s * QL + lane;
-        if (mt[s] < 0) continue;
-        double p[6];
-        monos((mx[s] - cx) * isc, (my[s] - cy) * isc, p);
-        const double w = dot6(p, y);
-        a.out.idx[k * nn + slot] = a.perm[mt[s]];
-        a.out.w64[k * nn + slot] = w;
-        if (a.out.w32) a.out.w32[k * nn + slot] = static_cast<float>(w);
-        a.out.mem[k * nn + slot] = 0;
+            for (int t = 0; t < 6; ++t) sv.B[t] = 0.0;
+        }
+        wave_svd(sv, lane, n);
+        const double b[6] = {1.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        w = wave_svd_solve(sv, b, lane);
+        if (sv.rank < 6) {
+            flags |= MF_RANKDEF | MF_RD0;
+            nrd = 1;
+        } else {
+            kmax = wave_svd_gram_cond(sv);
+        }
+        nsys = 1;
     }
-    if (lane == 0) a.out.meta[slot] = meta_pack(type, n, 0, 0, 0, flags);
+    if (in) {
+        a.out.idx[lane * nn + slot] = uid;
+        a.out.w64[lane * nn + slot] = w;
+        if (a.out.w32) a.out.w32[lane * nn + slot] = static_cast<float>(w);
+        a.out.mem[lane * nn + slot] = type == NT_PENDING ? static_cast<uint8_t>(e >> 28) : 0;
+    }
+    if (lane == 0) {
+        const uint32_t ft = type == NT_PENDING ? NT_INTERIOR : (type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING);
+        a.out.meta[slot] = type == NT_PENDING ? meta_pack(ft, n, meta_t(meta, 0), meta_t(meta, 1), meta_t(meta, 2), flags)
+                                              : meta_pack(ft, n, 0, 0, 0, flags);
+    }
+    return nsys;
 }
 
 // ------------------------------------------------------------ fast kernel
@@ -1634,8 +1463,13 @@ constexpr int SKP = SK + 1;  // row pitch: conflict-free LDS banks across quads
 // stream while the fast rows are being weighted).
 // Diagnostic counts of one wave's rows: interior, closure and outside-hull
 // rows, and the largest support.
+// Per-tile record of the weights pass: the four counts, then the largest
+// condition estimate (FP32 bits).
+constexpr int TD = BUILD_TD, TD_KMAX = 4;
+static_assert(TD == 5, "four counts and the condition estimate");
 struct WaveCounts {
     int c[4];
+    float kmax;  // largest condition estimate of a system solved by Cholesky
 };
 enum { WC_INTERIOR, WC_CLOSURE, WC_OUTSIDE, WC_SUPMAX };
 
@@ -1709,6 +1543,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
         return img(a.pos_s[a.out.idx[k * nn + slot]]);
     };
     int ok = 1;
+    double kap = 0.0;  // condition estimate of this lane's system
     double y[6] = {0, 0, 0, 0, 0, 0};
     // edge / closure frame: x~ = (p - c) * s
     double cx = 0.0, cy = 0.0, sc = 1.0, coef = 0.0;
@@ -1747,7 +1582,13 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
             });
             double L[6][6];
             mo.gram(L);
+            const double tr = mo.trace();
             ok = chol6(L) ? 1 : 0;
+            if (ok) {
+                // ill-conditioned systems go to the rank-revealing solver
+                kap = tr * chol6_inv_trace(L);
+                if (!(kap <= a.svd_kappa)) ok = 0;
+            }
             if (ok) {
                 chol6_solve(L, b, y);
                 double r[6] = {0, 0, 0, 0, 0, 0};
@@ -1797,7 +1638,12 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
         monos((q.x - cx) * sc, (q.y - cy) * sc, b);
         double L[6][6];
         mo.gram(L);
+        const double tr = mo.trace();
         ok = chol6(L) ? 1 : 0;
+        if (ok) {
+            kap = tr * chol6_inv_trace(L);
+            if (!(kap <= a.svd_kappa)) ok = 0;
+        }
         if (ok) {
             chol6_solve(L, b, y);
             double r[6] = {0, 0, 0, 0, 0, 0};
@@ -1820,7 +1666,8 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
     ok = min(ok, lane_xor<QL>(ok, 1));
     ok = min(ok, lane_xor<QL>(ok, 2));
     if ((pend || clos) && !ok) {
-        // rank-deficient: the row stays pending for k_weights_rd
+        // ill-conditioned or rank-deficient: the row stays pending for the
+        // rank-revealing solver (k_weights_rd)
         if (lane == 0 && sub == 0) {
             const int lpos = static_cast<int>(atomicAdd(&a.diag[D_RDCNT], 1ull));
             a.rd[lpos] = static_cast<int32_t>(slot);
@@ -1869,6 +1716,9 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
     int sup = (pend || clos) ? n : 0;
     for (int off = 32; off > 0; off >>= 1) sup = max(sup, __shfl_xor(sup, off));
     wc.c[WC_SUPMAX] = sup;
+    float kf = ((pend || clos) && ok) ? static_cast<float>(kap) : 0.0f;
+    for (int off = 32; off > 0; off >>= 1) kf = fmaxf(kf, __shfl_xor(kf, off));
+    wc.kmax = kf;
     return wc;
 }
 
@@ -1879,6 +1729,9 @@ __device__ __forceinline__ void count_wave(const KArgs& a, const WaveCounts& wc)
     if (wc.c[WC_CLOSURE]) atomicAdd(&a.diag[D_CLOSURE], static_cast<unsigned long long>(wc.c[WC_CLOSURE]));
     if (wc.c[WC_OUTSIDE]) atomicAdd(&a.diag[D_OUTSIDE], static_cast<unsigned long long>(wc.c[WC_OUTSIDE]));
     if (wc.c[WC_SUPMAX]) atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(wc.c[WC_SUPMAX]));
+    if (wc.kmax > 0.0f)
+        atomicMax(&a.diag[D_GRAMCOND],
+                  static_cast<unsigned long long>(__double_as_longlong(static_cast<double>(wc.kmax))));
 }
 
 // One wave per listed node: certified Delaunay search (exact predicates)
@@ -2090,7 +1943,7 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     __shared__ double2 sp[QPB * SKP];
     __shared__ uint32_t se[QPB * SKP];
     __shared__ int32_t su[QPB * SKP];
-    __shared__ int wsum[QWG / WAVE][4];
+    __shared__ int wsum[QWG / WAVE][TD];
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
     const SetDesc sd = tile_set(a, blockIdx.x);
@@ -2103,68 +1956,71 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     // the tile's counts as one plain record, folded into the diagnostics by
     // k_weights_rd: device-wide atomics from every wave on the same few
     // counters serialise at their memory partition and stall the pass
-    if (threadIdx.x % WAVE == 0)
+    if (threadIdx.x % WAVE == 0) {
         for (int c = 0; c < 4; ++c) wsum[threadIdx.x / WAVE][c] = wc.c[c];
+        wsum[threadIdx.x / WAVE][TD_KMAX] = __float_as_int(wc.kmax);
+    }
     __syncthreads();
-    if (threadIdx.x < 4) {
+    if (threadIdx.x < TD) {
         int v = 0;
-        for (int w = 0; w < QWG / WAVE; ++w)
-            v = threadIdx.x == WC_SUPMAX ? max(v, wsum[w][threadIdx.x]) : v + wsum[w][threadIdx.x];
-        a.tdiag[blockIdx.x * 4 + threadIdx.x] = v;
+        for (int w = 0; w < QWG / WAVE; ++w) {
+            const int x = wsum[w][threadIdx.x];
+            // (non-negative floats order as their bit patterns)
+            v = (threadIdx.x == WC_SUPMAX || threadIdx.x == TD_KMAX) ? max(v, x) : v + x;
+        }
+        a.tdiag[blockIdx.x * TD + threadIdx.x] = v;
     }
 }
 
-// Nodes whose moment systems are rank-deficient (listed by k_weights): the
-// minimum-norm solution through the pseudo-inverse, one quad per node.  Block
+// Rows listed by either weights pass because one of their systems is
+// ill-conditioned (condition estimate above svd_kappa) or lost rank: every
+// system of the row by the rank-revealing solver, one wave per row.  Block
 // 0 first folds k_weights' per-tile counts into the diagnostics.
 template <bool PER>
 __global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
     if (blockIdx.x == 0) {
-        unsigned long long v[4] = {0, 0, 0, 0};
+        unsigned long long v[TD] = {0, 0, 0, 0, 0};
         const int64_t tiles = a.n_slots / TILE_N;
         for (int64_t t = threadIdx.x; t < tiles; t += QWG) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const unsigned long long x = static_cast<unsigned long long>(a.tdiag[t * 4 + c]);
-                v[c] = c == WC_SUPMAX ? max(v[c], x) : v[c] + x;
+            for (int c = 0; c < TD; ++c) {
+                const unsigned long long x = static_cast<unsigned long long>(static_cast<uint32_t>(a.tdiag[t * TD + c]));
+                v[c] = (c == WC_SUPMAX || c == TD_KMAX) ? max(v[c], x) : v[c] + x;
             }
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < TD; ++c)
             for (int off = 32; off > 0; off >>= 1) {
                 const unsigned long long o = __shfl_xor(v[c], off);
-                v[c] = c == WC_SUPMAX ? max(v[c], o) : v[c] + o;
+                v[c] = (c == WC_SUPMAX || c == TD_KMAX) ? max(v[c], o) : v[c] + o;
             }
         if (threadIdx.x % WAVE == 0) {
             if (v[WC_INTERIOR]) atomicAdd(&a.diag[D_INTERIOR], v[WC_INTERIOR]);
             if (v[WC_CLOSURE]) atomicAdd(&a.diag[D_CLOSURE], v[WC_CLOSURE]);
             if (v[WC_OUTSIDE]) atomicAdd(&a.diag[D_OUTSIDE], v[WC_OUTSIDE]);
             if (v[WC_SUPMAX]) atomicMax(&a.diag[D_SUPMAX], v[WC_SUPMAX]);
+            if (v[TD_KMAX]) {
+                const double k = static_cast<double>(__int_as_float(static_cast<int>(v[TD_KMAX])));
+                atomicMax(&a.diag[D_GRAMCOND], static_cast<unsigned long long>(__double_as_longlong(k)));
+            }
         }
     }
-    const int lane = threadIdx.x & (QL - 1);
+    const int lane = threadIdx.x & (WAVE - 1);
     const int count = static_cast<int>(a.diag[D_RDCNT]);
-    const int64_t nn = a.n_slots;
-    for (int li = (blockIdx.x * QWG + threadIdx.x) / QL; li < count; li += gridDim.x * (QWG / QL)) {
+    const int waves = static_cast<int>(gridDim.x) * (QWG / WAVE);
+    const int w0 = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (QWG / WAVE) + threadIdx.x / WAVE));
+    for (int li = w0; li < count; li += waves) {
         const int64_t slot = a.rd[li];
         const SetDesc sd = slot_set(a, slot);
         int i, j;
         slot_ij(sd, slot, i, j);
-        const uint32_t meta = a.out.meta[slot];
-        const uint32_t type = meta_type(meta);
-        const int n = static_cast<int>(meta_cnt(meta));
-        if (type == NT_PENDING) {
-            int T[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) T[k] = a.out.idx[static_cast<int64_t>(meta_t(meta, k)) * nn + slot];
-            auto uget = [&](int k) {
-                return static_cast<int32_t>(static_cast<uint32_t>(a.out.idx[k * nn + slot]) |
-                                            (static_cast<uint32_t>(a.out.mem[k * nn + slot]) << 28));
-            };
-            quad_weights<PER>(a, sd.m, slot, node_at(sd.m, i, j, PER), uget, n, T, lane, meta_flags(meta));
-        } else {
-            quad_closure(a, slot, node_pos(sd.m, i, j), n, lane, type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING,
-                         meta_flags(meta));
+        int nrd = 0;
+        double kmax = 0.0;
+        const int nsys = wave_row_svd<PER>(a, sd, slot, node_at(sd.m, i, j, PER), lane, nrd, kmax);
+        if (lane == 0) {
+            atomicAdd(&a.diag[D_SVD], static_cast<unsigned long long>(nsys));
+            if (nrd) atomicAdd(&a.diag[D_RANKDEF], static_cast<unsigned long long>(nrd));
+            if (kmax > 0.0) atomicMax(&a.diag[D_GRAMCOND], static_cast<unsigned long long>(__double_as_longlong(kmax)));
         }
     }
 }
@@ -2275,7 +2131,7 @@ __global__ void __launch_bounds__(QWG) k_seam_copy(KArgs a) {
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
                   const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,
                   unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear,
-                  bool periodic) {
+                  bool periodic, double svd_kappa) {
     PhaseTimer _timer(PH_BUILD, st);
     // row slots are listed as int32
     if (n_tiles * TILE_N >= (int64_t(1) << 31)) {
@@ -2298,6 +2154,7 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     a.diag = diag;
     a.linear = linear ? 1 : 0;
     a.per = periodic ? 1 : 0;
+    a.svd_kappa = svd_kappa;
     const int tiles = static_cast<int>(n_tiles);
     {
         PhaseTimer t1(PH_BUILD_FAST, st);
@@ -2333,8 +2190,9 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         else k_weights<false><<<tiles, QWG, 0, st>>>(a);
         P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
         // rank-deficient nodes of either pass (normally none)
-        if (periodic) k_weights_rd<true><<<16, QWG, 0, st>>>(a);
-        else k_weights_rd<false><<<16, QWG, 0, st>>>(a);
+        // (a wave per listed row; the grid loops over the list)
+        if (periodic) k_weights_rd<true><<<64, QWG, 0, st>>>(a);
+        else k_weights_rd<false><<<64, QWG, 0, st>>>(a);
         if (periodic) k_seam_copy<<<tiles, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());

@@ -24,6 +24,10 @@ struct Tuning {
     double fast_radius = 2.6;     // fast path: candidate radius, in units of h
     double closure_radius = 4.0;  // fast path, boundary ring: candidate radius / h
     int levels = 3;               // doublings before the global scan
+    // condition estimate trace(G) trace(G^-1) above which a moment system
+    // goes to the rank-revealing solver: 1e8 keeps Cholesky (with one
+    // refinement step) within about eps cond(M) of the minimum-norm answer
+    double svd_cond = 1e8;
 } g_tune;
 
 // Candidate slots per lane for pi (Rf/h)^2 expected candidates, with a margin
@@ -75,7 +79,7 @@ struct p2m_weights {
     int32_t* idx = nullptr;
     int32_t* slow = nullptr;
     int32_t* rd = nullptr;
-    int32_t* tdiag = nullptr;  // per node tile counts of the weights pass [4 per tile]
+    int32_t* tdiag = nullptr;  // per node tile records of the weights pass [BUILD_TD per tile]
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;  // side-stream fork / join
     double* w64 = nullptr;
     float* w32 = nullptr;
@@ -189,6 +193,8 @@ WeightsView view(const p2m_weights* w) {
     v.w64 = w->w64;
     v.w32 = (w->flags & P2M_WEIGHTS_F32) ? w->w32 : nullptr;
     v.mem = w->mem;
+    v.rd = w->rd;
+    v.diag = w->diag;
     return v;
 }
 
@@ -250,6 +256,7 @@ int make_sets(const p2m_mesh* meshes, const double* hs, const int64_t* off, int 
         d.Rf = g_tune.fast_radius * h;
         d.hwf = std::max(1, static_cast<int>(std::ceil(d.Rf / d.g.bw)));
         d.Rc = g_tune.closure_radius * h;
+        d.h = h;
         d.hwc = std::max(1, static_cast<int>(std::ceil(d.Rc / d.g.bw)));
         tot.n_nodes += static_cast<int64_t>(mesh.nx + 1) * (mesh.ny + 1);
         tot.nbins += static_cast<int64_t>(d.g.nbx) * d.g.nby;
@@ -337,7 +344,7 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     if (!rc) rc = grow(&w->meta, n_slots, w->capSlots);
     if (!rc) rc = grow(&w->slow, n_nodes, w->capNodes);
     if (!rc) rc = grow(&w->rd, n_nodes, w->capNodes);
-    if (!rc) rc = grow(&w->tdiag, 4 * tot.n_tiles, 4 * (w->capSlots / TILE_N));
+    if (!rc) rc = grow(&w->tdiag, BUILD_TD * tot.n_tiles, BUILD_TD * (w->capSlots / TILE_N));
     if (!rc && !w->ev_fork) {
         hipError_t e = hipEventCreateWithFlags(&w->ev_fork, hipEventDisableTiming);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev_join, hipEventDisableTiming);
@@ -382,7 +389,7 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     if (rc) return rc;
     return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, fast_slots(), w->slow,
                          w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0,
-                         (flags & P2M_PERIODIC) != 0);
+                         (flags & P2M_PERIODIC) != 0, g_tune.svd_cond);
 }
 
 // Per-device workspace of the fused (recompute) entry points: a weights
@@ -436,6 +443,8 @@ int p2m_set_option(const char* name, double value) {
         g_tune.closure_radius = value;
     } else if (!std::strcmp(name, "levels") && value >= 0.0 && value <= 8.0) {
         g_tune.levels = static_cast<int>(value);
+    } else if (!std::strcmp(name, "svd_cond") && value >= 1.0 && value <= 1e16) {
+        g_tune.svd_cond = value;
     } else {
         set_error("unknown option or value out of range: %s=%g", name, value);
         return P2M_EINVAL;
@@ -458,6 +467,8 @@ int p2m_get_option(const char* name, double* value) {
         *value = g_tune.closure_radius;
     } else if (!std::strcmp(name, "levels")) {
         *value = g_tune.levels;
+    } else if (!std::strcmp(name, "svd_cond")) {
+        *value = g_tune.svd_cond;
     } else if (!std::strcmp(name, "fast_slots")) {
         *value = fast_slots();
     } else {
@@ -577,6 +588,14 @@ int p2m_weights_diag(const p2m_weights* w, p2m_diag* d, void* stream) {
     d->support_max = static_cast<int32_t>(h[D_SUPMAX]);
     d->duplicate_pairs = static_cast<int64_t>(h[D_DUP]);
     d->slow_nodes = static_cast<int64_t>(h[D_SLOWCNT]);
+    d->svd_systems = static_cast<int64_t>(h[D_SVD]);
+    {
+        const unsigned long long b = h[D_GRAMCOND];
+        double g = 0.0;
+        std::memcpy(&g, &b, sizeof g);
+        d->max_gram_cond = g;
+    }
+    d->bwd_rank_deficient = static_cast<int64_t>(h[D_BWDSKIP]);
     int status = P2M_OK;
     if (d->bad_particles) {
         status = P2M_EDOMAIN;

@@ -37,7 +37,11 @@ enum DiagIdx : int {
     D_SUPMAX,
     D_DUP,
     D_SLOWCNT,  // length of the slow-path node list
-    D_RDCNT,    // length of the rank-deficient node list (weights kernel)
+    D_RDCNT,    // length of the list of rows for the rank-revealing solver
+    D_SVD,      // moment systems solved by the rank-revealing solver
+    D_GRAMCOND, // largest condition number of a full-rank system's Gram
+                // matrix (bits of a non-negative double: ordered as integers)
+    D_BWDSKIP,  // rank-deficient systems the last position adjoint left out
     D_COUNT
 };
 
@@ -67,6 +71,10 @@ __host__ __device__ inline int row_len(uint32_t m) {
 }
 __host__ __device__ inline uint32_t meta_t(uint32_t m, int k) { return (m >> (9 + 5 * k)) & 31u; }
 constexpr uint32_t MF_NEARDEG = 1u, MF_RANKDEF = 2u, MF_ESCALATED = 4u, MF_GLOBAL = 8u;
+// MF_SVD: the row's systems were solved by the rank-revealing solver;
+// MF_RD0 << e: system e of the row (the closure's one system: e = 0) has
+// rank below 6 (its weights are the minimum-norm least-squares answer).
+constexpr uint32_t MF_SVD = 16u, MF_RD0 = 32u;
 __host__ __device__ inline uint32_t meta_flags(uint32_t m) { return m >> 24; }
 
 // Membership bits stored per ELL entry: bit k set when the particle belongs to
@@ -89,6 +97,8 @@ struct SetDesc {
     int32_t hwc;      // fast path: half-width (bins) scanned for ring nodes
     double Rf;        // fast path: candidate radius of interior nodes
     double Rc;        // fast path: candidate radius of boundary-ring nodes
+    double h;         // the caller's particle spacing: the length unit of a
+                      // closure system solved by the rank-revealing solver
 };
 
 // Index of the set that holds item v, where first(s) is the first item of
@@ -178,6 +188,8 @@ struct WeightsView {
     const double* w64;      // [KMAX][n_slots]
     const float* w32;       // [KMAX][n_slots] or null
     const uint8_t* mem;     // [KMAX][n_slots]
+    const int32_t* rd;      // row slots solved by the rank-revealing solver
+    unsigned long long* diag;  // the build's diagnostics (count of rd: D_RDCNT)
 };
 
 // Exact-rounding helpers: products/sums that must not be contracted into

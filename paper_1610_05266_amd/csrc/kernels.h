@@ -69,12 +69,15 @@ struct SideWork {
 };
 int side_stream(int device, hipStream_t* out);
 // fast_slots: candidate slots per lane of the fast pass (7, 8 or 10); slow, rd:
-// row-slot lists (capacity n_nodes); tdiag: per-tile counts [n_tiles][4];
-// linear: interior rows are the triangle's barycentric coordinates alone.
+// row-slot lists (capacity n_nodes); tdiag: per-tile records
+// [n_tiles][BUILD_TD]; svd_kappa: condition estimate above which a system
+// goes to the rank-revealing solver; linear: interior rows are the
+// triangle's barycentric coordinates alone.
+constexpr int BUILD_TD = 5;
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
                   const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,
                   unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear,
-                  bool periodic);
+                  bool periodic, double svd_kappa);
 
 // ---- projection and interpolation (project.hip, m2p.hip) ----
 int project(const WeightsView& w, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st);

@@ -80,7 +80,12 @@ struct MeshOf {
     }
 };
 
-// TM mesh value type (accumulation type), TO particle output type
+// TM mesh value type, TO particle output type.  The three products are
+// summed in FP64 and rounded once: with FP32 storage the output is the
+// correctly rounded value of the interpolant (BF16: rounded through FP32),
+// not a sum of rounded products (a position gradient
+// taken through these values amplifies their rounding by |a| / (h |grad a|),
+// some hundreds on fine meshes, so an extra rounding of a sum would show).
 template <typename TM, typename TO, int CC>
 __global__ void __launch_bounds__(256) k_m2p(MeshOf mo, const TM* __restrict__ mv, int Crt,
                                              const double2* __restrict__ pos, int64_t N, TO* __restrict__ out) {
@@ -93,13 +98,13 @@ __global__ void __launch_bounds__(256) k_m2p(MeshOf mo, const TM* __restrict__ m
     L.n0 += n0;
     L.n1 += n0;
     L.n2 += n0;
-    const TM w0 = static_cast<TM>(L.w0), w1 = static_cast<TM>(L.w1), w2 = static_cast<TM>(L.w2);
 #pragma unroll
     for (int c = 0; c < (CC > 0 ? CC : CMAX); ++c) {
         if (c >= C) break;
-        TM v = w0 * ldm(mv, L.n0 * C + c) + w1 * ldm(mv, L.n1 * C + c) + w2 * ldm(mv, L.n2 * C + c);
-        if (!L.ok) v = static_cast<TM>(NAN);
-        st(out, mu * C + c, v);
+        const double v = L.w0 * static_cast<double>(ldm(mv, L.n0 * C + c)) +
+                         L.w1 * static_cast<double>(ldm(mv, L.n1 * C + c)) +
+                         L.w2 * static_cast<double>(ldm(mv, L.n2 * C + c));
+        st(out, mu * C + c, static_cast<TM>(L.ok ? v : NAN));
     }
 }
 

@@ -1,0 +1,163 @@
+"""GPU parity where the moment systems are ill-conditioned or lose rank.
+
+The paper solves each edge's moment system (eqs. A0, A1, A2_2) by an SVD with
+automatic rank detection (App. A); both sides take the minimum-norm answer
+with singular values at or below eps max(6, K) s_max dropped.  The GPU solves
+a system through its Gram matrix only while a condition estimate stays below
+the "svd_cond" option, otherwise by its own SVD of M.
+
+* A cloud on a rotated ellipse moved off it by a relative delta
+  (``workloads.conic_cloud``): every support lies near one conic, so
+  cond(M) sweeps from about 1e2 (delta = 1e-1) to about 1e10 (delta = 1e-10),
+  and supports of fewer than six particles give rank-deficient systems.
+  Every row is compared element by element with the oracle at
+  max(1e-12, 10 eps cond_row), cond_row the largest ratio of extreme kept
+  singular values among the row's systems (the forward error of a
+  backward-stable minimum-norm solve is about eps cond).
+* The SVD path forced on every system (svd_cond = 1) on the 32 x 32 lattice
+  workload and in the periodic box: weights at 1e-12, and the position
+  adjoint of those rows at 1e-10 against the oracle's complex-step
+  derivatives.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as wl
+from oracle import Mesh as OMesh, P2MOracle
+from oracle.adjoint import p2m_grad_pos as o_p2m_grad_pos
+from oracle.periodic import PeriodicP2MOracle
+from paper_1610_05266_amd import ops
+from paper_1610_05266_amd._lib import P2M_PERIODIC
+from tests._util import assert_close, ell_to_csr
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+EPS = np.finfo(np.float64).eps
+
+
+def _g(a, dt=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV, dt)
+
+
+def _row_cond(info, t):
+    """Largest s_max / s_min(kept) over the systems of row t (oracle SVD)."""
+    if info["closure"][t]:
+        sig = info["closure_sigma"][t][None]
+        rank = np.array([info["closure_rank"][t]])
+    else:
+        sig = info["edge_sigma"][t]
+        rank = info["edge_rank"][t]
+    return max(s[0] / s[r - 1] for s, r in zip(sig, rank))
+
+
+def _oracle_rank_deficient(info):
+    c = info["closure"]
+    return int((info["edge_rank"][~c] < 6).sum() + (info["closure_rank"][c] < 6).sum())
+
+
+@pytest.fixture
+def svd_everywhere():
+    old = ops.p2m_get_option("svd_cond")
+    ops.p2m_set_option("svd_cond", 1.0)
+    yield
+    ops.p2m_set_option("svd_cond", old)
+
+
+@pytest.mark.parametrize("delta", [1e-1, 1e-2, 1e-4, 1e-6, 1e-8, 1e-10])
+def test_conic_cloud_rows_match_oracle_across_conditioning(delta):
+    c = wl.conic_cloud(8, 24, delta, seed=3)
+    om = OMesh.from_spec(c.mesh)
+    print(f"[gpu] conic cloud delta={delta:g} N={c.N}", flush=True)
+    W, info = P2MOracle(c.pos, om, c.h).matrix()
+    w = ops.p2m_build_weights(c.mesh, c.h, _g(c.pos))
+    d = w.diag(check_status=False)
+    assert d["failed_nodes"] == 0 and d["bad_particles"] == 0 and d["cap_overflow"] == 0
+    assert d["closure_nodes"] == int(info["closure"].sum())
+    # the same rank decisions as the oracle's SVD
+    assert d["rank_deficient"] == _oracle_rank_deficient(info)
+    idx, wt, cnt, _ = w.export()
+    G = ell_to_csr(idx.numpy(), wt.numpy(), cnt.numpy(), c.N)
+    conds = []
+    for t in range(om.n_nodes):
+        ref = W[t].toarray().ravel()
+        got = G[t].toarray().ravel()
+        cond = _row_cond(info, t)
+        conds.append(cond)
+        tol = max(1e-12, 10.0 * EPS * cond)
+        assert np.abs(got - ref).max() <= tol * np.abs(ref).max(), (t, cond, np.abs(got - ref).max())
+    conds = np.array(conds)
+    print(f"  rows: cond {conds.min():.2e}..{conds.max():.2e}, svd systems {d['svd_systems']}, "
+          f"rank-deficient {d['rank_deficient']}, max_gram_cond {d['max_gram_cond']:.3e}", flush=True)
+    if delta <= 1e-6:
+        # every system's estimate is above the threshold: all of them were
+        # solved by the SVD, whose cond2(G) of the full-rank systems is exact
+        n_sys = 3 * int((~info["closure"]).sum()) + int(info["closure"].sum())
+        assert d["svd_systems"] == n_sys
+        full = []
+        c_ = info["closure"]
+        for t in range(om.n_nodes):
+            if c_[t]:
+                if info["closure_rank"][t] == 6:
+                    full.append(info["closure_sigma"][t])
+            else:
+                full += [s for s, r in zip(info["edge_sigma"][t], info["edge_rank"][t]) if r == 6]
+        ref_cond = max((s[0] / s[5]) ** 2 for s in full)
+        assert abs(d["max_gram_cond"] / ref_cond - 1.0) <= 1e-2
+    if delta == 1e-1:
+        assert d["svd_systems"] == 0
+
+
+def test_svd_path_on_every_system_matches_oracle_and_its_adjoint(svd_everywhere):
+    c = wl.config1()
+    om = OMesh.from_spec(c.mesh)
+    orc = P2MOracle(c.pos, om, c.h)
+    W, _ = orc.matrix()
+    pos = _g(c.pos)
+    w = ops.p2m_build_weights(c.mesh, c.h, pos)
+    d = w.diag()
+    assert d["svd_systems"] == 3 * d["interior_nodes"] + d["closure_nodes"]
+    assert d["rank_deficient"] == 0
+    idx, wt, cnt, _ = w.export()
+    G = ell_to_csr(idx.numpy(), wt.numpy(), cnt.numpy(), c.N)
+    assert ((G != 0).astype(int) != (W != 0).astype(int)).nnz == 0
+    assert abs(G - W).max() <= 1e-12 * abs(W).max()
+    rng = np.random.default_rng(8)
+    gmesh = rng.normal(size=(om.n_nodes, 3))
+    _, gw = ops.p2m_project_backward(w, _g(gmesh), _g(c.vals), want_vals=False, want_w=True)
+    gp = ops.p2m_build_weights_backward(w, pos, gw).cpu().numpy()
+    assert w.diag()["bwd_rank_deficient"] == 0
+    assert_close(gp, o_p2m_grad_pos(orc, c.vals, gmesh), 1e-10, "P2M grad pos, SVD rows")
+
+
+def test_svd_path_in_the_periodic_box(svd_everywhere):
+    c = wl.periodic_tg_cloud(16, 2, 0.25, seed=12)
+    om = OMesh.from_spec(c.mesh)
+    W, _ = PeriodicP2MOracle(c.pos, om, c.h).matrix()
+    w = ops.p2m_build_weights(c.mesh, c.h, _g(c.pos), P2M_PERIODIC)
+    d = w.diag()
+    assert d["svd_systems"] > 0 and d["rank_deficient"] == 0
+    idx, wt, cnt, _ = w.export()
+    G = ell_to_csr(idx.numpy(), wt.numpy(), cnt.numpy(), c.N)
+    assert abs(G - W).max() <= 1e-12 * abs(W).max()
+
+
+def test_rank_deficient_systems_are_counted_by_the_adjoint():
+    """Supports of fewer than six particles (ear vertices of the conic
+    cloud's triangulation) give least-squares weights that have no position
+    derivative across rank changes: the adjoint leaves their coefficient
+    part out, counts it, and stays finite."""
+    c = wl.conic_cloud(8, 24, 1e-4, seed=3)
+    om = OMesh.from_spec(c.mesh)
+    _, info = P2MOracle(c.pos, om, c.h).matrix()
+    assert _oracle_rank_deficient(info) > 0
+    pos = _g(c.pos)
+    w = ops.p2m_build_weights(c.mesh, c.h, pos)
+    nrd = w.diag(check_status=False)["rank_deficient"]
+    assert nrd == _oracle_rank_deficient(info)
+    rng = np.random.default_rng(9)
+    gmesh = rng.normal(size=(om.n_nodes, 3))
+    _, gw = ops.p2m_project_backward(w, _g(gmesh), _g(c.vals), want_vals=False, want_w=True)
+    gp = ops.p2m_build_weights_backward(w, pos, gw)
+    assert torch.isfinite(gp).all()
+    assert w.diag(check_status=False)["bwd_rank_deficient"] == nrd

@@ -91,14 +91,20 @@ def test_c4_full_backward_sampled_against_oracle(c4):
     W, _ = orc.matrix(nodes)
     g = c.extra["g_mesh"]
     f64 = c.extra["f_mesh"]
-    # the mixed path's reference is the oracle on its FP32-rounded mesh input:
-    # the interpolant's gradient differences f over one cell, which turns the
-    # input rounding alone into ~1e-5 relative error
+    # The mixed path stores the mesh input and the particle values of M2P in
+    # FP32: its reference is the oracle on those FP32-rounded arrays (the
+    # mesh input rounded, the oracle's M2P rounded once, as the GPU's M2P
+    # rounds its FP64 sum once).  Rounding either array moves dL/dpos by
+    # ~1e-5 of its terms (see below), which is the storage's doing, not the
+    # arithmetic's: that total is reported, and bounded, separately.
     f32 = f64.astype(np.float32).astype(np.float64)
     near = np.flatnonzero(np.asarray(abs(m2p_matrix(om, c.pos)[:, snodes]).sum(1)).ravel() > 0)
-    for f, out_g, gp_g, gf_g, tol, what in ((f64, out64, gp64, gf64, 1e-12, "FP64"),
-                                           (f32, out32, gp32, gf32, 1e-5, "mixed")):
-        a = o_m2p(om, f, c.pos)
+    a64 = o_m2p(om, f64, c.pos)
+    a32 = o_m2p(om, f32, c.pos).astype(np.float32).astype(np.float64)
+    ref_terms = {}
+    for f, a, out_g, gp_g, gf_g, tol, gtol, what in (
+            (f64, a64, out64, gp64, gf64, 1e-12, 1e-10, "FP64"),
+            (f32, a32, out32, gp32, gf32, 1e-5, 1e-5, "mixed")):
         out = W @ a
         r = out - g[nodes]
         assert_close(out_g[nodes], out, tol, f"C4 P2M(M2P f) at sampled nodes, {what}")
@@ -109,18 +115,23 @@ def test_c4_full_backward_sampled_against_oracle(c4):
         # The weight term and the M2P term of dL/dpos nearly cancel (P2M(M2P f)
         # follows f as particles move), by about three orders of magnitude
         # here, so the error is measured against the size of the two terms.
-        # FP32 sums leave out with ~1e-7 absolute error; the residual r is
-        # several times smaller than out, which scales its relative error
-        # (and every gradient formed from it) by |out| / |r|.
-        cond = max(1.0, np.abs(out).max() / np.abs(r).max())
-        gtol = 1e-10 if what == "FP64" else 1e-5 * cond
-        print(f"C4 {what}: residual conditioning {cond:.2f}, gradient tolerance {gtol:.2e}", flush=True)
         scale = np.abs(g_p2m) + np.abs(g_m2p)
         d = gp_g[parts] - gp
-        assert np.linalg.norm(d) <= gtol * np.linalg.norm(scale), f"C4 dL/dpos {what}: normwise"
-        assert np.abs(d).max() <= gtol * scale.max(), f"C4 dL/dpos {what}: max"
+        nrm = np.linalg.norm(d) / np.linalg.norm(scale)
+        mx = np.abs(d).max() / scale.max()
+        print(f"C4 dL/dpos {what}: normwise {nrm:.3e}, max {mx:.3e} (of the terms)", flush=True)
+        assert nrm <= gtol and mx <= gtol, f"C4 dL/dpos {what}: {nrm:.3e} {mx:.3e} > {gtol:.1e}"
+        if what == "FP64":
+            assert_close(gp64[parts], gp, 1e-7, "C4 dL/dpos, FP64, relative to the sum")
+            ref_terms = dict(gp=gp, scale=scale)
         gf = m2p_matrix(om, c.pos[near])[:, snodes].T @ abar[near]
         assert_close(gf_g[snodes], gf, gtol, f"C4 dL/df, {what}")
+    # the mixed form against the unrounded FP64 reference: the storage
+    # rounding included (measured ~1.5e-5 of the terms; bounded at 1e-4)
+    d = gp32[parts] - ref_terms["gp"]
+    tot = (np.linalg.norm(d) / np.linalg.norm(ref_terms["scale"]), np.abs(d).max() / ref_terms["scale"].max())
+    print(f"C4 dL/dpos mixed vs unrounded FP64 reference (storage included): {tot[0]:.3e}, {tot[1]:.3e}", flush=True)
+    assert max(tot) <= 1e-4
 
 
 def test_c4_recompute_mode_gives_the_stored_mode_gradients(c4):

@@ -35,6 +35,7 @@ __all__ = [
     "config5",
     "small_cloud",
     "cluster_void_cloud",
+    "conic_cloud",
     "CONFIGS",
 ]
 
@@ -276,6 +277,27 @@ def cluster_void_cloud(n: int, N: int, seed: int,
     mesh = MeshSpec(n, n, 1.0 / n)
     h = 1.0 / math.sqrt(N)
     return Cloud(f"cluster{n}", mesh, h, pos, _fields(pos, channels), channels)
+
+
+def conic_cloud(n: int, n_pts: int, delta: float, seed: int,
+                channels: Tuple[str, ...] = ("u", "v", "q")) -> Cloud:
+    """Conditioning stress input (not a benchmark): n_pts particles on a
+    rotated ellipse inside the unit square, at seeded random angles, each
+    moved off the ellipse radially by a factor 1 + delta * U(-1, 1).  Every
+    particle is a hull vertex, so every support of a node lies within
+    relative distance delta of one conic: the moment systems of such
+    supports are nearly rank-deficient, with condition numbers growing like
+    1 / delta."""
+    rng = np.random.default_rng(seed)
+    t = np.sort(rng.uniform(0.0, 2.0 * math.pi, size=n_pts))
+    r = 1.0 + delta * rng.uniform(-1.0, 1.0, size=n_pts)
+    ex, ey = 0.41 * r * np.cos(t), 0.29 * r * np.sin(t)
+    c, s = math.cos(0.35), math.sin(0.35)
+    pos = np.stack([0.5 + c * ex - s * ey, 0.5 + s * ex + c * ey], 1)
+    pos = np.ascontiguousarray(pos[rng.permutation(n_pts)])
+    mesh = MeshSpec(n, n, 1.0 / n)
+    h = 2.2 / n_pts
+    return Cloud(f"conic{n}", mesh, h, pos, _fields(pos, channels), channels)
 
 
 def periodic_void_cloud(n: int, N: int, seed: int,
