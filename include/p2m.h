@@ -323,9 +323,11 @@ void p2m_weights_destroy(p2m_weights* w);
  * Recompute forms: the weights are rebuilt inside the call in a workspace
  * the library keeps per device (grown on demand, never freed), so a caller
  * keeps no weights between a forward and its backward -- the form for the
- * largest sizes.  Calls on one device are serialised; results are those of
- * p2m_build_weights + p2m_project (+ the backward calls) bit for bit, since
- * the build is deterministic.
+ * largest sizes.  Calls on one device are serialised: the host calls by a
+ * lock, the device work by an event each call records on its stream and the
+ * next call, on whatever stream, waits for before it rebuilds the workspace.
+ * Results are those of p2m_build_weights + p2m_project (+ the backward calls)
+ * bit for bit, since the build is deterministic.
  * ------------------------------------------------------------------------ */
 
 /* eq. (p2m) with the App. B weights built for this call (arguments as in

@@ -2166,30 +2166,35 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     }
     P2M_HIP(hipGetLastError());
     // The few nodes the fast pass could not certify take the exact wave path
-    // on a side stream, concurrently with the weights of all other nodes.
-    P2M_HIP(hipEventRecord(side.fork, st));
-    P2M_HIP(hipStreamWaitEvent(side.stream, side.fork, 0));
+    // on a side stream, concurrently with the weights of all other nodes
+    // (without a side stream, after them on the caller's stream).
+    const bool fork = side.stream != nullptr && side.stream != st && side.fork && side.join;
+    hipStream_t sst = fork ? side.stream : st;
+    if (fork) {
+        P2M_HIP(hipEventRecord(side.fork, st));
+        P2M_HIP(hipStreamWaitEvent(side.stream, side.fork, 0));
+    }
     {
-        PhaseTimer t2(PH_BUILD_SLOW, side.stream);
+        PhaseTimer t2(PH_BUILD_SLOW, sst);
         // one block per slow node; the grid loops over the actual list.  It
         // is sized for many more nodes than an ordered cloud leaves here (a
         // sheared one leaves thousands), beyond the blocks resident at once:
         // the blocks past the list leave at once
         const int64_t expect = n_nodes / 64 + 64 * static_cast<int64_t>(S);
         const int gs = static_cast<int>(std::min<int64_t>(expect, 4096));
-        if (periodic) k_slow_geom<true><<<gs, SWG, 0, side.stream>>>(a);
-        else k_slow_geom<false><<<gs, SWG, 0, side.stream>>>(a);
+        if (periodic) k_slow_geom<true><<<gs, SWG, 0, sst>>>(a);
+        else k_slow_geom<false><<<gs, SWG, 0, sst>>>(a);
     }
     P2M_HIP(hipGetLastError());
-    P2M_HIP(hipEventRecord(side.join, side.stream));
+    if (fork) P2M_HIP(hipEventRecord(side.join, side.stream));
     {
         PhaseTimer t3(PH_WEIGHTS, st);
         // (one weighting code for both passes, so that a row does not depend
         // on the pass that found it)
         if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
         else k_weights<false><<<tiles, QWG, 0, st>>>(a);
-        P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
-        // rank-deficient nodes of either pass (normally none)
+        if (fork) P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
+        // ill-conditioned or rank-deficient rows of either pass (normally none)
         // (a wave per listed row; the grid loops over the list)
         if (periodic) k_weights_rd<true><<<64, QWG, 0, st>>>(a);
         else k_weights_rd<false><<<64, QWG, 0, st>>>(a);

@@ -281,14 +281,10 @@ int make_sets(const p2m_mesh* meshes, const double* hs, const int64_t* off, int 
 
 // Shared by the single-set and batched builds: workspace, set table upload
 // (only when it changed), binning and the three build kernels.
-int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const double* pos, int flags,
-               p2m_weights** wout, hipStream_t st) {
+// Arguments of a build that do not depend on the workspace.
+int check_build(const std::vector<SetDesc>& sets, const double* pos, int flags) {
     if (!pos || !aligned(pos, 16)) {
         set_error("pos is NULL or not 16-byte aligned");
-        return P2M_EINVAL;
-    }
-    if (!wout) {
-        set_error("output handle pointer is NULL");
         return P2M_EINVAL;
     }
     if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR | P2M_PERIODIC)) {
@@ -301,6 +297,32 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
                 set_error("a periodic box needs at least 4 cells per side (nx=%d ny=%d)", d.m.nx, d.m.ny);
                 return P2M_EINVAL;
             }
+    return P2M_OK;
+}
+
+// The build's launches on a handle whose buffers and device set table are
+// in place: binning, then the build kernels (slow path on side.stream, or on
+// st when side.stream is null).
+int launch_build(p2m_weights* w, const SetTotals& tot, const double* pos, int flags, const SideWork& side,
+                 hipStream_t st) {
+    // (the binning clears the diagnostics before anything counts into them)
+    int rc = bin_particles(w->bins, pos, tot.N, w->dsets, w->S, tot.nbins, w->diag, st);
+    if (rc) return rc;
+    const bool want32 = (flags & P2M_WEIGHTS_F32) != 0;
+    BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem};
+    return build_weights(w->bins, w->dsets, w->S, tot.n_tiles, tot.n_nodes, out, g_tune.levels, fast_slots(),
+                         w->slow, w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0,
+                         (flags & P2M_PERIODIC) != 0, g_tune.svd_cond);
+}
+
+int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const double* pos, int flags,
+               p2m_weights** wout, hipStream_t st) {
+    int rc0 = check_build(sets, pos, flags);
+    if (rc0) return rc0;
+    if (!wout) {
+        set_error("output handle pointer is NULL");
+        return P2M_EINVAL;
+    }
     int nch = 0, sbs = 0, nsb = 0;
     int rc = bin_layout(tot.N, tot.nbins, &nch, &sbs, &nsb);
     if (rc) return rc;
@@ -380,27 +402,42 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     w->flags = flags;
     *wout = w;
 
-    // (the binning clears the diagnostics before anything counts into them)
-    rc = bin_particles(w->bins, pos, N, w->dsets, S, nbins, w->diag, st);
-    if (rc) return rc;
-    BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem};
     SideWork side{nullptr, w->ev_fork, w->ev_join};
     rc = side_stream(dev, &side.stream);
     if (rc) return rc;
-    return build_weights(w->bins, w->dsets, S, tot.n_tiles, n_nodes, out, g_tune.levels, fast_slots(), w->slow,
-                         w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0,
-                         (flags & P2M_PERIODIC) != 0, g_tune.svd_cond);
+    return launch_build(w, tot, pos, flags, side, st);
 }
 
 // Per-device workspace of the fused (recompute) entry points: a weights
 // handle and an ELL-shaped gradient buffer, grown on demand and kept for the
 // life of the process.  Calls on one device are serialised by a lock.
+// An event recorded on the caller's stream after each call makes the next
+// call, on whatever stream, wait for the kernels still reading the
+// workspace before it is rebuilt.
 struct FusedWork {
     std::mutex mu;
     p2m_weights* w = nullptr;
     double* grad_w = nullptr;
     int64_t cap_gw = 0;
+    hipEvent_t done = nullptr;
 };
+// Before reusing the workspace: wait on stream for the previous call's work.
+int fused_enter(FusedWork& fw, hipStream_t st) {
+    if (!fw.done) {
+        P2M_HIP(hipEventCreateWithFlags(&fw.done, hipEventDisableTiming));
+        return P2M_OK;
+    }
+    P2M_HIP(hipStreamWaitEvent(st, fw.done, 0));
+    return P2M_OK;
+}
+int fused_leave(FusedWork& fw, hipStream_t st, int rc) {
+    if (fw.done) {
+        const hipError_t e = hipEventRecord(fw.done, st);
+        if (e != hipSuccess && rc == P2M_OK) return hip_check(e, "hipEventRecord");
+    }
+    return rc;
+}
+
 FusedWork& fused_work(int device) {
     static FusedWork works[64];
     return works[device & 63];
@@ -779,9 +816,12 @@ int p2m_project_fused(const p2m_mesh* mesh, double h, const double* pos, int64_t
     P2M_HIP(hipGetDevice(&dev));
     FusedWork& fw = fused_work(dev);
     std::lock_guard<std::mutex> lock(fw.mu);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = fused_enter(fw, st);
+    if (rc) return rc;
     rc = p2m_build_weights(mesh, h, pos, N, dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32, &fw.w, stream);
     if (!rc) rc = p2m_project(fw.w, vals, C, dtype, mesh_vals, stream);
-    return rc;
+    return fused_leave(fw, st, rc);
 }
 
 int p2m_backward_fused(const p2m_mesh* mesh, double h, const double* pos, int64_t N, const void* vals, int C,
@@ -797,20 +837,22 @@ int p2m_backward_fused(const p2m_mesh* mesh, double h, const double* pos, int64_
     P2M_HIP(hipGetDevice(&dev));
     FusedWork& fw = fused_work(dev);
     std::lock_guard<std::mutex> lock(fw.mu);
-    rc = p2m_build_weights(mesh, h, pos, N, dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32, &fw.w, stream);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    rc = fused_enter(fw, st);
     if (rc) return rc;
+    rc = p2m_build_weights(mesh, h, pos, N, dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32, &fw.w, stream);
     double* gw = nullptr;
-    if (grad_pos) {
+    if (!rc && grad_pos) {
         const int64_t need = fw.w->n_nodes * KMAX;
         rc = grow(&fw.grad_w, need, fw.cap_gw);
-        if (rc) return rc;
-        fw.cap_gw = std::max(fw.cap_gw, need);
-        gw = fw.grad_w;
+        if (!rc) {
+            fw.cap_gw = std::max(fw.cap_gw, need);
+            gw = fw.grad_w;
+        }
     }
-    if (!grad_vals && !gw) return P2M_OK;
-    rc = p2m_project_backward(fw.w, grad_mesh, C, dtype, vals, grad_vals, gw, stream);
+    if (!rc && (grad_vals || gw)) rc = p2m_project_backward(fw.w, grad_mesh, C, dtype, vals, grad_vals, gw, stream);
     if (!rc && gw) rc = p2m_build_weights_backward(fw.w, pos, gw, grad_pos, stream);
-    return rc;
+    return fused_leave(fw, st, rc);
 }
 
 int p2m_mesh_qcsf_create(const p2m_mesh* mesh, p2m_mesh_qcsf** out, void* stream) {
