@@ -348,6 +348,25 @@ int p2m_backward_fused(const p2m_mesh* mesh, double h, const double* pos, int64_
                        const void* vals, int C, int dtype, const void* grad_mesh,
                        void* grad_vals, double* grad_pos, void* stream);
 
+/*
+ * p2m_project_fused_noalloc -- p2m_project_fused for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, tight
+ * serving loops, harnesses that forbid hipMalloc.  The weights are rebuilt in
+ * a static workspace of the library (about 16 MiB of device memory, held by
+ * every GPU the library runs on until the process ends) instead of the
+ * allocated per-device workspace; the call makes no allocation (no hipMalloc,
+ * no stream or event creation) and runs every kernel, the exact-path ones
+ * included, on `stream`.  Arguments and results as p2m_project_fused.
+ * Limits (EINVAL beyond them): N <= 131072 particles, a mesh of at most 256
+ * tiles of 8 x 8 nodes (e.g. 127 x 127 cells), at most 262144 binning bins
+ * (about (extent / h)^2).  Every call on a GPU shares that GPU's workspace,
+ * which keeps the last call's contents: calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller.  The
+ * diagnostics of these builds are not reported.
+ */
+int p2m_project_fused_noalloc(const p2m_mesh* mesh, double h, const double* pos, int64_t N,
+                              const void* vals, int C, int dtype, void* mesh_vals, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batches: many independent particle sets, each with its own mesh and h,
  * handled by one launch sequence.  The sets are the paper's problem

@@ -83,6 +83,8 @@ _SIGS = {
     "p2m_backward_fused": (c_int, [POINTER(P2MMesh), c_double, c_void_p, c_int64, c_void_p, c_int, c_int, c_void_p,
                                    c_void_p, c_void_p, c_void_p]),
     "p2m_fused_handle": (c_void_p, []),
+    "p2m_project_fused_noalloc": (c_int, [POINTER(P2MMesh), c_double, c_void_p, c_int64, c_void_p, c_int, c_int,
+                                          c_void_p, c_void_p]),
     "p2m_batch_create": (c_int, [POINTER(P2MMesh), POINTER(c_double), c_int, POINTER(c_int64), POINTER(c_void_p)]),
     "p2m_batch_shape": (c_int, [c_void_p, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
     "p2m_batch_destroy": (None, [c_void_p]),

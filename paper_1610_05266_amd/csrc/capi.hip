@@ -58,7 +58,63 @@ struct SetTotals {
     int64_t N = 0, n_nodes = 0, nbins = 0, n_tiles = 0;
 };
 
+// ---------------------------------------------------- static workspace
+// The workspace of p2m_project_fused_noalloc: a file-scope device array, of
+// which every GPU the library runs on holds its own copy until the process
+// ends.  Its name in host code is a host-side stand-in: host code takes the
+// array's device address once per device (hipGetSymbolAddress, with that
+// device current) and uses only that address, carving the build's buffers
+// from it.
+constexpr int64_t NA_MAX_N = int64_t(1) << 17;     // particles
+constexpr int64_t NA_MAX_TILES = 256;              // 8 x 8 node tiles (e.g. 127 x 127 cells)
+constexpr int64_t NA_MAX_SLOTS = NA_MAX_TILES * TILE_N;
+constexpr int64_t NA_MAX_BINS = int64_t(1) << 18;  // binning grid
+constexpr int64_t NA_MAX_HIST = 8192;              // (super-bin, chunk) counters
+constexpr int64_t NA_MAX_TSUM = 1024;              // scan tiles of those
+constexpr size_t na_align(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+// Byte offsets of the buffers in the array (each 256-byte aligned).
+struct NaLayout {
+    size_t key, rank, perm, pos_s, part_pos, part_key, part_uid, start, hist, tsum;
+    size_t meta, slow, rd, tdiag, idx, w64, w32, mem, diag, sets, total;
+};
+constexpr NaLayout na_layout() {
+    NaLayout L{};
+    size_t o = 0;
+    auto take = [&o](size_t bytes) {
+        const size_t at = o;
+        o += na_align(bytes);
+        return at;
+    };
+    L.key = take(4 * NA_MAX_N);
+    L.rank = take(4 * NA_MAX_N);
+    L.perm = take(4 * NA_MAX_N);
+    L.pos_s = take(16 * NA_MAX_N);
+    L.part_pos = take(16 * NA_MAX_N);
+    L.part_key = take(4 * NA_MAX_N);
+    L.part_uid = take(4 * NA_MAX_N);
+    L.start = take(4 * (NA_MAX_BINS + 2));
+    L.hist = take(4 * (NA_MAX_HIST + 1));
+    L.tsum = take(4 * (NA_MAX_TSUM + 1));
+    L.meta = take(4 * NA_MAX_SLOTS);
+    L.slow = take(4 * NA_MAX_SLOTS);
+    L.rd = take(4 * NA_MAX_SLOTS);
+    L.tdiag = take(4 * BUILD_TD * NA_MAX_TILES);
+    L.idx = take(4 * KMAX * NA_MAX_SLOTS);
+    L.w64 = take(8 * KMAX * NA_MAX_SLOTS);
+    L.w32 = take(4 * KMAX * NA_MAX_SLOTS);
+    L.mem = take(1 * KMAX * NA_MAX_SLOTS);
+    L.diag = take(8 * D_COUNT);
+    L.sets = take(sizeof(SetDesc));
+    L.total = o;
+    return L;
+}
+constexpr NaLayout NA = na_layout();
+
 }  // namespace p2m
+
+// The static workspace of p2m_project_fused_noalloc (layout: na_layout).
+static __device__ __align__(256) unsigned char scratch[p2m::NA.total];
 
 using namespace p2m;
 
@@ -438,6 +494,19 @@ int fused_leave(FusedWork& fw, hipStream_t st, int rc) {
     return rc;
 }
 
+// Set table of a static-workspace build, stored by a kernel from its argument
+// (no host buffer has to outlive the call).
+__global__ void k_store_set(SetDesc* d, SetDesc s) { *d = s; }
+
+struct NoAllocWork {
+    std::mutex mu;
+    unsigned char* base[64] = {};  // device address of `scratch` on each device
+    p2m_weights w[64];             // handles whose buffers point into it
+};
+NoAllocWork& noalloc_work() {
+    static NoAllocWork nw;
+    return nw;
+}
 FusedWork& fused_work(int device) {
     static FusedWork works[64];
     return works[device & 63];
@@ -853,6 +922,88 @@ int p2m_backward_fused(const p2m_mesh* mesh, double h, const double* pos, int64_
     if (!rc && (grad_vals || gw)) rc = p2m_project_backward(fw.w, grad_mesh, C, dtype, vals, grad_vals, gw, stream);
     if (!rc && gw) rc = p2m_build_weights_backward(fw.w, pos, gw, grad_pos, stream);
     return fused_leave(fw, st, rc);
+}
+
+int p2m_project_fused_noalloc(const p2m_mesh* mesh, double h, const double* pos, int64_t N, const void* vals,
+                              int C, int dtype, void* mesh_vals, void* stream) {
+    int rc = check_mesh(mesh);
+    if (!rc) rc = check_vals(vals, C, dtype, "vals", false);
+    if (!rc) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (rc) return rc;
+    if (N < 3 || N > NA_MAX_N) {
+        set_error("p2m_project_fused_noalloc: N=%lld outside [3, %lld] (the static workspace's limit)",
+                  static_cast<long long>(N), static_cast<long long>(NA_MAX_N));
+        return P2M_EINVAL;
+    }
+    const int64_t off[2] = {0, N};
+    std::vector<SetDesc> sets;
+    SetTotals tot;
+    rc = make_sets(mesh, &h, off, 1, sets, tot);
+    const int flags = dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32;
+    if (!rc) rc = check_build(sets, pos, flags);
+    if (rc) return rc;
+    int nch = 0, sbs = 0, nsb = 0;
+    rc = bin_layout(tot.N, tot.nbins, &nch, &sbs, &nsb);
+    if (rc) return rc;
+    const int64_t nhist = static_cast<int64_t>(nsb) * nch;
+    if (tot.n_tiles > NA_MAX_TILES || tot.nbins > NA_MAX_BINS || nhist > NA_MAX_HIST ||
+        scan_tile_count(nhist + 1) + 1 > NA_MAX_TSUM) {
+        set_error("p2m_project_fused_noalloc: mesh of %lld node tiles or %lld bins (h=%g) exceeds the static "
+                  "workspace (at most %lld tiles of 8 x 8 nodes and %lld bins)",
+                  static_cast<long long>(tot.n_tiles), static_cast<long long>(tot.nbins), h,
+                  static_cast<long long>(NA_MAX_TILES), static_cast<long long>(NA_MAX_BINS));
+        return P2M_EINVAL;
+    }
+    int dev = 0;
+    P2M_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) {
+        set_error("device %d out of range", dev);
+        return P2M_EINVAL;
+    }
+    NoAllocWork& nw = noalloc_work();
+    std::lock_guard<std::mutex> lock(nw.mu);
+    p2m_weights* w = &nw.w[dev];
+    if (!nw.base[dev]) {
+        // this device's copy of the array: its device address, taken once
+        void* ptr = nullptr;
+        P2M_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        unsigned char* b = static_cast<unsigned char*>(ptr);
+        w->device = dev;
+        w->bins.key = reinterpret_cast<uint32_t*>(b + NA.key);
+        w->bins.rank = reinterpret_cast<int32_t*>(b + NA.rank);
+        w->bins.perm = reinterpret_cast<int32_t*>(b + NA.perm);
+        w->bins.pos_s = reinterpret_cast<double*>(b + NA.pos_s);
+        w->bins.part_pos = reinterpret_cast<double*>(b + NA.part_pos);
+        w->bins.part_key = reinterpret_cast<uint32_t*>(b + NA.part_key);
+        w->bins.part_uid = reinterpret_cast<int32_t*>(b + NA.part_uid);
+        w->bins.start = reinterpret_cast<int32_t*>(b + NA.start);
+        w->bins.hist = reinterpret_cast<int32_t*>(b + NA.hist);
+        w->bins.tsum = reinterpret_cast<int32_t*>(b + NA.tsum);
+        w->meta = reinterpret_cast<uint32_t*>(b + NA.meta);
+        w->slow = reinterpret_cast<int32_t*>(b + NA.slow);
+        w->rd = reinterpret_cast<int32_t*>(b + NA.rd);
+        w->tdiag = reinterpret_cast<int32_t*>(b + NA.tdiag);
+        w->idx = reinterpret_cast<int32_t*>(b + NA.idx);
+        w->w64 = reinterpret_cast<double*>(b + NA.w64);
+        w->w32 = reinterpret_cast<float*>(b + NA.w32);
+        w->mem = b + NA.mem;
+        w->diag = reinterpret_cast<unsigned long long*>(b + NA.diag);
+        w->dsets = reinterpret_cast<SetDesc*>(b + NA.sets);
+        nw.base[dev] = b;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    w->S = 1;
+    w->N = tot.N;
+    w->n_nodes = tot.n_nodes;
+    w->n_tiles = tot.n_tiles;
+    w->flags = flags;
+    k_store_set<<<1, 1, 0, st>>>(w->dsets, sets[0]);
+    P2M_HIP(hipGetLastError());
+    // no side stream: the exact path runs on the caller's stream
+    const SideWork side{nullptr, nullptr, nullptr};
+    rc = launch_build(w, tot, pos, flags, side, st);
+    if (!rc) rc = p2m_project(w, vals, C, dtype, mesh_vals, stream);
+    return rc;
 }
 
 int p2m_mesh_qcsf_create(const p2m_mesh* mesh, p2m_mesh_qcsf** out, void* stream) {

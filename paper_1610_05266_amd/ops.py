@@ -27,6 +27,7 @@ __all__ = [
     "p2m_get_option",
     "p2m_project_fused",
     "p2m_backward_fused",
+    "p2m_project_fused_noalloc",
     "Batch",
     "p2m_build_weights_batched",
     "m2p_interpolate_batched",
@@ -393,6 +394,25 @@ def p2m_project_fused(mesh, h: float, pos: torch.Tensor, vals: torch.Tensor,
             d = fused_diag()
             if d["status"] != 0:
                 check(d["status"])
+    return out
+
+
+def p2m_project_fused_noalloc(mesh, h: float, pos: torch.Tensor, vals: torch.Tensor,
+                              out: torch.Tensor) -> torch.Tensor:
+    """p2m_project_fused in the library's static per-device workspace: the
+    call allocates no device memory (the caller passes ``out``)."""
+    mesh = Mesh.of(mesh)
+    _need(pos, "pos", torch.float64)
+    _need(vals, "vals")
+    if vals.dim() != 2 or vals.shape[0] != pos.shape[0]:
+        raise ValueError(f"vals must have shape [{pos.shape[0]}, C]")
+    code = _dtype_code(vals.dtype)
+    C = vals.shape[1]
+    _need(out, "out", _mesh_dtype(code), (mesh.n_nodes, C))
+    cm = mesh.c()
+    with torch.cuda.device(pos.device):
+        check(load().p2m_project_fused_noalloc(ctypes.byref(cm), float(h), _ptr(pos), pos.shape[0], _ptr(vals), C,
+                                               code, _ptr(out), _stream(pos)))
     return out
 
 
