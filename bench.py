@@ -50,6 +50,10 @@ def parse(argv=None):
     ap.add_argument("--no-tune", action="store_true", help="keep the library's default build options")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the linear-FE and kinematic-loop measurements (profiles of the headline step)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the batched (64 sets), 4.2M-particle and 16.8M-particle BF16 measurements")
+    ap.add_argument("--only-large", action="store_true",
+                    help="time the large workloads only (profiles of their kernels)")
     ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE",
                     help="set a build option (p2m_set_option) instead of autotuning")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -126,9 +130,21 @@ def cpu_baseline(cloud, side):
     t0 = time.perf_counter()
     orc = P2MOracle(pos, om, cloud.h)
     W, _ = orc.matrix()
+    t1 = time.perf_counter()
     mesh_vals = W @ vals
+    t2 = time.perf_counter()
     oracle.m2p(om, mesh_vals, pos)
-    t = time.perf_counter() - t0
+    t3 = time.perf_counter()
+    t = t3 - t0
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": round(pos.shape[0] / t / 1e6, 4),
         "unit": "Mparticles/s",
@@ -137,11 +153,186 @@ def cpu_baseline(cloud, side):
         "sample": (f"sub-square [0,{side:g}]^2 of the workload: {pos.shape[0]} particles, "
                    f"{om.nx}x{om.ny} cells; FP64 Qhull (1 thread) + LAPACK SVD weights + P2M + M2P, "
                    f"{t:.1f} s"),
+        "phases_s": {"build": round(t1 - t0, 3), "project": round(t2 - t1, 4), "interpolate": round(t3 - t2, 4)},
+        "cpu_model": model,
+        "logical_cpus": os.cpu_count(),
     }
+
+
+def hbm_entry(nbytes, ms):
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"algorithmic_bytes": int(nbytes), "achieved_GBs": round(gbs, 2), "frac": round(gbs / HBM_PEAK_GBS, 5)}
+
+
+def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, graph_notes, tuning, log):
+    """The other measured workloads, each timed as HIP graph replays:
+    * 64 independent sets (~10 M particles, h = H/2) built, projected and
+      interpolated in one launch sequence, with the build options tuned on it;
+    * the 4.2 M-particle differentiation workload: M2P -> P2M -> loss
+      residual -> full backward (grad of values, positions and mesh input);
+    * the 16.8 M-particle advected cloud with BF16 particle storage: P2M (and
+      M2P of its result) forward, P2M backward to values and positions.
+    Algorithmic bytes: forward N (2*16 + (v_in + v_out) C) + N_m C (v_out +
+    v_in); a backward adds N (2 C v + 16 + 16) + 2 N_m C v (gradients of values
+    in and out, positions read and gradient written, mesh gradients)."""
+    import numpy as np
+    import torch
+
+    import workloads as wl
+    from paper_1610_05266_amd import ops, tune
+    from paper_1610_05266_amd._lib import P2M_WEIGHTS_F32
+
+    out = {}
+    # ---- 64 sets in one launch sequence
+    log("large: 64-set batch")
+    sets = wl.config3()
+    offs = np.concatenate([[0], np.cumsum([c.N for c in sets])])
+    b = ops.Batch([c.mesh for c in sets], [c.h for c in sets], offs)
+    P = torch.from_numpy(np.concatenate([c.pos for c in sets])).to(dev)
+    V = torch.from_numpy(np.concatenate([c.vals for c in sets])).to(dev, torch.float32)
+    C3 = V.shape[1]
+    wb = ops.p2m_build_weights_batched(b, P, P2M_WEIGHTS_F32)
+    dgb = wb.diag()
+    key = tune.workload_key(torch.cuda.get_device_name(dev), b.N, b.n_nodes, 0.5, P2M_WEIGHTS_F32) + "|64 sets"
+    tres = None
+    if not a.no_tune and not a.set:
+        tres = tune.autotune(lambda: ops.p2m_build_weights_batched(b, P, P2M_WEIGHTS_F32, weights=wb,
+                                                                   check_diag=False),
+                             lambda hd: ops.p2m_project(hd, V), key)
+        log(f"large: batch tuning {tres.options} {tres.median_ms:.4f} ms (default {tres.default_ms:.4f})")
+    bm = torch.empty((b.n_nodes, C3), dtype=torch.float32, device=dev)
+    bo = torch.empty_like(V)
+
+    def step3():
+        ops.p2m_build_weights_batched(b, P, P2M_WEIGHTS_F32, weights=wb, check_diag=False)
+        ops.p2m_project(wb, V, out=bm)
+        ops.m2p_interpolate_batched(b, bm, P, out=bo)
+
+    run3 = as_graph(step3)
+    if run3 is not step3:
+        check_replay(run3, step3, [bm, bo])
+    ms3 = time_loop(run3, "batch64", steps=max(3, a.steps // 2), warmup=2)
+    ph3 = phase_times(step3)
+    B3 = b.N * (2 * 16 + 8 * C3) + b.n_nodes * C3 * 8
+    out["batch64"] = {
+        "workload": f"64 independent sets, {b.N} particles, {b.n_nodes} nodes, meshes 64^2..384^2 (h=H/2), "
+                    "4 FP32 channels, seeded; build + P2M + M2P of all sets in one launch sequence",
+        "ms_per_step": round(ms3, 5), "Mparticles_per_s": round(b.N / (ms3 * 1e-3) / 1e6, 3),
+        "round_trip_hbm": hbm_entry(B3, ms3), "kernels_ms": {k: round(v, 5) for k, v in ph3.items()},
+        "diag": {k: dgb[k] for k in ("slow_nodes", "failed_nodes", "rank_deficient", "svd_systems")},
+        "tuning": None if tres is None else {"options": tres.options, "build_ms_tuned": round(tres.median_ms, 5),
+                                             "build_ms_default": round(tres.default_ms, 5), "cached": tres.cached}}
+    log(f"large: batch64 {ms3:.4f} ms/step")
+    if tres is not None and tuning is not None:
+        tune.apply_options(tuning["options"])
+    del wb, P, V, bm, bo, b, sets
+
+    # ---- 4.2 M particles: M2P -> P2M -> loss -> full backward
+    log("large: 4.2M round trip with backward")
+    c = wl.config4()
+    mesh = ops.Mesh.of(c.mesh)
+    N, nn = c.N, mesh.n_nodes
+    pos = torch.from_numpy(c.pos).to(dev)
+    f32 = torch.from_numpy(c.extra["f_mesh"]).to(dev, torch.float32)
+    g32 = torch.from_numpy(c.extra["g_mesh"]).to(dev, torch.float32)
+    C4 = f32.shape[1]
+    w4 = ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32)
+    a32 = torch.empty((N, C4), dtype=torch.float32, device=dev)
+    o32 = torch.empty((nn, C4), dtype=torch.float32, device=dev)
+    gpos = torch.zeros_like(pos)
+
+    def fwd4():
+        ops.m2p_interpolate(mesh, f32, pos, out=a32)
+        ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32, weights=w4, check_diag=False)
+        ops.p2m_project(w4, a32, out=o32)
+
+    def step4():
+        fwd4()
+        r = o32 - g32
+        gv, gw = ops.p2m_project_backward(w4, r, a32, want_vals=True, want_w=True)
+        gpos.zero_()
+        ops.p2m_build_weights_backward(w4, pos, gw, grad_pos=gpos)
+        ops.m2p_interpolate_backward(mesh, f32, pos, gv, want_mesh=True, grad_pos=gpos)
+
+    steps = max(3, a.steps // 2)
+    run4f = as_graph(fwd4)
+    msf4 = time_loop(run4f, "c4_forward", steps=steps, warmup=2)
+    run4 = as_graph(step4)
+    ms4 = time_loop(run4, "c4_forward_backward", steps=steps, warmup=2)
+    ph4 = phase_times(step4)
+    Bf4 = N * (2 * 16 + 8 * C4) + nn * C4 * 8
+    Bb4 = Bf4 + N * (8 * C4 + 32) + 2 * nn * C4 * 4
+    out["c4"] = {
+        "workload": f"512x512 mesh, 2048x2048 jittered lattice ({N} particles, h=H/4, jitter 0.25h, seed 4), "
+                    "2 FP32 channels: M2P of a mesh field, P2M (weights rebuilt), loss residual, backward to "
+                    "values, positions and the mesh input",
+        "forward_ms": round(msf4, 5), "forward_Mparticles_per_s": round(N / (msf4 * 1e-3) / 1e6, 3),
+        "forward_hbm": hbm_entry(Bf4, msf4),
+        "ms_per_step": round(ms4, 5), "Mparticles_per_s": round(N / (ms4 * 1e-3) / 1e6, 3),
+        "forward_backward_hbm": hbm_entry(Bb4, ms4), "kernels_ms": {k: round(v, 5) for k, v in ph4.items()},
+        "backward_kernels_hbm": {
+            "m2p_bwd": hbm_entry(N * (16 + 4 * C4 + 16) + nn * C4 * 4, ph4["m2p_bwd"]),
+            "project_bwd": hbm_entry(nn * C4 * 4 + N * C4 * 4, ph4["project_bwd"])}}
+    log(f"large: c4 forward {msf4:.4f} ms, forward+backward {ms4:.4f} ms")
+    del w4, pos, f32, g32, a32, o32, gpos
+
+    # ---- 16.8 M particles, BF16 particle storage: forward and backward
+    log("large: 16.8M BF16 workload (generating)")
+    c = wl.config5(device=str(dev))
+    mesh = ops.Mesh.of(c.mesh)
+    N, nn = c.N, mesh.n_nodes
+    pos = torch.from_numpy(c.pos).to(dev)
+    vb = torch.from_numpy(c.vals).to(dev, torch.bfloat16)
+    C5 = vb.shape[1]
+    nodes = np.asarray(c.mesh.node_xy())
+    tgt = torch.from_numpy(np.stack([wl.tg_u(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03),
+                                     wl.tg_v(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03),
+                                     wl.tg_p(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03)], 1)).to(dev, torch.float32)
+    w5 = ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32)
+    d5 = w5.diag()
+    o5 = torch.empty((nn, C5), dtype=torch.float32, device=dev)
+    back5 = torch.empty((N, C5), dtype=torch.bfloat16, device=dev)
+    gp5 = torch.zeros_like(pos)
+
+    def fwd5():
+        ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32, weights=w5, check_diag=False)
+        ops.p2m_project(w5, vb, out=o5)
+        ops.m2p_interpolate(mesh, o5, pos, out=back5, bf16_out=True)
+
+    def step5():
+        fwd5()
+        r = o5 - tgt
+        gv, gw = ops.p2m_project_backward(w5, r, vb, want_vals=True, want_w=True)
+        gp5.zero_()
+        ops.p2m_build_weights_backward(w5, pos, gw, grad_pos=gp5)
+
+    steps = max(3, a.steps // 4)
+    msf5 = time_loop(as_graph(fwd5), "c5_forward", steps=steps, warmup=1)
+    ms5 = time_loop(as_graph(step5), "c5_forward_backward", steps=steps, warmup=1)
+    ph5 = phase_times(step5)
+    Bf5 = N * (2 * 16 + 2 * C5 + 2 * C5) + nn * C5 * 8
+    Bb5 = Bf5 + N * (2 * C5 + 4 * C5 + 16 + 16) + nn * C5 * 4
+    out["c5"] = {
+        "workload": f"1024x1024 mesh, 4096x4096 jittered lattice advected 200 Euler steps through the steady "
+                    f"vortex ({N} particles, h=H/4), 3 channels in BF16 particle storage, FP32 sums, FP64 "
+                    "geometry: P2M (weights rebuilt) and M2P of its result (BF16 out), P2M backward to values "
+                    "and positions",
+        "forward_ms": round(msf5, 5), "forward_Mparticles_per_s": round(N / (msf5 * 1e-3) / 1e6, 3),
+        "forward_hbm": hbm_entry(Bf5, msf5),
+        "ms_per_step": round(ms5, 5), "Mparticles_per_s": round(N / (ms5 * 1e-3) / 1e6, 3),
+        "forward_backward_hbm": hbm_entry(Bb5, ms5), "kernels_ms": {k: round(v, 5) for k, v in ph5.items()},
+        "diag": {k: d5[k] for k in ("slow_nodes", "failed_nodes", "rank_deficient", "svd_systems",
+                                    "max_gram_cond")}}
+    log(f"large: c5 forward {msf5:.4f} ms, forward+backward {ms5:.4f} ms")
+    del w5, pos, vb, o5, back5, gp5
+    torch.cuda.synchronize()
+    return out
 
 
 def main(argv=None):
     a = parse(argv)
+    if a.only_large:
+        a.no_extras = a.no_cpu_baseline = a.no_oracle_check = True
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU design is "
               "described in DESIGN.md and is not built.", file=sys.stderr)
@@ -247,18 +438,30 @@ def main(argv=None):
             fn()
             torch.cuda.synchronize()
 
-    def time_loop(run):
-        for _ in range(a.warmup):
+    step_stats = {}
+
+    def time_loop(run, label=None, steps=None, warmup=None):
+        """Mean ms per step of `steps` runs after `warmup` untimed ones; an
+        event between consecutive runs gives the per-step median and IQR
+        (kept in step_stats[label])."""
+        steps = a.steps if steps is None else steps
+        warmup = a.warmup if warmup is None else warmup
+        for _ in range(warmup):
             run()
         torch.cuda.synchronize()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(a.steps):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        ev[0].record()
+        for k in range(steps):
             run()
-        e1.record()
+            ev[k + 1].record()
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / a.steps
+        per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+        mean = ev[0].elapsed_time(ev[steps]) / steps
+        if label:
+            q25, q50, q75 = np.percentile(per, [25, 50, 75])
+            step_stats[label] = {"mean_ms": round(mean, 5), "median_ms": round(float(q50), 5),
+                                 "iqr_ms": [round(float(q25), 5), round(float(q75), 5)], "steps": steps}
+        return mean
 
     def timed(mixed):
         import ctypes
@@ -271,20 +474,29 @@ def main(argv=None):
             except RuntimeError as exc:
                 graph_notes.append(f"{exc}; eager launches timed")
                 run = fn
-        ms = time_loop(run)
-        # per-phase GPU times from the library's own events, in a separate
+        ms = time_loop(run, "mixed" if mixed else "fp64")
+        # per-kernel GPU times from the library's own events, in a separate
         # eager pass so that the event records do not perturb the timed loop
+        return ms, phase_times(lambda: step(mixed))
+
+    def phase_times(fn, names=("bin", "build", "project", "m2p", "build_fast", "build_slow", "weights",
+                               "k_weights", "k_weights_rd", "m2p_bwd", "project_bwd", "build_bwd")):
+        """Average ms per launch of each kernel group over a.steps eager runs
+        of fn, from the library's events on the stream each group runs on."""
+        import ctypes
+
         lib.p2m_profile_enable(1)
         for _ in range(a.steps):
-            step(mixed)
+            fn()
         torch.cuda.synchronize()
         phases = {}
-        for ph in ("bin", "build", "project", "m2p", "build_fast", "build_slow", "weights"):
+        for ph in names:
             tot, cnt = ctypes.c_double(), ctypes.c_int64()
             lib.p2m_profile_read(ph.encode(), ctypes.byref(tot), ctypes.byref(cnt))
-            phases[ph] = tot.value / max(cnt.value, 1)
+            if cnt.value:
+                phases[ph] = tot.value / cnt.value
         lib.p2m_profile_enable(0)
-        return ms, phases
+        return phases
 
     def cached(mixed):
         """P2M + M2P with the weights of the last build (no rebuild)."""
@@ -296,7 +508,7 @@ def main(argv=None):
             except RuntimeError as exc:
                 graph_notes.append(f"{exc}; eager launches timed")
                 run = fn
-        return time_loop(run)
+        return time_loop(run, "cached_mixed" if mixed else "cached_fp64")
 
     log("timing FP64 form")
     ms64, ph64 = timed(False)
@@ -463,6 +675,10 @@ def main(argv=None):
 
             tune.apply_options(tuning["options"])
 
+    large = None
+    if not a.no_large:
+        large = large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, graph_notes, tuning, log)
+
     # accuracy of the mixed form against the FP64 form (both full outputs)
     e_mesh = rel_errs(mesh32.cpu().numpy(), mesh64.cpu().numpy())
     e_part = rel_errs(out32.cpu().numpy(), out64.cpu().numpy())
@@ -487,7 +703,7 @@ def main(argv=None):
     kern = {
         "k_build_fast": ("alu", FAST_FLOP_INTERIOR * ni + FAST_FLOP_RING * nc, ph32["build_fast"],
                          f"{FAST_FLOP_INTERIOR:g} FP64 flop/interior node, {FAST_FLOP_RING:g}/ring node"),
-        "k_weights": ("alu", WEIGHTS_FLOP_INTERIOR * ni + WEIGHTS_FLOP_CLOSURE * nc, ph32["weights"],
+        "k_weights": ("alu", WEIGHTS_FLOP_INTERIOR * ni + WEIGHTS_FLOP_CLOSURE * nc, ph32["k_weights"],
                       f"{WEIGHTS_FLOP_INTERIOR:g} FP64 flop/interior node, {WEIGHTS_FLOP_CLOSURE:g}/closure node"),
         "binning": ("hbm", 36.0 * N, ph32["bin"], "36 B/particle (16 in, 20 out)"),
         "k_project": ("hbm", N * 4 * C + nn * C * 4, ph32["project"], "values in + mesh out, FP32"),
@@ -595,6 +811,8 @@ def main(argv=None):
         "phases_ms": {k: round(v, 5) for k, v in ph32.items()},
         "errors": result_err,
         "diag": diag,
+        "step_stats": step_stats,
+        "large": large,
     }
     print(json.dumps(out), flush=True)
     if a.copy_probe:

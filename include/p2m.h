@@ -451,7 +451,8 @@ int p2m_get_option(const char* name, double* value);
  * p2m_profile_enable(1) clears the totals and starts recording a pair of HIP
  * events on the caller's stream around each group ("bin", "build",
  * "project", "m2p", "m2p_bwd", "project_bwd", "build_bwd", and the three
- * parts of "build": "build_fast", "build_slow", "weights"); 0 stops.
+ * parts of "build": "build_fast", "build_slow", "weights", the last also
+ * as its two kernels alone: "k_weights", "k_weights_rd"); 0 stops.
  * p2m_profile_read() waits for the recorded events and returns the summed
  * GPU time in milliseconds and the number of launches of one group. */
 int p2m_profile_enable(int on);

@@ -15,8 +15,8 @@
 //     is the exact derivative.
 //   * the right-hand side -d d^t / 2 (d the scaled edge vector) of eq. A2_2
 //     depends on the two edge ends.
-// Contributions are accumulated per support entry in LDS and added to
-// grad_pos with one pair of atomics per entry.
+// A quad of lanes per node (the forward's layout, k_build_bwd); every
+// support entry ends with one pair of atomics on grad_pos.
 //
 // Rows the forward solved with the rank-revealing solver (flag MF_SVD) are
 // differentiated by a second kernel, one wave per row, from the SVD of each
@@ -28,6 +28,7 @@
 // Both kernels use the forward's algebra (algebra.h): its Cholesky with
 // reciprocal pivots and the same SVD.
 #include <cfloat>
+#include <type_traits>
 
 #include "algebra.h"
 #include "kernels.h"
@@ -35,8 +36,6 @@
 namespace p2m {
 
 namespace {
-
-constexpr int WG = 64;
 
 struct BArgs {
     WeightsView w;
@@ -46,204 +45,318 @@ struct BArgs {
     int per;  // periodic box: support positions are the nearest images
 };
 
-// Reverse-mode of one minimum-norm block.  Entries k < n with member(k);
-// coord(k, x, y) gives the centred, scaled coordinates, wb(k) the Abar
-// weights, and add(k, gx, gy) receives d/d(coords).  b is the right-hand side;
-// on return bbar holds z.
-template <class Member, class Coord, class Abar, class Add>
-__device__ bool block_backward(int n, Member member, Coord coord, const double b[6], Abar abar, Add add,
-                               double y[6], double bbar[6]) {
-    double L[6][6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i)
-#pragma unroll
-        for (int j = 0; j < 6; ++j) L[i][j] = 0.0;
-    for (int k = 0; k < n; ++k) {
-        if (!member(k)) continue;
-        double x, yy, p[6];
-        coord(k, x, yy);
-        monos(x, yy, p);
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-#pragma unroll
-            for (int j2 = 0; j2 <= i; ++j2) L[i][j2] += p[i] * p[j2];
-    }
-    if (!chol6(L)) return false;
-    chol6_solve(L, b, y);
-    // refine y as the forward does
-    double r[6] = {b[0], b[1], b[2], b[3], b[4], b[5]};
-    double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int k = 0; k < n; ++k) {
-        if (!member(k)) continue;
-        double x, yy, p[6];
-        coord(k, x, yy);
-        monos(x, yy, p);
-        const double a = dot6(p, y);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) r[i] -= a * p[i];
-    }
-    double d[6];
-    chol6_solve(L, r, d);
-#pragma unroll
-    for (int i = 0; i < 6; ++i) y[i] += d[i];
-    for (int k = 0; k < n; ++k) {
-        if (!member(k)) continue;
-        double x, yy, p[6];
-        coord(k, x, yy);
-        monos(x, yy, p);
-        const double ab = abar(k);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) v[i] += ab * p[i];
-    }
-    double z[6];
-    chol6_solve(L, v, z);
-    for (int k = 0; k < n; ++k) {
-        if (!member(k)) continue;
-        double x, yy, p[6];
-        coord(k, x, yy);
-        monos(x, yy, p);
-        const double A = dot6(p, y);
-        const double zp = dot6(z, p);
-        const double ab = abar(k);
-        double pb[6];
-#pragma unroll
-        for (int i = 0; i < 6; ++i) pb[i] = y[i] * ab - z[i] * A - y[i] * zp;
-        // d p / dx = (0, 1, 0, 2x, y, 0), d p / dy = (0, 0, 1, 0, x, 2y)
-        const double gx = pb[1] + 2.0 * x * pb[3] + yy * pb[4];
-        const double gy = pb[2] + x * pb[4] + 2.0 * yy * pb[5];
-        add(k, gx, gy);
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) bbar[i] = z[i];
-    return true;
+// ---- rows solved by Cholesky: a quad of four lanes per node, nodes in the
+// 8 x 8 tiles of the forward's weights pass.  Lanes 0..2 each redo one edge
+// system as the forward solved it (same frame: the edge midpoint and length;
+// moments, Cholesky with reciprocal pivots, one refinement step), then
+// z = G^-1 M Abar and sum_mu wbar_mu A_mu; a closure row's one system is
+// computed by all four lanes (strided passes, quad sums), as in the forward.
+// Each lane then differentiates the support entries it owns (entry k by
+// lane k % 4) with every system's y, z and frame broadcast within the quad:
+// Mbar_k = y Abar_k - z A_k - y (z . p_k), chained through the monomials
+// p_k of the frame (whose centre and scale are held fixed: the solution does
+// not depend on them).  The edge ends also get the derivative through the
+// right-hand side -d d^t / 2, and the triangle's vertices the barycentric
+// part.  Every owned entry ends with one pair of atomics on grad_pos.
+constexpr int QL = 4;
+constexpr int QWG = 256;
+constexpr int QPB = QWG / QL;
+constexpr int SK = 16;       // support entries staged in LDS per node
+constexpr int SKP = SK + 1;  // LDS row pitch (distinct banks across quads)
+constexpr int MSE = KMAX / QL;
+
+// Value of v in lane L of the quad (DPP quad permute, no LDS round trip).
+template <int L>
+__device__ __forceinline__ double quad_bcast(double v) {
+    constexpr int ctrl = L | (L << 2) | (L << 4) | (L << 6);
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), ctrl, 0xF, 0xF, false);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ double quad_sum(double v) {
+    v += lane_xor<QL>(v, 1);
+    v += lane_xor<QL>(v, 2);
+    return v;
 }
 
-__global__ void __launch_bounds__(WG) k_build_bwd(BArgs a) {
-    __shared__ double sgx[KMAX * WG];
-    __shared__ double sgy[KMAX * WG];
-    const int tid = threadIdx.x;
-    const int64_t node = static_cast<int64_t>(blockIdx.x) * WG + tid;
-    if (node >= a.w.n_nodes) return;
-    const SetDesc& sd = a.w.sets[set_search(a.w.S, node, [&](int s) { return a.w.sets[s].n0; })];
-    const MeshD m = sd.m;
-    const int stride = m.nx + 1;
-    const int64_t ln = node - sd.n0;
-    const int i = static_cast<int>(ln % stride), j = static_cast<int>(ln / stride);
-    const int64_t slot = node_slot(sd, i, j);
-    const uint32_t meta = a.w.meta[slot];
-    const uint32_t type = meta_type(meta);
-    const int n = row_len(meta);
-    if (type == NT_FAILED || n == 0) return;
-    if (meta_flags(meta) & MF_SVD) return;  // k_build_bwd_svd
-    const int64_t nn = a.w.n_nodes, ns = a.w.n_slots;
-    const bool per = a.per != 0;
-    const double2 q = node_at(m, i, j, per);
-    double* gx = sgx + tid;
-    double* gy = sgy + tid;
-    for (int k = 0; k < n; ++k) {
-        gx[k * WG] = 0.0;
-        gy[k * WG] = 0.0;
-    }
-    // (an image moves with its particle: its derivative is the particle's)
-    auto P = [&](int k) {
-        const double2 p = a.pos[a.w.idx[k * ns + slot]];
-        return per ? image_near(m, p, q) : p;
-    };
-    auto wbar = [&](int k) { return a.gw[k * nn + node]; };
-    auto add = [&](int k, double dx, double dy) {
-        gx[k * WG] += dx;
-        gy[k * WG] += dy;
-    };
+// dL/d(position) of a support entry at frame coordinates (x, y) (frame
+// scale sc) for the block derivative pbar = dL/dp_k.
+__device__ __forceinline__ void chain_monos(const double pbar[6], double x, double y, double sc, double& gx,
+                                            double& gy) {
+    // d p / dx = (0, 1, 0, 2x, y, 0), d p / dy = (0, 0, 1, 0, x, 2y)
+    gx += sc * (pbar[1] + 2.0 * x * pbar[3] + y * pbar[4]);
+    gy += sc * (pbar[2] + x * pbar[4] + 2.0 * y * pbar[5]);
+}
 
-    if (type == NT_INTERIOR) {
-        const int lt[3] = {static_cast<int>(meta_t(meta, 0)), static_cast<int>(meta_t(meta, 1)),
-                           static_cast<int>(meta_t(meta, 2))};
+template <bool PER>
+__global__ void __launch_bounds__(QWG) k_build_bwd(BArgs a) {
+    __shared__ double2 sp[QPB * SKP];
+    __shared__ double sw[QPB * SKP];
+    __shared__ uint32_t sm[QPB * SKP];
+    const int lane = threadIdx.x & (QL - 1);
+    const int qi = threadIdx.x / QL;
+    const int64_t tile = blockIdx.x;
+    const SetDesc& sd = a.w.sets[set_search(a.w.S, tile, [&](int s) { return a.w.sets[s].t0; })];
+    const int64_t slot = tile * TILE_N + qi;
+    int i, j;
+    const bool valid = slot_ij(sd, slot, i, j);
+    const uint32_t meta = valid ? a.w.meta[slot] : 0u;
+    const uint32_t type = meta_type(meta);
+    const int n = valid ? row_len(meta) : 0;
+    const bool inter = valid && n > 0 && !(meta_flags(meta) & MF_SVD) && type == NT_INTERIOR;
+    const bool clos = valid && n > 0 && !(meta_flags(meta) & MF_SVD) && (type == NT_RING || type == NT_OUTSIDE);
+    const bool act = inter || clos;
+    const int64_t node = valid ? ij_node(sd, i, j) : 0;
+    const int64_t nn = a.w.n_nodes, ns = a.w.n_slots;
+    const double2 q = node_at(sd.m, i, j, PER);
+    auto img = [&](double2 p) { return PER ? image_near(sd.m, p, q) : p; };
+    // stage the first SK entries: position (image), wbar, ring bits
+    const int nst = act ? min(n, SK) : 0;
+#pragma unroll
+    for (int s = 0; s < SK / QL; ++s) {
+        const int k = s * QL + lane;
+        if (k < nst) {
+            const int64_t u = a.w.idx[k * ns + slot];
+            sp[qi * SKP + k] = img(a.pos[u]);
+            sw[qi * SKP + k] = a.gw[k * nn + node];
+            sm[qi * SKP + k] = a.w.mem[k * ns + slot];
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    auto P = [&](int k) -> double2 { return k < SK ? sp[qi * SKP + k] : img(a.pos[a.w.idx[k * ns + slot]]); };
+    auto W = [&](int k) -> double { return k < SK ? sw[qi * SKP + k] : a.gw[k * nn + node]; };
+    auto Mb = [&](int k) -> uint32_t { return k < SK ? sm[qi * SKP + k] : a.w.mem[k * ns + slot]; };
+
+    double gx[MSE], gy[MSE];  // owned entries k = s * QL + lane
+#pragma unroll
+    for (int s = 0; s < MSE; ++s) gx[s] = gy[s] = 0.0;
+    double tvx[3] = {0.0, 0.0, 0.0}, tvy[3] = {0.0, 0.0, 0.0};  // extra terms of T's vertices
+    int lt[3] = {-1, -1, -1};
+    int skipped = 0;
+    if (inter) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) lt[k] = static_cast<int>(meta_t(meta, k));
         const double2 P0 = P(lt[0]), P1 = P(lt[1]), P2 = P(lt[2]);
         const double D = (P1.x - P0.x) * (P2.y - P0.y) - (P1.y - P0.y) * (P2.x - P0.x);
         const double phi[3] = {((P1.x - q.x) * (P2.y - q.y) - (P1.y - q.y) * (P2.x - q.x)) / D,
                                ((q.x - P0.x) * (P2.y - P0.y) - (q.y - P0.y) * (P2.x - P0.x)) / D,
                                ((P1.x - P0.x) * (q.y - P0.y) - (P1.y - P0.y) * (q.x - P0.x)) / D};
-        double phib[3] = {wbar(lt[0]), wbar(lt[1]), wbar(lt[2])};
-        for (int e = 0; e < 3; ++e) {
-            const int pa = e, pb = (e + 1) % 3;
-            const double2 rn = P(lt[pa]), rs = P(lt[pb]);
-            const double cxm = 0.5 * (rn.x + rs.x), cym = 0.5 * (rn.y + rs.y);
+        // phase 1: lane e < 3 redoes edge system e
+        double y[6] = {0, 0, 0, 0, 0, 0}, z[6] = {0, 0, 0, 0, 0, 0};
+        double cx = 0.0, cy = 0.0, sc = 1.0, sa = 0.0;
+        int ok = 1;
+        if (lane < 3) {
+            const int pb = lane == 2 ? 0 : lane + 1;
+            const double2 rn = lane == 0 ? P0 : (lane == 1 ? P1 : P2);
+            const double2 rs = pb == 0 ? P0 : (pb == 1 ? P1 : P2);
+            cx = 0.5 * (rn.x + rs.x);
+            cy = 0.5 * (rn.y + rs.y);
             const double dxv = rn.x - rs.x, dyv = rn.y - rs.y;
-            const double is = 1.0 / sqrt(dxv * dxv + dyv * dyv);
-            const int mask = (1 << pa) | (1 << pb);
-            auto member = [&](int k) { return (a.w.mem[k * ns + slot] & mask) != 0; };
-            auto coord = [&](int k, double& x, double& y) {
-                const double2 p = P(k);
-                x = (p.x - cxm) * is;
-                y = (p.y - cym) * is;
-            };
-            const double coef = 2.0 * phi[pa] * phi[pb];
-            auto abar = [&](int k) { return coef * wbar(k); };
-            auto addsc = [&](int k, double dx, double dy) { add(k, dx * is, dy * is); };
-            const double dx = dxv * is, dy = dyv * is;
+            sc = 1.0 / sqrt(dxv * dxv + dyv * dyv);
+            const uint32_t mask = (1u << lane) | (1u << pb);
+            const double pa_ = lane == 0 ? phi[0] : (lane == 1 ? phi[1] : phi[2]);
+            const double pb_ = pb == 0 ? phi[0] : (pb == 1 ? phi[1] : phi[2]);
+            const double coef = 2.0 * pa_ * pb_;
+            const double dx = dxv * sc, dy = dyv * sc;
             const double b[6] = {0.0, 0.0, 0.0, -0.5 * dx * dx, -0.5 * dx * dy, -0.5 * dy * dy};
-            double y[6], bb[6];
-            if (!block_backward(n, member, coord, b, abar, addsc, y, bb)) {
+            Moments mo;
+            mo.zero();
+            for (int k = 0; k < n; ++k) {
+                if (!(Mb(k) & mask)) continue;
+                const double2 p = P(k);
+                mo.add((p.x - cx) * sc, (p.y - cy) * sc);
+            }
+            double L[6][6];
+            mo.gram(L);
+            ok = chol6(L) ? 1 : 0;
+            if (ok) {
+                chol6_solve(L, b, y);
+                double r[6] = {0, 0, 0, 0, 0, 0};
+                for (int k = 0; k < n; ++k) {
+                    if (!(Mb(k) & mask)) continue;
+                    const double2 p = P(k);
+                    double pm[6];
+                    monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
+                    const double A = dot6(pm, y);
+#pragma unroll
+                    for (int t = 0; t < 6; ++t) r[t] += A * pm[t];
+                }
+#pragma unroll
+                for (int t = 0; t < 6; ++t) r[t] = b[t] - r[t];
+                double d[6];
+                chol6_solve(L, r, d);
+#pragma unroll
+                for (int t = 0; t < 6; ++t) y[t] += d[t];
+                // v = M Abar (Abar_k = coef wbar_k) and sum_k wbar_k A_k
+                double v[6] = {0, 0, 0, 0, 0, 0};
+                for (int k = 0; k < n; ++k) {
+                    if (!(Mb(k) & mask)) continue;
+                    const double2 p = P(k);
+                    double pm[6];
+                    monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
+                    const double wk = W(k);
+                    sa += wk * dot6(pm, y);
+                    const double ab = coef * wk;
+#pragma unroll
+                    for (int t = 0; t < 6; ++t) v[t] += ab * pm[t];
+                }
+                chol6_solve(L, v, z);
+            } else {
                 // (the forward's Cholesky accepted this system with a wide
                 // margin, so this does not happen; counted if it does)
-                atomicAdd(&a.w.diag[D_BWDSKIP], 1ull);
-                continue;
+#pragma unroll
+                for (int t = 0; t < 6; ++t) y[t] = z[t] = 0.0;
+                skipped = 1;
             }
-            // sum_mu wbar_mu A_mu feeds phibar of the two edge ends
-            double sa = 0.0;
-            for (int k = 0; k < n; ++k) {
-                if (!member(k)) continue;
-                double x, yy, p[6];
-                coord(k, x, yy);
-                monos(x, yy, p);
-                sa += wbar(k) * dot6(p, y);
-            }
-            phib[pa] += 2.0 * phi[pb] * sa;
-            phib[pb] += 2.0 * phi[pa] * sa;
-            // right-hand side: b = (0,0,0,-dx^2/2,-dx dy/2,-dy^2/2), d = (r_nu - r_sigma) * is
-            const double ddx = -bb[3] * dx - 0.5 * bb[4] * dy;
-            const double ddy = -0.5 * bb[4] * dx - bb[5] * dy;
-            add(lt[pa], ddx * is, ddy * is);
-            add(lt[pb], -ddx * is, -ddy * is);
         }
+        // phase 2: every lane differentiates its own entries
+        double phib[3] = {W(lt[0]), W(lt[1]), W(lt[2])};
+        auto edge = [&](auto E) {
+            constexpr int e = decltype(E)::value;
+            constexpr int pa = e, pb = e == 2 ? 0 : e + 1;
+            double ye[6], ze[6];
+#pragma unroll
+            for (int t = 0; t < 6; ++t) {
+                ye[t] = quad_bcast<e>(y[t]);
+                ze[t] = quad_bcast<e>(z[t]);
+            }
+            const double cxe = quad_bcast<e>(cx), cye = quad_bcast<e>(cy), sce = quad_bcast<e>(sc);
+            const double sae = quad_bcast<e>(sa);
+            const double coef = 2.0 * phi[pa] * phi[pb];
+            phib[pa] += 2.0 * phi[pb] * sae;
+            phib[pb] += 2.0 * phi[pa] * sae;
+            constexpr uint32_t mask = (1u << pa) | (1u << pb);
+#pragma unroll
+            for (int s = 0; s < MSE; ++s) {
+                const int k = s * QL + lane;
+                if (k >= n || !(Mb(k) & mask)) continue;
+                const double2 p = P(k);
+                const double x = (p.x - cxe) * sce, yy = (p.y - cye) * sce;
+                double pm[6];
+                monos(x, yy, pm);
+                const double A = dot6(pm, ye), zp = dot6(ze, pm), ab = coef * W(k);
+                double pbar[6];
+#pragma unroll
+                for (int t = 0; t < 6; ++t) pbar[t] = ye[t] * ab - ze[t] * A - ye[t] * zp;
+                chain_monos(pbar, x, yy, sce, gx[s], gy[s]);
+            }
+            // right-hand side: b = (0, 0, 0, -dx^2/2, -dx dy/2, -dy^2/2), d = (r_nu - r_sigma) sc
+            const double2 rn = pa == 0 ? P0 : (pa == 1 ? P1 : P2);
+            const double2 rs = pb == 0 ? P0 : (pb == 1 ? P1 : P2);
+            const double dx = (rn.x - rs.x) * sce, dy = (rn.y - rs.y) * sce;
+            const double ddx = -ze[3] * dx - 0.5 * ze[4] * dy;
+            const double ddy = -0.5 * ze[4] * dx - ze[5] * dy;
+            tvx[pa] += ddx * sce;
+            tvy[pa] += ddy * sce;
+            tvx[pb] -= ddx * sce;
+            tvy[pb] -= ddy * sce;
+        };
+        edge(std::integral_constant<int, 0>{});
+        edge(std::integral_constant<int, 1>{});
+        edge(std::integral_constant<int, 2>{});
         // barycentric coordinates
         const double e1x = P1.x - P0.x, e1y = P1.y - P0.y, e2x = P2.x - P0.x, e2y = P2.y - P0.y;
         const double f1 = phib[1] - phib[0], f2 = phib[2] - phib[0];
         const double lx = (f1 * e2y - f2 * e1y) / D;
         const double ly = (-f1 * e2x + f2 * e1x) / D;
-        for (int k = 0; k < 3; ++k) add(lt[k], -phi[k] * lx, -phi[k] * ly);
-    } else {
-        // closure node: weights = M^t y with G y = p(q), centroid / RMS scaled
-        double mx = 0.0, my = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double2 p = P(k);
-            mx += p.x;
-            my += p.y;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            tvx[k] -= phi[k] * lx;
+            tvy[k] -= phi[k] * ly;
         }
-        mx /= n;
-        my /= n;
-        double r2 = 0.0;
-        for (int k = 0; k < n; ++k) {
-            const double2 p = P(k);
-            r2 += (p.x - mx) * (p.x - mx) + (p.y - my) * (p.y - my);
-        }
-        const double isc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
-        auto member = [&](int) { return true; };
-        auto coord = [&](int k, double& x, double& y) {
-            const double2 p = P(k);
-            x = (p.x - mx) * isc;
-            y = (p.y - my) * isc;
+        skipped += lane_xor<QL>(skipped, 1);
+        skipped += lane_xor<QL>(skipped, 2);
+    } else if (clos) {
+        // weights = M^t y with G y = p(q), the forward's frame: centroid of the
+        // nearest particles, RMS radius; passes shared by the four lanes
+        auto each4 = [&](auto&& f) {
+            for (int k = lane; k < nst; k += QL) f(k, sp[qi * SKP + k]);
+            for (int k = SK + lane; k < n; k += QL) f(k, P(k));
         };
-        auto addsc = [&](int k, double dx, double dy) { add(k, dx * isc, dy * isc); };
+        double sx = 0.0, sy = 0.0;
+        each4([&](int, double2 p) {
+            sx += p.x;
+            sy += p.y;
+        });
+        const double cx = quad_sum(sx) / n, cy = quad_sum(sy) / n;
+        double r2 = 0.0;
+        each4([&](int, double2 p) { r2 += (p.x - cx) * (p.x - cx) + (p.y - cy) * (p.y - cy); });
+        r2 = quad_sum(r2);
+        const double sc = r2 > 0.0 ? 1.0 / sqrt(r2 / n) : 1.0;
+        Moments mo;
+        mo.zero();
+        each4([&](int, double2 p) { mo.add((p.x - cx) * sc, (p.y - cy) * sc); });
+#pragma unroll
+        for (int t = 0; t < 15; ++t) mo.m[t] = quad_sum(mo.m[t]);
         double b[6];
-        monos((q.x - mx) * isc, (q.y - my) * isc, b);
-        double y[6], bb[6];
-        if (!block_backward(n, member, coord, b, wbar, addsc, y, bb)) atomicAdd(&a.w.diag[D_BWDSKIP], 1ull);
+        monos((q.x - cx) * sc, (q.y - cy) * sc, b);
+        double L[6][6];
+        mo.gram(L);
+        if (chol6(L)) {
+            double y[6], z[6];
+            chol6_solve(L, b, y);
+            double r[6] = {0, 0, 0, 0, 0, 0}, v[6] = {0, 0, 0, 0, 0, 0};
+            each4([&](int, double2 p) {
+                double pm[6];
+                monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
+                const double A = dot6(pm, y);
+#pragma unroll
+                for (int t = 0; t < 6; ++t) r[t] += A * pm[t];
+            });
+#pragma unroll
+            for (int t = 0; t < 6; ++t) r[t] = b[t] - quad_sum(r[t]);
+            double d[6];
+            chol6_solve(L, r, d);
+#pragma unroll
+            for (int t = 0; t < 6; ++t) y[t] += d[t];
+            each4([&](int k, double2 p) {
+                double pm[6];
+                monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
+                const double wk = W(k);
+#pragma unroll
+                for (int t = 0; t < 6; ++t) v[t] += wk * pm[t];
+            });
+#pragma unroll
+            for (int t = 0; t < 6; ++t) v[t] = quad_sum(v[t]);
+            chol6_solve(L, v, z);
+#pragma unroll
+            for (int s = 0; s < MSE; ++s) {
+                const int k = s * QL + lane;
+                if (k >= n) continue;
+                const double2 p = P(k);
+                const double x = (p.x - cx) * sc, yy = (p.y - cy) * sc;
+                double pm[6];
+                monos(x, yy, pm);
+                const double A = dot6(pm, y), zp = dot6(z, pm), ab = W(k);
+                double pbar[6];
+#pragma unroll
+                for (int t = 0; t < 6; ++t) pbar[t] = y[t] * ab - z[t] * A - y[t] * zp;
+                chain_monos(pbar, x, yy, sc, gx[s], gy[s]);
+            }
+        } else {
+            skipped = 1;
+        }
     }
-    for (int k = 0; k < n; ++k) {
-        const int64_t u = a.w.idx[k * ns + slot];
-        atomicAdd(&a.gpos[u].x, gx[k * WG]);
-        atomicAdd(&a.gpos[u].y, gy[k * WG]);
+    if (act) {
+#pragma unroll
+        for (int s = 0; s < MSE; ++s) {
+            const int k = s * QL + lane;
+            if (k >= n) continue;
+            double ax = gx[s], ay = gy[s];
+#pragma unroll
+            for (int t = 0; t < 3; ++t)
+                if (k == lt[t]) {
+                    ax += tvx[t];
+                    ay += tvy[t];
+                }
+            const int64_t u = a.w.idx[k * ns + slot];
+            atomicAdd(&a.gpos[u].x, ax);
+            atomicAdd(&a.gpos[u].y, ay);
+        }
+        if (lane == 0 && skipped) atomicAdd(&a.w.diag[D_BWDSKIP], static_cast<unsigned long long>(skipped));
     }
 }
 
@@ -445,8 +558,10 @@ int build_backward(const WeightsView& w, const double* pos, const double* grad_w
     // kernel, so that the call can be captured in a graph)
     int rc = fill_u64(w.diag + D_BWDSKIP, 0ull, 1, st);
     if (rc) return rc;
-    const int blocks = static_cast<int>((w.n_nodes + WG - 1) / WG);
-    k_build_bwd<<<blocks, WG, 0, st>>>(a);
+    // a block per 8 x 8 node tile (the forward's tiles), a quad per node
+    const int blocks = static_cast<int>(w.n_slots / TILE_N);
+    if (periodic) k_build_bwd<true><<<blocks, QWG, 0, st>>>(a);
+    else k_build_bwd<false><<<blocks, QWG, 0, st>>>(a);
     P2M_HIP(hipGetLastError());
     // rows of the rank-revealing solver (normally none; the grid loops over
     // the list)

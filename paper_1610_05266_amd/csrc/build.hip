@@ -2191,13 +2191,19 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         PhaseTimer t3(PH_WEIGHTS, st);
         // (one weighting code for both passes, so that a row does not depend
         // on the pass that found it)
-        if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
-        else k_weights<false><<<tiles, QWG, 0, st>>>(a);
+        {
+            PhaseTimer t4(PH_K_WEIGHTS, st);
+            if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
+            else k_weights<false><<<tiles, QWG, 0, st>>>(a);
+        }
         if (fork) P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
         // ill-conditioned or rank-deficient rows of either pass (normally none)
         // (a wave per listed row; the grid loops over the list)
-        if (periodic) k_weights_rd<true><<<64, QWG, 0, st>>>(a);
-        else k_weights_rd<false><<<64, QWG, 0, st>>>(a);
+        {
+            PhaseTimer t5(PH_K_WEIGHTS_RD, st);
+            if (periodic) k_weights_rd<true><<<64, QWG, 0, st>>>(a);
+            else k_weights_rd<false><<<64, QWG, 0, st>>>(a);
+        }
         if (periodic) k_seam_copy<<<tiles, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());

@@ -8,7 +8,7 @@ namespace p2m {
 // ---- optional event timing of kernel groups (profile.hip) ----
 enum Phase : int {
     PH_BIN = 0, PH_BUILD, PH_PROJECT, PH_M2P, PH_M2P_BWD, PH_PROJECT_BWD, PH_BUILD_BWD,
-    PH_BUILD_FAST, PH_BUILD_SLOW, PH_WEIGHTS, PH_COUNT
+    PH_BUILD_FAST, PH_BUILD_SLOW, PH_WEIGHTS, PH_K_WEIGHTS, PH_K_WEIGHTS_RD, PH_COUNT
 };
 class PhaseTimer {
   public:

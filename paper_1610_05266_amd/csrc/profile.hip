@@ -23,8 +23,9 @@ std::vector<Rec> g_recs;
 double g_total_ms[PH_COUNT];
 long long g_count[PH_COUNT];
 
-const char* kNames[PH_COUNT] = {"bin",       "build",      "project",    "m2p",    "m2p_bwd",
-                                "project_bwd", "build_bwd", "build_fast", "build_slow", "weights"};
+const char* kNames[PH_COUNT] = {"bin",       "build",      "project",    "m2p",        "m2p_bwd",
+                                "project_bwd", "build_bwd", "build_fast", "build_slow", "weights",
+                                "k_weights",   "k_weights_rd"};
 
 hipEvent_t take() {
     if (g_pool.empty()) {
