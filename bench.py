@@ -252,7 +252,9 @@ def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, grap
         gv, gw = ops.p2m_project_backward(w4, r, a32, want_vals=True, want_w=True)
         gpos.zero_()
         ops.p2m_build_weights_backward(w4, pos, gw, grad_pos=gpos)
-        ops.m2p_interpolate_backward(mesh, f32, pos, gv, want_mesh=True, grad_pos=gpos)
+        # the M2P adjoint gathered per node through the build's binning (the
+        # handle was built from the same positions): no atomics
+        ops.m2p_interpolate_backward_binned(w4, f32, pos, gv, want_mesh=True, grad_pos=gpos)
 
     steps = max(3, a.steps // 2)
     run4f = as_graph(fwd4)

@@ -294,6 +294,24 @@ int m2p_interpolate_backward(const p2m_mesh* mesh, const void* mesh_vals, int C,
                              void* grad_mesh, double* grad_pos, void* stream);
 
 /*
+ * m2p_interpolate_backward_binned -- m2p_interpolate_backward at the particles
+ * a weights handle was built from, using that build's binning (the adjoint
+ * of eq. m2p: grad_mesh[i] = sum_mu phi^m_i(r_mu) grad_vals[mu]).
+ *  w          handle built from `pos` (the same array, unchanged since); its
+ *             mesh, or for a batched handle every set's mesh, is the mesh.
+ *  grad_mesh  OVERWRITTEN, as in m2p_interpolate_backward, but gathered per
+ *             node from the particles of the bins around its cells (each
+ *             located exactly as the forward locates it): no atomics, and
+ *             the same bits on every run.  May be NULL.
+ *  grad_pos   ACCUMULATED exactly as m2p_interpolate_backward does.  May be
+ *             NULL; mesh_vals is needed only when it is not.
+ * Other arguments and types as m2p_interpolate_backward.
+ */
+int m2p_interpolate_backward_binned(const p2m_weights* w, const void* mesh_vals, int C, int dtype,
+                                    const double* pos, const void* grad_vals, void* grad_mesh,
+                                    double* grad_pos, void* stream);
+
+/*
  * p2m_project_backward -- adjoint of p2m_project for fixed weights.
  *  grad_mesh  device [(nx+1)(ny+1)][C] upstream gradient (dtype; FP32 for BF16).
  *  grad_vals  device [N][C] output (dtype; FP32 for BF16), OVERWRITTEN with

@@ -72,6 +72,8 @@ _SIGS = {
     "m2p_interpolate_backward": (c_int, [POINTER(P2MMesh), c_void_p, c_int, c_int, c_void_p, c_int64, c_void_p,
                                          c_void_p, c_void_p, c_void_p]),
     "p2m_project_backward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "m2p_interpolate_backward_binned": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_void_p,
+                                                c_void_p, c_void_p]),
     "p2m_build_weights_backward": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "p2m_weights_destroy": (None, [c_void_p]),
     "p2m_mesh_qcsf_create": (c_int, [POINTER(P2MMesh), POINTER(c_void_p), c_void_p]),

@@ -251,6 +251,9 @@ WeightsView view(const p2m_weights* w) {
     v.mem = w->mem;
     v.rd = w->rd;
     v.diag = w->diag;
+    v.pos_s = reinterpret_cast<const double2*>(w->bins.pos_s);
+    v.perm = w->bins.perm;
+    v.start = w->bins.start;
     return v;
 }
 
@@ -838,6 +841,22 @@ int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, 
     }
     return m2p_backward(MeshD{}, b->dsets, b->S(), b->tot.n_nodes, mesh_vals, C, dtype, pos, b->tot.N, grad_vals,
                         grad_mesh, grad_pos, static_cast<hipStream_t>(stream));
+}
+
+int m2p_interpolate_backward_binned(const p2m_weights* w, const void* mesh_vals, int C, int dtype,
+                                    const double* pos, const void* grad_vals, void* grad_mesh, double* grad_pos,
+                                    void* stream) {
+    int rc = check_handle(w);
+    if (!rc) rc = check_vals(grad_vals, C, dtype == P2M_BF16 ? P2M_F32 : dtype, "grad_vals", true);
+    if (!rc && grad_mesh) rc = check_vals(grad_mesh, C, dtype, "grad_mesh", true);
+    if (!rc && grad_pos) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
+    if (rc) return rc;
+    if (!pos || !aligned(pos, 16) || (grad_pos && !aligned(grad_pos, 16))) {
+        set_error("pos / grad_pos NULL or misaligned");
+        return P2M_EINVAL;
+    }
+    return m2p_backward_binned(view(w), mesh_vals, C, dtype, pos, grad_vals, grad_mesh, grad_pos,
+                               static_cast<hipStream_t>(stream));
 }
 
 int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int dtype, const void* vals,

@@ -190,6 +190,9 @@ struct WeightsView {
     const uint8_t* mem;     // [KMAX][n_slots]
     const int32_t* rd;      // row slots solved by the rank-revealing solver
     unsigned long long* diag;  // the build's diagnostics (count of rd: D_RDCNT)
+    const double2* pos_s;   // [N] positions in bin order (the binning)
+    const int32_t* perm;    // [N] bin order -> user id
+    const int32_t* start;   // first bin-order slot of every bin (bins of set s from sets[s].b0)
 };
 
 // Exact-rounding helpers: products/sums that must not be contracted into

@@ -99,6 +99,10 @@ int advect_midpoint(const MeshD& m, double* pos, int64_t N, double amp, double d
                     bool periodic);
 int m2p(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C, int dtype,
         const double* pos, int64_t N, void* vals, hipStream_t st);
+// M2P adjoint at the particles of a weights handle (built from `pos`): grad_mesh
+// gathered per node through the handle's binning, grad_pos per particle.
+int m2p_backward_binned(const WeightsView& wv, const void* mesh_vals, int C, int dtype, const double* pos,
+                        const void* grad_vals, void* grad_mesh, double* grad_pos, hipStream_t st);
 int m2p_backward(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C,
                  int dtype, const double* pos, int64_t N, const void* grad_vals, void* grad_mesh, double* grad_pos,
                  hipStream_t st);

@@ -306,7 +306,98 @@ __global__ void __launch_bounds__(256) k_m2p_bwd(MeshOf mo, const TM* __restrict
     }
 }
 
+// grad_mesh of M2P as a gather: a quad per mesh node, nodes in the 8 x 8
+// tiles of a weights handle built from the same positions.  The node takes
+// every particle of the bins around its (up to four) cells, with one bin of
+// margin (a particle's bin and its cell can differ by rounding on a cell
+// side), locates it exactly as the forward does and adds its weight for
+// this node: the sum over the particles whose triangle holds the node, with
+// no atomics, in a fixed order (deterministic).  Lane l takes the particles
+// l, l + 4, ... of each bin row of the window; FP64 sums, one rounding.
+template <typename TG, int CC>
+__global__ void __launch_bounds__(256) k_m2p_bwd_gather(WeightsView wv, const TG* __restrict__ gv, int Crt,
+                                                        TG* __restrict__ gmesh) {
+    constexpr int NC = CC > 0 ? CC : CMAX;
+    const int C = CC > 0 ? CC : Crt;
+    const int lane = threadIdx.x & 3;
+    const int64_t tile = blockIdx.x;
+    const SetDesc& sd = wv.sets[set_search(wv.S, tile, [&](int s) { return wv.sets[s].t0; })];
+    const int64_t slot = tile * TILE_N + (threadIdx.x >> 2);
+    int i, j;
+    if (!slot_ij(sd, slot, i, j)) return;  // the four lanes of a node leave together
+    const MeshD m = sd.m;
+    const Grid g = sd.g;
+    const int64_t lnode = static_cast<int64_t>(j) * (m.nx + 1) + i;
+    const int32_t* start = wv.start + sd.b0;
+    const int bx0 = max((i - 1) * g.kb - 1, 0), bx1 = min((i + 1) * g.kb + 1, g.nbx);
+    const int by0 = max((j - 1) * g.kb - 1, 0), by1 = min((j + 1) * g.kb + 1, g.nby);
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    for (int by = by0; by < by1; ++by) {
+        const int s0 = start[by * g.nbx + bx0], s1 = start[by * g.nbx + bx1];
+        for (int s = s0 + lane; s < s1; s += 4) {
+            const Loc L = locate_cell(m, wv.pos_s[s]);
+            if (!L.ok) continue;
+            const double w = L.n0 == lnode ? L.w0 : (L.n1 == lnode ? L.w1 : (L.n2 == lnode ? L.w2 : 0.0));
+            if (w == 0.0) continue;
+            const int64_t u = wv.perm[s];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < C) acc[c] += w * static_cast<double>(gv[u * C + c]);
+        }
+    }
+    const int64_t node = sd.n0 + lnode;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c >= C) break;
+        double v = acc[c];
+        v += lane_xor<4>(v, 1);
+        v += lane_xor<4>(v, 2);
+        if (lane == (c & 3)) gmesh[node * C + c] = static_cast<TG>(v);
+    }
+}
+
+template <typename TG>
+void launch_m2p_bwd_gather(const WeightsView& wv, const void* gv, int C, void* gmesh, hipStream_t st) {
+    const int blocks = static_cast<int>(wv.n_slots / TILE_N);
+    const TG* G = static_cast<const TG*>(gv);
+    TG* M = static_cast<TG*>(gmesh);
+    switch (C) {
+        case 1: k_m2p_bwd_gather<TG, 1><<<blocks, 256, 0, st>>>(wv, G, C, M); break;
+        case 2: k_m2p_bwd_gather<TG, 2><<<blocks, 256, 0, st>>>(wv, G, C, M); break;
+        case 3: k_m2p_bwd_gather<TG, 3><<<blocks, 256, 0, st>>>(wv, G, C, M); break;
+        case 4: k_m2p_bwd_gather<TG, 4><<<blocks, 256, 0, st>>>(wv, G, C, M); break;
+        default: k_m2p_bwd_gather<TG, 0><<<blocks, 256, 0, st>>>(wv, G, C, M); break;
+    }
+}
+
 }  // namespace
+
+int m2p_backward_binned(const WeightsView& wv, const void* mesh_vals, int C, int dtype, const double* pos,
+                        const void* grad_vals, void* grad_mesh, double* grad_pos, hipStream_t st) {
+    PhaseTimer _timer(PH_M2P_BWD, st);
+    if (grad_mesh) {
+        if (dtype == P2M_F64) launch_m2p_bwd_gather<double>(wv, grad_vals, C, grad_mesh, st);
+        else launch_m2p_bwd_gather<float>(wv, grad_vals, C, grad_mesh, st);
+        P2M_HIP(hipGetLastError());
+    }
+    if (grad_pos) {
+        // the position gradient per particle (its own entry, no atomics)
+        const int blocks = static_cast<int>((wv.N + 255) / 256);
+        const MeshOf m{MeshD{}, wv.sets, wv.S};
+        const double2* P = reinterpret_cast<const double2*>(pos);
+        double2* GP = reinterpret_cast<double2*>(grad_pos);
+        if (dtype == P2M_F64)
+            k_m2p_bwd<double><<<blocks, 256, 0, st>>>(m, static_cast<const double*>(mesh_vals), C, P, wv.N,
+                                                      static_cast<const double*>(grad_vals), nullptr, GP);
+        else
+            k_m2p_bwd<float><<<blocks, 256, 0, st>>>(m, static_cast<const float*>(mesh_vals), C, P, wv.N,
+                                                     static_cast<const float*>(grad_vals), nullptr, GP);
+        P2M_HIP(hipGetLastError());
+    }
+    return P2M_OK;
+}
 
 int m2p(const MeshD& mesh, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C, int dtype,
         const double* pos, int64_t N, void* vals, hipStream_t st) {

@@ -21,6 +21,7 @@ __all__ = [
     "p2m_project",
     "m2p_interpolate",
     "m2p_interpolate_backward",
+    "m2p_interpolate_backward_binned",
     "p2m_project_backward",
     "p2m_build_weights_backward",
     "p2m_set_option",
@@ -320,6 +321,32 @@ def m2p_interpolate_backward(mesh, mesh_vals: Optional[torch.Tensor], pos: torch
     with torch.cuda.device(pos.device):
         check(load().m2p_interpolate_backward(ctypes.byref(cm), _ptr(mesh_vals), C, code, _ptr(pos), pos.shape[0],
                                               _ptr(grad_vals), _ptr(gm), _ptr(grad_pos), _stream(pos)))
+    return gm, grad_pos
+
+
+def m2p_interpolate_backward_binned(w: Weights, mesh_vals: Optional[torch.Tensor], pos: torch.Tensor,
+                                    grad_vals: torch.Tensor, want_mesh: bool = True,
+                                    grad_pos: Optional[torch.Tensor] = None, grad_mesh: Optional[torch.Tensor] = None):
+    """Adjoint of m2p_interpolate at the particles ``w`` was built from
+    (``pos``), grad_mesh gathered per node through w's binning (no atomics):
+    (grad_mesh or None, grad_pos or None); grad_pos, when given, is
+    accumulated into."""
+    _need(pos, "pos", torch.float64, (w.N, 2))
+    _need(grad_vals, "grad_vals")
+    C = grad_vals.shape[1]
+    code = P2M_F64 if grad_vals.dtype == torch.float64 else P2M_F32
+    mdt = _mesh_dtype(code)
+    gm = grad_mesh
+    if want_mesh and gm is None:
+        gm = torch.empty((w.n_nodes, C), dtype=mdt, device=pos.device)
+    if gm is not None:
+        _need(gm, "grad_mesh", mdt, (w.n_nodes, C))
+    if grad_pos is not None:
+        _need(grad_pos, "grad_pos", torch.float64, tuple(pos.shape))
+        _need(mesh_vals, "mesh_vals", mdt, (w.n_nodes, C))
+    with torch.cuda.device(pos.device):
+        check(load().m2p_interpolate_backward_binned(w.handle, _ptr(mesh_vals), C, code, _ptr(pos), _ptr(grad_vals),
+                                                     _ptr(gm), _ptr(grad_pos), _stream(pos)))
     return gm, grad_pos
 
 
