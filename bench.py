@@ -291,6 +291,15 @@ def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, grap
                                      wl.tg_v(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03),
                                      wl.tg_p(nodes[:, 0] - 0.05, nodes[:, 1] + 0.03)], 1)).to(dev, torch.float32)
     w5 = ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32)
+    t5 = None
+    if not a.no_tune and not a.set:
+        # the advected cloud is sheared: its own build options
+        key5 = tune.workload_key(torch.cuda.get_device_name(dev), N, nn, c.h / mesh.H, P2M_WEIGHTS_F32) + "|advected"
+        t5 = tune.autotune(lambda: ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32, weights=w5,
+                                                         check_diag=False),
+                           lambda hd: ops.p2m_project(hd, vb), key5)
+        log(f"large: c5 tuning {t5.options} {t5.median_ms:.4f} ms (default {t5.default_ms:.4f})")
+        ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32, weights=w5)
     d5 = w5.diag()
     o5 = torch.empty((nn, C5), dtype=torch.float32, device=dev)
     back5 = torch.empty((N, C5), dtype=torch.bfloat16, device=dev)
@@ -324,8 +333,12 @@ def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, grap
         "ms_per_step": round(ms5, 5), "Mparticles_per_s": round(N / (ms5 * 1e-3) / 1e6, 3),
         "forward_backward_hbm": hbm_entry(Bb5, ms5), "kernels_ms": {k: round(v, 5) for k, v in ph5.items()},
         "diag": {k: d5[k] for k in ("slow_nodes", "failed_nodes", "rank_deficient", "svd_systems",
-                                    "max_gram_cond")}}
+                                    "max_gram_cond")},
+        "tuning": None if t5 is None else {"options": t5.options, "build_ms_tuned": round(t5.median_ms, 5),
+                                           "build_ms_default": round(t5.default_ms, 5), "cached": t5.cached}}
     log(f"large: c5 forward {msf5:.4f} ms, forward+backward {ms5:.4f} ms")
+    if t5 is not None and tuning is not None:
+        tune.apply_options(tuning["options"])
     del w5, pos, vb, o5, back5, gp5
     torch.cuda.synchronize()
     return out

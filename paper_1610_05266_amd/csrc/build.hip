@@ -593,8 +593,10 @@ struct QuadSource {
         const double R2 = Rf * Rf;
         const double crmin = 32.0 * EPS * R2;
         const double errS = 2048.0 * EPS * R2 * R2;
+        // only the winner's index and key travel through the loop and the
+        // quad reduction; its position is read back from LDS once at the end
         int bt = -1;
-        double bn = 0.0, bc = 1.0, bx = 0.0, by = 0.0;
+        double bn = 0.0, bc = 1.0;
         bool amb = false;
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
@@ -611,8 +613,6 @@ struct QuadSource {
             bt = take ? t : bt;
             bn = take ? num : bn;
             bc = take ? cr : bc;
-            bx = take ? b.x : bx;
-            by = take ? b.y : by;
             // at most two candidates' loads in flight: the registers of all
             // of them would cost the fourth wave per SIMD
             if (s & 1) __builtin_amdgcn_sched_barrier(0);
@@ -621,7 +621,6 @@ struct QuadSource {
         for (int m = 1; m < QL; m <<= 1) {
             const int ot = lane_xor<QL>(bt, m);
             const double on = lane_xor<QL>(bn, m), oc = lane_xor<QL>(bc, m);
-            const double ox = lane_xor<QL>(bx, m), oy = lane_xor<QL>(by, m);
             const double d = on * bc - bn * oc;
             const bool other = ot >= 0 && ot != bt;
             amb = amb || (other && bt >= 0 && fabs(d) <= errS);
@@ -629,8 +628,6 @@ struct QuadSource {
             bt = take ? ot : bt;
             bn = take ? on : bn;
             bc = take ? oc : bc;
-            bx = take ? ox : bx;
-            by = take ? oy : by;
         }
         int am = amb ? 1 : 0;
         am |= lane_xor<QL>(am, 1);
@@ -640,8 +637,9 @@ struct QuadSource {
         k.num = bn;
         k.cr = bc;
         k.Nm = k.Cm = 0.0;
-        k.bx = bx;
-        k.by = by;
+        const double2 pb = lpos[bt >= 0 ? bt : 0];
+        k.bx = pb.x;
+        k.by = pb.y;
         return k;
     }
 };

@@ -69,7 +69,7 @@ constexpr int64_t NA_MAX_N = int64_t(1) << 17;     // particles
 constexpr int64_t NA_MAX_TILES = 256;              // 8 x 8 node tiles (e.g. 127 x 127 cells)
 constexpr int64_t NA_MAX_SLOTS = NA_MAX_TILES * TILE_N;
 constexpr int64_t NA_MAX_BINS = int64_t(1) << 18;  // binning grid
-constexpr int64_t NA_MAX_HIST = 8192;              // (super-bin, chunk) counters
+constexpr int64_t NA_MAX_HIST = 16384;             // (super-bin, chunk) counters
 constexpr int64_t NA_MAX_TSUM = 1024;              // scan tiles of those
 constexpr size_t na_align(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 

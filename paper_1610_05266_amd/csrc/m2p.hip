@@ -83,43 +83,65 @@ struct MeshOf {
 // TM mesh value type, TO particle output type.  The three products are
 // summed in FP64 and rounded once: with FP32 storage the output is the
 // correctly rounded value of the interpolant (BF16: rounded through FP32),
-// not a sum of rounded products (a position gradient
-// taken through these values amplifies their rounding by |a| / (h |grad a|),
-// some hundreds on fine meshes, so an extra rounding of a sum would show).
-template <typename TM, typename TO, int CC>
+// not a sum of rounded products (a position gradient taken through these
+// values amplifies their rounding by |a| / (h |grad a|), some hundreds on
+// fine meshes, so an extra rounding of a sum would show).
+// PPT particles per thread, strided by the block size (coalesced): all their
+// position loads are issued before the first is used, then all their mesh
+// gathers, so that a wave keeps PPT times the loads in flight.
+template <typename TM, typename TO, int CC, int PPT>
 __global__ void __launch_bounds__(256) k_m2p(MeshOf mo, const TM* __restrict__ mv, int Crt,
                                              const double2* __restrict__ pos, int64_t N, TO* __restrict__ out) {
-    const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (mu >= N) return;
+    constexpr int NC = CC > 0 ? CC : CMAX;
     const int C = CC > 0 ? CC : Crt;
-    int64_t n0;
-    const MeshD m = mo.get(mu, n0);
-    Loc L = locate_cell(m, pos[mu]);
-    L.n0 += n0;
-    L.n1 += n0;
-    L.n2 += n0;
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * (256 * PPT) + threadIdx.x;
+    double2 p[PPT];
 #pragma unroll
-    for (int c = 0; c < (CC > 0 ? CC : CMAX); ++c) {
-        if (c >= C) break;
-        const double v = L.w0 * static_cast<double>(ldm(mv, L.n0 * C + c)) +
-                         L.w1 * static_cast<double>(ldm(mv, L.n1 * C + c)) +
-                         L.w2 * static_cast<double>(ldm(mv, L.n2 * C + c));
-        st(out, mu * C + c, static_cast<TM>(L.ok ? v : NAN));
+    for (int k = 0; k < PPT; ++k) {
+        const int64_t mu = base + k * 256;
+        p[k] = pos[mu < N ? mu : N - 1];
+    }
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int64_t mu = base + k * 256;
+        if (mu >= N) break;
+        int64_t n0;
+        const MeshD m = mo.get(mu, n0);
+        Loc L = locate_cell(m, p[k]);
+        L.n0 += n0;
+        L.n1 += n0;
+        L.n2 += n0;
+        TM g0[NC], g1[NC], g2[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c >= C) break;
+            g0[c] = ldm(mv, L.n0 * C + c);
+            g1[c] = ldm(mv, L.n1 * C + c);
+            g2[c] = ldm(mv, L.n2 * C + c);
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c >= C) break;
+            const double v = L.w0 * static_cast<double>(g0[c]) + L.w1 * static_cast<double>(g1[c]) +
+                             L.w2 * static_cast<double>(g2[c]);
+            st(out, mu * C + c, static_cast<TM>(L.ok ? v : NAN));
+        }
     }
 }
 
 template <typename TM, typename TO>
 void launch_m2p(const MeshOf& m, const void* mv, int C, const double* pos, int64_t N, void* out, hipStream_t s) {
-    const int blocks = static_cast<int>((N + 255) / 256);
+    constexpr int PPT = 4;
+    const int blocks = static_cast<int>((N + 256 * PPT - 1) / (256 * PPT));
     const TM* M = static_cast<const TM*>(mv);
     const double2* P = reinterpret_cast<const double2*>(pos);
     TO* O = static_cast<TO*>(out);
     switch (C) {
-        case 1: k_m2p<TM, TO, 1><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
-        case 2: k_m2p<TM, TO, 2><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
-        case 3: k_m2p<TM, TO, 3><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
-        case 4: k_m2p<TM, TO, 4><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
-        default: k_m2p<TM, TO, 0><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        case 1: k_m2p<TM, TO, 1, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        case 2: k_m2p<TM, TO, 2, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        case 3: k_m2p<TM, TO, 3, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        case 4: k_m2p<TM, TO, 4, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        default: k_m2p<TM, TO, 0, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
     }
 }
 
