@@ -72,8 +72,11 @@ typedef enum p2m_dtype {
                                 nodes instead of psi_mu (see p2m_build_weights) */
 #define P2M_PERIODIC    0x8  /* periodic box (see p2m_build_weights)            */
 
-/* Largest number of particles one node's weights may involve (ELL width). */
-#define P2M_MAX_SUPPORT 32
+/* Largest number of particles one node's weights may involve: the width of
+ * exported rows and of grad_w.  Rows longer than 32 (only around particles
+ * of high Delaunay degree) are kept in a small overflow store of the handle
+ * and counted in p2m_diag.long_rows. */
+#define P2M_MAX_SUPPORT 63
 /* Nearest particles used by a closure node (boundary ring / outside hull). */
 #define P2M_CLOSURE_K 12
 
@@ -85,7 +88,8 @@ typedef struct p2m_diag {
     int64_t rank_deficient;     /* moment systems of rank below 6: their
                                    weights are the minimum-norm least-squares
                                    answer (see svd_systems)                    */
-    int64_t cap_overflow;       /* nodes whose support exceeded the ELL width  */
+    int64_t cap_overflow;       /* nodes whose support exceeded P2M_MAX_SUPPORT,
+                                   or that found the overflow store full       */
     int64_t escalated_nodes;    /* nodes that needed a larger search region    */
     int64_t global_nodes;       /* nodes that needed a scan of every particle  */
     int64_t near_degenerate;    /* predicate decisions inside the error bound  */
@@ -106,6 +110,8 @@ typedef struct p2m_diag {
                                    derivative the last
                                    p2m_build_weights_backward on this handle
                                    left out (see that call)                    */
+    int64_t long_rows;          /* rows of more than 32 particles (kept in the
+                                   overflow store; solved by the SVD path)     */
 } p2m_diag;
 
 /* How each moment system M A = b (6 conditions, K support particles) is

@@ -17,7 +17,7 @@ HEADER = os.path.join(os.path.dirname(PKG_DIR), "include", "p2m.h")
 P2M_OK, P2M_EINVAL, P2M_EDOMAIN, P2M_ECAP, P2M_EGEOM, P2M_EHIP, P2M_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 P2M_F64, P2M_F32, P2M_BF16 = 0, 1, 2
 P2M_WEIGHTS_F32, P2M_STRICT, P2M_LINEAR, P2M_PERIODIC = 0x1, 0x2, 0x4, 0x8
-MAX_SUPPORT = 32
+MAX_SUPPORT = 63
 CLOSURE_K = 12
 MAX_SETS = 65536
 
@@ -48,6 +48,7 @@ class P2MDiag(ctypes.Structure):
         ("svd_systems", c_int64),
         ("max_gram_cond", c_double),
         ("bwd_rank_deficient", c_int64),
+        ("long_rows", c_int64),
     ]
 
     def as_dict(self):

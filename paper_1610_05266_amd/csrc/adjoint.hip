@@ -393,11 +393,14 @@ __global__ void __launch_bounds__(256) k_build_bwd_svd(BArgs a) {
         double wb = 0.0;
         uint32_t bits = 0;
         if (in) {
-            u = a.w.idx[lane * ns + slot];
+            // entries KMAX.. of a long row live in its overflow row
+            const bool main = lane < KMAX;
+            const int64_t at = main ? lane * ns + slot : ovf_at(a.w.n_ovf, a.w.orow[slot], lane);
+            u = main ? a.w.idx[at] : a.w.oidx[at];
             const double2 r = a.pos[u];
             p = per ? image_near(sd.m, r, q) : r;
             wb = a.gw[lane * nn + node];
-            bits = a.w.mem[lane * ns + slot];
+            bits = main ? a.w.mem[at] : a.w.omem[at];
         }
         double gx = 0.0, gy = 0.0;
         int skipped = 0;
@@ -531,9 +534,12 @@ __global__ void __launch_bounds__(256) k_export(WeightsView w, int32_t* __restri
     const uint32_t meta = w.meta[slot];
     const int n = row_len(meta);
     const int64_t nn = w.n_nodes, ns = w.n_slots;
-    for (int k = 0; k < KMAX; ++k) {
-        if (idx) idx[k * nn + node] = k < n ? w.idx[k * ns + slot] : -1;
-        if (wts) wts[k * nn + node] = k < n ? w.w64[k * ns + slot] : 0.0;
+    const int32_t r = n > KMAX ? w.orow[slot] : 0;
+    for (int k = 0; k < KROW; ++k) {
+        const bool main = k < KMAX;
+        const int64_t at = main ? k * ns + slot : ovf_at(w.n_ovf, r, k);
+        if (idx) idx[k * nn + node] = k < n ? (main ? w.idx[at] : w.oidx[at]) : -1;
+        if (wts) wts[k * nn + node] = k < n ? (main ? w.w64[at] : w.ow64[at]) : 0.0;
     }
     if (cnt) cnt[node] = n;
     if (tri) {

@@ -69,7 +69,6 @@ constexpr int QL = 4;          // lanes per node in the quad kernels
 constexpr int NS_MAX = 10;     // candidate slots per lane (fast kernel), at most
 constexpr int QWG = 256;       // quad kernels: 64 nodes per block
 constexpr int QPB = QWG / QL;
-constexpr int MS = KMAX / QL;  // support entries per lane
 constexpr int KPITCH = KMAX + 1;  // LDS row pitch of per-quad support lists
 constexpr uint32_t IDX_MASK = 0x0fffffffu;
 
@@ -684,7 +683,7 @@ struct Support {
 };
 
 
-// Support list of one node on the wave path, entry k in lane k (KMAX <= 64):
+// Support list of one node on the wave path, entry k in lane k (KROW <= 64):
 // a search is one compare and a ballot, an insertion a select, with no LDS
 // round trip.  Same entries and order as Support.
 struct WaveSupport {
@@ -701,11 +700,17 @@ struct WaveSupport {
         if (f >= 0) {
             if (lane == f) e |= bit << 28;
         } else {
-            if (n >= KMAX) return false;
+            if (n >= KROW) return false;
             if (lane == n) e = t | (bit << 28);
             ++n;
         }
         return true;
+    }
+    // Exchange the entries at positions a and b (wave-uniform).
+    __device__ void swap(int a, int b) {
+        const int ea = __builtin_amdgcn_readlane(e, a), eb = __builtin_amdgcn_readlane(e, b);
+        if (lane == a) e = eb;
+        if (lane == b) e = ea;
     }
 };
 
@@ -1083,8 +1088,13 @@ __device__ int wave_row_svd(const KArgs& a, const SetDesc& sd, int64_t slot, dou
     uint32_t e = 0;
     double2 p = make_double2(0.0, 0.0);
     int32_t uid = 0;
+    // entries KMAX.. of a long row live in its overflow row
+    const int32_t orow = n > KMAX ? a.out.orow[slot] : 0;
+    const int64_t at = lane < KMAX ? lane * nn + slot : ovf_at(a.out.n_ovf, orow, lane);
+    int32_t* const pidx = lane < KMAX ? a.out.idx : a.out.oidx;
+    uint8_t* const pmem = lane < KMAX ? a.out.mem : a.out.omem;
     if (in) {
-        e = static_cast<uint32_t>(a.out.idx[lane * nn + slot]) | (static_cast<uint32_t>(a.out.mem[lane * nn + slot]) << 28);
+        e = static_cast<uint32_t>(pidx[at]) | (static_cast<uint32_t>(pmem[at]) << 28);
         const double2 r = a.pos_s[e & IDX_MASK];
         p = PER ? image_near(sd.m, r, q) : r;
         uid = a.perm[e & IDX_MASK];
@@ -1158,10 +1168,12 @@ __device__ int wave_row_svd(const KArgs& a, const SetDesc& sd, int64_t slot, dou
         nsys = 1;
     }
     if (in) {
-        a.out.idx[lane * nn + slot] = uid;
-        a.out.w64[lane * nn + slot] = w;
-        if (a.out.w32) a.out.w32[lane * nn + slot] = static_cast<float>(w);
-        a.out.mem[lane * nn + slot] = type == NT_PENDING ? static_cast<uint8_t>(e >> 28) : 0;
+        double* const pw64 = lane < KMAX ? a.out.w64 : a.out.ow64;
+        float* const pw32 = lane < KMAX ? a.out.w32 : a.out.ow32;
+        pidx[at] = uid;
+        pw64[at] = w;
+        if (pw32) pw32[at] = static_cast<float>(w);
+        pmem[at] = type == NT_PENDING ? static_cast<uint8_t>(e >> 28) : 0;
     }
     if (lane == 0) {
         const uint32_t ft = type == NT_PENDING ? NT_INTERIOR : (type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING);
@@ -1740,12 +1752,12 @@ template <bool PER>
 __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     constexpr int WPB = SWG / WAVE;
     static_assert(WPB == 3, "one wave per ring");
-    __shared__ int32_t svis[WPB * KMAX];
+    __shared__ int32_t svis[WPB * KROW];
     __shared__ double2 slp[WPB * STAGE];
     __shared__ int32_t slt[WPB * STAGE];
     // each ring's list (entry | ring bit << 28), its status, length and
     // near-tie count, for the ring-0 wave to merge
-    __shared__ int32_t sring[WPB][KMAX];
+    __shared__ int32_t sring[WPB][KROW];
     __shared__ int sinfo[WPB][3];
     // the weights of the finished row, by the first quad of the ring-0 wave
     __shared__ double2 wsp[(WAVE / QL) * SKP];
@@ -1785,7 +1797,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         c.lane = lane;
         c.lp = slp + wv * STAGE;
         c.lt = slt + wv * STAGE;
-        static_assert(KMAX <= WAVE, "one support entry per lane");
+        static_assert(KROW <= WAVE, "one support entry per lane");
         WaveSupport S;
         S.e = 0;
         S.n = 0;
@@ -1801,7 +1813,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
                 const int hw = level < a.levels ? (sd.hw0 << level) : big;
                 c.set_region(per ? make_region_periodic(sd.g, cbx, cby, hw) : make_region(sd.g, cbx, cby, hw));
                 S.n = 0;
-                const int sk = delaunay_node(c, q, T, S, svis + wv * KMAX, a.linear ? -2 : wv);
+                const int sk = delaunay_node(c, q, T, S, svis + wv * KROW, a.linear ? -2 : wv, KROW);
                 if (lane < S.n) sring[wv][lane] = S.e;
                 if (lane == 0) {
                     sinfo[wv][0] = sk;
@@ -1847,17 +1859,53 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         }
         c.neardeg = ndeg;
         if (c.neardeg) flags |= MF_NEARDEG;
+        bool long_row = false;
         if (type == NT_INTERIOR) {
-            const int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
+            int lt[3] = {S.find(T[0]), S.find(T[1]), S.find(T[2])};
+            // The metadata word holds the triangle's positions in five bits.
+            // In the ring order T[0] follows the whole ring of T[0]; in a
+            // row longer than that a triangle vertex past the ELL width is
+            // exchanged with the first entry that is not one (the order of
+            // a long row's entries is its own: only this path builds it).
+            for (int k = 0; k < 3; ++k) {
+                if (lt[k] < KMAX) continue;
+                int t = 0;
+                while (t == lt[0] || t == lt[1] || t == lt[2]) ++t;
+                S.swap(lt[k], t);
+                lt[k] = t;
+            }
+            const int lt0 = lt[0], lt1 = lt[1], lt2 = lt[2];
             if (lt0 < 0 || lt1 < 0 || lt2 < 0) {
                 type = NT_FAILED;
             } else {
-                if (lane < S.n) {
-                    const uint32_t e = static_cast<uint32_t>(S.e);
-                    a.out.idx[lane * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
-                    a.out.mem[lane * nn + slot] = static_cast<uint8_t>(e >> 28);
+                long_row = S.n > KMAX;
+                int orow = 0;
+                if (long_row) {
+                    // entries KMAX.. go to an overflow row of the handle
+                    int r = 0;
+                    if (lane == 0) r = static_cast<int>(atomicAdd(&a.diag[D_OVF], 1ull));
+                    orow = __builtin_amdgcn_readfirstlane(r);
+                    if (orow >= a.out.n_ovf) {
+                        type = NT_FAILED;
+                        st = R_CAP;
+                        if (lane == 0) atomicAdd(&a.diag[D_CAP], 1ull);
+                    } else if (lane == 0) {
+                        a.out.orow[slot] = orow;
+                    }
                 }
-                if (lane == 0) a.out.meta[slot] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
+                if (type == NT_INTERIOR) {
+                    if (lane < S.n) {
+                        const uint32_t e = static_cast<uint32_t>(S.e);
+                        if (lane < KMAX) {
+                            a.out.idx[lane * nn + slot] = static_cast<int32_t>(e & IDX_MASK);
+                            a.out.mem[lane * nn + slot] = static_cast<uint8_t>(e >> 28);
+                        } else {
+                            a.out.oidx[ovf_at(a.out.n_ovf, orow, lane)] = static_cast<int32_t>(e & IDX_MASK);
+                            a.out.omem[ovf_at(a.out.n_ovf, orow, lane)] = static_cast<uint8_t>(e >> 28);
+                        }
+                    }
+                    if (lane == 0) a.out.meta[slot] = meta_pack(NT_PENDING, S.n, lt0, lt1, lt2, flags);
+                }
             }
         }
         if (type == NT_RING || type == NT_OUTSIDE) {
@@ -1927,6 +1975,16 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (long_row) {
+            // a row longer than the ELL width is solved by the wave solver
+            // of k_weights_rd (one entry per lane); counted here
+            if (lane == 0) {
+                a.rd[atomicAdd(&a.diag[D_RDCNT], 1ull)] = static_cast<int32_t>(slot);
+                atomicAdd(&a.diag[D_INTERIOR], 1ull);
+                atomicMax(&a.diag[D_SUPMAX], static_cast<unsigned long long>(S.n));
+            }
+            continue;
+        }
         // every quad of the wave computes the row's systems; they share
         // its final pass
         count_wave(a, weights_node<PER, WAVE / QL>(a, sd, i, j, true, slot, lane & (QL - 1), lane / QL, wsp, wse, wsu,
@@ -2118,6 +2176,8 @@ __global__ void __launch_bounds__(QWG) k_seam_copy(KArgs a) {
     if (lane == 0) {
         const uint32_t meta = a.out.meta[src];
         a.out.meta[dst] = meta;
+        // a long row's overflow entries are shared, not copied
+        if (row_len(meta) > KMAX) a.out.orow[dst] = a.out.orow[src];
         if (meta_type(meta) == NT_INTERIOR) atomicAdd(&a.diag[D_INTERIOR], 1ull);
         if (meta_flags(meta) & MF_RANKDEF) atomicAdd(&a.diag[D_RANKDEF], 1ull);
         if (meta_type(meta) == NT_FAILED) atomicAdd(&a.diag[D_FAILED], 1ull);

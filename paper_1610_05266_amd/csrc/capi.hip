@@ -1,5 +1,6 @@
 // C ABI of libp2m: argument validation, handle and workspace management,
 // diagnostics and error reporting.  All device work is in the other files.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -71,12 +72,13 @@ constexpr int64_t NA_MAX_SLOTS = NA_MAX_TILES * TILE_N;
 constexpr int64_t NA_MAX_BINS = int64_t(1) << 18;  // binning grid
 constexpr int64_t NA_MAX_HIST = 16384;             // (super-bin, chunk) counters
 constexpr int64_t NA_MAX_TSUM = 1024;              // scan tiles of those
+constexpr int64_t NA_OVF = 256;                    // rows longer than the ELL width
 constexpr size_t na_align(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
 
 // Byte offsets of the buffers in the array (each 256-byte aligned).
 struct NaLayout {
     size_t key, rank, perm, pos_s, part_pos, part_key, part_uid, start, hist, tsum;
-    size_t meta, slow, rd, tdiag, idx, w64, w32, mem, diag, sets, total;
+    size_t meta, slow, rd, tdiag, idx, w64, w32, mem, orow, oidx, ow64, ow32, omem, diag, sets, total;
 };
 constexpr NaLayout na_layout() {
     NaLayout L{};
@@ -104,6 +106,11 @@ constexpr NaLayout na_layout() {
     L.w64 = take(8 * KMAX * NA_MAX_SLOTS);
     L.w32 = take(4 * KMAX * NA_MAX_SLOTS);
     L.mem = take(1 * KMAX * NA_MAX_SLOTS);
+    L.orow = take(4 * NA_MAX_SLOTS);
+    L.oidx = take(4 * (KROW - KMAX) * NA_OVF);
+    L.ow64 = take(8 * (KROW - KMAX) * NA_OVF);
+    L.ow32 = take(4 * (KROW - KMAX) * NA_OVF);
+    L.omem = take(1 * (KROW - KMAX) * NA_OVF);
     L.diag = take(8 * D_COUNT);
     L.sets = take(sizeof(SetDesc));
     L.total = o;
@@ -140,6 +147,14 @@ struct p2m_weights {
     double* w64 = nullptr;
     float* w32 = nullptr;
     uint8_t* mem = nullptr;
+    // rows longer than the ELL width: overflow row per slot, and the
+    // overflow rows' entries KMAX.. ([KROW - KMAX][capOvf] each)
+    int32_t* orow = nullptr;
+    int32_t* oidx = nullptr;
+    double* ow64 = nullptr;
+    float* ow32 = nullptr;
+    uint8_t* omem = nullptr;
+    int64_t capOvf = 0, capOvf32 = 0;
     unsigned long long* diag = nullptr;
 };
 
@@ -184,7 +199,8 @@ int grow(T** p, int64_t count, int64_t have) {
 void release(p2m_weights* w) {
     void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.hist, w->bins.start, w->bins.tsum, w->bins.pos_s,
                     w->bins.perm, w->bins.part_pos, w->bins.part_key, w->bins.part_uid, w->meta, w->idx, w->slow,
-                    w->rd, w->tdiag, w->w64, w->w32, w->mem, w->diag, w->dsets};
+                    w->rd, w->tdiag, w->w64, w->w32, w->mem, w->diag, w->dsets, w->orow, w->oidx, w->ow64,
+                    w->ow32, w->omem};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
@@ -249,6 +265,12 @@ WeightsView view(const p2m_weights* w) {
     v.w64 = w->w64;
     v.w32 = (w->flags & P2M_WEIGHTS_F32) ? w->w32 : nullptr;
     v.mem = w->mem;
+    v.orow = w->orow;
+    v.oidx = w->oidx;
+    v.ow64 = w->ow64;
+    v.ow32 = (w->flags & P2M_WEIGHTS_F32) ? w->ow32 : nullptr;
+    v.omem = w->omem;
+    v.n_ovf = w->capOvf;
     v.rd = w->rd;
     v.diag = w->diag;
     v.pos_s = reinterpret_cast<const double2*>(w->bins.pos_s);
@@ -368,7 +390,8 @@ int launch_build(p2m_weights* w, const SetTotals& tot, const double* pos, int fl
     int rc = bin_particles(w->bins, pos, tot.N, w->dsets, w->S, tot.nbins, w->diag, st);
     if (rc) return rc;
     const bool want32 = (flags & P2M_WEIGHTS_F32) != 0;
-    BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem};
+    BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem,
+                 w->orow, w->oidx, w->ow64, want32 ? w->ow32 : nullptr, w->omem, w->capOvf};
     return build_weights(w->bins, w->dsets, w->S, tot.n_tiles, tot.n_nodes, out, g_tune.levels, fast_slots(),
                          w->slow, w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0,
                          (flags & P2M_PERIODIC) != 0, g_tune.svd_cond);
@@ -435,6 +458,18 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     if (!rc) rc = grow(&w->w64, n_slots * KMAX, w->capSlots * KMAX);
     if (!rc) rc = grow(&w->mem, n_slots * KMAX, w->capSlots * KMAX);
     if (!rc && want32) rc = grow(&w->w32, n_slots * KMAX, w->capW32 ? w->capSlots * KMAX : 0);
+    // overflow rows: a small store for the rare rows longer than KMAX
+    // (the row stride of every overflow array is capOvf, so they all keep
+    // at least that many rows)
+    const int64_t novf = std::max({w->capOvf, int64_t{64}, n_nodes / 64});
+    const int64_t ovw = KROW - KMAX;
+    if (!rc) rc = grow(&w->orow, n_slots, w->capSlots);
+    if (!rc) rc = grow(&w->oidx, ovw * novf, ovw * w->capOvf);
+    if (!rc) rc = grow(&w->ow64, ovw * novf, ovw * w->capOvf);
+    if (!rc) rc = grow(&w->omem, ovw * novf, ovw * w->capOvf);
+    if (!rc && want32) rc = grow(&w->ow32, ovw * novf, ovw * w->capOvf32);
+    if (!rc) w->capOvf = novf;
+    if (!rc && want32) w->capOvf32 = novf;
     if (!rc && !w->diag) rc = grow(&w->diag, D_COUNT, 0);
     if (!rc) rc = grow(&w->dsets, S, w->capSets);
     if (rc) {
@@ -705,6 +740,7 @@ int p2m_weights_diag(const p2m_weights* w, p2m_diag* d, void* stream) {
         d->max_gram_cond = g;
     }
     d->bwd_rank_deficient = static_cast<int64_t>(h[D_BWDSKIP]);
+    d->long_rows = static_cast<int64_t>(h[D_OVF]);
     int status = P2M_OK;
     if (d->bad_particles) {
         status = P2M_EDOMAIN;
@@ -714,7 +750,8 @@ int p2m_weights_diag(const p2m_weights* w, p2m_diag* d, void* stream) {
         set_error("%lld pair(s) of coincident particles", static_cast<long long>(d->duplicate_pairs));
     } else if (d->cap_overflow) {
         status = P2M_ECAP;
-        set_error("%lld node(s) exceeded the support cap %d", static_cast<long long>(d->cap_overflow), KMAX);
+        set_error("%lld node(s) exceeded the support cap %d or found the overflow store full",
+                  static_cast<long long>(d->cap_overflow), KROW);
     } else if ((w->flags & P2M_STRICT) && d->rank_deficient) {
         status = P2M_EGEOM;
         set_error("%lld rank-deficient moment system(s)", static_cast<long long>(d->rank_deficient));
@@ -931,7 +968,7 @@ int p2m_backward_fused(const p2m_mesh* mesh, double h, const double* pos, int64_
     rc = p2m_build_weights(mesh, h, pos, N, dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32, &fw.w, stream);
     double* gw = nullptr;
     if (!rc && grad_pos) {
-        const int64_t need = fw.w->n_nodes * KMAX;
+        const int64_t need = fw.w->n_nodes * KROW;
         rc = grow(&fw.grad_w, need, fw.cap_gw);
         if (!rc) {
             fw.cap_gw = std::max(fw.cap_gw, need);
@@ -1006,6 +1043,12 @@ int p2m_project_fused_noalloc(const p2m_mesh* mesh, double h, const double* pos,
         w->w64 = reinterpret_cast<double*>(b + NA.w64);
         w->w32 = reinterpret_cast<float*>(b + NA.w32);
         w->mem = b + NA.mem;
+        w->orow = reinterpret_cast<int32_t*>(b + NA.orow);
+        w->oidx = reinterpret_cast<int32_t*>(b + NA.oidx);
+        w->ow64 = reinterpret_cast<double*>(b + NA.ow64);
+        w->ow32 = reinterpret_cast<float*>(b + NA.ow32);
+        w->omem = b + NA.omem;
+        w->capOvf = w->capOvf32 = NA_OVF;
         w->diag = reinterpret_cast<unsigned long long*>(b + NA.diag);
         w->dsets = reinterpret_cast<SetDesc*>(b + NA.sets);
         nw.base[dev] = b;

@@ -42,10 +42,17 @@ enum DiagIdx : int {
     D_GRAMCOND, // largest condition number of a full-rank system's Gram
                 // matrix (bits of a non-negative double: ordered as integers)
     D_BWDSKIP,  // rank-deficient systems the last position adjoint left out
+    D_OVF,      // rows longer than KMAX (overflow rows taken)
     D_COUNT
 };
 
-constexpr int KMAX = P2M_MAX_SUPPORT;  // ELL width
+// A row holds up to KROW support entries: the first KMAX in the ELL arrays
+// of its node slot, the rest (rows found by the exact path around vertices of
+// high degree, rare) in an overflow row of the same layout, whose index is
+// kept per slot.
+constexpr int KMAX = 32;               // ELL entries stored per node slot
+constexpr int KROW = P2M_MAX_SUPPORT;  // longest row (count field: 6 bits)
+static_assert(KROW <= 63 && KROW > KMAX, "row count fits the metadata word");
 constexpr int KNN = P2M_CLOSURE_K;
 
 // Per-node metadata word of the ELL weights.
@@ -64,10 +71,10 @@ __host__ __device__ inline uint32_t meta_pack(uint32_t type, uint32_t cnt, uint3
 }
 __host__ __device__ inline uint32_t meta_type(uint32_t m) { return m & 7u; }
 __host__ __device__ inline uint32_t meta_cnt(uint32_t m) { return (m >> 3) & 63u; }
-// Row length for readers of finished rows: never beyond the ELL width.
+// Row length for readers of finished rows: never beyond KROW.
 __host__ __device__ inline int row_len(uint32_t m) {
     const int n = static_cast<int>((m >> 3) & 63u);
-    return n < KMAX ? n : KMAX;
+    return n < KROW ? n : KROW;
 }
 __host__ __device__ inline uint32_t meta_t(uint32_t m, int k) { return (m >> (9 + 5 * k)) & 31u; }
 constexpr uint32_t MF_NEARDEG = 1u, MF_RANKDEF = 2u, MF_ESCALATED = 4u, MF_GLOBAL = 8u;
@@ -188,12 +195,23 @@ struct WeightsView {
     const double* w64;      // [KMAX][n_slots]
     const float* w32;       // [KMAX][n_slots] or null
     const uint8_t* mem;     // [KMAX][n_slots]
+    const int32_t* orow;    // [n_slots] overflow row of a slot (rows longer than KMAX only)
+    const int32_t* oidx;    // [KROW - KMAX][n_ovf] entries KMAX.. of overflow rows
+    const double* ow64;
+    const float* ow32;
+    const uint8_t* omem;
+    int64_t n_ovf;          // overflow rows (capacity)
     const int32_t* rd;      // row slots solved by the rank-revealing solver
     unsigned long long* diag;  // the build's diagnostics (count of rd: D_RDCNT)
     const double2* pos_s;   // [N] positions in bin order (the binning)
     const int32_t* perm;    // [N] bin order -> user id
     const int32_t* start;   // first bin-order slot of every bin (bins of set s from sets[s].b0)
 };
+
+// Index of entry k (>= KMAX) of an overflow row r in the overflow arrays.
+__host__ __device__ inline int64_t ovf_at(int64_t n_ovf, int32_t r, int k) {
+    return static_cast<int64_t>(k - KMAX) * n_ovf + r;
+}
 
 // Exact-rounding helpers: products/sums that must not be contracted into
 // FMAs (node coordinates are defined as x0 + i*H with two roundings).

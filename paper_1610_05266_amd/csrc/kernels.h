@@ -56,6 +56,12 @@ struct BuildOut {
     double* w64;     // [KMAX][n_nodes]
     float* w32;      // [KMAX][n_nodes] or null
     uint8_t* mem;    // [KMAX][n_nodes]
+    int32_t* orow;   // [n_slots] overflow row of a long row
+    int32_t* oidx;   // [KROW - KMAX][n_ovf] entries KMAX.. of long rows
+    double* ow64;
+    float* ow32;     // or null
+    uint8_t* omem;
+    int64_t n_ovf;   // overflow rows available
 };
 // All sets of a batch in one pass: fast quad path, then the weights of its
 // rows on the caller's stream while the slow wave path (and the weights of

@@ -37,7 +37,7 @@ __device__ __forceinline__ bool tile_node(const WeightsView& wv, int64_t& slot, 
 // are combined by a quad reduction (fixed order, so results are bitwise
 // reproducible), and lane c % 4 stores channel c.
 template <typename TV, typename TW, typename TO, int CC>
-__global__ void __launch_bounds__(256) k_project(WeightsView wv, const TW* __restrict__ w,
+__global__ void __launch_bounds__(256) k_project(WeightsView wv, const TW* __restrict__ w, const TW* __restrict__ ow,
                                                  const TV* __restrict__ vals, int Crt, TO* __restrict__ out) {
     constexpr int NC = CC > 0 ? CC : CMAX;
     const int lane = threadIdx.x & 3;
@@ -49,12 +49,25 @@ __global__ void __launch_bounds__(256) k_project(WeightsView wv, const TW* __res
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = TW(0);
     const int cnt = row_len(wv.meta[slot]);
-    for (int k = lane; k < cnt; k += 4) {
+    const int ce = cnt < KMAX ? cnt : KMAX;
+    for (int k = lane; k < ce; k += 4) {
         const int64_t j = wv.idx[k * ns + slot];
         const TW wk = w[k * ns + slot];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (c < C) acc[c] += wk * static_cast<TW>(ld(vals, j * C + c));
+    }
+    if (cnt > KMAX) {
+        // a long row's entries KMAX.. (overflow row)
+        const int32_t r = wv.orow[slot];
+        for (int k = KMAX + lane; k < cnt; k += 4) {
+            const int64_t o = ovf_at(wv.n_ovf, r, k);
+            const int64_t j = wv.oidx[o];
+            const TW wk = ow[o];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < C) acc[c] += wk * static_cast<TW>(ld(vals, j * C + c));
+        }
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
@@ -67,24 +80,25 @@ __global__ void __launch_bounds__(256) k_project(WeightsView wv, const TW* __res
 }
 
 template <typename TV, typename TW, typename TO>
-void launch_project(const WeightsView& wv, const TW* w, const void* vals, int C, void* out, hipStream_t st) {
+void launch_project(const WeightsView& wv, const TW* w, const TW* ow, const void* vals, int C, void* out,
+                    hipStream_t st) {
     const int blocks = static_cast<int>(wv.n_slots / TILE_N);  // one node tile (64 quads) per block
     const TV* v = static_cast<const TV*>(vals);
     TO* o = static_cast<TO*>(out);
     switch (C) {
-        case 1: k_project<TV, TW, TO, 1><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
-        case 2: k_project<TV, TW, TO, 2><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
-        case 3: k_project<TV, TW, TO, 3><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
-        case 4: k_project<TV, TW, TO, 4><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
-        default: k_project<TV, TW, TO, 0><<<blocks, 256, 0, st>>>(wv, w, v, C, o); break;
+        case 1: k_project<TV, TW, TO, 1><<<blocks, 256, 0, st>>>(wv, w, ow, v, C, o); break;
+        case 2: k_project<TV, TW, TO, 2><<<blocks, 256, 0, st>>>(wv, w, ow, v, C, o); break;
+        case 3: k_project<TV, TW, TO, 3><<<blocks, 256, 0, st>>>(wv, w, ow, v, C, o); break;
+        case 4: k_project<TV, TW, TO, 4><<<blocks, 256, 0, st>>>(wv, w, ow, v, C, o); break;
+        default: k_project<TV, TW, TO, 0><<<blocks, 256, 0, st>>>(wv, w, ow, v, C, o); break;
     }
 }
 
 // grad_vals[j][c] += w * grad_mesh[i][c] (atomics) ; grad_w[k][i] = sum_c grad_mesh[i][c] vals[j][c]
-// (grad_w in mesh-node order [KMAX][n_nodes]).  One thread per row slot.
+// (grad_w in mesh-node order [KROW][n_nodes]).  One thread per row slot.
 template <typename TV, typename TW, typename TG>
 __global__ void __launch_bounds__(256) k_project_bwd(WeightsView wv, const TW* __restrict__ w,
-                                                     const TG* __restrict__ gmesh, int C,
+                                                     const TW* __restrict__ ow, const TG* __restrict__ gmesh, int C,
                                                      const TV* __restrict__ vals, TG* __restrict__ gvals,
                                                      double* __restrict__ gw) {
     const int64_t slot = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -97,10 +111,13 @@ __global__ void __launch_bounds__(256) k_project_bwd(WeightsView wv, const TW* _
     const int cnt = row_len(wv.meta[slot]);
     TG g[CMAX];
     for (int c = 0; c < C; ++c) g[c] = gmesh[node * C + c];
+    const int32_t r = cnt > KMAX ? wv.orow[slot] : 0;
     for (int k = 0; k < cnt; ++k) {
-        const int64_t p = wv.idx[k * ns + slot];
+        const bool main = k < KMAX;
+        const int64_t at = main ? k * ns + slot : ovf_at(wv.n_ovf, r, k);
+        const int64_t p = main ? wv.idx[at] : wv.oidx[at];
         if (gvals) {
-            const TG wk = static_cast<TG>(w[k * ns + slot]);
+            const TG wk = static_cast<TG>(main ? w[at] : ow[at]);
             for (int c = 0; c < C; ++c) atomicAdd(&gvals[p * C + c], wk * g[c]);
         }
         if (gw) {
@@ -110,7 +127,7 @@ __global__ void __launch_bounds__(256) k_project_bwd(WeightsView wv, const TW* _
         }
     }
     if (gw)
-        for (int k = cnt; k < KMAX; ++k) gw[k * nn + node] = 0.0;
+        for (int k = cnt; k < KROW; ++k) gw[k * nn + node] = 0.0;
 }
 
 }  // namespace
@@ -118,16 +135,16 @@ __global__ void __launch_bounds__(256) k_project_bwd(WeightsView wv, const TW* _
 int project(const WeightsView& wv, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st) {
     PhaseTimer _timer(PH_PROJECT, st);
     if (dtype == P2M_F64) {
-        launch_project<double, double, double>(wv, wv.w64, vals, C, mesh_vals, st);
+        launch_project<double, double, double>(wv, wv.w64, wv.ow64, vals, C, mesh_vals, st);
     } else {
         if (!wv.w32) {
             set_error("p2m_project: FP32/BF16 values need a handle built with P2M_WEIGHTS_F32");
             return P2M_EINVAL;
         }
         if (dtype == P2M_F32)
-            launch_project<float, float, float>(wv, wv.w32, vals, C, mesh_vals, st);
+            launch_project<float, float, float>(wv, wv.w32, wv.ow32, vals, C, mesh_vals, st);
         else
-            launch_project<uint16_t, float, float>(wv, wv.w32, vals, C, mesh_vals, st);
+            launch_project<uint16_t, float, float>(wv, wv.w32, wv.ow32, vals, C, mesh_vals, st);
     }
     P2M_HIP(hipGetLastError());
     return P2M_OK;
@@ -143,7 +160,7 @@ int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dt
             if (rc) return rc;
         }
         k_project_bwd<double, double, double><<<blocks, 256, 0, st>>>(
-            wv, wv.w64, static_cast<const double*>(grad_mesh), C,
+            wv, wv.w64, wv.ow64, static_cast<const double*>(grad_mesh), C,
             static_cast<const double*>(vals), static_cast<double*>(grad_vals), grad_w);
     } else {
         if (!wv.w32) {
@@ -156,11 +173,11 @@ int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dt
         }
         if (dtype == P2M_F32)
             k_project_bwd<float, float, float><<<blocks, 256, 0, st>>>(
-                wv, wv.w32, static_cast<const float*>(grad_mesh), C,
+                wv, wv.w32, wv.ow32, static_cast<const float*>(grad_mesh), C,
                 static_cast<const float*>(vals), static_cast<float*>(grad_vals), grad_w);
         else
             k_project_bwd<uint16_t, float, float><<<blocks, 256, 0, st>>>(
-                wv, wv.w32, static_cast<const float*>(grad_mesh), C,
+                wv, wv.w32, wv.ow32, static_cast<const float*>(grad_mesh), C,
                 static_cast<const uint16_t*>(vals), static_cast<float*>(grad_vals), grad_w);
     }
     P2M_HIP(hipGetLastError());

@@ -1,7 +1,8 @@
 """The no-allocation form p2m_project_fused_noalloc against the allocating
 p2m_project_fused (same build kernels, weights in the library's static
-workspace): two calls in a row, the second on a smaller input, FP64 and
-mixed; and the host-side rejections beyond the workspace's limits."""
+workspace): calls in a row, each on a smaller input than the one before
+(the middle one with rows longer than the ELL width), FP64 and mixed; and
+the host-side rejections beyond the workspace's limits."""
 import numpy as np
 import pytest
 import torch
@@ -21,7 +22,9 @@ def _g(a, dt=torch.float64):
 
 @pytest.mark.parametrize("dt,tol", [(torch.float64, 1e-12), (torch.float32, 1e-5)])
 def test_noalloc_equals_fused_on_two_calls(dt, tol):
-    for c in (wl.small_cloud(32, 2, 0.25, seed=61), wl.small_cloud(12, 2, 0.3, seed=62)):
+    # the middle call holds rows longer than the ELL width (overflow store)
+    for c in (wl.small_cloud(32, 2, 0.25, seed=61), wl.hub_cloud(16, ((0.37, 0.41, 40), (0.66, 0.63, 50)), seed=21),
+              wl.small_cloud(12, 2, 0.3, seed=62)):
         print(f"[gpu] noalloc {c.name} N={c.N} nodes={c.mesh.n_nodes} {dt}", flush=True)
         pos = _g(c.pos)
         vals = _g(c.vals, dt)

@@ -36,6 +36,7 @@ __all__ = [
     "small_cloud",
     "cluster_void_cloud",
     "conic_cloud",
+    "hub_cloud",
     "CONFIGS",
 ]
 
@@ -298,6 +299,32 @@ def conic_cloud(n: int, n_pts: int, delta: float, seed: int,
     mesh = MeshSpec(n, n, 1.0 / n)
     h = 2.2 / n_pts
     return Cloud(f"conic{n}", mesh, h, pos, _fields(pos, channels), channels)
+
+
+def hub_cloud(n: int, hubs: Tuple[Tuple[float, float, int], ...], seed: int,
+              channels: Tuple[str, ...] = ("u", "v", "q")) -> Cloud:
+    """Support-size stress input (not a benchmark): a jittered lattice
+    (h = H/2) with "hub" particles of high Delaunay degree.  Each hub
+    (cx, cy, degree) is one particle at (cx, cy) ringed by `degree`
+    particles on a circle of radius 1.5 H (equal angles with a 2 % angular
+    jitter and a 1e-3 relative radial jitter); the lattice is cleared within
+    1.7 H of the hub.  Every mesh node inside the circle lies in a triangle
+    of the hub's fan, so its support holds the hub's whole ring."""
+    rng = np.random.default_rng(seed)
+    pos, _ = jittered_lattice(2 * n, 0.25, rng, permute=False)
+    H = 1.0 / n
+    parts = []
+    keep = np.ones(pos.shape[0], bool)
+    for cx, cy, deg in hubs:
+        keep &= (pos[:, 0] - cx) ** 2 + (pos[:, 1] - cy) ** 2 > (1.7 * H) ** 2
+        t = (np.arange(deg) + 0.02 * rng.uniform(-1.0, 1.0, size=deg)) * (2.0 * math.pi / deg)
+        r = 1.5 * H * (1.0 + 1e-3 * rng.uniform(-1.0, 1.0, size=deg))
+        parts.append(np.array([[cx, cy]]))
+        parts.append(np.stack([cx + r * np.cos(t), cy + r * np.sin(t)], 1))
+    pos = np.concatenate([pos[keep]] + parts)
+    pos = np.ascontiguousarray(pos[rng.permutation(pos.shape[0])])
+    mesh = MeshSpec(n, n, H)
+    return Cloud(f"hub{n}", mesh, H / 2, pos, _fields(pos, channels), channels)
 
 
 def periodic_void_cloud(n: int, N: int, seed: int,
