@@ -369,6 +369,7 @@ constexpr int STAGE = 512;
 
 template <bool PER>
 struct WaveSource {
+    // (every member inlined: a call would put the source in scratch memory)
     static constexpr bool per = PER;
     const double2* __restrict__ pos;
     const int32_t* __restrict__ perm;
@@ -392,19 +393,19 @@ struct WaveSource {
 
     // every particle was a candidate (a periodic box has no hull: its widest
     // window answers only what it certifies)
-    __device__ bool global() const { return R.global && !per; }
+    __device__ __forceinline__ bool global() const { return R.global && !per; }
     // near-tie count when the rings phase begins
-    __device__ void mark_rings() { ring_mark = neardeg; }
-    __device__ double2 at(int t) const {
+    __device__ __forceinline__ void mark_rings() { ring_mark = neardeg; }
+    __device__ __forceinline__ double2 at(int t) const {
         const double2 p = pos[t];
         return per ? image_near(m, p, q) : p;
     }
-    __device__ double2 P(int t) const { return at(t); }
-    __device__ bool certify(double cx, double cy, double r) const {
+    __device__ __forceinline__ double2 P(int t) const { return at(t); }
+    __device__ __forceinline__ bool certify(double cx, double cy, double r) const {
         r *= 1.0 + 1e-9;
         return cx - r >= R.xlo && cx + r <= R.xhi && cy - r >= R.ylo && cy + r <= R.yhi;
     }
-    __device__ void set_region(const Region& reg) {
+    __device__ __forceinline__ void set_region(const Region& reg) {
         R = reg;
         // run lengths, one lane per run (a bin row, or a part of one that
         // wraps), 64 runs at a time
@@ -467,7 +468,7 @@ struct WaveSource {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     template <class F>
-    __device__ void scan(F&& f) const {
+    __device__ __forceinline__ void scan(F&& f) const {
         if (nreg >= 0) {
             if (lane < nreg) f(rt0, rp0);
             if (lane + WAVE < nreg) f(rt1, rp1);
@@ -486,7 +487,7 @@ struct WaveSource {
             flat += e - s;
         }
     }
-    __device__ int nearest(double2 c, int exclude, double& d2best, double2& pbest) {
+    __device__ __forceinline__ int nearest(double2 c, int exclude, double& d2best, double2& pbest) {
         int best = -1;
         d2best = INFINITY;
         pbest = make_double2(0.0, 0.0);
@@ -503,7 +504,7 @@ struct WaveSource {
         wave_nearest(d2best, best, pbest, perm);
         return best;
     }
-    __device__ Key wrap(int iv, double2 v, int ia, double2 a, double sgn) {
+    __device__ __forceinline__ Key wrap(int iv, double2 v, int ia, double2 a, double sgn) {
         Key best = no_key();
         auto uid = [&](int t) { return perm[t]; };
         int nd = 0;
@@ -1861,20 +1862,23 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         if (c.neardeg) flags |= MF_NEARDEG;
         bool long_row = false;
         if (type == NT_INTERIOR) {
-            int lt[3] = {S.find(T[0]), S.find(T[1]), S.find(T[2])};
+            int lt0 = S.find(T[0]), lt1 = S.find(T[1]), lt2 = S.find(T[2]);
             // The metadata word holds the triangle's positions in five bits.
             // In the ring order T[0] follows the whole ring of T[0]; in a
             // row longer than that a triangle vertex past the ELL width is
             // exchanged with the first entry that is not one (the order of
             // a long row's entries is its own: only this path builds it).
-            for (int k = 0; k < 3; ++k) {
-                if (lt[k] < KMAX) continue;
-                int t = 0;
-                while (t == lt[0] || t == lt[1] || t == lt[2]) ++t;
-                S.swap(lt[k], t);
-                lt[k] = t;
-            }
-            const int lt0 = lt[0], lt1 = lt[1], lt2 = lt[2];
+            auto front = [&](int& l) {
+                if (l < KMAX) return;
+                const int t = (lt0 != 0 && lt1 != 0 && lt2 != 0) ? 0
+                            : (lt0 != 1 && lt1 != 1 && lt2 != 1) ? 1
+                            : (lt0 != 2 && lt1 != 2 && lt2 != 2) ? 2 : 3;
+                S.swap(l, t);
+                l = t;
+            };
+            front(lt0);
+            front(lt1);
+            front(lt2);
             if (lt0 < 0 || lt1 < 0 || lt2 < 0) {
                 type = NT_FAILED;
             } else {
