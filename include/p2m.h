@@ -71,6 +71,11 @@ typedef enum p2m_dtype {
 #define P2M_LINEAR      0x4  /* linear FE particle functions phi_mu at interior
                                 nodes instead of psi_mu (see p2m_build_weights) */
 #define P2M_PERIODIC    0x8  /* periodic box (see p2m_build_weights)            */
+#define P2M_DETERMINISTIC 0x10 /* also index the entries by particle, so that
+                                p2m_project_backward and
+                                p2m_build_weights_backward sum each
+                                particle's terms in a fixed order: no atomics,
+                                the same bits on every run                   */
 
 /* Largest number of particles one node's weights may involve: the width of
  * exported rows and of grad_w.  Rows longer than 32 (only around particles
@@ -321,7 +326,10 @@ int m2p_interpolate_backward_binned(const p2m_weights* w, const void* mesh_vals,
  * p2m_project_backward -- adjoint of p2m_project for fixed weights.
  *  grad_mesh  device [(nx+1)(ny+1)][C] upstream gradient (dtype; FP32 for BF16).
  *  grad_vals  device [N][C] output (dtype; FP32 for BF16), OVERWRITTEN with
- *             sum_i psi_mu(r_i) grad_mesh[i][c]; may be NULL (atomic adds).
+ *             sum_i psi_mu(r_i) grad_mesh[i][c]; may be NULL.  Summed by
+ *             atomic adds, or, for a handle built with P2M_DETERMINISTIC,
+ *             per particle over its entries in a fixed order (the same bits
+ *             on every run).
  *  vals       device [N][C] forward particle values; needed iff grad_w.
  *  grad_w     device FP64 [P2M_MAX_SUPPORT][n_nodes] output, OVERWRITTEN with
  *             d L / d psi = sum_c grad_mesh[i][c] vals[idx][c]; may be NULL.
@@ -335,7 +343,10 @@ int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int
  * d psi_k(r_i) / d r_mu for the particle positions pos (the same array the
  * handle was built from; geometry is recomputed, not stored).  The
  * combinatorial structure (triangles, rings, nearest sets) is held fixed.
- *  grad_pos  device [N][2] FP64, ACCUMULATED with atomic adds.
+ *  grad_pos  device [N][2] FP64, ACCUMULATED with atomic adds; for a handle
+ *            built with P2M_DETERMINISTIC each entry's derivative is stored
+ *            and every particle adds its own in a fixed order (the same bits
+ *            on every run for the same grad_pos on entry).
  * Errors: EINVAL also for a handle built with P2M_LINEAR.
  */
 int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const double* grad_w,

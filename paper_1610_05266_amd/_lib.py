@@ -16,7 +16,7 @@ HEADER = os.path.join(os.path.dirname(PKG_DIR), "include", "p2m.h")
 
 P2M_OK, P2M_EINVAL, P2M_EDOMAIN, P2M_ECAP, P2M_EGEOM, P2M_EHIP, P2M_ENOMEM = 0, -1, -2, -3, -4, -5, -6
 P2M_F64, P2M_F32, P2M_BF16 = 0, 1, 2
-P2M_WEIGHTS_F32, P2M_STRICT, P2M_LINEAR, P2M_PERIODIC = 0x1, 0x2, 0x4, 0x8
+P2M_WEIGHTS_F32, P2M_STRICT, P2M_LINEAR, P2M_PERIODIC, P2M_DETERMINISTIC = 0x1, 0x2, 0x4, 0x8, 0x10
 MAX_SUPPORT = 63
 CLOSURE_K = 12
 MAX_SETS = 65536

@@ -19,8 +19,8 @@ OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libp2m.so")
 ARCH = os.environ.get("P2M_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["util.hip", "binning.hip", "build.hip", "project.hip", "m2p.hip", "adjoint.hip", "advect.hip", "profile.hip",
-           "capi.hip"]
+SOURCES = ["util.hip", "binning.hip", "build.hip", "project.hip", "m2p.hip", "adjoint.hip", "transpose.hip",
+           "advect.hip", "profile.hip", "capi.hip"]
 
 
 def hipcc() -> str:

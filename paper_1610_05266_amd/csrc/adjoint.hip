@@ -57,7 +57,9 @@ struct BArgs {
 // p_k of the frame (whose centre and scale are held fixed: the solution does
 // not depend on them).  The edge ends also get the derivative through the
 // right-hand side -d d^t / 2, and the triangle's vertices the barycentric
-// part.  Every owned entry ends with one pair of atomics on grad_pos.
+// part.  Every owned entry ends with one pair of atomics on grad_pos, or,
+// for a handle with a particle-major index, one store of its derivative
+// (summed per particle afterwards).
 constexpr int QL = 4;
 constexpr int QWG = 256;
 constexpr int QPB = QWG / QL;
@@ -352,9 +354,14 @@ __global__ void __launch_bounds__(QWG) k_build_bwd(BArgs a) {
                     ax += tvx[t];
                     ay += tvy[t];
                 }
-            const int64_t u = a.w.idx[k * ns + slot];
-            atomicAdd(&a.gpos[u].x, ax);
-            atomicAdd(&a.gpos[u].y, ay);
+            if (a.w.gent) {
+                // (rows of this kernel are at most KMAX long)
+                a.w.gent[k * ns + slot] = make_double2(ax, ay);
+            } else {
+                const int64_t u = a.w.idx[k * ns + slot];
+                atomicAdd(&a.gpos[u].x, ax);
+                atomicAdd(&a.gpos[u].y, ay);
+            }
         }
         if (lane == 0 && skipped) atomicAdd(&a.w.diag[D_BWDSKIP], static_cast<unsigned long long>(skipped));
     }
@@ -517,8 +524,13 @@ __global__ void __launch_bounds__(256) k_build_bwd_svd(BArgs a) {
             }
         }
         if (in) {
-            atomicAdd(&a.gpos[u].x, gx);
-            atomicAdd(&a.gpos[u].y, gy);
+            if (a.w.gent) {
+                const int32_t orow = n > KMAX ? a.w.orow[slot] : 0;
+                a.w.gent[entry_at(ns, a.w.n_ovf, orow, slot, lane)] = make_double2(gx, gy);
+            } else {
+                atomicAdd(&a.gpos[u].x, gx);
+                atomicAdd(&a.gpos[u].y, gy);
+            }
         }
         if (lane == 0 && skipped) atomicAdd(&a.w.diag[D_BWDSKIP], static_cast<unsigned long long>(skipped));
     }
@@ -573,6 +585,8 @@ int build_backward(const WeightsView& w, const double* pos, const double* grad_w
     // the list)
     k_build_bwd_svd<<<16, 256, 0, st>>>(a);
     P2M_HIP(hipGetLastError());
+    // a particle-major index: the per-entry derivatives summed per particle
+    if (w.gent) return gather_entry_grads(w, grad_pos, st);
     return P2M_OK;
 }
 

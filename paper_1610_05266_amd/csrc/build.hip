@@ -2185,6 +2185,9 @@ __global__ void __launch_bounds__(QWG) k_seam_copy(KArgs a) {
         if (meta_type(meta) == NT_INTERIOR) atomicAdd(&a.diag[D_INTERIOR], 1ull);
         if (meta_flags(meta) & MF_RANKDEF) atomicAdd(&a.diag[D_RANKDEF], 1ull);
         if (meta_type(meta) == NT_FAILED) atomicAdd(&a.diag[D_FAILED], 1ull);
+        // a copy of a row of the rank-revealing solver joins its list, which
+        // the position adjoint walks (the forward is done with it)
+        if (meta_flags(meta) & MF_SVD) a.rd[atomicAdd(&a.diag[D_RDCNT], 1ull)] = static_cast<int32_t>(dst);
     }
 }
 

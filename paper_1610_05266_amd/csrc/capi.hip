@@ -155,6 +155,16 @@ struct p2m_weights {
     float* ow32 = nullptr;
     uint8_t* omem = nullptr;
     int64_t capOvf = 0, capOvf32 = 0;
+    // particle-major index of the entries (P2M_DETERMINISTIC): counts or
+    // cursors [N], range starts [N + 1], entry indices and their nodes
+    // [n_ent], scan tile totals, and the per-entry position adjoint [n_ent]
+    int32_t* tcnt = nullptr;
+    int32_t* tptr = nullptr;
+    int32_t* tent = nullptr;
+    int32_t* tnode = nullptr;
+    int32_t* ttile = nullptr;
+    double2* gent = nullptr;
+    int64_t capTN = 0, capTE = 0, capTT = 0;
     unsigned long long* diag = nullptr;
 };
 
@@ -200,7 +210,7 @@ void release(p2m_weights* w) {
     void* ptrs[] = {w->bins.key, w->bins.rank, w->bins.hist, w->bins.start, w->bins.tsum, w->bins.pos_s,
                     w->bins.perm, w->bins.part_pos, w->bins.part_key, w->bins.part_uid, w->meta, w->idx, w->slow,
                     w->rd, w->tdiag, w->w64, w->w32, w->mem, w->diag, w->dsets, w->orow, w->oidx, w->ow64,
-                    w->ow32, w->omem};
+                    w->ow32, w->omem, w->tcnt, w->tptr, w->tent, w->tnode, w->ttile, w->gent};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (w->ev_fork) (void)hipEventDestroy(w->ev_fork);
@@ -231,7 +241,7 @@ bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) %
 size_t dsize(int dtype) { return dtype == P2M_F64 ? 8 : dtype == P2M_F32 ? 4 : 2; }
 
 int check_vals(const void* p, int C, int dtype, const char* what, bool mesh_side) {
-    if (C < 1 || C > 16) {
+    if (C < 1 || C > CMAX) {
         set_error("C=%d out of range [1, 16]", C);
         return P2M_EINVAL;
     }
@@ -276,6 +286,11 @@ WeightsView view(const p2m_weights* w) {
     v.pos_s = reinterpret_cast<const double2*>(w->bins.pos_s);
     v.perm = w->bins.perm;
     v.start = w->bins.start;
+    const bool det = (w->flags & P2M_DETERMINISTIC) != 0;
+    v.tptr = det ? w->tptr : nullptr;
+    v.tent = det ? w->tent : nullptr;
+    v.tnode = det ? w->tnode : nullptr;
+    v.gent = det ? w->gent : nullptr;
     return v;
 }
 
@@ -368,7 +383,7 @@ int check_build(const std::vector<SetDesc>& sets, const double* pos, int flags) 
         set_error("pos is NULL or not 16-byte aligned");
         return P2M_EINVAL;
     }
-    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR | P2M_PERIODIC)) {
+    if (flags & ~(P2M_WEIGHTS_F32 | P2M_STRICT | P2M_LINEAR | P2M_PERIODIC | P2M_DETERMINISTIC)) {
         set_error("unknown flags 0x%x", flags);
         return P2M_EINVAL;
     }
@@ -392,9 +407,12 @@ int launch_build(p2m_weights* w, const SetTotals& tot, const double* pos, int fl
     const bool want32 = (flags & P2M_WEIGHTS_F32) != 0;
     BuildOut out{w->meta, w->idx, w->w64, want32 ? w->w32 : nullptr, w->mem,
                  w->orow, w->oidx, w->ow64, want32 ? w->ow32 : nullptr, w->omem, w->capOvf};
-    return build_weights(w->bins, w->dsets, w->S, tot.n_tiles, tot.n_nodes, out, g_tune.levels, fast_slots(),
-                         w->slow, w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0,
-                         (flags & P2M_PERIODIC) != 0, g_tune.svd_cond);
+    rc = build_weights(w->bins, w->dsets, w->S, tot.n_tiles, tot.n_nodes, out, g_tune.levels, fast_slots(),
+                       w->slow, w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0,
+                       (flags & P2M_PERIODIC) != 0, g_tune.svd_cond);
+    if (!rc && (flags & P2M_DETERMINISTIC))
+        rc = build_transpose(view(w), w->tcnt, w->tptr, w->tent, w->tnode, w->ttile, st);
+    return rc;
 }
 
 int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const double* pos, int flags,
@@ -470,6 +488,25 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     if (!rc && want32) rc = grow(&w->ow32, ovw * novf, ovw * w->capOvf32);
     if (!rc) w->capOvf = novf;
     if (!rc && want32) w->capOvf32 = novf;
+    if (!rc && (flags & P2M_DETERMINISTIC)) {
+        // entry indices are int32 (checked), one per ELL or overflow entry
+        const int64_t n_ent = KMAX * n_slots + (KROW - KMAX) * novf;
+        if (n_ent >= (int64_t(1) << 31) || N >= (int64_t(1) << 31) - 1) {
+            set_error("P2M_DETERMINISTIC: %lld entries / %lld particles exceed the int32 index",
+                      static_cast<long long>(n_ent), static_cast<long long>(N));
+            rc = P2M_EINVAL;
+        }
+        const int64_t ntt = transpose_scan_tiles(N) + 1;
+        if (!rc) rc = grow(&w->tcnt, N, w->capTN);
+        if (!rc) rc = grow(&w->tptr, N + 1, w->capTN + 1);
+        if (!rc) w->capTN = std::max(w->capTN, N);
+        if (!rc) rc = grow(&w->tent, n_ent, w->capTE);
+        if (!rc) rc = grow(&w->tnode, n_ent, w->capTE);
+        if (!rc) rc = grow(&w->gent, n_ent, w->capTE);
+        if (!rc) w->capTE = std::max(w->capTE, n_ent);
+        if (!rc) rc = grow(&w->ttile, ntt, w->capTT);
+        if (!rc) w->capTT = std::max(w->capTT, ntt);
+    }
     if (!rc && !w->diag) rc = grow(&w->diag, D_COUNT, 0);
     if (!rc) rc = grow(&w->dsets, S, w->capSets);
     if (rc) {

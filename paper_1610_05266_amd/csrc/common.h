@@ -54,6 +54,7 @@ constexpr int KMAX = 32;               // ELL entries stored per node slot
 constexpr int KROW = P2M_MAX_SUPPORT;  // longest row (count field: 6 bits)
 static_assert(KROW <= 63 && KROW > KMAX, "row count fits the metadata word");
 constexpr int KNN = P2M_CLOSURE_K;
+constexpr int CMAX = 16;  // channels per call (checked at the boundary)
 
 // Per-node metadata word of the ELL weights.
 // NT_PENDING*: node whose support is known (interior: ring union; closure:
@@ -206,7 +207,23 @@ struct WeightsView {
     const double2* pos_s;   // [N] positions in bin order (the binning)
     const int32_t* perm;    // [N] bin order -> user id
     const int32_t* start;   // first bin-order slot of every bin (bins of set s from sets[s].b0)
+    // Particle-major index of the entries (handles built with
+    // P2M_DETERMINISTIC, else null): the entries that reference user
+    // particle u are tent[tptr[u] .. tptr[u + 1]), ascending, each an entry
+    // index (see entry_at) with its node in tnode; gent is per-entry scratch
+    // of the position adjoint.
+    const int32_t* tptr;    // [N + 1]
+    const int32_t* tent;
+    const int32_t* tnode;
+    double2* gent;          // [n_ent]
 };
+
+// Entry index of entry k of slot s: k * n_slots + s in the ELL arrays, else
+// KMAX * n_slots + its overflow index (n_ent = KMAX n_slots + (KROW - KMAX) n_ovf).
+__host__ __device__ inline int64_t entry_at(int64_t n_slots, int64_t n_ovf, int32_t orow, int64_t s, int k) {
+    return k < KMAX ? static_cast<int64_t>(k) * n_slots + s
+                    : KMAX * n_slots + static_cast<int64_t>(k - KMAX) * n_ovf + orow;
+}
 
 // Index of entry k (>= KMAX) of an overflow row r in the overflow arrays.
 __host__ __device__ inline int64_t ovf_at(int64_t n_ovf, int32_t r, int k) {

@@ -113,6 +113,18 @@ int m2p_backward(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, co
                  int dtype, const double* pos, int64_t N, const void* grad_vals, void* grad_mesh, double* grad_pos,
                  hipStream_t st);
 
+// ---- particle-major index of the entries (transpose.hip) ----
+// Scan tiles of the per-particle counts (tsum needs one more entry).
+int64_t transpose_scan_tiles(int64_t N);
+// cnt [N] scratch, ptr [N + 1], ent and nodes [n_ent], tsum [tiles + 1].
+int build_transpose(const WeightsView& w, int32_t* cnt, int32_t* ptr, int32_t* ent, int32_t* nodes, int32_t* tsum,
+                    hipStream_t st);
+// P2M^t gathered per particle through the index (grad_vals overwritten).
+int project_backward_gather(const WeightsView& w, const void* grad_mesh, int C, int dtype, void* grad_vals,
+                            hipStream_t st);
+// grad_pos[u] += the per-entry position derivatives in w.gent of particle u.
+int gather_entry_grads(const WeightsView& w, double* grad_pos, hipStream_t st);
+
 // ---- adjoint of the weights (adjoint.hip) ----
 int build_backward(const WeightsView& w, const double* pos, const double* grad_w, double* grad_pos,
                    hipStream_t st, bool periodic);

@@ -15,7 +15,6 @@ namespace p2m {
 
 namespace {
 
-constexpr int CMAX = 16;
 
 struct Loc {
     int64_t n0, n1, n2;

@@ -11,7 +11,6 @@ namespace p2m {
 
 namespace {
 
-constexpr int CMAX = 16;
 
 template <typename T> struct Acc;
 template <> struct Acc<double> { using type = double; };
@@ -154,6 +153,18 @@ int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dt
                      void* grad_vals, double* grad_w, hipStream_t st) {
     PhaseTimer _timer(PH_PROJECT_BWD, st);
     const int blocks = static_cast<int>((wv.n_slots + 255) / 256);
+    if (dtype != P2M_F64 && !wv.w32) {
+        set_error("p2m_project_backward: FP32/BF16 needs a handle built with P2M_WEIGHTS_F32");
+        return P2M_EINVAL;
+    }
+    if (grad_vals && wv.tptr) {
+        // a particle-major index: grad_vals gathered per particle (no
+        // atomics); the row pass below then forms grad_w alone
+        int rc = project_backward_gather(wv, grad_mesh, C, dtype, grad_vals, st);
+        if (rc) return rc;
+        grad_vals = nullptr;
+        if (!grad_w) return P2M_OK;
+    }
     if (dtype == P2M_F64) {
         if (grad_vals) {
             int rc = fill_bytes_zero(grad_vals, sizeof(double) * wv.N * C, st);
@@ -163,10 +174,6 @@ int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dt
             wv, wv.w64, wv.ow64, static_cast<const double*>(grad_mesh), C,
             static_cast<const double*>(vals), static_cast<double*>(grad_vals), grad_w);
     } else {
-        if (!wv.w32) {
-            set_error("p2m_project_backward: FP32/BF16 needs a handle built with P2M_WEIGHTS_F32");
-            return P2M_EINVAL;
-        }
         if (grad_vals) {
             int rc = fill_bytes_zero(grad_vals, sizeof(float) * wv.N * C, st);
             if (rc) return rc;

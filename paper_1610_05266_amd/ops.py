@@ -11,7 +11,7 @@ from typing import Optional, Tuple
 import torch
 
 from . import _lib
-from ._lib import (P2M_BF16, P2M_F32, P2M_F64, P2M_LINEAR, P2M_PERIODIC, P2M_STRICT, P2M_WEIGHTS_F32, MAX_SUPPORT, P2MDiag, P2MError,
+from ._lib import (P2M_BF16, P2M_DETERMINISTIC, P2M_F32, P2M_F64, P2M_LINEAR, P2M_PERIODIC, P2M_STRICT, P2M_WEIGHTS_F32, MAX_SUPPORT, P2MDiag, P2MError,
                    P2MMesh, check, load)
 
 __all__ = [
@@ -38,6 +38,7 @@ __all__ = [
     "P2M_STRICT",
     "P2M_LINEAR",
     "P2M_PERIODIC",
+    "P2M_DETERMINISTIC",
     "p2m_advect",
     "MeshQCSF",
     "kinematic_step",

@@ -16,7 +16,8 @@ from paper_1610_05266_amd import build as B
 pytestmark = pytest.mark.skipif(shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"),
                                 reason="hipcc not available")
 
-KERNEL_SOURCES = ["util.hip", "binning.hip", "build.hip", "project.hip", "m2p.hip", "adjoint.hip"]
+KERNEL_SOURCES = ["util.hip", "binning.hip", "build.hip", "project.hip", "m2p.hip", "adjoint.hip", "transpose.hip",
+                  "advect.hip"]
 
 
 def _kernels(asm: str):

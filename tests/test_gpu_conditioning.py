@@ -28,7 +28,7 @@ from oracle import Mesh as OMesh, P2MOracle
 from oracle.adjoint import p2m_grad_pos as o_p2m_grad_pos
 from oracle.periodic import PeriodicP2MOracle
 from paper_1610_05266_amd import ops
-from paper_1610_05266_amd._lib import P2M_PERIODIC
+from paper_1610_05266_amd._lib import P2M_DETERMINISTIC, P2M_PERIODIC
 from tests._util import assert_close, ell_to_csr
 
 pytestmark = pytest.mark.gpu
@@ -140,6 +140,22 @@ def test_svd_path_in_the_periodic_box(svd_everywhere):
     idx, wt, cnt, _ = w.export()
     G = ell_to_csr(idx.numpy(), wt.numpy(), cnt.numpy(), c.N)
     assert abs(G - W).max() <= 1e-12 * abs(W).max()
+
+
+def test_svd_path_position_adjoint_in_the_periodic_box(svd_everywhere):
+    """Rows of the seam (copies of the rows of the nodes they repeat) take
+    the SVD-path adjoint as well."""
+    from oracle.periodic import periodic_p2m_grad_pos
+    c = wl.periodic_tg_cloud(16, 2, 0.25, seed=12)
+    orc = PeriodicP2MOracle(c.pos, OMesh.from_spec(c.mesh), c.h)
+    gmesh = np.random.default_rng(13).normal(size=(c.mesh.n_nodes, c.vals.shape[1]))
+    pos = _g(c.pos)
+    for flags in (P2M_PERIODIC, P2M_PERIODIC | P2M_DETERMINISTIC):
+        w = ops.p2m_build_weights(c.mesh, c.h, pos, flags)
+        _, gw = ops.p2m_project_backward(w, _g(gmesh), _g(c.vals), want_vals=False, want_w=True)
+        gp = ops.p2m_build_weights_backward(w, pos, gw).cpu().numpy()
+        assert w.diag()["bwd_rank_deficient"] == 0
+        assert_close(gp, periodic_p2m_grad_pos(orc, c.vals, gmesh), 1e-10, f"periodic SVD-path grad pos {flags}")
 
 
 def test_rank_deficient_systems_are_counted_by_the_adjoint():
