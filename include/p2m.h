@@ -366,13 +366,21 @@ void p2m_weights_destroy(p2m_weights* w);
  * ------------------------------------------------------------------------ */
 
 /* eq. (p2m) with the App. B weights built for this call (arguments as in
- * p2m_build_weights and p2m_project; FP32/BF16 values use FP32 weights). */
+ * p2m_build_weights and p2m_project; FP32/BF16 values use FP32 weights).
+ * For C <= 4 the weights pass adds each row of the fast path into its node's
+ * sum as it weighs it and keeps no weights of it; rows of the exact path and
+ * of the rank-revealing solver keep their weights and are summed afterwards.
+ * The order of every sum is p2m_project's: the result is
+ * p2m_build_weights + p2m_project bit for bit. */
 int p2m_project_fused(const p2m_mesh* mesh, double h, const double* pos, int64_t N,
                       const void* vals, int C, int dtype, void* mesh_vals, void* stream);
 
 /* The current device's workspace handle of the recompute forms (NULL before
- * the first call): p2m_weights_diag / p2m_weights_export on it describe the
- * last recompute build.  Owned by the library; do not destroy. */
+ * the first call): p2m_weights_diag on it describes the last recompute
+ * build.  After a p2m_project_fused the handle holds no weights, and the calls
+ * that read weights (p2m_project, p2m_weights_export, the backward calls)
+ * refuse it with EINVAL; after a p2m_backward_fused it holds that build's
+ * weights.  Owned by the library; do not destroy. */
 const p2m_weights* p2m_fused_handle(void);
 
 /* Adjoint of p2m_project_fused for the upstream gradient grad_mesh

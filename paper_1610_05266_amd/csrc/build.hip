@@ -1488,10 +1488,29 @@ enum { WC_INTERIOR, WC_CLOSURE, WC_OUTSIDE, WC_SUPMAX };
 // row's systems, identically, and they split the final pass over the support
 // entries (quad sub takes entries sub, sub + QS, ...), whose weights do not
 // depend on one another, so the row is the same bit for bit for any QS.
-template <bool PER, int QS = 1>
+// What the weights pass does with a finished row: store its weights in the
+// handle's rows (StoreRows), or add them into the node's weighted sum of
+// eq. (p2m) at once and store that (ProjRows: the fused build, which keeps
+// no weights of these rows).
+struct StoreRows {
+    static constexpr bool proj = false;
+};
+template <typename TV, typename TW, typename TO, int CC>
+struct ProjRows {
+    static constexpr bool proj = true;
+    using Sum = RowSum<TV, TW, TO, CC>;
+    using W = TW;
+    const TV* vals;
+    TO* out;
+    int C;
+};
+
+template <bool PER, int QS = 1, class R = StoreRows>
 __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc& sd, int i, int j, bool valid,
                                                    int64_t slot, int lane, int qi, double2* sp, uint32_t* se,
-                                                   int32_t* su, bool escalated_rows, int sub = 0) {
+                                                   int32_t* su, bool escalated_rows, int sub = 0,
+                                                   const R& rp = R{}) {
+    static_assert(!R::proj || QS == 1, "a projected row is summed by one quad");
     const int64_t nn = a.n_slots;
     const uint32_t meta = valid ? a.out.meta[slot] : 0u;
     const bool mine = valid && (((meta_flags(meta) & MF_ESCALATED) != 0) == escalated_rows);
@@ -1695,7 +1714,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
                 f(k, e, img(a.pos_s[e & IDX_MASK]), a.perm[e & IDX_MASK]);
             }
         };
-        each_sub([&](int k, uint32_t e, double2 p, int32_t u) {
+        auto weight = [&](int k, uint32_t e, double2 p) {
             double c = 0.0;
             if (pend && lane == 3) {
                 c = (k == lt[0] ? phi[0] : 0.0) + (k == lt[1] ? phi[1] : 0.0) + (k == lt[2] ? phi[2] : 0.0);
@@ -1704,14 +1723,29 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
                 monos((p.x - cx) * sc, (p.y - cy) * sc, pm);
                 c = coef * dot6(pm, y);
             }
-            const double w = quad_sum(c);
-            if (lane == (k & (QL - 1))) {
-                a.out.idx[k * nn + slot] = u;
-                a.out.w64[k * nn + slot] = w;
-                if (a.out.w32) a.out.w32[k * nn + slot] = static_cast<float>(w);
-                a.out.mem[k * nn + slot] = clos ? 0 : static_cast<uint8_t>(e >> 28);
-            }
-        });
+            return quad_sum(c);
+        };
+        if constexpr (R::proj) {
+            // lane k % 4 adds entry k, in ascending k: the order of the
+            // stored-weights projection
+            typename R::Sum rs;
+            rs.init();
+            each_sub([&](int k, uint32_t e, double2 p, int32_t u) {
+                const double w = weight(k, e, p);
+                if (lane == (k & (QL - 1))) rs.add(static_cast<typename R::W>(w), rp.vals, u, rp.C);
+            });
+            rs.store(rp.out, ij_node(sd, i, j), rp.C, lane);
+        } else {
+            each_sub([&](int k, uint32_t e, double2 p, int32_t u) {
+                const double w = weight(k, e, p);
+                if (lane == (k & (QL - 1))) {
+                    a.out.idx[k * nn + slot] = u;
+                    a.out.w64[k * nn + slot] = w;
+                    if (a.out.w32) a.out.w32[k * nn + slot] = static_cast<float>(w);
+                    a.out.mem[k * nn + slot] = clos ? 0 : static_cast<uint8_t>(e >> 28);
+                }
+            });
+        }
         if (lane == 0 && sub == 0) {
             const uint32_t ft = pend ? NT_INTERIOR : (type == NT_PEND_OUT ? NT_OUTSIDE : NT_RING);
             a.out.meta[slot] = pend ? meta_pack(ft, n, lt[0], lt[1], lt[2], meta_flags(meta))
@@ -1998,8 +2032,8 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
 
 // Weights of the fast path's pending rows, one quad per node, nodes in the
 // same 8 x 8 tiles as the fast kernel.
-template <bool PER>
-__global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
+template <bool PER, class R = StoreRows>
+__global__ void __launch_bounds__(QWG) k_weights(KArgs a, R rp = R{}) {
     __shared__ double2 sp[QPB * SKP];
     __shared__ uint32_t se[QPB * SKP];
     __shared__ int32_t su[QPB * SKP];
@@ -2012,7 +2046,7 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a) {
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
     const int64_t slot = static_cast<int64_t>(blockIdx.x) * TILE_N + qi;
-    const WaveCounts wc = weights_node<PER>(a, sd, i, j, valid, slot, lane, qi, sp, se, su, false);
+    const WaveCounts wc = weights_node<PER, 1, R>(a, sd, i, j, valid, slot, lane, qi, sp, se, su, false, 0, rp);
     // the tile's counts as one plain record, folded into the diagnostics by
     // k_weights_rd: device-wide atomics from every wave on the same few
     // counters serialise at their memory partition and stall the pass
@@ -2191,13 +2225,36 @@ __global__ void __launch_bounds__(QWG) k_seam_copy(KArgs a) {
     }
 }
 
+// The projecting weights pass for the value type of the fused build.
+template <typename TV, typename TW, typename TO>
+void launch_weights_proj_t(const KArgs& a, const FusedProj& fp, int tiles, hipStream_t st) {
+    const TV* v = static_cast<const TV*>(fp.vals);
+    TO* o = static_cast<TO*>(fp.out);
+    // (channel counts up to FUSED_CMAX: the sums stay in registers)
+    switch (fp.C) {
+        case 1: k_weights<false, ProjRows<TV, TW, TO, 1>><<<tiles, QWG, 0, st>>>(a, {v, o, fp.C}); break;
+        case 2: k_weights<false, ProjRows<TV, TW, TO, 2>><<<tiles, QWG, 0, st>>>(a, {v, o, fp.C}); break;
+        case 3: k_weights<false, ProjRows<TV, TW, TO, 3>><<<tiles, QWG, 0, st>>>(a, {v, o, fp.C}); break;
+        default: k_weights<false, ProjRows<TV, TW, TO, 4>><<<tiles, QWG, 0, st>>>(a, {v, o, fp.C}); break;
+    }
+}
+void launch_weights_proj(const KArgs& a, const FusedProj& fp, int tiles, hipStream_t st) {
+    if (fp.dtype == P2M_F64) launch_weights_proj_t<double, double, double>(a, fp, tiles, st);
+    else if (fp.dtype == P2M_F32) launch_weights_proj_t<float, float, float>(a, fp, tiles, st);
+    else launch_weights_proj_t<uint16_t, float, float>(a, fp, tiles, st);
+}
+
 }  // namespace
 
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
                   const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,
                   unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear,
-                  bool periodic, double svd_kappa) {
+                  bool periodic, double svd_kappa, const FusedProj* fp) {
     PhaseTimer _timer(PH_BUILD, st);
+    if (fp && (periodic || fp->C < 1 || fp->C > FUSED_CMAX)) {
+        set_error("the fused build takes a bounded box and 1..%d channels", FUSED_CMAX);
+        return P2M_EINVAL;
+    }
     // row slots are listed as int32
     if (n_tiles * TILE_N >= (int64_t(1) << 31)) {
         set_error("too many node tiles (%lld)", static_cast<long long>(n_tiles));
@@ -2258,7 +2315,8 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         // on the pass that found it)
         {
             PhaseTimer t4(PH_K_WEIGHTS, st);
-            if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
+            if (fp) launch_weights_proj(a, *fp, tiles, st);
+            else if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
             else k_weights<false><<<tiles, QWG, 0, st>>>(a);
         }
         if (fork) P2M_HIP(hipStreamWaitEvent(st, side.join, 0));

@@ -136,7 +136,9 @@ struct p2m_weights {
     int flags = 0;
     // capacities of the device buffers
     int64_t capN = 0, capBins = 0, capNodes = 0, capSlots = 0, capTiles = 0, capSets = 0, capHist = 0;
-    bool capW32 = false;
+    // slots the FP32 weights hold: tracked on their own, since a build
+    // without P2M_WEIGHTS_F32 grows the other row buffers but not these
+    int64_t capSlots32 = 0;
     BinBuffers bins{};
     uint32_t* meta = nullptr;  // ELL rows per node slot (64 per node tile)
     int32_t* idx = nullptr;
@@ -165,6 +167,9 @@ struct p2m_weights {
     int32_t* ttile = nullptr;
     double2* gent = nullptr;
     int64_t capTN = 0, capTE = 0, capTT = 0;
+    // the last build projected its values as it weighted them and kept the
+    // weights of the exact and rank-revealing rows only (p2m_project_fused)
+    bool rows_only = false;
     unsigned long long* diag = nullptr;
 };
 
@@ -307,6 +312,16 @@ int check_handle(const p2m_weights* w) {
     return P2M_OK;
 }
 
+// A handle whose rows hold weights (not the workspace of a fused projection).
+int check_rows(const p2m_weights* w) {
+    int rc = check_handle(w);
+    if (!rc && w->rows_only) {
+        set_error("the last build of this handle was a fused projection, which keeps no weights");
+        rc = P2M_EINVAL;
+    }
+    return rc;
+}
+
 // Set table of a batch: grid, fast-path radii and offsets of every set from
 // its mesh, its particle spacing h and the current tuning options.
 int make_sets(const p2m_mesh* meshes, const double* hs, const int64_t* off, int S, std::vector<SetDesc>& sets,
@@ -400,7 +415,8 @@ int check_build(const std::vector<SetDesc>& sets, const double* pos, int flags) 
 // in place: binning, then the build kernels (slow path on side.stream, or on
 // st when side.stream is null).
 int launch_build(p2m_weights* w, const SetTotals& tot, const double* pos, int flags, const SideWork& side,
-                 hipStream_t st) {
+                 hipStream_t st, const FusedProj* fp = nullptr) {
+    w->rows_only = fp != nullptr;
     // (the binning clears the diagnostics before anything counts into them)
     int rc = bin_particles(w->bins, pos, tot.N, w->dsets, w->S, tot.nbins, w->diag, st);
     if (rc) return rc;
@@ -409,14 +425,14 @@ int launch_build(p2m_weights* w, const SetTotals& tot, const double* pos, int fl
                  w->orow, w->oidx, w->ow64, want32 ? w->ow32 : nullptr, w->omem, w->capOvf};
     rc = build_weights(w->bins, w->dsets, w->S, tot.n_tiles, tot.n_nodes, out, g_tune.levels, fast_slots(),
                        w->slow, w->rd, w->tdiag, w->diag, side, st, (flags & P2M_LINEAR) != 0,
-                       (flags & P2M_PERIODIC) != 0, g_tune.svd_cond);
+                       (flags & P2M_PERIODIC) != 0, g_tune.svd_cond, fp);
     if (!rc && (flags & P2M_DETERMINISTIC))
         rc = build_transpose(view(w), w->tcnt, w->tptr, w->tent, w->tnode, w->ttile, st);
     return rc;
 }
 
 int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const double* pos, int flags,
-               p2m_weights** wout, hipStream_t st) {
+               p2m_weights** wout, hipStream_t st, const FusedProj* fp = nullptr) {
     int rc0 = check_build(sets, pos, flags);
     if (rc0) return rc0;
     if (!wout) {
@@ -475,7 +491,8 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     if (!rc) rc = grow(&w->idx, n_slots * KMAX, w->capSlots * KMAX);
     if (!rc) rc = grow(&w->w64, n_slots * KMAX, w->capSlots * KMAX);
     if (!rc) rc = grow(&w->mem, n_slots * KMAX, w->capSlots * KMAX);
-    if (!rc && want32) rc = grow(&w->w32, n_slots * KMAX, w->capW32 ? w->capSlots * KMAX : 0);
+    if (!rc && want32) rc = grow(&w->w32, n_slots * KMAX, w->capSlots32 * KMAX);
+    if (!rc && want32) w->capSlots32 = std::max(w->capSlots32, n_slots);
     // overflow rows: a small store for the rare rows longer than KMAX
     // (the row stride of every overflow array is capOvf, so they all keep
     // at least that many rows)
@@ -516,7 +533,6 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
         }
         return rc;
     }
-    if (want32 && !w->capW32) w->capW32 = true;
     w->capNodes = std::max(w->capNodes, n_nodes);
     w->capSlots = std::max(w->capSlots, n_slots);
     w->capSets = std::max<int64_t>(w->capSets, S);
@@ -536,7 +552,7 @@ int build_sets(const std::vector<SetDesc>& sets, const SetTotals& tot, const dou
     SideWork side{nullptr, w->ev_fork, w->ev_join};
     rc = side_stream(dev, &side.stream);
     if (rc) return rc;
-    return launch_build(w, tot, pos, flags, side, st);
+    return launch_build(w, tot, pos, flags, side, st, fp);
 }
 
 // Per-device workspace of the fused (recompute) entry points: a weights
@@ -659,8 +675,8 @@ int p2m_get_option(const char* name, double* value) {
     return P2M_OK;
 }
 
-int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t N, int flags,
-                      p2m_weights** wout, void* stream) {
+int build_single(const p2m_mesh* mesh, double h, const double* pos, int64_t N, int flags, p2m_weights** wout,
+                 hipStream_t st, const FusedProj* fp) {
     int rc = check_mesh(mesh);
     if (rc) return rc;
     if (N < 3 || N >= (int64_t(1) << 28)) {
@@ -672,7 +688,12 @@ int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t
     SetTotals tot;
     rc = make_sets(mesh, &h, off, 1, sets, tot);
     if (rc) return rc;
-    return build_sets(sets, tot, pos, flags, wout, static_cast<hipStream_t>(stream));
+    return build_sets(sets, tot, pos, flags, wout, st, fp);
+}
+
+int p2m_build_weights(const p2m_mesh* mesh, double h, const double* pos, int64_t N, int flags,
+                      p2m_weights** wout, void* stream) {
+    return build_single(mesh, h, pos, N, flags, wout, static_cast<hipStream_t>(stream), nullptr);
 }
 
 int p2m_batch_create(const p2m_mesh* meshes, const double* h, int S, const int64_t* set_offsets, p2m_batch** out) {
@@ -801,7 +822,7 @@ int p2m_weights_diag(const p2m_weights* w, p2m_diag* d, void* stream) {
 }
 
 int p2m_weights_export(const p2m_weights* w, int32_t* idx, double* wts, int32_t* cnt, int32_t* tri, void* stream) {
-    int rc = check_handle(w);
+    int rc = check_rows(w);
     if (rc) return rc;
     return export_weights(view(w), idx, wts, cnt, tri, static_cast<hipStream_t>(stream));
 }
@@ -817,7 +838,7 @@ int p2m_weights_shape(const p2m_weights* w, int64_t* n_nodes, int64_t* n_particl
 }
 
 int p2m_project(const p2m_weights* w, const void* vals, int C, int dtype, void* mesh_vals, void* stream) {
-    int rc = check_handle(w);
+    int rc = check_rows(w);
     if (!rc) rc = check_vals(vals, C, dtype, "vals", false);
     if (!rc) rc = check_vals(mesh_vals, C, dtype, "mesh_vals", true);
     if (rc) return rc;
@@ -935,7 +956,7 @@ int m2p_interpolate_backward_binned(const p2m_weights* w, const void* mesh_vals,
 
 int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int dtype, const void* vals,
                          void* grad_vals, double* grad_w, void* stream) {
-    int rc = check_handle(w);
+    int rc = check_rows(w);
     if (!rc) rc = check_vals(grad_mesh, C, dtype, "grad_mesh", true);
     if (!rc && grad_vals) rc = check_vals(grad_vals, C, dtype == P2M_BF16 ? P2M_F32 : dtype, "grad_vals", false);
     if (!rc && grad_w) rc = check_vals(vals, C, dtype, "vals", false);
@@ -949,7 +970,7 @@ int p2m_project_backward(const p2m_weights* w, const void* grad_mesh, int C, int
 
 int p2m_build_weights_backward(const p2m_weights* w, const double* pos, const double* grad_w, double* grad_pos,
                                void* stream) {
-    int rc = check_handle(w);
+    int rc = check_rows(w);
     if (rc) return rc;
     if (!pos || !aligned(pos, 16) || !grad_w || !aligned(grad_w, 8) || !grad_pos || !aligned(grad_pos, 16)) {
         set_error("pos / grad_w / grad_pos NULL or misaligned");
@@ -981,8 +1002,17 @@ int p2m_project_fused(const p2m_mesh* mesh, double h, const double* pos, int64_t
     hipStream_t st = static_cast<hipStream_t>(stream);
     rc = fused_enter(fw, st);
     if (rc) return rc;
-    rc = p2m_build_weights(mesh, h, pos, N, dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32, &fw.w, stream);
-    if (!rc) rc = p2m_project(fw.w, vals, C, dtype, mesh_vals, stream);
+    const int flags = dtype == P2M_F64 ? 0 : P2M_WEIGHTS_F32;
+    if (C <= FUSED_CMAX) {
+        // the rows of the fast path are projected as they are weighted; the
+        // rest (exact and rank-revealing paths) from their stored weights
+        const FusedProj fp{vals, C, dtype, mesh_vals};
+        rc = build_single(mesh, h, pos, N, flags, &fw.w, st, &fp);
+        if (!rc) rc = project_listed(view(fw.w), fw.w->slow, vals, C, dtype, mesh_vals, st);
+    } else {
+        rc = build_single(mesh, h, pos, N, flags, &fw.w, st, nullptr);
+        if (!rc) rc = p2m_project(fw.w, vals, C, dtype, mesh_vals, stream);
+    }
     return fused_leave(fw, st, rc);
 }
 

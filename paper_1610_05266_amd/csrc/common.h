@@ -285,6 +285,43 @@ __device__ __forceinline__ float lane_xor(float v, int m) {
 __device__ __forceinline__ float bf16_to_f32(uint16_t v) {
     return __uint_as_float(static_cast<uint32_t>(v) << 16);
 }
+// Field element load widened to the accumulation type.
+__device__ __forceinline__ double ld(const double* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ld(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float ld(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
+
+// One node's weighted sum of eq. (p2m) by the four lanes of a quad: lane l
+// adds the entries k = l, l + 4, ... in ascending k (add), then the partial
+// sums are combined in a fixed order and lane c % 4 stores channel c
+// (store).  The stored-weights projection and the fused build share it, so
+// both give the same bits.
+template <typename TV, typename TW, typename TO, int CC>
+struct RowSum {
+    static constexpr int NC = CC > 0 ? CC : CMAX;
+    TW acc[NC];
+    __device__ __forceinline__ void init() {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[c] = TW(0);
+    }
+    __device__ __forceinline__ void add(TW wk, const TV* vals, int64_t j, int C) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < C) acc[c] += wk * static_cast<TW>(ld(vals, j * C + c));
+    }
+    __device__ __forceinline__ void store(TO* out, int64_t node, int C, int lane) {
+        // (a constant trip count: the loop unrolls and acc stays in registers)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (c < C) {
+                TW v = acc[c];
+                v += lane_xor<4>(v, 1);
+                v += lane_xor<4>(v, 2);
+                if (lane == (c & 3)) out[node * C + c] = static_cast<TO>(v);
+            }
+        }
+    }
+};
+
 // Round-to-nearest-even FP32 -> BF16 (NaN kept quiet).
 __device__ __forceinline__ uint16_t f32_to_bf16(float f) {
     uint32_t u = __float_as_uint(f);

@@ -80,15 +80,30 @@ int side_stream(int device, hipStream_t* out);
 // goes to the rank-revealing solver; linear: interior rows are the
 // triangle's barycentric coordinates alone.
 constexpr int BUILD_TD = 5;
+// Fused build (fp non-null; bounded box only): the weights pass adds each
+// row it finishes into mesh value `out` at once and stores no weights for
+// it; the rows of the exact and rank-revealing paths keep stored weights and
+// are projected afterwards by project_listed.
+constexpr int FUSED_CMAX = 4;  // channels of a fused build (more: build, then project)
+struct FusedProj {
+    const void* vals;
+    int C;
+    int dtype;
+    void* out;
+};
 int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_tiles, int64_t n_nodes,
                   const BuildOut& out, int levels, int fast_slots, int32_t* slow, int32_t* rd, int32_t* tdiag,
                   unsigned long long* diag, const SideWork& side, hipStream_t st, bool linear,
-                  bool periodic, double svd_kappa);
+                  bool periodic, double svd_kappa, const FusedProj* fp = nullptr);
 
 // ---- projection and interpolation (project.hip, m2p.hip) ----
 int project(const WeightsView& w, const void* vals, int C, int dtype, void* mesh_vals, hipStream_t st);
 int project_backward(const WeightsView& w, const void* grad_mesh, int C, int dtype, const void* vals,
                      void* grad_vals, double* grad_w, hipStream_t st);
+// After a fused build: the rows on the slow-path list and the rank-revealing
+// list, projected from their stored weights.
+int project_listed(const WeightsView& w, const int32_t* slow, const void* vals, int C, int dtype, void* mesh_vals,
+                   hipStream_t st);
 // sets == nullptr: one mesh m; else particles/nodes of set s start at
 // sets[s].p0 / sets[s].n0 and m is ignored.  n_nodes: all sets.
 // Mesh-side quadratically consistent functions: edge count and the table of

@@ -16,9 +16,6 @@ template <typename T> struct Acc;
 template <> struct Acc<double> { using type = double; };
 template <> struct Acc<float> { using type = float; };
 
-__device__ __forceinline__ double ld(const double* p, int64_t i) { return p[i]; }
-__device__ __forceinline__ float ld(const float* p, int64_t i) { return p[i]; }
-__device__ __forceinline__ float ld(const uint16_t* p, int64_t i) { return bf16_to_f32(p[i]); }
 
 // The mesh node of a quad's slot in a one-tile block (false beyond the mesh).
 __device__ __forceinline__ bool tile_node(const WeightsView& wv, int64_t& slot, int64_t& node) {
@@ -36,45 +33,53 @@ __device__ __forceinline__ bool tile_node(const WeightsView& wv, int64_t& slot, 
 // are combined by a quad reduction (fixed order, so results are bitwise
 // reproducible), and lane c % 4 stores channel c.
 template <typename TV, typename TW, typename TO, int CC>
-__global__ void __launch_bounds__(256) k_project(WeightsView wv, const TW* __restrict__ w, const TW* __restrict__ ow,
-                                                 const TV* __restrict__ vals, int Crt, TO* __restrict__ out) {
-    constexpr int NC = CC > 0 ? CC : CMAX;
-    const int lane = threadIdx.x & 3;
-    int64_t slot, node;
-    if (!tile_node(wv, slot, node)) return;  // the four lanes of a node leave together
+__device__ __forceinline__ void project_row(const WeightsView& wv, const TW* __restrict__ w,
+                                            const TW* __restrict__ ow, const TV* __restrict__ vals, int C,
+                                            int64_t slot, int64_t node, int lane, TO* __restrict__ out) {
     const int64_t ns = wv.n_slots;
-    const int C = CC > 0 ? CC : Crt;
-    TW acc[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] = TW(0);
+    RowSum<TV, TW, TO, CC> rs;
+    rs.init();
     const int cnt = row_len(wv.meta[slot]);
     const int ce = cnt < KMAX ? cnt : KMAX;
-    for (int k = lane; k < ce; k += 4) {
-        const int64_t j = wv.idx[k * ns + slot];
-        const TW wk = w[k * ns + slot];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            if (c < C) acc[c] += wk * static_cast<TW>(ld(vals, j * C + c));
-    }
+    for (int k = lane; k < ce; k += 4) rs.add(w[k * ns + slot], vals, wv.idx[k * ns + slot], C);
     if (cnt > KMAX) {
         // a long row's entries KMAX.. (overflow row)
         const int32_t r = wv.orow[slot];
         for (int k = KMAX + lane; k < cnt; k += 4) {
             const int64_t o = ovf_at(wv.n_ovf, r, k);
-            const int64_t j = wv.oidx[o];
-            const TW wk = ow[o];
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-                if (c < C) acc[c] += wk * static_cast<TW>(ld(vals, j * C + c));
+            rs.add(ow[o], vals, wv.oidx[o], C);
         }
     }
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (c >= C) break;
-        TW v = acc[c];
-        v += lane_xor<4>(v, 1);
-        v += lane_xor<4>(v, 2);
-        if (lane == (c & 3)) out[node * C + c] = static_cast<TO>(v);
+    rs.store(out, node, C, lane);
+}
+
+template <typename TV, typename TW, typename TO, int CC>
+__global__ void __launch_bounds__(256) k_project(WeightsView wv, const TW* __restrict__ w, const TW* __restrict__ ow,
+                                                 const TV* __restrict__ vals, int Crt, TO* __restrict__ out) {
+    const int lane = threadIdx.x & 3;
+    int64_t slot, node;
+    if (!tile_node(wv, slot, node)) return;  // the four lanes of a node leave together
+    project_row<TV, TW, TO, CC>(wv, w, ow, vals, CC > 0 ? CC : Crt, slot, node, lane, out);
+}
+
+// The rows of the exact and rank-revealing paths after a fused build (whose
+// other rows were projected as they were weighted): the slow-path list, then
+// the rank-revealing list (a row on both is projected twice, to the same
+// bits).  A quad per listed row, the grid looping over the lists.
+template <typename TV, typename TW, typename TO, int CC>
+__global__ void __launch_bounds__(256) k_project_list(WeightsView wv, const int32_t* __restrict__ slow,
+                                                      const TW* __restrict__ w, const TW* __restrict__ ow,
+                                                      const TV* __restrict__ vals, int Crt, TO* __restrict__ out) {
+    const int lane = threadIdx.x & 3;
+    const int ns = static_cast<int>(wv.diag[D_SLOWCNT]), nr = static_cast<int>(wv.diag[D_RDCNT]);
+    const int stride = static_cast<int>(gridDim.x) * 64;
+    for (int li = static_cast<int>(blockIdx.x) * 64 + static_cast<int>(threadIdx.x >> 2); li < ns + nr;
+         li += stride) {
+        const int64_t slot = li < ns ? slow[li] : wv.rd[li - ns];
+        const SetDesc& sd = wv.sets[set_search(wv.S, slot / TILE_N, [&](int s) { return wv.sets[s].t0; })];
+        int i, j;
+        if (!slot_ij(sd, slot, i, j)) continue;
+        project_row<TV, TW, TO, CC>(wv, w, ow, vals, CC > 0 ? CC : Crt, slot, ij_node(sd, i, j), lane, out);
     }
 }
 
@@ -91,6 +96,15 @@ void launch_project(const WeightsView& wv, const TW* w, const TW* ow, const void
         case 4: k_project<TV, TW, TO, 4><<<blocks, 256, 0, st>>>(wv, w, ow, v, C, o); break;
         default: k_project<TV, TW, TO, 0><<<blocks, 256, 0, st>>>(wv, w, ow, v, C, o); break;
     }
+}
+
+template <typename TV, typename TW, typename TO>
+void launch_project_list(const WeightsView& wv, const int32_t* slow, const TW* w, const TW* ow, const void* vals,
+                         int C, void* out, hipStream_t st) {
+    const TV* v = static_cast<const TV*>(vals);
+    TO* o = static_cast<TO*>(out);
+    if (C == 3) k_project_list<TV, TW, TO, 3><<<64, 256, 0, st>>>(wv, slow, w, ow, v, C, o);
+    else k_project_list<TV, TW, TO, 0><<<64, 256, 0, st>>>(wv, slow, w, ow, v, C, o);
 }
 
 // grad_vals[j][c] += w * grad_mesh[i][c] (atomics) ; grad_w[k][i] = sum_c grad_mesh[i][c] vals[j][c]
@@ -145,6 +159,15 @@ int project(const WeightsView& wv, const void* vals, int C, int dtype, void* mes
         else
             launch_project<uint16_t, float, float>(wv, wv.w32, wv.ow32, vals, C, mesh_vals, st);
     }
+    P2M_HIP(hipGetLastError());
+    return P2M_OK;
+}
+
+int project_listed(const WeightsView& wv, const int32_t* slow, const void* vals, int C, int dtype, void* mesh_vals,
+                   hipStream_t st) {
+    if (dtype == P2M_F64) launch_project_list<double, double, double>(wv, slow, wv.w64, wv.ow64, vals, C, mesh_vals, st);
+    else if (dtype == P2M_F32) launch_project_list<float, float, float>(wv, slow, wv.w32, wv.ow32, vals, C, mesh_vals, st);
+    else launch_project_list<uint16_t, float, float>(wv, slow, wv.w32, wv.ow32, vals, C, mesh_vals, st);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }
