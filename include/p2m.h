@@ -360,7 +360,9 @@ void p2m_weights_destroy(p2m_weights* w);
  * keeps no weights between a forward and its backward -- the form for the
  * largest sizes.  Calls on one device are serialised: the host calls by a
  * lock, the device work by an event each call records on its stream and the
- * next call, on whatever stream, waits for before it rebuilds the workspace.
+ * next call, on whatever stream, waits for before it rebuilds the workspace
+ * (a call captured into a HIP graph takes no part in this: the graph orders
+ * its own work, and its replays must not overlap other calls on the device).
  * Results are those of p2m_build_weights + p2m_project (+ the backward calls)
  * bit for bit, since the build is deterministic.
  * ------------------------------------------------------------------------ */

@@ -569,7 +569,14 @@ struct FusedWork {
     hipEvent_t done = nullptr;
 };
 // Before reusing the workspace: wait on stream for the previous call's work.
+// Under stream capture the graph orders its own nodes (and its replays run
+// in stream order), so the event is neither waited for nor recorded there.
+bool capturing(hipStream_t st) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return hipStreamIsCapturing(st, &cs) == hipSuccess && cs == hipStreamCaptureStatusActive;
+}
 int fused_enter(FusedWork& fw, hipStream_t st) {
+    if (capturing(st)) return P2M_OK;
     if (!fw.done) {
         P2M_HIP(hipEventCreateWithFlags(&fw.done, hipEventDisableTiming));
         return P2M_OK;
@@ -578,7 +585,7 @@ int fused_enter(FusedWork& fw, hipStream_t st) {
     return P2M_OK;
 }
 int fused_leave(FusedWork& fw, hipStream_t st, int rc) {
-    if (fw.done) {
+    if (fw.done && !capturing(st)) {
         const hipError_t e = hipEventRecord(fw.done, st);
         if (e != hipSuccess && rc == P2M_OK) return hip_check(e, "hipEventRecord");
     }
