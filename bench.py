@@ -180,7 +180,7 @@ def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, grap
 
     import workloads as wl
     from paper_1610_05266_amd import ops, tune
-    from paper_1610_05266_amd._lib import P2M_WEIGHTS_F32
+    from paper_1610_05266_amd._lib import P2M_DETERMINISTIC, P2M_WEIGHTS_F32
 
     out = {}
     # ---- 64 sets in one launch sequence
@@ -256,12 +256,29 @@ def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, grap
         # handle was built from the same positions): no atomics
         ops.m2p_interpolate_backward_binned(w4, f32, pos, gv, want_mesh=True, grad_pos=gpos)
 
+    # the same step with the deterministic adjoints: the build also indexes
+    # the entries by particle, P2M^t and the position adjoint gather per
+    # particle (no atomics)
+    w4d = ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32 | P2M_DETERMINISTIC)
+
+    def step4d():
+        ops.m2p_interpolate(mesh, f32, pos, out=a32)
+        ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32 | P2M_DETERMINISTIC, weights=w4d, check_diag=False)
+        ops.p2m_project(w4d, a32, out=o32)
+        r = o32 - g32
+        gv, gw = ops.p2m_project_backward(w4d, r, a32, want_vals=True, want_w=True)
+        gpos.zero_()
+        ops.p2m_build_weights_backward(w4d, pos, gw, grad_pos=gpos)
+        ops.m2p_interpolate_backward_binned(w4d, f32, pos, gv, want_mesh=True, grad_pos=gpos)
+
     steps = max(3, a.steps // 2)
     run4f = as_graph(fwd4)
     msf4 = time_loop(run4f, "c4_forward", steps=steps, warmup=2)
     run4 = as_graph(step4)
     ms4 = time_loop(run4, "c4_forward_backward", steps=steps, warmup=2)
     ph4 = phase_times(step4)
+    ms4d = time_loop(as_graph(step4d), "c4_forward_backward_deterministic", steps=steps, warmup=2)
+    ph4d = phase_times(step4d)
     Bf4 = N * (2 * 16 + 8 * C4) + nn * C4 * 8
     Bb4 = Bf4 + N * (8 * C4 + 32) + 2 * nn * C4 * 4
     out["c4"] = {
@@ -274,9 +291,13 @@ def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, grap
         "forward_backward_hbm": hbm_entry(Bb4, ms4), "kernels_ms": {k: round(v, 5) for k, v in ph4.items()},
         "backward_kernels_hbm": {
             "m2p_bwd": hbm_entry(N * (16 + 4 * C4 + 16) + nn * C4 * 4, ph4["m2p_bwd"]),
-            "project_bwd": hbm_entry(nn * C4 * 4 + N * C4 * 4, ph4["project_bwd"])}}
-    log(f"large: c4 forward {msf4:.4f} ms, forward+backward {ms4:.4f} ms")
-    del w4, pos, f32, g32, a32, o32, gpos
+            "project_bwd": hbm_entry(nn * C4 * 4 + N * C4 * 4, ph4["project_bwd"])},
+        "deterministic": {"note": "built with P2M_DETERMINISTIC: P2M^t and the position adjoint gathered per "
+                                  "particle in a fixed order (the build indexes the entries by particle)",
+                          "ms_per_step": round(ms4d, 5), "Mparticles_per_s": round(N / (ms4d * 1e-3) / 1e6, 3),
+                          "kernels_ms": {k: round(v, 5) for k, v in ph4d.items()}}}
+    log(f"large: c4 forward {msf4:.4f} ms, forward+backward {ms4:.4f} ms (deterministic {ms4d:.4f} ms)")
+    del w4, w4d, pos, f32, g32, a32, o32, gpos
 
     # ---- 16.8 M particles, BF16 particle storage: forward and backward
     log("large: 16.8M BF16 workload (generating)")
@@ -317,10 +338,23 @@ def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, grap
         gp5.zero_()
         ops.p2m_build_weights_backward(w5, pos, gw, grad_pos=gp5)
 
+    w5d = ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32 | P2M_DETERMINISTIC)
+
+    def step5d():
+        ops.p2m_build_weights(mesh, c.h, pos, P2M_WEIGHTS_F32 | P2M_DETERMINISTIC, weights=w5d, check_diag=False)
+        ops.p2m_project(w5d, vb, out=o5)
+        ops.m2p_interpolate(mesh, o5, pos, out=back5, bf16_out=True)
+        r = o5 - tgt
+        gv, gw = ops.p2m_project_backward(w5d, r, vb, want_vals=True, want_w=True)
+        gp5.zero_()
+        ops.p2m_build_weights_backward(w5d, pos, gw, grad_pos=gp5)
+
     steps = max(3, a.steps // 4)
     msf5 = time_loop(as_graph(fwd5), "c5_forward", steps=steps, warmup=1)
     ms5 = time_loop(as_graph(step5), "c5_forward_backward", steps=steps, warmup=1)
     ph5 = phase_times(step5)
+    ms5d = time_loop(as_graph(step5d), "c5_forward_backward_deterministic", steps=steps, warmup=1)
+    ph5d = phase_times(step5d)
     Bf5 = N * (2 * 16 + 2 * C5 + 2 * C5) + nn * C5 * 8
     Bb5 = Bf5 + N * (2 * C5 + 4 * C5 + 16 + 16) + nn * C5 * 4
     out["c5"] = {
@@ -335,11 +369,15 @@ def large_workloads(a, dev, time_loop, as_graph, check_replay, phase_times, grap
         "diag": {k: d5[k] for k in ("slow_nodes", "failed_nodes", "rank_deficient", "svd_systems",
                                     "max_gram_cond")},
         "tuning": None if t5 is None else {"options": t5.options, "build_ms_tuned": round(t5.median_ms, 5),
-                                           "build_ms_default": round(t5.default_ms, 5), "cached": t5.cached}}
-    log(f"large: c5 forward {msf5:.4f} ms, forward+backward {ms5:.4f} ms")
+                                           "build_ms_default": round(t5.default_ms, 5), "cached": t5.cached},
+        "deterministic": {"note": "built with P2M_DETERMINISTIC: P2M^t and the position adjoint gathered per "
+                                  "particle in a fixed order (the build indexes the entries by particle)",
+                          "ms_per_step": round(ms5d, 5), "Mparticles_per_s": round(N / (ms5d * 1e-3) / 1e6, 3),
+                          "kernels_ms": {k: round(v, 5) for k, v in ph5d.items()}}}
+    log(f"large: c5 forward {msf5:.4f} ms, forward+backward {ms5:.4f} ms (deterministic {ms5d:.4f} ms)")
     if t5 is not None and tuning is not None:
         tune.apply_options(tuning["options"])
-    del w5, pos, vb, o5, back5, gp5
+    del w5, w5d, pos, vb, o5, back5, gp5
     torch.cuda.synchronize()
     return out
 

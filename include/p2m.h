@@ -467,9 +467,9 @@ int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, 
                                      const double* pos, const void* grad_vals, void* grad_mesh,
                                      double* grad_pos, void* stream);
 
-/* Process-wide tuning knobs for the weight build (performance only; results
- * do not depend on them, "svd_cond" aside, which moves them by rounding
- * only).  Not thread-safe with concurrent builds.
+/* Process-wide tuning knobs of the weight build and of M2P (performance
+ * only; results do not depend on them, "svd_cond" aside, which moves them by
+ * rounding only).  Not thread-safe with concurrent calls.
  *   "bin_scale"  bin width ~ bin_scale * h        (0.25 .. 8,  default 1)
  *   "fast_radius" candidate radius / h of the
  *                register-resident first pass     (1.5 .. 8,   default 2.6)
@@ -482,6 +482,8 @@ int m2p_interpolate_backward_batched(const p2m_batch* b, const void* mesh_vals, 
  *   "svd_cond"   condition estimate of a moment system above which it is
  *                solved by the SVD (see p2m_diag)  (1 .. 1e16, default 1e8;
  *                results change only by rounding)
+ *   "m2p_ppt"    particles per thread of m2p_interpolate (1, 2 or 4,
+ *                default 1; up to 4 channels)
  * Returns P2M_EINVAL for an unknown name or a value out of range. */
 int p2m_set_option(const char* name, double value);
 

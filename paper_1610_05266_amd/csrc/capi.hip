@@ -29,6 +29,7 @@ struct Tuning {
     // goes to the rank-revealing solver: 1e8 keeps Cholesky (with one
     // refinement step) within about eps cond(M) of the minimum-norm answer
     double svd_cond = 1e8;
+    int m2p_ppt = 1;  // particles per thread of the M2P kernel (1, 2 or 4)
 } g_tune;
 
 // Candidate slots per lane for pi (Rf/h)^2 expected candidates, with a margin
@@ -649,6 +650,8 @@ int p2m_set_option(const char* name, double value) {
         g_tune.levels = static_cast<int>(value);
     } else if (!std::strcmp(name, "svd_cond") && value >= 1.0 && value <= 1e16) {
         g_tune.svd_cond = value;
+    } else if (!std::strcmp(name, "m2p_ppt") && (value == 1.0 || value == 2.0 || value == 4.0)) {
+        g_tune.m2p_ppt = static_cast<int>(value);
     } else {
         set_error("unknown option or value out of range: %s=%g", name, value);
         return P2M_EINVAL;
@@ -673,6 +676,8 @@ int p2m_get_option(const char* name, double* value) {
         *value = g_tune.levels;
     } else if (!std::strcmp(name, "svd_cond")) {
         *value = g_tune.svd_cond;
+    } else if (!std::strcmp(name, "m2p_ppt")) {
+        *value = g_tune.m2p_ppt;
     } else if (!std::strcmp(name, "fast_slots")) {
         *value = fast_slots();
     } else {
@@ -864,7 +869,7 @@ int m2p_interpolate(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtyp
     }
     const MeshD m = to_meshd(mesh);
     return m2p(m, nullptr, 1, static_cast<int64_t>(m.nx + 1) * (m.ny + 1), mesh_vals, C, dtype, pos, N, vals,
-               static_cast<hipStream_t>(stream));
+               static_cast<hipStream_t>(stream), g_tune.m2p_ppt);
 }
 
 int p2m_advect(const p2m_mesh* mesh, double* pos, int64_t N, double amp, double dt, void* stream) {
@@ -906,7 +911,7 @@ int m2p_interpolate_batched(const p2m_batch* b, const void* mesh_vals, int C, in
         return P2M_EINVAL;
     }
     return m2p(MeshD{}, b->dsets, b->S(), b->tot.n_nodes, mesh_vals, C, dtype, pos, b->tot.N, vals,
-               static_cast<hipStream_t>(stream));
+               static_cast<hipStream_t>(stream), g_tune.m2p_ppt);
 }
 
 int m2p_interpolate_backward(const p2m_mesh* mesh, const void* mesh_vals, int C, int dtype, const double* pos,

@@ -118,8 +118,9 @@ int m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, const void*
 // mesh box, clamped into the box (advect.hip).
 int advect_midpoint(const MeshD& m, double* pos, int64_t N, double amp, double dt, hipStream_t st,
                     bool periodic);
+// m2p_ppt: particles per thread (1, 2 or 4), a performance option.
 int m2p(const MeshD& m, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C, int dtype,
-        const double* pos, int64_t N, void* vals, hipStream_t st);
+        const double* pos, int64_t N, void* vals, hipStream_t st, int m2p_ppt = 1);
 // M2P adjoint at the particles of a weights handle (built from `pos`): grad_mesh
 // gathered per node through the handle's binning, grad_pos per particle.
 int m2p_backward_binned(const WeightsView& wv, const void* mesh_vals, int C, int dtype, const double* pos,

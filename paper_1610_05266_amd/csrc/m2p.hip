@@ -86,8 +86,9 @@ struct MeshOf {
 // values amplifies their rounding by |a| / (h |grad a|), some hundreds on
 // fine meshes, so an extra rounding of a sum would show).
 // PPT particles per thread, strided by the block size (coalesced): all their
-// position loads are issued before the first is used, then all their mesh
-// gathers, so that a wave keeps PPT times the loads in flight.
+// position loads are issued before the first is used, then all their cells
+// are located and all their mesh gathers issued before the first sum, so
+// that a wave keeps every load of its particles in flight at once.
 template <typename TM, typename TO, int CC, int PPT>
 __global__ void __launch_bounds__(256) k_m2p(MeshOf mo, const TM* __restrict__ mv, int Crt,
                                              const double2* __restrict__ pos, int64_t N, TO* __restrict__ out) {
@@ -100,48 +101,73 @@ __global__ void __launch_bounds__(256) k_m2p(MeshOf mo, const TM* __restrict__ m
         const int64_t mu = base + k * 256;
         p[k] = pos[mu < N ? mu : N - 1];
     }
+    // per particle only what the sums need: the three weights and the
+    // element offsets of the three nodes (32-bit: the host keeps C times the
+    // node count below 2^31), NaN weights marking a particle off its mesh
+    double w[PPT][3];
+    int32_t o[PPT][3];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int64_t mu = base + k * 256;
-        if (mu >= N) break;
         int64_t n0;
-        const MeshD m = mo.get(mu, n0);
-        Loc L = locate_cell(m, p[k]);
-        L.n0 += n0;
-        L.n1 += n0;
-        L.n2 += n0;
-        TM g0[NC], g1[NC], g2[NC];
+        const MeshD m = mo.get(mu < N ? mu : N - 1, n0);
+        const Loc L = locate_cell(m, p[k]);
+        w[k][0] = L.ok ? L.w0 : NAN;
+        w[k][1] = L.w1;
+        w[k][2] = L.w2;
+        o[k][0] = static_cast<int32_t>((L.n0 + n0) * C);
+        o[k][1] = static_cast<int32_t>((L.n1 + n0) * C);
+        o[k][2] = static_cast<int32_t>((L.n2 + n0) * C);
+    }
+    TM g[PPT][3][NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            if (c >= C) break;
-            g0[c] = ldm(mv, L.n0 * C + c);
-            g1[c] = ldm(mv, L.n1 * C + c);
-            g2[c] = ldm(mv, L.n2 * C + c);
-        }
+    for (int k = 0; k < PPT; ++k)
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            if (c >= C) break;
-            const double v = L.w0 * static_cast<double>(g0[c]) + L.w1 * static_cast<double>(g1[c]) +
-                             L.w2 * static_cast<double>(g2[c]);
-            st(out, mu * C + c, static_cast<TM>(L.ok ? v : NAN));
-        }
+        for (int c = 0; c < NC; ++c)
+            if (c < C)
+#pragma unroll
+                for (int t = 0; t < 3; ++t) g[k][t][c] = ldm(mv, o[k][t] + c);
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int64_t mu = base + k * 256;
+        if (mu >= N) continue;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < C) {
+                const double v = w[k][0] * static_cast<double>(g[k][0][c]) + w[k][1] * static_cast<double>(g[k][1][c]) +
+                                 w[k][2] * static_cast<double>(g[k][2][c]);
+                st(out, mu * C + c, static_cast<TM>(v));
+            }
     }
 }
 
-template <typename TM, typename TO>
-void launch_m2p(const MeshOf& m, const void* mv, int C, const double* pos, int64_t N, void* out, hipStream_t s) {
-    constexpr int PPT = 4;
+template <typename TM, typename TO, int PPT>
+void launch_m2p_ppt(const MeshOf& m, const TM* M, int C, const double2* P, int64_t N, TO* O, hipStream_t s) {
     const int blocks = static_cast<int>((N + 256 * PPT - 1) / (256 * PPT));
-    const TM* M = static_cast<const TM*>(mv);
-    const double2* P = reinterpret_cast<const double2*>(pos);
-    TO* O = static_cast<TO*>(out);
     switch (C) {
         case 1: k_m2p<TM, TO, 1, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
         case 2: k_m2p<TM, TO, 2, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
         case 3: k_m2p<TM, TO, 3, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
-        case 4: k_m2p<TM, TO, 4, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
-        default: k_m2p<TM, TO, 0, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
+        default: k_m2p<TM, TO, 4, PPT><<<blocks, 256, 0, s>>>(m, M, C, P, N, O); break;
     }
+}
+
+// ppt: particles per thread (1, 2 or 4; a performance option, the results
+// do not depend on it).  More than four channels: one particle per thread,
+// the gathered values of up to CMAX channels in registers.
+template <typename TM, typename TO>
+void launch_m2p(const MeshOf& m, const void* mv, int C, const double* pos, int64_t N, void* out, int ppt,
+                hipStream_t s) {
+    const TM* M = static_cast<const TM*>(mv);
+    const double2* P = reinterpret_cast<const double2*>(pos);
+    TO* O = static_cast<TO*>(out);
+    if (C > 4) {
+        k_m2p<TM, TO, 0, 1><<<static_cast<int>((N + 255) / 256), 256, 0, s>>>(m, M, C, P, N, O);
+        return;
+    }
+    if (ppt >= 4) launch_m2p_ppt<TM, TO, 4>(m, M, C, P, N, O, s);
+    else if (ppt == 2) launch_m2p_ppt<TM, TO, 2>(m, M, C, P, N, O, s);
+    else launch_m2p_ppt<TM, TO, 1>(m, M, C, P, N, O, s);
 }
 
 // Offsets (relative to an edge's first end) of the ten support slots of a
@@ -421,16 +447,20 @@ int m2p_backward_binned(const WeightsView& wv, const void* mesh_vals, int C, int
 }
 
 int m2p(const MeshD& mesh, const SetDesc* sets, int S, int64_t n_nodes, const void* mesh_vals, int C, int dtype,
-        const double* pos, int64_t N, void* vals, hipStream_t st) {
+        const double* pos, int64_t N, void* vals, hipStream_t st, int m2p_ppt) {
     PhaseTimer _timer(PH_M2P, st);
-    (void)n_nodes;
+    // (the kernel keeps element offsets of the mesh array in 32 bits)
+    if (n_nodes * C >= (int64_t(1) << 31)) {
+        set_error("m2p: %lld mesh nodes x %d channels exceed 2^31 elements", static_cast<long long>(n_nodes), C);
+        return P2M_EINVAL;
+    }
     const MeshOf m{mesh, sets, S};
     if (dtype == P2M_F64)
-        launch_m2p<double, double>(m, mesh_vals, C, pos, N, vals, st);
+        launch_m2p<double, double>(m, mesh_vals, C, pos, N, vals, m2p_ppt, st);
     else if (dtype == P2M_F32)
-        launch_m2p<float, float>(m, mesh_vals, C, pos, N, vals, st);
+        launch_m2p<float, float>(m, mesh_vals, C, pos, N, vals, m2p_ppt, st);
     else
-        launch_m2p<float, uint16_t>(m, mesh_vals, C, pos, N, vals, st);
+        launch_m2p<float, uint16_t>(m, mesh_vals, C, pos, N, vals, m2p_ppt, st);
     P2M_HIP(hipGetLastError());
     return P2M_OK;
 }

@@ -151,3 +151,27 @@ def test_c1_build_options_change_no_bit(c1, fast_radius, region_h, bin_scale, mi
         assert torch.equal(g, r), name
     G = ell_to_csr(got[0].numpy(), got[1].numpy(), got[2].numpy(), c.N)
     assert abs(G - W).max() <= 1e-12
+
+
+@pytest.mark.parametrize("C", [1, 3, 5])
+def test_m2p_particles_per_thread_change_no_bit(C):
+    """The M2P option m2p_ppt (particles per thread) changes only the launch
+    shape: the same bits for 1, 2 and 4 at a particle count that is no
+    multiple of any block's share, and the oracle's values at 1e-12."""
+    rng = np.random.default_rng(C)
+    mesh = wl.MeshSpec(20, 17, 1.0 / 20)
+    N = 3 * 1024 + 77
+    pos = rng.uniform([0.0, 0.0], [1.0, 17.0 / 20], size=(N, 2))
+    mv = rng.normal(size=(mesh.n_nodes, C))
+    ref = o_m2p(OMesh.from_spec(mesh), mv, pos)
+    saved = ops.p2m_get_option("m2p_ppt")
+    outs = []
+    try:
+        for ppt in (1, 2, 4):
+            ops.p2m_set_option("m2p_ppt", ppt)
+            outs.append(ops.m2p_interpolate(mesh, _gpu(mv), _gpu(pos)).cpu())
+    finally:
+        ops.p2m_set_option("m2p_ppt", saved)
+    for o in outs[1:]:
+        assert torch.equal(o, outs[0])
+    assert_close(outs[0].numpy(), ref, 1e-12, "M2P")
