@@ -30,7 +30,7 @@ constexpr int SCAN_THREADS = 256;
 constexpr int SCAN_ITEMS = 8;
 constexpr int SCAN_TILE = SCAN_THREADS * SCAN_ITEMS;
 constexpr int BT = 1024;         // threads of the binning kernels (16 waves)
-constexpr int MAX_SB = 4096;     // super-bins (LDS counters of kernels 1 and 3)
+constexpr int MAX_SB = 8192;     // super-bins (LDS counters of kernels 1 and 3)
 constexpr int MAX_SBS = 14;      // bins per super-bin <= 2^14 (LDS of kernel 4)
 
 // Bin key of particle i (key nbins: outside its set's mesh, or non-finite).
@@ -159,8 +159,10 @@ __device__ __forceinline__ int hist_offset(const int32_t* hist, const int32_t* t
 // consecutive threads write consecutive slots of each run (coalesced).
 // Dynamic LDS: gcur[nsb], lcnt[nsb], lstart[nsb], then sub (position, key,
 // user id) records.
-constexpr int PART_PER_THREAD = 2;  // sub <= PART_PER_THREAD * BT
-
+// PPT records per thread: sub <= PPT * BT.  Consecutive slots of a run are
+// written together only if a sub-chunk holds several particles of each
+// super-bin, so many super-bins (large grids) take the larger sub-chunks.
+template <int PPT>
 __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos, const uint32_t* __restrict__ key,
                                                 BinGeom bg, const int32_t* __restrict__ offs,
                                                 const int32_t* __restrict__ tsum, int ntiles, int sub,
@@ -188,11 +190,11 @@ __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos
         // in registers; only real elements are counted and placed
         // (coordinates as plain doubles: an array of the vector type would be
         // kept in scratch memory across the scan)
-        uint32_t kk[PART_PER_THREAD];
-        int rr[PART_PER_THREAD];
-        double px[PART_PER_THREAD], py[PART_PER_THREAD];
+        uint32_t kk[PPT];
+        int rr[PPT];
+        double px[PPT], py[PPT];
 #pragma unroll
-        for (int j = 0; j < PART_PER_THREAD; ++j) {
+        for (int j = 0; j < PPT; ++j) {
             const int e = min(static_cast<int>(threadIdx.x) + j * BT, n - 1);
             kk[j] = key[b0 + e];
             const double2 p = pos[b0 + e];
@@ -200,14 +202,14 @@ __global__ void __launch_bounds__(BT) k_bin_part(const double2* __restrict__ pos
             py[j] = p.y;
         }
 #pragma unroll
-        for (int j = 0; j < PART_PER_THREAD; ++j) {
+        for (int j = 0; j < PPT; ++j) {
             const int e = threadIdx.x + j * BT;
             rr[j] = e < n ? atomicAdd(&lcnt[kk[j] >> bg.sbs], 1) : 0;
         }
         __syncthreads();
         block_exclusive_scan(lcnt, lstart, nsb, part);
 #pragma unroll
-        for (int j = 0; j < PART_PER_THREAD; ++j) {
+        for (int j = 0; j < PPT; ++j) {
             const int e = threadIdx.x + j * BT;
             if (e < n) {
                 const int sl = lstart[kk[j] >> bg.sbs] + rr[j];
@@ -421,31 +423,43 @@ int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDe
     k_bin_key<<<bg.nch, BT, 0, st>>>(P, sets, S, bg, b.key, b.hist);
     const int ntiles = static_cast<int>(scan_tile_count(nh + 1));
     k_hist_scan<<<ntiles, SCAN_THREADS, 0, st>>>(b.hist, static_cast<int>(nh), b.tsum, diag);
-    // sub-chunk size: as many records as fit beside the counters in 64 KB
-    int sub = PART_PER_THREAD * BT;
-    const int64_t fixed = 12 * static_cast<int64_t>(bg.nsb) + 4 * static_cast<int64_t>(ntiles);
-    while (sub > 256 && fixed + 24 * static_cast<int64_t>(sub) > 65536) sub >>= 1;
-    if (fixed + 24 * static_cast<int64_t>(sub) > 65536) {
-        set_error("binning: too many super-bins (%d)", bg.nsb);
-        return P2M_EINVAL;
-    }
-    const size_t lds = static_cast<size_t>(24) * sub + static_cast<size_t>(fixed);
-    k_bin_part<<<bg.nch, BT, lds, st>>>(P, b.key, bg, b.hist, b.tsum, ntiles, sub,
-                                        reinterpret_cast<double2*>(b.part_pos), b.part_key, b.part_uid);
-    // particles of a super-bin staged in LDS: as many as fit beside the bin
-    // starts in 160 KB (16-byte position, user id, three 16-bit fields)
-    const int M = 1 << bg.sbs;
-    const int64_t room = 163840 - 2048 - 4 * static_cast<int64_t>(M + 1);
-    const int cap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(room / 26, 0) & ~int64_t(7), 65535));
-    const size_t llds = static_cast<size_t>(cap) * 26 + 4 * static_cast<size_t>(M + 1);
     // dynamic LDS beyond 64 KB must be allowed once per function
+    constexpr int64_t LDS_MAX = 163840 - 2048;
     static std::once_flag lds_once;
     static hipError_t lds_err = hipSuccess;
     std::call_once(lds_once, [] {
         lds_err = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bin_local),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 163840 - 2048);
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX);
+        if (lds_err == hipSuccess)
+            lds_err = hipFuncSetAttribute(reinterpret_cast<const void*>(k_bin_part<4>),
+                                          hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX);
     });
     P2M_HIP(lds_err);
+    // sub-chunk size: two records per thread within 64 KB while the
+    // super-bins are few; with more super-bins than half a sub-chunk, four
+    // per thread in up to 160 KB
+    const int64_t fixed = 12 * static_cast<int64_t>(bg.nsb) + 4 * static_cast<int64_t>(ntiles);
+    const bool wide = 2 * static_cast<int64_t>(bg.nsb) > 2 * BT && fixed + 24 * 4 * BT <= LDS_MAX;
+    int sub = (wide ? 4 : 2) * BT;
+    const int64_t lds_cap = wide ? LDS_MAX : 65536;
+    while (sub > 256 && fixed + 24 * static_cast<int64_t>(sub) > lds_cap) sub >>= 1;
+    if (fixed + 24 * static_cast<int64_t>(sub) > lds_cap) {
+        set_error("binning: too many super-bins (%d)", bg.nsb);
+        return P2M_EINVAL;
+    }
+    const size_t lds = static_cast<size_t>(24) * sub + static_cast<size_t>(fixed);
+    if (wide)
+        k_bin_part<4><<<bg.nch, BT, lds, st>>>(P, b.key, bg, b.hist, b.tsum, ntiles, sub,
+                                               reinterpret_cast<double2*>(b.part_pos), b.part_key, b.part_uid);
+    else
+        k_bin_part<2><<<bg.nch, BT, lds, st>>>(P, b.key, bg, b.hist, b.tsum, ntiles, sub,
+                                               reinterpret_cast<double2*>(b.part_pos), b.part_key, b.part_uid);
+    // particles of a super-bin staged in LDS: as many as fit beside the bin
+    // starts in 160 KB (16-byte position, user id, three 16-bit fields)
+    const int M = 1 << bg.sbs;
+    const int64_t room = LDS_MAX - 4 * static_cast<int64_t>(M + 1);
+    const int cap = static_cast<int>(std::min<int64_t>(std::max<int64_t>(room / 26, 0) & ~int64_t(7), 65535));
+    const size_t llds = static_cast<size_t>(cap) * 26 + 4 * static_cast<size_t>(M + 1);
     k_bin_local<<<bg.nsb, BT, llds, st>>>(bg, b.hist, b.tsum, cap, reinterpret_cast<const double2*>(b.part_pos), b.part_key,
                                           b.part_uid, b.rank, b.start, reinterpret_cast<double2*>(b.pos_s), b.perm,
                                           diag);
