@@ -436,10 +436,10 @@ int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDe
     });
     P2M_HIP(lds_err);
     // sub-chunk size: two records per thread within 64 KB while the
-    // super-bins are few; with more super-bins than half a sub-chunk, four
-    // per thread in up to 160 KB
+    // super-bins are few; with more super-bins than threads, up to four per
+    // thread in up to 160 KB (as many as fit beside the counters)
     const int64_t fixed = 12 * static_cast<int64_t>(bg.nsb) + 4 * static_cast<int64_t>(ntiles);
-    const bool wide = 2 * static_cast<int64_t>(bg.nsb) > 2 * BT && fixed + 24 * 4 * BT <= LDS_MAX;
+    const bool wide = bg.nsb > BT;
     int sub = (wide ? 4 : 2) * BT;
     const int64_t lds_cap = wide ? LDS_MAX : 65536;
     while (sub > 256 && fixed + 24 * static_cast<int64_t>(sub) > lds_cap) sub >>= 1;

@@ -20,29 +20,50 @@ constexpr int TB = 256;        // threads per block
 constexpr int TSCAN = 2048;    // entries per block of the count scan
 constexpr int TSCAN_PT = TSCAN / TB;
 
-// Slot of node `node` (handle numbering) and its row length.
-__device__ __forceinline__ int64_t node_row(const WeightsView& w, int64_t node, int& n, int32_t& orow) {
-    const SetDesc& sd = w.sets[set_search(w.S, node, [&](int s) { return w.sets[s].n0; })];
-    const int64_t ln = node - sd.n0;
-    const int64_t slot = node_slot(sd, static_cast<int>(ln % (sd.m.nx + 1)), static_cast<int>(ln / (sd.m.nx + 1)));
-    n = row_len(w.meta[slot]);
-    orow = n > KMAX ? w.orow[slot] : 0;
-    return slot;
+// Entry e of the grid over all entries: k = e / n_slots, slot = e % n_slots
+// for e < KMAX n_slots (the ELL arrays), then the overflow rows' entries
+// (k >= KMAX of the slots whose rows are long).  Writes the entry's user id,
+// its node and its entry index; false when there is no such entry.  One
+// thread per entry, so that the atomics of a row's entries run side by side
+// instead of one after another.
+__device__ __forceinline__ bool entry_of(const WeightsView& w, int64_t e, int32_t& u, int64_t& node, int64_t& ei) {
+    const int64_t ns = w.n_slots;
+    int64_t slot;
+    int k;
+    if (e < KMAX * ns) {
+        k = static_cast<int>(e / ns);
+        slot = e - k * ns;
+    } else {
+        // overflow entries are visited through their slot: e - KMAX ns runs
+        // over (k - KMAX) * n_slots + slot
+        const int64_t r = e - KMAX * ns;
+        k = KMAX + static_cast<int>(r / ns);
+        slot = r - (k - KMAX) * ns;
+    }
+    const uint32_t meta = w.meta[slot];
+    const int n = row_len(meta);
+    if (k >= n) return false;
+    const SetDesc& sd = w.sets[set_search(w.S, slot / TILE_N, [&](int s) { return w.sets[s].t0; })];
+    int i, j;
+    if (!slot_ij(sd, slot, i, j)) return false;
+    node = ij_node(sd, i, j);
+    const int32_t orow = k >= KMAX ? w.orow[slot] : 0;
+    u = k < KMAX ? w.idx[k * ns + slot] : w.oidx[ovf_at(w.n_ovf, orow, k)];
+    ei = entry_at(ns, w.n_ovf, orow, slot, k);
+    return true;
 }
 
-// User id of entry k of a row.
-__device__ __forceinline__ int32_t entry_uid(const WeightsView& w, int64_t slot, int32_t orow, int k) {
-    return k < KMAX ? w.idx[k * w.n_slots + slot] : w.oidx[ovf_at(w.n_ovf, orow, k)];
-}
+// Entries of the grid: every ELL entry, then (KROW - KMAX) per slot for the
+// long rows (empty unless a row is long).
+inline int64_t entry_grid(const WeightsView& w) { return static_cast<int64_t>(KROW) * w.n_slots; }
 
 // 1. entries per particle
-__global__ void __launch_bounds__(TB) k_tcount(WeightsView w, int32_t* __restrict__ cnt) {
-    const int64_t node = static_cast<int64_t>(blockIdx.x) * TB + threadIdx.x;
-    if (node >= w.n_nodes) return;
-    int n;
-    int32_t orow;
-    const int64_t slot = node_row(w, node, n, orow);
-    for (int k = 0; k < n; ++k) atomicAdd(&cnt[entry_uid(w, slot, orow, k)], 1);
+__global__ void __launch_bounds__(256) k_tcount(WeightsView w, int64_t ne, int32_t* __restrict__ cnt) {
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= ne) return;
+    int32_t u;
+    int64_t node, ei;
+    if (entry_of(w, e, u, node, ei)) atomicAdd(&cnt[u], 1);
 }
 
 // Exclusive prefix of v over the block and the block total.
@@ -119,20 +140,17 @@ __global__ void __launch_bounds__(TB) k_tscan_add(int32_t* __restrict__ ptr, int
 }
 
 // 3. every entry to its particle's range (order within a range: arrival)
-__global__ void __launch_bounds__(TB) k_tfill(WeightsView w, const int32_t* __restrict__ ptr,
+__global__ void __launch_bounds__(TB) k_tfill(WeightsView w, int64_t ne, const int32_t* __restrict__ ptr,
                                              int32_t* __restrict__ cur, int32_t* __restrict__ ent,
                                              int32_t* __restrict__ nodes) {
-    const int64_t node = static_cast<int64_t>(blockIdx.x) * TB + threadIdx.x;
-    if (node >= w.n_nodes) return;
-    int n;
-    int32_t orow;
-    const int64_t slot = node_row(w, node, n, orow);
-    for (int k = 0; k < n; ++k) {
-        const int32_t u = entry_uid(w, slot, orow, k);
-        const int32_t at = ptr[u] + atomicAdd(&cur[u], 1);
-        ent[at] = static_cast<int32_t>(entry_at(w.n_slots, w.n_ovf, orow, slot, k));
-        nodes[at] = static_cast<int32_t>(node);
-    }
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * TB + threadIdx.x;
+    if (e >= ne) return;
+    int32_t u;
+    int64_t node, ei;
+    if (!entry_of(w, e, u, node, ei)) return;
+    const int32_t at = ptr[u] + atomicAdd(&cur[u], 1);
+    ent[at] = static_cast<int32_t>(ei);
+    nodes[at] = static_cast<int32_t>(node);
 }
 
 // 4. each particle's range sorted by entry index (a handful of entries)
@@ -231,11 +249,12 @@ int build_transpose(const WeightsView& w, int32_t* cnt, int32_t* ptr, int32_t* e
     }
     int rc = fill_bytes_zero(cnt, sizeof(int32_t) * w.N, st);
     if (rc) return rc;
-    k_tcount<<<grid(w.n_nodes), TB, 0, st>>>(w, cnt);
+    const int64_t ne = entry_grid(w);
+    k_tcount<<<grid(ne), TB, 0, st>>>(w, ne, cnt);
     k_tscan_tiles<<<static_cast<unsigned>(nt), TB, 0, st>>>(cnt, w.N, ptr, tsum);
     k_tscan_totals<<<1, TB, 0, st>>>(tsum, static_cast<int>(nt));
     k_tscan_add<<<grid(w.N + 1), TB, 0, st>>>(ptr, w.N, tsum, static_cast<int>(nt), cnt);
-    k_tfill<<<grid(w.n_nodes), TB, 0, st>>>(w, ptr, cnt, ent, nodes);
+    k_tfill<<<grid(ne), TB, 0, st>>>(w, ne, ptr, cnt, ent, nodes);
     k_tsort<<<grid(w.N), TB, 0, st>>>(ptr, w.N, ent, nodes);
     P2M_HIP(hipGetLastError());
     return P2M_OK;

@@ -188,3 +188,23 @@ def test_c3_full_batch_quadratic_exact_and_sampled_oracle(c3):
         c = sets[s]
         n0, n1, p0, p1 = b.node_offsets[s], b.node_offsets[s + 1], b.offsets[s], b.offsets[s + 1]
         assert_close(out[p0:p1], o_m2p(OMesh.from_spec(c.mesh), m64[n0:n1], c.pos), 1e-13, f"C3 set {s} M2P")
+
+
+@pytest.mark.parametrize("bin_scale", [0.75, 0.5])
+def test_c3_finer_binning_grids_change_no_bit(c3, bin_scale):
+    """Finer binning grids over the 64-set batch (thousands of super-bins:
+    the partition pass's LDS plan and the local pass's staging at their
+    limits) give the default grid's projection bit for bit."""
+    sets, b, pos, vals = c3
+    P = _g(pos)
+    v = _g(vals, torch.float32)
+    ref = ops.p2m_project(ops.p2m_build_weights_batched(b, P, P2M_WEIGHTS_F32), v)
+    saved = ops.p2m_get_option("bin_scale")
+    try:
+        ops.p2m_set_option("bin_scale", bin_scale)
+        w = ops.p2m_build_weights_batched(b, P, P2M_WEIGHTS_F32)
+        print(f"C3 bin_scale={bin_scale}: {w.diag()['slow_nodes']} slow nodes", flush=True)
+        got = ops.p2m_project(w, v)
+    finally:
+        ops.p2m_set_option("bin_scale", saved)
+    assert torch.equal(got, ref)
