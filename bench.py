@@ -38,6 +38,10 @@ WEIGHTS_FLOP_INTERIOR = 2100.0
 WEIGHTS_FLOP_CLOSURE = 700.0
 TRAFFIC_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
                             "roundtrip_256x256_1M_hbm_traffic.md")
+# FP64 instruction counts of the build kernels (rocprofv3 SQ counters):
+# 64 x (2 FMA + ADD + MUL) wave instructions per launch
+COUNTERS_FILE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                             "build_kernels_256x256_1M_counters.md")
 
 
 def parse(argv=None):
@@ -89,6 +93,23 @@ def source_digest():
     return h.hexdigest()[:16]
 
 
+def counted_flops(kernel):
+    """FP64 flops per launch of `kernel` counted by the committed rocprofv3
+    instruction counters, or None when there are none or the sources changed
+    since they were taken."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    import re
+
+    m = re.search(r"^source_digest: (\w+)$", text, flags=re.M)
+    if not m or m.group(1) != source_digest():
+        return None
+    m = re.search(r"^fp64_flop_per_launch " + re.escape(kernel.replace(" ", "")) + r" (\d+)$", text, flags=re.M)
+    return int(m.group(1)) if m else None
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, calibrated on a plain copy), or None
@@ -102,7 +123,7 @@ def measured_traffic(kernel):
     m = re.search(r"^source_digest: (\w+)$", text, flags=re.M)
     if not m or m.group(1) != source_digest():
         return None
-    m = re.search(r"^traffic_bytes_per_launch " + re.escape(kernel) + r" (\d+)$", text, flags=re.M)
+    m = re.search(r"^traffic_bytes_per_launch " + re.escape(kernel.replace(" ", "")) + r" (\d+)$", text, flags=re.M)
     return int(m.group(1)) if m else None
 
 
@@ -796,9 +817,17 @@ def main(argv=None):
     # per-kernel rooflines (times: the library's events around each launch)
     b32 = N * (2 * 16 + (4 + 4) * C) + nn * C * (4 + 4)
     ni, nc = diag["interior_nodes"], diag["closure_nodes"]
+    # the fast pass's Delaunay work depends on the algorithm: its FP64 work
+    # per launch as counted by the committed instruction counters (lane
+    # operations issued on this workload), the hand model when they are stale
+    fast_name = f"k_build_fast<{int(ops.p2m_get_option('fast_slots'))}>"
+    fast_counted = counted_flops(fast_name)
+    fast_work = fast_counted if fast_counted else FAST_FLOP_INTERIOR * ni + FAST_FLOP_RING * nc
+    fast_unit = (f"{fast_counted / nn:.0f} FP64 flop/node counted (rocprofv3 FP64 instruction counters)"
+                 if fast_counted else
+                 f"{FAST_FLOP_INTERIOR:g} FP64 flop/interior node, {FAST_FLOP_RING:g}/ring node (model)")
     kern = {
-        "k_build_fast": ("alu", FAST_FLOP_INTERIOR * ni + FAST_FLOP_RING * nc, ph32["build_fast"],
-                         f"{FAST_FLOP_INTERIOR:g} FP64 flop/interior node, {FAST_FLOP_RING:g}/ring node"),
+        "k_build_fast": ("alu", fast_work, ph32["build_fast"], fast_unit),
         "k_weights": ("alu", WEIGHTS_FLOP_INTERIOR * ni + WEIGHTS_FLOP_CLOSURE * nc, ph32["k_weights"],
                       f"{WEIGHTS_FLOP_INTERIOR:g} FP64 flop/interior node, {WEIGHTS_FLOP_CLOSURE:g}/closure node"),
         "binning": ("hbm", 36.0 * N, ph32["bin"], "36 B/particle (16 in, 20 out)"),
@@ -806,12 +835,19 @@ def main(argv=None):
         "k_m2p": ("hbm", N * (16 + 4 * C) + nn * 4 * C, ph32["m2p"], "positions + mesh in + values out, FP32"),
     }
     kernels = {}
+    counted_names = {"k_build_fast": fast_name, "k_weights": "k_weights<false, StoreRows>"}
     for name, (bound, work, ms, per_unit) in kern.items():
         if bound == "alu":
             ach = work / (ms * 1e-3) / 1e12
             kernels[name] = {"bound": "alu", "achieved": round(ach, 4), "peak": FP64_VECTOR_PEAK_TFS,
                              "unit": "TFLOP/s", "frac": round(ach / FP64_VECTOR_PEAK_TFS, 5),
                              "avg_launch_ms": round(ms, 5), "algorithmic_per_launch": f"{work:.4g} flop ({per_unit})"}
+            cf = counted_flops(counted_names[name])
+            if cf:
+                # every FP64 lane operation the kernel issued (redundant lanes
+                # of a quad included): its FP64 issue rate against the peak
+                kernels[name]["counted_fp64_flop_per_launch"] = cf
+                kernels[name]["counted_frac"] = round(cf / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFS, 5)
         else:
             ach = work / (ms * 1e-3) / 1e9
             kernels[name] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -822,7 +858,7 @@ def main(argv=None):
     roof["kernel"] = dom
     # the counter summary names template instances: the fast pass by its
     # candidate slots per lane
-    prof_name = f"k_build_fast<{int(ops.p2m_get_option('fast_slots'))}>" if dom == "k_build_fast" else dom
+    prof_name = fast_name if dom == "k_build_fast" else dom
     roof["traffic"] = measured_traffic(prof_name)
     b64 = N * (2 * 16 + (8 + 8) * C) + nn * C * (8 + 8)
     rt = {"algorithmic_bytes": b32, "achieved_GBs": round(b32 / (ms32_head * 1e-3) / 1e9, 2),
