@@ -22,37 +22,56 @@ struct Loc {
     bool lower, ok;
 };
 
-__device__ __forceinline__ Loc locate_cell(const MeshD& m, double2 p) {
-    Loc L;
+// The particle's cell and local coordinates (the first half of locating
+// it), and the triangle's nodes and weights from them (the second half):
+// split so that a kernel can keep the first and finish later with the same
+// bits.
+struct Cell {
+    int64_t n00;  // the cell's lower-left node (index within the set)
+    double xi, eta;
+    bool lower, ok;
+};
+
+__device__ __forceinline__ Cell cell_of(const MeshD& m, double2 p) {
+    Cell c;
     const double x1 = add_rn(m.x0, mul_rn(static_cast<double>(m.nx), m.H));
     const double y1 = add_rn(m.y0, mul_rn(static_cast<double>(m.ny), m.H));
-    L.ok = p.x >= m.x0 && p.x <= x1 && p.y >= m.y0 && p.y <= y1;
+    c.ok = p.x >= m.x0 && p.x <= x1 && p.y >= m.y0 && p.y <= y1;
     const double tx = (p.x - m.x0) / m.H;
     const double ty = (p.y - m.y0) / m.H;
     // clamp in floating point first (NaN and huge values included)
     const int i = static_cast<int>(fmax(fmin(floor(tx), static_cast<double>(m.nx - 1)), 0.0));
     const int j = static_cast<int>(fmax(fmin(floor(ty), static_cast<double>(m.ny - 1)), 0.0));
-    const double xi = tx - i, eta = ty - j;
+    c.xi = tx - i;
+    c.eta = ty - j;
+    c.n00 = static_cast<int64_t>(j) * (m.nx + 1) + i;
+    c.lower = c.xi >= c.eta;
+    return c;
+}
+
+__device__ __forceinline__ Loc loc_of(const MeshD& m, const Cell& c) {
+    Loc L;
     const int64_t s = m.nx + 1;
-    const int64_t n00 = static_cast<int64_t>(j) * s + i;
-    L.lower = xi >= eta;
-    if (L.lower) {
-        L.n0 = n00;
-        L.n1 = n00 + 1;
-        L.n2 = n00 + s + 1;
-        L.w0 = 1.0 - xi;
-        L.w1 = xi - eta;
-        L.w2 = eta;
+    L.ok = c.ok;
+    L.lower = c.lower;
+    L.n0 = c.n00;
+    if (c.lower) {
+        L.n1 = c.n00 + 1;
+        L.n2 = c.n00 + s + 1;
+        L.w0 = 1.0 - c.xi;
+        L.w1 = c.xi - c.eta;
+        L.w2 = c.eta;
     } else {
-        L.n0 = n00;
-        L.n1 = n00 + s + 1;
-        L.n2 = n00 + s;
-        L.w0 = 1.0 - eta;
-        L.w1 = xi;
-        L.w2 = eta - xi;
+        L.n1 = c.n00 + s + 1;
+        L.n2 = c.n00 + s;
+        L.w0 = 1.0 - c.eta;
+        L.w1 = c.xi;
+        L.w2 = c.eta - c.xi;
     }
     return L;
 }
+
+__device__ __forceinline__ Loc locate_cell(const MeshD& m, double2 p) { return loc_of(m, cell_of(m, p)); }
 
 __device__ __forceinline__ double ldm(const double* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float ldm(const float* p, int64_t i) { return p[i]; }
@@ -312,12 +331,17 @@ void launch_m2p_qcsf(const MeshD& m, const int32_t* idx, const double* coef, con
     }
 }
 
-// grad_mesh += phi_i(r_mu) g_mu (atomics); grad_pos[mu] += sum_c g_mu,c grad u_c
-template <typename TM>
-__global__ void __launch_bounds__(256) k_m2p_bwd(MeshOf mo, const TM* __restrict__ mv, int C,
+// grad_mesh += phi_i(r_mu) g_mu (atomics); grad_pos[mu] += sum_c g_mu,c grad u_c.
+// For a fixed channel count (CC > 0) every load of the particle (its
+// upstream gradient and the nine mesh values) is issued before the first
+// sum, as in the forward kernel.
+template <typename TM, int CC>
+__global__ void __launch_bounds__(256) k_m2p_bwd(MeshOf mo, const TM* __restrict__ mv, int Crt,
                                                  const double2* __restrict__ pos, int64_t N,
                                                  const TM* __restrict__ gv, TM* __restrict__ gmesh,
                                                  double2* __restrict__ gpos) {
+    constexpr int NC = CC > 0 ? CC : 1;
+    const int C = CC > 0 ? CC : Crt;
     const int64_t mu = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (mu >= N) return;
     int64_t n0;
@@ -331,18 +355,46 @@ __global__ void __launch_bounds__(256) k_m2p_bwd(MeshOf mo, const TM* __restrict
     const double dxi0 = L.lower ? -1.0 : 0.0, dxi1 = 1.0, dxi2 = L.lower ? 0.0 : -1.0;
     const double det0 = L.lower ? 0.0 : -1.0, det1 = L.lower ? -1.0 : 0.0, det2 = 1.0;
     double gx = 0.0, gy = 0.0;
-    for (int c = 0; c < C; ++c) {
-        const TM g = gv[mu * C + c];
-        if (gmesh) {
-            atomicAdd(&gmesh[L.n0 * C + c], static_cast<TM>(L.w0) * g);
-            atomicAdd(&gmesh[L.n1 * C + c], static_cast<TM>(L.w1) * g);
-            atomicAdd(&gmesh[L.n2 * C + c], static_cast<TM>(L.w2) * g);
-        }
+    if constexpr (CC > 0) {
+        TM g[NC], v[3][NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) g[c] = gv[mu * C + c];
         if (gpos) {
-            const double v0 = ldm(mv, L.n0 * C + c), v1 = ldm(mv, L.n1 * C + c), v2 = ldm(mv, L.n2 * C + c);
-            const double gd = static_cast<double>(g);
-            gx += gd * (dxi0 * v0 + dxi1 * v1 + dxi2 * v2);
-            gy += gd * (det0 * v0 + det1 * v1 + det2 * v2);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                v[0][c] = mv[L.n0 * C + c];
+                v[1][c] = mv[L.n1 * C + c];
+                v[2][c] = mv[L.n2 * C + c];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            if (gmesh) {
+                atomicAdd(&gmesh[L.n0 * C + c], static_cast<TM>(L.w0) * g[c]);
+                atomicAdd(&gmesh[L.n1 * C + c], static_cast<TM>(L.w1) * g[c]);
+                atomicAdd(&gmesh[L.n2 * C + c], static_cast<TM>(L.w2) * g[c]);
+            }
+            if (gpos) {
+                const double v0 = v[0][c], v1 = v[1][c], v2 = v[2][c];
+                const double gd = static_cast<double>(g[c]);
+                gx += gd * (dxi0 * v0 + dxi1 * v1 + dxi2 * v2);
+                gy += gd * (det0 * v0 + det1 * v1 + det2 * v2);
+            }
+        }
+    } else {
+        for (int c = 0; c < C; ++c) {
+            const TM g = gv[mu * C + c];
+            if (gmesh) {
+                atomicAdd(&gmesh[L.n0 * C + c], static_cast<TM>(L.w0) * g);
+                atomicAdd(&gmesh[L.n1 * C + c], static_cast<TM>(L.w1) * g);
+                atomicAdd(&gmesh[L.n2 * C + c], static_cast<TM>(L.w2) * g);
+            }
+            if (gpos) {
+                const double v0 = ldm(mv, L.n0 * C + c), v1 = ldm(mv, L.n1 * C + c), v2 = ldm(mv, L.n2 * C + c);
+                const double gd = static_cast<double>(g);
+                gx += gd * (dxi0 * v0 + dxi1 * v1 + dxi2 * v2);
+                gy += gd * (det0 * v0 + det1 * v1 + det2 * v2);
+            }
         }
     }
     if (gpos) {
@@ -353,6 +405,19 @@ __global__ void __launch_bounds__(256) k_m2p_bwd(MeshOf mo, const TM* __restrict
     }
 }
 
+template <typename TM>
+void launch_m2p_bwd(const MeshOf& m, const TM* mv, int C, const double2* P, int64_t N, const TM* gv, TM* gmesh,
+                    double2* gpos, hipStream_t st) {
+    const int blocks = static_cast<int>((N + 255) / 256);
+    switch (C) {
+        case 1: k_m2p_bwd<TM, 1><<<blocks, 256, 0, st>>>(m, mv, C, P, N, gv, gmesh, gpos); break;
+        case 2: k_m2p_bwd<TM, 2><<<blocks, 256, 0, st>>>(m, mv, C, P, N, gv, gmesh, gpos); break;
+        case 3: k_m2p_bwd<TM, 3><<<blocks, 256, 0, st>>>(m, mv, C, P, N, gv, gmesh, gpos); break;
+        case 4: k_m2p_bwd<TM, 4><<<blocks, 256, 0, st>>>(m, mv, C, P, N, gv, gmesh, gpos); break;
+        default: k_m2p_bwd<TM, 0><<<blocks, 256, 0, st>>>(m, mv, C, P, N, gv, gmesh, gpos); break;
+    }
+}
+
 // grad_mesh of M2P as a gather: a quad per mesh node, nodes in the 8 x 8
 // tiles of a weights handle built from the same positions.  The node takes
 // every particle of the bins around its (up to four) cells, with one bin of
@@ -360,48 +425,130 @@ __global__ void __launch_bounds__(256) k_m2p_bwd(MeshOf mo, const TM* __restrict
 // side), locates it exactly as the forward does and adds its weight for
 // this node: the sum over the particles whose triangle holds the node, with
 // no atomics, in a fixed order (deterministic).  Lane l takes the particles
-// l, l + 4, ... of each bin row of the window; FP64 sums, one rounding.
+// l, l + 4, ... of each bin row of the node's window; FP64 sums, one
+// rounding.
+//
+// The windows of a tile's nodes overlap (each particle lies in the windows
+// of about nine nodes), so the block first locates every particle of the
+// union of its nodes' windows once, into LDS (cell, local coordinates, user
+// id), and the nodes then read those; a union too large for the LDS arrays
+// (dense clusters, very fine bins) makes the block locate per node instead.
+// Both ways visit the same particles in the same order with the same
+// arithmetic: the sums are equal bit for bit.
+constexpr int MB_ROWS = 128;   // bin rows of a tile's window held in LDS
+constexpr int MB_CAP = 2048;   // particles of a tile's window held in LDS
+constexpr int MB_WAVE = 64;
+
 template <typename TG, int CC>
 __global__ void __launch_bounds__(256) k_m2p_bwd_gather(WeightsView wv, const TG* __restrict__ gv, int Crt,
                                                         TG* __restrict__ gmesh) {
     constexpr int NC = CC > 0 ? CC : CMAX;
     const int C = CC > 0 ? CC : Crt;
-    const int lane = threadIdx.x & 3;
+    __shared__ double s_xi[MB_CAP], s_eta[MB_CAP];
+    __shared__ int32_t s_code[MB_CAP], s_uid[MB_CAP];
+    __shared__ int32_t s_off[MB_ROWS + 1], s_rs[MB_ROWS];
+    const int tid = threadIdx.x;
+    const int lane = tid & 3;
     const int64_t tile = blockIdx.x;
     const SetDesc& sd = wv.sets[set_search(wv.S, tile, [&](int s) { return wv.sets[s].t0; })];
-    const int64_t slot = tile * TILE_N + (threadIdx.x >> 2);
-    int i, j;
-    if (!slot_ij(sd, slot, i, j)) return;  // the four lanes of a node leave together
     const MeshD m = sd.m;
     const Grid g = sd.g;
-    const int64_t lnode = static_cast<int64_t>(j) * (m.nx + 1) + i;
     const int32_t* start = wv.start + sd.b0;
+    // the union of the tile's node windows, in bins
+    int tx, ty;
+    tile_xy(sd, static_cast<int>(tile - sd.t0), tx, ty);
+    const int wx0 = max((8 * tx - 1) * g.kb - 1, 0), wx1 = min((8 * tx + 8) * g.kb + 1, g.nbx);
+    const int wy0 = max((8 * ty - 1) * g.kb - 1, 0), wy1 = min((8 * ty + 8) * g.kb + 1, g.nby);
+    const int nrow = wy1 - wy0;
+    // cell codes n00 * 2 + lower need the set's nodes below 2^30
+    bool staged = nrow <= MB_ROWS && static_cast<int64_t>(m.nx + 1) * (m.ny + 1) < (int64_t(1) << 30);
+    if (staged) {
+        // row lengths, prefixed over the rows (two waves, one row a lane)
+        int len = 0, rs = 0;
+        if (tid < nrow) {
+            const int row = (wy0 + tid) * g.nbx;
+            rs = start[row + wx0];
+            len = start[row + wx1] - rs;
+            s_rs[tid] = rs;
+        }
+        int inc = len;
+#pragma unroll
+        for (int d = 1; d < MB_WAVE; d <<= 1) {
+            const int o = __shfl_up(inc, d);
+            if ((tid & (MB_WAVE - 1)) >= d) inc += o;
+        }
+        if (tid == MB_WAVE - 1) s_off[MB_ROWS] = inc;  // the first wave's total
+        __syncthreads();
+        if (tid >= MB_WAVE && tid < 2 * MB_WAVE) inc += s_off[MB_ROWS];
+        if (tid < MB_ROWS) s_off[tid + 1] = inc;
+        if (tid == 0) s_off[0] = 0;
+        __syncthreads();
+        staged = s_off[nrow] <= MB_CAP;  // uniform over the block
+    }
+    if (staged) {
+        const int total = s_off[nrow];
+        for (int f = tid; f < total; f += 256) {
+            int lo = 0, hi = nrow - 1;  // the row holding f
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= f) lo = mid;
+                else hi = mid - 1;
+            }
+            const int64_t sp = s_rs[lo] + (f - s_off[lo]);
+            const Cell c = cell_of(m, wv.pos_s[sp]);
+            s_xi[f] = c.xi;
+            s_eta[f] = c.eta;
+            s_code[f] = c.ok ? static_cast<int32_t>(c.n00 * 2 + (c.lower ? 1 : 0)) : -1;
+            s_uid[f] = wv.perm[sp];
+        }
+        __syncthreads();
+    }
+    const int64_t slot = tile * TILE_N + (tid >> 2);
+    int i, j;
+    if (!slot_ij(sd, slot, i, j)) return;  // the four lanes of a node leave together
+    const int64_t lnode = static_cast<int64_t>(j) * (m.nx + 1) + i;
     const int bx0 = max((i - 1) * g.kb - 1, 0), bx1 = min((i + 1) * g.kb + 1, g.nbx);
     const int by0 = max((j - 1) * g.kb - 1, 0), by1 = min((j + 1) * g.kb + 1, g.nby);
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
+    auto add = [&](const Loc& L, int64_t u) {
+        if (!L.ok) return;
+        const double w = L.n0 == lnode ? L.w0 : (L.n1 == lnode ? L.w1 : (L.n2 == lnode ? L.w2 : 0.0));
+        if (w == 0.0) return;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < C) acc[c] += w * static_cast<double>(gv[u * C + c]);
+    };
     for (int by = by0; by < by1; ++by) {
         const int s0 = start[by * g.nbx + bx0], s1 = start[by * g.nbx + bx1];
-        for (int s = s0 + lane; s < s1; s += 4) {
-            const Loc L = locate_cell(m, wv.pos_s[s]);
-            if (!L.ok) continue;
-            const double w = L.n0 == lnode ? L.w0 : (L.n1 == lnode ? L.w1 : (L.n2 == lnode ? L.w2 : 0.0));
-            if (w == 0.0) continue;
-            const int64_t u = wv.perm[s];
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-                if (c < C) acc[c] += w * static_cast<double>(gv[u * C + c]);
+        if (staged) {
+            const int r = by - wy0;
+            const int fo = s_off[r] + (s0 - s_rs[r]);
+            for (int s = s0 + lane; s < s1; s += 4) {
+                const int f = fo + (s - s0);
+                const int code = s_code[f];
+                Cell c;
+                c.ok = code >= 0;
+                c.n00 = code >> 1;
+                c.lower = (code & 1) != 0;
+                c.xi = s_xi[f];
+                c.eta = s_eta[f];
+                add(loc_of(m, c), s_uid[f]);
+            }
+        } else {
+            for (int s = s0 + lane; s < s1; s += 4) add(locate_cell(m, wv.pos_s[s]), wv.perm[s]);
         }
     }
     const int64_t node = sd.n0 + lnode;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        if (c >= C) break;
-        double v = acc[c];
-        v += lane_xor<4>(v, 1);
-        v += lane_xor<4>(v, 2);
-        if (lane == (c & 3)) gmesh[node * C + c] = static_cast<TG>(v);
+        if (c < C) {
+            double v = acc[c];
+            v += lane_xor<4>(v, 1);
+            v += lane_xor<4>(v, 2);
+            if (lane == (c & 3)) gmesh[node * C + c] = static_cast<TG>(v);
+        }
     }
 }
 
@@ -431,16 +578,15 @@ int m2p_backward_binned(const WeightsView& wv, const void* mesh_vals, int C, int
     }
     if (grad_pos) {
         // the position gradient per particle (its own entry, no atomics)
-        const int blocks = static_cast<int>((wv.N + 255) / 256);
         const MeshOf m{MeshD{}, wv.sets, wv.S};
         const double2* P = reinterpret_cast<const double2*>(pos);
         double2* GP = reinterpret_cast<double2*>(grad_pos);
         if (dtype == P2M_F64)
-            k_m2p_bwd<double><<<blocks, 256, 0, st>>>(m, static_cast<const double*>(mesh_vals), C, P, wv.N,
-                                                      static_cast<const double*>(grad_vals), nullptr, GP);
+            launch_m2p_bwd<double>(m, static_cast<const double*>(mesh_vals), C, P, wv.N,
+                                   static_cast<const double*>(grad_vals), nullptr, GP, st);
         else
-            k_m2p_bwd<float><<<blocks, 256, 0, st>>>(m, static_cast<const float*>(mesh_vals), C, P, wv.N,
-                                                     static_cast<const float*>(grad_vals), nullptr, GP);
+            launch_m2p_bwd<float>(m, static_cast<const float*>(mesh_vals), C, P, wv.N,
+                                  static_cast<const float*>(grad_vals), nullptr, GP, st);
         P2M_HIP(hipGetLastError());
     }
     return P2M_OK;
@@ -486,7 +632,6 @@ int m2p_backward(const MeshD& mesh, const SetDesc* sets, int S, int64_t n_nodes,
                  int dtype, const double* pos, int64_t N, const void* grad_vals, void* grad_mesh, double* grad_pos,
                  hipStream_t st) {
     PhaseTimer _timer(PH_M2P_BWD, st);
-    const int blocks = static_cast<int>((N + 255) / 256);
     const int64_t nn = n_nodes;
     const MeshOf m{mesh, sets, S};
     const double2* P = reinterpret_cast<const double2*>(pos);
@@ -496,17 +641,15 @@ int m2p_backward(const MeshD& mesh, const SetDesc* sets, int S, int64_t n_nodes,
             int rc = fill_bytes_zero(grad_mesh, sizeof(double) * nn * C, st);
             if (rc) return rc;
         }
-        k_m2p_bwd<double><<<blocks, 256, 0, st>>>(m, static_cast<const double*>(mesh_vals), C, P, N,
-                                                  static_cast<const double*>(grad_vals),
-                                                  static_cast<double*>(grad_mesh), GP);
+        launch_m2p_bwd<double>(m, static_cast<const double*>(mesh_vals), C, P, N,
+                               static_cast<const double*>(grad_vals), static_cast<double*>(grad_mesh), GP, st);
     } else {
         if (grad_mesh) {
             int rc = fill_bytes_zero(grad_mesh, sizeof(float) * nn * C, st);
             if (rc) return rc;
         }
-        k_m2p_bwd<float><<<blocks, 256, 0, st>>>(m, static_cast<const float*>(mesh_vals), C, P, N,
-                                                 static_cast<const float*>(grad_vals),
-                                                 static_cast<float*>(grad_mesh), GP);
+        launch_m2p_bwd<float>(m, static_cast<const float*>(mesh_vals), C, P, N,
+                              static_cast<const float*>(grad_vals), static_cast<float*>(grad_mesh), GP, st);
     }
     P2M_HIP(hipGetLastError());
     return P2M_OK;

@@ -87,3 +87,32 @@ def test_binned_m2p_adjoint_of_a_batch():
         om = OMesh.from_spec(c.mesh)
         n0, n1, p0, p1 = b.node_offsets[s], b.node_offsets[s + 1], offs[s], offs[s + 1]
         assert_close(gm[n0:n1], m2p_matrix(om, c.pos).T @ gb[p0:p1], 1e-12, f"set {s}")
+
+
+def test_binned_m2p_adjoint_in_dense_clusters():
+    """Clusters dense enough that some tiles' windows hold more particles
+    than the kernel keeps in LDS (those tiles locate per node) beside sparse
+    tiles that stage their windows: both kinds against the oracle, and the
+    same bits on every call."""
+    c = wl.cluster_void_cloud(32, 24000, seed=74)
+    om = OMesh.from_spec(c.mesh)
+    # particles per tile window (cells of the tile and one around it, plus a
+    # bin of margin): the densest exceed the 2048 held in LDS, the sparsest
+    # do not
+    ij = np.floor(c.pos / om.H).astype(int)
+    counts = []
+    for ty in range((om.ny + 1 + 7) // 8):
+        for tx in range((om.nx + 1 + 7) // 8):
+            inx = (ij[:, 0] >= 8 * tx - 2) & (ij[:, 0] <= 8 * tx + 8)
+            iny = (ij[:, 1] >= 8 * ty - 2) & (ij[:, 1] <= 8 * ty + 8)
+            counts.append(int((inx & iny).sum()))
+    assert max(counts) > 2 * 2048 and min(counts) < 2048 // 2
+    print(f"[gpu] binned M2P adjoint, clusters N={c.N} window counts {min(counts)}..{max(counts)}", flush=True)
+    rng = np.random.default_rng(75)
+    gb = rng.normal(size=(c.N, 2))
+    P = _g(c.pos)
+    w = ops.p2m_build_weights(c.mesh, c.h, P, 0, check_diag=False)
+    gm1, _ = ops.m2p_interpolate_backward_binned(w, None, P, _g(gb), want_mesh=True)
+    gm2, _ = ops.m2p_interpolate_backward_binned(w, None, P, _g(gb), want_mesh=True)
+    assert torch.equal(gm1, gm2)
+    assert_close(gm1.cpu().numpy(), m2p_matrix(om, c.pos).T @ gb, 1e-12, "binned M2P adjoint, clusters")
