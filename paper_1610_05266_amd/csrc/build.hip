@@ -552,9 +552,13 @@ struct QuadSource {
     }
     __device__ int uid(int t) const { return perm[sorted(t)]; }
     __device__ bool global() const { return false; }
+    // the disk (c, r) inside the disk (q, Rf), with margins far above the
+    // rounding of either side: |c - q| + r (1 + 1e-9) <= Rf (1 - 1e-12),
+    // compared squared (one square root fewer per step)
     __device__ bool certify(double cx, double cy, double r) const {
         const double dx = cx - q.x, dy = cy - q.y;
-        return sqrt(dx * dx + dy * dy) + r * (1.0 + 1e-9) <= Rf * (1.0 - 1e-12);
+        const double u = Rf * (1.0 - 1e-12) - r * (1.0 + 1e-9);
+        return u >= 0.0 && dx * dx + dy * dy <= u * u;
     }
     __device__ int nearest(double2 c, int exclude, double& d2best, double2& pbest) {
         int best = -1;
@@ -598,36 +602,76 @@ struct QuadSource {
         int bt = -1;
         double bn = 0.0, bc = 1.0;
         bool amb = false;
+        if constexpr (NS <= 7) {
+            // The key starts at a sentinel (num, cr) = (128 R^2, 0) that every
+            // candidate on the left beats by more than the error bound
+            // (0 - 128 R^2 cr < -128 R^2 crmin < -errS), so no test for "no
+            // winner yet" is needed, and the tests are combined without
+            // short circuits: the same decisions in fewer instructions (with
+            // more slots the compiler keeps too many of them live)
+            bn = 128.0 * R2;
+            bc = 0.0;
 #pragma unroll
-        for (int s = 0; s < NS; ++s) {
-            const int t = cand(s);  // slots past n hold index 0
-            const double2 b = lpos[t];
-            const double Bx = b.x - v.x, By = b.y - v.y;
-            const double cr = nx * Bx + ny * By;
-            const double num = Bx * (Bx - Ax) + By * (By - Ay);
-            const bool ok = s < n && t != iv && t != ia;
-            const bool left = ok && cr > crmin;
-            const double d = num * bc - bn * cr;
-            amb = amb || (ok && fabs(cr) <= crmin) || (left && bt >= 0 && fabs(d) <= errS);
-            const bool take = left && (bt < 0 || d < -errS);
-            bt = take ? t : bt;
-            bn = take ? num : bn;
-            bc = take ? cr : bc;
-            // at most two candidates' loads in flight: the registers of all
-            // of them would cost the fourth wave per SIMD
-            if (s & 1) __builtin_amdgcn_sched_barrier(0);
-        }
+            for (int s = 0; s < NS; ++s) {
+                const int t = cand(s);  // slots past n hold index 0
+                const double2 b = lpos[t];
+                const double Bx = b.x - v.x, By = b.y - v.y;
+                const double cr = nx * Bx + ny * By;
+                const double num = Bx * (Bx - Ax) + By * (By - Ay);
+                const bool ok = (s < n) & (t != iv) & (t != ia);
+                const bool left = ok & (cr > crmin);
+                const double d = num * bc - bn * cr;
+                amb |= (ok & (fabs(cr) <= crmin)) | (left & (fabs(d) <= errS));
+                const bool take = left & (d < -errS);
+                bt = take ? t : bt;
+                bn = take ? num : bn;
+                bc = take ? cr : bc;
+                if (s & 1) __builtin_amdgcn_sched_barrier(0);
+            }
 #pragma unroll
-        for (int m = 1; m < QL; m <<= 1) {
-            const int ot = lane_xor<QL>(bt, m);
-            const double on = lane_xor<QL>(bn, m), oc = lane_xor<QL>(bc, m);
-            const double d = on * bc - bn * oc;
-            const bool other = ot >= 0 && ot != bt;
-            amb = amb || (other && bt >= 0 && fabs(d) <= errS);
-            const bool take = other && (bt < 0 || d < -errS);
-            bt = take ? ot : bt;
-            bn = take ? on : bn;
-            bc = take ? oc : bc;
+            for (int m = 1; m < QL; m <<= 1) {
+                const int ot = lane_xor<QL>(bt, m);
+                const double on = lane_xor<QL>(bn, m), oc = lane_xor<QL>(bc, m);
+                const double d = on * bc - bn * oc;
+                const bool other = (ot >= 0) & (ot != bt);
+                amb |= other & (fabs(d) <= errS);
+                const bool take = other & (d < -errS);
+                bt = take ? ot : bt;
+                bn = take ? on : bn;
+                bc = take ? oc : bc;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const int t = cand(s);  // slots past n hold index 0
+                const double2 b = lpos[t];
+                const double Bx = b.x - v.x, By = b.y - v.y;
+                const double cr = nx * Bx + ny * By;
+                const double num = Bx * (Bx - Ax) + By * (By - Ay);
+                const bool ok = s < n && t != iv && t != ia;
+                const bool left = ok && cr > crmin;
+                const double d = num * bc - bn * cr;
+                amb = amb || (ok && fabs(cr) <= crmin) || (left && bt >= 0 && fabs(d) <= errS);
+                const bool take = left && (bt < 0 || d < -errS);
+                bt = take ? t : bt;
+                bn = take ? num : bn;
+                bc = take ? cr : bc;
+                // at most two candidates' loads in flight: the registers of all
+                // of them would cost the fourth wave per SIMD
+                if (s & 1) __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+            for (int m = 1; m < QL; m <<= 1) {
+                const int ot = lane_xor<QL>(bt, m);
+                const double on = lane_xor<QL>(bn, m), oc = lane_xor<QL>(bc, m);
+                const double d = on * bc - bn * oc;
+                const bool other = ot >= 0 && ot != bt;
+                amb = amb || (other && bt >= 0 && fabs(d) <= errS);
+                const bool take = other && (bt < 0 || d < -errS);
+                bt = take ? ot : bt;
+                bn = take ? on : bn;
+                bc = take ? oc : bc;
+            }
         }
         int am = amb ? 1 : 0;
         am |= lane_xor<QL>(am, 1);
