@@ -108,13 +108,20 @@ void launch_project_list(const WeightsView& wv, const int32_t* slow, const TW* w
 }
 
 // grad_vals[j][c] += w * grad_mesh[i][c] (atomics) ; grad_w[k][i] = sum_c grad_mesh[i][c] vals[j][c]
-// (grad_w in mesh-node order [KROW][n_nodes]).  One thread per row slot.
-template <typename TV, typename TW, typename TG>
+// (grad_w in mesh-node order [KROW][n_nodes]; entries past the row are
+// zero).  A quad per row slot, in the tiles' slot order as the forward
+// projection takes them: lane l takes entries l, l + 4, ..., so that four
+// times as many rows are walked at once; for a fixed channel count (CC > 0)
+// an entry's loads are all issued before its sums.
+template <typename TV, typename TW, typename TG, int CC>
 __global__ void __launch_bounds__(256) k_project_bwd(WeightsView wv, const TW* __restrict__ w,
-                                                     const TW* __restrict__ ow, const TG* __restrict__ gmesh, int C,
+                                                     const TW* __restrict__ ow, const TG* __restrict__ gmesh, int Crt,
                                                      const TV* __restrict__ vals, TG* __restrict__ gvals,
                                                      double* __restrict__ gw) {
-    const int64_t slot = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    constexpr int NC = CC > 0 ? CC : CMAX;
+    const int C = CC > 0 ? CC : Crt;
+    const int64_t slot = static_cast<int64_t>(blockIdx.x) * TILE_N + (threadIdx.x >> 2);
+    const int lane = threadIdx.x & 3;
     if (slot >= wv.n_slots) return;
     const SetDesc& sd = wv.sets[set_search(wv.S, slot / TILE_N, [&](int s) { return wv.sets[s].t0; })];
     int i, j;
@@ -122,25 +129,48 @@ __global__ void __launch_bounds__(256) k_project_bwd(WeightsView wv, const TW* _
     const int64_t node = ij_node(sd, i, j);
     const int64_t ns = wv.n_slots, nn = wv.n_nodes;
     const int cnt = row_len(wv.meta[slot]);
-    TG g[CMAX];
-    for (int c = 0; c < C; ++c) g[c] = gmesh[node * C + c];
+    TG g[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (c < C) g[c] = gmesh[node * C + c];
     const int32_t r = cnt > KMAX ? wv.orow[slot] : 0;
-    for (int k = 0; k < cnt; ++k) {
+    for (int k = lane; k < cnt; k += 4) {
         const bool main = k < KMAX;
         const int64_t at = main ? k * ns + slot : ovf_at(wv.n_ovf, r, k);
         const int64_t p = main ? wv.idx[at] : wv.oidx[at];
         if (gvals) {
             const TG wk = static_cast<TG>(main ? w[at] : ow[at]);
-            for (int c = 0; c < C; ++c) atomicAdd(&gvals[p * C + c], wk * g[c]);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < C) atomicAdd(&gvals[p * C + c], wk * g[c]);
         }
         if (gw) {
+            double v[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < C) v[c] = static_cast<double>(ld(vals, p * C + c));
             double s = 0.0;
-            for (int c = 0; c < C; ++c) s += static_cast<double>(g[c]) * static_cast<double>(ld(vals, p * C + c));
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (c < C) s += static_cast<double>(g[c]) * v[c];
             gw[k * nn + node] = s;
         }
     }
     if (gw)
-        for (int k = cnt; k < KROW; ++k) gw[k * nn + node] = 0.0;
+        for (int k = cnt + lane; k < KROW; k += 4) gw[k * nn + node] = 0.0;
+}
+
+template <typename TV, typename TW, typename TG>
+void launch_project_bwd(const WeightsView& wv, const TW* w, const TW* ow, const TG* gmesh, int C, const TV* vals,
+                        TG* gvals, double* gw, hipStream_t st) {
+    const int blocks = static_cast<int>(wv.n_slots / TILE_N);
+    switch (C) {
+        case 1: k_project_bwd<TV, TW, TG, 1><<<blocks, 256, 0, st>>>(wv, w, ow, gmesh, C, vals, gvals, gw); break;
+        case 2: k_project_bwd<TV, TW, TG, 2><<<blocks, 256, 0, st>>>(wv, w, ow, gmesh, C, vals, gvals, gw); break;
+        case 3: k_project_bwd<TV, TW, TG, 3><<<blocks, 256, 0, st>>>(wv, w, ow, gmesh, C, vals, gvals, gw); break;
+        case 4: k_project_bwd<TV, TW, TG, 4><<<blocks, 256, 0, st>>>(wv, w, ow, gmesh, C, vals, gvals, gw); break;
+        default: k_project_bwd<TV, TW, TG, 0><<<blocks, 256, 0, st>>>(wv, w, ow, gmesh, C, vals, gvals, gw); break;
+    }
 }
 
 }  // namespace
@@ -175,7 +205,6 @@ int project_listed(const WeightsView& wv, const int32_t* slow, const void* vals,
 int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dtype, const void* vals,
                      void* grad_vals, double* grad_w, hipStream_t st) {
     PhaseTimer _timer(PH_PROJECT_BWD, st);
-    const int blocks = static_cast<int>((wv.n_slots + 255) / 256);
     if (dtype != P2M_F64 && !wv.w32) {
         set_error("p2m_project_backward: FP32/BF16 needs a handle built with P2M_WEIGHTS_F32");
         return P2M_EINVAL;
@@ -193,22 +222,22 @@ int project_backward(const WeightsView& wv, const void* grad_mesh, int C, int dt
             int rc = fill_bytes_zero(grad_vals, sizeof(double) * wv.N * C, st);
             if (rc) return rc;
         }
-        k_project_bwd<double, double, double><<<blocks, 256, 0, st>>>(
-            wv, wv.w64, wv.ow64, static_cast<const double*>(grad_mesh), C,
-            static_cast<const double*>(vals), static_cast<double*>(grad_vals), grad_w);
+        launch_project_bwd<double, double, double>(wv, wv.w64, wv.ow64, static_cast<const double*>(grad_mesh), C,
+                                                   static_cast<const double*>(vals),
+                                                   static_cast<double*>(grad_vals), grad_w, st);
     } else {
         if (grad_vals) {
             int rc = fill_bytes_zero(grad_vals, sizeof(float) * wv.N * C, st);
             if (rc) return rc;
         }
         if (dtype == P2M_F32)
-            k_project_bwd<float, float, float><<<blocks, 256, 0, st>>>(
-                wv, wv.w32, wv.ow32, static_cast<const float*>(grad_mesh), C,
-                static_cast<const float*>(vals), static_cast<float*>(grad_vals), grad_w);
+            launch_project_bwd<float, float, float>(wv, wv.w32, wv.ow32, static_cast<const float*>(grad_mesh), C,
+                                                    static_cast<const float*>(vals),
+                                                    static_cast<float*>(grad_vals), grad_w, st);
         else
-            k_project_bwd<uint16_t, float, float><<<blocks, 256, 0, st>>>(
-                wv, wv.w32, wv.ow32, static_cast<const float*>(grad_mesh), C,
-                static_cast<const uint16_t*>(vals), static_cast<float*>(grad_vals), grad_w);
+            launch_project_bwd<uint16_t, float, float>(wv, wv.w32, wv.ow32, static_cast<const float*>(grad_mesh), C,
+                                                       static_cast<const uint16_t*>(vals),
+                                                       static_cast<float*>(grad_vals), grad_w, st);
     }
     P2M_HIP(hipGetLastError());
     return P2M_OK;
