@@ -24,6 +24,9 @@ import time
 METRIC = "P2M+M2P round-trip Mparticles/s + % HBM roofline; FP32-mixed vs FP64 at ≤1e-5"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_VECTOR_PEAK_TFS = 78.6    # MI355X FP64 vector
+# VALU issue: 256 CUs x 4 SIMDs, one wave64 instruction per SIMD every 4
+# cycles at 2.4 GHz
+VALU_ISSUE_PEAK_G = 256 * 4 * 2.4 / 4
 # algorithmic FP64 work of the weight build per node (moment assembly of the
 # three edge systems, Gram/Cholesky/solve with one refinement, weights)
 # algorithmic FP64 work of the weight build per node, by kernel:
@@ -107,6 +110,22 @@ def counted_flops(kernel):
     if not m or m.group(1) != source_digest():
         return None
     m = re.search(r"^fp64_flop_per_launch " + re.escape(kernel.replace(" ", "")) + r" (\d+)$", text, flags=re.M)
+    return int(m.group(1)) if m else None
+
+
+def counted_valu(kernel):
+    """VALU wave instructions per launch of `kernel` from the committed
+    instruction counters (SQ_INSTS_VALU), or None when stale or absent."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    import re
+
+    m = re.search(r"^source_digest: (\w+)$", text, flags=re.M)
+    if not m or m.group(1) != source_digest():
+        return None
+    m = re.search(r"^valu_insts_per_launch " + re.escape(kernel.replace(" ", "")) + r" (\d+)$", text, flags=re.M)
     return int(m.group(1)) if m else None
 
 
@@ -848,6 +867,16 @@ def main(argv=None):
                 # of a quad included): its FP64 issue rate against the peak
                 kernels[name]["counted_fp64_flop_per_launch"] = cf
                 kernels[name]["counted_frac"] = round(cf / (ms * 1e-3) / 1e12 / FP64_VECTOR_PEAK_TFS, 5)
+            cv = counted_valu(counted_names[name])
+            if cv:
+                # VALU instruction issue against the chip's issue rate: the
+                # bound these kernels meet first (most of their instructions
+                # are integer, compare, select and exchange work)
+                rate = cv / (ms * 1e-3) / 1e9
+                kernels[name]["valu_issue"] = {"achieved": round(rate, 2), "peak": VALU_ISSUE_PEAK_G,
+                                               "unit": "G wave-instructions/s",
+                                               "frac": round(rate / VALU_ISSUE_PEAK_G, 5),
+                                               "per_launch": cv}
         else:
             ach = work / (ms * 1e-3) / 1e9
             kernels[name] = {"bound": "hbm", "achieved": round(ach, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
