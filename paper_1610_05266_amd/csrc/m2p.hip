@@ -435,8 +435,9 @@ void launch_m2p_bwd(const MeshOf& m, const TM* mv, int C, const double2* P, int6
 // (dense clusters, very fine bins) makes the block locate per node instead.
 // Both ways visit the same particles in the same order with the same
 // arithmetic: the sums are equal bit for bit.
-constexpr int MB_ROWS = 128;   // bin rows of a tile's window held in LDS
-constexpr int MB_CAP = 2048;   // particles of a tile's window held in LDS
+constexpr int MB_ROWS = 64;    // bin rows of a tile's window held in LDS
+constexpr int MB_CAP = 1920;   // particles of a tile's window held in LDS
+constexpr int MB_PT = (MB_CAP + 255) / 256;  // of them per thread
 constexpr int MB_WAVE = 64;
 
 template <typename TG, int CC>
@@ -446,7 +447,10 @@ __global__ void __launch_bounds__(256) k_m2p_bwd_gather(WeightsView wv, const TG
     const int C = CC > 0 ? CC : Crt;
     __shared__ double s_xi[MB_CAP], s_eta[MB_CAP];
     __shared__ int32_t s_code[MB_CAP], s_uid[MB_CAP];
-    __shared__ int32_t s_off[MB_ROWS + 1], s_rs[MB_ROWS];
+    __shared__ int32_t s_off[MB_ROWS + 1];
+    // start of bin column b of window row r: the lower window bounds of the
+    // tile's eight node columns (b < 8), then their upper bounds
+    __shared__ int32_t s_st[MB_ROWS][16];
     const int tid = threadIdx.x;
     const int lane = tid & 3;
     const int64_t tile = blockIdx.x;
@@ -457,19 +461,26 @@ __global__ void __launch_bounds__(256) k_m2p_bwd_gather(WeightsView wv, const TG
     // the union of the tile's node windows, in bins
     int tx, ty;
     tile_xy(sd, static_cast<int>(tile - sd.t0), tx, ty);
-    const int wx0 = max((8 * tx - 1) * g.kb - 1, 0), wx1 = min((8 * tx + 8) * g.kb + 1, g.nbx);
+    const int i0 = 8 * tx;
+    auto col_lo = [&](int i) { return max((i - 1) * g.kb - 1, 0); };
+    auto col_hi = [&](int i) { return min((i + 1) * g.kb + 1, g.nbx); };
+    const int wx0 = col_lo(i0), wx1 = col_hi(i0 + 7);
     const int wy0 = max((8 * ty - 1) * g.kb - 1, 0), wy1 = min((8 * ty + 8) * g.kb + 1, g.nby);
     const int nrow = wy1 - wy0;
     // cell codes n00 * 2 + lower need the set's nodes below 2^30
     bool staged = nrow <= MB_ROWS && static_cast<int64_t>(m.nx + 1) * (m.ny + 1) < (int64_t(1) << 30);
     if (staged) {
-        // row lengths, prefixed over the rows (two waves, one row a lane)
-        int len = 0, rs = 0;
+        // the bounds of every node window in every window row, and the rows'
+        // lengths prefixed (the first wave, one row a lane)
+        for (int e = tid; e < nrow * 16; e += 256) {
+            const int r = e >> 4, b = e & 15;
+            const int i = i0 + (b & 7);
+            s_st[r][b] = start[(wy0 + r) * g.nbx + (b < 8 ? col_lo(i) : col_hi(i))];
+        }
+        int len = 0;
         if (tid < nrow) {
             const int row = (wy0 + tid) * g.nbx;
-            rs = start[row + wx0];
-            len = start[row + wx1] - rs;
-            s_rs[tid] = rs;
+            len = start[row + wx1] - start[row + wx0];
         }
         int inc = len;
 #pragma unroll
@@ -477,29 +488,43 @@ __global__ void __launch_bounds__(256) k_m2p_bwd_gather(WeightsView wv, const TG
             const int o = __shfl_up(inc, d);
             if ((tid & (MB_WAVE - 1)) >= d) inc += o;
         }
-        if (tid == MB_WAVE - 1) s_off[MB_ROWS] = inc;  // the first wave's total
-        __syncthreads();
-        if (tid >= MB_WAVE && tid < 2 * MB_WAVE) inc += s_off[MB_ROWS];
-        if (tid < MB_ROWS) s_off[tid + 1] = inc;
+        if (tid < MB_WAVE) s_off[tid + 1] = inc;
         if (tid == 0) s_off[0] = 0;
         __syncthreads();
         staged = s_off[nrow] <= MB_CAP;  // uniform over the block
     }
     if (staged) {
+        // every particle of the window located once; a thread's particles
+        // have all their loads in flight before the first is located
         const int total = s_off[nrow];
-        for (int f = tid; f < total; f += 256) {
+        int64_t sp[MB_PT];
+#pragma unroll
+        for (int k = 0; k < MB_PT; ++k) {
+            const int f = tid + 256 * k;
             int lo = 0, hi = nrow - 1;  // the row holding f
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
                 if (s_off[mid] <= f) lo = mid;
                 else hi = mid - 1;
             }
-            const int64_t sp = s_rs[lo] + (f - s_off[lo]);
-            const Cell c = cell_of(m, wv.pos_s[sp]);
+            sp[k] = f < total ? s_st[lo][0] + (f - s_off[lo]) : -1;
+        }
+        double2 pp[MB_PT];
+        int32_t uu[MB_PT];
+#pragma unroll
+        for (int k = 0; k < MB_PT; ++k) {
+            pp[k] = wv.pos_s[sp[k] >= 0 ? sp[k] : 0];
+            uu[k] = wv.perm[sp[k] >= 0 ? sp[k] : 0];
+        }
+#pragma unroll
+        for (int k = 0; k < MB_PT; ++k) {
+            const int f = tid + 256 * k;
+            if (f >= total) continue;
+            const Cell c = cell_of(m, pp[k]);
             s_xi[f] = c.xi;
             s_eta[f] = c.eta;
             s_code[f] = c.ok ? static_cast<int32_t>(c.n00 * 2 + (c.lower ? 1 : 0)) : -1;
-            s_uid[f] = wv.perm[sp];
+            s_uid[f] = uu[k];
         }
         __syncthreads();
     }
@@ -507,7 +532,7 @@ __global__ void __launch_bounds__(256) k_m2p_bwd_gather(WeightsView wv, const TG
     int i, j;
     if (!slot_ij(sd, slot, i, j)) return;  // the four lanes of a node leave together
     const int64_t lnode = static_cast<int64_t>(j) * (m.nx + 1) + i;
-    const int bx0 = max((i - 1) * g.kb - 1, 0), bx1 = min((i + 1) * g.kb + 1, g.nbx);
+    const int bx0 = col_lo(i), bx1 = col_hi(i);
     const int by0 = max((j - 1) * g.kb - 1, 0), by1 = min((j + 1) * g.kb + 1, g.nby);
     double acc[NC];
 #pragma unroll
@@ -520,11 +545,12 @@ __global__ void __launch_bounds__(256) k_m2p_bwd_gather(WeightsView wv, const TG
         for (int c = 0; c < NC; ++c)
             if (c < C) acc[c] += w * static_cast<double>(gv[u * C + c]);
     };
-    for (int by = by0; by < by1; ++by) {
-        const int s0 = start[by * g.nbx + bx0], s1 = start[by * g.nbx + bx1];
-        if (staged) {
+    if (staged) {
+        const int bl = i - i0;
+        for (int by = by0; by < by1; ++by) {
             const int r = by - wy0;
-            const int fo = s_off[r] + (s0 - s_rs[r]);
+            const int s0 = s_st[r][bl], s1 = s_st[r][8 + bl];
+            const int fo = s_off[r] + (s0 - s_st[r][0]);
             for (int s = s0 + lane; s < s1; s += 4) {
                 const int f = fo + (s - s0);
                 const int code = s_code[f];
@@ -536,7 +562,10 @@ __global__ void __launch_bounds__(256) k_m2p_bwd_gather(WeightsView wv, const TG
                 c.eta = s_eta[f];
                 add(loc_of(m, c), s_uid[f]);
             }
-        } else {
+        }
+    } else {
+        for (int by = by0; by < by1; ++by) {
+            const int s0 = start[by * g.nbx + bx0], s1 = start[by * g.nbx + bx1];
             for (int s = s0 + lane; s < s1; s += 4) add(locate_cell(m, wv.pos_s[s]), wv.perm[s]);
         }
     }
