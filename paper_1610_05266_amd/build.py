@@ -86,6 +86,50 @@ def build(jobs: int = 8, debug: bool = False) -> str:
     return LIB
 
 
+# sources whose host code the sanitizer build instruments: the C ABI's
+# argument checks, handles and workspaces (the rest is linked as built)
+ASAN_SOURCES = ["capi.hip", "util.hip", "profile.hip"]
+ASAN_DIR = os.path.join(OBJDIR, "asan")
+ASAN_LIB = os.path.join(ASAN_DIR, "libp2m_asan.so")
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's shared AddressSanitizer runtime."""
+    r = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("the AddressSanitizer runtime of the HIP compiler was not found")
+    return path
+
+
+def build_host_asan(jobs: int = 8) -> str:
+    """libp2m with AddressSanitizer in the host code of ASAN_SOURCES (device
+    code and the other sources as in build()), for checking the C ABI's host
+    paths on a CPU; load it with the runtime from asan_runtime() preloaded."""
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    host_asan = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+    def one(src: str) -> str:
+        if src in ASAN_SOURCES:
+            out = os.path.join(ASAN_DIR, os.path.splitext(src)[0] + ".o")
+            cmd = [hipcc(), *flags(False), *host_asan, "-c", os.path.join(CSRC, src), "-o", out]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+            return out
+        out = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+        return out if os.path.exists(out) else compile_one(src, False)
+
+    with cf.ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
+        objs = list(ex.map(one, SOURCES))
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Xarch_host", "-fsanitize=address",
+           "-Xarch_host", "-shared-libsan", *objs, "-o", ASAN_LIB]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
+    return ASAN_LIB
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=min(8, os.cpu_count() or 1))
