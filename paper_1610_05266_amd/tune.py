@@ -213,3 +213,80 @@ def autotune(build: Callable[[], object], probe: Callable[[object], "object"], k
     data[key] = {"options": res.options, "median_ms": res.median_ms, "default_ms": res.default_ms}
     _store(path, data)
     return res
+
+
+def _median_time(run: Callable[[], object], repeats: int) -> float:
+    import torch
+
+    run()
+    times = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    return statistics.median(times)
+
+
+def choose(variants: Dict[str, Callable[[], None]], run: Callable[[], object], result: Callable[[], list],
+           key: str, cache_path: Optional[str] = None, repeats: int = 5, retune: bool = False,
+           graph: bool = True, time_of: Optional[Callable[[Callable[[], object]], float]] = None) -> dict:
+    """Pick the fastest of alternative ways to compute one result.
+
+    ``variants`` maps a name to a setter that selects that way (an option,
+    a form); the first is the default.  ``run()`` computes with the current
+    selection; ``result()`` returns the tensors every variant must reproduce
+    bit for bit (a variant that does not is rejected).  Each variant is
+    timed on graph replays of ``run`` (``time_of`` replaces the timer, for
+    tests); another variant replaces the default only when it wins by more
+    than NOISE in a second, interleaved measurement.  The choice is cached
+    under ``key`` and left selected.  Returns {"choice", "ms", "default_ms"}."""
+    import torch
+
+    path = cache_path or default_cache_path()
+    data = _load(path)
+    names = list(variants)
+    if not retune and key in data and data[key].get("choice") in variants:
+        ent = data[key]
+        variants[ent["choice"]]()
+        return dict(ent, cached=True)
+    timer = time_of or (lambda fn: _median_time(_timer(fn, graph), repeats))
+    variants[names[0]]()
+    run()
+    ref = [t.clone() for t in result()]
+    times = {}
+    for name in names:
+        variants[name]()
+        run()
+        if not all(torch.equal(a, b) for a, b in zip(result(), ref)):
+            continue
+        times[name] = timer(run)
+    best = min(times, key=times.get)
+    t_def = times[names[0]]
+    if best != names[0]:
+        tb, td = [], []
+        for _ in range(3):
+            variants[best]()
+            tb.append(timer(run))
+            variants[names[0]]()
+            td.append(timer(run))
+        if statistics.median(tb) < statistics.median(td) * (1.0 - NOISE):
+            times[best], t_def = statistics.median(tb), statistics.median(td)
+        else:
+            best = names[0]
+    variants[best]()
+    ent = {"choice": best, "ms": times[best], "default_ms": t_def}
+    data[key] = ent
+    _store(path, data)
+    return dict(ent, cached=False)
+
+
+def m2p_variants() -> Dict[str, Callable[[], None]]:
+    """The particles-per-thread settings of m2p_interpolate (results do not
+    depend on them), the library default first."""
+    from . import ops
+
+    return {f"m2p_ppt={v}": (lambda v=v: ops.p2m_set_option("m2p_ppt", float(v))) for v in (1, 2, 4)}

@@ -55,6 +55,35 @@ def test_cache_round_trip_and_keys(tmp_path):
         del os.environ[tune.CACHE_ENV]
 
 
+def test_choose_takes_the_fastest_equal_variant(tmp_path):
+    """The variant chooser on the CPU: a synthetic cost per variant, one
+    variant whose result differs (rejected however fast), the noise margin,
+    and the cache."""
+    import torch
+
+    state = {"v": "a"}
+    cost = {"a": 1.0, "b": 0.7, "c": 0.5, "d": 0.995}
+    out = torch.zeros(4)
+
+    def run():
+        out.fill_(1.0 if state["v"] != "c" else 2.0)   # "c" computes something else
+
+    variants = {k: (lambda k=k: state.__setitem__("v", k)) for k in ("a", "b", "c", "d")}
+    path = str(tmp_path / "choose.json")
+    res = tune.choose(variants, run, lambda: [out], "k1", cache_path=path, time_of=lambda fn: cost[state["v"]])
+    assert res["choice"] == "b" and not res["cached"] and state["v"] == "b"
+    assert res["ms"] == pytest.approx(0.7) and res["default_ms"] == pytest.approx(1.0)
+    # a gain inside the noise margin keeps the default
+    only = {k: variants[k] for k in ("a", "d")}
+    assert tune.choose(only, run, lambda: [out], "k2", cache_path=path,
+                       time_of=lambda fn: cost[state["v"]])["choice"] == "a"
+    # the cache answers without timing, and selects the cached variant
+    state["v"] = "a"
+    again = tune.choose(variants, run, lambda: [out], "k1", cache_path=path, time_of=None)
+    assert again["cached"] and again["choice"] == "b" and state["v"] == "b"
+    assert set(tune.m2p_variants()) == {"m2p_ppt=1", "m2p_ppt=2", "m2p_ppt=4"}
+
+
 @pytest.mark.gpu
 def test_autotune_on_gpu_keeps_results_and_uses_the_cache(tmp_path):
     import torch
