@@ -1444,8 +1444,21 @@ k_build_fast(KArgs a) {
                 }
             }
         } else if (!ovf) {
+            // the KNN nearest candidates, one per round as the smallest
+            // (d^2, user id) above the previous pick: every slot's distance
+            // is computed once, user ids are read only to break an exact tie,
+            // and the picks wait in the quad's support row (free on this
+            // path) until the rounds are over
+            double d2s[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const double2 b = tpos[g.cand(s)];  // slots past n hold index 0
+                const double dx = b.x - g.q.x, dy = b.y - g.q.y;
+                d2s[s] = dx * dx + dy * dy;
+            }
+            int32_t* const picks = su + qi * KPITCH;
             double pd = -1.0;
-            int pt = -1, pu = -1, found = 0;
+            int pt = -1, found = 0;
             for (int r = 0; r < KNN; ++r) {
                 double bd = INFINITY;
                 int bt = -1;
@@ -1453,10 +1466,8 @@ k_build_fast(KArgs a) {
                 for (int s = 0; s < NS; ++s) {
                     if (s >= g.n) continue;
                     const int t = g.cand(s);
-                    const double2 b = tpos[t];
-                    const double dx = b.x - g.q.x, dy = b.y - g.q.y;
-                    const double d2 = dx * dx + dy * dy;
-                    const bool after = d2 > pd || (d2 == pd && t != pt && g.uid(t) > pu);
+                    const double d2 = d2s[s];
+                    const bool after = d2 > pd || (d2 == pd && t != pt && g.uid(t) > g.uid(pt));
                     const bool better = d2 < bd || (d2 == bd && bt >= 0 && g.uid(t) < g.uid(bt));
                     if (after && better) {
                         bd = d2;
@@ -1473,14 +1484,17 @@ k_build_fast(KArgs a) {
                     }
                 }
                 if (bt < 0) break;
-                if (lane == 0) {
-                    a.out.idx[r * nn + slot] = g.sorted(bt);
-                    a.out.mem[r * nn + slot] = 0;
-                }
+                if (lane == 0) picks[r] = bt;
                 pd = bd;
                 pt = bt;
-                pu = g.uid(bt);
                 ++found;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            for (int k = lane; k < found; k += QL) {
+                a.out.idx[k * nn + slot] = g.sorted(picks[k]);
+                a.out.mem[k * nn + slot] = 0;
             }
             // certified when the K-th distance is inside the gathered disk
             if (found == KNN && sqrt(pd) <= g.Rf * (1.0 - 1e-12)) {
