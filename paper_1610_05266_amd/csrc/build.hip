@@ -1292,9 +1292,22 @@ k_build_fast(KArgs a) {
     const int ncol = rbx1 - rbx0, nrow = rby1 - rby0;
     bool staged = ncol <= TDIM && nrow <= TDIM;
     if (staged) {
-        for (int e = threadIdx.x; e < nrow * (ncol + 1); e += QWG) {
-            const int r = e / (ncol + 1), c = e - r * (ncol + 1);
-            tst[r * (TDIM + 1) + c] = start[(rby0 + r) * sd.g.nbx + rbx0 + c];
+        {
+            // a thread's bin starts all in flight before the first is stored
+            constexpr int SPT = (TDIM * (TDIM + 1) + QWG - 1) / QWG;
+            const int nst = nrow * (ncol + 1);
+            int sv[SPT], sat[SPT];
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) {
+                const int e = static_cast<int>(threadIdx.x) + u * QWG;
+                const int r = e / (ncol + 1), c = e - r * (ncol + 1);
+                // (entries past the table load bin 0 and are not stored)
+                sat[u] = e < nst ? r * (TDIM + 1) + c : -1;
+                sv[u] = start[e < nst ? (rby0 + r) * sd.g.nbx + rbx0 + c : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < SPT; ++u)
+                if (sat[u] >= 0) tst[sat[u]] = sv[u];
         }
         __syncthreads();
         if (threadIdx.x < WAVE) {
