@@ -711,19 +711,29 @@ struct Support {
             return f;
         }
     }
-    __device__ bool add(int t, int bit) {
+    // Add t with membership bit `bit` (or the bit to its entry); returns
+    // its position, or -1 when the list is full.
+    __device__ __forceinline__ int add(int t, int bit) {
         const int f = find(t);
+        int at = f;
         if (f >= 0) {
             const int e = u[f];
             __builtin_amdgcn_wave_barrier();
             u[f] = e | (bit << 28);
         } else {
-            if (n >= KMAX) return false;
+            if (n >= KMAX) return -1;
             u[n] = t | (bit << 28);
-            ++n;
+            at = n++;
         }
         __builtin_amdgcn_wave_barrier();
-        return true;
+        return at;
+    }
+    // The bit to the entry at position p (known to hold the particle).
+    __device__ __forceinline__ void set_bit(int p, int bit) {
+        const int e = u[p];
+        __builtin_amdgcn_wave_barrier();
+        u[p] = e | (bit << 28);
+        __builtin_amdgcn_wave_barrier();
     }
 };
 
@@ -740,17 +750,19 @@ struct WaveSupport {
             __ballot(lane < n && static_cast<int>(static_cast<uint32_t>(e) & IDX_MASK) == t);
         return b ? __ffsll(static_cast<long long>(b)) - 1 : -1;
     }
-    __device__ bool add(int t, int bit) {
+    // (updates as selects, not branches around stores: the struct then
+    // stays in registers)
+    __device__ __forceinline__ int add(int t, int bit) {
         const int f = find(t);
         if (f >= 0) {
-            if (lane == f) e |= bit << 28;
-        } else {
-            if (n >= KROW) return false;
-            if (lane == n) e = t | (bit << 28);
-            ++n;
+            e |= lane == f ? bit << 28 : 0;
+            return f;
         }
-        return true;
+        if (n >= KROW) return -1;
+        e = lane == n ? t | (bit << 28) : e;
+        return n++;
     }
+    __device__ __forceinline__ void set_bit(int p, int bit) { e |= lane == p ? bit << 28 : 0; }
     // Exchange the entries at positions a and b (wave-uniform).
     __device__ void swap(int a, int b) {
         const int ea = __builtin_amdgcn_readlane(e, a), eb = __builtin_amdgcn_readlane(e, b);
@@ -758,6 +770,27 @@ struct WaveSupport {
         if (lane == b) e = ea;
     }
 };
+
+// Positions in a support list of a triangle's three vertices, packed 7 bits
+// each (position + 1; 0: not in the list), so that they stay in a register.
+__device__ __forceinline__ int vertex_pos(int tpk, int k) {
+    return static_cast<int>((static_cast<uint32_t>(tpk) >> (7 * k)) & 127u) - 1;
+}
+// Vertex k (particle t) into the list with membership bit `bit`: a bit set
+// at its known position, else an add (and its position recorded).  False
+// when the list is full.
+template <class S_>
+__device__ __forceinline__ bool add_vertex(S_& S, int& tpk, int k, int t, int bit) {
+    const int p0 = vertex_pos(tpk, k);
+    if (p0 >= 0) {
+        S.set_bit(p0, bit);
+        return true;
+    }
+    const int p = S.add(t, bit);
+    if (p < 0) return false;
+    tpk |= (p + 1) << (7 * k);
+    return true;
+}
 
 // Delaunay work of one node q: the triangle T (CCW, sorted indices) of the
 // particles' Delaunay triangulation that contains q, and the rings of its
@@ -784,7 +817,7 @@ struct WaveSupport {
 // (ring k > 0 starting at T[k-1] meets first the apex that the previous
 // ring saw last before T[k], where the chained version starts).
 template <class G, class S_>
-__device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, int only = -1, int vcap = KMAX) {
+__device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, int only = -1, int vcap = KMAX) {
     // the current triangle as scalars, selected by value (an array indexed
     // at run time would live in scratch memory)
     int T0 = -1, T1 = -1, T2 = -1;
@@ -901,7 +934,7 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
     // from T2 back to a0, which continues ring 0 counter-clockwise from T2.
     g.mark_rings();
     if (only == -2) {
-        if (!S.add(T0, 0) || !S.add(T1, 0) || !S.add(T2, 0)) return R_CAP;
+        if (S.add(T0, 0) < 0 || S.add(T1, 0) < 0 || S.add(T2, 0) < 0) return R_CAP;
         Tout[0] = T0;
         Tout[1] = T1;
         Tout[2] = T2;
@@ -914,15 +947,23 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
     bool cwise = false;     // rotating clockwise through the rest of an open fan
     int x0 = -1;            // first apex of ring 0 (across edge T0-T2)
     int nrot = 0;           // apexes found by rotation in the current ring
+    // Positions in S of T's vertices (tpk, packed) and of `cur` (always in
+    // it): entries never move, so adding a bit to a vertex or apex whose
+    // position is known needs no search.  The lists are those of S.add.
+    int tpk = 0, cpos = -1;
     {
         const int f1 = rk == 2 ? 0 : rk + 1, f2 = rk == 0 ? 2 : rk - 1;
-        if (!S.add(tsel(f1), 1 << rk) || !S.add(tsel(f2), 1 << rk)) return R_CAP;
+        if (!add_vertex(S, tpk, f1, tsel(f1), 1 << rk) || !add_vertex(S, tpk, f2, tsel(f2), 1 << rk)) return R_CAP;
         cur = tsel(f2);
         pcur = psel(f2);
+        cpos = vertex_pos(tpk, f2);
     }
     if (kept && dir < 0.0 && nvis >= 2 && T2 == vis[nvis - 1]) {
-        for (int s = nvis - 2; s >= 0; --s)
-            if (!S.add(vis[s], 1)) return R_CAP;
+        for (int s = nvis - 2; s >= 0; --s) {
+            const int p = S.add(vis[s], 1);
+            if (p < 0) return R_CAP;
+            if (s == 0) cpos = p;  // vis[0] is a0
+        }
         x0 = vis[nvis - 2];
         nrot = nvis - 1;
         cur = a0;
@@ -935,6 +976,7 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
         const double2 pvk = psel(rk);
         bool closed = false;
         int pred = cur;  // apex preceding `first` when the ring closes
+        int ppos = cpos;
         double2 ppred = pcur;
         int nt = -1;
         double2 pk = pcur;
@@ -956,6 +998,7 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
                 reuse0 = false;
                 cur = first;
                 pcur = pf;
+                cpos = vertex_pos(tpk, f);
                 continue;
             } else {
                 circumcircle(k, pvk, pcur, 1.0, cx, cy, rr);
@@ -964,8 +1007,11 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
                     // co-circular ties can step past the stop: the turn is then complete
                     closed = nt == a0 || (orient(pvk, pcur, pa0) > 0.0 && orient(pvk, pa0, pk) > 0.0);
                     if (closed) {
-                        for (int s = 0; s < nvis; ++s)
-                            if (!S.add(vis[s], 1)) return R_CAP;
+                        for (int s = 0; s < nvis; ++s) {
+                            const int p = S.add(vis[s], 1);
+                            if (p < 0) return R_CAP;
+                            if (s == nvis - 2) ppos = p;
+                        }
                         if (nvis >= 2) {
                             pred = vis[nvis - 2];
                             ppred = g.P(pred);
@@ -986,22 +1032,27 @@ __device__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S, int32_t* vis, 
             }
             cwise = false;
             const int f1 = rk == 2 ? 0 : rk + 1, f2 = rk == 0 ? 2 : rk - 1;
-            if (!S.add(tsel(f1), 1 << rk) || !S.add(tsel(f2), 1 << rk)) return R_CAP;
+            if (!add_vertex(S, tpk, f1, tsel(f1), 1 << rk) || !add_vertex(S, tpk, f2, tsel(f2), 1 << rk))
+                return R_CAP;
             if (chain && pred != tsel(f2)) {
                 // the first apex of this ring is the one that preceded
-                // `first` in the ring just closed
-                if (!S.add(pred, 1 << rk)) return R_CAP;
+                // `first` in the ring just closed (already in the list)
+                S.set_bit(ppos, 1 << rk);
                 cur = pred;
                 pcur = ppred;
+                cpos = ppos;
             } else {
                 cur = tsel(f2);
                 pcur = psel(f2);
+                cpos = vertex_pos(tpk, f2);
             }
             nrot = 0;
         } else {
-            if (!S.add(nt, 1 << rk)) return R_CAP;
+            const int p = S.add(nt, 1 << rk);
+            if (p < 0) return R_CAP;
             cur = nt;
             pcur = pk;
+            cpos = p;
             ++nrot;
         }
     }
@@ -1949,7 +2000,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             for (int w = 1; w < WPB && st == R_OK; ++w)
                 for (int k = 0; k < sinfo[w][1]; ++k) {
                     const uint32_t e = static_cast<uint32_t>(sring[w][k]);
-                    if (!S.add(static_cast<int>(e & IDX_MASK), static_cast<int>(e >> 28))) {
+                    if (S.add(static_cast<int>(e & IDX_MASK), static_cast<int>(e >> 28)) < 0) {
                         st = R_CAP;
                         break;
                     }
