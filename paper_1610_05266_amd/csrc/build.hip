@@ -129,15 +129,44 @@ __device__ __forceinline__ bool key_better(const Key& o, const Key& m, Uid uid, 
     return uid(o.t) < uid(m.t);
 }
 
+// With FAST the division and the square root are the hardware's reciprocal
+// and reciprocal square root, each refined by two Newton steps (a few ulp:
+// the certificates that use the circle leave margins of 1e-9 r and 1e-12 Rf),
+// and a divisor or squared radius outside [2^-900, 2^900] (or not a number)
+// gives an infinite radius, which no certificate accepts: the node is then
+// left to the exact path, which uses the correctly rounded forms.
+template <bool FAST>
 __device__ __forceinline__ void circumcircle(const Key& k, double2 v, double2 a, double sgn, double& cx,
                                              double& cy, double& rr) {
     const double Ax = a.x - v.x, Ay = a.y - v.y;
-    const double tk = k.num / (2.0 * k.cr);
-    const double ox = 0.5 * Ax - sgn * tk * Ay;
-    const double oy = 0.5 * Ay + sgn * tk * Ax;
-    cx = v.x + ox;
-    cy = v.y + oy;
-    rr = sqrt(ox * ox + oy * oy);
+    if constexpr (FAST) {
+        const double d = 2.0 * k.cr;
+        double y = __builtin_amdgcn_rcp(d);
+        y = fma(fma(-d, y, 1.0), y, y);
+        y = fma(fma(-d, y, 1.0), y, y);
+        const double tk = k.num * y;
+        const double ox = 0.5 * Ax - sgn * tk * Ay;
+        const double oy = 0.5 * Ay + sgn * tk * Ax;
+        cx = v.x + ox;
+        cy = v.y + oy;
+        const double x = ox * ox + oy * oy;
+        // g -> sqrt(x), h -> 1 / (2 sqrt(x)): one coupled step, one residual step
+        const double r0 = __builtin_amdgcn_rsq(x);
+        double g = x * r0, h = 0.5 * r0;
+        const double e = fma(-g, h, 0.5);
+        g = fma(g, e, g);
+        h = fma(h, e, h);
+        g = fma(fma(-g, g, x), h, g);
+        const bool ok = (d >= 0x1p-900) & (d <= 0x1p900) & (x >= 0x1p-900) & (x <= 0x1p900);
+        rr = ok ? g : INFINITY;
+    } else {
+        const double tk = k.num / (2.0 * k.cr);
+        const double ox = 0.5 * Ax - sgn * tk * Ay;
+        const double oy = 0.5 * Ay + sgn * tk * Ax;
+        cx = v.x + ox;
+        cy = v.y + oy;
+        rr = sqrt(ox * ox + oy * oy);
+    }
 }
 
 // Butterfly reductions over groups of W lanes: every lane of a group ends
@@ -369,6 +398,7 @@ constexpr int STAGE = 512;
 
 template <bool PER>
 struct WaveSource {
+    static constexpr bool kFastCircle = false;
     // (every member inlined: a call would put the source in scratch memory)
     static constexpr bool per = PER;
     const double2* __restrict__ pos;
@@ -529,6 +559,7 @@ struct WaveSource {
 // particle's index in the sorted arrays.
 template <int NS>
 struct QuadSource {
+    static constexpr bool kFastCircle = true;
     const int32_t* __restrict__ perm;
     const double2* lpos;  // the staged positions
     const int32_t* lrb;   // staged index of the first particle of each staged row (nrow + 1)
@@ -857,7 +888,7 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
             open = true;
             break;
         }
-        circumcircle(k, v, pcur, dir, cx, cy, rr);
+        circumcircle<G::kFastCircle>(k, v, pcur, dir, cx, cy, rr);
         if (!g.certify(cx, cy, rr)) return R_MORE;
         const double2 pk = make_double2(k.bx, k.by);
         // the triangle's two rays in counter-clockwise order
@@ -921,7 +952,7 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
         const Key k = g.wrap(tY, qY, tX, qX, 1.0);
         if (k.t == -2) return R_MORE;
         if (k.t < 0) return g.global() ? R_OUTSIDE : R_MORE;
-        circumcircle(k, qY, qX, 1.0, cx, cy, rr);
+        circumcircle<G::kFastCircle>(k, qY, qX, 1.0, cx, cy, rr);
         if (!g.certify(cx, cy, rr)) return R_MORE;
         T0 = tY; T1 = tX; T2 = k.t;
         P0 = qY; P1 = qX; P2 = make_double2(k.bx, k.by);
@@ -1001,7 +1032,7 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
                 cpos = vertex_pos(tpk, f);
                 continue;
             } else {
-                circumcircle(k, pvk, pcur, 1.0, cx, cy, rr);
+                circumcircle<G::kFastCircle>(k, pvk, pcur, 1.0, cx, cy, rr);
                 if (!g.certify(cx, cy, rr)) return R_MORE;
                 if (rk == 0 && reuse0) {
                     // co-circular ties can step past the stop: the turn is then complete
