@@ -426,6 +426,7 @@ struct WaveSource {
     __device__ __forceinline__ bool global() const { return R.global && !per; }
     // near-tie count when the rings phase begins
     __device__ __forceinline__ void mark_rings() { ring_mark = neardeg; }
+    __device__ __forceinline__ void progress(int) const {}
     __device__ __forceinline__ double2 at(int t) const {
         const double2 p = pos[t];
         return per ? image_near(m, p, q) : p;
@@ -614,6 +615,17 @@ struct QuadSource {
     }
     __device__ double2 P(int t) const { return lpos[t]; }
     __device__ void mark_rings() {}
+    // Issue priority by progress through the rings (the iteration count is
+    // wave-uniform): a CU holds four blocks that start together, and the
+    // arbiter favours the oldest waves; lowering a wave's priority as it
+    // advances lets the waves behind it catch up, so that the CU keeps all
+    // its waves (and their latency hiding) until near the end instead of
+    // finishing its last block alone.
+    __device__ __forceinline__ void progress(int it) const {
+        if (it == 4) __builtin_amdgcn_s_setprio(2);
+        else if (it == 8) __builtin_amdgcn_s_setprio(1);
+        else if (it == 12) __builtin_amdgcn_s_setprio(0);
+    }
     // A branch-free loop that compares bisector keys against a static
     // forward error bound valid for every candidate (all candidates, and v
     // and a, lie within Rf of q, so |A|, |B| <= 2 Rf and both error
@@ -1001,6 +1013,7 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
         pcur = pa0;
     }
     for (int it = 0; it < 8 * KMAX; ++it) {
+        g.progress(it);
         const int f = rk == 2 ? 0 : rk + 1;
         const int first = tsel(f);
         const double2 pf = psel(f);
@@ -1327,6 +1340,8 @@ constexpr int VPITCH = 16;  // wedge-search visit list per quad (longer: the exa
 template <int NS>
 __global__ void __launch_bounds__(QWG) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_build_fast(KArgs a) {
+    // highest issue priority until the rings (lowered as they progress)
+    __builtin_amdgcn_s_setprio(3);
     // the tile's bin region (its nodes' search windows): bin starts, row
     // bases and the particles, copied once with coalesced row reads.  The
     // bin starts are needed only until every quad has gathered; the per-quad
@@ -1539,6 +1554,10 @@ k_build_fast(KArgs a) {
                 }
             }
         } else if (!ovf) {
+            // (after the rings of the wave's interior nodes, if any: the
+            // waves that hold ring nodes are a tile's longest, so this part
+            // takes the highest priority again)
+            __builtin_amdgcn_s_setprio(3);
             // the KNN nearest candidates, one per round as the smallest
             // (d^2, user id) above the previous pick: every slot's distance
             // is computed once, user ids are read only to break an exact tie,
