@@ -1558,22 +1558,58 @@ k_build_fast(KArgs a) {
             // waves that hold ring nodes are a tile's longest, so this part
             // takes the highest priority again)
             __builtin_amdgcn_s_setprio(3);
-            // the KNN nearest candidates, one per round as the smallest
-            // (d^2, user id) above the previous pick: every slot's distance
-            // is computed once, user ids are read only to break an exact tie,
-            // and the picks wait in the quad's support row (free on this
-            // path) until the rounds are over
+            // the KNN nearest candidates in the order of (d^2, user id).
+            // Every slot's distance is computed once (slots past n: +inf);
+            // the picks wait in the quad's support row (free on this path)
+            // until the selection is over.
             double d2s[NS];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 const double2 b = tpos[g.cand(s)];  // slots past n hold index 0
                 const double dx = b.x - g.q.x, dy = b.y - g.q.y;
-                d2s[s] = dx * dx + dy * dy;
+                d2s[s] = s < g.n ? dx * dx + dy * dy : INFINITY;
             }
             int32_t* const picks = su + qi * KPITCH;
+            // A candidate's place in that order is the number of the quad's
+            // candidates strictly nearer, when no two distances are equal:
+            // the KNN places are then written at once, with no chain of
+            // rounds.  Equal distances give equal places; the quad sees that
+            // (fewer distinct places than candidates placed) and takes the
+            // rounds below, which break ties by user id.
+            int place[NS];
+#pragma unroll
+            for (int s = 0; s < NS; ++s) place[s] = 0;
+#pragma unroll
+            for (int m = 0; m < QL; ++m)
+#pragma unroll
+                for (int so = 0; so < NS; ++so) {
+                    const double od = m == 0 ? d2s[so] : lane_xor<QL>(d2s[so], m);
+#pragma unroll
+                    for (int s = 0; s < NS; ++s) place[s] += od < d2s[s] ? 1 : 0;
+                }
+            int hit = 0, placed = 0;
             double pd = -1.0;
-            int pt = -1, found = 0;
-            for (int r = 0; r < KNN; ++r) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (s < g.n && place[s] < KNN) {
+                    picks[place[s]] = g.cand(s);
+                    hit |= 1 << place[s];
+                    ++placed;
+                    pd = fmax(pd, d2s[s]);
+                }
+#pragma unroll
+            for (int m = 1; m < QL; m <<= 1) {
+                hit |= lane_xor<QL>(hit, m);
+                placed += lane_xor<QL>(placed, m);
+                pd = fmax(pd, lane_xor<QL>(pd, m));
+            }
+            int found = placed;
+            int pt = -1;
+            if (__popc(static_cast<unsigned>(hit)) != placed) {
+                found = 0;
+                pd = -1.0;
+            }
+            for (int r = found > 0 || placed == 0 ? KNN : 0; r < KNN; ++r) {
                 double bd = INFINITY;
                 int bt = -1;
 #pragma unroll

@@ -258,14 +258,16 @@ __device__ __forceinline__ double2 node_at(const MeshD& m, int i, int j, bool pe
 
 // Value of v in lane (lane ^ m) of the same group of W lanes (m < W).  For
 // quads the exchange is a DPP quad permute ([1,0,3,2] for m = 1, [2,3,0,1]
-// for m = 2) that needs no LDS round trip; the four lanes must be active.
-// A quad permute always reads a lane of its own quad, so every lane is
-// written and the destination needs no prior value (bound_ctrl set).
+// for m = 2, [3,2,1,0] for m = 3) that needs no LDS round trip; the four
+// lanes must be active.  A quad permute always reads a lane of its own quad,
+// so every lane is written and the destination needs no prior value
+// (bound_ctrl set).
 template <int W>
 __device__ __forceinline__ int lane_xor(int v, int m) {
     if constexpr (W == 4) {
-        return m == 1 ? __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true)
-                      : __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true);
+        return m == 1   ? __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true)
+               : m == 2 ? __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true)
+                        : __builtin_amdgcn_mov_dpp(v, 0x1B, 0xF, 0xF, true);
     } else {
         return __shfl_xor(v, m, W);
     }

@@ -88,6 +88,35 @@ def test_unjittered_lattice_reproduces_quadratics():
     assert np.abs(got - want).max() <= 1e-10
 
 
+def test_boundary_ring_selection_with_exact_distance_ties():
+    """Boundary-ring (closure) rows on an unjittered lattice: particles at
+    odd multiples of 1/64, nodes at multiples of 1/16, so every squared
+    distance is exact in binary (fused or not) and many are equal.  Each
+    row must hold the twelve particles first in the order of (d^2, user id)
+    -- ties broken by user id, also at the twelfth place -- computed here on
+    the host."""
+    m, n = 32, 16
+    g = (np.arange(m) + 0.5) / m
+    X, Y = np.meshgrid(g, g)
+    pos = np.stack([X.ravel(), Y.ravel()], 1)[np.random.default_rng(3).permutation(m * m)]
+    mesh = wl.MeshSpec(n, n, 1.0 / n)
+    w = ops.p2m_build_weights(mesh, 1.0 / m, _g(pos))
+    idx, _, cnt, _ = (t.numpy() for t in w.export())
+    om = OMesh(n, n, 1.0 / n)
+    nodes = om.nodes()
+    ring = np.flatnonzero(om.on_boundary_ring(np.arange(om.n_nodes)))
+    assert ring.size == 4 * n
+    ties = 0
+    for k in ring:
+        d2 = ((pos - nodes[k]) ** 2).sum(1)
+        order = np.lexsort((np.arange(len(pos)), d2))
+        want = order[:12]
+        ties += int(d2[order[11]] == d2[order[12]])
+        assert cnt[k] == 12, k
+        assert sorted(idx[:12, k].tolist()) == sorted(want.tolist()), k
+    assert ties > 0  # the twelfth place is tied at some nodes
+
+
 def test_offset_mesh_and_ragged_sizes():
     rng = np.random.default_rng(4)
     mesh = wl.MeshSpec(13, 7, 0.0625, -0.4, 1.3)
