@@ -1763,6 +1763,11 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // weights pass: issue priority lowered as a wave advances (staged, then
+    // solved), so that a CU's later blocks (its last, a boundary tile's
+    // closure rows) are not held back by the older ones; the exact path
+    // keeps the highest priority throughout
+    if (!escalated_rows) __builtin_amdgcn_s_setprio(2);
     // f(k, entry, position, user id) over the support: staged slots from LDS,
     // the rest (rare) from global memory, in two loops so that neither
     // needs a generic (flat) address
@@ -1901,6 +1906,7 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
         }
         coef = 1.0;
     }
+    if (!escalated_rows) __builtin_amdgcn_s_setprio(1);
     ok = min(ok, lane_xor<QL>(ok, 1));
     ok = min(ok, lane_xor<QL>(ok, 2));
     if ((pend || clos) && !ok) {
@@ -2242,6 +2248,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
 // same 8 x 8 tiles as the fast kernel.
 template <bool PER, class R = StoreRows>
 __global__ void __launch_bounds__(QWG) k_weights(KArgs a, R rp = R{}) {
+    __builtin_amdgcn_s_setprio(3);
     __shared__ double2 sp[QPB * SKP];
     __shared__ uint32_t se[QPB * SKP];
     __shared__ int32_t su[QPB * SKP];
