@@ -1012,7 +1012,10 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
         cur = a0;
         pcur = pa0;
     }
-    for (int it = 0; it < 8 * KMAX; ++it) {
+    // one exit: the loop ends with res >= 0 (a single exit keeps the
+    // compiler from copying the live values at every early return)
+    int res = -1;
+    for (int it = 0; it < 8 * KMAX && res < 0; ++it) {
         g.progress(it);
         const int f = rk == 2 ? 0 : rk + 1;
         const int first = tsel(f);
@@ -1029,13 +1032,19 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
         } else {
             const double sgn = cwise ? -1.0 : 1.0;
             const Key k = g.wrap(tsel(rk), pvk, cur, pcur, sgn);
-            if (k.t == -2) return R_MORE;
+            if (k.t == -2) {
+                res = R_MORE;
+                break;
+            }
             nt = k.t;
             pk = make_double2(k.bx, k.by);
             if (cwise) {
                 closed = nt < 0;
             } else if (nt < 0) {
-                if (!g.global()) return R_MORE;
+                if (!g.global()) {
+                    res = R_MORE;
+                    break;
+                }
                 // open fan (hull vertex): the rest lies clockwise from `first`
                 cwise = true;
                 chain = false;
@@ -1046,16 +1055,23 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
                 continue;
             } else {
                 circumcircle<G::kFastCircle>(k, pvk, pcur, 1.0, cx, cy, rr);
-                if (!g.certify(cx, cy, rr)) return R_MORE;
+                if (!g.certify(cx, cy, rr)) {
+                    res = R_MORE;
+                    break;
+                }
                 if (rk == 0 && reuse0) {
                     // co-circular ties can step past the stop: the turn is then complete
                     closed = nt == a0 || (orient(pvk, pcur, pa0) > 0.0 && orient(pvk, pa0, pk) > 0.0);
                     if (closed) {
                         for (int s = 0; s < nvis; ++s) {
                             const int p = S.add(vis[s], 1);
-                            if (p < 0) return R_CAP;
+                            if (p < 0) {
+                                res = R_CAP;
+                                break;
+                            }
                             if (s == nvis - 2) ppos = p;
                         }
+                        if (res >= 0) break;
                         if (nvis >= 2) {
                             pred = vis[nvis - 2];
                             ppred = g.P(pred);
@@ -1069,15 +1085,15 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
         }
         if (closed) {
             if (++rk == 3 || only >= 0) {
-                Tout[0] = T0;
-                Tout[1] = T1;
-                Tout[2] = T2;
-                return R_OK;
+                res = R_OK;
+                break;
             }
             cwise = false;
             const int f1 = rk == 2 ? 0 : rk + 1, f2 = rk == 0 ? 2 : rk - 1;
-            if (!add_vertex(S, tpk, f1, tsel(f1), 1 << rk) || !add_vertex(S, tpk, f2, tsel(f2), 1 << rk))
-                return R_CAP;
+            if (!add_vertex(S, tpk, f1, tsel(f1), 1 << rk) || !add_vertex(S, tpk, f2, tsel(f2), 1 << rk)) {
+                res = R_CAP;
+                break;
+            }
             if (chain && pred != tsel(f2)) {
                 // the first apex of this ring is the one that preceded
                 // `first` in the ring just closed (already in the list)
@@ -1093,14 +1109,22 @@ __device__ __forceinline__ int delaunay_node(G& g, double2 q, int Tout[3], S_& S
             nrot = 0;
         } else {
             const int p = S.add(nt, 1 << rk);
-            if (p < 0) return R_CAP;
+            if (p < 0) {
+                res = R_CAP;
+                break;
+            }
             cur = nt;
             pcur = pk;
             cpos = p;
             ++nrot;
         }
     }
-    return R_FAIL;
+    if (res == R_OK) {
+        Tout[0] = T0;
+        Tout[1] = T1;
+        Tout[2] = T2;
+    }
+    return res < 0 ? R_FAIL : res;
 }
 
 // ---------------------------------------------------------------- algebra
