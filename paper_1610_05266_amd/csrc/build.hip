@@ -569,6 +569,10 @@ struct QuadSource {
     double2 q;
     double Rf;
     uint32_t ci_[(NS + 1) / 2];  // candidate s in bits 16 (s & 1) .. of word s / 2
+    // some lane of the wave that runs the Delaunay routine holds NS
+    // candidates (wave-uniform); else every query skips the last slot, which
+    // all those lanes leave empty
+    bool use_last = true;
     int n;
     int lane;  // 0..3
 
@@ -598,6 +602,7 @@ struct QuadSource {
         pbest = make_double2(0.0, 0.0);
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
+            if (s == NS - 1 && !use_last) break;
             if (s >= n) continue;
             const int t = cand(s);
             if (t == exclude) continue;
@@ -656,6 +661,7 @@ struct QuadSource {
             bc = 0.0;
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
+                if (s == NS - 1 && !use_last) break;
                 const int t = cand(s);  // slots past n hold index 0
                 const double2 b = lpos[t];
                 const double Bx = b.x - v.x, By = b.y - v.y;
@@ -686,6 +692,7 @@ struct QuadSource {
         } else {
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
+                if (s == NS - 1 && !use_last) break;
                 const int t = cand(s);  // slots past n hold index 0
                 const double2 b = lpos[t];
                 const double Bx = b.x - v.x, By = b.y - v.y;
@@ -1555,6 +1562,8 @@ k_build_fast(KArgs a) {
         }
     }
     __syncthreads();  // every quad has gathered: the support rows replace the bin starts
+    // (an overflowed lane holds NS candidates too: it only keeps the slot)
+    g.use_last = __ballot(valid && !ring && g.n >= NS) != 0;
     if (valid) {
         ovf |= lane_xor<QL>(ovf, 1);
         ovf |= lane_xor<QL>(ovf, 2);
