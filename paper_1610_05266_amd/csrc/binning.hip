@@ -435,11 +435,13 @@ int bin_particles(const BinBuffers& b, const double* pos, int64_t N, const SetDe
                                           hipFuncAttributeMaxDynamicSharedMemorySize, LDS_MAX);
     });
     P2M_HIP(lds_err);
-    // sub-chunk size: two records per thread within 64 KB while the
-    // super-bins are few; with more super-bins than threads, up to four per
-    // thread in up to 160 KB (as many as fit beside the counters)
+    // sub-chunk size: four records per thread in up to 160 KB (as many as
+    // fit beside the counters) when a chunk holds more than two per thread
+    // or the super-bins outnumber the threads: the partition runs one block
+    // per CU, so the LDS costs no occupancy, and a whole chunk in one pass
+    // saves a round of barriers and scans; else two per thread in 64 KB
     const int64_t fixed = 12 * static_cast<int64_t>(bg.nsb) + 4 * static_cast<int64_t>(ntiles);
-    const bool wide = bg.nsb > BT;
+    const bool wide = bg.nsb > BT || bg.cs > 2 * BT;
     int sub = (wide ? 4 : 2) * BT;
     const int64_t lds_cap = wide ? LDS_MAX : 65536;
     while (sub > 256 && fixed + 24 * static_cast<int64_t>(sub) > lds_cap) sub >>= 1;
