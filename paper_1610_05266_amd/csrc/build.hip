@@ -414,12 +414,6 @@ struct WaveSource {
     double2* lp;   // LDS stage of this wave [STAGE]
     int32_t* lt;   // sorted indices of the staged particles
     int ln;        // staged count, -1 when streaming
-    // regions of at most 2 WAVE particles (and WAVE bin rows) are held in
-    // registers instead: flat element f by lane f % WAVE, as the staged loop
-    // deals them
-    int nreg;      // particles held in registers, -1 when not
-    double2 rp0, rp1;
-    int rt0, rt1;
 
     // every particle was a candidate (a periodic box has no hull: its widest
     // window answers only what it certifies)
@@ -441,7 +435,7 @@ struct WaveSource {
         // run lengths, one lane per run (a bin row, or a part of one that
         // wraps), 64 runs at a time
         const int nrow = R.nrun();
-        int total = 0, rs = 0, rpre = 0;  // this lane's run (first 64 runs): start, flat offset
+        int total = 0;
         for (int r0 = 0; r0 < nrow; r0 += WAVE) {
             const int r = r0 + lane;
             int len = 0, s0 = 0;
@@ -457,29 +451,7 @@ struct WaveSource {
                 const int o = __shfl_up(inc, d);
                 if (lane >= d) inc += o;
             }
-            if (r0 == 0) {
-                rs = s0;
-                rpre = inc - len;
-            }
             total += read_lane(inc, WAVE - 1);
-        }
-        nreg = -1;
-        if (total <= 2 * WAVE && nrow <= WAVE) {
-            // each lane finds the rows of its flat elements lane and lane + WAVE
-            int t0 = -1, t1 = -1;
-            for (int r = 0; r < nrow; ++r) {
-                const int sr = read_lane(rs, r), pr = read_lane(rpre, r);
-                const int pe = r + 1 < nrow ? read_lane(rpre, r + 1) : total;
-                if (lane >= pr && lane < pe) t0 = sr + lane - pr;
-                if (lane + WAVE >= pr && lane + WAVE < pe) t1 = sr + lane + WAVE - pr;
-            }
-            rt0 = t0;
-            rt1 = t1;
-            rp0 = at(t0 >= 0 ? t0 : 0);
-            rp1 = at(t1 >= 0 ? t1 : 0);
-            nreg = total;
-            ln = -1;
-            return;
         }
         ln = total <= STAGE ? total : -1;
         if (ln < 0) return;
@@ -500,11 +472,6 @@ struct WaveSource {
     }
     template <class F>
     __device__ __forceinline__ void scan(F&& f) const {
-        if (nreg >= 0) {
-            if (lane < nreg) f(rt0, rp0);
-            if (lane + WAVE < nreg) f(rt1, rp1);
-            return;
-        }
         if (ln >= 0) {
             for (int k = lane; k < ln; k += WAVE) f(lt[k], lp[k]);
             return;
@@ -2030,23 +1997,28 @@ __device__ __forceinline__ void count_wave(const KArgs& a, const WaveCounts& wc)
 // over square bin regions that double in half-width up to every particle;
 // interior nodes leave their support in the ELL row, closure nodes (ring, or
 // outside the hull) their nearest particles; k_weights does the rest.
-template <bool PER>
-__global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
+// LDS of the exact path's node loop: visit lists, staged regions and ring
+// lists of its three waves, and (when it weighs its rows) the row staging.
+struct SlowLds {
+    int32_t* svis;   // [3 * KROW]
+    double2* slp;    // [3 * STAGE]
+    int32_t* slt;    // [3 * STAGE]
+    int32_t* sring;  // [3 * KROW]
+    int* sinfo;      // [3 * 3]
+    double2* wsp;    // [(WAVE / QL) * SKP] (weighing only)
+    uint32_t* wse;
+    int32_t* wsu;
+};
+
+template <bool PER, bool WEIGH>
+__device__ __forceinline__ void slow_nodes(const KArgs& a, int first, int stride, const SlowLds& L) {
     constexpr int WPB = SWG / WAVE;
     static_assert(WPB == 3, "one wave per ring");
-    __shared__ int32_t svis[WPB * KROW];
-    __shared__ double2 slp[WPB * STAGE];
-    __shared__ int32_t slt[WPB * STAGE];
-    // each ring's list (entry | ring bit << 28), its status, length and
-    // near-tie count, for the ring-0 wave to merge
-    __shared__ int32_t sring[WPB][KROW];
-    __shared__ int sinfo[WPB][3];
-    // the weights of the finished row, by the first quad of the ring-0 wave
-    __shared__ double2 wsp[(WAVE / QL) * SKP];
-    __shared__ uint32_t wse[(WAVE / QL) * SKP];
-    __shared__ int32_t wsu[(WAVE / QL) * SKP];
-    // These few waves are a serial latency chain that runs beside the
-    // weights kernel: they take issue priority over its waves.
+    int32_t* const svis = L.svis;
+    double2* const slp = L.slp;
+    int32_t* const slt = L.slt;
+    // These few waves are a serial latency chain beside the weights pass:
+    // they take issue priority over its waves.
     __builtin_amdgcn_s_setprio(3);
     const int lane = threadIdx.x & (WAVE - 1);
     // the wave's index, read as a scalar: every value derived from it (the
@@ -2055,7 +2027,7 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
     const int count = static_cast<int>(a.diag[D_SLOWCNT]);
     const int64_t nn = a.n_slots;
-    for (int li = blockIdx.x; li < count; li += gridDim.x) {
+    for (int li = first; li < count; li += stride) {
         // the previous node's lists have been read
         __syncthreads();
         const int64_t slot = a.slow[li];
@@ -2077,8 +2049,9 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         c.neardeg = 0;
         c.ring_mark = 0;
         c.lane = lane;
-        c.lp = slp + wv * STAGE;
-        c.lt = slt + wv * STAGE;
+        // (a fourth wave of a block takes part in its barriers only)
+        c.lp = slp + min(wv, WPB - 1) * STAGE;
+        c.lt = slt + min(wv, WPB - 1) * STAGE;
         static_assert(KROW <= WAVE, "one support entry per lane");
         WaveSupport S;
         S.e = 0;
@@ -2093,22 +2066,27 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             // wave k finds the triangle and then the ring of its vertex k
             for (int level = 0;; ++level) {
                 const int hw = level < a.levels ? (sd.hw0 << level) : big;
-                c.set_region(per ? make_region_periodic(sd.g, cbx, cby, hw) : make_region(sd.g, cbx, cby, hw));
-                S.n = 0;
-                const int sk = delaunay_node(c, q, T, S, svis + wv * KROW, a.linear ? -2 : wv, KROW);
-                if (lane < S.n) sring[wv][lane] = S.e;
-                if (lane == 0) {
-                    sinfo[wv][0] = sk;
-                    sinfo[wv][1] = S.n;
-                    // the wedge and walk counted once, by the ring-0 wave
-                    sinfo[wv][2] = wv == 0 ? c.neardeg : c.neardeg - c.ring_mark;
+                const Region reg = per ? make_region_periodic(sd.g, cbx, cby, hw) : make_region(sd.g, cbx, cby, hw);
+                if (wv < WPB) {
+                    c.set_region(reg);
+                    S.n = 0;
+                    const int sk = delaunay_node(c, q, T, S, svis + wv * KROW, a.linear ? -2 : wv, KROW);
+                    if (lane < S.n) L.sring[wv * KROW + lane] = S.e;
+                    if (lane == 0) {
+                        L.sinfo[wv * 3] = sk;
+                        L.sinfo[wv * 3 + 1] = S.n;
+                        // the wedge and walk counted once, by the ring-0 wave
+                        L.sinfo[wv * 3 + 2] = wv == 0 ? c.neardeg : c.neardeg - c.ring_mark;
+                    }
+                } else {
+                    c.R = reg;
                 }
                 __syncthreads();
                 // the chained routine returns the first failure in ring order
                 st = R_OK;
                 for (int w = 0; w < WPB; ++w)
-                    if (st == R_OK) st = sinfo[w][0];
-                ndeg = sinfo[0][2] + sinfo[1][2] + sinfo[2][2];
+                    if (st == R_OK) st = L.sinfo[w * 3];
+                ndeg = L.sinfo[2] + L.sinfo[5] + L.sinfo[8];
                 if (st != R_MORE) break;
                 __syncthreads();  // every wave has read this level's results
                 if (c.R.global) {
@@ -2123,8 +2101,8 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
             // ring 0's list, then the new entries of rings 1 and 2 in their
             // order (ring bits of shared entries OR-ed): the chained order
             for (int w = 1; w < WPB && st == R_OK; ++w)
-                for (int k = 0; k < sinfo[w][1]; ++k) {
-                    const uint32_t e = static_cast<uint32_t>(sring[w][k]);
+                for (int k = 0; k < L.sinfo[w * 3 + 1]; ++k) {
+                    const uint32_t e = static_cast<uint32_t>(L.sring[w * KROW + k]);
                     if (S.add(static_cast<int>(e & IDX_MASK), static_cast<int>(e >> 28)) < 0) {
                         st = R_CAP;
                         break;
@@ -2272,45 +2250,134 @@ __global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
         }
         // every quad of the wave computes the row's systems; they share
         // its final pass
-        count_wave(a, weights_node<PER, WAVE / QL>(a, sd, i, j, true, slot, lane & (QL - 1), lane / QL, wsp, wse, wsu,
-                                              true, lane / QL));
+        if constexpr (WEIGH)
+            count_wave(a, weights_node<PER, WAVE / QL>(a, sd, i, j, true, slot, lane & (QL - 1), lane / QL, L.wsp,
+                                                  L.wse, L.wsu, true, lane / QL));
     }
+}
+
+// The exact path's nodes, geometry and weights, one block of three waves
+// per listed node (on a side stream, beside the weights pass).
+template <bool PER>
+__global__ void __launch_bounds__(SWG) k_slow_geom(KArgs a) {
+    constexpr int WPB = SWG / WAVE;
+    __shared__ int32_t svis[WPB * KROW];
+    __shared__ double2 slp[WPB * STAGE];
+    __shared__ int32_t slt[WPB * STAGE];
+    // each ring's list (entry | ring bit << 28), its status, length and
+    // near-tie count, for the ring-0 wave to merge
+    __shared__ int32_t sring[WPB * KROW];
+    __shared__ int sinfo[WPB * 3];
+    // the weights of the finished row, by the first quad of the ring-0 wave
+    __shared__ double2 wsp[(WAVE / QL) * SKP];
+    __shared__ uint32_t wse[(WAVE / QL) * SKP];
+    __shared__ int32_t wsu[(WAVE / QL) * SKP];
+    const SlowLds L{svis, slp, slt, sring, sinfo, wsp, wse, wsu};
+    slow_nodes<PER, true>(a, blockIdx.x, gridDim.x, L);
 }
 
 // Weights of the fast path's pending rows, one quad per node, nodes in the
 // same 8 x 8 tiles as the fast kernel.
-template <bool PER, class R = StoreRows>
-__global__ void __launch_bounds__(QWG) k_weights(KArgs a, R rp = R{}) {
+// One node tile of the weights pass (tile b of the build, QWG threads).
+template <bool PER, class R>
+__device__ __forceinline__ void weights_tile(const KArgs& a, const R& rp, int b, double2* sp, uint32_t* se,
+                                             int32_t* su, int* wsum) {
     __builtin_amdgcn_s_setprio(3);
-    __shared__ double2 sp[QPB * SKP];
-    __shared__ uint32_t se[QPB * SKP];
-    __shared__ int32_t su[QPB * SKP];
-    __shared__ int wsum[QWG / WAVE][TD];
     const int lane = threadIdx.x & (QL - 1);
     const int qi = threadIdx.x / QL;
-    const SetDesc sd = tile_set(a, blockIdx.x);
+    const SetDesc sd = tile_set(a, b);
     int tx, ty;
-    tile_xy(sd, static_cast<int>(blockIdx.x - sd.t0), tx, ty);
+    tile_xy(sd, static_cast<int>(b - sd.t0), tx, ty);
     const int i = tx * 8 + (qi & 7), j = ty * 8 + (qi >> 3);
     const bool valid = i <= sd.m.nx && j <= sd.m.ny;
-    const int64_t slot = static_cast<int64_t>(blockIdx.x) * TILE_N + qi;
+    const int64_t slot = static_cast<int64_t>(b) * TILE_N + qi;
     const WaveCounts wc = weights_node<PER, 1, R>(a, sd, i, j, valid, slot, lane, qi, sp, se, su, false, 0, rp);
     // the tile's counts as one plain record, folded into the diagnostics by
     // k_weights_rd: device-wide atomics from every wave on the same few
     // counters serialise at their memory partition and stall the pass
     if (threadIdx.x % WAVE == 0) {
-        for (int c = 0; c < 4; ++c) wsum[threadIdx.x / WAVE][c] = wc.c[c];
-        wsum[threadIdx.x / WAVE][TD_KMAX] = __float_as_int(wc.kmax);
+        for (int c = 0; c < 4; ++c) wsum[(threadIdx.x / WAVE) * TD + c] = wc.c[c];
+        wsum[(threadIdx.x / WAVE) * TD + TD_KMAX] = __float_as_int(wc.kmax);
     }
     __syncthreads();
     if (threadIdx.x < TD) {
         int v = 0;
         for (int w = 0; w < QWG / WAVE; ++w) {
-            const int x = wsum[w][threadIdx.x];
+            const int x = wsum[w * TD + threadIdx.x];
             // (non-negative floats order as their bit patterns)
             v = (threadIdx.x == WC_SUPMAX || threadIdx.x == TD_KMAX) ? max(v, x) : v + x;
         }
-        a.tdiag[blockIdx.x * TD + threadIdx.x] = v;
+        a.tdiag[static_cast<int64_t>(b) * TD + threadIdx.x] = v;
+    }
+}
+
+template <bool PER, class R = StoreRows>
+__global__ void __launch_bounds__(QWG) k_weights(KArgs a, R rp = R{}) {
+    __shared__ double2 sp[QPB * SKP];
+    __shared__ uint32_t se[QPB * SKP];
+    __shared__ int32_t su[QPB * SKP];
+    __shared__ int wsum[(QWG / WAVE) * TD];
+    weights_tile<PER, R>(a, rp, static_cast<int>(blockIdx.x), sp, se, su, wsum);
+}
+
+// The weights pass and the exact path's geometry in one launch, on the
+// caller's stream (no fork or join of a second stream): gs blocks run the
+// exact path's nodes (three waves; the fourth takes part in the block's
+// barriers only) and leave their rows pending, the others are the weights
+// pass's tiles.  The first g1 exact-path blocks come before the tiles (the
+// few nodes of an ordered cloud then start at once), the rest after them
+// (the many of a sheared one, without holding back the tiles' dispatch).
+// The two roles share one LDS allocation.  The exact path's rows are
+// weighed after it by k_slow_weights.
+constexpr int WT_LDS = QPB * SKP * (16 + 4 + 4) + (QWG / WAVE) * BUILD_TD * 4;
+constexpr int SG_LDS = 3 * KROW * 4 + 3 * STAGE * (16 + 4) + 3 * KROW * 4 + 3 * 3 * 4;
+constexpr int WS_LDS = WT_LDS > SG_LDS ? WT_LDS : SG_LDS;
+template <bool PER>
+__global__ void __launch_bounds__(QWG) k_weights_slow(KArgs a, int gs, int g1, int tiles) {
+    __shared__ __align__(16) unsigned char lds[WS_LDS];
+    const int b = static_cast<int>(blockIdx.x);
+    if (b < g1 || b >= g1 + tiles) {
+        double2* slp = reinterpret_cast<double2*>(lds);
+        int32_t* slt = reinterpret_cast<int32_t*>(slp + 3 * STAGE);
+        int32_t* svis = slt + 3 * STAGE;
+        int32_t* sring = svis + 3 * KROW;
+        int* sinfo = sring + 3 * KROW;
+        const SlowLds L{svis, slp, slt, sring, sinfo, nullptr, nullptr, nullptr};
+        slow_nodes<PER, false>(a, b < g1 ? b : b - tiles, gs, L);
+        return;
+    }
+    double2* sp = reinterpret_cast<double2*>(lds);
+    uint32_t* se = reinterpret_cast<uint32_t*>(sp + QPB * SKP);
+    int32_t* su = reinterpret_cast<int32_t*>(se + QPB * SKP);
+    int* wsum = su + QPB * SKP;
+    weights_tile<PER, StoreRows>(a, StoreRows{}, b - g1, sp, se, su, wsum);
+}
+
+// Weights of the exact path's rows left pending by k_weights_slow: a wave
+// per listed node (every quad of it computes the row's systems; they share
+// its final pass), as k_slow_geom weighs them.  Rows longer than the ELL
+// width are on the rank-revealing list already.
+template <bool PER>
+__global__ void __launch_bounds__(QWG) k_slow_weights(KArgs a) {
+    constexpr int WPB = QWG / WAVE;
+    __shared__ double2 wsp[WPB * (WAVE / QL) * SKP];
+    __shared__ uint32_t wse[WPB * (WAVE / QL) * SKP];
+    __shared__ int32_t wsu[WPB * (WAVE / QL) * SKP];
+    __builtin_amdgcn_s_setprio(3);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
+    const int count = static_cast<int>(a.diag[D_SLOWCNT]);
+    const int waves = static_cast<int>(gridDim.x) * WPB;
+    for (int li = static_cast<int>(blockIdx.x) * WPB + wv; li < count; li += waves) {
+        const int64_t slot = a.slow[li];
+        const uint32_t meta = a.out.meta[slot];
+        if (meta_type(meta) == NT_PENDING && static_cast<int>(meta_cnt(meta)) > KMAX) continue;
+        const SetDesc sd = slot_set(a, slot);
+        int i, j;
+        slot_ij(sd, slot, i, j);
+        const int o = wv * (WAVE / QL) * SKP;
+        count_wave(a, weights_node<PER, WAVE / QL>(a, sd, i, j, true, slot, lane & (QL - 1), lane / QL, wsp + o,
+                                              wse + o, wsu + o, true, lane / QL));
     }
 }
 
@@ -2535,9 +2602,43 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         else k_build_fast<NS_MAX><<<tiles, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());
-    // The few nodes the fast pass could not certify take the exact wave path
-    // on a side stream, concurrently with the weights of all other nodes
-    // (without a side stream, after them on the caller's stream).
+    // The few nodes the fast pass could not certify take the exact wave path.
+    // Its blocks loop over the actual list; their number is sized for many
+    // more nodes than an ordered cloud leaves there (a sheared one leaves
+    // thousands), and the blocks past the list leave at once.
+    const int64_t expect = n_nodes / 64 + 64 * static_cast<int64_t>(S);
+    if (!fp) {
+        // Stored weights: the exact path's geometry rides in the weights
+        // pass's launch on the caller's stream (a fork and join of a second
+        // stream would cost more than its rows' weights, which a short pass
+        // adds after it).
+        const int gs = static_cast<int>(std::min<int64_t>(expect, 4096));
+        const int g1 = std::min(gs, 256);
+        {
+            PhaseTimer t3(PH_WEIGHTS, st);
+            {
+                PhaseTimer t4(PH_K_WEIGHTS, st);
+                if (periodic) k_weights_slow<true><<<gs + tiles, QWG, 0, st>>>(a, gs, g1, static_cast<int>(tiles));
+                else k_weights_slow<false><<<gs + tiles, QWG, 0, st>>>(a, gs, g1, static_cast<int>(tiles));
+            }
+            {
+                PhaseTimer t2(PH_BUILD_SLOW, st);
+                if (periodic) k_slow_weights<true><<<64, QWG, 0, st>>>(a);
+                else k_slow_weights<false><<<64, QWG, 0, st>>>(a);
+            }
+            {
+                PhaseTimer t5(PH_K_WEIGHTS_RD, st);
+                if (periodic) k_weights_rd<true><<<64, QWG, 0, st>>>(a);
+                else k_weights_rd<false><<<64, QWG, 0, st>>>(a);
+            }
+            if (periodic) k_seam_copy<<<tiles, QWG, 0, st>>>(a);
+        }
+        P2M_HIP(hipGetLastError());
+        return P2M_OK;
+    }
+    // Fused form: the exact path on a side stream, concurrently with the
+    // weights (and sums) of all other nodes (without a side stream, after
+    // them on the caller's stream).
     const bool fork = side.stream != nullptr && side.stream != st && side.fork && side.join;
     hipStream_t sst = fork ? side.stream : st;
     if (fork) {
@@ -2546,11 +2647,7 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     }
     {
         PhaseTimer t2(PH_BUILD_SLOW, sst);
-        // one block per slow node; the grid loops over the actual list.  It
-        // is sized for many more nodes than an ordered cloud leaves here (a
-        // sheared one leaves thousands), beyond the blocks resident at once:
-        // the blocks past the list leave at once
-        const int64_t expect = n_nodes / 64 + 64 * static_cast<int64_t>(S);
+        // one block per slow node (the grid loops over the list)
         const int gs = static_cast<int>(std::min<int64_t>(expect, 4096));
         if (periodic) k_slow_geom<true><<<gs, SWG, 0, sst>>>(a);
         else k_slow_geom<false><<<gs, SWG, 0, sst>>>(a);
@@ -2563,9 +2660,7 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         // on the pass that found it)
         {
             PhaseTimer t4(PH_K_WEIGHTS, st);
-            if (fp) launch_weights_proj(a, *fp, tiles, st);
-            else if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
-            else k_weights<false><<<tiles, QWG, 0, st>>>(a);
+            launch_weights_proj(a, *fp, tiles, st);
         }
         if (fork) P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
         // ill-conditioned or rank-deficient rows of either pass (normally none)
