@@ -396,7 +396,9 @@ __device__ Region make_region(const Grid& g, int cbx, int cby, int hw) {
 // they are dealt round-robin over the 64 lanes.
 constexpr int STAGE = 512;
 
-template <bool PER>
+// REGS: regions of at most 2 WAVE particles (and WAVE bin rows) held in
+// registers instead of LDS (fewer LDS reads per query, more registers).
+template <bool PER, bool REGS = true>
 struct WaveSource {
     static constexpr bool kFastCircle = false;
     // (every member inlined: a call would put the source in scratch memory)
@@ -414,6 +416,11 @@ struct WaveSource {
     double2* lp;   // LDS stage of this wave [STAGE]
     int32_t* lt;   // sorted indices of the staged particles
     int ln;        // staged count, -1 when streaming
+    // (REGS) regions held in registers: flat element f by lane f % WAVE, as
+    // the staged loop deals them
+    int nreg;      // particles held in registers, -1 when not
+    double2 rp0, rp1;
+    int rt0, rt1;
 
     // every particle was a candidate (a periodic box has no hull: its widest
     // window answers only what it certifies)
@@ -435,7 +442,7 @@ struct WaveSource {
         // run lengths, one lane per run (a bin row, or a part of one that
         // wraps), 64 runs at a time
         const int nrow = R.nrun();
-        int total = 0;
+        int total = 0, rs = 0, rpre = 0;  // this lane's run (first 64 runs): start, flat offset
         for (int r0 = 0; r0 < nrow; r0 += WAVE) {
             const int r = r0 + lane;
             int len = 0, s0 = 0;
@@ -451,7 +458,31 @@ struct WaveSource {
                 const int o = __shfl_up(inc, d);
                 if (lane >= d) inc += o;
             }
+            if (r0 == 0) {
+                rs = s0;
+                rpre = inc - len;
+            }
             total += read_lane(inc, WAVE - 1);
+        }
+        nreg = -1;
+        if constexpr (REGS) {
+            if (total <= 2 * WAVE && nrow <= WAVE) {
+                // each lane finds the rows of its flat elements lane and lane + WAVE
+                int t0 = -1, t1 = -1;
+                for (int r = 0; r < nrow; ++r) {
+                    const int sr = read_lane(rs, r), pr = read_lane(rpre, r);
+                    const int pe = r + 1 < nrow ? read_lane(rpre, r + 1) : total;
+                    if (lane >= pr && lane < pe) t0 = sr + lane - pr;
+                    if (lane + WAVE >= pr && lane + WAVE < pe) t1 = sr + lane + WAVE - pr;
+                }
+                rt0 = t0;
+                rt1 = t1;
+                rp0 = at(t0 >= 0 ? t0 : 0);
+                rp1 = at(t1 >= 0 ? t1 : 0);
+                nreg = total;
+                ln = -1;
+                return;
+            }
         }
         ln = total <= STAGE ? total : -1;
         if (ln < 0) return;
@@ -472,6 +503,13 @@ struct WaveSource {
     }
     template <class F>
     __device__ __forceinline__ void scan(F&& f) const {
+        if constexpr (REGS) {
+            if (nreg >= 0) {
+                if (lane < nreg) f(rt0, rp0);
+                if (lane + WAVE < nreg) f(rt1, rp1);
+                return;
+            }
+        }
         if (ln >= 0) {
             for (int k = lane; k < ln; k += WAVE) f(lt[k], lp[k]);
             return;
@@ -2039,7 +2077,9 @@ __device__ __forceinline__ void slow_nodes(const KArgs& a, int first, int stride
         const double2 q = node_at(sd.m, i, j, per);
         const bool ring = !per && (i == 0 || j == 0 || i == sd.m.nx || j == sd.m.ny);
         const int cbx = (per && i == sd.m.nx ? 0 : i) * sd.g.kb, cby = (per && j == sd.m.ny ? 0 : j) * sd.g.kb;
-        WaveSource<PER> c;
+        // (the launch that shares its blocks with the weights pass keeps the
+        // regions in LDS: its register budget is the weights pass's)
+        WaveSource<PER, WEIGH> c;
         c.pos = a.pos_s;
         c.perm = a.perm;
         c.start = a.start + sd.b0;
@@ -2607,8 +2647,8 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     // more nodes than an ordered cloud leaves there (a sheared one leaves
     // thousands), and the blocks past the list leave at once.
     const int64_t expect = n_nodes / 64 + 64 * static_cast<int64_t>(S);
-    if (!fp) {
-        // Stored weights: the exact path's geometry rides in the weights
+    if (!fp && !periodic) {
+        // Stored weights in a bounded box: the exact path's geometry rides in the weights
         // pass's launch on the caller's stream (a fork and join of a second
         // stream would cost more than its rows' weights, which a short pass
         // adds after it).
@@ -2618,27 +2658,29 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
             PhaseTimer t3(PH_WEIGHTS, st);
             {
                 PhaseTimer t4(PH_K_WEIGHTS, st);
-                if (periodic) k_weights_slow<true><<<gs + tiles, QWG, 0, st>>>(a, gs, g1, static_cast<int>(tiles));
-                else k_weights_slow<false><<<gs + tiles, QWG, 0, st>>>(a, gs, g1, static_cast<int>(tiles));
+                k_weights_slow<false><<<gs + tiles, QWG, 0, st>>>(a, gs, g1, static_cast<int>(tiles));
             }
             {
+                // a wave per listed row, for as many rows as the exact path
+                // is sized for (a periodic box or a sheared cloud lists
+                // hundreds): the waves past the list leave at once
                 PhaseTimer t2(PH_BUILD_SLOW, st);
-                if (periodic) k_slow_weights<true><<<64, QWG, 0, st>>>(a);
-                else k_slow_weights<false><<<64, QWG, 0, st>>>(a);
+                const int gw = static_cast<int>(std::min<int64_t>((gs + 3) / 4, 1024));
+                k_slow_weights<false><<<gw, QWG, 0, st>>>(a);
             }
             {
                 PhaseTimer t5(PH_K_WEIGHTS_RD, st);
-                if (periodic) k_weights_rd<true><<<64, QWG, 0, st>>>(a);
-                else k_weights_rd<false><<<64, QWG, 0, st>>>(a);
+                k_weights_rd<false><<<64, QWG, 0, st>>>(a);
             }
-            if (periodic) k_seam_copy<<<tiles, QWG, 0, st>>>(a);
         }
         P2M_HIP(hipGetLastError());
         return P2M_OK;
     }
-    // Fused form: the exact path on a side stream, concurrently with the
-    // weights (and sums) of all other nodes (without a side stream, after
-    // them on the caller's stream).
+    // Fused form and periodic box: the exact path on a side stream,
+    // concurrently with the weights (and sums) of all other nodes (without a
+    // side stream, after them on the caller's stream).  (A periodic box lists
+    // hundreds of exact-path nodes, whose blocks would crowd the weights
+    // pass's tiles out of a shared launch.)
     const bool fork = side.stream != nullptr && side.stream != st && side.fork && side.join;
     hipStream_t sst = fork ? side.stream : st;
     if (fork) {
@@ -2660,7 +2702,9 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         // on the pass that found it)
         {
             PhaseTimer t4(PH_K_WEIGHTS, st);
-            launch_weights_proj(a, *fp, tiles, st);
+            if (fp) launch_weights_proj(a, *fp, tiles, st);
+            else if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
+            else k_weights<false><<<tiles, QWG, 0, st>>>(a);
         }
         if (fork) P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
         // ill-conditioned or rank-deficient rows of either pass (normally none)
