@@ -383,7 +383,7 @@ __global__ void __launch_bounds__(256) k_build_bwd_svd(BArgs a) {
     const int64_t nn = a.w.n_nodes, ns = a.w.n_slots;
     const bool per = a.per != 0;
     for (int li = w0; li < count; li += waves) {
-        const int64_t slot = a.w.rd[li];
+        const int64_t slot = static_cast<int64_t>(static_cast<uint32_t>(a.w.rd[li]) & ~RD_SOLVED);
         const SetDesc& sd = a.w.sets[set_search(a.w.S, slot / TILE_N, [&](int s) { return a.w.sets[s].t0; })];
         int i, j;
         if (!slot_ij(sd, slot, i, j)) continue;

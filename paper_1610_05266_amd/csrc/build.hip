@@ -1755,7 +1755,7 @@ template <bool PER, int QS = 1, class R = StoreRows>
 __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc& sd, int i, int j, bool valid,
                                                    int64_t slot, int lane, int qi, double2* sp, uint32_t* se,
                                                    int32_t* su, bool escalated_rows, int sub = 0,
-                                                   const R& rp = R{}) {
+                                                   const R& rp = R{}, int* svd_here = nullptr) {
     static_assert(!R::proj || QS == 1, "a projected row is summed by one quad");
     const int64_t nn = a.n_slots;
     const uint32_t meta = valid ? a.out.meta[slot] : 0u;
@@ -1949,8 +1949,11 @@ __device__ __forceinline__ WaveCounts weights_node(const KArgs& a, const SetDesc
     ok = min(ok, lane_xor<QL>(ok, 2));
     if ((pend || clos) && !ok) {
         // ill-conditioned or rank-deficient: the row stays pending for the
-        // rank-revealing solver (k_weights_rd)
-        if (lane == 0 && sub == 0) {
+        // rank-revealing solver (k_weights_rd), or, with svd_here, for the
+        // caller to solve that way at once
+        if (svd_here) {
+            *svd_here = 1;
+        } else if (lane == 0 && sub == 0) {
             const int lpos = static_cast<int>(atomicAdd(&a.diag[D_RDCNT], 1ull));
             a.rd[lpos] = static_cast<int32_t>(slot);
         }
@@ -2393,22 +2396,93 @@ __global__ void __launch_bounds__(QWG) k_weights_slow(KArgs a, int gs, int g1, i
     weights_tile<PER, StoreRows>(a, StoreRows{}, b - g1, sp, se, su, wsum);
 }
 
-// Weights of the exact path's rows left pending by k_weights_slow: a wave
-// per listed node (every quad of it computes the row's systems; they share
-// its final pass), as k_slow_geom weighs them.  Rows longer than the ELL
-// width are on the rank-revealing list already.
+
+// Rows listed by either weights pass because one of their systems is
+// ill-conditioned (condition estimate above svd_kappa) or lost rank: every
+// system of the row by the rank-revealing solver, one wave per row.  Block
+// 0 first folds k_weights' per-tile counts into the diagnostics.
+// The weights pass's per-tile counts folded into the diagnostics, by one
+// block of QWG threads.
+__device__ __forceinline__ void fold_tile_counts(const KArgs& a) {
+    unsigned long long v[TD] = {0, 0, 0, 0, 0};
+    const int64_t tiles = a.n_slots / TILE_N;
+    for (int64_t t = threadIdx.x; t < tiles; t += QWG) {
+#pragma unroll
+        for (int c = 0; c < TD; ++c) {
+            const unsigned long long x = static_cast<unsigned long long>(static_cast<uint32_t>(a.tdiag[t * TD + c]));
+            v[c] = (c == WC_SUPMAX || c == TD_KMAX) ? max(v[c], x) : v[c] + x;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < TD; ++c)
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(v[c], off);
+            v[c] = (c == WC_SUPMAX || c == TD_KMAX) ? max(v[c], o) : v[c] + o;
+        }
+    if (threadIdx.x % WAVE == 0) {
+        if (v[WC_INTERIOR]) atomicAdd(&a.diag[D_INTERIOR], v[WC_INTERIOR]);
+        if (v[WC_CLOSURE]) atomicAdd(&a.diag[D_CLOSURE], v[WC_CLOSURE]);
+        if (v[WC_OUTSIDE]) atomicAdd(&a.diag[D_OUTSIDE], v[WC_OUTSIDE]);
+        if (v[WC_SUPMAX]) atomicMax(&a.diag[D_SUPMAX], v[WC_SUPMAX]);
+        if (v[TD_KMAX]) {
+            const double k = static_cast<double>(__int_as_float(static_cast<int>(v[TD_KMAX])));
+            atomicMax(&a.diag[D_GRAMCOND], static_cast<unsigned long long>(__double_as_longlong(k)));
+        }
+    }
+}
+
+// One row by the rank-revealing solver, by one wave, with its counts.
+template <bool PER>
+__device__ __forceinline__ void svd_row(const KArgs& a, int64_t slot, int lane) {
+    const SetDesc sd = slot_set(a, slot);
+    int i, j;
+    slot_ij(sd, slot, i, j);
+    int nrd = 0;
+    double kmax = 0.0;
+    const int nsys = wave_row_svd<PER>(a, sd, slot, node_at(sd.m, i, j, PER), lane, nrd, kmax);
+    if (lane == 0) {
+        atomicAdd(&a.diag[D_SVD], static_cast<unsigned long long>(nsys));
+        if (nrd) atomicAdd(&a.diag[D_RANKDEF], static_cast<unsigned long long>(nrd));
+        if (kmax > 0.0) atomicMax(&a.diag[D_GRAMCOND], static_cast<unsigned long long>(__double_as_longlong(kmax)));
+    }
+}
+
+template <bool PER>
+__global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
+    if (blockIdx.x == 0) fold_tile_counts(a);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int count = static_cast<int>(a.diag[D_RDCNT]);
+    const int waves = static_cast<int>(gridDim.x) * (QWG / WAVE);
+    const int w0 = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (QWG / WAVE) + threadIdx.x / WAVE));
+    for (int li = w0; li < count; li += waves) svd_row<PER>(a, a.rd[li], lane);
+}
+
+// After k_weights_slow: the exact path's rows that it left pending, weighed
+// as k_slow_geom weighs them (a wave per listed node; every quad of it
+// computes the row's systems and they share its final pass), a row with an
+// ill-conditioned or rank-deficient system solved at once by the
+// rank-revealing solver in the same wave (and listed for the adjoint,
+// marked RD_SOLVED), and then the rows that the weights pass listed for
+// that solver (the work of k_weights_rd: every one of them is listed
+// before this launch starts, so each wave's view of the list holds them
+// all, and the marked ones are skipped).  Rows longer than the ELL width
+// are on that list already.  Block 0 first folds the weights pass's
+// per-tile counts into the diagnostics.
 template <bool PER>
 __global__ void __launch_bounds__(QWG) k_slow_weights(KArgs a) {
     constexpr int WPB = QWG / WAVE;
     __shared__ double2 wsp[WPB * (WAVE / QL) * SKP];
     __shared__ uint32_t wse[WPB * (WAVE / QL) * SKP];
     __shared__ int32_t wsu[WPB * (WAVE / QL) * SKP];
+    if (blockIdx.x == 0) fold_tile_counts(a);
     __builtin_amdgcn_s_setprio(3);
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x / WAVE));
     const int count = static_cast<int>(a.diag[D_SLOWCNT]);
+    const int nlisted = static_cast<int>(a.diag[D_RDCNT]);
     const int waves = static_cast<int>(gridDim.x) * WPB;
-    for (int li = static_cast<int>(blockIdx.x) * WPB + wv; li < count; li += waves) {
+    const int w0 = static_cast<int>(blockIdx.x) * WPB + wv;
+    for (int li = w0; li < count; li += waves) {
         const int64_t slot = a.slow[li];
         const uint32_t meta = a.out.meta[slot];
         if (meta_type(meta) == NT_PENDING && static_cast<int>(meta_cnt(meta)) > KMAX) continue;
@@ -2416,61 +2490,18 @@ __global__ void __launch_bounds__(QWG) k_slow_weights(KArgs a) {
         int i, j;
         slot_ij(sd, slot, i, j);
         const int o = wv * (WAVE / QL) * SKP;
+        int svd = 0;
         count_wave(a, weights_node<PER, WAVE / QL>(a, sd, i, j, true, slot, lane & (QL - 1), lane / QL, wsp + o,
-                                              wse + o, wsu + o, true, lane / QL));
-    }
-}
-
-// Rows listed by either weights pass because one of their systems is
-// ill-conditioned (condition estimate above svd_kappa) or lost rank: every
-// system of the row by the rank-revealing solver, one wave per row.  Block
-// 0 first folds k_weights' per-tile counts into the diagnostics.
-template <bool PER>
-__global__ void __launch_bounds__(QWG) k_weights_rd(KArgs a) {
-    if (blockIdx.x == 0) {
-        unsigned long long v[TD] = {0, 0, 0, 0, 0};
-        const int64_t tiles = a.n_slots / TILE_N;
-        for (int64_t t = threadIdx.x; t < tiles; t += QWG) {
-#pragma unroll
-            for (int c = 0; c < TD; ++c) {
-                const unsigned long long x = static_cast<unsigned long long>(static_cast<uint32_t>(a.tdiag[t * TD + c]));
-                v[c] = (c == WC_SUPMAX || c == TD_KMAX) ? max(v[c], x) : v[c] + x;
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < TD; ++c)
-            for (int off = 32; off > 0; off >>= 1) {
-                const unsigned long long o = __shfl_xor(v[c], off);
-                v[c] = (c == WC_SUPMAX || c == TD_KMAX) ? max(v[c], o) : v[c] + o;
-            }
-        if (threadIdx.x % WAVE == 0) {
-            if (v[WC_INTERIOR]) atomicAdd(&a.diag[D_INTERIOR], v[WC_INTERIOR]);
-            if (v[WC_CLOSURE]) atomicAdd(&a.diag[D_CLOSURE], v[WC_CLOSURE]);
-            if (v[WC_OUTSIDE]) atomicAdd(&a.diag[D_OUTSIDE], v[WC_OUTSIDE]);
-            if (v[WC_SUPMAX]) atomicMax(&a.diag[D_SUPMAX], v[WC_SUPMAX]);
-            if (v[TD_KMAX]) {
-                const double k = static_cast<double>(__int_as_float(static_cast<int>(v[TD_KMAX])));
-                atomicMax(&a.diag[D_GRAMCOND], static_cast<unsigned long long>(__double_as_longlong(k)));
-            }
+                                              wse + o, wsu + o, true, lane / QL, StoreRows{}, &svd));
+        if (__builtin_amdgcn_readfirstlane(svd)) {
+            if (lane == 0)
+                a.rd[atomicAdd(&a.diag[D_RDCNT], 1ull)] = static_cast<int32_t>(static_cast<uint32_t>(slot) | RD_SOLVED);
+            svd_row<PER>(a, slot, lane);
         }
     }
-    const int lane = threadIdx.x & (WAVE - 1);
-    const int count = static_cast<int>(a.diag[D_RDCNT]);
-    const int waves = static_cast<int>(gridDim.x) * (QWG / WAVE);
-    const int w0 = __builtin_amdgcn_readfirstlane(static_cast<int>(blockIdx.x * (QWG / WAVE) + threadIdx.x / WAVE));
-    for (int li = w0; li < count; li += waves) {
-        const int64_t slot = a.rd[li];
-        const SetDesc sd = slot_set(a, slot);
-        int i, j;
-        slot_ij(sd, slot, i, j);
-        int nrd = 0;
-        double kmax = 0.0;
-        const int nsys = wave_row_svd<PER>(a, sd, slot, node_at(sd.m, i, j, PER), lane, nrd, kmax);
-        if (lane == 0) {
-            atomicAdd(&a.diag[D_SVD], static_cast<unsigned long long>(nsys));
-            if (nrd) atomicAdd(&a.diag[D_RANKDEF], static_cast<unsigned long long>(nrd));
-            if (kmax > 0.0) atomicMax(&a.diag[D_GRAMCOND], static_cast<unsigned long long>(__double_as_longlong(kmax)));
-        }
+    for (int li = w0; li < nlisted; li += waves) {
+        const int32_t e = a.rd[li];
+        if (!(static_cast<uint32_t>(e) & RD_SOLVED)) svd_row<PER>(a, e, lane);
     }
 }
 
@@ -2662,15 +2693,12 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
             }
             {
                 // a wave per listed row, for as many rows as the exact path
-                // is sized for (a periodic box or a sheared cloud lists
-                // hundreds): the waves past the list leave at once
+                // is sized for (a sheared cloud lists hundreds): the waves
+                // past the list leave at once; the same launch takes the
+                // rank-revealing solver's list
                 PhaseTimer t2(PH_BUILD_SLOW, st);
-                const int gw = static_cast<int>(std::min<int64_t>((gs + 3) / 4, 1024));
+                const int gw = static_cast<int>(std::min<int64_t>(std::max<int64_t>((gs + 3) / 4, 64), 1024));
                 k_slow_weights<false><<<gw, QWG, 0, st>>>(a);
-            }
-            {
-                PhaseTimer t5(PH_K_WEIGHTS_RD, st);
-                k_weights_rd<false><<<64, QWG, 0, st>>>(a);
             }
         }
         P2M_HIP(hipGetLastError());

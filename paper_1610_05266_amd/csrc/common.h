@@ -46,6 +46,11 @@ enum DiagIdx : int {
     D_COUNT
 };
 
+// An entry of the rank-revealing solver's row list with this bit set names a
+// row solved that way already (listed for the adjoint, which also reads the
+// list).
+constexpr uint32_t RD_SOLVED = 0x80000000u;
+
 // A row holds up to KROW support entries: the first KMAX in the ELL arrays
 // of its node slot, the rest (rows found by the exact path around vertices of
 // high degree, rare) in an overflow row of the same layout, whose index is

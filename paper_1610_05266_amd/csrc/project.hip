@@ -75,7 +75,7 @@ __global__ void __launch_bounds__(256) k_project_list(WeightsView wv, const int3
     const int stride = static_cast<int>(gridDim.x) * 64;
     for (int li = static_cast<int>(blockIdx.x) * 64 + static_cast<int>(threadIdx.x >> 2); li < ns + nr;
          li += stride) {
-        const int64_t slot = li < ns ? slow[li] : wv.rd[li - ns];
+        const int64_t slot = li < ns ? slow[li] : static_cast<int64_t>(static_cast<uint32_t>(wv.rd[li - ns]) & ~RD_SOLVED);
         const SetDesc& sd = wv.sets[set_search(wv.S, slot / TILE_N, [&](int s) { return wv.sets[s].t0; })];
         int i, j;
         if (!slot_ij(sd, slot, i, j)) continue;
