@@ -2371,12 +2371,13 @@ __global__ void __launch_bounds__(QWG) k_weights(KArgs a, R rp = R{}) {
 // few nodes of an ordered cloud then start at once), the rest after them
 // (the many of a sheared one, without holding back the tiles' dispatch).
 // The two roles share one LDS allocation.  The exact path's rows are
-// weighed after it by k_slow_weights.
+// weighed after it by k_slow_weights.  With ProjRows (the fused form) the
+// tiles add each finished row into its node's sum instead of storing it.
 constexpr int WT_LDS = QPB * SKP * (16 + 4 + 4) + (QWG / WAVE) * BUILD_TD * 4;
 constexpr int SG_LDS = 3 * KROW * 4 + 3 * STAGE * (16 + 4) + 3 * KROW * 4 + 3 * 3 * 4;
 constexpr int WS_LDS = WT_LDS > SG_LDS ? WT_LDS : SG_LDS;
-template <bool PER>
-__global__ void __launch_bounds__(QWG) k_weights_slow(KArgs a, int gs, int g1, int tiles) {
+template <bool PER, class R = StoreRows>
+__global__ void __launch_bounds__(QWG) k_weights_slow(KArgs a, int gs, int g1, int tiles, R rp = R{}) {
     __shared__ __align__(16) unsigned char lds[WS_LDS];
     const int b = static_cast<int>(blockIdx.x);
     if (b < g1 || b >= g1 + tiles) {
@@ -2393,7 +2394,7 @@ __global__ void __launch_bounds__(QWG) k_weights_slow(KArgs a, int gs, int g1, i
     uint32_t* se = reinterpret_cast<uint32_t*>(sp + QPB * SKP);
     int32_t* su = reinterpret_cast<int32_t*>(se + QPB * SKP);
     int* wsum = su + QPB * SKP;
-    weights_tile<PER, StoreRows>(a, StoreRows{}, b - g1, sp, se, su, wsum);
+    weights_tile<PER, R>(a, rp, b - g1, sp, se, su, wsum);
 }
 
 
@@ -2611,23 +2612,25 @@ __global__ void __launch_bounds__(QWG) k_seam_copy(KArgs a) {
     }
 }
 
-// The projecting weights pass for the value type of the fused build.
+// The shared weights launch of the fused build, its tiles projecting, for
+// the value type and channel count of the build.
 template <typename TV, typename TW, typename TO>
-void launch_weights_proj_t(const KArgs& a, const FusedProj& fp, int tiles, hipStream_t st) {
+void launch_weights_proj_t(const KArgs& a, const FusedProj& fp, int gs, int g1, int tiles, hipStream_t st) {
     const TV* v = static_cast<const TV*>(fp.vals);
     TO* o = static_cast<TO*>(fp.out);
+    const unsigned grid = static_cast<unsigned>(gs + tiles);
     // (channel counts up to FUSED_CMAX: the sums stay in registers)
     switch (fp.C) {
-        case 1: k_weights<false, ProjRows<TV, TW, TO, 1>><<<tiles, QWG, 0, st>>>(a, {v, o, fp.C}); break;
-        case 2: k_weights<false, ProjRows<TV, TW, TO, 2>><<<tiles, QWG, 0, st>>>(a, {v, o, fp.C}); break;
-        case 3: k_weights<false, ProjRows<TV, TW, TO, 3>><<<tiles, QWG, 0, st>>>(a, {v, o, fp.C}); break;
-        default: k_weights<false, ProjRows<TV, TW, TO, 4>><<<tiles, QWG, 0, st>>>(a, {v, o, fp.C}); break;
+        case 1: k_weights_slow<false, ProjRows<TV, TW, TO, 1>><<<grid, QWG, 0, st>>>(a, gs, g1, tiles, {v, o, fp.C}); break;
+        case 2: k_weights_slow<false, ProjRows<TV, TW, TO, 2>><<<grid, QWG, 0, st>>>(a, gs, g1, tiles, {v, o, fp.C}); break;
+        case 3: k_weights_slow<false, ProjRows<TV, TW, TO, 3>><<<grid, QWG, 0, st>>>(a, gs, g1, tiles, {v, o, fp.C}); break;
+        default: k_weights_slow<false, ProjRows<TV, TW, TO, 4>><<<grid, QWG, 0, st>>>(a, gs, g1, tiles, {v, o, fp.C}); break;
     }
 }
-void launch_weights_proj(const KArgs& a, const FusedProj& fp, int tiles, hipStream_t st) {
-    if (fp.dtype == P2M_F64) launch_weights_proj_t<double, double, double>(a, fp, tiles, st);
-    else if (fp.dtype == P2M_F32) launch_weights_proj_t<float, float, float>(a, fp, tiles, st);
-    else launch_weights_proj_t<uint16_t, float, float>(a, fp, tiles, st);
+void launch_weights_proj(const KArgs& a, const FusedProj& fp, int gs, int g1, int tiles, hipStream_t st) {
+    if (fp.dtype == P2M_F64) launch_weights_proj_t<double, double, double>(a, fp, gs, g1, tiles, st);
+    else if (fp.dtype == P2M_F32) launch_weights_proj_t<float, float, float>(a, fp, gs, g1, tiles, st);
+    else launch_weights_proj_t<uint16_t, float, float>(a, fp, gs, g1, tiles, st);
 }
 
 }  // namespace
@@ -2678,18 +2681,21 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
     // more nodes than an ordered cloud leaves there (a sheared one leaves
     // thousands), and the blocks past the list leave at once.
     const int64_t expect = n_nodes / 64 + 64 * static_cast<int64_t>(S);
-    if (!fp && !periodic) {
-        // Stored weights in a bounded box: the exact path's geometry rides in the weights
+    if (!periodic) {
+        // A bounded box: the exact path's geometry rides in the weights
         // pass's launch on the caller's stream (a fork and join of a second
         // stream would cost more than its rows' weights, which a short pass
-        // adds after it).
+        // adds after it).  The fused form's tiles project their rows; the
+        // exact path's and the rank-revealing solver's rows are stored, and
+        // projected after the build from the two lists.
         const int gs = static_cast<int>(std::min<int64_t>(expect, 4096));
         const int g1 = std::min(gs, 256);
         {
             PhaseTimer t3(PH_WEIGHTS, st);
             {
                 PhaseTimer t4(PH_K_WEIGHTS, st);
-                k_weights_slow<false><<<gs + tiles, QWG, 0, st>>>(a, gs, g1, static_cast<int>(tiles));
+                if (fp) launch_weights_proj(a, *fp, gs, g1, static_cast<int>(tiles), st);
+                else k_weights_slow<false><<<gs + tiles, QWG, 0, st>>>(a, gs, g1, static_cast<int>(tiles));
             }
             {
                 // a wave per listed row, for as many rows as the exact path
@@ -2704,11 +2710,11 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         P2M_HIP(hipGetLastError());
         return P2M_OK;
     }
-    // Fused form and periodic box: the exact path on a side stream,
-    // concurrently with the weights (and sums) of all other nodes (without a
-    // side stream, after them on the caller's stream).  (A periodic box lists
-    // hundreds of exact-path nodes, whose blocks would crowd the weights
-    // pass's tiles out of a shared launch.)
+    // Periodic box: the exact path on a side stream, concurrently with the
+    // weights of all other nodes (without a side stream, after them on the
+    // caller's stream).  (A periodic box lists hundreds of exact-path nodes,
+    // whose blocks would crowd the weights pass's tiles out of a shared
+    // launch.)
     const bool fork = side.stream != nullptr && side.stream != st && side.fork && side.join;
     hipStream_t sst = fork ? side.stream : st;
     if (fork) {
@@ -2719,8 +2725,7 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         PhaseTimer t2(PH_BUILD_SLOW, sst);
         // one block per slow node (the grid loops over the list)
         const int gs = static_cast<int>(std::min<int64_t>(expect, 4096));
-        if (periodic) k_slow_geom<true><<<gs, SWG, 0, sst>>>(a);
-        else k_slow_geom<false><<<gs, SWG, 0, sst>>>(a);
+        k_slow_geom<true><<<gs, SWG, 0, sst>>>(a);
     }
     P2M_HIP(hipGetLastError());
     if (fork) P2M_HIP(hipEventRecord(side.join, side.stream));
@@ -2730,19 +2735,16 @@ int build_weights(const BinBuffers& b, const SetDesc* sets, int S, int64_t n_til
         // on the pass that found it)
         {
             PhaseTimer t4(PH_K_WEIGHTS, st);
-            if (fp) launch_weights_proj(a, *fp, tiles, st);
-            else if (periodic) k_weights<true><<<tiles, QWG, 0, st>>>(a);
-            else k_weights<false><<<tiles, QWG, 0, st>>>(a);
+            k_weights<true><<<tiles, QWG, 0, st>>>(a);
         }
         if (fork) P2M_HIP(hipStreamWaitEvent(st, side.join, 0));
         // ill-conditioned or rank-deficient rows of either pass (normally none)
         // (a wave per listed row; the grid loops over the list)
         {
             PhaseTimer t5(PH_K_WEIGHTS_RD, st);
-            if (periodic) k_weights_rd<true><<<64, QWG, 0, st>>>(a);
-            else k_weights_rd<false><<<64, QWG, 0, st>>>(a);
+            k_weights_rd<true><<<64, QWG, 0, st>>>(a);
         }
-        if (periodic) k_seam_copy<<<tiles, QWG, 0, st>>>(a);
+        k_seam_copy<<<tiles, QWG, 0, st>>>(a);
     }
     P2M_HIP(hipGetLastError());
     return P2M_OK;

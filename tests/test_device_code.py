@@ -51,13 +51,16 @@ def test_every_kernel_is_inlined_and_fully_reachable(listings):
 
 
 def test_exact_fallback_kernel_keeps_its_delaunay_code(listings):
-    """The wave-per-node build kernel (bounded and periodic forms) must
-    contain its gift-wrapping reductions (dozens of cross-lane permutes), not
-    just the first query."""
+    """The kernels that run the exact wave-per-node path (periodic box:
+    k_slow_geom; bounded box: inside the shared weights launch, stored and
+    fused forms) must contain its gift-wrapping reductions (dozens of
+    cross-lane permutes), not just the first query."""
     bodies = dict(_kernels(listings["build.hip"]))
-    slow = [b for n, b in bodies.items() if "k_slow_geom" in n]
-    assert len(slow) == 2
-    for b in slow:
+    periodic = [b for n, b in bodies.items() if "k_slow_geom" in n]
+    bounded = [b for n, b in bodies.items() if "k_weights_slow" in n]
+    assert len(periodic) == 1
+    assert len(bounded) == 13  # stored rows, and 3 value types x 4 channel counts projecting
+    for b in periodic + bounded:
         assert b.count("ds_bpermute_b32") >= 200
 
 
