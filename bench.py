@@ -875,7 +875,7 @@ def main(argv=None):
         "k_m2p": ("hbm", N * (16 + 4 * C) + nn * 4 * C, ph32["m2p"], "positions + mesh in + values out, FP32"),
     }
     kernels = {}
-    counted_names = {"k_build_fast": fast_name, "k_weights": "k_weights_slow<false>"}
+    counted_names = {"k_build_fast": fast_name, "k_weights": "k_weights_slow<false, StoreRows>"}
     for name, (bound, work, ms, per_unit) in kern.items():
         if bound == "alu":
             ach = work / (ms * 1e-3) / 1e12
